@@ -1,0 +1,424 @@
+"""CPU oracle for full-sky pixel-relative Taylor lensing -- TEST INFRASTRUCTURE.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this module.  It shares no code with the GPU library
+(``paper_1307_0719_amd``) and never imports it.
+
+What it computes, in the order the paper gives (Sec. II, eqs. 1, 2, 4, 5):
+
+1. Unlensed derivative maps D_{j,k} = d^j_theta d^k_phi s at the pixel centres
+   of an equal-theta (Clenshaw-Curtis) ring grid, theta_i = pi i/(ntheta-1),
+   phi_k = 2 pi k/nphi, for s in {T, Q, U} and j + k <= order.  The theta part
+   comes from ``sht_oracle.c`` (exact Legendre / Wigner-d recursions with
+   Leibniz derivatives, long double); the phi part is the Fourier sum
+   sum_m (i m)^k F^{(j)}_m e^{i m phi} (numpy's FFT as a library primitive,
+   or a direct sum at arbitrary phi).
+2. Deflection alpha = grad phi (Sec. II.A): alpha_theta = d_theta phi,
+   alpha_phi = d_phi phi / sin theta; on a pole ring the limit
+   +- d_theta d_phi phi (all pixels of a pole ring then share one x').
+3. Displaced position x' (Sec. II.A, parallel transport): the point at
+   great-circle distance |alpha| from x in the direction
+   (alpha_theta e_theta + alpha_phi e_phi)/|alpha|.
+   Optional "naive" rule: theta' = theta + alpha_theta,
+   phi' = phi + alpha_phi / sin theta, reflected over the poles.
+4. Nearest pixel and sub-pixel offset (Sec. II.B): i0 = round(theta'/dtheta)
+   clamped to the grid, k^ = round(phi'/dphi) (round half up), k0 = k^ mod
+   nphi, dth = theta' - i0 dtheta, dph = phi' - k^ dphi.
+5. Taylor sum (eq. 5): s' = sum_{n<=N} sum_{j<=n} dth^j dph^(n-j) /
+   (j!(n-j)!) D_{j,n-j}(i0, k0), for each of T, Q, U.
+6. Polarization rotation R (eq. 2, parallel transport): the spin-2 tensor
+   Q(e'_t e'_t^T - e'_p e'_p^T) + U(e'_t e'_p^T + e'_p e'_t^T) at x' is
+   carried to x by the rotation about x' cross x through the angle between
+   them, and read back as Q = e_t^T P e_t, U = e_t^T P e_p.
+
+Everything is float64 (the harmonic sums long double).  Speed is not a goal.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "sht_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+
+def build_library(force: bool = True) -> str:
+    """Compile sht_oracle.c into liboracle.so (plain gcc, -O2, OpenMP)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared",
+                               "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build_library(force=False)
+        lib = ctypes.CDLL(_LIB)
+        dp = ctypes.POINTER(ctypes.c_double)
+        lib.oracle_synth_rings.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, dp,
+                                           dp, dp, dp, dp, dp, dp, ctypes.c_int]
+        lib.oracle_synth_rings.restype = ctypes.c_int
+        lib.oracle_spin_lambda.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                           ctypes.c_int, ctypes.c_double, dp]
+        lib.oracle_spin_lambda.restype = ctypes.c_int
+        _lib = lib
+    return _lib
+
+
+def _ptr(a):
+    if a is None:
+        return None
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _cplx(a):
+    if a is None:
+        return None
+    a = np.ascontiguousarray(a, dtype=np.complex128)
+    return a.view(np.float64)
+
+
+# ---------------------------------------------------------------- grid ----
+
+def grid_theta(ntheta: int) -> np.ndarray:
+    """Ring colatitudes of the equal-theta grid with both poles."""
+    return math.pi * np.arange(ntheta, dtype=np.float64) / (ntheta - 1)
+
+
+def grid_phi(nphi: int) -> np.ndarray:
+    return 2.0 * math.pi * np.arange(nphi, dtype=np.float64) / nphi
+
+
+# ----------------------------------------------------- harmonic part -----
+
+def spin_lambda(lmax: int, nderiv: int, s: int, m: int, theta: float) -> np.ndarray:
+    """[l, j] = d^j/dtheta^j  s_lambda_lm(theta) for l = 0..lmax."""
+    out = np.zeros((lmax + 1, nderiv + 1))
+    rc = _load().oracle_spin_lambda(lmax, nderiv, s, m, float(theta), _ptr(out))
+    if rc != 0:
+        raise ValueError("oracle_spin_lambda rejected its arguments")
+    return out
+
+
+def ring_coeffs(lmax: int, nderiv: int, thetas, alm_T=None, alm_E=None, alm_B=None,
+                nthreads: int = 0) -> dict:
+    """Per-ring Fourier coefficients F^{(j)}_m(theta) of T, Q, U.
+
+    Returns {'T': [nring, nderiv+1, lmax+1] complex128, 'Q': ..., 'U': ...}
+    (only the fields given)."""
+    th = np.ascontiguousarray(np.atleast_1d(thetas), dtype=np.float64)
+    nr = th.size
+    shape = (nr, nderiv + 1, lmax + 1)
+    outT = np.zeros(shape, np.complex128) if alm_T is not None else None
+    outQ = np.zeros(shape, np.complex128) if alm_E is not None else None
+    outU = np.zeros(shape, np.complex128) if alm_E is not None else None
+    aT, aE, aB = _cplx(alm_T), _cplx(alm_E), _cplx(alm_B)
+    rc = _load().oracle_synth_rings(
+        lmax, nderiv, nr, _ptr(th), _ptr(aT), _ptr(aE), _ptr(aB),
+        _ptr(outT.view(np.float64)) if outT is not None else None,
+        _ptr(outQ.view(np.float64)) if outQ is not None else None,
+        _ptr(outU.view(np.float64)) if outU is not None else None,
+        int(nthreads))
+    if rc != 0:
+        raise ValueError("oracle_synth_rings rejected its arguments")
+    res = {}
+    if outT is not None:
+        res["T"] = outT
+    if outQ is not None:
+        res["Q"] = outQ
+        res["U"] = outU
+    return res
+
+
+def phi_synth(F: np.ndarray, k: int, nphi: int) -> np.ndarray:
+    """Real ring values sum_{m=-L}^{L} (i m)^k F_m e^{i m phi_n} with
+    F_{-m} = conj(F_m) (only Re F_0 counts), at phi_n = 2 pi n/nphi.
+
+    F: [..., L+1] complex.  Uses x_n = Re(sum_m w_m c_m e^{2 pi i m n/N}),
+    w_0 = 1, w_m = 2 (exact for L < nphi)."""
+    L = F.shape[-1] - 1
+    if L >= nphi:
+        raise ValueError("need lmax < nphi")
+    m = np.arange(L + 1)
+    c = F * (1j * m) ** k
+    w = np.full(L + 1, 2.0)
+    w[0] = 1.0
+    z = np.zeros(F.shape[:-1] + (nphi,), np.complex128)
+    z[..., :L + 1] = w * c
+    return np.real(np.fft.ifft(z, axis=-1) * nphi)
+
+
+def phi_eval(F: np.ndarray, k: int, phi) -> np.ndarray:
+    """Same sum as phi_synth at arbitrary phi (direct evaluation).
+    F: [L+1] complex; phi: array."""
+    L = F.shape[-1] - 1
+    m = np.arange(L + 1)
+    c = F * (1j * m) ** k
+    w = np.full(L + 1, 2.0)
+    w[0] = 1.0
+    ph = np.asarray(phi, dtype=np.float64)
+    e = np.exp(1j * np.multiply.outer(ph, m))
+    return np.real(e @ (w * c))
+
+
+def jk_pairs(order: int):
+    """(j, k) pairs with j + k <= order, j-major (the derivative-map order)."""
+    return [(j, k) for j in range(order + 1) for k in range(order + 1 - j)]
+
+
+def derivative_rings(lmax: int, order: int, ntheta: int, nphi: int, rings,
+                     alm_T=None, alm_E=None, alm_B=None, nthreads: int = 0) -> dict:
+    """Exact derivative maps on selected rings.
+
+    Returns {field: {(j,k): [len(rings), nphi] float64}}."""
+    rings = np.atleast_1d(np.asarray(rings, dtype=np.int64))
+    th = grid_theta(ntheta)[rings]
+    F = ring_coeffs(lmax, order, th, alm_T, alm_E, alm_B, nthreads)
+    out = {}
+    for f, arr in F.items():
+        d = {}
+        for (j, k) in jk_pairs(order):
+            d[(j, k)] = phi_synth(arr[:, j, :], k, nphi)
+        out[f] = d
+    return out
+
+
+def deflection_rings(lmax: int, alm_phi, ntheta: int, nphi: int, rings, nthreads: int = 0):
+    """alpha_theta, alpha_phi on the given rings ([nring, nphi] each)."""
+    rings = np.atleast_1d(np.asarray(rings, dtype=np.int64))
+    th = grid_theta(ntheta)[rings]
+    F = ring_coeffs(lmax, 1, th, alm_T=alm_phi, nthreads=nthreads)["T"]
+    a_t = phi_synth(F[:, 1, :], 0, nphi)
+    dphi = phi_synth(F[:, 0, :], 1, nphi)
+    dtdphi = phi_synth(F[:, 1, :], 1, nphi)
+    a_p = np.empty_like(a_t)
+    for r, i in enumerate(rings):
+        if i == 0:
+            a_p[r] = dtdphi[r]            # lim_{theta->0} d_phi phi / sin theta
+        elif i == ntheta - 1:
+            a_p[r] = -dtdphi[r]           # lim_{theta->pi}
+        else:
+            a_p[r] = dphi[r] / math.sin(th[r])
+    return a_t, a_p
+
+
+# ------------------------------------------------------------ geometry ---
+
+def unit_vectors(theta, phi):
+    """x^, e_theta, e_phi as [..., 3] arrays."""
+    st, ct = np.sin(theta), np.cos(theta)
+    sp, cp = np.sin(phi), np.cos(phi)
+    x = np.stack([st * cp, st * sp, ct], axis=-1)
+    et = np.stack([ct * cp, ct * sp, -st], axis=-1)
+    ep = np.stack([-sp, cp, np.zeros_like(sp)], axis=-1)
+    return x, et, ep
+
+
+def geodesic_positions(theta, phi, a_t, a_p):
+    """Displaced positions by parallel transport along the great circle.
+
+    Returns (theta', phi' in [0, 2pi), xhat', d, u) with u the unit initial
+    direction (3-vector; zero where |alpha| = 0)."""
+    theta, phi = np.broadcast_arrays(np.asarray(theta, float), np.asarray(phi, float))
+    a_t = np.asarray(a_t, float)
+    a_p = np.asarray(a_p, float)
+    x, et, ep = unit_vectors(theta, phi)
+    d = np.sqrt(a_t * a_t + a_p * a_p)
+    safe = np.where(d > 0, d, 1.0)
+    u = (a_t[..., None] * et + a_p[..., None] * ep) / safe[..., None]
+    u = np.where((d > 0)[..., None], u, 0.0)
+    xp = np.cos(d)[..., None] * x + np.sin(d)[..., None] * u
+    thp = np.arctan2(np.hypot(xp[..., 0], xp[..., 1]), xp[..., 2])
+    php = np.mod(np.arctan2(xp[..., 1], xp[..., 0]), 2 * math.pi)
+    # no displacement: keep the coordinates exactly
+    thp = np.where(d > 0, thp, theta)
+    php = np.where(d > 0, php, np.mod(phi, 2 * math.pi))
+    return thp, php, xp, d, u
+
+
+def naive_positions(theta, phi, a_t, a_p):
+    """Coordinate addition, reflected across the poles; pole rings (sin = 0)
+    fall back to the geodesic rule."""
+    theta, phi = np.broadcast_arrays(np.asarray(theta, float), np.asarray(phi, float))
+    st = np.sin(theta)
+    pole = (theta == 0.0) | (theta == math.pi)
+    thp = theta + a_t
+    php = phi + np.where(pole, 0.0, a_p / np.where(pole, 1.0, st))
+    neg = thp < 0
+    thp = np.where(neg, -thp, thp)
+    php = np.where(neg, php + math.pi, php)
+    big = thp > math.pi
+    thp = np.where(big, 2 * math.pi - thp, thp)
+    php = np.where(big, php + math.pi, php)
+    php = np.mod(php, 2 * math.pi)
+    if np.any(pole):
+        gt, gp, _, _, _ = geodesic_positions(theta, phi, a_t, a_p)
+        thp = np.where(pole, gt, thp)
+        php = np.where(pole, gp, php)
+    return thp, php
+
+
+def nearest_pixel(thp, php, ntheta: int, nphi: int):
+    """Nearest grid point (round half up in each coordinate) and residuals.
+
+    Returns i0, k0, dth, dph, tie (distance of each scaled coordinate's
+    fractional part from 1/2, min over theta/phi)."""
+    dtheta = math.pi / (ntheta - 1)
+    dphi = 2 * math.pi / nphi
+    tt = thp / dtheta
+    tp = php / dphi
+    i0 = np.clip(np.floor(tt + 0.5), 0, ntheta - 1).astype(np.int64)
+    kh = np.floor(tp + 0.5).astype(np.int64)
+    k0 = np.mod(kh, nphi)
+    # centres computed exactly as grid_theta / grid_phi compute them, so that
+    # a position on a pixel centre has residual exactly zero
+    dth = thp - math.pi * i0 / (ntheta - 1)
+    dph = php - 2.0 * math.pi * kh / nphi
+    tie = np.minimum(np.abs(tt - np.floor(tt) - 0.5), np.abs(tp - np.floor(tp) - 0.5))
+    return i0, k0, dth, dph, tie
+
+
+def taylor_sum(Dget, dth, dph, order: int):
+    """eq. 5: sum_{n<=N} sum_{j<=n} dth^j dph^(n-j)/(j!(n-j)!) D_{j,n-j}.
+
+    Dget(j, k) returns the derivative values at the expansion points."""
+    out = np.zeros_like(np.asarray(dth, float))
+    for n in range(order + 1):
+        for j in range(n + 1):
+            k = n - j
+            out = out + dth ** j * dph ** k / (math.factorial(j) * math.factorial(k)) * Dget(j, k)
+    return out
+
+
+def rotate_pol_3d(Q, U, theta, phi, thp, php, xp):
+    """Parallel transport of the spin-2 tensor from x' to x (3D construction).
+
+    Q, U are components at x' in the (e_theta, e_phi) basis of (thp, php);
+    returns the components at x in the basis of (theta, phi)."""
+    x, et, ep = unit_vectors(theta, phi)
+    _, etp, epp = unit_vectors(thp, php)
+    Q = np.asarray(Q, float)
+    U = np.asarray(U, float)
+    P = (Q[..., None, None] * (etp[..., :, None] * etp[..., None, :] - epp[..., :, None] * epp[..., None, :])
+         + U[..., None, None] * (etp[..., :, None] * epp[..., None, :] + epp[..., :, None] * etp[..., None, :]))
+    axis = np.cross(xp, x)
+    s = np.linalg.norm(axis, axis=-1)
+    c = np.sum(xp * x, axis=-1)
+    ang = np.arctan2(s, c)
+    n = axis / np.where(s > 0, s, 1.0)[..., None]
+    # Rodrigues rotation matrix about n by ang
+    K = np.zeros(n.shape[:-1] + (3, 3))
+    K[..., 0, 1] = -n[..., 2]
+    K[..., 0, 2] = n[..., 1]
+    K[..., 1, 0] = n[..., 2]
+    K[..., 1, 2] = -n[..., 0]
+    K[..., 2, 0] = -n[..., 1]
+    K[..., 2, 1] = n[..., 0]
+    I = np.broadcast_to(np.eye(3), K.shape)
+    sa = np.sin(ang)[..., None, None]
+    ca = np.cos(ang)[..., None, None]
+    R = I + sa * K + (1 - ca) * (K @ K)
+    R = np.where((s > 0)[..., None, None], R, I)
+    Px = R @ P @ np.swapaxes(R, -1, -2)
+    Qx = np.einsum("...i,...ij,...j->...", et, Px, et)
+    Ux = np.einsum("...i,...ij,...j->...", et, Px, ep)
+    return Qx, Ux
+
+
+# ---------------------------------------------------------- pipelines ----
+
+def _remap_rings(out_rings, ntheta, nphi, order, a_t, a_p, deriv_fn, fields,
+                 rotate=True, naive=False):
+    """Remap + Taylor (+ rotation) for the pixels of the given output rings.
+
+    deriv_fn(src_rings) -> {field: {(j,k): [nsrc, nphi]}}."""
+    out_rings = np.atleast_1d(np.asarray(out_rings, dtype=np.int64))
+    th = grid_theta(ntheta)[out_rings][:, None] * np.ones((1, nphi))
+    ph = grid_phi(nphi)[None, :] * np.ones((out_rings.size, 1))
+    if naive:
+        thp, php = naive_positions(th, ph, a_t, a_p)
+        xp = unit_vectors(thp, php)[0]
+        dist = np.hypot(a_t, a_p)
+    else:
+        thp, php, xp, dist, _ = geodesic_positions(th, ph, a_t, a_p)
+    i0, k0, dth, dph, tie = nearest_pixel(thp, php, ntheta, nphi)
+    src = np.unique(i0)
+    D = deriv_fn(src)
+    pos = np.searchsorted(src, i0)
+    res = {}
+    for f in fields:
+        Df = D[f]
+        res[f] = taylor_sum(lambda j, k: Df[(j, k)][pos, k0], dth, dph, order)
+    if "Q" in res and rotate and not naive:
+        Qr, Ur = rotate_pol_3d(res["Q"], res["U"], th, ph, thp, php, xp)
+        # no displacement: no transport (keeps the alpha = 0 identity exact)
+        res["Q"] = np.where(dist > 0, Qr, res["Q"])
+        res["U"] = np.where(dist > 0, Ur, res["U"])
+    res["_i0"] = i0
+    res["_k0"] = k0
+    res["_dth"] = dth
+    res["_dph"] = dph
+    res["_tie"] = tie
+    res["_thp"] = thp
+    res["_php"] = php
+    return res
+
+
+def lens_rings(lmax, order, ntheta, nphi, out_rings, alm_T, alm_E=None, alm_B=None,
+               alm_phi=None, rotate=True, naive=False, nthreads: int = 0) -> dict:
+    """Lensed T (and Q, U) on the selected output rings ([nring, nphi])."""
+    out_rings = np.atleast_1d(np.asarray(out_rings, dtype=np.int64))
+    if alm_phi is None:
+        a_t = np.zeros((out_rings.size, nphi))
+        a_p = np.zeros((out_rings.size, nphi))
+    else:
+        a_t, a_p = deflection_rings(lmax, alm_phi, ntheta, nphi, out_rings, nthreads)
+    fields = ["T"] + (["Q", "U"] if alm_E is not None else [])
+
+    def deriv_fn(src):
+        return derivative_rings(lmax, order, ntheta, nphi, src, alm_T, alm_E, alm_B, nthreads)
+
+    res = _remap_rings(out_rings, ntheta, nphi, order, a_t, a_p, deriv_fn, fields,
+                       rotate=rotate, naive=naive)
+    res["_alpha_theta"] = a_t
+    res["_alpha_phi"] = a_p
+    return res
+
+
+def lens_map(lmax, order, ntheta, nphi, alm_T, alm_E=None, alm_B=None, alm_phi=None,
+             rotate=True, naive=False, nthreads: int = 0) -> dict:
+    """Full lensed maps ([ntheta, nphi] per field)."""
+    return lens_rings(lmax, order, ntheta, nphi, np.arange(ntheta), alm_T, alm_E, alm_B,
+                      alm_phi, rotate, naive, nthreads)
+
+
+def lens_at_positions(lmax, order, ntheta, nphi, thp, php, alm_T, alm_E=None, alm_B=None,
+                      nthreads: int = 0) -> dict:
+    """Taylor remap at caller-given source positions (no rotation)."""
+    thp = np.asarray(thp, float)
+    php = np.mod(np.asarray(php, float), 2 * math.pi)
+    i0, k0, dth, dph, tie = nearest_pixel(thp, php, ntheta, nphi)
+    src = np.unique(i0)
+    D = derivative_rings(lmax, order, ntheta, nphi, src, alm_T, alm_E, alm_B, nthreads)
+    pos = np.searchsorted(src, i0)
+    res = {}
+    for f in D:
+        Df = D[f]
+        res[f] = taylor_sum(lambda j, k: Df[(j, k)][pos, k0], dth, dph, order)
+    res["_tie"] = tie
+    return res
+
+
+def unlensed_map(lmax, ntheta, nphi, alm_T, alm_E=None, alm_B=None, nthreads: int = 0):
+    D = derivative_rings(lmax, 0, ntheta, nphi, np.arange(ntheta), alm_T, alm_E, alm_B, nthreads)
+    return {f: D[f][(0, 0)] for f in D}

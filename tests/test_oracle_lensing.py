@@ -1,0 +1,274 @@
+"""Pins of the oracle's lensing pipeline (remap, Taylor sum, rotation,
+positions) against results fixed by mathematics it does not use:
+
+P1  brute-force sum a_lm Y_lm(x') (scipy / Goldberg), error within the
+    Bernstein bound of a band-limited function, for N = 0..14;
+P2  a constant azimuthal shift, whose exact order-N result is a phase factor
+    E_N(i m r) per m;
+P3  a constant theta shift, exact via the doubled-circle Fourier series;
+P4  alpha = 0 gives back the unlensed map bit for bit;
+P8  the rotation equals the closed-form angle 2 gamma, is unitary, and obeys
+    the pole-ring invariants;
+P9  the positions lie at great-circle distance |alpha| in direction psi.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_1307_0719_amd import skygen
+from tests import pinlib
+
+
+def _sup_bound_T(alm, lmax):
+    """sup |T| <= sum_l sqrt((2l+1)/(4 pi) sum_{|m|<=l} |a_lm|^2)."""
+    tot = 0.0
+    for l in range(lmax + 1):
+        s = 0.0
+        for m in range(0, l + 1):
+            a = alm[m * (2 * lmax + 1 - m) // 2 + l]
+            s += (1.0 if m == 0 else 2.0) * abs(a) ** 2
+        tot += math.sqrt((2 * l + 1) / (4 * math.pi) * s)
+    return tot
+
+
+def _sup_bound_P(almE, almB, lmax):
+    tot = 0.0
+    for l in range(2, lmax + 1):
+        s = 0.0
+        for m in range(-l, l + 1):
+            e = pinlib.alm_get(almE, lmax, l, m)
+            b = pinlib.alm_get(almB, lmax, l, m)
+            s += abs(e + 1j * b) ** 2
+        tot += math.sqrt((2 * l + 1) / (4 * math.pi) * s)
+    return tot
+
+
+@pytest.fixture(scope="module")
+def small_sky():
+    lmax = 16
+    ntheta, nphi = 4 * lmax + 1, 8 * lmax
+    # deflection of ~2 pixels RMS so that the nearest pixel really moves
+    pix_arcmin = (math.pi / (ntheta - 1)) / skygen.ARCMIN
+    sky = skygen.make_sky(lmax, 101, pol=True, rms_arcmin=2.0 * pix_arcmin)
+    almB = skygen.random_alm(lmax, 102, lmin=2) * 0.3
+    return lmax, ntheta, nphi, sky, almB
+
+
+def test_p1_brute_force_convergence(oracle, small_sky):
+    lmax, ntheta, nphi, sky, almB = small_sky
+    supT = _sup_bound_T(sky.alm_T, lmax)
+    supP = _sup_bound_P(sky.alm_E, almB, lmax)
+    exact = None
+    errs = []
+    for N in range(0, 15):
+        res = oracle.lens_map(lmax, N, ntheta, nphi, sky.alm_T, sky.alm_E, almB, sky.alm_phi,
+                              rotate=False)
+        if exact is None:
+            thp, php = res["_thp"], res["_php"]
+            # the deflection must move most pixels off their own centre
+            moved = np.mean(res["_i0"] != np.arange(ntheta)[:, None])
+            assert moved > 0.5
+            exact = {"T": pinlib.brute_T(sky.alm_T, lmax, thp, php)}
+            exact["Q"], exact["U"] = pinlib.brute_QU(sky.alm_E, almB, lmax, thp, php)
+        sigma = lmax * (np.abs(res["_dth"]) + np.abs(res["_dph"]))
+        assert np.max(sigma) <= math.pi / 4 + 1e-12
+        tail = sigma ** (N + 1) / math.factorial(N + 1)
+        e = {}
+        for f, sup in (("T", supT), ("Q", supP), ("U", supP)):
+            err = np.abs(res[f] - exact[f])
+            assert np.all(err <= sup * tail + 1e-13 * sup), (f, N)
+            e[f] = np.max(err) / sup
+        errs.append(max(e.values()))
+    errs = np.array(errs)
+    # the series converges: decreasing (to rounding level) and ~1e-13 by N = 14
+    assert errs[14] < 1e-13
+    assert np.all(np.diff(np.maximum(errs, 1e-14)) <= 1e-15)
+
+
+@pytest.mark.parametrize("N", [0, 1, 2, 3, 5, 8])
+def test_p2_constant_azimuthal_shift(oracle, N):
+    lmax = 48
+    ntheta, nphi = 2 * lmax + 1, 2 * lmax  # nphi = 2 lmax: Nyquist bin present
+    aT = skygen.random_alm(lmax, 7)
+    th = oracle.grid_theta(ntheta)
+    ph = oracle.grid_phi(nphi)
+    dphi = 2 * math.pi / nphi
+    c = 2.37 * dphi
+    q = math.floor(c / dphi + 0.5)
+    r = c - q * dphi
+    TH = th[:, None] * np.ones((1, nphi))
+    PHp = ph[None, :] + c + 0 * TH
+    res = oracle.lens_at_positions(lmax, N, ntheta, nphi, TH, PHp, aT)
+    assert np.min(res["_tie"]) > 1e-6
+    # exact: sum_m w_m Re[F_m(theta_i) e^{i m (phi_k + q dphi)} E_N(i m r)]
+    m = np.arange(lmax + 1)
+    EN = sum((1j * m * r) ** n / math.factorial(n) for n in range(N + 1))
+    Fm = np.zeros((ntheta, lmax + 1), np.complex128)
+    for mm in range(lmax + 1):
+        for l in range(mm, lmax + 1):
+            Fm[:, mm] += aT[mm * (2 * lmax + 1 - mm) // 2 + l] * pinlib.scalar_lambda(l, mm, th)
+    w = np.where(m == 0, 1.0, 2.0)
+    ex = np.real((w * Fm * EN)[:, None, :] * np.exp(1j * np.multiply.outer(ph + q * dphi, m))[None]).sum(-1)
+    scale = np.max(np.abs(ex))
+    np.testing.assert_allclose(res["T"], ex, atol=2e-13 * scale)
+
+
+@pytest.mark.parametrize("N", [1, 2, 4, 7])
+def test_p3_constant_theta_shift(oracle, N):
+    lmax = 32
+    ntheta, nphi = lmax + 3, 2 * lmax + 2
+    aT = skygen.random_alm(lmax, 9)
+    th = oracle.grid_theta(ntheta)
+    ph = oracle.grid_phi(nphi)
+    dth = math.pi / (ntheta - 1)
+    c = 0.41 * dth
+    rings = np.arange(1, ntheta - 1)  # interior rings (theta + c stays inside)
+    TH = th[rings][:, None] + c + 0 * ph[None, :]
+    PH = ph[None, :] + 0 * TH
+    res = oracle.lens_at_positions(lmax, N, ntheta, nphi, TH, PH, aT)
+    # F_m on the doubled circle: F_m(2 pi - t) = (-1)^m F_m(t); trig polynomial
+    # of degree <= lmax in t, sampled at 2(ntheta-1) > 2 lmax points.
+    nd = 2 * (ntheta - 1)
+    m = np.arange(lmax + 1)
+    Fm = np.zeros((ntheta, lmax + 1), np.complex128)
+    for mm in range(lmax + 1):
+        for l in range(mm, lmax + 1):
+            Fm[:, mm] += aT[mm * (2 * lmax + 1 - mm) // 2 + l] * pinlib.scalar_lambda(l, mm, th)
+    dbl = np.zeros((nd, lmax + 1), np.complex128)
+    dbl[:ntheta] = Fm
+    for qq in range(ntheta, nd):
+        dbl[qq] = (-1.0) ** m * Fm[nd - qq]
+    cq = np.fft.fft(dbl, axis=0) / nd
+    p = np.fft.fftfreq(nd, d=1.0 / nd)
+    assert np.max(np.abs(cq[np.abs(p) > lmax])) < 1e-12 * np.max(np.abs(cq))
+    EN = sum((1j * p * c) ** n / math.factorial(n) for n in range(N + 1))
+    Ft = (cq[None, :, :] * (np.exp(1j * np.multiply.outer(th[rings], p)) * EN)[:, :, None]).sum(1)
+    w = np.where(m == 0, 1.0, 2.0)
+    ex = np.real((w * Ft)[:, None, :] * np.exp(1j * np.multiply.outer(ph, m))[None]).sum(-1)
+    scale = np.max(np.abs(ex))
+    np.testing.assert_allclose(res["T"], ex, atol=1e-12 * scale)
+
+
+def test_p4_zero_deflection_is_identity(oracle):
+    lmax = 24
+    ntheta, nphi = 2 * lmax + 1, 2 * lmax + 4
+    sky = skygen.make_sky(lmax, 3)
+    zero = np.zeros_like(sky.alm_phi)
+    for N in (0, 3):
+        res = oracle.lens_map(lmax, N, ntheta, nphi, sky.alm_T, sky.alm_E, sky.alm_B, zero)
+        un = oracle.unlensed_map(lmax, ntheta, nphi, sky.alm_T, sky.alm_E, sky.alm_B)
+        for f in ("T", "Q", "U"):
+            assert np.array_equal(res[f], un[f]), f
+
+
+def _closed_form_rotation(Q, U, theta, phi, a_t, a_p):
+    x, et, ep = [np.asarray(v) for v in _uv(theta, phi)]
+    d = np.hypot(a_t, a_p)
+    u = (a_t[..., None] * et + a_p[..., None] * ep) / d[..., None]
+    xp = np.cos(d)[..., None] * x + np.sin(d)[..., None] * u
+    tp = -np.sin(d)[..., None] * x + np.cos(d)[..., None] * u
+    thp = np.arctan2(np.hypot(xp[..., 0], xp[..., 1]), xp[..., 2])
+    php = np.arctan2(xp[..., 1], xp[..., 0])
+    _, etp, epp = _uv(thp, php)
+    psi = np.arctan2(a_p, a_t)
+    psip = np.arctan2(np.sum(tp * epp, -1), np.sum(tp * etp, -1))
+    g = psi - psip
+    P = (Q + 1j * U) * np.exp(2j * g)
+    return np.real(P), np.imag(P), thp, np.mod(php, 2 * math.pi), xp
+
+
+def _uv(theta, phi):
+    st, ct, sp, cp = np.sin(theta), np.cos(theta), np.sin(phi), np.cos(phi)
+    return (np.stack([st * cp, st * sp, ct], -1), np.stack([ct * cp, ct * sp, -st], -1),
+            np.stack([-sp, cp, 0 * sp], -1))
+
+
+def test_p8_rotation_closed_form_matches_3d_transport(oracle):
+    rng = np.random.default_rng(0)
+    n = 4000
+    theta = np.concatenate([rng.uniform(0, math.pi, n - 8), [0.0] * 4, [math.pi] * 4])
+    phi = rng.uniform(0, 2 * math.pi, n)
+    a_t = rng.normal(0, 0.2, n)
+    a_p = rng.normal(0, 0.2, n)
+    Q = rng.normal(size=n)
+    U = rng.normal(size=n)
+    Qc, Uc, thp, php, xp = _closed_form_rotation(Q, U, theta, phi, a_t, a_p)
+    Q3, U3 = oracle.rotate_pol_3d(Q, U, theta, phi, thp, php, xp)
+    np.testing.assert_allclose(Q3, Qc, atol=2e-13)
+    np.testing.assert_allclose(U3, Uc, atol=2e-13)
+    # unitary
+    np.testing.assert_allclose(np.hypot(Q3, U3), np.hypot(Q, U), rtol=1e-13)
+    # the oracle's own positions agree with the construction used here
+    gt, gp, gx, _, _ = oracle.geodesic_positions(theta, phi, a_t, a_p)
+    np.testing.assert_allclose(gx, xp, atol=1e-15)
+
+
+def test_p8_rotation_identity_at_zero_deflection(oracle):
+    rng = np.random.default_rng(1)
+    theta = rng.uniform(0, math.pi, 50)
+    phi = rng.uniform(0, 2 * math.pi, 50)
+    Q, U = rng.normal(size=50), rng.normal(size=50)
+    x = _uv(theta, phi)[0]
+    Q3, U3 = oracle.rotate_pol_3d(Q, U, theta, phi, theta, phi, x)
+    np.testing.assert_allclose(Q3, Q, atol=1e-15)
+    np.testing.assert_allclose(U3, U, atol=1e-15)
+
+
+def test_p8_pole_ring_invariants(oracle):
+    lmax = 32
+    ntheta, nphi = 2 * lmax + 1, 2 * lmax + 2
+    pix = (math.pi / (ntheta - 1)) / skygen.ARCMIN
+    sky = skygen.make_sky(lmax, 21, rms_arcmin=1.5 * pix)
+    res = oracle.lens_rings(lmax, 3, ntheta, nphi, [0, ntheta - 1], sky.alm_T, sky.alm_E, sky.alm_B,
+                            sky.alm_phi)
+    ph = oracle.grid_phi(nphi)
+    T = res["T"]
+    P = res["Q"] + 1j * res["U"]
+    for r, sgn in ((0, 1), (1, -1)):
+        assert np.ptp(T[r]) <= 1e-12 * np.max(np.abs(T))
+        rot = P[r] * np.exp(2j * sgn * ph)
+        assert np.max(np.abs(rot - rot[0])) <= 1e-12 * np.max(np.abs(P))
+
+
+def test_p9_positions_geometry(oracle):
+    rng = np.random.default_rng(2)
+    n = 3000
+    theta = rng.uniform(0.01, math.pi - 0.01, n)
+    phi = rng.uniform(0, 2 * math.pi, n)
+    a_t = rng.normal(0, 1e-3, n)
+    a_p = rng.normal(0, 1e-3, n)
+    thp, php, xp, d, u = oracle.geodesic_positions(theta, phi, a_t, a_p)
+    x, et, ep = _uv(theta, phi)
+    dist = np.arctan2(np.linalg.norm(np.cross(x, xp), axis=-1), np.sum(x * xp, -1))
+    np.testing.assert_allclose(dist, np.hypot(a_t, a_p), atol=1e-15, rtol=1e-13)
+    # bearing at x of the great circle through x and x'
+    t0 = xp - np.sum(x * xp, -1)[:, None] * x
+    bearing = np.arctan2(np.sum(t0 * ep, -1), np.sum(t0 * et, -1))
+    dpsi = np.angle(np.exp(1j * (bearing - np.arctan2(a_p, a_t))))
+    assert np.max(np.abs(dpsi)) < 1e-9
+    # the naive rule differs at second order in alpha
+    nt, npp = oracle.naive_positions(theta, phi, a_t, a_p)
+    diff = np.hypot(nt - thp, np.sin(theta) * np.angle(np.exp(1j * (npp - php))))
+    alpha2 = a_t ** 2 + a_p ** 2
+    assert np.max(diff / (alpha2 / np.sin(theta))) < 2.0
+
+
+def test_p9_pole_ring_shares_one_position(oracle):
+    lmax = 40
+    ntheta, nphi = 2 * lmax + 1, 2 * lmax + 2
+    sky = skygen.make_sky(lmax, 5)
+    a_t, a_p = oracle.deflection_rings(lmax, sky.alm_phi, ntheta, nphi, [0, ntheta - 1])
+    th = oracle.grid_theta(ntheta)[[0, ntheta - 1]][:, None] + 0 * a_t
+    ph = oracle.grid_phi(nphi)[None, :] + 0 * a_t
+    _, _, xp, _, _ = oracle.geodesic_positions(th, ph, a_t, a_p)
+    for r in range(2):
+        # unit-vector components agree to a few ulp of 1
+        assert np.max(np.abs(xp[r] - xp[r, 0])) < 1e-15
+    # continuity: alpha_phi at a tiny colatitude tends to the pole-ring value
+    eps = 1e-7
+    F = oracle.ring_coeffs(lmax, 1, [eps], alm_T=sky.alm_phi)["T"]
+    ap_eps = oracle.phi_synth(F[:, 0, :], 1, nphi)[0] / math.sin(eps)
+    at_eps = oracle.phi_synth(F[:, 1, :], 0, nphi)[0]
+    np.testing.assert_allclose(ap_eps, a_p[0], atol=1e-5 * np.max(np.abs(a_p[0])))
+    np.testing.assert_allclose(at_eps, a_t[0], atol=1e-5 * np.max(np.abs(a_t[0])))
