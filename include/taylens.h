@@ -1,0 +1,182 @@
+/*
+ * taylens.h -- C ABI of the MI355X (gfx950) full-sky Taylor-lensing library.
+ *
+ * The library lenses band-limited CMB fields given as spherical-harmonic
+ * coefficients: T'(x) = T(x + alpha), P'(x) = R P(x + alpha) with
+ * alpha = grad phi (eqs. 1-2 of Naess & Louis 2013, "Lensing simulations by
+ * Taylor expansion -- not so inefficient after all").  The value at the
+ * displaced point is the Taylor series about the nearest pixel centre,
+ * truncated at order N (eq. 4; per component eq. 5, Sec. II.B), so the
+ * expansion variable is the sub-pixel residual, not the full deflection.
+ *
+ * Pixelization: equal-theta (Clenshaw-Curtis) ring grid with both poles,
+ *     theta_i = pi * i / (ntheta - 1),  i = 0..ntheta-1   (ring 0 = north pole)
+ *     phi_k   = 2 pi * k / nphi,        k = 0..nphi-1
+ * Maps are row-major [ntheta][nphi].  Q/U are components in the local
+ * (e_theta, e_phi) basis of each pixel (Q = P_tt, U = P_tp).
+ *
+ * Harmonic coefficients: complex128 (interleaved re, im), triangular
+ * m-major layout, a_lm at index m*(2*lmax+1-m)/2 + l for 0 <= m <= l <= lmax;
+ * negative m follow from a_{l,-m} = (-1)^m conj(a_lm) (real fields).  The
+ * imaginary part of m = 0 entries is ignored.  Orthonormal Y_lm with the
+ * Condon-Shortley phase; spin-2 harmonics sY_lm = sqrt((l-2)!/(l+2)!) eth^2 Y_lm,
+ * with Q + iU = sum -(E_lm + i B_lm) 2Y_lm; E/B entries with l < 2 are ignored.
+ *
+ * Memory: every array argument is a DEVICE pointer owned by the caller.  A
+ * plan owns only its workspace (allocated at tl_plan_create, released by
+ * tl_plan_destroy).  All work is queued on the plan's HIP stream; no call
+ * synchronizes the stream except tl_plan_create (which builds its tables).
+ * A plan is not thread-safe: use one plan per host thread / stream.
+ *
+ * Errors: every function returns TL_OK (0) or a negative code; arguments are
+ * validated on the host before any HIP call, so invalid arguments never
+ * launch work.  tl_last_error() gives a thread-local message for the last
+ * failure on the calling thread.  The library never aborts or exits.
+ */
+#ifndef TAYLENS_H
+#define TAYLENS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TL_OK 0
+#define TL_ERR_INVALID (-1)     /* bad argument (null plan/pointer, sizes)       */
+#define TL_ERR_UNSUPPORTED (-2) /* valid request this build does not provide     */
+#define TL_ERR_HIP (-3)         /* a HIP runtime call failed (see tl_last_error)  */
+#define TL_ERR_NOMEM (-4)       /* allocation failed or workspace_cap exceeded   */
+
+#define TL_MAX_ORDER 8 /* largest Taylor order N */
+
+/* Contraction precision of the harmonic (Legendre) stage.  The recursion of
+ * the Legendre functions is always FP64. */
+enum {
+    TL_FP64 = 0, /* FP64 throughout; maps are float64                          */
+    TL_FP32 = 1, /* FP32 contraction, derivative maps and Taylor sum; float32 out */
+    TL_BF16X3 = 2,
+    TL_FP16X2 = 3,
+    TL_FP16 = 4,
+    TL_BF16 = 5
+};
+
+typedef struct {
+    int32_t ntheta; /* rings, >= 2                        */
+    int32_t nphi;   /* pixels per ring, even, >= 2*lmax, and nphi/2 a product of 2, 3, 5 */
+} tl_grid;
+
+typedef struct {
+    int32_t order;         /* Taylor order N, 0..TL_MAX_ORDER (0 = nearest pixel)    */
+    int32_t precision;     /* TL_FP64 / TL_FP32 / ...                                */
+    int32_t pol;           /* 1: T and Q/U; 0: T only                                 */
+    int32_t rotate;        /* 1: apply the parallel-transport rotation R to Q/U       */
+    int32_t naive_pos;     /* 1: theta' = theta + a_t, phi' = phi + a_p / sin theta
+                              (reflected over the poles; pole rings stay geodesic;
+                              no rotation).  0: geodesic displacement.             */
+    int32_t reserved;      /* must be 0                                                */
+    int64_t workspace_cap; /* bytes; 0 = no cap.  tl_plan_create fails with
+                              TL_ERR_NOMEM if the plan would need more.            */
+} tl_options;
+
+typedef struct tl_plan_s *tl_plan;
+
+/* Create a plan for band limit lmax (>= 0) on the given grid.  hip_stream is a
+ * hipStream_t (NULL = default stream).  Builds the recursion-coefficient and
+ * start-value tables on the device and waits for them.  On failure *plan is
+ * set to NULL. */
+int tl_plan_create(tl_plan *plan, int32_t lmax, tl_grid grid, const tl_options *opt,
+                   void *hip_stream);
+
+/* Release a plan and its workspace (NULL is accepted).  Waits for the plan's
+ * stream first. */
+int tl_plan_destroy(tl_plan plan);
+
+/* Device bytes held by the plan. */
+int tl_plan_workspace_bytes(tl_plan plan, int64_t *bytes);
+
+/* Lens one realization (the full method, eqs. 1, 2, 5):
+ *   alm_T (required), alm_E (required iff opt.pol), alm_B (NULL = 0),
+ *   alm_phi (NULL = no deflection: the unlensed maps).
+ *   T_out, Q_out, U_out: [ntheta][nphi] float64 (TL_FP64) or float32
+ *   (other precisions); Q_out/U_out are ignored when opt.pol = 0. */
+int tl_lens_map(tl_plan plan, const void *alm_T, const void *alm_E, const void *alm_B,
+                const void *alm_phi, void *T_out, void *Q_out, void *U_out);
+
+/* Same remap + Taylor sum at caller-given source positions theta_src,
+ * phi_src ([ntheta][nphi] float64, theta in [0, pi], any real phi).  No
+ * rotation is applied (the positions do not define a transport path). */
+int tl_lens_map_pos(tl_plan plan, const void *alm_T, const void *alm_E, const void *alm_B,
+                    const double *theta_src, const double *phi_src, void *T_out, void *Q_out,
+                    void *U_out);
+
+/* ---- stage entry points (the same kernels tl_lens_map runs) ---- */
+
+/* Deflection alpha = grad phi on the grid (Sec. II.A):
+ * alpha_theta = d_theta phi, alpha_phi = d_phi phi / sin theta, with the
+ * limits +- d_theta d_phi phi on the pole rings.  float64 [ntheta][nphi]. */
+int tl_deflection(tl_plan plan, const void *alm_phi, double *alpha_theta, double *alpha_phi);
+
+/* Harmonic stage: per-ring Fourier coefficients of the theta-derivatives,
+ * F[field][j][ring][m] complex (complex128 for TL_FP64, complex64 otherwise),
+ * field in (T) or (T, Q, U), j = 0..order, m = 0..lmax:
+ *   F^{(j)}_m(theta_i) = sum_l a_lm d^j/dtheta^j lambda_lm(theta_i)   (T)
+ * and the Fourier coefficients of the real Q and U maps likewise. */
+int tl_legendre(tl_plan plan, const void *alm_T, const void *alm_E, const void *alm_B,
+                void *F_out);
+
+/* Derivative maps: D[field][jk][ring][pix] (float64 / float32), jk running
+ * over (j, k) with j + k <= order, j-major (j = 0: k = 0..N; j = 1: k = 0..N-1;
+ * ...), each map SCALED by dtheta^j dphi^k / (j! k!) with dtheta = pi/(ntheta-1),
+ * dphi = 2 pi/nphi:  D = dtheta^j dphi^k/(j!k!) d^j_theta d^k_phi s. */
+int tl_synth_derivs(tl_plan plan, const void *alm_T, const void *alm_E, const void *alm_B,
+                    void *D_out);
+
+/* Remap + Taylor sum + rotation from given scaled derivative maps (layout of
+ * tl_synth_derivs) and deflection maps (layout of tl_deflection). */
+int tl_remap(tl_plan plan, const void *D, const double *alpha_theta, const double *alpha_phi,
+             void *T_out, void *Q_out, void *U_out);
+
+/* Lens n realizations, plans[i] with coefficient pointers alms[4i..4i+3]
+ * (T, E, B, phi) and outputs outs[3i..3i+2] (T, Q, U).  Plans may differ in
+ * lmax and grid.  Queued on plans[0]'s stream in one pass. */
+int tl_lens_map_batch(int32_t n, const tl_plan *plans, const void *const *alms,
+                      void *const *outs);
+
+/* Convenience form with the signature
+ *   lens_map(alm_T, alm_E, alm_B, alm_phi, lmax, order, grid) -> T', Q', U'
+ * (FP32, geodesic positions, rotation on, T+Q/U iff alm_E != NULL): creates a
+ * plan on the default stream, lenses, synchronizes and destroys the plan. */
+int tl_lens_map_simple(const void *alm_T, const void *alm_E, const void *alm_B,
+                       const void *alm_phi, int32_t lmax, int32_t order, tl_grid grid,
+                       void *T_out, void *Q_out, void *U_out);
+
+/* ---- instrumentation ---- */
+
+/* Stages timed by tl_plan_profile: deflection (harmonic + ring FFT of phi),
+ * harmonic stage of T, harmonic stage of Q/U, ring FFTs of the derivative
+ * maps, remap + Taylor sum + rotation. */
+#define TL_NSTAGE 5
+
+/* enable != 0: from now on record a HIP event pair on the plan's stream
+ * around every stage of every call (no synchronization is added); 0: stop.
+ * Either way the accumulated records are cleared. */
+int tl_plan_profile(tl_plan plan, int32_t enable);
+
+/* Synchronize the plan's stream and return, per stage, the summed elapsed
+ * milliseconds (ms[TL_NSTAGE]) and the number of timed launches
+ * (calls[TL_NSTAGE], may be NULL) since profiling was enabled. */
+int tl_plan_stage_times(tl_plan plan, double *ms, int64_t *calls);
+
+/* Thread-local message of the last failure on this thread ("" if none). */
+const char *tl_last_error(void);
+
+/* Library version: major*10000 + minor*100 + patch. */
+int tl_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TAYLENS_H */

@@ -1,0 +1,622 @@
+// C ABI of the taylens library: plans, argument validation, stage sequencing.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "tl_internal.h"
+
+namespace tl {
+
+static thread_local std::string g_err;
+
+void set_error(const std::string &msg) { g_err = msg; }
+
+hipError_t fft_prepare(Plan &p);
+
+}  // namespace tl
+
+using namespace tl;
+
+#define TL_VERSION 10000
+
+namespace {
+
+int fail(int code, const std::string &msg)
+{
+    set_error(msg);
+    return code;
+}
+
+int hipfail(hipError_t e, const char *what)
+{
+    set_error(std::string(what) + ": " + hipGetErrorString(e));
+    return TL_ERR_HIP;
+}
+
+#define TL_HIP(call, what)                           \
+    do {                                             \
+        hipError_t e_ = (call);                      \
+        if (e_ != hipSuccess) return hipfail(e_, what); \
+    } while (0)
+
+// Records a HIP event pair around one stage when the plan is profiling.
+struct StageScope {
+    Plan &p;
+    int stage;
+    hipEvent_t a = nullptr, b = nullptr;
+    StageScope(Plan &pl, int st) : p(pl), stage(st)
+    {
+        if (!p.profile) return;
+        if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
+            a = b = nullptr;
+            return;
+        }
+        (void)hipEventRecord(a, p.stream);
+    }
+    ~StageScope()
+    {
+        if (!a) return;
+        (void)hipEventRecord(b, p.stream);
+        p.prof.push_back({stage, a, b});
+    }
+};
+
+void clear_prof(Plan &p)
+{
+    for (auto &r : p.prof) {
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+    }
+    p.prof.clear();
+}
+
+bool factor_radices(int M, Plan &p)
+{
+    p.nradix = 0;
+    int n = M;
+    while (n % 8 == 0 && n > 1) {
+        p.radix[p.nradix++] = 8;
+        n /= 8;
+    }
+    while (n % 4 == 0 && n > 1) {
+        p.radix[p.nradix++] = 4;
+        n /= 4;
+    }
+    while (n % 2 == 0 && n > 1) {
+        p.radix[p.nradix++] = 2;
+        n /= 2;
+    }
+    while (n % 5 == 0 && n > 1) {
+        p.radix[p.nradix++] = 5;
+        n /= 5;
+    }
+    while (n % 3 == 0 && n > 1) {
+        p.radix[p.nradix++] = 3;
+        n /= 3;
+    }
+    return n == 1 && p.nradix <= 16;
+}
+
+void free_buf(DevBuf &b)
+{
+    if (b.ptr) (void)hipFree(b.ptr);
+    b.ptr = nullptr;
+    b.bytes = 0;
+}
+
+void free_plan_buffers(Plan &p)
+{
+    DevBuf *bufs[] = {&p.theta, &p.trig, &p.phitab, &p.phival, &p.twid64, &p.twid32, &p.coef0, &p.coef2,
+                      &p.start, &p.exps, &p.Fphi, &p.alpha, &p.F, &p.D, &p.jobsDefl, &p.jobsMain};
+    for (DevBuf *b : bufs) free_buf(*b);
+}
+
+int alloc(Plan &p, DevBuf &b, size_t bytes, const char *name)
+{
+    if (bytes == 0) bytes = 16;
+    hipError_t e = hipMalloc(&b.ptr, bytes);
+    if (e != hipSuccess) {
+        b.ptr = nullptr;
+        (void)hipGetLastError();
+        return fail(TL_ERR_NOMEM, std::string("hipMalloc failed for ") + name + " (" +
+                                     std::to_string(bytes) + " bytes): " + hipGetErrorString(e));
+    }
+    b.bytes = bytes;
+    p.total_bytes += bytes;
+    return TL_OK;
+}
+
+int dmap_index(int N, int j, int k) { return j * (N + 1) - j * (j - 1) / 2 + k; }
+
+double factorial(int n)
+{
+    double r = 1.0;
+    for (int i = 2; i <= n; ++i) r *= i;
+    return r;
+}
+
+struct Sizes {
+    size_t theta, trig, phitab, phival, twid64, twid32, coef, start, exps, Fphi, alpha, F, D, jd, jm;
+    size_t total() const
+    {
+        return theta + trig + phitab + phival + twid64 + twid32 + 2 * coef + start + exps + Fphi + alpha + F + D +
+               jd + jm;
+    }
+};
+
+Sizes plan_sizes(const Plan &p)
+{
+    Sizes s;
+    const size_t nalm = p.nalm();
+    const size_t rowc = (size_t)p.ntheta * (p.lmax + 1);
+    const size_t cbytes = p.fp64() ? 16 : 8;
+    const size_t rbytes = p.fp64() ? 8 : 4;
+    s.theta = p.ntheta * sizeof(double);
+    s.trig = p.ntheta * sizeof(double2);
+    s.phitab = p.nphi * sizeof(double2);
+    s.phival = (p.nphi + 1) * sizeof(double);
+    s.twid64 = p.nphi * sizeof(double2);
+    s.twid32 = p.nphi * sizeof(float2);
+    s.coef = nalm * sizeof(double4);
+    s.start = 3 * (size_t)(p.lmax + 1) * p.jtab * p.nrp * sizeof(double);
+    s.exps = 3 * (size_t)(p.lmax + 1) * p.nrp * sizeof(int);
+    s.Fphi = 2 * rowc * 16;
+    s.alpha = 2 * p.npix() * sizeof(double);
+    s.F = (size_t)p.nfield() * (p.order + 1) * rowc * cbytes;
+    s.D = (size_t)p.nfield() * p.ndmap() * p.npix() * rbytes;
+    s.jd = 2 * (size_t)p.ntheta * sizeof(FftJob);
+    s.jm = (size_t)p.nfield() * (p.order + 1) * p.ntheta * sizeof(FftJob);
+    return s;
+}
+
+int validate_options(int32_t lmax, tl_grid grid, const tl_options *opt)
+{
+    if (!opt) return fail(TL_ERR_INVALID, "options pointer is NULL");
+    if (lmax < 0) return fail(TL_ERR_INVALID, "lmax must be >= 0");
+    if (lmax > 16384) return fail(TL_ERR_UNSUPPORTED, "lmax above 16384 is not supported");
+    if (grid.ntheta < 2) return fail(TL_ERR_INVALID, "ntheta must be >= 2");
+    if (grid.nphi < 2 || (grid.nphi & 1)) return fail(TL_ERR_INVALID, "nphi must be even and >= 2");
+    if ((int64_t)grid.nphi < 2 * (int64_t)lmax)
+        return fail(TL_ERR_INVALID, "nphi must be >= 2*lmax (band limit of each ring)");
+    if (opt->order < 0 || opt->order > TL_MAX_ORDER) return fail(TL_ERR_INVALID, "order must be in 0..8");
+    if (opt->precision < TL_FP64 || opt->precision > TL_BF16) return fail(TL_ERR_INVALID, "unknown precision");
+    if (opt->precision != TL_FP64 && opt->precision != TL_FP32)
+        return fail(TL_ERR_UNSUPPORTED, "this precision form is not provided by this build");
+    if (opt->pol != 0 && opt->pol != 1) return fail(TL_ERR_INVALID, "pol must be 0 or 1");
+    if (opt->rotate != 0 && opt->rotate != 1) return fail(TL_ERR_INVALID, "rotate must be 0 or 1");
+    if (opt->naive_pos != 0 && opt->naive_pos != 1) return fail(TL_ERR_INVALID, "naive_pos must be 0 or 1");
+    if (opt->reserved != 0) return fail(TL_ERR_INVALID, "reserved option field must be 0");
+    if (opt->workspace_cap < 0) return fail(TL_ERR_INVALID, "workspace_cap must be >= 0");
+    Plan tmp;
+    if (!factor_radices(grid.nphi / 2, tmp))
+        return fail(TL_ERR_UNSUPPORTED, "nphi/2 must be a product of 2, 3 and 5");
+    return TL_OK;
+}
+
+int build_jobs(Plan &p)
+{
+    const int N = p.order;
+    const double dth = M_PI / (double)(p.ntheta - 1);
+    const double dph = 2.0 * M_PI / (double)p.nphi;
+    const size_t row = (size_t)(p.lmax + 1);
+    // deflection: alpha_theta = d_theta phi (j=1, k=0); alpha_phi = d_phi phi / sin theta
+    // (j=0, k=1), on the pole rings +- d_theta d_phi phi (j=1, k=1).
+    std::vector<FftJob> jd(2 * (size_t)p.ntheta);
+    for (int i = 0; i < p.ntheta; ++i) {
+        FftJob a{};
+        a.src = (int64_t)((size_t)(1 * p.ntheta + i) * row);
+        a.nk = 1;
+        a.k[0] = 0;
+        a.dst[0] = (int64_t)i * p.nphi;
+        a.scale[0] = 1.0;
+        jd[2 * i] = a;
+        FftJob b{};
+        b.nk = 1;
+        b.k[0] = 1;
+        b.dst[0] = (int64_t)((size_t)p.ntheta + i) * p.nphi;
+        if (i == 0 || i == p.ntheta - 1) {
+            b.src = (int64_t)((size_t)(1 * p.ntheta + i) * row);
+            b.scale[0] = (i == 0) ? 1.0 : -1.0;
+        } else {
+            b.src = (int64_t)((size_t)(0 * p.ntheta + i) * row);
+            b.scale[0] = 1.0 / std::sin(M_PI * (double)i / (double)(p.ntheta - 1));
+        }
+        jd[2 * i + 1] = b;
+    }
+    p.njobsDefl = (int)jd.size();
+    std::vector<FftJob> jm((size_t)p.nfield() * (N + 1) * p.ntheta);
+    size_t q = 0;
+    for (int f = 0; f < p.nfield(); ++f)
+        for (int j = 0; j <= N; ++j)
+            for (int i = 0; i < p.ntheta; ++i) {
+                FftJob a{};
+                a.src = (int64_t)((((size_t)f * (N + 1) + j) * p.ntheta + i) * row);
+                a.nk = N - j + 1;
+                for (int k = 0; k <= N - j; ++k) {
+                    a.k[k] = k;
+                    a.dst[k] = (int64_t)((((size_t)f * p.ndmap() + dmap_index(N, j, k)) * p.ntheta + i) * p.nphi);
+                    a.scale[k] = std::pow(dth, j) * std::pow(dph, k) / (factorial(j) * factorial(k));
+                }
+                jm[q++] = a;
+            }
+    p.njobsMain = (int)jm.size();
+    TL_HIP(hipMemcpy(p.jobsDefl.ptr, jd.data(), jd.size() * sizeof(FftJob), hipMemcpyHostToDevice), "jobs copy");
+    TL_HIP(hipMemcpy(p.jobsMain.ptr, jm.data(), jm.size() * sizeof(FftJob), hipMemcpyHostToDevice), "jobs copy");
+    return TL_OK;
+}
+
+int upload_tables(Plan &p)
+{
+    std::vector<double> th(p.ntheta);
+    std::vector<double2> tr(p.ntheta);
+    for (int i = 0; i < p.ntheta; ++i) {
+        th[i] = M_PI * (double)i / (double)(p.ntheta - 1);
+        tr[i] = make_double2(std::cos(th[i]), std::sin(th[i]));
+    }
+    std::vector<double2> pt(p.nphi);
+    std::vector<double> pv(p.nphi + 1);
+    for (int k = 0; k <= p.nphi; ++k) {
+        pv[k] = 2.0 * M_PI * (double)k / (double)p.nphi;
+        if (k < p.nphi) pt[k] = make_double2(std::cos(pv[k]), std::sin(pv[k]));
+    }
+    const int N = p.nphi;  // FFT twiddles e^{2 pi i t / nphi}
+    std::vector<double2> t64(N);
+    std::vector<float2> t32(N);
+    for (int t = 0; t < N; ++t) {
+        long double a = 2.0L * 3.141592653589793238462643383279502884L * (long double)t / (long double)N;
+        t64[t] = make_double2((double)cosl(a), (double)sinl(a));
+        t32[t] = make_float2((float)cosl(a), (float)sinl(a));
+    }
+    TL_HIP(hipMemcpy(p.theta.ptr, th.data(), th.size() * sizeof(double), hipMemcpyHostToDevice), "table copy");
+    TL_HIP(hipMemcpy(p.trig.ptr, tr.data(), tr.size() * sizeof(double2), hipMemcpyHostToDevice), "table copy");
+    TL_HIP(hipMemcpy(p.phitab.ptr, pt.data(), pt.size() * sizeof(double2), hipMemcpyHostToDevice), "table copy");
+    TL_HIP(hipMemcpy(p.phival.ptr, pv.data(), pv.size() * sizeof(double), hipMemcpyHostToDevice), "table copy");
+    TL_HIP(hipMemcpy(p.twid64.ptr, t64.data(), t64.size() * sizeof(double2), hipMemcpyHostToDevice), "table copy");
+    TL_HIP(hipMemcpy(p.twid32.ptr, t32.data(), t32.size() * sizeof(float2), hipMemcpyHostToDevice), "table copy");
+    return TL_OK;
+}
+
+int check_plan(tl_plan plan)
+{
+    if (!plan) return fail(TL_ERR_INVALID, "plan is NULL");
+    return TL_OK;
+}
+
+// deflection into plan.alpha (zeros when alm_phi is NULL)
+int run_deflection(Plan &p, const void *alm_phi)
+{
+    if (!alm_phi) {
+        TL_HIP(hipMemsetAsync(p.alpha.ptr, 0, p.alpha.bytes, p.stream), "alpha clear");
+        return TL_OK;
+    }
+    StageScope sc(p, 0);
+    TL_HIP(launch_legendre_scalar(p, 1, alm_phi, p.Fphi.ptr, true), "deflection legendre");
+    TL_HIP(launch_fft_jobs(p, p.Fphi.ptr, p.alpha.ptr, (const FftJob *)p.jobsDefl.ptr, p.njobsDefl, true),
+           "deflection fft");
+    return TL_OK;
+}
+
+int run_legendre(Plan &p, const void *T, const void *E, const void *B, void *Fout)
+{
+    const size_t rowc = (size_t)p.ntheta * (p.lmax + 1) * (p.order + 1);
+    const size_t cb = p.fp64() ? 16 : 8;
+    char *F = (char *)Fout;
+    {
+        StageScope sc(p, 1);
+        TL_HIP(launch_legendre_scalar(p, p.order, T, F, p.fp64()), "legendre T");
+    }
+    if (p.pol) {
+        StageScope sc(p, 2);
+        TL_HIP(launch_legendre_spin(p, p.order, E, B, F + rowc * cb, F + 2 * rowc * cb, p.fp64()), "legendre QU");
+    }
+    return TL_OK;
+}
+
+int run_derivs(Plan &p, const void *T, const void *E, const void *B, void *Dout)
+{
+    int rc = run_legendre(p, T, E, B, p.F.ptr);
+    if (rc) return rc;
+    StageScope sc(p, 3);
+    TL_HIP(launch_fft_jobs(p, p.F.ptr, Dout, (const FftJob *)p.jobsMain.ptr, p.njobsMain, p.fp64()), "ring fft");
+    return TL_OK;
+}
+
+int check_fields(const Plan &p, const void *T, const void *E)
+{
+    if (!T) return fail(TL_ERR_INVALID, "alm_T is NULL");
+    if (p.pol && !E) return fail(TL_ERR_INVALID, "alm_E is NULL for a polarized plan");
+    return TL_OK;
+}
+
+int check_outputs(const Plan &p, const void *T, const void *Q, const void *U)
+{
+    if (!T) return fail(TL_ERR_INVALID, "T_out is NULL");
+    if (p.pol && (!Q || !U)) return fail(TL_ERR_INVALID, "Q_out/U_out are NULL for a polarized plan");
+    return TL_OK;
+}
+
+int set_device_of(Plan &p)
+{
+    int cur = 0;
+    TL_HIP(hipGetDevice(&cur), "hipGetDevice");
+    if (cur != p.device) TL_HIP(hipSetDevice(p.device), "hipSetDevice");
+    return TL_OK;
+}
+
+}  // namespace
+
+struct tl_plan_s {
+    Plan p;
+};
+
+extern "C" {
+
+int tl_version(void) { return TL_VERSION; }
+
+const char *tl_last_error(void) { return g_err.c_str(); }
+
+int tl_plan_create(tl_plan *out, int32_t lmax, tl_grid grid, const tl_options *opt, void *hip_stream)
+{
+    if (!out) return fail(TL_ERR_INVALID, "plan output pointer is NULL");
+    *out = nullptr;
+    int rc = validate_options(lmax, grid, opt);
+    if (rc) return rc;
+
+    tl_plan_s *h = new (std::nothrow) tl_plan_s();
+    if (!h) return fail(TL_ERR_NOMEM, "host allocation failed");
+    Plan &p = h->p;
+    p.lmax = lmax;
+    p.ntheta = grid.ntheta;
+    p.nphi = grid.nphi;
+    p.nrp = (grid.ntheta + 1) / 2;
+    p.order = opt->order;
+    p.jtab = (opt->order > 1 ? opt->order : 1) + 1;
+    p.precision = opt->precision;
+    p.pol = opt->pol;
+    p.rotate = opt->rotate;
+    p.naive = opt->naive_pos;
+    p.cap = opt->workspace_cap;
+    p.stream = (hipStream_t)hip_stream;
+    factor_radices(p.nphi / 2, p);
+
+    Sizes sz = plan_sizes(p);
+    if (p.cap > 0 && sz.total() > (size_t)p.cap) {
+        delete h;
+        return fail(TL_ERR_NOMEM, "plan needs " + std::to_string(sz.total()) + " bytes, above workspace_cap " +
+                                      std::to_string(p.cap));
+    }
+    hipError_t e = hipGetDevice(&p.device);
+    if (e != hipSuccess) {
+        delete h;
+        return hipfail(e, "hipGetDevice");
+    }
+    {
+        int smem = 0;
+        e = hipDeviceGetAttribute(&smem, hipDeviceAttributeMaxSharedMemoryPerBlock, p.device);
+        if (e != hipSuccess) {
+            delete h;
+            return hipfail(e, "hipDeviceGetAttribute");
+        }
+        const size_t need64 = 2 * (size_t)(p.nphi / 2) * sizeof(double2);
+        if (need64 > (size_t)smem) {
+            delete h;
+            return fail(TL_ERR_UNSUPPORTED, "nphi too large for the FP64 ring FFT in LDS on this device (" +
+                                                std::to_string(need64) + " > " + std::to_string(smem) + " bytes)");
+        }
+    }
+    struct {
+        DevBuf *b;
+        size_t n;
+        const char *name;
+    } list[] = {{&p.theta, sz.theta, "theta"},   {&p.trig, sz.trig, "trig"},       {&p.phitab, sz.phitab, "phitab"},
+                {&p.phival, sz.phival, "phival"}, {&p.twid64, sz.twid64, "twid64"}, {&p.twid32, sz.twid32, "twid32"},
+                {&p.coef0, sz.coef, "coef0"},    {&p.coef2, sz.coef, "coef2"},     {&p.start, sz.start, "start"},
+                {&p.exps, sz.exps, "exps"},      {&p.Fphi, sz.Fphi, "Fphi"},       {&p.alpha, sz.alpha, "alpha"},
+                {&p.F, sz.F, "F"},               {&p.D, sz.D, "D"},                {&p.jobsDefl, sz.jd, "jobsDefl"},
+                {&p.jobsMain, sz.jm, "jobsMain"}};
+    for (auto &it : list) {
+        rc = alloc(p, *it.b, it.n, it.name);
+        if (rc) {
+            free_plan_buffers(p);
+            delete h;
+            return rc;
+        }
+    }
+    auto bail = [&](int code) {
+        free_plan_buffers(p);
+        delete h;
+        return code;
+    };
+    if ((rc = upload_tables(p))) return bail(rc);
+    if ((rc = build_jobs(p))) return bail(rc);
+    e = hipMemsetAsync(p.start.ptr, 0, p.start.bytes, p.stream);
+    if (e == hipSuccess) e = hipMemsetAsync(p.exps.ptr, 0, p.exps.bytes, p.stream);
+    if (e == hipSuccess) e = launch_tables(p);
+    if (e == hipSuccess) e = fft_prepare(p);
+    if (e == hipSuccess) e = hipStreamSynchronize(p.stream);
+    if (e != hipSuccess) return bail(hipfail(e, "plan tables"));
+    *out = h;
+    return TL_OK;
+}
+
+int tl_plan_destroy(tl_plan plan)
+{
+    if (!plan) return TL_OK;
+    Plan &p = plan->p;
+    (void)set_device_of(p);
+    (void)hipStreamSynchronize(p.stream);
+    clear_prof(p);
+    free_plan_buffers(p);
+    delete plan;
+    return TL_OK;
+}
+
+int tl_plan_profile(tl_plan plan, int32_t enable)
+{
+    if (check_plan(plan)) return TL_ERR_INVALID;
+    Plan &p = plan->p;
+    int rc = set_device_of(p);
+    if (rc) return rc;
+    TL_HIP(hipStreamSynchronize(p.stream), "synchronize");
+    clear_prof(p);
+    p.profile = enable != 0;
+    return TL_OK;
+}
+
+int tl_plan_stage_times(tl_plan plan, double *ms, int64_t *calls)
+{
+    if (check_plan(plan)) return TL_ERR_INVALID;
+    if (!ms) return fail(TL_ERR_INVALID, "ms is NULL");
+    Plan &p = plan->p;
+    int rc = set_device_of(p);
+    if (rc) return rc;
+    TL_HIP(hipStreamSynchronize(p.stream), "synchronize");
+    for (int i = 0; i < TL_NSTAGE; ++i) {
+        ms[i] = 0.0;
+        if (calls) calls[i] = 0;
+    }
+    for (auto &r : p.prof) {
+        float t = 0.f;
+        TL_HIP(hipEventElapsedTime(&t, r.a, r.b), "event time");
+        ms[r.stage] += t;
+        if (calls) calls[r.stage] += 1;
+    }
+    return TL_OK;
+}
+
+int tl_plan_workspace_bytes(tl_plan plan, int64_t *bytes)
+{
+    if (check_plan(plan)) return TL_ERR_INVALID;
+    if (!bytes) return fail(TL_ERR_INVALID, "bytes pointer is NULL");
+    *bytes = (int64_t)plan->p.total_bytes;
+    return TL_OK;
+}
+
+int tl_deflection(tl_plan plan, const void *alm_phi, double *alpha_theta, double *alpha_phi)
+{
+    if (check_plan(plan)) return TL_ERR_INVALID;
+    Plan &p = plan->p;
+    if (!alm_phi || !alpha_theta || !alpha_phi) return fail(TL_ERR_INVALID, "NULL argument");
+    int rc = set_device_of(p);
+    if (rc) return rc;
+    if ((rc = run_deflection(p, alm_phi))) return rc;
+    const size_t bytes = p.npix() * sizeof(double);
+    TL_HIP(hipMemcpyAsync(alpha_theta, p.alpha.ptr, bytes, hipMemcpyDeviceToDevice, p.stream), "copy");
+    TL_HIP(hipMemcpyAsync(alpha_phi, (char *)p.alpha.ptr + bytes, bytes, hipMemcpyDeviceToDevice, p.stream), "copy");
+    return TL_OK;
+}
+
+int tl_legendre(tl_plan plan, const void *alm_T, const void *alm_E, const void *alm_B, void *F_out)
+{
+    if (check_plan(plan)) return TL_ERR_INVALID;
+    Plan &p = plan->p;
+    int rc = check_fields(p, alm_T, alm_E);
+    if (rc) return rc;
+    if (!F_out) return fail(TL_ERR_INVALID, "F_out is NULL");
+    if ((rc = set_device_of(p))) return rc;
+    return run_legendre(p, alm_T, alm_E, alm_B, F_out);
+}
+
+int tl_synth_derivs(tl_plan plan, const void *alm_T, const void *alm_E, const void *alm_B, void *D_out)
+{
+    if (check_plan(plan)) return TL_ERR_INVALID;
+    Plan &p = plan->p;
+    int rc = check_fields(p, alm_T, alm_E);
+    if (rc) return rc;
+    if (!D_out) return fail(TL_ERR_INVALID, "D_out is NULL");
+    if ((rc = set_device_of(p))) return rc;
+    return run_derivs(p, alm_T, alm_E, alm_B, D_out);
+}
+
+int tl_remap(tl_plan plan, const void *D, const double *alpha_theta, const double *alpha_phi, void *T_out,
+             void *Q_out, void *U_out)
+{
+    if (check_plan(plan)) return TL_ERR_INVALID;
+    Plan &p = plan->p;
+    if (!D || !alpha_theta || !alpha_phi) return fail(TL_ERR_INVALID, "NULL argument");
+    int rc = check_outputs(p, T_out, Q_out, U_out);
+    if (rc) return rc;
+    if ((rc = set_device_of(p))) return rc;
+    TL_HIP(launch_remap(p, D, alpha_theta, alpha_phi, nullptr, nullptr, T_out, Q_out, U_out), "remap");
+    return TL_OK;
+}
+
+int tl_lens_map(tl_plan plan, const void *alm_T, const void *alm_E, const void *alm_B, const void *alm_phi,
+                void *T_out, void *Q_out, void *U_out)
+{
+    if (check_plan(plan)) return TL_ERR_INVALID;
+    Plan &p = plan->p;
+    int rc = check_fields(p, alm_T, alm_E);
+    if (rc) return rc;
+    if ((rc = check_outputs(p, T_out, Q_out, U_out))) return rc;
+    if ((rc = set_device_of(p))) return rc;
+    if ((rc = run_deflection(p, alm_phi))) return rc;
+    if ((rc = run_derivs(p, alm_T, alm_E, alm_B, p.D.ptr))) return rc;
+    const double *at = (const double *)p.alpha.ptr;
+    StageScope sc(p, 4);
+    TL_HIP(launch_remap(p, p.D.ptr, at, at + p.npix(), nullptr, nullptr, T_out, Q_out, U_out), "remap");
+    return TL_OK;
+}
+
+int tl_lens_map_pos(tl_plan plan, const void *alm_T, const void *alm_E, const void *alm_B, const double *theta_src,
+                    const double *phi_src, void *T_out, void *Q_out, void *U_out)
+{
+    if (check_plan(plan)) return TL_ERR_INVALID;
+    Plan &p = plan->p;
+    int rc = check_fields(p, alm_T, alm_E);
+    if (rc) return rc;
+    if (!theta_src || !phi_src) return fail(TL_ERR_INVALID, "position pointers are NULL");
+    if ((rc = check_outputs(p, T_out, Q_out, U_out))) return rc;
+    if ((rc = set_device_of(p))) return rc;
+    if ((rc = run_derivs(p, alm_T, alm_E, alm_B, p.D.ptr))) return rc;
+    TL_HIP(launch_remap(p, p.D.ptr, nullptr, nullptr, theta_src, phi_src, T_out, Q_out, U_out), "remap");
+    return TL_OK;
+}
+
+int tl_lens_map_batch(int32_t n, const tl_plan *plans, const void *const *alms, void *const *outs)
+{
+    if (n < 0) return fail(TL_ERR_INVALID, "n must be >= 0");
+    if (n == 0) return TL_OK;
+    if (!plans || !alms || !outs) return fail(TL_ERR_INVALID, "NULL argument");
+    for (int i = 0; i < n; ++i) {
+        if (!plans[i]) return fail(TL_ERR_INVALID, "plan " + std::to_string(i) + " is NULL");
+        int rc = check_fields(plans[i]->p, alms[4 * i], alms[4 * i + 1]);
+        if (rc) return rc;
+        if ((rc = check_outputs(plans[i]->p, outs[3 * i], outs[3 * i + 1], outs[3 * i + 2]))) return rc;
+    }
+    hipStream_t s0 = plans[0]->p.stream;
+    for (int i = 0; i < n; ++i) {
+        Plan &p = plans[i]->p;
+        hipStream_t keep = p.stream;
+        p.stream = s0;
+        int rc = tl_lens_map(plans[i], alms[4 * i], alms[4 * i + 1], alms[4 * i + 2], alms[4 * i + 3], outs[3 * i],
+                             outs[3 * i + 1], outs[3 * i + 2]);
+        p.stream = keep;
+        if (rc) return rc;
+    }
+    return TL_OK;
+}
+
+int tl_lens_map_simple(const void *alm_T, const void *alm_E, const void *alm_B, const void *alm_phi, int32_t lmax,
+                       int32_t order, tl_grid grid, void *T_out, void *Q_out, void *U_out)
+{
+    tl_options o{};
+    o.order = order;
+    o.precision = TL_FP32;
+    o.pol = alm_E != nullptr;
+    o.rotate = 1;
+    tl_plan plan = nullptr;
+    int rc = tl_plan_create(&plan, lmax, grid, &o, nullptr);
+    if (rc) return rc;
+    rc = tl_lens_map(plan, alm_T, alm_E, alm_B, alm_phi, T_out, Q_out, U_out);
+    if (rc == TL_OK) {
+        hipError_t e = hipStreamSynchronize(nullptr);
+        if (e != hipSuccess) rc = hipfail(e, "synchronize");
+    }
+    tl_plan_destroy(plan);
+    return rc;
+}
+
+}  // extern "C"

@@ -1,0 +1,588 @@
+// Harmonic (Legendre) stage of Taylor lensing on gfx950.
+//
+// For every m and ring the stage forms the theta-derivatives of the per-m
+// Fourier coefficients of the unlensed fields (the derivative inputs of the
+// pixel-relative Taylor expansion, eqs. 4-5 of Naess & Louis 2013),
+//
+//     F^{(j)}_m(theta) = sum_{l>=m} a_lm d^j/dtheta^j s_lambda_lm(theta),  j = 0..J,
+//
+// for spin s = 0 (T) and s = +-2 (Q/U).  s_lambda_lm obeys, at fixed (m, s),
+//     lam_L = a_L (cos t + b_L) lam_{L-1} - c_L lam_{L-2}
+// with a_L = sqrt((2L+1)(2L-1)) L / R_L,  b_L = m s / (L(L-1)),
+// c_L = sqrt((2L+1)/(2L-3)) L R_{L-1} / ((L-1) R_L), R_L = sqrt((L^2-m^2)(L^2-s^2)).
+// Differentiating every step by Leibniz' rule gives the recursion of all
+// derivative orders at once: d^j[(cos t + b) p] = b p^{(j)} + sum_i C(j,i) cos^{(i)} p^{(j-i)}.
+//
+// Design:
+//  * one lane per ring pair (theta, pi - theta): the north/south values come
+//    from the parity lam(pi - t) = (-1)^{l+m+j} lam(t) (spin: the opposite spin
+//    family), so the recursion runs once per pair;
+//  * one wave per m; eight waves (eight consecutive m) per workgroup so that
+//    the F[.][ring][m] writes of a workgroup fill whole cache lines;
+//  * all recursion arithmetic in FP64 registers; a_lm and the recursion
+//    coefficients are wave-uniform (scalar loads);
+//  * underflow of sin^m t for large m: values are kept as mantissa * 2^(-512 e)
+//    with an integer e per lane and family; e > 0 means "below 2^-256, not
+//    accumulated"; the start values at l = max(m, |s|) come from a plan-time
+//    table built by an m-recursion with the same scaling.
+#include "tl_internal.h"
+
+namespace tl {
+
+namespace {
+
+constexpr double kHi = 0x1p256;
+constexpr double kLo = 0x1p-256;
+constexpr double kUp = 0x1p512;
+constexpr double kDown = 0x1p-512;
+
+__host__ __device__ constexpr double binom(int n, int k)
+{
+    double r = 1.0;
+    for (int i = 1; i <= k; ++i) r = r * (double)(n - k + i) / (double)i;
+    return r;
+}
+
+// d^i/dt^i cos t  and  d^i/dt^i sin t
+__device__ __forceinline__ double cosd(double c, double s, int i)
+{
+    switch (i & 3) {
+    case 0: return c;
+    case 1: return -s;
+    case 2: return -c;
+    default: return s;
+    }
+}
+__device__ __forceinline__ double sind(double c, double s, int i)
+{
+    switch (i & 3) {
+    case 0: return s;
+    case 1: return c;
+    case 2: return -s;
+    default: return -c;
+    }
+}
+
+// ------------------------------------------------------------ tables ----
+
+// Recursion coefficients {a, b, c, 0} for spin 0 and spin +2 at every (l, m)
+// of the triangular layout (entries with l <= l_min hold zeros; b of spin -2
+// is -b of spin +2).
+__global__ void k_coef(int lmax, double4 *__restrict__ coef0, double4 *__restrict__ coef2)
+{
+    const int m = blockIdx.y;
+    const size_t base = (size_t)m * (2 * lmax + 1 - m) / 2;
+    for (int L = m + threadIdx.x + blockIdx.x * blockDim.x; L <= lmax; L += blockDim.x * gridDim.x) {
+        double4 c0 = make_double4(0, 0, 0, 0), c2 = make_double4(0, 0, 0, 0);
+        const double dL = L, dm = m;
+        if (L >= m + 1) {
+            // spin 0: a = sqrt((4L^2-1)/(L^2-m^2)), c = sqrt((2L+1)/(2L-3) ((L-1)^2-m^2)/(L^2-m^2))
+            const double q = dL * dL - dm * dm;
+            c0.x = sqrt((4.0 * dL * dL - 1.0) / q);
+            if (L >= m + 2) {
+                const double K = L - 1;
+                c0.z = sqrt((2.0 * dL + 1.0) / (2.0 * dL - 3.0) * ((K * K - dm * dm) / q));
+            }
+        }
+        const int lmin2 = m > 2 ? m : 2;
+        if (L >= lmin2 + 1) {
+            const double qm = dL * dL - dm * dm, qs = dL * dL - 4.0;
+            c2.x = sqrt((2.0 * dL + 1.0) * (2.0 * dL - 1.0) * dL * dL / (qm * qs));
+            c2.y = (m == 0) ? 0.0 : 2.0 * dm / (dL * (dL - 1.0));
+            if (L >= lmin2 + 2) {
+                const double K = L - 1;
+                c2.z = sqrt((2.0 * dL + 1.0) / (2.0 * dL - 3.0) * (dL * dL) / (K * K) *
+                            ((K * K - dm * dm) / qm) * ((K * K - 4.0) / qs));
+            }
+        }
+        coef0[base + L] = c0;
+        coef2[base + L] = c2;
+    }
+}
+
+// Start values lam^{(j)}_{l_min, m}(theta_r) for every m, as (mantissa, e):
+// family 0: spin 0, l_min = m; family 1/2: spin +2/-2, l_min = max(m, 2).
+//   lambda_00 = 1/sqrt(4 pi), lambda_mm = -sqrt((2m+1)/(2m)) sin t lambda_{m-1,m-1};
+//   s = +-2: m = 0: sqrt(5/4pi) sqrt(6)/4 sin^2 t;  m = 1: -+ sqrt(5/4pi) sin t g;
+//   m = 2: sqrt(5/4pi) g^2 with g = sin^2(t/2) (s=+2), cos^2(t/2) (s=-2);
+//   m >= 3: -sqrt((2m+1) m / (2(m^2-4))) sin t lam_{m-1}.
+// Products only, derivatives by Leibniz (no cancellation at small t).
+template <int J>
+__global__ void k_start(int lmax, int nrp, int jtab, const double2 *__restrict__ trig,
+                        const double *__restrict__ theta, double *__restrict__ start,
+                        int *__restrict__ exps)
+{
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    const int fam = blockIdx.y;
+    if (r >= nrp) return;
+    const double c = trig[r].x, s = trig[r].y;
+    double sd[J + 1];
+#pragma unroll
+    for (int i = 0; i <= J; ++i) sd[i] = sind(c, s, i);
+
+    double *st = start + (size_t)fam * (lmax + 1) * jtab * nrp;
+    int *ex = exps + (size_t)fam * (lmax + 1) * nrp;
+    auto put = [&](int m, const double(&v)[J + 1], int e) {
+#pragma unroll
+        for (int j = 0; j <= J; ++j) st[((size_t)m * jtab + j) * nrp + r] = v[j];
+        ex[(size_t)m * nrp + r] = e;
+    };
+    auto leib = [&](const double(&a)[J + 1], const double(&b)[J + 1], double(&o)[J + 1]) {
+#pragma unroll
+        for (int j = 0; j <= J; ++j) {
+            double acc = 0.0;
+#pragma unroll
+            for (int i = 0; i <= j; ++i) acc = fma(binom(j, i) * a[i], b[j - i], acc);
+            o[j] = acc;
+        }
+    };
+    auto renorm_up = [&](double(&v)[J + 1], int &e) {
+        double mx = 0.0;
+#pragma unroll
+        for (int j = 0; j <= J; ++j) mx = fmax(mx, fabs(v[j]));
+        if (mx != 0.0 && mx < kLo) {
+#pragma unroll
+            for (int j = 0; j <= J; ++j) v[j] *= kUp;
+            e += 1;
+        }
+    };
+
+    const double k5 = sqrt(5.0 / (4.0 * M_PI));
+    double prev[J + 1], cur[J + 1];
+    int e = 0;
+    int m0;
+    if (fam == 0) {
+#pragma unroll
+        for (int j = 0; j <= J; ++j) prev[j] = 0.0;
+        prev[0] = 1.0 / sqrt(4.0 * M_PI);
+        put(0, prev, 0);
+        m0 = 1;
+    } else {
+        if (lmax < 2) {
+            // nothing: spin-2 functions need l >= 2
+            return;
+        }
+        const double t = theta[r];
+        const double sh = sin(0.5 * t), ch = cos(0.5 * t);
+        double g[J + 1];
+#pragma unroll
+        for (int i = 0; i <= J; ++i)
+            g[i] = (i == 0) ? ((fam == 1) ? sh * sh : ch * ch)
+                            : ((fam == 1) ? -0.5 : 0.5) * cosd(c, s, i);
+        double v[J + 1];
+        leib(sd, sd, v);
+#pragma unroll
+        for (int j = 0; j <= J; ++j) v[j] *= k5 * sqrt(6.0) * 0.25;
+        put(0, v, 0);
+        leib(sd, g, v);
+#pragma unroll
+        for (int j = 0; j <= J; ++j) v[j] *= (fam == 1) ? -k5 : k5;
+        put(1, v, 0);
+        leib(g, g, prev);
+#pragma unroll
+        for (int j = 0; j <= J; ++j) prev[j] *= k5;
+        put(2, prev, 0);
+        m0 = 3;
+    }
+    for (int m = m0; m <= lmax; ++m) {
+        const double dm = m;
+        const double f = (fam == 0) ? -sqrt((2.0 * dm + 1.0) / (2.0 * dm))
+                                    : -sqrt((2.0 * dm + 1.0) * dm / (2.0 * (dm * dm - 4.0)));
+        leib(sd, prev, cur);
+#pragma unroll
+        for (int j = 0; j <= J; ++j) prev[j] = f * cur[j];
+        renorm_up(prev, e);
+        put(m, prev, e);
+    }
+}
+
+// ------------------------------------------------------------ recursion --
+
+template <int J>
+struct Rec {
+    double p1[J + 1], p2[J + 1];
+    int e;
+};
+
+template <int J>
+__device__ __forceinline__ void rec_step(Rec<J> &st, double4 cf, double xb, const double (&w)[J + 1][J + 1])
+{
+    double cur[J + 1];
+#pragma unroll
+    for (int j = 0; j <= J; ++j) {
+        double t = xb * st.p1[j];
+#pragma unroll
+        for (int i = 1; i <= j; ++i) t = fma(w[j][i], st.p1[j - i], t);
+        cur[j] = fma(cf.x, t, -cf.z * st.p2[j]);
+    }
+#pragma unroll
+    for (int j = 0; j <= J; ++j) {
+        st.p2[j] = st.p1[j];
+        st.p1[j] = cur[j];
+    }
+}
+
+template <int J>
+__device__ __forceinline__ void renorm_down(Rec<J> &st)
+{
+    double mx = 0.0;
+#pragma unroll
+    for (int j = 0; j <= J; ++j) mx = fmax(mx, fmax(fabs(st.p1[j]), fabs(st.p2[j])));
+    if (mx > kHi) {
+#pragma unroll
+        for (int j = 0; j <= J; ++j) {
+            st.p1[j] *= kDown;
+            st.p2[j] *= kDown;
+        }
+        st.e -= 1;
+    }
+}
+
+template <int J, int NR>
+__device__ __forceinline__ void accum(double2 (&acc)[NR][J + 1], const double2 (&a)[NR], const double (&p)[J + 1])
+{
+#pragma unroll
+    for (int q = 0; q < NR; ++q)
+#pragma unroll
+        for (int j = 0; j <= J; ++j) {
+            acc[q][j].x = fma(a[q].x, p[j], acc[q][j].x);
+            acc[q][j].y = fma(a[q].y, p[j], acc[q][j].y);
+        }
+}
+
+template <int NR>
+__device__ __forceinline__ void load_rhs(double2 (&a)[NR], const double2 *__restrict__ r0,
+                                         const double2 *__restrict__ r1, int l)
+{
+    a[0] = r0[l];
+    if constexpr (NR > 1) a[1] = r1[l];
+}
+
+// Run one family over l = lmin..lmax, accumulating into accE (l even) and
+// accO (l odd).  rhs pointers and coef are based at (l = 0, m) of the
+// triangular layout.  bsgn multiplies the table's b (spin -2: -1).
+template <int J, int NR>
+__device__ void run_family(int lmin, int lmax, double x, double bsgn, const double (&w)[J + 1][J + 1],
+                           const double4 *__restrict__ coef, const double2 *__restrict__ r0,
+                           const double2 *__restrict__ r1, Rec<J> &st, double2 (&accE)[NR][J + 1],
+                           double2 (&accO)[NR][J + 1])
+{
+    double2 a[NR];
+    if (lmin > lmax) return;
+    if (st.e == 0) {
+        load_rhs<NR>(a, r0, r1, lmin);
+        if (lmin & 1) accum<J, NR>(accO, a, st.p1);
+        else accum<J, NR>(accE, a, st.p1);
+    }
+    int l = lmin + 1;
+    if (l <= lmax && (l & 1)) {
+        double4 cf = coef[l];
+        rec_step<J>(st, cf, x + bsgn * cf.y, w);
+        if (st.e > 0) renorm_down<J>(st);
+        if (st.e == 0) {
+            load_rhs<NR>(a, r0, r1, l);
+            accum<J, NR>(accO, a, st.p1);
+        }
+        ++l;
+    }
+    for (; l + 1 <= lmax; l += 2) {
+        double4 cf = coef[l];
+        rec_step<J>(st, cf, x + bsgn * cf.y, w);
+        if (st.e == 0) {
+            load_rhs<NR>(a, r0, r1, l);
+            accum<J, NR>(accE, a, st.p1);
+        }
+        cf = coef[l + 1];
+        rec_step<J>(st, cf, x + bsgn * cf.y, w);
+        if (st.e == 0) {
+            load_rhs<NR>(a, r0, r1, l + 1);
+            accum<J, NR>(accO, a, st.p1);
+        }
+        if (st.e > 0) renorm_down<J>(st);
+    }
+    if (l <= lmax) {
+        double4 cf = coef[l];
+        rec_step<J>(st, cf, x + bsgn * cf.y, w);
+        if (st.e > 0) renorm_down<J>(st);
+        if (st.e == 0) {
+            load_rhs<NR>(a, r0, r1, l);
+            accum<J, NR>(accE, a, st.p1);
+        }
+    }
+}
+
+template <int J>
+__device__ __forceinline__ void leibniz_weights(double c, double s, double (&w)[J + 1][J + 1])
+{
+#pragma unroll
+    for (int j = 0; j <= J; ++j)
+#pragma unroll
+        for (int i = 0; i <= J; ++i) w[j][i] = (i <= j) ? binom(j, i) * cosd(c, s, i) : 0.0;
+}
+
+template <int J>
+__device__ __forceinline__ void load_start(Rec<J> &st, const double *__restrict__ start,
+                                           const int *__restrict__ exps, int fam, int m, int lmax,
+                                           int jtab, int nrp, int r)
+{
+    const double *sb = start + ((size_t)fam * (lmax + 1) + m) * jtab * nrp;
+#pragma unroll
+    for (int j = 0; j <= J; ++j) {
+        st.p1[j] = sb[(size_t)j * nrp + r];
+        st.p2[j] = 0.0;
+    }
+    st.e = exps[((size_t)fam * (lmax + 1) + m) * nrp + r];
+}
+
+template <typename FT>
+__device__ __forceinline__ void store_c(FT *F, size_t idx, double2 v);
+template <>
+__device__ __forceinline__ void store_c<double>(double *F, size_t idx, double2 v)
+{
+    reinterpret_cast<double2 *>(F)[idx] = v;
+}
+template <>
+__device__ __forceinline__ void store_c<float>(float *F, size_t idx, double2 v)
+{
+    reinterpret_cast<float2 *>(F)[idx] = make_float2((float)v.x, (float)v.y);
+}
+
+// Scalar field: F[j][ring][m] = sum_l a_lm d^j lambda_lm(theta_ring).
+template <int J, typename FT>
+__global__ __launch_bounds__(512) void k_legendre_scalar(
+    int lmax, int ntheta, int nrp, int jtab, const double2 *__restrict__ trig,
+    const double4 *__restrict__ coef0, const double *__restrict__ start, const int *__restrict__ exps,
+    const double2 *__restrict__ alm, FT *__restrict__ F)
+{
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int m = blockIdx.y * 8 + wave;
+    const int r = blockIdx.x * 64 + (threadIdx.x & 63);
+    if (m > lmax || r >= nrp) return;
+    const double c = trig[r].x, s = trig[r].y;
+    double w[J + 1][J + 1];
+    leibniz_weights<J>(c, s, w);
+    const size_t base = (size_t)m * (2 * lmax + 1 - m) / 2;
+
+    Rec<J> st;
+    load_start<J>(st, start, exps, 0, m, lmax, jtab, nrp, r);
+    double2 accE[1][J + 1], accO[1][J + 1];
+#pragma unroll
+    for (int j = 0; j <= J; ++j) accE[0][j] = accO[0][j] = make_double2(0, 0);
+    run_family<J, 1>(m, lmax, c, 0.0, w, coef0 + base, alm + base, nullptr, st, accE, accO);
+
+    const bool modd = m & 1;
+    const size_t plane = (size_t)ntheta * (lmax + 1);
+    const int rs = ntheta - 1 - r;
+#pragma unroll
+    for (int j = 0; j <= J; ++j) {
+        const double2 ev = modd ? accO[0][j] : accE[0][j];  // l + m even
+        const double2 od = modd ? accE[0][j] : accO[0][j];
+        store_c<FT>(F, j * plane + (size_t)r * (lmax + 1) + m, make_double2(ev.x + od.x, ev.y + od.y));
+        if (rs != r) {
+            const double sg = (j & 1) ? -1.0 : 1.0;
+            store_c<FT>(F, j * plane + (size_t)rs * (lmax + 1) + m,
+                        make_double2(sg * (ev.x - od.x), sg * (ev.y - od.y)));
+        }
+    }
+}
+
+// i * z
+__device__ __forceinline__ double2 mul_i(double2 z) { return make_double2(-z.y, z.x); }
+__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ double2 cscale(double2 a, double s) { return make_double2(a.x * s, a.y * s); }
+
+// Spin-2 field from E (and B): FQ/FU[j][ring][m] = Fourier coefficients of
+// d^j Q and d^j U with
+//   P_m = -sum (E + iB) 2lam,  M_m = -sum (E - iB) (-2)lam,
+//   Q_m = (P_m + M_m)/2,       U_m = (P_m - M_m)/(2i),
+// and, at the south ring, 2lam^{(j)}(pi - t) = (-1)^{l+m+j} (-2)lam^{(j)}(t).
+template <int J, bool HASB, typename FT>
+__global__ __launch_bounds__(512) void k_legendre_spin(
+    int lmax, int ntheta, int nrp, int jtab, const double2 *__restrict__ trig,
+    const double4 *__restrict__ coef2, const double *__restrict__ start, const int *__restrict__ exps,
+    const double2 *__restrict__ almE, const double2 *__restrict__ almB, FT *__restrict__ FQ,
+    FT *__restrict__ FU)
+{
+    constexpr int NR = HASB ? 2 : 1;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int m = blockIdx.y * 8 + wave;
+    const int r = blockIdx.x * 64 + (threadIdx.x & 63);
+    if (m > lmax || r >= nrp) return;
+    const double c = trig[r].x, s = trig[r].y;
+    double w[J + 1][J + 1];
+    leibniz_weights<J>(c, s, w);
+    const size_t base = (size_t)m * (2 * lmax + 1 - m) / 2;
+    const int lmin = m > 2 ? m : 2;
+    const bool modd = m & 1;
+
+    double2 PN[J + 1], MS[J + 1];
+    {
+        Rec<J> st;
+        load_start<J>(st, start, exps, 1, m, lmax, jtab, nrp, r);
+        double2 accE[NR][J + 1], accO[NR][J + 1];
+#pragma unroll
+        for (int q = 0; q < NR; ++q)
+#pragma unroll
+            for (int j = 0; j <= J; ++j) accE[q][j] = accO[q][j] = make_double2(0, 0);
+        run_family<J, NR>(lmin, lmax, c, 1.0, w, coef2 + base, almE + base, HASB ? almB + base : nullptr,
+                          st, accE, accO);
+#pragma unroll
+        for (int j = 0; j <= J; ++j) {
+            const double2 Ee = modd ? accO[0][j] : accE[0][j], Eo = modd ? accE[0][j] : accO[0][j];
+            double2 Be = make_double2(0, 0), Bo = make_double2(0, 0);
+            if constexpr (HASB) {
+                Be = modd ? accO[NR - 1][j] : accE[NR - 1][j];
+                Bo = modd ? accE[NR - 1][j] : accO[NR - 1][j];
+            }
+            const double sg = (j & 1) ? -1.0 : 1.0;
+            // P_N = -(SE + i SB), SE = Ee + Eo
+            PN[j] = cscale(cadd(cadd(Ee, Eo), mul_i(cadd(Be, Bo))), -1.0);
+            // M_S = -(-1)^j [(Ee - Eo) - i (Be - Bo)]
+            MS[j] = cscale(csub(csub(Ee, Eo), mul_i(csub(Be, Bo))), -sg);
+        }
+    }
+    double2 MN[J + 1], PS[J + 1];
+    {
+        Rec<J> st;
+        load_start<J>(st, start, exps, 2, m, lmax, jtab, nrp, r);
+        double2 accE[NR][J + 1], accO[NR][J + 1];
+#pragma unroll
+        for (int q = 0; q < NR; ++q)
+#pragma unroll
+            for (int j = 0; j <= J; ++j) accE[q][j] = accO[q][j] = make_double2(0, 0);
+        run_family<J, NR>(lmin, lmax, c, -1.0, w, coef2 + base, almE + base, HASB ? almB + base : nullptr,
+                          st, accE, accO);
+#pragma unroll
+        for (int j = 0; j <= J; ++j) {
+            const double2 Ee = modd ? accO[0][j] : accE[0][j], Eo = modd ? accE[0][j] : accO[0][j];
+            double2 Be = make_double2(0, 0), Bo = make_double2(0, 0);
+            if constexpr (HASB) {
+                Be = modd ? accO[NR - 1][j] : accE[NR - 1][j];
+                Bo = modd ? accE[NR - 1][j] : accO[NR - 1][j];
+            }
+            const double sg = (j & 1) ? -1.0 : 1.0;
+            // M_N = -[(SE) - i SB]
+            MN[j] = cscale(csub(cadd(Ee, Eo), mul_i(cadd(Be, Bo))), -1.0);
+            // P_S = -(-1)^j [(Ee - Eo) + i (Be - Bo)]
+            PS[j] = cscale(cadd(csub(Ee, Eo), mul_i(csub(Be, Bo))), -sg);
+        }
+    }
+    const size_t plane = (size_t)ntheta * (lmax + 1);
+    const int rs = ntheta - 1 - r;
+#pragma unroll
+    for (int j = 0; j <= J; ++j) {
+        // Q = (P + M)/2,  U = -i (P - M)/2
+        const double2 qn = cscale(cadd(PN[j], MN[j]), 0.5);
+        const double2 un = cscale(mul_i(csub(PN[j], MN[j])), -0.5);
+        store_c<FT>(FQ, j * plane + (size_t)r * (lmax + 1) + m, qn);
+        store_c<FT>(FU, j * plane + (size_t)r * (lmax + 1) + m, un);
+        if (rs != r) {
+            const double2 qs = cscale(cadd(PS[j], MS[j]), 0.5);
+            const double2 us = cscale(mul_i(csub(PS[j], MS[j])), -0.5);
+            store_c<FT>(FQ, j * plane + (size_t)rs * (lmax + 1) + m, qs);
+            store_c<FT>(FU, j * plane + (size_t)rs * (lmax + 1) + m, us);
+        }
+    }
+}
+
+template <int J>
+hipError_t start_tables_J(Plan &p)
+{
+    dim3 grid((p.nrp + 63) / 64, 3);
+    hipLaunchKernelGGL((k_start<J>), grid, dim3(64), 0, p.stream, p.lmax, p.nrp, p.jtab,
+                       (const double2 *)p.trig.ptr, (const double *)p.theta.ptr, (double *)p.start.ptr,
+                       (int *)p.exps.ptr);
+    return hipGetLastError();
+}
+
+template <int J, typename FT>
+hipError_t scalar_J(Plan &p, const void *alm, void *F)
+{
+    dim3 grid((p.nrp + 63) / 64, (p.lmax + 1 + 7) / 8);
+    hipLaunchKernelGGL((k_legendre_scalar<J, FT>), grid, dim3(512), 0, p.stream, p.lmax, p.ntheta, p.nrp,
+                       p.jtab, (const double2 *)p.trig.ptr, (const double4 *)p.coef0.ptr,
+                       (const double *)p.start.ptr, (const int *)p.exps.ptr, (const double2 *)alm, (FT *)F);
+    return hipGetLastError();
+}
+
+template <int J, bool HASB, typename FT>
+hipError_t spin_J(Plan &p, const void *E, const void *B, void *FQ, void *FU)
+{
+    dim3 grid((p.nrp + 63) / 64, (p.lmax + 1 + 7) / 8);
+    hipLaunchKernelGGL((k_legendre_spin<J, HASB, FT>), grid, dim3(512), 0, p.stream, p.lmax, p.ntheta, p.nrp,
+                       p.jtab, (const double2 *)p.trig.ptr, (const double4 *)p.coef2.ptr,
+                       (const double *)p.start.ptr, (const int *)p.exps.ptr, (const double2 *)E,
+                       (const double2 *)B, (FT *)FQ, (FT *)FU);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_tables(Plan &p)
+{
+    {
+        dim3 grid(((p.lmax + 1) + 255) / 256, p.lmax + 1);
+        hipLaunchKernelGGL(k_coef, grid, dim3(256), 0, p.stream, p.lmax, (double4 *)p.coef0.ptr,
+                           (double4 *)p.coef2.ptr);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    switch (p.jtab - 1) {
+    case 1: return start_tables_J<1>(p);
+    case 2: return start_tables_J<2>(p);
+    case 3: return start_tables_J<3>(p);
+    case 4: return start_tables_J<4>(p);
+    case 5: return start_tables_J<5>(p);
+    case 6: return start_tables_J<6>(p);
+    case 7: return start_tables_J<7>(p);
+    case 8: return start_tables_J<8>(p);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_legendre_scalar(Plan &p, int J, const void *alm, void *F, bool out64)
+{
+#define TL_CASE(JJ) \
+    case JJ: return out64 ? scalar_J<JJ, double>(p, alm, F) : scalar_J<JJ, float>(p, alm, F);
+    switch (J) {
+        TL_CASE(0)
+        TL_CASE(1)
+        TL_CASE(2)
+        TL_CASE(3)
+        TL_CASE(4)
+        TL_CASE(5)
+        TL_CASE(6)
+        TL_CASE(7)
+        TL_CASE(8)
+    default: return hipErrorInvalidValue;
+    }
+#undef TL_CASE
+}
+
+hipError_t launch_legendre_spin(Plan &p, int J, const void *almE, const void *almB, void *FQ, void *FU,
+                                bool out64)
+{
+#define TL_CASE(JJ)                                                                          \
+    case JJ:                                                                                 \
+        if (almB)                                                                            \
+            return out64 ? spin_J<JJ, true, double>(p, almE, almB, FQ, FU)                   \
+                         : spin_J<JJ, true, float>(p, almE, almB, FQ, FU);                   \
+        return out64 ? spin_J<JJ, false, double>(p, almE, almB, FQ, FU)                      \
+                     : spin_J<JJ, false, float>(p, almE, almB, FQ, FU);
+    switch (J) {
+        TL_CASE(0)
+        TL_CASE(1)
+        TL_CASE(2)
+        TL_CASE(3)
+        TL_CASE(4)
+        TL_CASE(5)
+        TL_CASE(6)
+        TL_CASE(7)
+        TL_CASE(8)
+    default: return hipErrorInvalidValue;
+    }
+#undef TL_CASE
+}
+
+}  // namespace tl

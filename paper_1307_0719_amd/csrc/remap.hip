@@ -1,0 +1,182 @@
+// Remap + Taylor sum + polarization rotation (Sec. II.B, eqs. 2, 4, 5).
+//
+// One lane per output pixel x = (theta_i, phi_k), lanes of a wave along phi:
+//  1. displaced position x' from alpha by the geodesic of length |alpha| in the
+//     direction (a_t e_theta + a_p e_phi)/|alpha| (parallel transport, Sec. II.A),
+//     or by coordinate addition (naive rule), or given by the caller;
+//  2. nearest grid point (i0, k0) by rounding half up in theta and phi, with
+//     scaled residuals u = (theta' - theta_i0)/dtheta, v = (phi' - phi_k0)/dphi;
+//  3. s' = sum_{j+k<=N} u^j v^k Dt_{jk}(i0, k0) for s in {T, Q, U}, Horner in v then
+//     u, where Dt are the derivative maps pre-scaled by dtheta^j dphi^k/(j!k!);
+//  4. Q' + iU' = e^{2 i gamma} (Q + iU), gamma the angle between the transported
+//     e_theta(x') and e_theta(x): e^{i gamma} = e^{i psi} e^{-i psi'} with psi the
+//     bearing of alpha at x and psi' the bearing of the geodesic's tangent at x'.
+// Positions, residuals and the rotation angle are FP64; the sum uses R (FP32 or
+// FP64).  Neighbouring lanes gather neighbouring source pixels, so the gathers
+// from each derivative map are mostly coalesced.
+#include "tl_internal.h"
+
+namespace tl {
+
+namespace {
+
+template <typename R, int N, bool POL>
+__global__ __launch_bounds__(256) void k_remap(int ntheta, int nphi, const double *__restrict__ theta,
+                                               const double2 *__restrict__ trig, const double2 *__restrict__ phitrig,
+                                               const double *__restrict__ phival, const R *__restrict__ D,
+                                               const double *__restrict__ at, const double *__restrict__ ap,
+                                               const double *__restrict__ thsrc, const double *__restrict__ phsrc,
+                                               int rotate, int naive, R *__restrict__ To, R *__restrict__ Qo,
+                                               R *__restrict__ Uo)
+{
+    constexpr int ND = (N + 1) * (N + 2) / 2;
+    const int i = blockIdx.y;
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nphi) return;
+    const size_t idx = (size_t)i * nphi + k;
+    const double TWO_PI = 6.283185307179586476925286766559;
+    const double dth_grid = M_PI / (double)(ntheta - 1);
+    const double dph_grid = TWO_PI / (double)nphi;
+
+    double thp, php;
+    double cg = 1.0, sg = 0.0;  // cos 2 gamma, sin 2 gamma
+    if (thsrc) {
+        thp = thsrc[idx];
+        php = phsrc[idx];
+        php = php - floor(php / TWO_PI) * TWO_PI;
+    } else {
+        const double a_t = at[idx], a_p = ap[idx];
+        const double d = sqrt(a_t * a_t + a_p * a_p);
+        const bool pole = (i == 0) || (i == ntheta - 1);
+        if (d == 0.0) {
+            thp = theta[i];
+            php = phival[k];
+        } else if (naive && !pole) {
+            const double st = trig[i].y;
+            thp = theta[i] + a_t;
+            php = phival[k] + a_p / st;
+            if (thp < 0.0) {
+                thp = -thp;
+                php += M_PI;
+            }
+            if (thp > M_PI) {
+                thp = TWO_PI - thp;
+                php += M_PI;
+            }
+            php = php - floor(php / TWO_PI) * TWO_PI;
+        } else {
+            const double ct = trig[i].x, st = trig[i].y;
+            const double cp = phitrig[k].x, sp = phitrig[k].y;
+            const double x0 = st * cp, x1 = st * sp, x2 = ct;
+            const double et0 = ct * cp, et1 = ct * sp, et2 = -st;
+            const double ep0 = -sp, ep1 = cp;
+            const double u0 = (a_t * et0 + a_p * ep0) / d;
+            const double u1 = (a_t * et1 + a_p * ep1) / d;
+            const double u2 = (a_t * et2) / d;
+            double sd, cd;
+            sincos(d, &sd, &cd);
+            const double y0 = cd * x0 + sd * u0, y1 = cd * x1 + sd * u1, y2 = cd * x2 + sd * u2;
+            const double rho = sqrt(y0 * y0 + y1 * y1);
+            thp = atan2(rho, y2);
+            php = atan2(y1, y0);
+            if (php < 0.0) php += TWO_PI;
+            if (POL && rotate && !naive) {
+                // tangent of the geodesic at x'
+                const double t0 = -sd * x0 + cd * u0, t1 = -sd * x1 + cd * u1, t2 = -sd * x2 + cd * u2;
+                double cpp = 1.0, spp = 0.0;
+                if (rho > 0.0) {
+                    cpp = y0 / rho;
+                    spp = y1 / rho;
+                }
+                const double ctp = y2, stp = rho;
+                const double tt = t0 * ctp * cpp + t1 * ctp * spp - t2 * stp;  // t . e_theta(x')
+                const double tp = -t0 * spp + t1 * cpp;                       // t . e_phi(x')
+                // e^{i gamma} = (a_t + i a_p)(tt - i tp) / (d |t|)
+                const double gr = a_t * tt + a_p * tp;
+                const double gi = a_p * tt - a_t * tp;
+                const double nrm = gr * gr + gi * gi;
+                cg = (gr * gr - gi * gi) / nrm;
+                sg = 2.0 * gr * gi / nrm;
+            }
+        }
+    }
+    // nearest pixel (round half up), residuals against the grid tables
+    int i0 = (int)floor(thp / dth_grid + 0.5);
+    i0 = i0 < 0 ? 0 : (i0 > ntheta - 1 ? ntheta - 1 : i0);
+    int kh = (int)floor(php / dph_grid + 0.5);
+    kh = kh < 0 ? 0 : (kh > nphi ? nphi : kh);
+    const int k0 = kh == nphi ? 0 : kh;
+    const R u = (R)((thp - theta[i0]) / dth_grid);
+    const R v = (R)((php - phival[kh]) / dph_grid);
+
+    const size_t plane = (size_t)ntheta * nphi;
+    const size_t pix0 = (size_t)i0 * nphi + k0;
+    R res[POL ? 3 : 1];
+#pragma unroll
+    for (int f = 0; f < (POL ? 3 : 1); ++f) {
+        const R *Df = D + (size_t)f * ND * plane + pix0;
+        R acc = 0;
+#pragma unroll
+        for (int j = N; j >= 0; --j) {
+            const int base = j * (N + 1) - j * (j - 1) / 2;  // index of (j, 0)
+            R inner = 0;
+#pragma unroll
+            for (int kk = N - j; kk >= 0; --kk) inner = inner * v + Df[(size_t)(base + kk) * plane];
+            acc = acc * u + inner;
+        }
+        res[f] = acc;
+    }
+    To[idx] = res[0];
+    if constexpr (POL) {
+        const R q = res[1], uu = res[2];
+        Qo[idx] = (R)(cg * (double)q - sg * (double)uu);
+        Uo[idx] = (R)(sg * (double)q + cg * (double)uu);
+    }
+}
+
+template <typename R, int N>
+hipError_t remap_N(Plan &p, const void *D, const double *at, const double *ap, const double *ths,
+                   const double *phs, void *T, void *Q, void *U)
+{
+    dim3 grid((p.nphi + 255) / 256, p.ntheta);
+    if (p.pol)
+        hipLaunchKernelGGL((k_remap<R, N, true>), grid, dim3(256), 0, p.stream, p.ntheta, p.nphi,
+                           (const double *)p.theta.ptr, (const double2 *)p.trig.ptr,
+                           (const double2 *)p.phitab.ptr, (const double *)p.phival.ptr, (const R *)D, at, ap,
+                           ths, phs, p.rotate, p.naive, (R *)T, (R *)Q, (R *)U);
+    else
+        hipLaunchKernelGGL((k_remap<R, N, false>), grid, dim3(256), 0, p.stream, p.ntheta, p.nphi,
+                           (const double *)p.theta.ptr, (const double2 *)p.trig.ptr,
+                           (const double2 *)p.phitab.ptr, (const double *)p.phival.ptr, (const R *)D, at, ap,
+                           ths, phs, p.rotate, p.naive, (R *)T, (R *)Q, (R *)U);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t remap_R(Plan &p, const void *D, const double *at, const double *ap, const double *ths,
+                   const double *phs, void *T, void *Q, void *U)
+{
+    switch (p.order) {
+    case 0: return remap_N<R, 0>(p, D, at, ap, ths, phs, T, Q, U);
+    case 1: return remap_N<R, 1>(p, D, at, ap, ths, phs, T, Q, U);
+    case 2: return remap_N<R, 2>(p, D, at, ap, ths, phs, T, Q, U);
+    case 3: return remap_N<R, 3>(p, D, at, ap, ths, phs, T, Q, U);
+    case 4: return remap_N<R, 4>(p, D, at, ap, ths, phs, T, Q, U);
+    case 5: return remap_N<R, 5>(p, D, at, ap, ths, phs, T, Q, U);
+    case 6: return remap_N<R, 6>(p, D, at, ap, ths, phs, T, Q, U);
+    case 7: return remap_N<R, 7>(p, D, at, ap, ths, phs, T, Q, U);
+    case 8: return remap_N<R, 8>(p, D, at, ap, ths, phs, T, Q, U);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_remap(Plan &p, const void *D, const double *at, const double *ap, const double *thsrc,
+                        const double *phsrc, void *T, void *Q, void *U)
+{
+    if (p.fp64()) return remap_R<double>(p, D, at, ap, thsrc, phsrc, T, Q, U);
+    return remap_R<float>(p, D, at, ap, thsrc, phsrc, T, Q, U);
+}
+
+}  // namespace tl

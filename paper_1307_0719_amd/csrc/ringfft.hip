@@ -1,0 +1,276 @@
+// Ring FFT stage: per-m theta-derivative coefficients -> derivative maps.
+//
+// Each workgroup takes one job = one row of Fourier coefficients F_m
+// (m = 0..L, complex) of one ring, and produces up to kMaxJobK real rings
+//     out[n] = scale * sum_{m=-L}^{L} (i m)^k F_m e^{i m phi_n},  phi_n = 2 pi n / N,
+// with F_{-m} = conj(F_m).  These are the phi-derivatives d^k_phi of the
+// theta-derivative maps (the derivative inputs of eq. 5 of the paper); the
+// (i m)^k factor is applied in Fourier space while the row is loaded.
+//
+// Real output from a Hermitian half spectrum: with X_0 = Re c_0,
+// X_m = c_m (0 < m < N/2), X_{N/2} = 2 Re c_{N/2} (present iff L = N/2, the
+// alias of +-N/2 at the pixel centres), M = N/2 and
+//     Z_m = (X_m + conj X_{M-m}) + i e^{2 pi i m/N} (X_m - conj X_{M-m}),
+// the length-M inverse DFT z = IDFT_M(Z) gives out[2n] = Re z_n, out[2n+1] = Im z_n.
+// The length-M transform is a Stockham autosort FFT in LDS (ping-pong
+// buffers, radices 8, 4, 2, 5, 3), twiddles from a table e^{2 pi i t/N}.
+#include "tl_internal.h"
+
+namespace tl {
+
+namespace {
+
+template <typename R>
+struct C2;
+template <>
+struct C2<float> {
+    using T = float2;
+};
+template <>
+struct C2<double> {
+    using T = double2;
+};
+
+template <typename V>
+__device__ __forceinline__ V cmk(decltype(V().x) a, decltype(V().x) b)
+{
+    V v;
+    v.x = a;
+    v.y = b;
+    return v;
+}
+template <typename V>
+__device__ __forceinline__ V cadd(V a, V b) { return cmk<V>(a.x + b.x, a.y + b.y); }
+template <typename V>
+__device__ __forceinline__ V csub(V a, V b) { return cmk<V>(a.x - b.x, a.y - b.y); }
+template <typename V>
+__device__ __forceinline__ V cmul(V a, V b) { return cmk<V>(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x); }
+template <typename V>
+__device__ __forceinline__ V cmuli(V a) { return cmk<V>(-a.y, a.x); }   // i a
+template <typename V>
+__device__ __forceinline__ V cconj(V a) { return cmk<V>(a.x, -a.y); }
+
+// In-register inverse DFT of size r (sign +): y_s = sum_q v_q e^{+2 pi i q s / r}.
+template <typename V>
+__device__ __forceinline__ void dft2(V *v)
+{
+    V a = v[0], b = v[1];
+    v[0] = cadd(a, b);
+    v[1] = csub(a, b);
+}
+template <typename V>
+__device__ __forceinline__ void dft4(V *v)
+{
+    V a0 = cadd(v[0], v[2]), a1 = csub(v[0], v[2]);
+    V b0 = cadd(v[1], v[3]), b1 = cmuli(csub(v[1], v[3]));
+    v[0] = cadd(a0, b0);
+    v[2] = csub(a0, b0);
+    v[1] = cadd(a1, b1);
+    v[3] = csub(a1, b1);
+}
+template <typename V>
+__device__ __forceinline__ void dft8(V *v)
+{
+    using R = decltype(V().x);
+    const R h = (R)0.70710678118654752440084436210484904;
+    V e[4] = {v[0], v[2], v[4], v[6]};
+    V o[4] = {v[1], v[3], v[5], v[7]};
+    dft4(e);
+    dft4(o);
+    // o_s *= e^{2 pi i s / 8}
+    o[1] = cmk<V>(h * (o[1].x - o[1].y), h * (o[1].x + o[1].y));
+    o[2] = cmuli(o[2]);
+    o[3] = cmk<V>(-h * (o[3].x + o[3].y), h * (o[3].x - o[3].y));
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        v[s] = cadd(e[s], o[s]);
+        v[s + 4] = csub(e[s], o[s]);
+    }
+}
+template <typename V>
+__device__ __forceinline__ void dft3(V *v)
+{
+    using R = decltype(V().x);
+    const R c = (R)-0.5, s = (R)0.86602540378443864676372317075293618;
+    V t = cadd(v[1], v[2]);
+    V d = csub(v[1], v[2]);
+    V y0 = cadd(v[0], t);
+    V m1 = cmk<V>(v[0].x + c * t.x, v[0].y + c * t.y);
+    V m2 = cmk<V>(-s * d.y, s * d.x);  // i s d
+    v[0] = y0;
+    v[1] = cadd(m1, m2);
+    v[2] = csub(m1, m2);
+}
+template <typename V>
+__device__ __forceinline__ void dft5(V *v)
+{
+    using R = decltype(V().x);
+    const R c1 = (R)0.30901699437494742410229341718281906;   // cos 2pi/5
+    const R c2 = (R)-0.80901699437494742410229341718281906;  // cos 4pi/5
+    const R s1 = (R)0.95105651629515357211643933337938214;   // sin 2pi/5
+    const R s2 = (R)0.58778525229247312916870595463907277;   // sin 4pi/5
+    V t1 = cadd(v[1], v[4]), d1 = csub(v[1], v[4]);
+    V t2 = cadd(v[2], v[3]), d2 = csub(v[2], v[3]);
+    V y0 = cadd(v[0], cadd(t1, t2));
+    V a1 = cmk<V>(v[0].x + c1 * t1.x + c2 * t2.x, v[0].y + c1 * t1.y + c2 * t2.y);
+    V a2 = cmk<V>(v[0].x + c2 * t1.x + c1 * t2.x, v[0].y + c2 * t1.y + c1 * t2.y);
+    // b1 = i (s1 d1 + s2 d2), b2 = i (s2 d1 - s1 d2)
+    V q1 = cmk<V>(s1 * d1.x + s2 * d2.x, s1 * d1.y + s2 * d2.y);
+    V q2 = cmk<V>(s2 * d1.x - s1 * d2.x, s2 * d1.y - s1 * d2.y);
+    V b1 = cmuli(q1), b2 = cmuli(q2);
+    v[0] = y0;
+    v[1] = cadd(a1, b1);
+    v[4] = csub(a1, b1);
+    v[2] = cadd(a2, b2);
+    v[3] = csub(a2, b2);
+}
+
+// One radix-RX Stockham pass (inverse): for every butterfly b < M/RX,
+// v_s = src[b + s M/RX] e^{2 pi i (b mod Ns) s / (Ns RX)}, v = IDFT_RX(v),
+// dst[(b / Ns) Ns RX + b mod Ns + s Ns] = v_s.
+template <int RX, typename V>
+__device__ __forceinline__ void stockham_pass(const V *__restrict__ src, V *__restrict__ dst, int M, int Ns, int N,
+                                              int tid, int T, const V *__restrict__ twN)
+{
+    const int nb = M / RX;
+    const int tstride = N / (Ns * RX);
+    for (int b = tid; b < nb; b += T) {
+        V v[RX];
+        const int kk = b % Ns;
+#pragma unroll
+        for (int s = 0; s < RX; ++s) {
+            V x = src[b + s * nb];
+            if (s > 0 && kk > 0) x = cmul(x, twN[kk * s * tstride]);
+            v[s] = x;
+        }
+        if constexpr (RX == 2) dft2(v);
+        else if constexpr (RX == 3) dft3(v);
+        else if constexpr (RX == 4) dft4(v);
+        else if constexpr (RX == 5) dft5(v);
+        else dft8(v);
+        const int base = (b / Ns) * Ns * RX + kk;
+#pragma unroll
+        for (int s = 0; s < RX; ++s) dst[base + s * Ns] = v[s];
+    }
+}
+
+struct Radices {
+    int n;
+    int r[16];
+};
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_ring_fft(const FftJob *__restrict__ jobs,
+                                                  const typename C2<R>::T *__restrict__ Fbase,
+                                                  R *__restrict__ Dbase, int lmax, int M,
+                                                  const typename C2<R>::T *__restrict__ twN, Radices rad)
+{
+    using V = typename C2<R>::T;
+    extern __shared__ unsigned char smem_raw[];
+    V *bufA = reinterpret_cast<V *>(smem_raw);
+    V *bufB = bufA + M;
+    const int tid = threadIdx.x;
+    const int T = blockDim.x;
+    const FftJob &job = jobs[blockIdx.x];
+    const V *F = Fbase + job.src;
+    const int N = 2 * M;
+    const int L = lmax;
+
+    for (int q = 0; q < job.nk; ++q) {
+        const int k = job.k[q];
+        const double scale = job.scale[q];
+        // X(m) = scale (i m)^k F_m for 0 < m < M (0 beyond L); X(0), X(M) real.
+        auto coefX = [&](int m) -> V {
+            if (m > L) return cmk<V>(0, 0);
+            const V f = F[m];
+            double mk = 1.0;
+            for (int t = 0; t < k; ++t) mk *= (double)m;
+            const double s = scale * mk;
+            double re = s * (double)f.x, im = s * (double)f.y;
+            // multiply by i^k
+            switch (k & 3) {
+            case 1: { double t2 = re; re = -im; im = t2; } break;
+            case 2: re = -re; im = -im; break;
+            case 3: { double t2 = re; re = im; im = -t2; } break;
+            default: break;
+            }
+            if (m == 0) return cmk<V>((R)re, 0);
+            if (m == M) return cmk<V>((R)(2.0 * re), 0);
+            return cmk<V>((R)re, (R)im);
+        };
+        for (int m = tid; m < M; m += T) {
+            const V xm = coefX(m);
+            const V xc = cconj(coefX(M - m));
+            const V sum = cadd(xm, xc);
+            const V dif = csub(xm, xc);
+            const V tw = twN[m];  // e^{2 pi i m / N}
+            bufA[m] = cadd(sum, cmuli(cmul(tw, dif)));
+        }
+        __syncthreads();
+        // Stockham passes (inverse transform)
+        V *src = bufA, *dst = bufB;
+        int Ns = 1;
+        for (int p = 0; p < rad.n; ++p) {
+            const int r = rad.r[p];
+            switch (r) {
+            case 2: stockham_pass<2, V>(src, dst, M, Ns, N, tid, T, twN); break;
+            case 3: stockham_pass<3, V>(src, dst, M, Ns, N, tid, T, twN); break;
+            case 4: stockham_pass<4, V>(src, dst, M, Ns, N, tid, T, twN); break;
+            case 5: stockham_pass<5, V>(src, dst, M, Ns, N, tid, T, twN); break;
+            default: stockham_pass<8, V>(src, dst, M, Ns, N, tid, T, twN); break;
+            }
+            __syncthreads();
+            V *t = src;
+            src = dst;
+            dst = t;
+            Ns *= r;
+        }
+        R *out = Dbase + job.dst[q];
+        for (int n = tid; n < M; n += T) reinterpret_cast<V *>(out)[n] = src[n];
+        __syncthreads();
+    }
+}
+
+}  // namespace
+
+// Allow the ping-pong LDS buffers of this plan's FFT length beyond the
+// default 64 KiB dynamic-LDS limit when the device has more.
+hipError_t fft_prepare(Plan &p)
+{
+    const size_t M = (size_t)p.nphi / 2;
+    const size_t b64 = 2 * M * sizeof(double2), b32 = 2 * M * sizeof(float2);
+    if (b64 > 65536) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_ring_fft<double>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)b64);
+        if (e != hipSuccess) return e;
+    }
+    if (b32 > 65536) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_ring_fft<float>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)b32);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t launch_fft_jobs(Plan &p, const void *Fbase, void *Dbase, const FftJob *jobs, int njobs, bool fp64)
+{
+    if (njobs <= 0) return hipSuccess;
+    const int M = p.nphi / 2;
+    Radices rad;
+    rad.n = p.nradix;
+    for (int i = 0; i < p.nradix; ++i) rad.r[i] = p.radix[i];
+    if (fp64) {
+        size_t shm = 2 * (size_t)M * sizeof(double2);
+        hipLaunchKernelGGL(k_ring_fft<double>, dim3(njobs), dim3(256), shm, p.stream, jobs,
+                           (const double2 *)Fbase, (double *)Dbase, p.lmax, M,
+                           (const double2 *)p.twid64.ptr, rad);
+    } else {
+        size_t shm = 2 * (size_t)M * sizeof(float2);
+        hipLaunchKernelGGL(k_ring_fft<float>, dim3(njobs), dim3(256), shm, p.stream, jobs,
+                           (const float2 *)Fbase, (float *)Dbase, p.lmax, M, (const float2 *)p.twid32.ptr,
+                           rad);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace tl

@@ -1,0 +1,104 @@
+// Internal declarations of the taylens HIP library (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/taylens.h"
+
+namespace tl {
+
+constexpr int kMaxOrder = TL_MAX_ORDER;
+
+// Per-thread last-error message (set by fail()).
+void set_error(const std::string &msg);
+
+// Device arrays owned by a plan.  Sizes in elements unless noted.
+struct DevBuf {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+};
+
+// One ring FFT job: one source row of per-m coefficients (complex, m = 0..lmax)
+// and up to kMaxJobK outputs, each the real ring
+//     out[n] = scale * sum_{m=-L}^{L} (i m)^k F_m e^{i m phi_n}.
+constexpr int kMaxJobK = kMaxOrder + 1;
+struct FftJob {
+    int64_t src;                 // element offset (complex) of F_0 of the row
+    int32_t nk;                  // number of outputs
+    int32_t pad;
+    int32_t k[kMaxJobK];         // phi-derivative order of each output
+    int32_t pad2;
+    int64_t dst[kMaxJobK];       // element offset (real) of each output ring
+    double scale[kMaxJobK];      // multiplier of each output
+};
+
+struct Plan {
+    int lmax = 0;
+    int ntheta = 0, nphi = 0;
+    int nrp = 0;      // ring pairs = ceil(ntheta/2)
+    int order = 0;    // N
+    int jtab = 0;     // derivative entries per start value (max(N,1)+1)
+    int precision = TL_FP32;
+    int pol = 0, rotate = 1, naive = 0;
+    int64_t cap = 0;
+    hipStream_t stream = nullptr;
+    int device = 0;
+
+    // FFT length factorization (M = nphi/2 = prod radix)
+    int nradix = 0;
+    int radix[32];
+
+    // tables
+    DevBuf theta;     // double [ntheta]
+    DevBuf trig;      // double2 {cos, sin} [nrp] (north rings)
+    DevBuf phitab;    // double2 {cos phi_k, sin phi_k} [nphi] + double phi_k [nphi]
+    DevBuf phival;    // double [nphi]
+    DevBuf twid64;    // double2 [M]  e^{2 pi i t / M}
+    DevBuf twid32;    // float2  [M]
+    DevBuf coef0;     // double4 {a, b, c, 0} spin 0, triangular
+    DevBuf coef2;     // double4 {a, b(+2), c, 0} spin 2, triangular
+    DevBuf start;     // double [3][lmax+1][jtab][nrp]
+    DevBuf exps;      // int    [3][lmax+1][nrp]
+
+    // work buffers
+    DevBuf Fphi;      // complex128 [2][ntheta][lmax+1]
+    DevBuf alpha;     // double [2][ntheta][nphi]
+    DevBuf F;         // complex (64 or 128) [nfield][N+1][ntheta][lmax+1]
+    DevBuf D;         // real [nfield][ndmap][ntheta][nphi]
+    DevBuf jobsDefl;  // FftJob [ntheta * 2]
+    DevBuf jobsMain;  // FftJob [nfield * (N+1) * ntheta]
+    int njobsDefl = 0, njobsMain = 0;
+
+    size_t total_bytes = 0;
+
+    // instrumentation: event pairs per timed stage launch
+    struct ProfRec {
+        int stage;
+        hipEvent_t a, b;
+    };
+    bool profile = false;
+    std::vector<ProfRec> prof;
+
+    int nfield() const { return pol ? 3 : 1; }
+    int ndmap() const { return (order + 1) * (order + 2) / 2; }
+    bool fp64() const { return precision == TL_FP64; }
+    size_t npix() const { return (size_t)ntheta * (size_t)nphi; }
+    size_t nalm() const { return (size_t)(lmax + 1) * (size_t)(lmax + 2) / 2; }
+};
+
+// ---- kernel launchers (return hipError_t) ----
+hipError_t launch_tables(Plan &p);
+hipError_t launch_legendre_scalar(Plan &p, int J, const void *alm, void *F, bool out64);
+hipError_t launch_legendre_spin(Plan &p, int J, const void *almE, const void *almB, void *FQ,
+                                void *FU, bool out64);
+hipError_t launch_fft_jobs(Plan &p, const void *Fbase, void *Dbase, const FftJob *jobs, int njobs,
+                           bool fp64);
+hipError_t launch_remap(Plan &p, const void *D, const double *at, const double *ap,
+                        const double *thsrc, const double *phsrc, void *T, void *Q, void *U);
+
+}  // namespace tl

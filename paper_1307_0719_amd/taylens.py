@@ -1,0 +1,285 @@
+"""Python binding of libtaylens (ctypes).  Argument marshalling only: every
+step of the lensing path runs in the library's HIP kernels.  PyTorch supplies
+device memory and the stream.
+
+The library must have been built (``python -m paper_1307_0719_amd.build``);
+importing this module raises if ``libtaylens.so`` is missing -- there is no
+fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtaylens.so")
+
+TL_OK = 0
+TL_ERR_INVALID = -1
+TL_ERR_UNSUPPORTED = -2
+TL_ERR_HIP = -3
+TL_ERR_NOMEM = -4
+MAX_ORDER = 8
+
+PRECISIONS = {"fp64": 0, "fp32": 1, "bf16x3": 2, "fp16x2": 3, "fp16": 4, "bf16": 5}
+
+# every symbol include/taylens.h declares
+EXPORTS = [
+    "tl_plan_create", "tl_plan_destroy", "tl_plan_workspace_bytes", "tl_lens_map", "tl_lens_map_pos",
+    "tl_deflection", "tl_legendre", "tl_synth_derivs", "tl_remap", "tl_lens_map_batch",
+    "tl_lens_map_simple", "tl_plan_profile", "tl_plan_stage_times", "tl_last_error", "tl_version",
+]
+STAGES = ["deflection", "legendre_T", "legendre_QU", "ring_fft", "remap"]
+
+
+class TaylensError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"taylens error {code}: {msg}")
+        self.code = code
+
+
+class Grid(ctypes.Structure):
+    _fields_ = [("ntheta", ctypes.c_int32), ("nphi", ctypes.c_int32)]
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("order", ctypes.c_int32), ("precision", ctypes.c_int32), ("pol", ctypes.c_int32),
+                ("rotate", ctypes.c_int32), ("naive_pos", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("workspace_cap", ctypes.c_int64)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library (raises ImportError if it is not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"libtaylens.so not built at {LIB_PATH}; run python -m paper_1307_0719_amd.build")
+        L = ctypes.CDLL(LIB_PATH)
+        vp = ctypes.c_void_p
+        L.tl_plan_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int32, Grid, ctypes.POINTER(Options), vp]
+        L.tl_plan_destroy.argtypes = [vp]
+        L.tl_plan_workspace_bytes.argtypes = [vp, ctypes.POINTER(ctypes.c_int64)]
+        L.tl_lens_map.argtypes = [vp] * 8
+        L.tl_lens_map_pos.argtypes = [vp] * 9
+        L.tl_deflection.argtypes = [vp] * 4
+        L.tl_legendre.argtypes = [vp] * 5
+        L.tl_synth_derivs.argtypes = [vp] * 5
+        L.tl_remap.argtypes = [vp] * 7
+        L.tl_lens_map_batch.argtypes = [ctypes.c_int32, vp, vp, vp]
+        L.tl_lens_map_simple.argtypes = [vp, vp, vp, vp, ctypes.c_int32, ctypes.c_int32, Grid, vp, vp, vp]
+        L.tl_plan_profile.argtypes = [vp, ctypes.c_int32]
+        L.tl_plan_stage_times.argtypes = [vp, vp, vp]
+        L.tl_last_error.restype = ctypes.c_char_p
+        L.tl_last_error.argtypes = []
+        L.tl_version.restype = ctypes.c_int
+        for name in EXPORTS:
+            getattr(L, name).restype = ctypes.c_int if name != "tl_last_error" else ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def _check(rc: int):
+    if rc != TL_OK:
+        raise TaylensError(rc, lib().tl_last_error().decode())
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    if t is None:
+        return None
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _alm(a, name, device, lmax):
+    """complex128 contiguous device tensor of the expected length (or None)."""
+    if a is None:
+        return None
+    if isinstance(a, np.ndarray):
+        a = torch.from_numpy(np.ascontiguousarray(a, dtype=np.complex128))
+    if a.dtype != torch.complex128:
+        raise TypeError(f"{name} must be complex128")
+    n = (lmax + 1) * (lmax + 2) // 2
+    if a.numel() != n:
+        raise ValueError(f"{name} has {a.numel()} coefficients, lmax={lmax} needs {n}")
+    return a.to(device).contiguous()
+
+
+class Plan:
+    """A lensing plan: band limit, ring grid, Taylor order, precision form."""
+
+    def __init__(self, lmax: int, ntheta: int, nphi: int, order: int, precision: str = "fp32",
+                 pol: bool = True, rotate: bool = True, naive_pos: bool = False, workspace_cap: int = 0,
+                 device: Optional[torch.device] = None, stream: Optional[torch.cuda.Stream] = None):
+        self.lmax, self.ntheta, self.nphi, self.order = int(lmax), int(ntheta), int(nphi), int(order)
+        self.precision = precision
+        self.pol = bool(pol)
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        if precision not in PRECISIONS:
+            raise ValueError(f"unknown precision {precision}")
+        opt = Options(order, PRECISIONS[precision], int(pol), int(rotate), int(naive_pos), 0, int(workspace_cap))
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(lib().tl_plan_create(ctypes.byref(h), self.lmax, Grid(self.ntheta, self.nphi),
+                                        ctypes.byref(opt), ctypes.c_void_p(self.stream.cuda_stream)))
+        self._h = h
+        self.real_dtype = torch.float64 if precision == "fp64" else torch.float32
+        self.cplx_dtype = torch.complex128 if precision == "fp64" else torch.complex64
+
+    # ---------------------------------------------------------------- utils
+    @property
+    def handle(self):
+        return self._h
+
+    @property
+    def nfield(self):
+        return 3 if self.pol else 1
+
+    @property
+    def ndmap(self):
+        return (self.order + 1) * (self.order + 2) // 2
+
+    def workspace_bytes(self) -> int:
+        b = ctypes.c_int64()
+        _check(lib().tl_plan_workspace_bytes(self._h, ctypes.byref(b)))
+        return int(b.value)
+
+    def profile(self, enable: bool = True):
+        """Start (or stop) per-stage HIP-event timing on the plan's stream."""
+        _check(lib().tl_plan_profile(self._h, int(enable)))
+
+    def stage_times(self):
+        """{stage: (total_ms, launches)} since profile() (synchronizes)."""
+        ms = (ctypes.c_double * len(STAGES))()
+        n = (ctypes.c_int64 * len(STAGES))()
+        _check(lib().tl_plan_stage_times(self._h, ctypes.cast(ms, ctypes.c_void_p), ctypes.cast(n, ctypes.c_void_p)))
+        return {s: (ms[i], n[i]) for i, s in enumerate(STAGES)}
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().tl_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _maps(self, n=None):
+        shape = (self.ntheta, self.nphi) if n is None else (n, self.ntheta, self.nphi)
+        return torch.empty(shape, dtype=self.real_dtype, device=self.device)
+
+    def _inputs(self, alm_T, alm_E, alm_B):
+        T = _alm(alm_T, "alm_T", self.device, self.lmax)
+        E = _alm(alm_E, "alm_E", self.device, self.lmax) if self.pol else None
+        B = _alm(alm_B, "alm_B", self.device, self.lmax) if self.pol else None
+        return T, E, B
+
+    # ------------------------------------------------------------- calls
+    def lens_map(self, alm_T, alm_E=None, alm_B=None, alm_phi=None, out=None):
+        """Lensed (T, Q, U) maps; Q/U are None for a T-only plan."""
+        T, E, B = self._inputs(alm_T, alm_E, alm_B)
+        P = _alm(alm_phi, "alm_phi", self.device, self.lmax)
+        if out is None:
+            out = (self._maps(), self._maps() if self.pol else None, self._maps() if self.pol else None)
+        _check(lib().tl_lens_map(self._h, _ptr(T), _ptr(E), _ptr(B), _ptr(P), _ptr(out[0]), _ptr(out[1]),
+                                 _ptr(out[2])))
+        self._keep = (T, E, B, P)
+        return out
+
+    def lens_map_pos(self, alm_T, alm_E, alm_B, theta_src: torch.Tensor, phi_src: torch.Tensor):
+        T, E, B = self._inputs(alm_T, alm_E, alm_B)
+        th = theta_src.to(self.device, torch.float64).contiguous()
+        ph = phi_src.to(self.device, torch.float64).contiguous()
+        out = (self._maps(), self._maps() if self.pol else None, self._maps() if self.pol else None)
+        _check(lib().tl_lens_map_pos(self._h, _ptr(T), _ptr(E), _ptr(B), _ptr(th), _ptr(ph), _ptr(out[0]),
+                                     _ptr(out[1]), _ptr(out[2])))
+        self._keep = (T, E, B, th, ph)
+        return out
+
+    def deflection(self, alm_phi):
+        P = _alm(alm_phi, "alm_phi", self.device, self.lmax)
+        at = torch.empty((self.ntheta, self.nphi), dtype=torch.float64, device=self.device)
+        ap = torch.empty_like(at)
+        _check(lib().tl_deflection(self._h, _ptr(P), _ptr(at), _ptr(ap)))
+        self._keep = (P,)
+        return at, ap
+
+    def legendre(self, alm_T, alm_E=None, alm_B=None):
+        """F[field][j][ring][m] complex."""
+        T, E, B = self._inputs(alm_T, alm_E, alm_B)
+        F = torch.empty((self.nfield, self.order + 1, self.ntheta, self.lmax + 1), dtype=self.cplx_dtype,
+                        device=self.device)
+        _check(lib().tl_legendre(self._h, _ptr(T), _ptr(E), _ptr(B), _ptr(F)))
+        self._keep = (T, E, B)
+        return F
+
+    def synth_derivs(self, alm_T, alm_E=None, alm_B=None):
+        """Scaled derivative maps D[field][jk][ring][pix]."""
+        T, E, B = self._inputs(alm_T, alm_E, alm_B)
+        D = torch.empty((self.nfield, self.ndmap, self.ntheta, self.nphi), dtype=self.real_dtype,
+                        device=self.device)
+        _check(lib().tl_synth_derivs(self._h, _ptr(T), _ptr(E), _ptr(B), _ptr(D)))
+        self._keep = (T, E, B)
+        return D
+
+    def remap(self, D: torch.Tensor, alpha_theta: torch.Tensor, alpha_phi: torch.Tensor):
+        D = D.to(self.device, self.real_dtype).contiguous()
+        at = alpha_theta.to(self.device, torch.float64).contiguous()
+        ap = alpha_phi.to(self.device, torch.float64).contiguous()
+        if D.numel() != self.nfield * self.ndmap * self.ntheta * self.nphi:
+            raise ValueError("D has the wrong size for this plan")
+        out = (self._maps(), self._maps() if self.pol else None, self._maps() if self.pol else None)
+        _check(lib().tl_remap(self._h, _ptr(D), _ptr(at), _ptr(ap), _ptr(out[0]), _ptr(out[1]), _ptr(out[2])))
+        self._keep = (D, at, ap)
+        return out
+
+
+def lens_map_batch(plans: Sequence[Plan], alms: Sequence[tuple], outs: Sequence[tuple]):
+    """Lens len(plans) realizations in one call (alms[i] = (T, E, B, phi),
+    outs[i] = (T, Q, U) preallocated)."""
+    n = len(plans)
+    keep = []
+    harr = (ctypes.c_void_p * n)(*[p.handle.value for p in plans])
+    aarr = (ctypes.c_void_p * (4 * n))()
+    oarr = (ctypes.c_void_p * (3 * n))()
+    for i, (p, a, o) in enumerate(zip(plans, alms, outs)):
+        T, E, B = p._inputs(a[0], a[1], a[2])
+        P = _alm(a[3], "alm_phi", p.device, p.lmax)
+        keep.append((T, E, B, P))
+        for q, t in enumerate((T, E, B, P)):
+            aarr[4 * i + q] = t.data_ptr() if t is not None else None
+        for q, t in enumerate(o):
+            oarr[3 * i + q] = t.data_ptr() if t is not None else None
+    _check(lib().tl_lens_map_batch(n, ctypes.cast(harr, ctypes.c_void_p), ctypes.cast(aarr, ctypes.c_void_p),
+                                   ctypes.cast(oarr, ctypes.c_void_p)))
+    return keep
+
+
+def lens_map(alm_T, alm_E, alm_B, alm_phi, lmax: int, order: int, ntheta: int, nphi: int):
+    """lens_map(alm_T, alm_E, alm_B, alm_phi, lmax, order, grid) -> T', Q', U'
+    (FP32, rotation on; Q'/U' None without alm_E).  Synchronizes."""
+    dev = torch.device("cuda", torch.cuda.current_device())
+    T = _alm(alm_T, "alm_T", dev, lmax)
+    E = _alm(alm_E, "alm_E", dev, lmax)
+    B = _alm(alm_B, "alm_B", dev, lmax)
+    P = _alm(alm_phi, "alm_phi", dev, lmax)
+    mk = lambda: torch.empty((ntheta, nphi), dtype=torch.float32, device=dev)
+    To = mk()
+    Qo = mk() if E is not None else None
+    Uo = mk() if E is not None else None
+    torch.cuda.synchronize()
+    _check(lib().tl_lens_map_simple(_ptr(T), _ptr(E), _ptr(B), _ptr(P), int(lmax), int(order),
+                                    Grid(ntheta, nphi), _ptr(To), _ptr(Qo), _ptr(Uo)))
+    return To, Qo, Uo
+
+
+def version() -> int:
+    return lib().tl_version()
