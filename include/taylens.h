@@ -154,10 +154,12 @@ int tl_lens_map_simple(const void *alm_T, const void *alm_E, const void *alm_B,
 
 /* ---- instrumentation ---- */
 
-/* Stages timed by tl_plan_profile: deflection (harmonic + ring FFT of phi),
- * harmonic stage of T, harmonic stage of Q/U, ring FFTs of the derivative
- * maps, remap + Taylor sum + rotation. */
-#define TL_NSTAGE 5
+/* Stages timed by tl_plan_profile: 0 deflection (harmonic + ring FFT of phi),
+ * 1 direct FP64 harmonic kernel of T, 2 direct FP64 harmonic kernel of Q/U
+ * (all rings in the FP64 form, the pole-adjacent rings in the others),
+ * 3 matrix-core harmonic kernel (T and Q/U, the remaining rings), 4 ring FFTs
+ * of the derivative maps, 5 remap + Taylor sum + rotation. */
+#define TL_NSTAGE 6
 
 /* enable != 0: from now on record a HIP event pair on the plan's stream
  * around every stage of every call (no synchronization is added); 0: stop.

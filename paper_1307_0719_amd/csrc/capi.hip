@@ -109,7 +109,7 @@ void free_buf(DevBuf &b)
 void free_plan_buffers(Plan &p)
 {
     DevBuf *bufs[] = {&p.theta, &p.trig, &p.phitab, &p.phival, &p.twid64, &p.twid32, &p.coef0, &p.coef2,
-                      &p.start, &p.exps, &p.Fphi, &p.alpha, &p.F, &p.D, &p.jobsDefl, &p.jobsMain};
+                      &p.start, &p.exps, &p.mcut, &p.Fphi, &p.alpha, &p.F, &p.D, &p.jobsDefl, &p.jobsMain};
     for (DevBuf *b : bufs) free_buf(*b);
 }
 
@@ -138,11 +138,11 @@ double factorial(int n)
 }
 
 struct Sizes {
-    size_t theta, trig, phitab, phival, twid64, twid32, coef, start, exps, Fphi, alpha, F, D, jd, jm;
+    size_t theta, trig, phitab, phival, twid64, twid32, coef, start, exps, mcut, Fphi, alpha, F, D, jd, jm;
     size_t total() const
     {
-        return theta + trig + phitab + phival + twid64 + twid32 + 2 * coef + start + exps + Fphi + alpha + F + D +
-               jd + jm;
+        return theta + trig + phitab + phival + twid64 + twid32 + 2 * coef + start + exps + mcut + Fphi + alpha + F +
+               D + jd + jm;
     }
 };
 
@@ -162,6 +162,7 @@ Sizes plan_sizes(const Plan &p)
     s.coef = nalm * sizeof(double4);
     s.start = 3 * (size_t)(p.lmax + 1) * p.jtab * p.nrp * sizeof(double);
     s.exps = 3 * (size_t)(p.lmax + 1) * p.nrp * sizeof(int);
+    s.mcut = (size_t)p.nrp * sizeof(int);
     s.Fphi = 2 * rowc * 16;
     s.alpha = 2 * p.npix() * sizeof(double);
     s.F = (size_t)p.nfield() * (p.order + 1) * rowc * cbytes;
@@ -292,7 +293,7 @@ int run_deflection(Plan &p, const void *alm_phi)
         return TL_OK;
     }
     StageScope sc(p, 0);
-    TL_HIP(launch_legendre_scalar(p, 1, alm_phi, p.Fphi.ptr, true), "deflection legendre");
+    TL_HIP(launch_legendre_scalar(p, 1, p.nrp, alm_phi, p.Fphi.ptr, true), "deflection legendre");
     TL_HIP(launch_fft_jobs(p, p.Fphi.ptr, p.alpha.ptr, (const FftJob *)p.jobsDefl.ptr, p.njobsDefl, true),
            "deflection fft");
     return TL_OK;
@@ -303,13 +304,23 @@ int run_legendre(Plan &p, const void *T, const void *E, const void *B, void *Fou
     const size_t rowc = (size_t)p.ntheta * (p.lmax + 1) * (p.order + 1);
     const size_t cb = p.fp64() ? 16 : 8;
     char *F = (char *)Fout;
+    const bool hasb = p.pol && B != nullptr;
+    // FP32 form: matrix-core contraction away from the poles, direct FP64
+    // recursion on the pole-adjacent ring pairs; FP64 form: direct everywhere.
+    const bool mfma = !p.fp64() && mfma_supported(p.order, hasb);
+    const int rend = mfma ? p.rpole : p.nrp;
     {
         StageScope sc(p, 1);
-        TL_HIP(launch_legendre_scalar(p, p.order, T, F, p.fp64()), "legendre T");
+        TL_HIP(launch_legendre_scalar(p, p.order, rend, T, F, p.fp64()), "legendre T");
     }
     if (p.pol) {
         StageScope sc(p, 2);
-        TL_HIP(launch_legendre_spin(p, p.order, E, B, F + rowc * cb, F + 2 * rowc * cb, p.fp64()), "legendre QU");
+        TL_HIP(launch_legendre_spin(p, p.order, rend, E, B, F + rowc * cb, F + 2 * rowc * cb, p.fp64()), "legendre QU");
+    }
+    if (mfma) {
+        StageScope sc(p, 3);
+        TL_HIP(launch_legendre_mfma(p, T, E, B, F, p.pol ? F + rowc * cb : nullptr, p.pol ? F + 2 * rowc * cb : nullptr),
+               "legendre mfma");
     }
     return TL_OK;
 }
@@ -318,7 +329,7 @@ int run_derivs(Plan &p, const void *T, const void *E, const void *B, void *Dout)
 {
     int rc = run_legendre(p, T, E, B, p.F.ptr);
     if (rc) return rc;
-    StageScope sc(p, 3);
+    StageScope sc(p, 4);
     TL_HIP(launch_fft_jobs(p, p.F.ptr, Dout, (const FftJob *)p.jobsMain.ptr, p.njobsMain, p.fp64()), "ring fft");
     return TL_OK;
 }
@@ -380,6 +391,14 @@ int tl_plan_create(tl_plan *out, int32_t lmax, tl_grid grid, const tl_options *o
     p.cap = opt->workspace_cap;
     p.stream = (hipStream_t)hip_stream;
     factor_radices(p.nphi / 2, p);
+    {
+        // polar caps (sin theta < 0.15) stay on the direct FP64 kernel: the
+        // 1/sin theta coefficients of the L-power form amplify FP32 rounding there
+        const double smin = 0.15;
+        int rp = 1;
+        while (rp < p.nrp && std::sin(M_PI * (double)rp / (double)(p.ntheta - 1)) < smin) ++rp;
+        p.rpole = rp;
+    }
 
     Sizes sz = plan_sizes(p);
     if (p.cap > 0 && sz.total() > (size_t)p.cap) {
@@ -413,7 +432,7 @@ int tl_plan_create(tl_plan *out, int32_t lmax, tl_grid grid, const tl_options *o
     } list[] = {{&p.theta, sz.theta, "theta"},   {&p.trig, sz.trig, "trig"},       {&p.phitab, sz.phitab, "phitab"},
                 {&p.phival, sz.phival, "phival"}, {&p.twid64, sz.twid64, "twid64"}, {&p.twid32, sz.twid32, "twid32"},
                 {&p.coef0, sz.coef, "coef0"},    {&p.coef2, sz.coef, "coef2"},     {&p.start, sz.start, "start"},
-                {&p.exps, sz.exps, "exps"},      {&p.Fphi, sz.Fphi, "Fphi"},       {&p.alpha, sz.alpha, "alpha"},
+                {&p.exps, sz.exps, "exps"},      {&p.mcut, sz.mcut, "mcut"},       {&p.Fphi, sz.Fphi, "Fphi"},       {&p.alpha, sz.alpha, "alpha"},
                 {&p.F, sz.F, "F"},               {&p.D, sz.D, "D"},                {&p.jobsDefl, sz.jd, "jobsDefl"},
                 {&p.jobsMain, sz.jm, "jobsMain"}};
     for (auto &it : list) {
@@ -555,7 +574,7 @@ int tl_lens_map(tl_plan plan, const void *alm_T, const void *alm_E, const void *
     if ((rc = run_deflection(p, alm_phi))) return rc;
     if ((rc = run_derivs(p, alm_T, alm_E, alm_B, p.D.ptr))) return rc;
     const double *at = (const double *)p.alpha.ptr;
-    StageScope sc(p, 4);
+    StageScope sc(p, 5);
     TL_HIP(launch_remap(p, p.D.ptr, at, at + p.npix(), nullptr, nullptr, T_out, Q_out, U_out), "remap");
     return TL_OK;
 }

@@ -196,6 +196,44 @@ __global__ void k_start(int lmax, int nrp, int jtab, const double2 *__restrict__
     }
 }
 
+// Evanescent cut: for ring pair r, the largest m whose lambda_lm(theta_r)
+// (or, at l = m, one of its stored theta-derivatives) reaches 2^-200 for some
+// l <= lmax.  Beyond it the derivative maps, scaled by dtheta^j / j!, get
+// contributions below 2^-200 (m / r)^j: dropped.  One lane per (r, m): the
+// j = 0 recursion with the same exponent scaling as the kernels, stopped at
+// the first significant l.
+__global__ void k_mcut(int lmax, int nrp, int jtab, const double2 *__restrict__ trig,
+                       const double4 *__restrict__ coef0, const double *__restrict__ start,
+                       const int *__restrict__ exps, int *__restrict__ mcut)
+{
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    const int m = blockIdx.y;
+    if (r >= nrp || m > lmax) return;
+    const double x = trig[r].x;
+    double p1 = start[(size_t)m * jtab * nrp + r], p2 = 0.0;
+    int e = exps[(size_t)m * nrp + r];
+    const size_t base = (size_t)m * (2 * lmax + 1 - m) / 2;
+    const double sig = 0x1p-200;
+    // at the start also test the stored theta-derivatives: on the pole ring the
+    // value vanishes for m >= 1 while derivatives of order >= m do not
+    double s0 = 0.0;
+    for (int j = 0; j < jtab; ++j) s0 = fmax(s0, fabs(start[((size_t)m * jtab + j) * nrp + r]));
+    bool hit = (e == 0) && s0 >= sig;
+    for (int l = m + 1; l <= lmax && !hit; ++l) {
+        const double4 cf = coef0[base + l];
+        const double nv = cf.x * (x * p1) - cf.z * p2;
+        p2 = p1;
+        p1 = nv;
+        if (e > 0 && fmax(fabs(p1), fabs(p2)) > kHi) {
+            p1 *= kDown;
+            p2 *= kDown;
+            e -= 1;
+        }
+        hit = (e == 0) && fabs(p1) >= sig;
+    }
+    if (hit) atomicMax(&mcut[r], m);
+}
+
 // ------------------------------------------------------------ recursion --
 
 template <int J>
@@ -350,14 +388,23 @@ __device__ __forceinline__ void store_c<float>(float *F, size_t idx, double2 v)
 // Scalar field: F[j][ring][m] = sum_l a_lm d^j lambda_lm(theta_ring).
 template <int J, typename FT>
 __global__ __launch_bounds__(512) void k_legendre_scalar(
-    int lmax, int ntheta, int nrp, int jtab, const double2 *__restrict__ trig,
+    int lmax, int ntheta, int nrp, int rend, int jtab, const double2 *__restrict__ trig,
     const double4 *__restrict__ coef0, const double *__restrict__ start, const int *__restrict__ exps,
-    const double2 *__restrict__ alm, FT *__restrict__ F)
+    const int *__restrict__ mcut, const double2 *__restrict__ alm, FT *__restrict__ F)
 {
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int m = blockIdx.y * 8 + wave;
     const int r = blockIdx.x * 64 + (threadIdx.x & 63);
-    if (m > lmax || r >= nrp) return;
+    if (m > lmax || r >= rend) return;
+    if (m > mcut[r]) {  // evanescent: every term below the cut
+        const size_t plane = (size_t)ntheta * (lmax + 1);
+        const int rs = ntheta - 1 - r;
+        for (int j = 0; j <= J; ++j) {
+            store_c<FT>(F, j * plane + (size_t)r * (lmax + 1) + m, make_double2(0, 0));
+            store_c<FT>(F, j * plane + (size_t)rs * (lmax + 1) + m, make_double2(0, 0));
+        }
+        return;
+    }
     const double c = trig[r].x, s = trig[r].y;
     double w[J + 1][J + 1];
     leibniz_weights<J>(c, s, w);
@@ -399,16 +446,28 @@ __device__ __forceinline__ double2 cscale(double2 a, double s) { return make_dou
 // and, at the south ring, 2lam^{(j)}(pi - t) = (-1)^{l+m+j} (-2)lam^{(j)}(t).
 template <int J, bool HASB, typename FT>
 __global__ __launch_bounds__(512) void k_legendre_spin(
-    int lmax, int ntheta, int nrp, int jtab, const double2 *__restrict__ trig,
+    int lmax, int ntheta, int nrp, int rend, int jtab, const double2 *__restrict__ trig,
     const double4 *__restrict__ coef2, const double *__restrict__ start, const int *__restrict__ exps,
-    const double2 *__restrict__ almE, const double2 *__restrict__ almB, FT *__restrict__ FQ,
-    FT *__restrict__ FU)
+    const int *__restrict__ mcut, const double2 *__restrict__ almE, const double2 *__restrict__ almB,
+    FT *__restrict__ FQ, FT *__restrict__ FU)
 {
     constexpr int NR = HASB ? 2 : 1;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int m = blockIdx.y * 8 + wave;
     const int r = blockIdx.x * 64 + (threadIdx.x & 63);
-    if (m > lmax || r >= nrp) return;
+    if (m > lmax || r >= rend) return;
+    // spin-2 functions stay below the scalar cut plus 2 (|m - s| <= m + 2)
+    if (m > mcut[r] + 2) {
+        const size_t plane = (size_t)ntheta * (lmax + 1);
+        const int rs = ntheta - 1 - r;
+        for (int j = 0; j <= J; ++j) {
+            store_c<FT>(FQ, j * plane + (size_t)r * (lmax + 1) + m, make_double2(0, 0));
+            store_c<FT>(FQ, j * plane + (size_t)rs * (lmax + 1) + m, make_double2(0, 0));
+            store_c<FT>(FU, j * plane + (size_t)r * (lmax + 1) + m, make_double2(0, 0));
+            store_c<FT>(FU, j * plane + (size_t)rs * (lmax + 1) + m, make_double2(0, 0));
+        }
+        return;
+    }
     const double c = trig[r].x, s = trig[r].y;
     double w[J + 1][J + 1];
     leibniz_weights<J>(c, s, w);
@@ -497,23 +556,26 @@ hipError_t start_tables_J(Plan &p)
 }
 
 template <int J, typename FT>
-hipError_t scalar_J(Plan &p, const void *alm, void *F)
+hipError_t scalar_J(Plan &p, int rend, const void *alm, void *F)
 {
-    dim3 grid((p.nrp + 63) / 64, (p.lmax + 1 + 7) / 8);
-    hipLaunchKernelGGL((k_legendre_scalar<J, FT>), grid, dim3(512), 0, p.stream, p.lmax, p.ntheta, p.nrp,
+    if (rend <= 0) return hipSuccess;
+    dim3 grid((rend + 63) / 64, (p.lmax + 1 + 7) / 8);
+    hipLaunchKernelGGL((k_legendre_scalar<J, FT>), grid, dim3(512), 0, p.stream, p.lmax, p.ntheta, p.nrp, rend,
                        p.jtab, (const double2 *)p.trig.ptr, (const double4 *)p.coef0.ptr,
-                       (const double *)p.start.ptr, (const int *)p.exps.ptr, (const double2 *)alm, (FT *)F);
+                       (const double *)p.start.ptr, (const int *)p.exps.ptr, (const int *)p.mcut.ptr,
+                       (const double2 *)alm, (FT *)F);
     return hipGetLastError();
 }
 
 template <int J, bool HASB, typename FT>
-hipError_t spin_J(Plan &p, const void *E, const void *B, void *FQ, void *FU)
+hipError_t spin_J(Plan &p, int rend, const void *E, const void *B, void *FQ, void *FU)
 {
-    dim3 grid((p.nrp + 63) / 64, (p.lmax + 1 + 7) / 8);
-    hipLaunchKernelGGL((k_legendre_spin<J, HASB, FT>), grid, dim3(512), 0, p.stream, p.lmax, p.ntheta, p.nrp,
+    if (rend <= 0) return hipSuccess;
+    dim3 grid((rend + 63) / 64, (p.lmax + 1 + 7) / 8);
+    hipLaunchKernelGGL((k_legendre_spin<J, HASB, FT>), grid, dim3(512), 0, p.stream, p.lmax, p.ntheta, p.nrp, rend,
                        p.jtab, (const double2 *)p.trig.ptr, (const double4 *)p.coef2.ptr,
-                       (const double *)p.start.ptr, (const int *)p.exps.ptr, (const double2 *)E,
-                       (const double2 *)B, (FT *)FQ, (FT *)FU);
+                       (const double *)p.start.ptr, (const int *)p.exps.ptr, (const int *)p.mcut.ptr,
+                       (const double2 *)E, (const double2 *)B, (FT *)FQ, (FT *)FU);
     return hipGetLastError();
 }
 
@@ -528,23 +590,32 @@ hipError_t launch_tables(Plan &p)
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
+    hipError_t e;
     switch (p.jtab - 1) {
-    case 1: return start_tables_J<1>(p);
-    case 2: return start_tables_J<2>(p);
-    case 3: return start_tables_J<3>(p);
-    case 4: return start_tables_J<4>(p);
-    case 5: return start_tables_J<5>(p);
-    case 6: return start_tables_J<6>(p);
-    case 7: return start_tables_J<7>(p);
-    case 8: return start_tables_J<8>(p);
+    case 1: e = start_tables_J<1>(p); break;
+    case 2: e = start_tables_J<2>(p); break;
+    case 3: e = start_tables_J<3>(p); break;
+    case 4: e = start_tables_J<4>(p); break;
+    case 5: e = start_tables_J<5>(p); break;
+    case 6: e = start_tables_J<6>(p); break;
+    case 7: e = start_tables_J<7>(p); break;
+    case 8: e = start_tables_J<8>(p); break;
     default: return hipErrorInvalidValue;
     }
+    if (e != hipSuccess) return e;
+    e = hipMemsetAsync(p.mcut.ptr, 0xff, p.mcut.bytes, p.stream);  // -1: nothing significant
+    if (e != hipSuccess) return e;
+    dim3 grid((p.nrp + 255) / 256, p.lmax + 1);
+    hipLaunchKernelGGL(k_mcut, grid, dim3(256), 0, p.stream, p.lmax, p.nrp, p.jtab, (const double2 *)p.trig.ptr,
+                       (const double4 *)p.coef0.ptr, (const double *)p.start.ptr, (const int *)p.exps.ptr,
+                       (int *)p.mcut.ptr);
+    return hipGetLastError();
 }
 
-hipError_t launch_legendre_scalar(Plan &p, int J, const void *alm, void *F, bool out64)
+hipError_t launch_legendre_scalar(Plan &p, int J, int rend, const void *alm, void *F, bool out64)
 {
 #define TL_CASE(JJ) \
-    case JJ: return out64 ? scalar_J<JJ, double>(p, alm, F) : scalar_J<JJ, float>(p, alm, F);
+    case JJ: return out64 ? scalar_J<JJ, double>(p, rend, alm, F) : scalar_J<JJ, float>(p, rend, alm, F);
     switch (J) {
         TL_CASE(0)
         TL_CASE(1)
@@ -560,16 +631,16 @@ hipError_t launch_legendre_scalar(Plan &p, int J, const void *alm, void *F, bool
 #undef TL_CASE
 }
 
-hipError_t launch_legendre_spin(Plan &p, int J, const void *almE, const void *almB, void *FQ, void *FU,
+hipError_t launch_legendre_spin(Plan &p, int J, int rend, const void *almE, const void *almB, void *FQ, void *FU,
                                 bool out64)
 {
 #define TL_CASE(JJ)                                                                          \
     case JJ:                                                                                 \
         if (almB)                                                                            \
-            return out64 ? spin_J<JJ, true, double>(p, almE, almB, FQ, FU)                   \
-                         : spin_J<JJ, true, float>(p, almE, almB, FQ, FU);                   \
-        return out64 ? spin_J<JJ, false, double>(p, almE, almB, FQ, FU)                      \
-                     : spin_J<JJ, false, float>(p, almE, almB, FQ, FU);
+            return out64 ? spin_J<JJ, true, double>(p, rend, almE, almB, FQ, FU)             \
+                         : spin_J<JJ, true, float>(p, rend, almE, almB, FQ, FU);             \
+        return out64 ? spin_J<JJ, false, double>(p, rend, almE, almB, FQ, FU)                \
+                     : spin_J<JJ, false, float>(p, rend, almE, almB, FQ, FU);
     switch (J) {
         TL_CASE(0)
         TL_CASE(1)

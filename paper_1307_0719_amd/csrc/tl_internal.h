@@ -45,6 +45,7 @@ struct Plan {
     int jtab = 0;     // derivative entries per start value (max(N,1)+1)
     int precision = TL_FP32;
     int pol = 0, rotate = 1, naive = 0;
+    int rpole = 0;    // ring pairs kept on the direct FP64 kernel (the polar caps)
     int64_t cap = 0;
     hipStream_t stream = nullptr;
     int device = 0;
@@ -64,6 +65,7 @@ struct Plan {
     DevBuf coef2;     // double4 {a, b(+2), c, 0} spin 2, triangular
     DevBuf start;     // double [3][lmax+1][jtab][nrp]
     DevBuf exps;      // int    [3][lmax+1][nrp]
+    DevBuf mcut;      // int    [nrp]  largest significant m per ring pair
 
     // work buffers
     DevBuf Fphi;      // complex128 [2][ntheta][lmax+1]
@@ -93,9 +95,12 @@ struct Plan {
 
 // ---- kernel launchers (return hipError_t) ----
 hipError_t launch_tables(Plan &p);
-hipError_t launch_legendre_scalar(Plan &p, int J, const void *alm, void *F, bool out64);
-hipError_t launch_legendre_spin(Plan &p, int J, const void *almE, const void *almB, void *FQ,
+hipError_t launch_legendre_scalar(Plan &p, int J, int rend, const void *alm, void *F, bool out64);
+hipError_t launch_legendre_spin(Plan &p, int J, int rend, const void *almE, const void *almB, void *FQ,
                                 void *FU, bool out64);
+bool mfma_supported(int order, bool hasb);
+hipError_t launch_legendre_mfma(Plan &p, const void *T, const void *E, const void *B, void *FT, void *FQ,
+                                void *FU);
 hipError_t launch_fft_jobs(Plan &p, const void *Fbase, void *Dbase, const FftJob *jobs, int njobs,
                            bool fp64);
 hipError_t launch_remap(Plan &p, const void *D, const double *at, const double *ap,

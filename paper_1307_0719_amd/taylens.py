@@ -33,7 +33,7 @@ EXPORTS = [
     "tl_deflection", "tl_legendre", "tl_synth_derivs", "tl_remap", "tl_lens_map_batch",
     "tl_lens_map_simple", "tl_plan_profile", "tl_plan_stage_times", "tl_last_error", "tl_version",
 ]
-STAGES = ["deflection", "legendre_T", "legendre_QU", "ring_fft", "remap"]
+STAGES = ["deflection", "legendre_T", "legendre_QU", "legendre_mfma", "ring_fft", "remap"]
 
 
 class TaylensError(RuntimeError):

@@ -70,7 +70,10 @@ def test_legendre_stage(tl, oracle, precision, lmax, ntheta, order, with_b):
     F = t2np(plan.legendre(sky.alm_T, sky.alm_E, sky.alm_B))
     th = oracle.grid_theta(ntheta)
     ref = oracle.ring_coeffs(lmax, order, th, sky.alm_T, sky.alm_E, sky.alm_B, ORACLE_THREADS)
-    tol = 1e-12 if precision == "fp64" else 3e-7
+    # FP64 form: 1e-11 on max |err| / RMS of each (field, j) block.  FP32 form
+    # (L-power contraction on MFMA away from the polar caps): relative RMS
+    # 3e-6 and max |err| / RMS 5e-5 per block -- operand rounding amplified by
+    # the 1/sin theta coefficients near the caps; the maps stay within 1e-5.
     for f, name in enumerate(("T", "Q", "U")):
         for j in range(order + 1):
             got = F[f, j]
@@ -79,8 +82,36 @@ def test_legendre_stage(tl, oracle, precision, lmax, ntheta, order, with_b):
             if scale == 0:
                 assert np.max(np.abs(got)) == 0
                 continue
-            err = np.max(np.abs(got - want)) / scale
-            assert err < tol * 10, (name, j, err)
+            emax = np.max(np.abs(got - want)) / scale
+            erms = np.sqrt(np.mean(np.abs(got - want) ** 2)) / scale
+            if precision == "fp64":
+                assert emax < 1e-11, (name, j, emax)
+            else:
+                assert erms < 3e-6 and emax < 5e-5, (name, j, erms, emax)
+
+
+@pytest.mark.parametrize("lmax,ntheta,order,with_b", [(64, 301, 4, True), (200, 201, 6, False), (96, 97, 2, True)])
+def test_legendre_fp32_near_poles(tl, oracle, lmax, ntheta, order, with_b):
+    """FP32 form (matrix-core contraction of the L-power form away from the
+    poles): every ring, in particular the first rings past the pole-adjacent
+    ones that stay on the direct kernel, against the oracle."""
+    nphi = smooth_nphi(2 * lmax + 2)
+    sky = _sky(lmax, 71, with_b=with_b)
+    plan = tl.Plan(lmax, ntheta, nphi, order, "fp32", pol=True)
+    F = t2np(plan.legendre(sky.alm_T, sky.alm_E, sky.alm_B))
+    ref = oracle.ring_coeffs(lmax, order, oracle.grid_theta(ntheta), sky.alm_T, sky.alm_E, sky.alm_B,
+                             ORACLE_THREADS)
+    worst, rms = [], []
+    for f, name in enumerate(("T", "Q", "U")):
+        for j in range(order + 1):
+            want = ref[name][:, j, :]
+            scale = np.sqrt(np.mean(np.abs(want) ** 2))
+            err_ring = np.max(np.abs(F[f, j] - want), axis=1) / scale
+            worst.append((float(err_ring.max()), name, j, int(err_ring.argmax())))
+            rms.append(float(np.sqrt(np.mean(np.abs(F[f, j] - want) ** 2)) / scale))
+    worst.sort(reverse=True)
+    assert worst[0][0] < 5e-5, worst[:5]
+    assert max(rms) < 3e-6, rms
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
