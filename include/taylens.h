@@ -52,10 +52,20 @@ extern "C" {
 #define TL_MAX_ORDER 8 /* largest Taylor order N */
 
 /* Contraction precision of the harmonic (Legendre) stage.  The recursion of
- * the Legendre functions is always FP64. */
+ * the Legendre functions is always FP64, and so are the positions, the
+ * rotation angle and the polar caps (sin theta < 0.15).
+ *   TL_FP64   FP64 throughout; maps are float64.
+ *   TL_FP32   FP32 matrix-core contraction (L-power form), FP32 derivative maps
+ *             and Taylor sum; float32 maps.
+ *   TL_BF16X3, TL_FP16X2, TL_FP16, TL_BF16: the lambda / lambda' values are
+ *             tabulated at plan creation (rounded to BF16 / FP16; the X3 / X2
+ *             forms keep hi + lo parts and take hi*hi + hi*lo + lo*hi on the
+ *             matrix cores), each call streams the table (up to opt.batch
+ *             realizations per pass, tl_lens_map_many); float32 maps.
+ *             Orders 0..6.  Tables: about 4 * nrp * lmax^2 bytes (x2 split). */
 enum {
-    TL_FP64 = 0, /* FP64 throughout; maps are float64                          */
-    TL_FP32 = 1, /* FP32 contraction, derivative maps and Taylor sum; float32 out */
+    TL_FP64 = 0,
+    TL_FP32 = 1,
     TL_BF16X3 = 2,
     TL_FP16X2 = 3,
     TL_FP16 = 4,
@@ -75,7 +85,10 @@ typedef struct {
     int32_t naive_pos;     /* 1: theta' = theta + a_t, phi' = phi + a_p / sin theta
                               (reflected over the poles; pole rings stay geodesic;
                               no rotation).  0: geodesic displacement.             */
-    int32_t reserved;      /* must be 0                                                */
+    int32_t batch;         /* realizations per harmonic-stage pass for the tabulated
+                              forms (tl_lens_map_many): 0 or 1 = one; at most 5,
+                              fewer for high orders (error if too many).  Must be
+                              0 or 1 for TL_FP64 / TL_FP32.                        */
     int64_t workspace_cap; /* bytes; 0 = no cap.  tl_plan_create fails with
                               TL_ERR_NOMEM if the plan would need more.            */
 } tl_options;
@@ -143,6 +156,12 @@ int tl_remap(tl_plan plan, const void *D, const double *alpha_theta, const doubl
  * lmax and grid.  Queued on plans[0]'s stream in one pass. */
 int tl_lens_map_batch(int32_t n, const tl_plan *plans, const void *const *alms,
                       void *const *outs);
+
+/* Lens n realizations on ONE plan (all share lmax, grid, order, precision):
+ * alms[4i..4i+3] = (T, E, B, phi), outs[3i..3i+2] = (T, Q, U).  For the
+ * tabulated forms the harmonic stage runs opt.batch realizations per pass over
+ * the lambda tables; the other stages run per realization. */
+int tl_lens_map_many(tl_plan plan, int32_t n, const void *const *alms, void *const *outs);
 
 /* Convenience form with the signature
  *   lens_map(alm_T, alm_E, alm_B, alm_phi, lmax, order, grid) -> T', Q', U'

@@ -2,6 +2,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <algorithm>
 #include <new>
 #include <vector>
 
@@ -109,7 +110,7 @@ void free_buf(DevBuf &b)
 void free_plan_buffers(Plan &p)
 {
     DevBuf *bufs[] = {&p.theta, &p.trig, &p.phitab, &p.phival, &p.twid64, &p.twid32, &p.coef0, &p.coef2,
-                      &p.start, &p.exps, &p.mcut, &p.Fphi, &p.alpha, &p.F, &p.D, &p.jobsDefl, &p.jobsMain};
+                      &p.start, &p.exps, &p.mcut, &p.tab, &p.moff, &p.kstart, &p.Fphi, &p.alpha, &p.F, &p.D, &p.jobsDefl, &p.jobsMain};
     for (DevBuf *b : bufs) free_buf(*b);
 }
 
@@ -139,10 +140,11 @@ double factorial(int n)
 
 struct Sizes {
     size_t theta, trig, phitab, phival, twid64, twid32, coef, start, exps, mcut, Fphi, alpha, F, D, jd, jm;
+    size_t tab = 0, moff = 0, kstart = 0;
     size_t total() const
     {
         return theta + trig + phitab + phival + twid64 + twid32 + 2 * coef + start + exps + mcut + Fphi + alpha + F +
-               D + jd + jm;
+               D + jd + jm + tab + moff + kstart;
     }
 };
 
@@ -165,7 +167,13 @@ Sizes plan_sizes(const Plan &p)
     s.mcut = (size_t)p.nrp * sizeof(int);
     s.Fphi = 2 * rowc * 16;
     s.alpha = 2 * p.npix() * sizeof(double);
-    s.F = (size_t)p.nfield() * (p.order + 1) * rowc * cbytes;
+    s.F = (size_t)p.nfield() * (p.order + 1) * rowc * cbytes * (p.tabform() ? p.batch : 1);
+    if (p.tabform()) {
+        std::vector<int64_t> mo;
+        s.tab = tab_bytes(p.lmax, p.ntile, p.precision == TL_BF16X3 || p.precision == TL_FP16X2, mo);
+        s.moff = (p.lmax + 2) * sizeof(int64_t);
+        s.kstart = (size_t)(p.lmax + 1) * (p.ntile > 0 ? p.ntile : 1) * sizeof(int);
+    }
     s.D = (size_t)p.nfield() * p.ndmap() * p.npix() * rbytes;
     s.jd = 2 * (size_t)p.ntheta * sizeof(FftJob);
     s.jm = (size_t)p.nfield() * (p.order + 1) * p.ntheta * sizeof(FftJob);
@@ -183,12 +191,16 @@ int validate_options(int32_t lmax, tl_grid grid, const tl_options *opt)
         return fail(TL_ERR_INVALID, "nphi must be >= 2*lmax (band limit of each ring)");
     if (opt->order < 0 || opt->order > TL_MAX_ORDER) return fail(TL_ERR_INVALID, "order must be in 0..8");
     if (opt->precision < TL_FP64 || opt->precision > TL_BF16) return fail(TL_ERR_INVALID, "unknown precision");
-    if (opt->precision != TL_FP64 && opt->precision != TL_FP32)
-        return fail(TL_ERR_UNSUPPORTED, "this precision form is not provided by this build");
+    const bool tab = opt->precision >= TL_BF16X3;
+    if (tab && opt->order > 6) return fail(TL_ERR_UNSUPPORTED, "the tabulated precision forms support orders 0..6");
     if (opt->pol != 0 && opt->pol != 1) return fail(TL_ERR_INVALID, "pol must be 0 or 1");
     if (opt->rotate != 0 && opt->rotate != 1) return fail(TL_ERR_INVALID, "rotate must be 0 or 1");
     if (opt->naive_pos != 0 && opt->naive_pos != 1) return fail(TL_ERR_INVALID, "naive_pos must be 0 or 1");
-    if (opt->reserved != 0) return fail(TL_ERR_INVALID, "reserved option field must be 0");
+    if (opt->batch < 0 || (!tab && opt->batch > 1))
+        return fail(TL_ERR_INVALID, "batch must be 0 or 1 for the FP64 / FP32 forms");
+    if (tab && opt->batch > tab_max_batch(opt->order, opt->pol != 0, false))
+        return fail(TL_ERR_INVALID, "batch too large for this order (at most " +
+                                        std::to_string(tab_max_batch(opt->order, opt->pol != 0, false)) + ")");
     if (opt->workspace_cap < 0) return fail(TL_ERR_INVALID, "workspace_cap must be >= 0");
     Plan tmp;
     if (!factor_radices(grid.nphi / 2, tmp))
@@ -299,30 +311,62 @@ int run_deflection(Plan &p, const void *alm_phi)
     return TL_OK;
 }
 
-int run_legendre(Plan &p, const void *T, const void *E, const void *B, void *Fout)
+int run_legendre_many(Plan &p, int n, const void *const *T, const void *const *E, const void *const *B,
+                      void *const *Fout)
 {
     const size_t rowc = (size_t)p.ntheta * (p.lmax + 1) * (p.order + 1);
     const size_t cb = p.fp64() ? 16 : 8;
-    char *F = (char *)Fout;
-    const bool hasb = p.pol && B != nullptr;
-    // FP32 form: matrix-core contraction away from the poles, direct FP64
-    // recursion on the pole-adjacent ring pairs; FP64 form: direct everywhere.
-    const bool mfma = !p.fp64() && mfma_supported(p.order, hasb);
-    const int rend = mfma ? p.rpole : p.nrp;
-    {
-        StageScope sc(p, 1);
-        TL_HIP(launch_legendre_scalar(p, p.order, rend, T, F, p.fp64()), "legendre T");
+    const bool hasb = p.pol && B[0] != nullptr;
+    // FP32 form: matrix-core contraction away from the polar caps; tabulated
+    // forms: table GEMM away from the caps; caps and the FP64 form: direct
+    // FP64 recursion.
+    const bool mfma = p.precision == TL_FP32 && mfma_supported(p.order, hasb);
+    const bool tab = p.tabform() && p.ntile > 0;
+    const int rend = (mfma || tab) ? p.rpole : p.nrp;
+    for (int i = 0; i < n; ++i) {
+        char *F = (char *)Fout[i];
+        {
+            StageScope sc(p, 1);
+            TL_HIP(launch_legendre_scalar(p, p.order, rend, T[i], F, p.fp64()), "legendre T");
+        }
+        if (p.pol) {
+            StageScope sc(p, 2);
+            TL_HIP(launch_legendre_spin(p, p.order, rend, E[i], B[i], F + rowc * cb, F + 2 * rowc * cb, p.fp64()),
+                   "legendre QU");
+        }
+        if (mfma) {
+            StageScope sc(p, 3);
+            TL_HIP(launch_legendre_mfma(p, T[i], E[i], B[i], F, p.pol ? F + rowc * cb : nullptr,
+                                        p.pol ? F + 2 * rowc * cb : nullptr),
+                   "legendre mfma");
+        }
     }
-    if (p.pol) {
-        StageScope sc(p, 2);
-        TL_HIP(launch_legendre_spin(p, p.order, rend, E, B, F + rowc * cb, F + 2 * rowc * cb, p.fp64()), "legendre QU");
-    }
-    if (mfma) {
-        StageScope sc(p, 3);
-        TL_HIP(launch_legendre_mfma(p, T, E, B, F, p.pol ? F + rowc * cb : nullptr, p.pol ? F + 2 * rowc * cb : nullptr),
-               "legendre mfma");
+    if (tab) {
+        const int gmax = tab_max_batch(p.order, p.pol != 0, hasb);
+        for (int i0 = 0; i0 < n; i0 += gmax) {
+            TabBatch b{};
+            b.n = std::min(gmax, n - i0);
+            for (int q = 0; q < b.n; ++q) {
+                char *F = (char *)Fout[i0 + q];
+                b.T[q] = (const double2 *)T[i0 + q];
+                b.E[q] = (const double2 *)E[i0 + q];
+                b.B[q] = (const double2 *)B[i0 + q];
+                b.FT[q] = (float2 *)F;
+                b.FQ[q] = (float2 *)(F + rowc * cb);
+                b.FU[q] = (float2 *)(F + 2 * rowc * cb);
+            }
+            StageScope sc(p, 3);
+            TL_HIP(launch_legendre_tab(p, b), "legendre table gemm");
+        }
     }
     return TL_OK;
+}
+
+int run_legendre(Plan &p, const void *T, const void *E, const void *B, void *Fout)
+{
+    const void *Ts[1] = {T}, *Es[1] = {E}, *Bs[1] = {B};
+    void *Fs[1] = {Fout};
+    return run_legendre_many(p, 1, Ts, Es, Bs, Fs);
 }
 
 int run_derivs(Plan &p, const void *T, const void *E, const void *B, void *Dout)
@@ -399,6 +443,8 @@ int tl_plan_create(tl_plan *out, int32_t lmax, tl_grid grid, const tl_options *o
         while (rp < p.nrp && std::sin(M_PI * (double)rp / (double)(p.ntheta - 1)) < smin) ++rp;
         p.rpole = rp;
     }
+    p.batch = opt->batch > 1 ? opt->batch : 1;
+    p.ntile = (p.nrp - p.rpole + 31) / 32;
 
     Sizes sz = plan_sizes(p);
     if (p.cap > 0 && sz.total() > (size_t)p.cap) {
@@ -434,8 +480,10 @@ int tl_plan_create(tl_plan *out, int32_t lmax, tl_grid grid, const tl_options *o
                 {&p.coef0, sz.coef, "coef0"},    {&p.coef2, sz.coef, "coef2"},     {&p.start, sz.start, "start"},
                 {&p.exps, sz.exps, "exps"},      {&p.mcut, sz.mcut, "mcut"},       {&p.Fphi, sz.Fphi, "Fphi"},       {&p.alpha, sz.alpha, "alpha"},
                 {&p.F, sz.F, "F"},               {&p.D, sz.D, "D"},                {&p.jobsDefl, sz.jd, "jobsDefl"},
-                {&p.jobsMain, sz.jm, "jobsMain"}};
+                {&p.jobsMain, sz.jm, "jobsMain"}, {&p.tab, sz.tab, "tab"},        {&p.moff, sz.moff, "moff"},
+                {&p.kstart, sz.kstart, "kstart"}};
     for (auto &it : list) {
+        if (it.n == 0) continue;
         rc = alloc(p, *it.b, it.n, it.name);
         if (rc) {
             free_plan_buffers(p);
@@ -453,6 +501,13 @@ int tl_plan_create(tl_plan *out, int32_t lmax, tl_grid grid, const tl_options *o
     e = hipMemsetAsync(p.start.ptr, 0, p.start.bytes, p.stream);
     if (e == hipSuccess) e = hipMemsetAsync(p.exps.ptr, 0, p.exps.bytes, p.stream);
     if (e == hipSuccess) e = launch_tables(p);
+    if (e == hipSuccess && p.tabform() && p.ntile > 0) {
+        std::vector<int64_t> mo;
+        tab_bytes(p.lmax, p.ntile, p.precision == TL_BF16X3 || p.precision == TL_FP16X2, mo);
+        e = hipMemcpy(p.moff.ptr, mo.data(), mo.size() * sizeof(int64_t), hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemsetAsync(p.kstart.ptr, 0x7f, p.kstart.bytes, p.stream);
+        if (e == hipSuccess) e = launch_build_tab(p);
+    }
     if (e == hipSuccess) e = fft_prepare(p);
     if (e == hipSuccess) e = hipStreamSynchronize(p.stream);
     if (e != hipSuccess) return bail(hipfail(e, "plan tables"));
@@ -614,6 +669,51 @@ int tl_lens_map_batch(int32_t n, const tl_plan *plans, const void *const *alms, 
                              outs[3 * i + 1], outs[3 * i + 2]);
         p.stream = keep;
         if (rc) return rc;
+    }
+    return TL_OK;
+}
+
+int tl_lens_map_many(tl_plan plan, int32_t n, const void *const *alms, void *const *outs)
+{
+    if (check_plan(plan)) return TL_ERR_INVALID;
+    if (n < 0) return fail(TL_ERR_INVALID, "n must be >= 0");
+    if (n == 0) return TL_OK;
+    if (!alms || !outs) return fail(TL_ERR_INVALID, "NULL argument");
+    Plan &p = plan->p;
+    int rc;
+    for (int i = 0; i < n; ++i) {
+        if ((rc = check_fields(p, alms[4 * i], alms[4 * i + 1]))) return rc;
+        if ((rc = check_outputs(p, outs[3 * i], outs[3 * i + 1], outs[3 * i + 2]))) return rc;
+        if ((alms[4 * i + 2] == nullptr) != (alms[2] == nullptr))
+            return fail(TL_ERR_INVALID, "alm_B must be given for all realizations or for none");
+    }
+    if ((rc = set_device_of(p))) return rc;
+    const size_t rowbytes = (size_t)p.nfield() * (p.order + 1) * p.ntheta * (p.lmax + 1) * (p.fp64() ? 16 : 8);
+    const int g = p.tabform() ? p.batch : 1;
+    for (int i0 = 0; i0 < n; i0 += g) {
+        const int k = std::min(g, n - i0);
+        const void *T[kTabMaxBatch], *E[kTabMaxBatch], *B[kTabMaxBatch];
+        void *F[kTabMaxBatch];
+        for (int q = 0; q < k; ++q) {
+            T[q] = alms[4 * (i0 + q)];
+            E[q] = alms[4 * (i0 + q) + 1];
+            B[q] = alms[4 * (i0 + q) + 2];
+            F[q] = (char *)p.F.ptr + q * rowbytes;
+        }
+        if ((rc = run_legendre_many(p, k, T, E, B, F))) return rc;
+        for (int q = 0; q < k; ++q) {
+            if ((rc = run_deflection(p, alms[4 * (i0 + q) + 3]))) return rc;
+            {
+                StageScope sc(p, 4);
+                TL_HIP(launch_fft_jobs(p, F[q], p.D.ptr, (const FftJob *)p.jobsMain.ptr, p.njobsMain, p.fp64()),
+                       "ring fft");
+            }
+            const double *at = (const double *)p.alpha.ptr;
+            StageScope sc(p, 5);
+            TL_HIP(launch_remap(p, p.D.ptr, at, at + p.npix(), nullptr, nullptr, outs[3 * (i0 + q)],
+                                outs[3 * (i0 + q) + 1], outs[3 * (i0 + q) + 2]),
+                   "remap");
+        }
     }
     return TL_OK;
 }

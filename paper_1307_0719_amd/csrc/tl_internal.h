@@ -37,6 +37,18 @@ struct FftJob {
     double scale[kMaxJobK];      // multiplier of each output
 };
 
+// Realizations handled by one pass of the table GEMM (reduced-precision forms).
+constexpr int kTabMaxBatch = 5;
+struct TabBatch {
+    int n;
+    const double2 *T[kTabMaxBatch];
+    const double2 *E[kTabMaxBatch];
+    const double2 *B[kTabMaxBatch];
+    float2 *FT[kTabMaxBatch];
+    float2 *FQ[kTabMaxBatch];
+    float2 *FU[kTabMaxBatch];
+};
+
 struct Plan {
     int lmax = 0;
     int ntheta = 0, nphi = 0;
@@ -46,6 +58,8 @@ struct Plan {
     int precision = TL_FP32;
     int pol = 0, rotate = 1, naive = 0;
     int rpole = 0;    // ring pairs kept on the direct FP64 kernel (the polar caps)
+    int batch = 1;    // realizations per table-GEMM pass (reduced-precision forms)
+    int ntile = 0;    // 32-ring-pair tiles outside the caps (table forms)
     int64_t cap = 0;
     hipStream_t stream = nullptr;
     int device = 0;
@@ -66,6 +80,9 @@ struct Plan {
     DevBuf start;     // double [3][lmax+1][jtab][nrp]
     DevBuf exps;      // int    [3][lmax+1][nrp]
     DevBuf mcut;      // int    [nrp]  largest significant m per ring pair
+    DevBuf tab;       // lambda / lambda' tables in MFMA operand layout (reduced-precision forms)
+    DevBuf moff;      // int64 [lmax+2] offsets (16-byte units) of each m in tab
+    DevBuf kstart;    // int [lmax+1][ntile] first non-empty 32-l chunk
 
     // work buffers
     DevBuf Fphi;      // complex128 [2][ntheta][lmax+1]
@@ -89,6 +106,7 @@ struct Plan {
     int nfield() const { return pol ? 3 : 1; }
     int ndmap() const { return (order + 1) * (order + 2) / 2; }
     bool fp64() const { return precision == TL_FP64; }
+    bool tabform() const { return precision >= TL_BF16X3; }
     size_t npix() const { return (size_t)ntheta * (size_t)nphi; }
     size_t nalm() const { return (size_t)(lmax + 1) * (size_t)(lmax + 2) / 2; }
 };
@@ -99,6 +117,10 @@ hipError_t launch_legendre_scalar(Plan &p, int J, int rend, const void *alm, voi
 hipError_t launch_legendre_spin(Plan &p, int J, int rend, const void *almE, const void *almB, void *FQ,
                                 void *FU, bool out64);
 bool mfma_supported(int order, bool hasb);
+int tab_max_batch(int order, bool pol, bool hasb);
+size_t tab_bytes(int lmax, int ntile, bool split, std::vector<int64_t> &moff);
+hipError_t launch_build_tab(Plan &p);
+hipError_t launch_legendre_tab(Plan &p, const TabBatch &b);
 hipError_t launch_legendre_mfma(Plan &p, const void *T, const void *E, const void *B, void *FT, void *FQ,
                                 void *FU);
 hipError_t launch_fft_jobs(Plan &p, const void *Fbase, void *Dbase, const FftJob *jobs, int njobs,

@@ -31,7 +31,7 @@ PRECISIONS = {"fp64": 0, "fp32": 1, "bf16x3": 2, "fp16x2": 3, "fp16": 4, "bf16":
 EXPORTS = [
     "tl_plan_create", "tl_plan_destroy", "tl_plan_workspace_bytes", "tl_lens_map", "tl_lens_map_pos",
     "tl_deflection", "tl_legendre", "tl_synth_derivs", "tl_remap", "tl_lens_map_batch",
-    "tl_lens_map_simple", "tl_plan_profile", "tl_plan_stage_times", "tl_last_error", "tl_version",
+    "tl_lens_map_simple", "tl_lens_map_many", "tl_plan_profile", "tl_plan_stage_times", "tl_last_error", "tl_version",
 ]
 STAGES = ["deflection", "legendre_T", "legendre_QU", "legendre_mfma", "ring_fft", "remap"]
 
@@ -48,7 +48,7 @@ class Grid(ctypes.Structure):
 
 class Options(ctypes.Structure):
     _fields_ = [("order", ctypes.c_int32), ("precision", ctypes.c_int32), ("pol", ctypes.c_int32),
-                ("rotate", ctypes.c_int32), ("naive_pos", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("rotate", ctypes.c_int32), ("naive_pos", ctypes.c_int32), ("batch", ctypes.c_int32),
                 ("workspace_cap", ctypes.c_int64)]
 
 
@@ -74,6 +74,7 @@ def lib():
         L.tl_remap.argtypes = [vp] * 7
         L.tl_lens_map_batch.argtypes = [ctypes.c_int32, vp, vp, vp]
         L.tl_lens_map_simple.argtypes = [vp, vp, vp, vp, ctypes.c_int32, ctypes.c_int32, Grid, vp, vp, vp]
+        L.tl_lens_map_many.argtypes = [vp, ctypes.c_int32, vp, vp]
         L.tl_plan_profile.argtypes = [vp, ctypes.c_int32]
         L.tl_plan_stage_times.argtypes = [vp, vp, vp]
         L.tl_last_error.restype = ctypes.c_char_p
@@ -115,7 +116,8 @@ class Plan:
 
     def __init__(self, lmax: int, ntheta: int, nphi: int, order: int, precision: str = "fp32",
                  pol: bool = True, rotate: bool = True, naive_pos: bool = False, workspace_cap: int = 0,
-                 device: Optional[torch.device] = None, stream: Optional[torch.cuda.Stream] = None):
+                 device: Optional[torch.device] = None, stream: Optional[torch.cuda.Stream] = None,
+                 batch: int = 1):
         self.lmax, self.ntheta, self.nphi, self.order = int(lmax), int(ntheta), int(nphi), int(order)
         self.precision = precision
         self.pol = bool(pol)
@@ -123,7 +125,9 @@ class Plan:
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         if precision not in PRECISIONS:
             raise ValueError(f"unknown precision {precision}")
-        opt = Options(order, PRECISIONS[precision], int(pol), int(rotate), int(naive_pos), 0, int(workspace_cap))
+        opt = Options(order, PRECISIONS[precision], int(pol), int(rotate), int(naive_pos), int(batch),
+                      int(workspace_cap))
+        self.batch = int(batch)
         h = ctypes.c_void_p()
         with torch.cuda.device(self.device):
             _check(lib().tl_plan_create(ctypes.byref(h), self.lmax, Grid(self.ntheta, self.nphi),
@@ -193,6 +197,28 @@ class Plan:
                                  _ptr(out[2])))
         self._keep = (T, E, B, P)
         return out
+
+    def lens_map_many(self, alms, outs=None):
+        """alms: list of (T, E, B, phi) tuples; returns list of (T, Q, U)."""
+        n = len(alms)
+        keep = []
+        aarr = (ctypes.c_void_p * (4 * n))()
+        oarr = (ctypes.c_void_p * (3 * n))()
+        if outs is None:
+            outs = [(self._maps(), self._maps() if self.pol else None, self._maps() if self.pol else None)
+                    for _ in range(n)]
+        for i, a in enumerate(alms):
+            T, E, B = self._inputs(a[0], a[1], a[2])
+            P = _alm(a[3], "alm_phi", self.device, self.lmax)
+            keep.append((T, E, B, P))
+            for q, t in enumerate((T, E, B, P)):
+                aarr[4 * i + q] = t.data_ptr() if t is not None else None
+            for q, t in enumerate(outs[i]):
+                oarr[3 * i + q] = t.data_ptr() if t is not None else None
+        _check(lib().tl_lens_map_many(self._h, n, ctypes.cast(aarr, ctypes.c_void_p),
+                                      ctypes.cast(oarr, ctypes.c_void_p)))
+        self._keep = keep
+        return outs
 
     def lens_map_pos(self, alm_T, alm_E, alm_B, theta_src: torch.Tensor, phi_src: torch.Tensor):
         T, E, B = self._inputs(alm_T, alm_E, alm_B)

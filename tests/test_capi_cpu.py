@@ -33,18 +33,18 @@ def test_every_declared_symbol_is_exported(tl):
     assert tl.version() == 10000
 
 
-def _create(tl, lmax, ntheta, nphi, order=3, prec=1, pol=1, rotate=1, naive=0, reserved=0, cap=0):
+def _create(tl, lmax, ntheta, nphi, order=3, prec=1, pol=1, rotate=1, naive=0, batch=0, cap=0):
     h = ctypes.c_void_p(123)
-    o = tl.Options(order, prec, pol, rotate, naive, reserved, cap)
+    o = tl.Options(order, prec, pol, rotate, naive, batch, cap)
     rc = tl.lib().tl_plan_create(ctypes.byref(h), lmax, tl.Grid(ntheta, nphi), ctypes.byref(o), None)
     return rc, h, tl.lib().tl_last_error().decode()
 
 
 @pytest.mark.parametrize("args,code", [
     ((-1, 3, 4), -1), ((10, 1, 20), -1), ((10, 11, 19), -1), ((10, 11, 18), -1), ((10, 11, 22), -2),
-    ((10, 11, 20, 9), -1), ((10, 11, 20, -1), -1), ((10, 11, 20, 3, 7), -1), ((10, 11, 20, 3, 2), -2),
+    ((10, 11, 20, 9), -1), ((10, 11, 20, -1), -1), ((10, 11, 20, 3, 7), -1), ((10, 11, 20, 7, 4), -2), ((10, 11, 20, 4, 4, 1, 1, 0, 6), -1),
     ((10, 11, 20, 3, 1, 2), -1), ((10, 11, 20, 3, 1, 1, 5), -1), ((10, 11, 20, 3, 1, 1, 1, 3), -1),
-    ((10, 11, 20, 3, 1, 1, 0, 0, 1), -1), ((10, 11, 20, 3, 1, 1, 0, 0, 0, -5), -1),
+    ((10, 11, 20, 3, 1, 1, 0, 0, 2), -1), ((10, 11, 20, 3, 1, 1, 0, 0, 0, -5), -1),
     ((64, 65, 128, 3, 1, 1, 1, 0, 0, 1000), -4)])
 def test_invalid_plan_arguments(tl, args, code):
     rc, h, msg = _create(tl, *args)
