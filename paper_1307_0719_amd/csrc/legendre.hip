@@ -296,6 +296,34 @@ __device__ __forceinline__ void load_rhs(double2 (&a)[NR], const double2 *__rest
     if constexpr (NR > 1) a[1] = r1[l];
 }
 
+// Per-wave LDS staging of the recursion coefficients and right-hand sides:
+// chunk k holds l in [64k, 64k + 64); lane q loads entry q with a vector
+// load, the recursion then reads the chunk by broadcast.  Only the owning
+// wave touches its region, so wave-scope fences order the accesses.
+template <int NR>
+struct Stage {
+    double4 cf[64];
+    double2 a[NR][64];
+};
+
+template <int NR>
+__device__ __forceinline__ void stage_fill(Stage<NR> &st, int cbase, int lmax, const double4 *__restrict__ coef,
+                                           const double2 *__restrict__ r0, const double2 *__restrict__ r1)
+{
+    const int q = threadIdx.x & 63;
+    const int l = cbase + q;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    if (l <= lmax) {
+        st.cf[q] = coef[l];
+        st.a[0][q] = r0[l];
+        if constexpr (NR > 1) st.a[1][q] = r1[l];
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Run one family over l = lmin..lmax, accumulating into accE (l even) and
 // accO (l odd).  rhs pointers and coef are based at (l = 0, m) of the
 // triangular layout.  bsgn multiplies the table's b (spin -2: -1).
@@ -303,49 +331,49 @@ template <int J, int NR>
 __device__ void run_family(int lmin, int lmax, double x, double bsgn, const double (&w)[J + 1][J + 1],
                            const double4 *__restrict__ coef, const double2 *__restrict__ r0,
                            const double2 *__restrict__ r1, Rec<J> &st, double2 (&accE)[NR][J + 1],
-                           double2 (&accO)[NR][J + 1])
+                           double2 (&accO)[NR][J + 1], Stage<NR> &sg)
 {
     double2 a[NR];
     if (lmin > lmax) return;
+    int cb = lmin & ~63;
+    stage_fill<NR>(sg, cb, lmax, coef, r0, r1);
+    auto fetch = [&](int l, double4 &cf) {
+        if (l >= cb + 64) {
+            cb = l & ~63;
+            stage_fill<NR>(sg, cb, lmax, coef, r0, r1);
+        }
+        cf = sg.cf[l - cb];
+        a[0] = sg.a[0][l - cb];
+        if constexpr (NR > 1) a[1] = sg.a[1][l - cb];
+    };
+    double4 cf;
     if (st.e == 0) {
-        load_rhs<NR>(a, r0, r1, lmin);
+        fetch(lmin, cf);
         if (lmin & 1) accum<J, NR>(accO, a, st.p1);
         else accum<J, NR>(accE, a, st.p1);
     }
     int l = lmin + 1;
     if (l <= lmax && (l & 1)) {
-        double4 cf = coef[l];
+        fetch(l, cf);
         rec_step<J>(st, cf, x + bsgn * cf.y, w);
         if (st.e > 0) renorm_down<J>(st);
-        if (st.e == 0) {
-            load_rhs<NR>(a, r0, r1, l);
-            accum<J, NR>(accO, a, st.p1);
-        }
+        if (st.e == 0) accum<J, NR>(accO, a, st.p1);
         ++l;
     }
     for (; l + 1 <= lmax; l += 2) {
-        double4 cf = coef[l];
+        fetch(l, cf);
         rec_step<J>(st, cf, x + bsgn * cf.y, w);
-        if (st.e == 0) {
-            load_rhs<NR>(a, r0, r1, l);
-            accum<J, NR>(accE, a, st.p1);
-        }
-        cf = coef[l + 1];
+        if (st.e == 0) accum<J, NR>(accE, a, st.p1);
+        fetch(l + 1, cf);
         rec_step<J>(st, cf, x + bsgn * cf.y, w);
-        if (st.e == 0) {
-            load_rhs<NR>(a, r0, r1, l + 1);
-            accum<J, NR>(accO, a, st.p1);
-        }
+        if (st.e == 0) accum<J, NR>(accO, a, st.p1);
         if (st.e > 0) renorm_down<J>(st);
     }
     if (l <= lmax) {
-        double4 cf = coef[l];
+        fetch(l, cf);
         rec_step<J>(st, cf, x + bsgn * cf.y, w);
         if (st.e > 0) renorm_down<J>(st);
-        if (st.e == 0) {
-            load_rhs<NR>(a, r0, r1, l);
-            accum<J, NR>(accE, a, st.p1);
-        }
+        if (st.e == 0) accum<J, NR>(accE, a, st.p1);
     }
 }
 
@@ -394,14 +422,19 @@ __global__ __launch_bounds__(512) void k_legendre_scalar(
 {
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int m = blockIdx.y * 8 + wave;
-    const int r = blockIdx.x * 64 + (threadIdx.x & 63);
-    if (m > lmax || r >= rend) return;
-    if (m > mcut[r]) {  // evanescent: every term below the cut
-        const size_t plane = (size_t)ntheta * (lmax + 1);
-        const int rs = ntheta - 1 - r;
-        for (int j = 0; j <= J; ++j) {
-            store_c<FT>(F, j * plane + (size_t)r * (lmax + 1) + m, make_double2(0, 0));
-            store_c<FT>(F, j * plane + (size_t)rs * (lmax + 1) + m, make_double2(0, 0));
+    const int r0 = blockIdx.x * 64 + (threadIdx.x & 63);
+    if (m > lmax) return;  // whole wave
+    const bool live = r0 < rend;
+    const bool active = live && m <= mcut[r0];
+    const int r = live ? r0 : 0;  // idle lanes still help fill the LDS chunks
+    if (!__any(active)) {          // evanescent for the whole wave: zeros
+        if (live) {
+            const size_t plane = (size_t)ntheta * (lmax + 1);
+            const int rs = ntheta - 1 - r;
+            for (int j = 0; j <= J; ++j) {
+                store_c<FT>(F, j * plane + (size_t)r * (lmax + 1) + m, make_double2(0, 0));
+                store_c<FT>(F, j * plane + (size_t)rs * (lmax + 1) + m, make_double2(0, 0));
+            }
         }
         return;
     }
@@ -415,15 +448,18 @@ __global__ __launch_bounds__(512) void k_legendre_scalar(
     double2 accE[1][J + 1], accO[1][J + 1];
 #pragma unroll
     for (int j = 0; j <= J; ++j) accE[0][j] = accO[0][j] = make_double2(0, 0);
-    run_family<J, 1>(m, lmax, c, 0.0, w, coef0 + base, alm + base, nullptr, st, accE, accO);
+    __shared__ Stage<1> sgs[8];
+    run_family<J, 1>(m, lmax, c, 0.0, w, coef0 + base, alm + base, nullptr, st, accE, accO, sgs[wave]);
 
     const bool modd = m & 1;
     const size_t plane = (size_t)ntheta * (lmax + 1);
     const int rs = ntheta - 1 - r;
+    if (!live) return;
 #pragma unroll
     for (int j = 0; j <= J; ++j) {
-        const double2 ev = modd ? accO[0][j] : accE[0][j];  // l + m even
-        const double2 od = modd ? accE[0][j] : accO[0][j];
+        double2 ev = modd ? accO[0][j] : accE[0][j];  // l + m even
+        double2 od = modd ? accE[0][j] : accO[0][j];
+        if (!active) ev = od = make_double2(0, 0);
         store_c<FT>(F, j * plane + (size_t)r * (lmax + 1) + m, make_double2(ev.x + od.x, ev.y + od.y));
         if (rs != r) {
             const double sg = (j & 1) ? -1.0 : 1.0;
@@ -454,17 +490,22 @@ __global__ __launch_bounds__(512) void k_legendre_spin(
     constexpr int NR = HASB ? 2 : 1;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int m = blockIdx.y * 8 + wave;
-    const int r = blockIdx.x * 64 + (threadIdx.x & 63);
-    if (m > lmax || r >= rend) return;
+    const int r0 = blockIdx.x * 64 + (threadIdx.x & 63);
+    if (m > lmax) return;  // whole wave
+    const bool live = r0 < rend;
     // spin-2 functions stay below the scalar cut plus 2 (|m - s| <= m + 2)
-    if (m > mcut[r] + 2) {
-        const size_t plane = (size_t)ntheta * (lmax + 1);
-        const int rs = ntheta - 1 - r;
-        for (int j = 0; j <= J; ++j) {
-            store_c<FT>(FQ, j * plane + (size_t)r * (lmax + 1) + m, make_double2(0, 0));
-            store_c<FT>(FQ, j * plane + (size_t)rs * (lmax + 1) + m, make_double2(0, 0));
-            store_c<FT>(FU, j * plane + (size_t)r * (lmax + 1) + m, make_double2(0, 0));
-            store_c<FT>(FU, j * plane + (size_t)rs * (lmax + 1) + m, make_double2(0, 0));
+    const bool active = live && m <= mcut[r0] + 2;
+    const int r = live ? r0 : 0;
+    if (!__any(active)) {
+        if (live) {
+            const size_t plane = (size_t)ntheta * (lmax + 1);
+            const int rs = ntheta - 1 - r;
+            for (int j = 0; j <= J; ++j) {
+                store_c<FT>(FQ, j * plane + (size_t)r * (lmax + 1) + m, make_double2(0, 0));
+                store_c<FT>(FQ, j * plane + (size_t)rs * (lmax + 1) + m, make_double2(0, 0));
+                store_c<FT>(FU, j * plane + (size_t)r * (lmax + 1) + m, make_double2(0, 0));
+                store_c<FT>(FU, j * plane + (size_t)rs * (lmax + 1) + m, make_double2(0, 0));
+            }
         }
         return;
     }
@@ -474,6 +515,7 @@ __global__ __launch_bounds__(512) void k_legendre_spin(
     const size_t base = (size_t)m * (2 * lmax + 1 - m) / 2;
     const int lmin = m > 2 ? m : 2;
     const bool modd = m & 1;
+    __shared__ Stage<NR> sgs[8];
 
     double2 PN[J + 1], MS[J + 1];
     {
@@ -485,7 +527,7 @@ __global__ __launch_bounds__(512) void k_legendre_spin(
 #pragma unroll
             for (int j = 0; j <= J; ++j) accE[q][j] = accO[q][j] = make_double2(0, 0);
         run_family<J, NR>(lmin, lmax, c, 1.0, w, coef2 + base, almE + base, HASB ? almB + base : nullptr,
-                          st, accE, accO);
+                          st, accE, accO, sgs[wave]);
 #pragma unroll
         for (int j = 0; j <= J; ++j) {
             const double2 Ee = modd ? accO[0][j] : accE[0][j], Eo = modd ? accE[0][j] : accO[0][j];
@@ -511,7 +553,7 @@ __global__ __launch_bounds__(512) void k_legendre_spin(
 #pragma unroll
             for (int j = 0; j <= J; ++j) accE[q][j] = accO[q][j] = make_double2(0, 0);
         run_family<J, NR>(lmin, lmax, c, -1.0, w, coef2 + base, almE + base, HASB ? almB + base : nullptr,
-                          st, accE, accO);
+                          st, accE, accO, sgs[wave]);
 #pragma unroll
         for (int j = 0; j <= J; ++j) {
             const double2 Ee = modd ? accO[0][j] : accE[0][j], Eo = modd ? accE[0][j] : accO[0][j];
@@ -529,6 +571,10 @@ __global__ __launch_bounds__(512) void k_legendre_spin(
     }
     const size_t plane = (size_t)ntheta * (lmax + 1);
     const int rs = ntheta - 1 - r;
+    if (!live) return;
+    if (!active)
+#pragma unroll
+        for (int j = 0; j <= J; ++j) PN[j] = MN[j] = PS[j] = MS[j] = make_double2(0, 0);
 #pragma unroll
     for (int j = 0; j <= J; ++j) {
         // Q = (P + M)/2,  U = -i (P - M)/2
