@@ -110,7 +110,7 @@ void free_buf(DevBuf &b)
 void free_plan_buffers(Plan &p)
 {
     DevBuf *bufs[] = {&p.theta, &p.trig, &p.phitab, &p.phival, &p.twid64, &p.twid32, &p.coef0, &p.coef2,
-                      &p.start, &p.exps, &p.mcut, &p.tab, &p.moff, &p.kstart, &p.Fphi, &p.alpha, &p.F, &p.D, &p.jobsDefl, &p.jobsMain};
+                      &p.start, &p.exps, &p.mcut, &p.tab, &p.moff, &p.kstart, &p.rhs, &p.colexp, &p.Fphi, &p.alpha, &p.F, &p.D, &p.jobsDefl, &p.jobsMain};
     for (DevBuf *b : bufs) free_buf(*b);
 }
 
@@ -140,11 +140,11 @@ double factorial(int n)
 
 struct Sizes {
     size_t theta, trig, phitab, phival, twid64, twid32, coef, start, exps, mcut, Fphi, alpha, F, D, jd, jm;
-    size_t tab = 0, moff = 0, kstart = 0;
+    size_t tab = 0, moff = 0, kstart = 0, rhs = 0, colexp = 0;
     size_t total() const
     {
         return theta + trig + phitab + phival + twid64 + twid32 + 2 * coef + start + exps + mcut + Fphi + alpha + F +
-               D + jd + jm + tab + moff + kstart;
+               D + jd + jm + tab + moff + kstart + rhs + colexp;
     }
 };
 
@@ -173,6 +173,9 @@ Sizes plan_sizes(const Plan &p)
         s.tab = tab_bytes(p.lmax, p.ntile, p.precision == TL_BF16X3 || p.precision == TL_FP16X2, mo);
         s.moff = (p.lmax + 2) * sizeof(int64_t);
         s.kstart = (size_t)(p.lmax + 1) * (p.ntile > 0 ? p.ntile : 1) * sizeof(int);
+        const int nb = tab_rhs_blocks(p.order, p.pol != 0, p.batch);
+        s.rhs = tab_rhs_bytes(p.lmax, p.precision == TL_BF16X3 || p.precision == TL_FP16X2, nb);
+        s.colexp = (size_t)(p.lmax + 1) * 32 * nb * sizeof(float);
     }
     s.D = (size_t)p.nfield() * p.ndmap() * p.npix() * rbytes;
     s.jd = 2 * (size_t)p.ntheta * sizeof(FftJob);
@@ -445,6 +448,7 @@ int tl_plan_create(tl_plan *out, int32_t lmax, tl_grid grid, const tl_options *o
     }
     p.batch = opt->batch > 1 ? opt->batch : 1;
     p.ntile = (p.nrp - p.rpole + 31) / 32;
+    if (p.tabform()) p.rhs_nb = tab_rhs_blocks(p.order, p.pol != 0, p.batch);
 
     Sizes sz = plan_sizes(p);
     if (p.cap > 0 && sz.total() > (size_t)p.cap) {
@@ -481,7 +485,7 @@ int tl_plan_create(tl_plan *out, int32_t lmax, tl_grid grid, const tl_options *o
                 {&p.exps, sz.exps, "exps"},      {&p.mcut, sz.mcut, "mcut"},       {&p.Fphi, sz.Fphi, "Fphi"},       {&p.alpha, sz.alpha, "alpha"},
                 {&p.F, sz.F, "F"},               {&p.D, sz.D, "D"},                {&p.jobsDefl, sz.jd, "jobsDefl"},
                 {&p.jobsMain, sz.jm, "jobsMain"}, {&p.tab, sz.tab, "tab"},        {&p.moff, sz.moff, "moff"},
-                {&p.kstart, sz.kstart, "kstart"}};
+                {&p.kstart, sz.kstart, "kstart"}, {&p.rhs, sz.rhs, "rhs"},          {&p.colexp, sz.colexp, "colexp"}};
     for (auto &it : list) {
         if (it.n == 0) continue;
         rc = alloc(p, *it.b, it.n, it.name);

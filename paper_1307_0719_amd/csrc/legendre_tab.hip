@@ -19,6 +19,8 @@
 // lo*hi.  FP16 operands are scaled by powers of two: lam' by 2^-7 in the
 // table, every right-hand-side column of a given m by the power of two that
 // brings its largest entry to [2^13, 2^14).
+#include <algorithm>
+
 #include "tl_internal.h"
 
 namespace tl {
@@ -28,6 +30,7 @@ namespace {
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef _Float16 halfx8 __attribute__((ext_vector_type(8)));
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 
 constexpr double kHi = 0x1p256;
 constexpr double kDown = 0x1p-512;
@@ -142,14 +145,14 @@ __global__ __launch_bounds__(64) void k_build_tab(int lmax, int nrp, int rbeg, i
 struct Cols {
     int PT, PS, nT, nE, nB, n1;
 };
-__host__ __device__ constexpr Cols cols_of(int N, bool hasb)
+__host__ __device__ constexpr Cols cols_of(int N, bool pol, bool hasb)
 {
     Cols c{};
     c.PT = N / 2;
     c.PS = N / 2 + 1;
     c.nT = 2 * (c.PT + 1);
-    c.nE = 2 * (c.PS + 1);
-    c.nB = hasb ? 2 * (c.PS + 1) : 0;
+    c.nE = pol ? 2 * (c.PS + 1) : 0;
+    c.nB = pol && hasb ? 2 * (c.PS + 1) : 0;
     c.n1 = c.nT + c.nE + c.nB;
     return c;
 }
@@ -215,18 +218,17 @@ __device__ void family_coeffs(Jet<N> (&al)[P + 1], Jet<N> (&be)[P + 1], const Je
     }
 }
 
-// Coefficients of one ring (theta) and m for T (ct*), W (cw*), X (cx*).
+// L-power coefficients of one ring (theta) and m: T family (ta, tb) and the
+// spin-2 combinations W (wa, wb) and X (xa, xb).  Built from the Taylor jets
+// of sin and cos at theta (csc, cot and m^2 csc^2 by jet products).
 template <int N>
-struct Coef {
-    static constexpr int PT = N / 2, PS = N / 2 + 1;
-    double ta[N + 1][PT + 1], tb[N + 1][PT + 1];
-    double wa[N + 1][PS + 1], wb[N + 1][PS + 1], xa[N + 1][PS + 1], xb[N + 1][PS + 1];
+struct Jets {
+    Jet<N> csc, cot, jm2;
 };
 template <int N>
-__device__ void coefficients(double th, int m, bool pol, Coef<N> &C)
+__device__ void base_jets(double th, int m, Jets<N> &J)
 {
-    constexpr int PT = N / 2, PS = N / 2 + 1;
-    Jet<N> js, jc, csc, cot, jm2;
+    Jet<N> js, jc;
     const double st = sin(th), ct = cos(th);
     double fac = 1.0;
 #pragma unroll
@@ -242,30 +244,53 @@ __device__ void coefficients(double th, int m, bool pol, Coef<N> &C)
         js.c[i] = sd / fac;
         jc.c[i] = cd / fac;
     }
-    csc.c[0] = 1.0 / js.c[0];
+    J.csc.c[0] = 1.0 / js.c[0];
 #pragma unroll
     for (int i = 1; i <= N; ++i) {
         double s = 0.0;
 #pragma unroll
-        for (int k = 1; k <= i; ++k) s = fma(js.c[k], csc.c[i - k], s);
-        csc.c[i] = -s * csc.c[0];
+        for (int k = 1; k <= i; ++k) s = fma(js.c[k], J.csc.c[i - k], s);
+        J.csc.c[i] = -s * J.csc.c[0];
     }
-    cot = jmul<N>(jc, csc, N);
-    Jet<N> csc2 = jmul<N>(csc, csc, N);
+    J.cot = jmul<N>(jc, J.csc, N);
+    Jet<N> csc2 = jmul<N>(J.csc, J.csc, N);
     const double mm = (double)m * (double)m;
 #pragma unroll
-    for (int i = 0; i <= N; ++i) jm2.c[i] = mm * csc2.c[i];
-    {
-        Jet<N> al[PT + 1], be[PT + 1];
+    for (int i = 0; i <= N; ++i) J.jm2.c[i] = mm * csc2.c[i];
+}
+
+template <int N>
+struct CoefT {
+    static constexpr int PT = N / 2;
+    double ta[N + 1][PT + 1], tb[N + 1][PT + 1];
+};
+template <int N>
+__device__ void coefficients_T(double th, int m, CoefT<N> &C)
+{
+    constexpr int PT = N / 2;
+    Jets<N> J;
+    base_jets<N>(th, m, J);
+    Jet<N> al[PT + 1], be[PT + 1];
 #pragma unroll
-        for (int p = 0; p <= PT; ++p)
+    for (int p = 0; p <= PT; ++p)
 #pragma unroll
-            for (int i = 0; i <= N; ++i) al[p].c[i] = be[p].c[i] = 0.0;
-        al[0].c[0] = 1.0;
-        family_coeffs<N, PT>(al, be, jm2, cot, C.ta, C.tb);
-    }
-    if (!pol) return;
-    Jet<N> cscot = jmul<N>(csc, cot, N);
+        for (int i = 0; i <= N; ++i) al[p].c[i] = be[p].c[i] = 0.0;
+    al[0].c[0] = 1.0;
+    family_coeffs<N, PT>(al, be, J.jm2, J.cot, C.ta, C.tb);
+}
+
+template <int N>
+struct CoefP {
+    static constexpr int PS = N / 2 + 1;
+    double wa[N + 1][PS + 1], wb[N + 1][PS + 1], xa[N + 1][PS + 1], xb[N + 1][PS + 1];
+};
+template <int N>
+__device__ void coefficients_P(double th, int m, CoefP<N> &C)
+{
+    constexpr int PS = N / 2 + 1;
+    Jets<N> J;
+    base_jets<N>(th, m, J);
+    Jet<N> cscot = jmul<N>(J.csc, J.cot, N);
     {
         Jet<N> al[PS + 1], be[PS + 1];
 #pragma unroll
@@ -274,11 +299,11 @@ __device__ void coefficients(double th, int m, bool pol, Coef<N> &C)
             for (int i = 0; i <= N; ++i) al[p].c[i] = be[p].c[i] = 0.0;
 #pragma unroll
         for (int i = 0; i <= N; ++i) {
-            al[0].c[i] = 2.0 * jm2.c[i];
-            be[0].c[i] = -2.0 * cot.c[i];
+            al[0].c[i] = 2.0 * J.jm2.c[i];
+            be[0].c[i] = -2.0 * J.cot.c[i];
         }
         al[1].c[0] = -1.0;
-        family_coeffs<N, PS>(al, be, jm2, cot, C.wa, C.wb);
+        family_coeffs<N, PS>(al, be, J.jm2, J.cot, C.wa, C.wb);
     }
     {
         const double dm = (double)m;
@@ -290,39 +315,150 @@ __device__ void coefficients(double th, int m, bool pol, Coef<N> &C)
 #pragma unroll
         for (int i = 0; i <= N; ++i) {
             al[0].c[i] = 2.0 * dm * cscot.c[i];
-            be[0].c[i] = -2.0 * dm * csc.c[i];
+            be[0].c[i] = -2.0 * dm * J.csc.c[i];
         }
-        family_coeffs<N, PS>(al, be, jm2, cot, C.xa, C.xb);
+        family_coeffs<N, PS>(al, be, J.jm2, J.cot, C.xa, C.xb);
     }
 }
 
-// Batched GEMM: one workgroup = 4 waves = 4 tiles of 32 ring pairs at one m;
-// NBAT realizations, NB = ceil(NBAT * n1 / 32) column blocks in one pass.
+// Right-hand side value of column c (realization c / n1, local column
+// c % n1) at degree l: {L^p a^T} for T, {N_l L^p a^E}, {N_l L^p a^B} for the
+// spin-2 families, real and imaginary parts in adjacent columns.
+template <int N, bool POL, bool HASB, int NBAT>
+__device__ __forceinline__ double rhs_value(const TabBatch &batch, size_t base, int lmax, int l, int c)
+{
+    constexpr Cols C = cols_of(N, POL, HASB);
+    const int b = c / C.n1, cc = c % C.n1;
+    if (b >= NBAT || l > lmax) return 0.0;
+    const double L = (double)l * (double)(l + 1);
+    if (cc < C.nT) {
+        const double2 a = batch.T[b][base + l];
+        double w = 1.0;
+        for (int t = 0; t < (cc >> 1); ++t) w *= L;
+        return w * ((cc & 1) ? a.y : a.x);
+    }
+    if (!POL || l < 2) return 0.0;
+    const double nl = 1.0 / sqrt((double)(l - 1) * l * (double)(l + 1) * (double)(l + 2));
+    int q = cc - C.nT;
+    const double2 *src = batch.E[b];
+    if (HASB && q >= C.nE) {
+        q -= C.nE;
+        src = batch.B[b];
+    }
+    const double2 a = src[base + l];
+    double w = nl;
+    for (int t = 0; t < (q >> 1); ++t) w *= L;
+    return w * ((q & 1) ? a.y : a.x);
+}
+
+// Right-hand sides of one call, built once per m (one workgroup per m) in
+// the B-operand layout of v_mfma_f32_32x32x16: per (m, 32-l chunk) the blocks
+// [split][column block][parity][k-half][column] of 8 values, so that lane i of
+// a wave loads entry i of a block.  FP16: every column of a given m is
+// scaled by the power of two 2^e that brings its largest |value| to
+// [2^13, 2^14); e goes to colexp[m][column].
 template <bool BF, bool SPLIT, int N, bool POL, bool HASB, int NBAT>
-__global__ __launch_bounds__(256) void k_legendre_tab(
-    int lmax, int ntheta, int nrp, int rbeg, int ntile, const double *__restrict__ theta,
-    const int *__restrict__ mcut, const int64_t *__restrict__ moff, const uint4 *__restrict__ tab,
-    const int *__restrict__ kstart, const TabBatch batch)
+__global__ __launch_bounds__(256) void k_tab_rhs(int lmax, int ntile, const int64_t *__restrict__ moff,
+                                                 const TabBatch batch, uint4 *__restrict__ rhs,
+                                                 float *__restrict__ colexp)
 {
     using T = typename H<BF>::T;
-    using V = typename H<BF>::V;
-    constexpr Cols C = cols_of(N, HASB);
+    constexpr Cols C = cols_of(N, POL, HASB);
     constexpr int NCOLS = NBAT * C.n1;
     constexpr int NB = (NCOLS + 31) / 32;
     constexpr int NSPL = SPLIT ? 2 : 1;
+    constexpr int RCH = NSPL * NB * 128;  // uint4 per chunk
+    __shared__ float s_ex[NB * 32];
+    const int m = blockIdx.x;
+    const int tid = threadIdx.x;
+    const size_t base = (size_t)m * (2 * lmax + 1 - m) / 2;
+    const int nk = (lmax - m + 1 + KC - 1) / KC;
+    const int64_t cum = moff[m] / ((int64_t)ntile * NSPL * 256);  // chunks of all m' < m
+    uint4 *out = rhs + cum * RCH;
 
-    __shared__ uint4 s_b[NSPL][NB][2][32][2];  // [split][block][parity][col][k-half] (8 values each)
-    __shared__ float s_scale[NB * 32];         // per column: value = stored * 2^-scale (log2 in float)
-    __shared__ float s_tr[4][32][4][33];       // epilogue transposition, per wave [ring][type*2+par][col]
-    __shared__ int s_ks;
+    if (!BF) {
+        for (int c = tid; c < NB * 32; c += 256) s_ex[c] = 0.f;
+        __syncthreads();
+        for (int idx = tid; idx < (lmax - m + 1) * NCOLS; idx += 256) {
+            const int l = m + idx / NCOLS, c = idx % NCOLS;
+            const float v = (float)fabs(rhs_value<N, POL, HASB, NBAT>(batch, base, lmax, l, c));
+            atomicMax((unsigned *)&s_ex[c], __float_as_uint(v));  // non-negative floats order as uints
+        }
+        __syncthreads();
+        for (int c = tid; c < NB * 32; c += 256) {
+            const float mx = s_ex[c];
+            int ex = 0;
+            if (mx > 0.f) frexpf(mx, &ex);  // mx in [2^(ex-1), 2^ex)
+            s_ex[c] = (float)(14 - ex);     // stored = value * 2^(14 - ex) < 2^14
+        }
+    } else {
+        for (int c = tid; c < NB * 32; c += 256) s_ex[c] = 0.f;
+    }
+    __syncthreads();
+    for (int c = tid; c < NB * 32; c += 256) colexp[(size_t)m * NB * 32 + c] = s_ex[c];
 
-    const int m = blockIdx.y;
+    for (int idx = tid; idx < nk * NB * 128; idx += 256) {
+        const int c = idx & 31, hh = (idx >> 5) & 1, p = (idx >> 6) & 1, b = (idx >> 7) % NB, kc = idx / (NB * 128);
+        const int col = b * 32 + c;
+        const double sc = exp2((double)s_ex[col]);
+        T hi8[8], lo8[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int l = m + kc * KC + p + 2 * (hh * 8 + k);
+            const float f = (float)(rhs_value<N, POL, HASB, NBAT>(batch, base, lmax, l, col) * sc);
+            hi8[k] = (T)f;
+            lo8[k] = (T)(f - (float)hi8[k]);
+        }
+        uint4 w;
+        uint4 *dst = out + (int64_t)kc * RCH + ((b * 2 + p) * 2 + hh) * 32 + c;
+        __builtin_memcpy(&w, hi8, 16);
+        dst[0] = w;
+        if constexpr (SPLIT) {
+            __builtin_memcpy(&w, lo8, 16);
+            dst[NB * 128] = w;
+        }
+    }
+}
+
+// Wave-local ordering of LDS accesses (each wave owns its region).
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Batched GEMM: one workgroup = 4 waves = 4 tiles of 32 ring pairs at one m;
+// NBAT realizations, NB = ceil(NBAT * n1 / 32) column blocks in one pass.  The
+// table streams from HBM once per pass; the right-hand sides of one m (built
+// by k_tab_rhs) are shared by all its tiles, and the workgroups of one m run
+// on one XCD (m = xcd + 8 i) so they are read from HBM once.  Each wave walks
+// its own tile from its first non-empty chunk; nothing in the main loop
+// synchronizes the workgroup.
+template <bool BF, bool SPLIT, int N, bool POL, bool HASB, int NBAT>
+__global__ __launch_bounds__(256) void k_legendre_tab(
+    int lmax, int ntheta, int nrp, int rbeg, int ntile, int ngrp, const double *__restrict__ theta,
+    const int *__restrict__ mcut, const int64_t *__restrict__ moff, const uint4 *__restrict__ tab,
+    const int *__restrict__ kstart, const uint4 *__restrict__ rhs, const float *__restrict__ colexp,
+    const TabBatch batch)
+{
+    using V = typename H<BF>::V;
+    constexpr Cols C = cols_of(N, POL, HASB);
+    constexpr int NCOLS = NBAT * C.n1;
+    constexpr int NB = (NCOLS + 31) / 32;
+    constexpr int NSPL = SPLIT ? 2 : 1;
+    constexpr int RCH = NSPL * NB * 128;
+
+    __shared__ float s_tr[4][32][4][33];  // epilogue transposition, per wave [ring][type*2+par][col]
+
+    const int xcd = blockIdx.x & 7, q = blockIdx.x >> 3;
+    const int m = xcd + 8 * (q / ngrp);
+    if (m > lmax) return;  // whole workgroup
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int tile = blockIdx.x * 4 + wave;
+    const int tile = (q % ngrp) * 4 + wave;
     const int rl = lane & 31, hl = lane >> 5;
     const int r = rbeg + tile * TILE + rl;
     const bool live = (tile < ntile) && (r < nrp);
-    const size_t base = (size_t)m * (2 * lmax + 1 - m) / 2;
     const int nk = (lmax - m + 1 + KC - 1) / KC;
     const size_t plane = (size_t)ntheta * (lmax + 1);
 
@@ -341,58 +477,6 @@ __global__ __launch_bounds__(256) void k_legendre_tab(
                 }
         return;
     }
-    // first chunk with a non-zero table value over the 4 tiles
-    if (tid == 0) s_ks = nk;
-    __syncthreads();
-    if (lane == 0 && tile < ntile) atomicMin(&s_ks, kstart[(size_t)m * ntile + tile]);
-
-    // right-hand-side value of column c (realization b, local column cc) at l
-    auto rhs = [&](int l, int c) -> double {
-        const int b = c / C.n1, cc = c % C.n1;
-        if (b >= NBAT || l > lmax) return 0.0;
-        const double L = (double)l * (double)(l + 1);
-        if (cc < C.nT) {
-            const double2 a = batch.T[b][base + l];
-            double w = 1.0;
-            for (int t = 0; t < (cc >> 1); ++t) w *= L;
-            return w * ((cc & 1) ? a.y : a.x);
-        }
-        if (!POL || l < 2) return 0.0;
-        const double nl = 1.0 / sqrt((double)(l - 1) * l * (double)(l + 1) * (double)(l + 2));
-        int q = cc - C.nT;
-        const double2 *src = batch.E[b];
-        if (HASB && q >= C.nE) {
-            q -= C.nE;
-            src = batch.B[b];
-        }
-        const double2 a = src[base + l];
-        double w = nl;
-        for (int t = 0; t < (q >> 1); ++t) w *= L;
-        return w * ((q & 1) ? a.y : a.x);
-    };
-
-    // per-column power-of-two scale (FP16 only): largest |value| over l
-    if (!BF) {
-        __shared__ float s_mx[NB * 32];
-        for (int c = tid; c < NB * 32; c += 256) s_mx[c] = 0.f;
-        __syncthreads();
-        for (int idx = tid; idx < (lmax - m + 1) * NCOLS; idx += 256) {
-            const int l = m + idx / NCOLS, c = idx % NCOLS;
-            const float v = (float)fabs(rhs(l, c));
-            atomicMax((unsigned *)&s_mx[c], __float_as_uint(v));  // non-negative floats order as uints
-        }
-        __syncthreads();
-        for (int c = tid; c < NB * 32; c += 256) {
-            const float mx = s_mx[c];
-            int ex = 0;
-            if (mx > 0.f) frexpf(mx, &ex);  // mx in [2^(ex-1), 2^ex)
-            s_scale[c] = (float)(14 - ex);  // stored = value * 2^(14 - ex) < 2^14
-        }
-    } else {
-        for (int c = tid; c < NB * 32; c += 256) s_scale[c] = 0.f;
-    }
-    __syncthreads();
-    const int ks = s_ks;
 
     floatx16 acc[NB][2][2];
 #pragma unroll
@@ -404,93 +488,99 @@ __global__ __launch_bounds__(256) void k_legendre_tab(
 #pragma unroll
                 for (int v = 0; v < 16; ++v) acc[b][t][p][v] = 0.f;
 
-    const uint4 *blk = (tile < ntile) ? tab + (moff[m] + (int64_t)tile * nk * NSPL * 4 * 64) : nullptr;
-    for (int kc = ks; kc < nk; ++kc) {
-        __syncthreads();
-        // right-hand sides of this chunk: 32 l (16 per parity) x NB*32 columns
-        for (int idx = tid; idx < NB * 32 * 2 * 2; idx += 256) {
-            const int hh = idx & 1, p = (idx >> 1) & 1, c = (idx >> 2) % 32, b = idx / 128;
-            const int col = b * 32 + c;
-            const float sc = exp2f(s_scale[col]);
-            T hi8[8], lo8[8];
+    if (tile < ntile) {
+        // The table streams with PF chunks in flight per wave (the loop is
+        // bound by HBM, not by the matrix cores); the right-hand sides of
+        // the next chunk are fetched one chunk ahead.
+        constexpr int PF = SPLIT ? 2 : 4;
+        constexpr int AW = NSPL * 4;  // uint4 per lane per chunk
+        const int ks = __builtin_amdgcn_readfirstlane(kstart[(size_t)m * ntile + tile]);
+        const uint4 *blk = tab + (moff[m] + (int64_t)tile * nk * AW * 64) + lane;
+        const int64_t cum = moff[m] / ((int64_t)ntile * NSPL * 256);
+        const uint4 *rb = rhs + cum * RCH + lane;
+        uint4 Ab[PF][AW];
+        uint4 Bb[2][NSPL][NB][2];
+        auto loadA = [&](uint4 (&dst)[AW], int kc) {
+            const uint4 *cb = blk + (int64_t)kc * AW * 64;
 #pragma unroll
-            for (int k = 0; k < 8; ++k) {
-                const int kk = hh * 8 + k;
-                const int l = m + kc * KC + p + 2 * kk;
-                const float f = (float)(rhs(l, col) * (double)sc);
-                hi8[k] = (T)f;
-                lo8[k] = (T)(f - (float)hi8[k]);
+            for (int u = 0; u < AW; ++u) {
+                const u32x4 v = __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(cb + u * 64));
+                __builtin_memcpy(&dst[u], &v, 16);
             }
-            uint4 w;
-            __builtin_memcpy(&w, hi8, 16);
-            s_b[0][b][p][c][hh] = w;
-            if (SPLIT) {
-                __builtin_memcpy(&w, lo8, 16);
-                s_b[NSPL - 1][b][p][c][hh] = w;
-            }
-        }
-        __syncthreads();
-        if (tile < ntile) {
-            const uint4 *cb = blk + (int64_t)kc * NSPL * 4 * 64;
-            V A[NSPL][2][2];
+        };
+        auto loadB = [&](uint4 (&dst)[NSPL][NB][2], int kc) {
+            const uint4 *rc = rb + (int64_t)kc * RCH;
 #pragma unroll
             for (int sp = 0; sp < NSPL; ++sp)
 #pragma unroll
-                for (int t = 0; t < 2; ++t)
+                for (int b = 0; b < NB; ++b)
+#pragma unroll
+                    for (int p = 0; p < 2; ++p) dst[sp][b][p] = rc[((sp * NB + b) * 2 + p) * 64];
+        };
+#pragma unroll
+        for (int u = 0; u < PF; ++u)
+            if (ks + u < nk) loadA(Ab[u], ks + u);
+        if (ks < nk) loadB(Bb[0], ks);
+        for (int k0 = ks; k0 < nk; k0 += PF) {
+#pragma unroll
+            for (int u = 0; u < PF; ++u) {
+                const int kc = k0 + u;
+                if (kc >= nk) break;
+                if (kc + 1 < nk) loadB(Bb[(u + 1) & 1], kc + 1);
+                V A[NSPL][2][2];
+#pragma unroll
+                for (int sp = 0; sp < NSPL; ++sp)
+#pragma unroll
+                    for (int t = 0; t < 2; ++t)
+#pragma unroll
+                        for (int p = 0; p < 2; ++p) __builtin_memcpy(&A[sp][t][p], &Ab[u][(sp * 2 + t) * 2 + p], 16);
+                if (kc + PF < nk) loadA(Ab[u], kc + PF);
+#pragma unroll
+                for (int b = 0; b < NB; ++b)
 #pragma unroll
                     for (int p = 0; p < 2; ++p) {
-                        const uint4 w = cb[((sp * 2 + t) * 2 + p) * 64 + lane];
-                        __builtin_memcpy(&A[sp][t][p], &w, 16);
-                    }
+                        V Bh, Bl;
+                        __builtin_memcpy(&Bh, &Bb[u & 1][0][b][p], 16);
+                        if constexpr (SPLIT) __builtin_memcpy(&Bl, &Bb[u & 1][NSPL - 1][b][p], 16);
 #pragma unroll
-            for (int b = 0; b < NB; ++b)
-#pragma unroll
-                for (int p = 0; p < 2; ++p) {
-                    V Bh, Bl;
-                    uint4 w = s_b[0][b][p][rl][hl];
-                    __builtin_memcpy(&Bh, &w, 16);
-                    if (SPLIT) {
-                        w = s_b[NSPL - 1][b][p][rl][hl];
-                        __builtin_memcpy(&Bl, &w, 16);
-                    }
-#pragma unroll
-                    for (int t = 0; t < 2; ++t) {
-                        if constexpr (BF) {
-                            acc[b][t][p] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[0][t][p], Bh, acc[b][t][p], 0, 0, 0);
-                            if constexpr (SPLIT) {
-                                acc[b][t][p] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[0][t][p], Bl, acc[b][t][p], 0, 0, 0);
-                                acc[b][t][p] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[NSPL - 1][t][p], Bh, acc[b][t][p], 0, 0, 0);
-                            }
-                        } else {
-                            acc[b][t][p] = __builtin_amdgcn_mfma_f32_32x32x16_f16(A[0][t][p], Bh, acc[b][t][p], 0, 0, 0);
-                            if constexpr (SPLIT) {
-                                acc[b][t][p] = __builtin_amdgcn_mfma_f32_32x32x16_f16(A[0][t][p], Bl, acc[b][t][p], 0, 0, 0);
-                                acc[b][t][p] = __builtin_amdgcn_mfma_f32_32x32x16_f16(A[NSPL - 1][t][p], Bh, acc[b][t][p], 0, 0, 0);
+                        for (int t = 0; t < 2; ++t) {
+                            if constexpr (BF) {
+                                acc[b][t][p] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[0][t][p], Bh, acc[b][t][p], 0, 0, 0);
+                                if constexpr (SPLIT) {
+                                    acc[b][t][p] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[0][t][p], Bl, acc[b][t][p], 0, 0, 0);
+                                    acc[b][t][p] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[NSPL - 1][t][p], Bh, acc[b][t][p], 0, 0, 0);
+                                }
+                            } else {
+                                acc[b][t][p] = __builtin_amdgcn_mfma_f32_32x32x16_f16(A[0][t][p], Bh, acc[b][t][p], 0, 0, 0);
+                                if constexpr (SPLIT) {
+                                    acc[b][t][p] = __builtin_amdgcn_mfma_f32_32x32x16_f16(A[0][t][p], Bl, acc[b][t][p], 0, 0, 0);
+                                    acc[b][t][p] = __builtin_amdgcn_mfma_f32_32x32x16_f16(A[NSPL - 1][t][p], Bh, acc[b][t][p], 0, 0, 0);
+                                }
                             }
                         }
                     }
-                }
+            }
         }
     }
 
     // ---- epilogue: per wave, transpose one 32-column block at a time ----
-    Coef<N> cf;
-    if (live) coefficients<N>(theta[r], m, POL, cf);
     const int rs = ntheta - 1 - r;
     const double dsc = BF ? 1.0 : 1.0 / kDerivScale;
+    const float *cex = colexp + (size_t)m * NB * 32;
     // output accumulators for this lane's ring: lanes 0..31 T, lanes 32..63 Q/U
     for (int bb = 0; bb < NBAT; ++bb) {
         // sums S[type*2+par][cc] of realization bb, gathered block by block
-        double S[4][C.n1];
+        // (exact in FP32: the accumulators times powers of two)
+        float S[4][C.n1];
 #pragma unroll
-        for (int q = 0; q < 4; ++q)
+        for (int q4 = 0; q4 < 4; ++q4)
 #pragma unroll
-            for (int c = 0; c < C.n1; ++c) S[q][c] = 0.0;
+            for (int c = 0; c < C.n1; ++c) S[q4][c] = 0.f;
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
             const int c0 = b * 32;
             if (c0 + 32 <= bb * C.n1 || c0 >= (bb + 1) * C.n1) continue;
-            __syncthreads();
+            wave_sync();
 #pragma unroll
             for (int t = 0; t < 2; ++t)
 #pragma unroll
@@ -500,22 +590,24 @@ __global__ __launch_bounds__(256) void k_legendre_tab(
                         const int row = 8 * (vv >> 2) + 4 * hl + (vv & 3);
                         s_tr[wave][row][t * 2 + p][rl] = acc[b][t][p][vv];
                     }
-            __syncthreads();
+            wave_sync();
 #pragma unroll
             for (int c = 0; c < C.n1; ++c) {
                 const int col = bb * C.n1 + c;
                 if (col < c0 || col >= c0 + 32) continue;
-                const double isc = exp2(-(double)s_scale[col]);
+                const float isc = exp2f(-cex[col]);
 #pragma unroll
-                for (int q = 0; q < 4; ++q)
-                    S[q][c] = (double)s_tr[wave][rl][q][col - c0] * isc * ((q >> 1) ? dsc : 1.0);
+                for (int q4 = 0; q4 < 4; ++q4)
+                    S[q4][c] = s_tr[wave][rl][q4][col - c0] * isc * ((q4 >> 1) ? (float)dsc : 1.f);
             }
         }
         if (!live) continue;
-        auto nsum = [&](int type, int c) { return S[type * 2][c] + S[type * 2 + 1][c]; };
-        auto dsum = [&](int type, int c) { return S[type * 2][c] - S[type * 2 + 1][c]; };
+        auto nsum = [&](int type, int c) { return (double)S[type * 2][c] + (double)S[type * 2 + 1][c]; };
+        auto dsum = [&](int type, int c) { return (double)S[type * 2][c] - (double)S[type * 2 + 1][c]; };
         float2 *FT = batch.FT[bb];
         if (hl == 0) {
+            CoefT<N> cf;
+            coefficients_T<N>(theta[r], m, cf);
 #pragma unroll
             for (int j = 0; j <= N; ++j) {
                 double nre = 0, nim = 0, sre = 0, sim = 0;
@@ -534,6 +626,8 @@ __global__ __launch_bounds__(256) void k_legendre_tab(
             }
         } else if constexpr (POL) {
             float2 *FQ = batch.FQ[bb], *FU = batch.FU[bb];
+            CoefP<N> cf;
+            coefficients_P<N>(theta[r], m, cf);
 #pragma unroll
             for (int j = 0; j <= N; ++j) {
                 double ewn[2] = {0, 0}, exn[2] = {0, 0}, bwn[2] = {0, 0}, bxn[2] = {0, 0};
@@ -589,13 +683,21 @@ hipError_t build_BS(Plan &p)
 template <bool BF, bool SPLIT, int N, bool POL, bool HASB, int NBAT>
 hipError_t gemm_launch(Plan &p, const TabBatch &b)
 {
-    if constexpr ((NBAT * cols_of(N, HASB).n1 + 31) / 32 > 4) {
+    constexpr int NB = (NBAT * cols_of(N, POL, HASB).n1 + 31) / 32;
+    if constexpr (NB > 4) {
         return hipErrorInvalidValue;
     } else {
-        dim3 grid((p.ntile + 3) / 4, p.lmax + 1);
-        hipLaunchKernelGGL((k_legendre_tab<BF, SPLIT, N, POL, HASB, NBAT>), grid, dim3(256), 0, p.stream, p.lmax,
-                           p.ntheta, p.nrp, p.rpole, p.ntile, (const double *)p.theta.ptr, (const int *)p.mcut.ptr,
-                           (const int64_t *)p.moff.ptr, (const uint4 *)p.tab.ptr, (const int *)p.kstart.ptr, b);
+        if ((size_t)NB > p.rhs_nb) return hipErrorInvalidValue;  // buffers sized at plan time
+        hipLaunchKernelGGL((k_tab_rhs<BF, SPLIT, N, POL, HASB, NBAT>), dim3(p.lmax + 1), dim3(256), 0, p.stream,
+                           p.lmax, p.ntile, (const int64_t *)p.moff.ptr, b, (uint4 *)p.rhs.ptr, (float *)p.colexp.ptr);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        const int ngrp = (p.ntile + 3) / 4;
+        const int m8 = (p.lmax + 1 + 7) / 8;
+        hipLaunchKernelGGL((k_legendre_tab<BF, SPLIT, N, POL, HASB, NBAT>), dim3(8 * m8 * ngrp), dim3(256), 0,
+                           p.stream, p.lmax, p.ntheta, p.nrp, p.rpole, p.ntile, ngrp, (const double *)p.theta.ptr,
+                           (const int *)p.mcut.ptr, (const int64_t *)p.moff.ptr, (const uint4 *)p.tab.ptr,
+                           (const int *)p.kstart.ptr, (const uint4 *)p.rhs.ptr, (const float *)p.colexp.ptr, b);
         return hipGetLastError();
     }
 }
@@ -640,11 +742,29 @@ hipError_t gemm_form(Plan &p, const TabBatch &b)
 int tab_max_batch(int order, bool pol, bool hasb)
 {
     if (order > 6) return 0;
-    const Cols c = cols_of(order, pol && hasb);
-    const int n1 = pol ? c.n1 : c.nT;
+    const int n1 = cols_of(order, pol, hasb).n1;
     int nb = 0;
     while (nb < 5 && ((nb + 1) * n1 + 31) / 32 <= 4) ++nb;
     return nb;
+}
+
+int tab_rhs_blocks(int order, bool pol, int batch)
+{
+    int nb = 1;
+    for (int hb = 0; hb < 2; ++hb) {
+        if (hb && !pol) break;
+        const int n1 = cols_of(order, pol, hb != 0).n1;
+        const int g = std::min(std::max(batch, 1), tab_max_batch(order, pol, hb != 0));
+        nb = std::max(nb, (g * n1 + 31) / 32);
+    }
+    return nb;
+}
+
+size_t tab_rhs_bytes(int lmax, bool split, int nblocks)
+{
+    size_t chunks = 0;
+    for (int m = 0; m <= lmax; ++m) chunks += (lmax - m + 1 + KC - 1) / KC;
+    return chunks * (split ? 2 : 1) * nblocks * 128 * 16;
 }
 
 size_t tab_bytes(int lmax, int ntile, bool split, std::vector<int64_t> &moff)

@@ -83,6 +83,9 @@ struct Plan {
     DevBuf tab;       // lambda / lambda' tables in MFMA operand layout (reduced-precision forms)
     DevBuf moff;      // int64 [lmax+2] offsets (16-byte units) of each m in tab
     DevBuf kstart;    // int [lmax+1][ntile] first non-empty 32-l chunk
+    DevBuf rhs;       // table-GEMM right-hand sides of one call, B-operand layout
+    DevBuf colexp;    // float [lmax+1][32 * rhs_nb] power-of-two column scales (FP16)
+    size_t rhs_nb = 0;  // 32-column blocks the rhs buffer holds per chunk
 
     // work buffers
     DevBuf Fphi;      // complex128 [2][ntheta][lmax+1]
@@ -119,6 +122,8 @@ hipError_t launch_legendre_spin(Plan &p, int J, int rend, const void *almE, cons
 bool mfma_supported(int order, bool hasb);
 int tab_max_batch(int order, bool pol, bool hasb);
 size_t tab_bytes(int lmax, int ntile, bool split, std::vector<int64_t> &moff);
+int tab_rhs_blocks(int order, bool pol, int batch);
+size_t tab_rhs_bytes(int lmax, bool split, int nblocks);
 hipError_t launch_build_tab(Plan &p);
 hipError_t launch_legendre_tab(Plan &p, const TabBatch &b);
 hipError_t launch_legendre_mfma(Plan &p, const void *T, const void *E, const void *B, void *FT, void *FQ,
