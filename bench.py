@@ -1,140 +1,213 @@
 #!/usr/bin/env python3
 """Throughput of full-sky Taylor lensing on one MI355X.
 
-One step = one call of the whole lensing path (deflection synthesis, harmonic
+One step = one pass of the whole lensing path (deflection synthesis, harmonic
 stage of T and Q/U with theta-derivatives, ring FFTs with the phi-derivative
-factors, remap + Taylor sum + polarization rotation) on one realization whose
-a_lm are already resident in HBM.  Default workload: T+Q/U, lmax = 4096 on the
-4097 x 8192 equal-theta ring grid, Taylor order 4, FP32 form.
+factors, remap + Taylor sum + polarization rotation) over one batch of
+realizations whose a_lm are already resident in HBM.  Workload: T+Q/U,
+lmax = 4096 on the 4097 x 8192 equal-theta ring grid, Taylor order 4.
 
-Prints ONE JSON line (see keys below).  ``roofline`` describes the dominant
-kernel, timed live with HIP events on the plan's stream; ``cpu_baseline`` is
-the CPU oracle timed on a bounded sample of the same workload (a band of
-output rings), which also gives the stated relative error of the GPU maps.
+Every precision form named by --forms ("fp32", "fp16:5" = FP16 tables, five
+realizations per table pass, ...) is timed; ``value`` is the pixel rate of
+the --headline form, the others go to ``forms`` with their speed-up over the
+FP32 form and their relative RMS error against the FP64 CPU oracle on a band
+of output rings.  ``roofline`` describes the headline's dominant kernel, its
+average launch duration timed live with HIP events on the plan's stream, its
+algorithmic work per launch from the plan's work counts.  ``cpu_baseline`` is
+the oracle's rate on that band of rings.
+
+Prints ONE JSON line.
 """
 from __future__ import annotations
 
 import argparse
 import json
-import math
 import os
 import sys
 import time
 
-FP64_VECTOR_PEAK = 78.6e12      # MI355X FP64 vector FLOP/s
-FP32_VECTOR_PEAK = 157.3e12
-HBM_PEAK = 8.0e12               # bytes/s
+# MI355X published peaks
+PEAK = {
+    "fp64": 78.6e12,        # FP64 vector (and matrix) FLOP/s
+    "fp32_mfma": 157.3e12,  # FP32 matrix FLOP/s
+    "f16_mfma": 2.5e15,     # dense FP16 / BF16 matrix FLOP/s
+    "hbm": 8.0e12,          # bytes/s
+}
 
 
-def legendre_flops(lmax: int, nrp: int, J: int, pol: bool, hasb: bool):
-    """Algorithmic FP64 flops of the harmonic stage per launch (direct
-    recursion): per (l, m, ring-pair) element and family,
-      recursion  sum_j [2(j+1) + 3] = (J+1)(J+5),
-      contraction 4 (J+1) per complex right-hand side."""
-    nalm = (lmax + 1) * (lmax + 2) // 2
-    per = (J + 1) * (J + 5)
-    t = nalm * nrp * (per + 4 * (J + 1))
-    if not pol or lmax < 2:
-        return t, 0
-    nspin = (nalm - 3) * nrp
-    s = 2 * nspin * (per + 4 * (J + 1) * (2 if hasb else 1))
-    return t, s
+def cols(order: int, pol: bool, hasb: bool):
+    """Real right-hand-side columns of the L-power contraction per realization."""
+    nT = 2 * (order // 2 + 1)
+    nE = 2 * (order // 2 + 2) if pol else 0
+    nB = nE if (pol and hasb) else 0
+    return nT + nE + nB
+
+
+def direct_flops_per_elem(J: int, spin: bool, hasb: bool):
+    """FP64 flops of the direct kernels per (l, m, ring pair) element: the
+    Leibniz recursion of the J+1 theta-derivatives, sum_j (2j + 4) + 1, plus
+    4 (J+1) per complex right-hand side; two families for spin 2."""
+    rec = (J + 1) * (J + 4) + 1
+    if not spin:
+        return rec + 4 * (J + 1)
+    return 2 * (rec + 4 * (J + 1) * (2 if hasb else 1))
+
+
+def a3_useful_flops(lmax: int, nrp: int, order: int, pol: bool, hasb: bool):
+    """Useful flops of the harmonic stage as the plain contraction counts them:
+    (N+1) theta-derivative rows times 2 real MACs for T and 8 for Q/U (16 with
+    B) per (l, m, ring pair), dense."""
+    nlm = (lmax + 1) * (lmax + 2) // 2
+    R = 2 + ((16 if hasb else 8) if pol else 0)
+    return 2 * nlm * nrp * (order + 1) * R
+
+
+def stage_work(w, order, form, q, hasb, n):
+    """Per-launch algorithmic work of each stage's kernel: (bound, amount,
+    unit, peak).  Harmonic-stage element counts are those below the
+    evanescent cut (plan work counts)."""
+    nfield = 3 if w.pol else 1
+    ndmap = (order + 1) * (order + 2) // 2
+    npix = w.ntheta * w.nphi
+    rowc = w.ntheta * (w.lmax + 1)
+    nlm = (w.lmax + 1) * (w.lmax + 2) // 2
+    fp64 = form == "fp64"
+    tab = form in ("bf16x3", "fp16x2", "fp16", "bf16")
+    caps = q["elems"] if fp64 else q["elems_caps"]
+    cbytes = 16 if fp64 else 8
+    rbytes = 8 if fp64 else 4
+    out = {
+        "defl_legendre": ("fp64", direct_flops_per_elem(1, False, False) * q["elems"]),
+        "defl_fft": ("hbm", 2 * rowc * 16 + 2 * npix * 8),
+        "legendre_T": ("fp64", direct_flops_per_elem(order, False, False) * caps),
+        "legendre_QU": ("fp64", direct_flops_per_elem(order, True, hasb) * caps),
+        "legendre_mfma": ("fp32_mfma", (q["elems"] - q["elems_caps"]) * 2 * cols(order, w.pol, hasb) * 2),
+        "tab_rhs": ("hbm", n * nlm * 16 * (1 + (2 if hasb else 1) * w.pol)),
+        "legendre_tab": ("hbm", q["tab_chunks"] * q["tab_chunk_bytes"]
+                         + n * nfield * (order + 1) * 2 * (w.ntheta // 2 - q["rpole"]) * (w.lmax + 1) * 8),
+        "ring_fft": ("hbm", nfield * (order + 1) * rowc * cbytes + nfield * ndmap * npix * rbytes),
+        "remap": ("hbm", npix * (16 + nfield * 4) + nfield * ndmap * npix * rbytes),
+    }
+    res = {}
+    for k, (res_kind, amount) in out.items():
+        unit = "GB/s" if res_kind == "hbm" else "TFLOP/s"
+        res[k] = (res_kind, float(amount), unit, PEAK[res_kind])
+    if tab:
+        # the table GEMM also issues f16 MFMA work (useful columns only)
+        res["legendre_tab_mfma"] = ("f16_mfma", float((q["elems"] - q["elems_caps"]) * 2 * n
+                                                     * cols(order, w.pol, hasb) * 2), "TFLOP/s", PEAK["f16_mfma"])
+    return res
+
+
+def parse_form(s: str):
+    prec, _, b = s.partition(":")
+    return prec, int(b) if b else 1
+
+
+def run_form(args, w, order, prec, batch, skies_dev):
+    import torch
+
+    from paper_1307_0719_amd import taylens
+
+    plan = taylens.Plan(w.lmax, w.ntheta, w.nphi, order, prec, pol=w.pol, batch=batch if batch > 1 else 0)
+    q = {k: plan.query(k) for k in taylens.QUERY_KEYS}
+    outs = [(plan._maps(), plan._maps() if w.pol else None, plan._maps() if w.pol else None) for _ in range(batch)]
+    alms = skies_dev[:batch]
+
+    def step():
+        if batch == 1:
+            a = alms[0]
+            plan.lens_map(a[0], a[1], a[2], a[3], out=outs[0])
+        else:
+            plan.lens_map_many(alms, outs)
+
+    for _ in range(args.warmup):
+        step()
+    # timed region: K whole steps
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / args.steps
+    # the same K steps again with a HIP event pair around every kernel launch
+    plan.profile(True)
+    for _ in range(args.steps):
+        step()
+    st = plan.stage_times()
+    plan.profile(False)
+    per_step = {k: v[0] / args.steps for k, v in st.items() if v[1]}
+    avg_launch = {k: v[0] / v[1] for k, v in st.items() if v[1]}
+    launches = {k: v[1] // args.steps for k, v in st.items() if v[1]}
+    ws = plan.workspace_bytes()
+    first = tuple(x.cpu().numpy() if x is not None else None for x in outs[0])
+    del outs
+    plan.close()
+    torch.cuda.empty_cache()
+    return {"sec": sec, "per_step": per_step, "avg_launch": avg_launch, "launches": launches, "q": q,
+            "workspace_bytes": ws, "maps0": first}
+
+
+def copy_calibration(args):
+    """A plain device copy of known size, for scaling the HBM byte counters."""
+    import torch
+
+    n = 1 << 28  # floats: 1 GiB
+    a = torch.ones(n, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(max(1, args.steps)):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "launches": max(1, args.steps)}))
 
 
 def main():
-    ap = argparse.ArgumentParser(description=__doc__)
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="TP4096")
-    ap.add_argument("--precision", default="fp32")
     ap.add_argument("--order", type=int, default=None)
+    ap.add_argument("--forms", default="fp32,fp16:5",
+                    help="comma list of precision[:realizations per step]; fp32 is the speed-up reference")
+    ap.add_argument("--headline", default=None, help="form reported as value (default: the last of --forms)")
     ap.add_argument("--cpu-rings", type=int, default=16, help="output rings in the CPU-oracle sample")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the oracle (no errors, no cpu_baseline)")
+    ap.add_argument("--copy-calibration", action="store_true", help="only run a 1 GiB device copy (counter scale)")
     args = ap.parse_args()
 
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
               "independent realizations would shard across GPUs without communication.", file=sys.stderr)
         sys.exit(2)
+    if args.copy_calibration:
+        copy_calibration(args)
+        return
 
     import numpy as np
     import torch
 
-    from paper_1307_0719_amd import skygen, taylens
+    from paper_1307_0719_amd import skygen
 
     w = skygen.WORKLOADS[args.workload]
     order = w.order if args.order is None else args.order
+    forms = [parse_form(f) for f in args.forms.split(",") if f]
+    headline = parse_form(args.headline) if args.headline else forms[-1]
+    if headline not in forms:
+        forms.append(headline)
+    nmax = max(b for _, b in forms)
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
-    sky = skygen.make_sky(w.lmax, w.seed, pol=w.pol)
+    skies = [skygen.make_sky(w.lmax, w.seed + i, pol=w.pol) for i in range(nmax)]
     to_dev = lambda a: None if a is None else torch.from_numpy(a).to(dev)
-    aT, aE, aP = to_dev(sky.alm_T), to_dev(sky.alm_E), to_dev(sky.alm_phi)
     # B = 0 in these workloads: pass NULL (the library then skips the B sums)
-    aB = to_dev(sky.alm_B) if (sky.alm_B is not None and np.any(sky.alm_B)) else None
-    plan = taylens.Plan(w.lmax, w.ntheta, w.nphi, order, args.precision, pol=w.pol)
-    outs = (plan._maps(), plan._maps() if w.pol else None, plan._maps() if w.pol else None)
+    hasb = any(s.alm_B is not None and np.any(s.alm_B) for s in skies)
+    skies_dev = [(to_dev(s.alm_T), to_dev(s.alm_E), to_dev(s.alm_B) if hasb else None, to_dev(s.alm_phi))
+                 for s in skies]
     npix = w.ntheta * w.nphi
 
-    for _ in range(args.warmup):
-        plan.lens_map(aT, aE, aB, aP, out=outs)
-    torch.cuda.synchronize()
-
-    # timed region: K whole steps
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        plan.lens_map(aT, aE, aB, aP, out=outs)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    sec = (t1 - t0) / args.steps
-
-    # the same K steps again with per-stage HIP events on the plan's stream
-    plan.profile(True)
-    for _ in range(args.steps):
-        plan.lens_map(aT, aE, aB, aP, out=outs)
-    st = plan.stage_times()
-    plan.profile(False)
-    stages_ms = {k: (v[0] / v[1] if v[1] else 0.0) for k, v in st.items()}
-
-    nrp = (w.ntheta + 1) // 2
-    fl_T, fl_S = legendre_flops(w.lmax, nrp, order, w.pol, aB is not None)
-    kern = {"legendre_QU": fl_S, "legendre_T": fl_T}
-    dom = max(("legendre_QU", "legendre_T", "ring_fft", "remap", "deflection"), key=lambda k: stages_ms[k])
-    if dom in kern:
-        flops = kern[dom]
-        achieved = flops / (stages_ms[dom] * 1e-3)
-        roof = {"kernel": "k_legendre_spin" if dom == "legendre_QU" else "k_legendre_scalar",
-                "bound": "alu", "achieved": achieved / 1e12, "peak": FP64_VECTOR_PEAK / 1e12,
-                "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK, "traffic": None,
-                "flops_per_launch": flops, "avg_launch_ms": stages_ms[dom]}
-    else:
-        roof = {"kernel": dom, "bound": "hbm", "achieved": None, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
-                "frac": None, "traffic": None}
-
-    res = {
-        "metric": "lensed pixels/sec (T+Q/U, lmax=4096) at stated rel. error; Legendre MFMA util %",
-        "value": npix / sec,
-        "unit": "pixels/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": sec * 1e3,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64/f32" if args.precision == "fp32" else "f64",
-        "data": "synthetic",
-        "config": {
-            "workload": w.name if order == w.order else f"{w.name} (order {order})",
-            "lmax": w.lmax, "ntheta": w.ntheta, "nphi": w.nphi, "order": order,
-            "precision_form": args.precision, "fields": "TQU" if w.pol else "T", "pixels": npix,
-            "legendre_mfma_util_pct": 0.0,
-            "stages_ms": stages_ms,
-        },
-        "roofline": roof,
-    }
-
+    # oracle on a band of equatorial output rings of realization 0
+    ref, rings, cpu = None, None, None
     if not args.no_cpu_baseline:
         from oracle import taylens_oracle as orc
 
@@ -142,25 +215,121 @@ def main():
         nr = max(1, args.cpu_rings)
         c = w.ntheta // 2
         rings = np.arange(c - nr // 2, c - nr // 2 + nr)
+        s0 = skies[0]
         o0 = time.perf_counter()
-        ref = orc.lens_rings(w.lmax, order, w.ntheta, w.nphi, rings, sky.alm_T, sky.alm_E, sky.alm_B,
-                             sky.alm_phi, nthreads=ncores)
+        ref = orc.lens_rings(w.lmax, order, w.ntheta, w.nphi, rings, s0.alm_T, s0.alm_E, s0.alm_B, s0.alm_phi,
+                             nthreads=ncores)
         o1 = time.perf_counter()
-        errs = {}
-        mask = ref["_tie"] > 1e-9
-        for f, g in zip(("T", "Q", "U"), outs):
-            if g is None:
-                continue
-            x = g.cpu().numpy()[rings][mask]
-            r = ref[f][mask]
-            errs[f] = float(np.sqrt(np.mean((x - r) ** 2)) / np.sqrt(np.mean(r ** 2)))
-        res["config"]["rel_rms_err_vs_oracle"] = errs
-        res["cpu_baseline"] = {
+        cpu = {
             "value": nr * w.nphi / (o1 - o0), "unit": "pixels/s", "cores": ncores, "kind": "oracle",
-            "sample": f"{nr} output rings ({rings[0]}..{rings[-1]}) of the same map: deflection on those "
-                      f"rings, derivative maps of every source ring they need, remap, Taylor sum, rotation; "
-                      f"{o1 - o0:.1f} s",
+            "sample": f"{nr} output rings ({rings[0]}..{rings[-1]}) of realization 0: deflection on those rings, "
+                      f"derivative maps of every source ring they need, remap, Taylor sum, rotation; "
+                      f"{o1 - o0:.1f} s, FP64",
         }
+
+    results = {}
+    for prec, batch in forms:
+        r = run_form(args, w, order, prec, batch, skies_dev)
+        if ref is not None:
+            mask = ref["_tie"] > 1e-9
+            errs = {}
+            for f, g in zip(("T", "Q", "U"), r["maps0"]):
+                if g is None:
+                    continue
+                x = g[rings][mask]
+                y = ref[f][mask]
+                errs[f] = float(np.sqrt(np.mean((x - y) ** 2)) / np.sqrt(np.mean(y ** 2)))
+            r["errs"] = errs
+        results[(prec, batch)] = r
+
+    def name(f):
+        return f[0] if f[1] == 1 else f"{f[0]}:{f[1]}"
+
+    fp32 = results.get(("fp32", 1))
+    forms_out = {}
+    for f, r in results.items():
+        px = f[1] * npix / r["sec"]
+        leg = sum(r["per_step"].get(k, 0.0) for k in ("legendre_T", "legendre_QU", "legendre_mfma", "tab_rhs",
+                                                       "legendre_tab"))
+        useful = f[1] * a3_useful_flops(w.lmax, (w.ntheta + 1) // 2, order, w.pol, hasb)
+        tabform = f[0] in ("bf16x3", "fp16x2", "fp16", "bf16")
+        pk = PEAK["f16_mfma"] if tabform else (PEAK["fp32_mfma"] if f[0] == "fp32" else PEAK["fp64"])
+        ent = {
+            "pixels_per_s": px, "ms_per_step": r["sec"] * 1e3, "realizations_per_step": f[1],
+            "ms_per_map": r["sec"] * 1e3 / f[1],
+            "speedup_vs_fp32": (px / (npix / fp32["sec"])) if fp32 else None,
+            "rel_rms_err_vs_oracle": r.get("errs"),
+            "stages_ms_per_step": {k: round(v, 3) for k, v in r["per_step"].items()},
+            "legendre_ms_per_step": leg,
+            "legendre_a3_useful_tflops": useful / (leg * 1e-3) / 1e12 if leg else None,
+            "legendre_mfma_util_pct": 100.0 * useful / (leg * 1e-3) / pk if leg else None,
+            "workspace_gib": r["workspace_bytes"] / 2**30,
+        }
+        forms_out[name(f)] = ent
+
+    H = results[headline]
+    work = stage_work(w, order, headline[0], H["q"], hasb, headline[1])
+    dom = max(H["per_step"], key=lambda k: H["per_step"][k])
+    kind, amount, unit, peak = work[dom]
+    from paper_1307_0719_amd import taylens
+
+    avg = H["avg_launch"][dom] * 1e-3
+    scale = 1e9 if unit == "GB/s" else 1e12
+    # per launch: the deflection, FFT and remap kernels run once per realization
+    roof = {
+        "kernel": taylens.STAGE_KERNELS[dom], "stage": dom,
+        "bound": "hbm" if kind == "hbm" else ("alu" if kind == "fp64" else "mfma"),
+        "achieved": amount / avg / scale,
+        "peak": peak / scale, "unit": unit, "frac": amount / avg / peak, "traffic": None,
+        "work_per_launch": amount, "avg_launch_ms": avg * 1e3, "launches_per_step": H["launches"][dom],
+        "peak_note": "FP64 vector peak (ALU-bound recursion)" if kind == "fp64" else None,
+    }
+    other = {}
+    for k in H["per_step"]:
+        if k in work:
+            kk, am, un, pk = work[k]
+            sc = 1e9 if un == "GB/s" else 1e12
+            a = H["avg_launch"][k] * 1e-3
+            other[k] = {"kernel": taylens.STAGE_KERNELS[k], "resource": kk, "achieved": am / a / sc, "unit": un,
+                        "frac": am / a / pk, "avg_launch_ms": a * 1e3, "ms_per_step": H["per_step"][k]}
+    if "legendre_tab" in H["per_step"]:
+        kk, am, un, pk = work["legendre_tab_mfma"]
+        a = H["avg_launch"]["legendre_tab"] * 1e-3
+        other["legendre_tab"]["mfma_f16_achieved_tflops"] = am / a / 1e12
+        other["legendre_tab"]["mfma_f16_frac"] = am / a / pk
+
+    hf = forms_out[name(headline)]
+    dt = {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16x3", "fp16x2": "f16x2", "fp16": "f16", "bf16": "bf16"}
+    res = {
+        "metric": "lensed pixels/sec (T+Q/U, lmax=4096) at stated rel. error; Legendre MFMA util %",
+        "value": hf["pixels_per_s"],
+        "unit": "pixels/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": hf["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": dt[headline[0]],
+        "data": "synthetic",
+        "config": {
+            "workload": f"T+Q/U lmax={w.lmax}, {w.ntheta}x{w.nphi} equal-theta rings, Taylor order {order}, "
+                        f"{headline[1]} realization(s) per step, {headline[0]} harmonic-stage contraction "
+                        f"(FP64 recursion, positions and rotation)",
+            "lmax": w.lmax, "ntheta": w.ntheta, "nphi": w.nphi, "order": order, "fields": "TQU" if w.pol else "T",
+            "precision_form": headline[0], "realizations_per_step": headline[1],
+            "rel_rms_err_vs_oracle": hf["rel_rms_err_vs_oracle"],
+            "speedup_vs_fp32": hf["speedup_vs_fp32"],
+            "legendre_mfma_util_pct": hf["legendre_mfma_util_pct"],
+            "pixels": npix,
+        },
+        "roofline": roof,
+        "kernels": other,
+        "forms": forms_out,
+    }
+    if cpu is not None:
+        res["cpu_baseline"] = cpu
     print(json.dumps(res))
 
 

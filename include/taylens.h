@@ -109,6 +109,23 @@ int tl_plan_destroy(tl_plan plan);
 /* Device bytes held by the plan. */
 int tl_plan_workspace_bytes(tl_plan plan, int64_t *bytes);
 
+/* Work counts of a plan, fixed at creation (for throughput accounting):
+ *   TL_Q_RPOLE       ring pairs near the poles kept on the direct FP64 kernels
+ *                    in the FP32 and tabulated forms
+ *   TL_Q_ELEMS       (l, m, ring pair) elements of the harmonic stage at or
+ *                    below the evanescent cut (all ring pairs)
+ *   TL_Q_ELEMS_CAPS  the same, restricted to the pole-adjacent ring pairs
+ *   TL_Q_TAB_CHUNKS  (m, 32-ring tile, 32-l chunk) table blocks the table
+ *                    GEMM streams per pass (tabulated forms; 0 otherwise)
+ *   TL_Q_TAB_CHUNK_BYTES  bytes of one such block (both tables, hi and lo)
+ * Returns TL_ERR_INVALID for an unknown key or a NULL value pointer. */
+#define TL_Q_RPOLE 0
+#define TL_Q_ELEMS 1
+#define TL_Q_ELEMS_CAPS 2
+#define TL_Q_TAB_CHUNKS 3
+#define TL_Q_TAB_CHUNK_BYTES 4
+int tl_plan_query(tl_plan plan, int32_t key, int64_t *value);
+
 /* Lens one realization (the full method, eqs. 1, 2, 5):
  *   alm_T (required), alm_E (required iff opt.pol), alm_B (NULL = 0),
  *   alm_phi (NULL = no deflection: the unlensed maps).
@@ -173,12 +190,14 @@ int tl_lens_map_simple(const void *alm_T, const void *alm_E, const void *alm_B,
 
 /* ---- instrumentation ---- */
 
-/* Stages timed by tl_plan_profile: 0 deflection (harmonic + ring FFT of phi),
- * 1 direct FP64 harmonic kernel of T, 2 direct FP64 harmonic kernel of Q/U
+/* Stages timed by tl_plan_profile, one kernel launch each:
+ * 0 harmonic kernel of the deflection (FP64, all rings), 1 its ring FFTs,
+ * 2 direct FP64 harmonic kernel of T, 3 direct FP64 harmonic kernel of Q/U
  * (all rings in the FP64 form, the pole-adjacent rings in the others),
- * 3 matrix-core harmonic kernel (T and Q/U, the remaining rings), 4 ring FFTs
- * of the derivative maps, 5 remap + Taylor sum + rotation. */
-#define TL_NSTAGE 6
+ * 4 matrix-core harmonic kernel of the FP32 form (T and Q/U, the remaining
+ * rings), 5 right-hand sides of the tabulated forms, 6 their table GEMM,
+ * 7 ring FFTs of the derivative maps, 8 remap + Taylor sum + rotation. */
+#define TL_NSTAGE 9
 
 /* enable != 0: from now on record a HIP event pair on the plan's stream
  * around every stage of every call (no synchronization is added); 0: stop.

@@ -307,8 +307,11 @@ int run_deflection(Plan &p, const void *alm_phi)
         TL_HIP(hipMemsetAsync(p.alpha.ptr, 0, p.alpha.bytes, p.stream), "alpha clear");
         return TL_OK;
     }
-    StageScope sc(p, 0);
-    TL_HIP(launch_legendre_scalar(p, 1, p.nrp, alm_phi, p.Fphi.ptr, true), "deflection legendre");
+    {
+        StageScope sc(p, ST_DEFL_LEG);
+        TL_HIP(launch_legendre_scalar(p, 1, p.nrp, alm_phi, p.Fphi.ptr, true), "deflection legendre");
+    }
+    StageScope sc(p, ST_DEFL_FFT);
     TL_HIP(launch_fft_jobs(p, p.Fphi.ptr, p.alpha.ptr, (const FftJob *)p.jobsDefl.ptr, p.njobsDefl, true),
            "deflection fft");
     return TL_OK;
@@ -329,16 +332,16 @@ int run_legendre_many(Plan &p, int n, const void *const *T, const void *const *E
     for (int i = 0; i < n; ++i) {
         char *F = (char *)Fout[i];
         {
-            StageScope sc(p, 1);
+            StageScope sc(p, ST_LEG_T);
             TL_HIP(launch_legendre_scalar(p, p.order, rend, T[i], F, p.fp64()), "legendre T");
         }
         if (p.pol) {
-            StageScope sc(p, 2);
+            StageScope sc(p, ST_LEG_QU);
             TL_HIP(launch_legendre_spin(p, p.order, rend, E[i], B[i], F + rowc * cb, F + 2 * rowc * cb, p.fp64()),
                    "legendre QU");
         }
         if (mfma) {
-            StageScope sc(p, 3);
+            StageScope sc(p, ST_LEG_MFMA);
             TL_HIP(launch_legendre_mfma(p, T[i], E[i], B[i], F, p.pol ? F + rowc * cb : nullptr,
                                         p.pol ? F + 2 * rowc * cb : nullptr),
                    "legendre mfma");
@@ -358,8 +361,12 @@ int run_legendre_many(Plan &p, int n, const void *const *T, const void *const *E
                 b.FQ[q] = (float2 *)(F + rowc * cb);
                 b.FU[q] = (float2 *)(F + 2 * rowc * cb);
             }
-            StageScope sc(p, 3);
-            TL_HIP(launch_legendre_tab(p, b), "legendre table gemm");
+            {
+                StageScope sc(p, ST_TAB_RHS);
+                TL_HIP(launch_legendre_tab(p, b, 0), "legendre table right-hand sides");
+            }
+            StageScope sc(p, ST_TAB_GEMM);
+            TL_HIP(launch_legendre_tab(p, b, 1), "legendre table gemm");
         }
     }
     return TL_OK;
@@ -376,7 +383,7 @@ int run_derivs(Plan &p, const void *T, const void *E, const void *B, void *Dout)
 {
     int rc = run_legendre(p, T, E, B, p.F.ptr);
     if (rc) return rc;
-    StageScope sc(p, 4);
+    StageScope sc(p, ST_FFT);
     TL_HIP(launch_fft_jobs(p, p.F.ptr, Dout, (const FftJob *)p.jobsMain.ptr, p.njobsMain, p.fp64()), "ring fft");
     return TL_OK;
 }
@@ -401,6 +408,46 @@ int set_device_of(Plan &p)
     TL_HIP(hipGetDevice(&cur), "hipGetDevice");
     if (cur != p.device) TL_HIP(hipSetDevice(p.device), "hipSetDevice");
     return TL_OK;
+}
+
+// Work counts for tl_plan_query, from the evanescent cut and the table's
+// first non-empty chunks (mirrors which blocks the kernels visit).
+hipError_t count_work(Plan &p)
+{
+    std::vector<int> mc(p.nrp);
+    hipError_t e = hipMemcpy(mc.data(), p.mcut.ptr, p.nrp * sizeof(int), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return e;
+    p.q_elems = p.q_elems_caps = 0;
+    for (int r = 0; r < p.nrp; ++r) {
+        const int64_t top = std::min(mc[r], p.lmax);
+        // sum_{m=0}^{top} (lmax - m + 1)
+        const int64_t n = top < 0 ? 0 : (top + 1) * (int64_t)(p.lmax + 1) - top * (top + 1) / 2;
+        p.q_elems += n;
+        if (r < p.rpole) p.q_elems_caps += n;
+    }
+    p.q_tab_chunks = p.q_tab_chunk_bytes = 0;
+    if (p.tabform() && p.ntile > 0) {
+        const int nspl = (p.precision == TL_BF16X3 || p.precision == TL_FP16X2) ? 2 : 1;
+        p.q_tab_chunk_bytes = (int64_t)nspl * 4 * 64 * 16;
+        std::vector<int> ks((size_t)(p.lmax + 1) * p.ntile);
+        e = hipMemcpy(ks.data(), p.kstart.ptr, ks.size() * sizeof(int), hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return e;
+        for (int m = 0; m <= p.lmax; ++m) {
+            const int nk = (p.lmax - m + 1 + 31) / 32;
+            for (int g = 0; g * 4 < p.ntile; ++g) {
+                bool any = false;  // some ring of the 4 tiles at or below its cut + 2
+                for (int t = g * 4; t < std::min(p.ntile, g * 4 + 4) && !any; ++t)
+                    for (int rl = 0; rl < 32 && !any; ++rl) {
+                        const int r = p.rpole + t * 32 + rl;
+                        if (r < p.nrp && m <= mc[r] + 2) any = true;
+                    }
+                if (!any) continue;
+                for (int t = g * 4; t < std::min(p.ntile, g * 4 + 4); ++t)
+                    p.q_tab_chunks += std::max(0, nk - ks[(size_t)m * p.ntile + t]);
+            }
+        }
+    }
+    return hipSuccess;
 }
 
 }  // namespace
@@ -514,6 +561,7 @@ int tl_plan_create(tl_plan *out, int32_t lmax, tl_grid grid, const tl_options *o
     }
     if (e == hipSuccess) e = fft_prepare(p);
     if (e == hipSuccess) e = hipStreamSynchronize(p.stream);
+    if (e == hipSuccess) e = count_work(p);
     if (e != hipSuccess) return bail(hipfail(e, "plan tables"));
     *out = h;
     return TL_OK;
@@ -562,6 +610,21 @@ int tl_plan_stage_times(tl_plan plan, double *ms, int64_t *calls)
         if (calls) calls[r.stage] += 1;
     }
     return TL_OK;
+}
+
+int tl_plan_query(tl_plan plan, int32_t key, int64_t *value)
+{
+    if (check_plan(plan)) return TL_ERR_INVALID;
+    if (!value) return fail(TL_ERR_INVALID, "value pointer is NULL");
+    const Plan &p = plan->p;
+    switch (key) {
+    case TL_Q_RPOLE: *value = p.rpole; return TL_OK;
+    case TL_Q_ELEMS: *value = p.q_elems; return TL_OK;
+    case TL_Q_ELEMS_CAPS: *value = p.q_elems_caps; return TL_OK;
+    case TL_Q_TAB_CHUNKS: *value = p.q_tab_chunks; return TL_OK;
+    case TL_Q_TAB_CHUNK_BYTES: *value = p.q_tab_chunk_bytes; return TL_OK;
+    default: return fail(TL_ERR_INVALID, "unknown query key " + std::to_string(key));
+    }
 }
 
 int tl_plan_workspace_bytes(tl_plan plan, int64_t *bytes)
@@ -633,7 +696,7 @@ int tl_lens_map(tl_plan plan, const void *alm_T, const void *alm_E, const void *
     if ((rc = run_deflection(p, alm_phi))) return rc;
     if ((rc = run_derivs(p, alm_T, alm_E, alm_B, p.D.ptr))) return rc;
     const double *at = (const double *)p.alpha.ptr;
-    StageScope sc(p, 5);
+    StageScope sc(p, ST_REMAP);
     TL_HIP(launch_remap(p, p.D.ptr, at, at + p.npix(), nullptr, nullptr, T_out, Q_out, U_out), "remap");
     return TL_OK;
 }
@@ -708,12 +771,12 @@ int tl_lens_map_many(tl_plan plan, int32_t n, const void *const *alms, void *con
         for (int q = 0; q < k; ++q) {
             if ((rc = run_deflection(p, alms[4 * (i0 + q) + 3]))) return rc;
             {
-                StageScope sc(p, 4);
+                StageScope sc(p, ST_FFT);
                 TL_HIP(launch_fft_jobs(p, F[q], p.D.ptr, (const FftJob *)p.jobsMain.ptr, p.njobsMain, p.fp64()),
                        "ring fft");
             }
             const double *at = (const double *)p.alpha.ptr;
-            StageScope sc(p, 5);
+            StageScope sc(p, ST_REMAP);
             TL_HIP(launch_remap(p, p.D.ptr, at, at + p.npix(), nullptr, nullptr, outs[3 * (i0 + q)],
                                 outs[3 * (i0 + q) + 1], outs[3 * (i0 + q) + 2]),
                    "remap");

@@ -681,17 +681,19 @@ hipError_t build_BS(Plan &p)
 }
 
 template <bool BF, bool SPLIT, int N, bool POL, bool HASB, int NBAT>
-hipError_t gemm_launch(Plan &p, const TabBatch &b)
+hipError_t gemm_launch(Plan &p, const TabBatch &b, int part)
 {
     constexpr int NB = (NBAT * cols_of(N, POL, HASB).n1 + 31) / 32;
     if constexpr (NB > 4) {
         return hipErrorInvalidValue;
     } else {
         if ((size_t)NB > p.rhs_nb) return hipErrorInvalidValue;  // buffers sized at plan time
-        hipLaunchKernelGGL((k_tab_rhs<BF, SPLIT, N, POL, HASB, NBAT>), dim3(p.lmax + 1), dim3(256), 0, p.stream,
-                           p.lmax, p.ntile, (const int64_t *)p.moff.ptr, b, (uint4 *)p.rhs.ptr, (float *)p.colexp.ptr);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
+        if (part == 0) {
+            hipLaunchKernelGGL((k_tab_rhs<BF, SPLIT, N, POL, HASB, NBAT>), dim3(p.lmax + 1), dim3(256), 0, p.stream,
+                               p.lmax, p.ntile, (const int64_t *)p.moff.ptr, b, (uint4 *)p.rhs.ptr,
+                               (float *)p.colexp.ptr);
+            return hipGetLastError();
+        }
         const int ngrp = (p.ntile + 3) / 4;
         const int m8 = (p.lmax + 1 + 7) / 8;
         hipLaunchKernelGGL((k_legendre_tab<BF, SPLIT, N, POL, HASB, NBAT>), dim3(8 * m8 * ngrp), dim3(256), 0,
@@ -703,27 +705,27 @@ hipError_t gemm_launch(Plan &p, const TabBatch &b)
 }
 
 template <bool BF, bool SPLIT, int N, bool POL, bool HASB>
-hipError_t gemm_nbat(Plan &p, const TabBatch &b)
+hipError_t gemm_nbat(Plan &p, const TabBatch &b, int part)
 {
     switch (b.n) {
-    case 1: return gemm_launch<BF, SPLIT, N, POL, HASB, 1>(p, b);
-    case 2: return gemm_launch<BF, SPLIT, N, POL, HASB, 2>(p, b);
-    case 3: return gemm_launch<BF, SPLIT, N, POL, HASB, 3>(p, b);
-    case 4: return gemm_launch<BF, SPLIT, N, POL, HASB, 4>(p, b);
-    case 5: return gemm_launch<BF, SPLIT, N, POL, HASB, 5>(p, b);
+    case 1: return gemm_launch<BF, SPLIT, N, POL, HASB, 1>(p, b, part);
+    case 2: return gemm_launch<BF, SPLIT, N, POL, HASB, 2>(p, b, part);
+    case 3: return gemm_launch<BF, SPLIT, N, POL, HASB, 3>(p, b, part);
+    case 4: return gemm_launch<BF, SPLIT, N, POL, HASB, 4>(p, b, part);
+    case 5: return gemm_launch<BF, SPLIT, N, POL, HASB, 5>(p, b, part);
     default: return hipErrorInvalidValue;
     }
 }
 
 template <bool BF, bool SPLIT>
-hipError_t gemm_form(Plan &p, const TabBatch &b)
+hipError_t gemm_form(Plan &p, const TabBatch &b, int part)
 {
     const bool hasb = p.pol && b.B[0] != nullptr;
 #define TL_CASE(NN)                                                              \
     case NN:                                                                     \
-        if (!p.pol) return gemm_nbat<BF, SPLIT, NN, false, false>(p, b);         \
-        if (hasb) return gemm_nbat<BF, SPLIT, NN, true, true>(p, b);             \
-        return gemm_nbat<BF, SPLIT, NN, true, false>(p, b);
+        if (!p.pol) return gemm_nbat<BF, SPLIT, NN, false, false>(p, b, part);   \
+        if (hasb) return gemm_nbat<BF, SPLIT, NN, true, true>(p, b, part);       \
+        return gemm_nbat<BF, SPLIT, NN, true, false>(p, b, part);
     switch (p.order) {
         TL_CASE(0)
         TL_CASE(1)
@@ -791,13 +793,13 @@ hipError_t launch_build_tab(Plan &p)
     }
 }
 
-hipError_t launch_legendre_tab(Plan &p, const TabBatch &b)
+hipError_t launch_legendre_tab(Plan &p, const TabBatch &b, int part)
 {
     switch (p.precision) {
-    case TL_BF16: return gemm_form<true, false>(p, b);
-    case TL_FP16: return gemm_form<false, false>(p, b);
-    case TL_BF16X3: return gemm_form<true, true>(p, b);
-    case TL_FP16X2: return gemm_form<false, true>(p, b);
+    case TL_BF16: return gemm_form<true, false>(p, b, part);
+    case TL_FP16: return gemm_form<false, false>(p, b, part);
+    case TL_BF16X3: return gemm_form<true, true>(p, b, part);
+    case TL_FP16X2: return gemm_form<false, true>(p, b, part);
     default: return hipErrorInvalidValue;
     }
 }

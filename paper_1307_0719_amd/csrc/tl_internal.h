@@ -97,6 +97,8 @@ struct Plan {
     int njobsDefl = 0, njobsMain = 0;
 
     size_t total_bytes = 0;
+    // work counts (tl_plan_query)
+    int64_t q_elems = 0, q_elems_caps = 0, q_tab_chunks = 0, q_tab_chunk_bytes = 0;
 
     // instrumentation: event pairs per timed stage launch
     struct ProfRec {
@@ -125,7 +127,10 @@ size_t tab_bytes(int lmax, int ntile, bool split, std::vector<int64_t> &moff);
 int tab_rhs_blocks(int order, bool pol, int batch);
 size_t tab_rhs_bytes(int lmax, bool split, int nblocks);
 hipError_t launch_build_tab(Plan &p);
-hipError_t launch_legendre_tab(Plan &p, const TabBatch &b);
+// part 0: right-hand sides of the batch (k_tab_rhs); part 1: the GEMM
+hipError_t launch_legendre_tab(Plan &p, const TabBatch &b, int part);
+// Stage numbers of the per-kernel profile (one kernel per stage).
+enum Stage { ST_DEFL_LEG = 0, ST_DEFL_FFT, ST_LEG_T, ST_LEG_QU, ST_LEG_MFMA, ST_TAB_RHS, ST_TAB_GEMM, ST_FFT, ST_REMAP };
 hipError_t launch_legendre_mfma(Plan &p, const void *T, const void *E, const void *B, void *FT, void *FQ,
                                 void *FU);
 hipError_t launch_fft_jobs(Plan &p, const void *Fbase, void *Dbase, const FftJob *jobs, int njobs,

@@ -29,11 +29,17 @@ PRECISIONS = {"fp64": 0, "fp32": 1, "bf16x3": 2, "fp16x2": 3, "fp16": 4, "bf16":
 
 # every symbol include/taylens.h declares
 EXPORTS = [
-    "tl_plan_create", "tl_plan_destroy", "tl_plan_workspace_bytes", "tl_lens_map", "tl_lens_map_pos",
+    "tl_plan_create", "tl_plan_destroy", "tl_plan_workspace_bytes", "tl_plan_query", "tl_lens_map", "tl_lens_map_pos",
     "tl_deflection", "tl_legendre", "tl_synth_derivs", "tl_remap", "tl_lens_map_batch",
     "tl_lens_map_simple", "tl_lens_map_many", "tl_plan_profile", "tl_plan_stage_times", "tl_last_error", "tl_version",
 ]
-STAGES = ["deflection", "legendre_T", "legendre_QU", "legendre_mfma", "ring_fft", "remap"]
+STAGES = ["defl_legendre", "defl_fft", "legendre_T", "legendre_QU", "legendre_mfma", "tab_rhs", "legendre_tab",
+          "ring_fft", "remap"]
+QUERY_KEYS = {"rpole": 0, "elems": 1, "elems_caps": 2, "tab_chunks": 3, "tab_chunk_bytes": 4}
+# kernel each stage launches
+STAGE_KERNELS = {"defl_legendre": "k_legendre_scalar", "defl_fft": "k_ring_fft", "legendre_T": "k_legendre_scalar",
+                 "legendre_QU": "k_legendre_spin", "legendre_mfma": "k_legendre_mfma", "tab_rhs": "k_tab_rhs",
+                 "legendre_tab": "k_legendre_tab", "ring_fft": "k_ring_fft", "remap": "k_remap"}
 
 
 class TaylensError(RuntimeError):
@@ -66,6 +72,7 @@ def lib():
         L.tl_plan_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int32, Grid, ctypes.POINTER(Options), vp]
         L.tl_plan_destroy.argtypes = [vp]
         L.tl_plan_workspace_bytes.argtypes = [vp, ctypes.POINTER(ctypes.c_int64)]
+        L.tl_plan_query.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64)]
         L.tl_lens_map.argtypes = [vp] * 8
         L.tl_lens_map_pos.argtypes = [vp] * 9
         L.tl_deflection.argtypes = [vp] * 4
@@ -153,6 +160,13 @@ class Plan:
         b = ctypes.c_int64()
         _check(lib().tl_plan_workspace_bytes(self._h, ctypes.byref(b)))
         return int(b.value)
+
+    def query(self, key: str) -> int:
+        """Work counts fixed at plan creation: rpole, elems, elems_caps,
+        tab_chunks, tab_chunk_bytes."""
+        b = ctypes.c_int64()
+        _check(lib().tl_plan_query(self._h, QUERY_KEYS[key], ctypes.byref(b)))
+        return b.value
 
     def profile(self, enable: bool = True):
         """Start (or stop) per-stage HIP-event timing on the plan's stream."""

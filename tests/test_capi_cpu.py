@@ -67,3 +67,5 @@ def test_null_arguments(tl):
     assert L.tl_lens_map_batch(2, None, None, None) == -1
     assert L.tl_plan_profile(None, 1) == -1
     assert L.tl_plan_stage_times(None, None, None) == -1
+    v = ctypes.c_int64()
+    assert L.tl_plan_query(None, 0, ctypes.byref(v)) == -1
