@@ -169,3 +169,28 @@ def batch_lmaxes(n: int = 64, seed: int = 3, choices=(512, 1024, 2048, 3000)):
     """lmax per realization for the uneven-lmax batch (uniform draw)."""
     rng = np.random.Generator(np.random.PCG64(seed))
     return [int(choices[i]) for i in rng.integers(0, len(choices), size=n)]
+
+
+# ---- learned correction: seeded draws shared by training and its checks ----
+
+CNN_SIZES = [(32, 20 * 9), (32,), (32, 32 * 9), (32,), (3, 32), (3,)]  # (rows, fan_in) of W1 b1 W2 b2 W3 b3
+
+
+def cnn_init(seed: int) -> np.ndarray:
+    """Initial parameter vector of the correction network, float32:
+    W1[32][20][3][3], b1[32], W2[32][32][3][3], b2[32], W3[3][32], b3[3]
+    uniform in +-1/sqrt(fan_in) of their layer, then three output scales 1."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    fans = [180, 180, 288, 288, 32, 32]
+    parts = []
+    for shp, fan in zip(CNN_SIZES, fans):
+        n = int(np.prod(shp))
+        parts.append(rng.uniform(-1.0, 1.0, n) / math.sqrt(fan))
+    parts.append(np.ones(3))
+    return np.concatenate(parts).astype(np.float32)
+
+
+def sample_pixels(npix: int, n: int, seed: int) -> np.ndarray:
+    """n distinct output-pixel indices in [0, npix), sorted, int64."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return np.sort(rng.choice(npix, size=min(n, npix), replace=False)).astype(np.int64)
