@@ -188,6 +188,69 @@ int tl_lens_map_simple(const void *alm_T, const void *alm_E, const void *alm_B,
                        const void *alm_phi, int32_t lmax, int32_t order, tl_grid grid,
                        void *T_out, void *Q_out, void *U_out);
 
+/* ---- learned remainder correction ----
+ *
+ * The Taylor series of eq. 5 is cut at order N; a small network predicts,
+ * per output pixel, what the terms beyond order 2 add (the order-6 minus
+ * order-2 sum), from the 5 x 5 patch of order <= 2 derivative maps around the
+ * nearest source pixel (Sec. II.B gives the nearest-pixel expansion it
+ * corrects).  The correction is added to the order-2 sum before the
+ * polarization rotation R.  Network: input channels = the 18 pre-scaled maps
+ * Dt_jk (j + k <= 2) of T, Q, U, each field divided by its RMS sigma_f over
+ * the patch, plus the scaled residuals u, v; conv 3x3 valid 20 -> 32 + tanh,
+ * conv 3x3 valid 32 -> 32 + tanh, 1x1 32 -> 3 = y; correction_f =
+ * sigma_f * scale_f * y_f.  Forward on BF16 matrix cores with FP32
+ * accumulation; FP32 master weights; training by Adam on the mean squared
+ * error of y against target_f / (sigma_f scale_f).
+ *
+ * Parameter vector (host, float, TL_CNN_NPARAM): W1[32][20][3][3], b1[32],
+ * W2[32][32][3][3], b2[32], W3[3][32], b3[3] (the TL_CNN_NTRAIN trained
+ * values), then scale[3] (fixed).
+ *
+ * Every call that takes a plan needs an order-2, polarized plan whose form
+ * is not TL_FP64 (its derivative maps are float); it runs on the plan's
+ * stream.  D = that plan's derivative maps (tl_synth_derivs layout, float
+ * [3][6][ntheta][nphi]), alpha_theta / alpha_phi its deflection
+ * (tl_deflection, double [ntheta][nphi]); pix = n flat output-pixel indices
+ * (ring-major, device int64) or NULL for pixels 0..n-1.  Device buffers are
+ * the caller's.  A network object is not thread-safe. */
+#define TL_CNN_NTRAIN 15139
+#define TL_CNN_NPARAM 15142
+typedef struct tl_cnn_s *tl_cnn;
+
+/* Create from a host parameter vector; Adam state zero.  The weights are
+ * uploaded on the null stream (synchronized before return). */
+int tl_cnn_create(tl_cnn *out, const float *params);
+int tl_cnn_destroy(tl_cnn net);
+/* Copy the current parameters to host memory (synchronizes the device). */
+int tl_cnn_get_params(tl_cnn net, float *params_out);
+/* Replace the parameters (host vector) and reset the Adam state. */
+int tl_cnn_set_params(tl_cnn net, const float *params);
+
+/* corr_out (device float [3][n]): the correction of each selected pixel. */
+int tl_cnn_forward(tl_cnn net, tl_plan plan, const float *D, const double *alpha_theta,
+                   const double *alpha_phi, const int64_t *pix, int64_t n, float *corr_out);
+
+/* Gradient of the training loss for target (device float [3][n], the
+ * remainder to predict for each pixel, same layout as corr_out):
+ * grad_out (device float [TL_CNN_NTRAIN + 1]) = d loss / d params in
+ * parameter order, then the loss itself.  Parameters are not changed. */
+int tl_cnn_grad(tl_cnn net, tl_plan plan, const float *D, const double *alpha_theta,
+                const double *alpha_phi, const int64_t *pix, int64_t n, const float *target,
+                float *grad_out);
+
+/* One Adam step (beta 0.9, 0.999, eps 1e-8, bias-corrected) at learning rate
+ * lr on the gradient for target; loss_out (device float, may be NULL) gets
+ * the loss before the step. */
+int tl_cnn_train_step(tl_cnn net, tl_plan plan, const float *D, const double *alpha_theta,
+                      const double *alpha_phi, const int64_t *pix, int64_t n, const float *target,
+                      float lr, float *loss_out);
+
+/* tl_lens_map of an order-2 plan with the network's correction added before
+ * the rotation. */
+int tl_lens_map_cnn(tl_plan plan, tl_cnn net, const void *alm_T, const void *alm_E,
+                    const void *alm_B, const void *alm_phi, void *T_out, void *Q_out, void *U_out);
+
 /* ---- instrumentation ---- */
 
 /* Stages timed by tl_plan_profile, one kernel launch each:
@@ -196,8 +259,9 @@ int tl_lens_map_simple(const void *alm_T, const void *alm_E, const void *alm_B,
  * (all rings in the FP64 form, the pole-adjacent rings in the others),
  * 4 matrix-core harmonic kernel of the FP32 form (T and Q/U, the remaining
  * rings), 5 right-hand sides of the tabulated forms, 6 their table GEMM,
- * 7 ring FFTs of the derivative maps, 8 remap + Taylor sum + rotation. */
-#define TL_NSTAGE 9
+ * 7 ring FFTs of the derivative maps, 8 remap + Taylor sum + rotation,
+ * 9 the learned correction network (tl_lens_map_cnn). */
+#define TL_NSTAGE 10
 
 /* enable != 0: from now on record a HIP event pair on the plan's stream
  * around every stage of every call (no synchronization is added); 0: stop.

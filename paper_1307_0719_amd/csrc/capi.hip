@@ -456,6 +456,69 @@ struct tl_plan_s {
     Plan p;
 };
 
+struct tl_cnn_s {
+    CnnBufs c;
+    int device = 0;
+    int step = 0;
+    DevBuf params, m, v, grad, packed;
+    DevBuf work;   // training activations
+    DevBuf corr;   // float [3][n] scratch of the training calls / full-map correction
+};
+
+namespace {
+
+void free_cnn(tl_cnn_s *h)
+{
+    DevBuf *b[] = {&h->params, &h->m, &h->v, &h->grad, &h->packed, &h->work, &h->corr};
+    for (DevBuf *x : b) free_buf(*x);
+}
+
+// Grow a scratch buffer of the network (synchronizes before a reallocation).
+int cnn_reserve(tl_cnn_s *h, DevBuf &b, size_t bytes, hipStream_t st)
+{
+    if (b.bytes >= bytes) return TL_OK;
+    TL_HIP(hipStreamSynchronize(st), "synchronize");
+    free_buf(b);
+    TL_HIP(hipMalloc(&b.ptr, bytes), "cnn scratch");
+    b.bytes = bytes;
+    if (&b == &h->work) h->c.work = b.ptr;
+    return TL_OK;
+}
+
+int cnn_check_plan(tl_plan plan, tl_cnn net)
+{
+    if (!plan) return fail(TL_ERR_INVALID, "plan is NULL");
+    if (!net) return fail(TL_ERR_INVALID, "network is NULL");
+    const Plan &p = plan->p;
+    if (p.order != 2 || !p.pol || p.fp64())
+        return fail(TL_ERR_UNSUPPORTED, "the correction network needs an order-2 polarized plan with float maps");
+    return TL_OK;
+}
+
+int cnn_check_pixels(const Plan &p, const float *D, const double *at, const double *ap, const int64_t *pix,
+                     int64_t n)
+{
+    if (!D || !at || !ap) return fail(TL_ERR_INVALID, "NULL derivative maps or deflection");
+    if (n < 0) return fail(TL_ERR_INVALID, "pixel count must be >= 0");
+    if (!pix && (size_t)n > p.npix()) return fail(TL_ERR_INVALID, "n exceeds the map size with pix NULL");
+    return TL_OK;
+}
+
+// forward (training mode) + backward into net->c.grad
+int cnn_grad_run(tl_cnn net, Plan &p, const float *D, const double *at, const double *ap, const int64_t *pix,
+                 int64_t n, const float *target)
+{
+    int rc;
+    if ((rc = cnn_reserve(net, net->work, std::max<size_t>(1, (size_t)n) * cnn_train_bytes_per_pixel(), p.stream)))
+        return rc;
+    if ((rc = cnn_reserve(net, net->corr, std::max<size_t>(1, (size_t)n) * 3 * sizeof(float), p.stream))) return rc;
+    TL_HIP(cnn_forward(p, net->c, D, at, ap, pix, n, (float *)net->corr.ptr, true, p.stream), "cnn forward");
+    TL_HIP(cnn_backward(net->c, n, target, p.stream), "cnn backward");
+    return TL_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 int tl_version(void) { return TL_VERSION; }
@@ -782,6 +845,159 @@ int tl_lens_map_many(tl_plan plan, int32_t n, const void *const *alms, void *con
                    "remap");
         }
     }
+    return TL_OK;
+}
+
+int tl_cnn_create(tl_cnn *out, const float *params)
+{
+    if (!out) return fail(TL_ERR_INVALID, "network output pointer is NULL");
+    *out = nullptr;
+    if (!params) return fail(TL_ERR_INVALID, "params is NULL");
+    tl_cnn_s *h = new (std::nothrow) tl_cnn_s;
+    if (!h) return fail(TL_ERR_NOMEM, "host allocation failed");
+    auto bail = [&](int code) {
+        free_cnn(h);
+        delete h;
+        return code;
+    };
+    hipError_t e = hipGetDevice(&h->device);
+    struct {
+        DevBuf *b;
+        size_t bytes;
+    } list[] = {{&h->params, kCnnParam * sizeof(float)},
+                {&h->m, kCnnTrain * sizeof(float)},
+                {&h->v, kCnnTrain * sizeof(float)},
+                {&h->grad, (kCnnTrain + 1) * sizeof(float)},
+                {&h->packed, cnn_packed_bytes()}};
+    for (auto &x : list) {
+        if (e != hipSuccess) break;
+        e = hipMalloc(&x.b->ptr, x.bytes);
+        if (e == hipSuccess) x.b->bytes = x.bytes;
+    }
+    if (e != hipSuccess) return bail(hipfail(e, "cnn allocation"));
+    h->c.params = h->params.ptr;
+    h->c.m = h->m.ptr;
+    h->c.v = h->v.ptr;
+    h->c.grad = h->grad.ptr;
+    // packed operands: layer 1 (14 steps), layer 2 (18), layer 3 (2), 64 x 16 B each
+    h->c.W1p = h->packed.ptr;
+    h->c.W2p = (char *)h->packed.ptr + 14 * 64 * 16;
+    h->c.W3p = (char *)h->packed.ptr + (14 + 18) * 64 * 16;
+    *out = h;
+    const int rc = tl_cnn_set_params(h, params);
+    if (rc) {
+        *out = nullptr;
+        return bail(rc);
+    }
+    return TL_OK;
+}
+
+int tl_cnn_destroy(tl_cnn net)
+{
+    if (!net) return TL_OK;
+    (void)hipDeviceSynchronize();
+    free_cnn(net);
+    delete net;
+    return TL_OK;
+}
+
+int tl_cnn_get_params(tl_cnn net, float *params_out)
+{
+    if (!net || !params_out) return fail(TL_ERR_INVALID, "NULL argument");
+    TL_HIP(hipDeviceSynchronize(), "synchronize");
+    TL_HIP(hipMemcpy(params_out, net->params.ptr, kCnnParam * sizeof(float), hipMemcpyDeviceToHost), "copy");
+    return TL_OK;
+}
+
+int tl_cnn_set_params(tl_cnn net, const float *params)
+{
+    if (!net || !params) return fail(TL_ERR_INVALID, "NULL argument");
+    for (int i = 0; i < kCnnParam; ++i)
+        if (!std::isfinite(params[i])) return fail(TL_ERR_INVALID, "non-finite parameter");
+    TL_HIP(hipDeviceSynchronize(), "synchronize");
+    TL_HIP(hipMemcpy(net->params.ptr, params, kCnnParam * sizeof(float), hipMemcpyHostToDevice), "copy");
+    TL_HIP(hipMemset(net->m.ptr, 0, net->m.bytes), "clear");
+    TL_HIP(hipMemset(net->v.ptr, 0, net->v.bytes), "clear");
+    net->step = 0;
+    TL_HIP(cnn_pack(net->c, nullptr), "cnn pack");
+    TL_HIP(hipDeviceSynchronize(), "synchronize");
+    return TL_OK;
+}
+
+int tl_cnn_forward(tl_cnn net, tl_plan plan, const float *D, const double *alpha_theta, const double *alpha_phi,
+                   const int64_t *pix, int64_t n, float *corr_out)
+{
+    int rc = cnn_check_plan(plan, net);
+    if (rc) return rc;
+    Plan &p = plan->p;
+    if ((rc = cnn_check_pixels(p, D, alpha_theta, alpha_phi, pix, n))) return rc;
+    if (!corr_out) return fail(TL_ERR_INVALID, "corr_out is NULL");
+    if ((rc = set_device_of(p))) return rc;
+    TL_HIP(cnn_forward(p, net->c, D, alpha_theta, alpha_phi, pix, n, corr_out, false, p.stream), "cnn forward");
+    return TL_OK;
+}
+
+int tl_cnn_grad(tl_cnn net, tl_plan plan, const float *D, const double *alpha_theta, const double *alpha_phi,
+                const int64_t *pix, int64_t n, const float *target, float *grad_out)
+{
+    int rc = cnn_check_plan(plan, net);
+    if (rc) return rc;
+    Plan &p = plan->p;
+    if ((rc = cnn_check_pixels(p, D, alpha_theta, alpha_phi, pix, n))) return rc;
+    if (!target || !grad_out) return fail(TL_ERR_INVALID, "target or grad_out is NULL");
+    if (n == 0) return fail(TL_ERR_INVALID, "the loss of zero pixels is undefined");
+    if ((rc = set_device_of(p))) return rc;
+    if ((rc = cnn_grad_run(net, p, D, alpha_theta, alpha_phi, pix, n, target))) return rc;
+    TL_HIP(hipMemcpyAsync(grad_out, net->grad.ptr, (kCnnTrain + 1) * sizeof(float), hipMemcpyDeviceToDevice,
+                          p.stream),
+           "copy");
+    return TL_OK;
+}
+
+int tl_cnn_train_step(tl_cnn net, tl_plan plan, const float *D, const double *alpha_theta, const double *alpha_phi,
+                      const int64_t *pix, int64_t n, const float *target, float lr, float *loss_out)
+{
+    int rc = cnn_check_plan(plan, net);
+    if (rc) return rc;
+    Plan &p = plan->p;
+    if ((rc = cnn_check_pixels(p, D, alpha_theta, alpha_phi, pix, n))) return rc;
+    if (!target) return fail(TL_ERR_INVALID, "target is NULL");
+    if (n == 0) return fail(TL_ERR_INVALID, "the loss of zero pixels is undefined");
+    if (!(lr > 0.f) || !std::isfinite(lr)) return fail(TL_ERR_INVALID, "lr must be positive");
+    if ((rc = set_device_of(p))) return rc;
+    if ((rc = cnn_grad_run(net, p, D, alpha_theta, alpha_phi, pix, n, target))) return rc;
+    if (loss_out)
+        TL_HIP(hipMemcpyAsync(loss_out, (float *)net->grad.ptr + kCnnTrain, sizeof(float), hipMemcpyDeviceToDevice,
+                              p.stream),
+               "copy");
+    net->step += 1;
+    TL_HIP(cnn_adam(net->c, net->step, lr, p.stream), "cnn adam");
+    return TL_OK;
+}
+
+int tl_lens_map_cnn(tl_plan plan, tl_cnn net, const void *alm_T, const void *alm_E, const void *alm_B,
+                    const void *alm_phi, void *T_out, void *Q_out, void *U_out)
+{
+    int rc = cnn_check_plan(plan, net);
+    if (rc) return rc;
+    Plan &p = plan->p;
+    if ((rc = check_fields(p, alm_T, alm_E))) return rc;
+    if ((rc = check_outputs(p, T_out, Q_out, U_out))) return rc;
+    if ((rc = set_device_of(p))) return rc;
+    if ((rc = cnn_reserve(net, net->corr, 3 * p.npix() * sizeof(float), p.stream))) return rc;
+    if ((rc = run_deflection(p, alm_phi))) return rc;
+    if ((rc = run_derivs(p, alm_T, alm_E, alm_B, p.D.ptr))) return rc;
+    const double *at = (const double *)p.alpha.ptr;
+    {
+        StageScope sc(p, ST_CNN);
+        TL_HIP(cnn_forward(p, net->c, (const float *)p.D.ptr, at, at + p.npix(), nullptr, (int64_t)p.npix(),
+                           (float *)net->corr.ptr, false, p.stream),
+               "cnn forward");
+    }
+    StageScope sc(p, ST_REMAP);
+    TL_HIP(launch_remap(p, p.D.ptr, at, at + p.npix(), nullptr, nullptr, T_out, Q_out, U_out,
+                        (const float *)net->corr.ptr),
+           "remap");
     return TL_OK;
 }
 

@@ -14,6 +14,7 @@
 // Positions, residuals and the rotation angle are FP64; the sum uses R (FP32 or
 // FP64).  Neighbouring lanes gather neighbouring source pixels, so the gathers
 // from each derivative map are mostly coalesced.
+#include "geom.h"
 #include "tl_internal.h"
 
 namespace tl {
@@ -26,8 +27,8 @@ __global__ __launch_bounds__(256) void k_remap(int ntheta, int nphi, const doubl
                                                const double *__restrict__ phival, const R *__restrict__ D,
                                                const double *__restrict__ at, const double *__restrict__ ap,
                                                const double *__restrict__ thsrc, const double *__restrict__ phsrc,
-                                               int rotate, int naive, R *__restrict__ To, R *__restrict__ Qo,
-                                               R *__restrict__ Uo)
+                                               int rotate, int naive, const float *__restrict__ corr,
+                                               R *__restrict__ To, R *__restrict__ Qo, R *__restrict__ Uo)
 {
     constexpr int ND = (N + 1) * (N + 2) / 2;
     const int i = blockIdx.y;
@@ -38,76 +39,12 @@ __global__ __launch_bounds__(256) void k_remap(int ntheta, int nphi, const doubl
     const double dth_grid = M_PI / (double)(ntheta - 1);
     const double dph_grid = TWO_PI / (double)nphi;
 
-    double thp, php;
-    double cg = 1.0, sg = 0.0;  // cos 2 gamma, sin 2 gamma
-    if (thsrc) {
-        thp = thsrc[idx];
-        php = phsrc[idx];
-        php = php - floor(php / TWO_PI) * TWO_PI;
-    } else {
-        const double a_t = at[idx], a_p = ap[idx];
-        const double d = sqrt(a_t * a_t + a_p * a_p);
-        const bool pole = (i == 0) || (i == ntheta - 1);
-        if (d == 0.0) {
-            thp = theta[i];
-            php = phival[k];
-        } else if (naive && !pole) {
-            const double st = trig[i].y;
-            thp = theta[i] + a_t;
-            php = phival[k] + a_p / st;
-            if (thp < 0.0) {
-                thp = -thp;
-                php += M_PI;
-            }
-            if (thp > M_PI) {
-                thp = TWO_PI - thp;
-                php += M_PI;
-            }
-            php = php - floor(php / TWO_PI) * TWO_PI;
-        } else {
-            const double ct = trig[i].x, st = trig[i].y;
-            const double cp = phitrig[k].x, sp = phitrig[k].y;
-            const double x0 = st * cp, x1 = st * sp, x2 = ct;
-            const double et0 = ct * cp, et1 = ct * sp, et2 = -st;
-            const double ep0 = -sp, ep1 = cp;
-            const double u0 = (a_t * et0 + a_p * ep0) / d;
-            const double u1 = (a_t * et1 + a_p * ep1) / d;
-            const double u2 = (a_t * et2) / d;
-            double sd, cd;
-            sincos(d, &sd, &cd);
-            const double y0 = cd * x0 + sd * u0, y1 = cd * x1 + sd * u1, y2 = cd * x2 + sd * u2;
-            const double rho = sqrt(y0 * y0 + y1 * y1);
-            thp = atan2(rho, y2);
-            php = atan2(y1, y0);
-            if (php < 0.0) php += TWO_PI;
-            if (POL && rotate && !naive) {
-                // tangent of the geodesic at x'
-                const double t0 = -sd * x0 + cd * u0, t1 = -sd * x1 + cd * u1, t2 = -sd * x2 + cd * u2;
-                double cpp = 1.0, spp = 0.0;
-                if (rho > 0.0) {
-                    cpp = y0 / rho;
-                    spp = y1 / rho;
-                }
-                const double ctp = y2, stp = rho;
-                const double tt = t0 * ctp * cpp + t1 * ctp * spp - t2 * stp;  // t . e_theta(x')
-                const double tp = -t0 * spp + t1 * cpp;                       // t . e_phi(x')
-                // e^{i gamma} = (a_t + i a_p)(tt - i tp) / (d |t|)
-                const double gr = a_t * tt + a_p * tp;
-                const double gi = a_p * tt - a_t * tp;
-                const double nrm = gr * gr + gi * gi;
-                cg = (gr * gr - gi * gi) / nrm;
-                sg = 2.0 * gr * gi / nrm;
-            }
-        }
-    }
-    // nearest pixel (round half up), residuals against the grid tables
-    int i0 = (int)floor(thp / dth_grid + 0.5);
-    i0 = i0 < 0 ? 0 : (i0 > ntheta - 1 ? ntheta - 1 : i0);
-    int kh = (int)floor(php / dph_grid + 0.5);
-    kh = kh < 0 ? 0 : (kh > nphi ? nphi : kh);
-    const int k0 = kh == nphi ? 0 : kh;
-    const R u = (R)((thp - theta[i0]) / dth_grid);
-    const R v = (R)((php - phival[kh]) / dph_grid);
+    const PixLoc L = locate_pixel(i, k, ntheta, nphi, theta, trig, phitrig, phival, thsrc ? 0.0 : at[idx],
+                                  thsrc ? 0.0 : ap[idx], thsrc, phsrc, idx, naive != 0, POL && rotate);
+    const double cg = L.cg, sg = L.sg;
+    const int i0 = L.i0, k0 = L.k0;
+    const R u = (R)((L.thp - theta[i0]) / dth_grid);
+    const R v = (R)((L.php - phival[L.kh]) / dph_grid);
 
     const size_t plane = (size_t)ntheta * nphi;
     const size_t pix0 = (size_t)i0 * nphi + k0;
@@ -126,6 +63,10 @@ __global__ __launch_bounds__(256) void k_remap(int ntheta, int nphi, const doubl
         }
         res[f] = acc;
     }
+    if (corr) {  // learned remainder of the order-N sum, added before the rotation
+#pragma unroll
+        for (int f = 0; f < (POL ? 3 : 1); ++f) res[f] += (R)corr[(size_t)f * plane + idx];
+    }
     To[idx] = res[0];
     if constexpr (POL) {
         const R q = res[1], uu = res[2];
@@ -136,36 +77,36 @@ __global__ __launch_bounds__(256) void k_remap(int ntheta, int nphi, const doubl
 
 template <typename R, int N>
 hipError_t remap_N(Plan &p, const void *D, const double *at, const double *ap, const double *ths,
-                   const double *phs, void *T, void *Q, void *U)
+                   const double *phs, const float *corr, void *T, void *Q, void *U)
 {
     dim3 grid((p.nphi + 255) / 256, p.ntheta);
     if (p.pol)
         hipLaunchKernelGGL((k_remap<R, N, true>), grid, dim3(256), 0, p.stream, p.ntheta, p.nphi,
                            (const double *)p.theta.ptr, (const double2 *)p.trig.ptr,
                            (const double2 *)p.phitab.ptr, (const double *)p.phival.ptr, (const R *)D, at, ap,
-                           ths, phs, p.rotate, p.naive, (R *)T, (R *)Q, (R *)U);
+                           ths, phs, p.rotate, p.naive, corr, (R *)T, (R *)Q, (R *)U);
     else
         hipLaunchKernelGGL((k_remap<R, N, false>), grid, dim3(256), 0, p.stream, p.ntheta, p.nphi,
                            (const double *)p.theta.ptr, (const double2 *)p.trig.ptr,
                            (const double2 *)p.phitab.ptr, (const double *)p.phival.ptr, (const R *)D, at, ap,
-                           ths, phs, p.rotate, p.naive, (R *)T, (R *)Q, (R *)U);
+                           ths, phs, p.rotate, p.naive, corr, (R *)T, (R *)Q, (R *)U);
     return hipGetLastError();
 }
 
 template <typename R>
 hipError_t remap_R(Plan &p, const void *D, const double *at, const double *ap, const double *ths,
-                   const double *phs, void *T, void *Q, void *U)
+                   const double *phs, const float *corr, void *T, void *Q, void *U)
 {
     switch (p.order) {
-    case 0: return remap_N<R, 0>(p, D, at, ap, ths, phs, T, Q, U);
-    case 1: return remap_N<R, 1>(p, D, at, ap, ths, phs, T, Q, U);
-    case 2: return remap_N<R, 2>(p, D, at, ap, ths, phs, T, Q, U);
-    case 3: return remap_N<R, 3>(p, D, at, ap, ths, phs, T, Q, U);
-    case 4: return remap_N<R, 4>(p, D, at, ap, ths, phs, T, Q, U);
-    case 5: return remap_N<R, 5>(p, D, at, ap, ths, phs, T, Q, U);
-    case 6: return remap_N<R, 6>(p, D, at, ap, ths, phs, T, Q, U);
-    case 7: return remap_N<R, 7>(p, D, at, ap, ths, phs, T, Q, U);
-    case 8: return remap_N<R, 8>(p, D, at, ap, ths, phs, T, Q, U);
+    case 0: return remap_N<R, 0>(p, D, at, ap, ths, phs, corr, T, Q, U);
+    case 1: return remap_N<R, 1>(p, D, at, ap, ths, phs, corr, T, Q, U);
+    case 2: return remap_N<R, 2>(p, D, at, ap, ths, phs, corr, T, Q, U);
+    case 3: return remap_N<R, 3>(p, D, at, ap, ths, phs, corr, T, Q, U);
+    case 4: return remap_N<R, 4>(p, D, at, ap, ths, phs, corr, T, Q, U);
+    case 5: return remap_N<R, 5>(p, D, at, ap, ths, phs, corr, T, Q, U);
+    case 6: return remap_N<R, 6>(p, D, at, ap, ths, phs, corr, T, Q, U);
+    case 7: return remap_N<R, 7>(p, D, at, ap, ths, phs, corr, T, Q, U);
+    case 8: return remap_N<R, 8>(p, D, at, ap, ths, phs, corr, T, Q, U);
     default: return hipErrorInvalidValue;
     }
 }
@@ -173,10 +114,10 @@ hipError_t remap_R(Plan &p, const void *D, const double *at, const double *ap, c
 }  // namespace
 
 hipError_t launch_remap(Plan &p, const void *D, const double *at, const double *ap, const double *thsrc,
-                        const double *phsrc, void *T, void *Q, void *U)
+                        const double *phsrc, void *T, void *Q, void *U, const float *corr)
 {
-    if (p.fp64()) return remap_R<double>(p, D, at, ap, thsrc, phsrc, T, Q, U);
-    return remap_R<float>(p, D, at, ap, thsrc, phsrc, T, Q, U);
+    if (p.fp64()) return remap_R<double>(p, D, at, ap, thsrc, phsrc, corr, T, Q, U);
+    return remap_R<float>(p, D, at, ap, thsrc, phsrc, corr, T, Q, U);
 }
 
 }  // namespace tl

@@ -130,12 +130,34 @@ hipError_t launch_build_tab(Plan &p);
 // part 0: right-hand sides of the batch (k_tab_rhs); part 1: the GEMM
 hipError_t launch_legendre_tab(Plan &p, const TabBatch &b, int part);
 // Stage numbers of the per-kernel profile (one kernel per stage).
-enum Stage { ST_DEFL_LEG = 0, ST_DEFL_FFT, ST_LEG_T, ST_LEG_QU, ST_LEG_MFMA, ST_TAB_RHS, ST_TAB_GEMM, ST_FFT, ST_REMAP };
+enum Stage { ST_DEFL_LEG = 0, ST_DEFL_FFT, ST_LEG_T, ST_LEG_QU, ST_LEG_MFMA, ST_TAB_RHS, ST_TAB_GEMM, ST_FFT, ST_REMAP, ST_CNN };
+
+// ---- learned remainder correction (cnn.hip) ----
+constexpr int kCnnTrain = 32 * 20 * 9 + 32 + 32 * 32 * 9 + 32 + 3 * 32 + 3;  // trainable parameters
+constexpr int kCnnParam = kCnnTrain + 3;                                     // + output scales
+struct CnnBufs {
+    void *params = nullptr;  // float [kCnnParam] (FP32 master)
+    void *m = nullptr, *v = nullptr;  // float [kCnnTrain] Adam moments
+    void *grad = nullptr;    // float [kCnnTrain + 1]: gradient, then the loss
+    void *W1p = nullptr, *W2p = nullptr, *W3p = nullptr;  // BF16 MFMA operands
+    void *work = nullptr;    // training activations (cnn_train_bytes_per_pixel each)
+};
+hipError_t cnn_pack(const CnnBufs &c, hipStream_t st);
+size_t cnn_packed_bytes();
+size_t cnn_train_bytes_per_pixel();
+// corr: float [3][n]; train: also keep activations in c.work (n pixels)
+hipError_t cnn_forward(const Plan &p, const CnnBufs &c, const float *D, const double *at, const double *ap,
+                       const int64_t *pix, int64_t n, float *corr, bool train, hipStream_t st);
+hipError_t cnn_backward(const CnnBufs &c, int64_t n, const float *target, hipStream_t st);
+hipError_t cnn_adam(const CnnBufs &c, int step, float lr, hipStream_t st);
+hipError_t cnn_zero(float *x, int64_t n, hipStream_t st);
 hipError_t launch_legendre_mfma(Plan &p, const void *T, const void *E, const void *B, void *FT, void *FQ,
                                 void *FU);
 hipError_t launch_fft_jobs(Plan &p, const void *Fbase, void *Dbase, const FftJob *jobs, int njobs,
                            bool fp64);
+// corr (optional, FP32 [3][ntheta][nphi]): added to the Taylor sums before the rotation
 hipError_t launch_remap(Plan &p, const void *D, const double *at, const double *ap,
-                        const double *thsrc, const double *phsrc, void *T, void *Q, void *U);
+                        const double *thsrc, const double *phsrc, void *T, void *Q, void *U,
+                        const float *corr = nullptr);
 
 }  // namespace tl

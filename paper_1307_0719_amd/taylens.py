@@ -32,14 +32,19 @@ EXPORTS = [
     "tl_plan_create", "tl_plan_destroy", "tl_plan_workspace_bytes", "tl_plan_query", "tl_lens_map", "tl_lens_map_pos",
     "tl_deflection", "tl_legendre", "tl_synth_derivs", "tl_remap", "tl_lens_map_batch",
     "tl_lens_map_simple", "tl_lens_map_many", "tl_plan_profile", "tl_plan_stage_times", "tl_last_error", "tl_version",
+    "tl_cnn_create", "tl_cnn_destroy", "tl_cnn_get_params", "tl_cnn_set_params", "tl_cnn_forward", "tl_cnn_grad",
+    "tl_cnn_train_step", "tl_lens_map_cnn",
 ]
+CNN_NTRAIN = 15139
+CNN_NPARAM = 15142
 STAGES = ["defl_legendre", "defl_fft", "legendre_T", "legendre_QU", "legendre_mfma", "tab_rhs", "legendre_tab",
-          "ring_fft", "remap"]
+          "ring_fft", "remap", "cnn"]
 QUERY_KEYS = {"rpole": 0, "elems": 1, "elems_caps": 2, "tab_chunks": 3, "tab_chunk_bytes": 4}
 # kernel each stage launches
 STAGE_KERNELS = {"defl_legendre": "k_legendre_scalar", "defl_fft": "k_ring_fft", "legendre_T": "k_legendre_scalar",
                  "legendre_QU": "k_legendre_spin", "legendre_mfma": "k_legendre_mfma", "tab_rhs": "k_tab_rhs",
-                 "legendre_tab": "k_legendre_tab", "ring_fft": "k_ring_fft", "remap": "k_remap"}
+                 "legendre_tab": "k_legendre_tab", "ring_fft": "k_ring_fft", "remap": "k_remap",
+                 "cnn": "k_cnn_forward"}
 
 
 class TaylensError(RuntimeError):
@@ -84,6 +89,14 @@ def lib():
         L.tl_lens_map_many.argtypes = [vp, ctypes.c_int32, vp, vp]
         L.tl_plan_profile.argtypes = [vp, ctypes.c_int32]
         L.tl_plan_stage_times.argtypes = [vp, vp, vp]
+        L.tl_cnn_create.argtypes = [ctypes.POINTER(vp), vp]
+        L.tl_cnn_destroy.argtypes = [vp]
+        L.tl_cnn_get_params.argtypes = [vp, vp]
+        L.tl_cnn_set_params.argtypes = [vp, vp]
+        L.tl_cnn_forward.argtypes = [vp, vp, vp, vp, vp, vp, ctypes.c_int64, vp]
+        L.tl_cnn_grad.argtypes = [vp, vp, vp, vp, vp, vp, ctypes.c_int64, vp, vp]
+        L.tl_cnn_train_step.argtypes = [vp, vp, vp, vp, vp, vp, ctypes.c_int64, vp, ctypes.c_float, vp]
+        L.tl_lens_map_cnn.argtypes = [vp] * 9
         L.tl_last_error.restype = ctypes.c_char_p
         L.tl_last_error.argtypes = []
         L.tl_version.restype = ctypes.c_int
@@ -279,6 +292,94 @@ class Plan:
         out = (self._maps(), self._maps() if self.pol else None, self._maps() if self.pol else None)
         _check(lib().tl_remap(self._h, _ptr(D), _ptr(at), _ptr(ap), _ptr(out[0]), _ptr(out[1]), _ptr(out[2])))
         self._keep = (D, at, ap)
+        return out
+
+
+class Cnn:
+    """The learned remainder correction (weights on the device, Adam state).
+
+    Parameter vector layout: W1[32][20][3][3], b1[32], W2[32][32][3][3],
+    b2[32], W3[3][32], b3[3], scale[3] (float32, CNN_NPARAM values)."""
+
+    def __init__(self, params):
+        p = np.ascontiguousarray(np.asarray(params, dtype=np.float32))
+        if p.size != CNN_NPARAM:
+            raise ValueError(f"expected {CNN_NPARAM} parameters, got {p.size}")
+        h = ctypes.c_void_p()
+        _check(lib().tl_cnn_create(ctypes.byref(h), p.ctypes.data_as(ctypes.c_void_p)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().tl_cnn_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def params(self) -> np.ndarray:
+        out = np.empty(CNN_NPARAM, dtype=np.float32)
+        _check(lib().tl_cnn_get_params(self._h, out.ctypes.data_as(ctypes.c_void_p)))
+        return out
+
+    def set_params(self, params):
+        p = np.ascontiguousarray(np.asarray(params, dtype=np.float32))
+        if p.size != CNN_NPARAM:
+            raise ValueError(f"expected {CNN_NPARAM} parameters")
+        _check(lib().tl_cnn_set_params(self._h, p.ctypes.data_as(ctypes.c_void_p)))
+
+    @staticmethod
+    def _args(plan, D, at, ap, pix):
+        D = D.to(plan.device, torch.float32).contiguous()
+        at = at.to(plan.device, torch.float64).contiguous()
+        ap = ap.to(plan.device, torch.float64).contiguous()
+        if pix is not None:
+            pix = torch.as_tensor(pix, dtype=torch.int64).to(plan.device).contiguous()
+        return D, at, ap, pix
+
+    def forward(self, plan: Plan, D, alpha_theta, alpha_phi, pix=None, n=None):
+        """Corrections [3][n] of the pixels pix (or of pixels 0..n-1)."""
+        D, at, ap, pix = self._args(plan, D, alpha_theta, alpha_phi, pix)
+        n = int(pix.numel()) if pix is not None else int(n if n is not None else plan.ntheta * plan.nphi)
+        out = torch.empty((3, n), dtype=torch.float32, device=plan.device)
+        _check(lib().tl_cnn_forward(self._h, plan.handle, _ptr(D), _ptr(at), _ptr(ap), _ptr(pix), n, _ptr(out)))
+        self._keep = (D, at, ap, pix)
+        return out
+
+    def grad(self, plan: Plan, D, alpha_theta, alpha_phi, pix, target):
+        """[CNN_NTRAIN + 1]: gradient of the loss, then the loss."""
+        D, at, ap, pix = self._args(plan, D, alpha_theta, alpha_phi, pix)
+        t = target.to(plan.device, torch.float32).contiguous()
+        n = int(t.shape[-1])
+        out = torch.empty(CNN_NTRAIN + 1, dtype=torch.float32, device=plan.device)
+        _check(lib().tl_cnn_grad(self._h, plan.handle, _ptr(D), _ptr(at), _ptr(ap), _ptr(pix), n, _ptr(t),
+                                 _ptr(out)))
+        self._keep = (D, at, ap, pix, t)
+        return out
+
+    def train_step(self, plan: Plan, D, alpha_theta, alpha_phi, pix, target, lr: float):
+        """One Adam step; returns the loss before it (device scalar tensor)."""
+        D, at, ap, pix = self._args(plan, D, alpha_theta, alpha_phi, pix)
+        t = target.to(plan.device, torch.float32).contiguous()
+        n = int(t.shape[-1])
+        loss = torch.empty(1, dtype=torch.float32, device=plan.device)
+        _check(lib().tl_cnn_train_step(self._h, plan.handle, _ptr(D), _ptr(at), _ptr(ap), _ptr(pix), n, _ptr(t),
+                                       ctypes.c_float(lr), _ptr(loss)))
+        self._keep = (D, at, ap, pix, t)
+        return loss
+
+    def lens_map(self, plan: Plan, alm_T, alm_E, alm_B, alm_phi, out=None):
+        """Order-2 lensing of plan with the network's correction."""
+        T, E, B = plan._inputs(alm_T, alm_E, alm_B)
+        P = _alm(alm_phi, "alm_phi", plan.device, plan.lmax)
+        if out is None:
+            out = (plan._maps(), plan._maps(), plan._maps())
+        _check(lib().tl_lens_map_cnn(plan.handle, self._h, _ptr(T), _ptr(E), _ptr(B), _ptr(P), _ptr(out[0]),
+                                     _ptr(out[1]), _ptr(out[2])))
+        self._keep = (T, E, B, P)
         return out
 
 

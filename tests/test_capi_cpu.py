@@ -69,3 +69,18 @@ def test_null_arguments(tl):
     assert L.tl_plan_stage_times(None, None, None) == -1
     v = ctypes.c_int64()
     assert L.tl_plan_query(None, 0, ctypes.byref(v)) == -1
+
+
+def test_cnn_null_arguments(tl):
+    L = tl.lib()
+    h = ctypes.c_void_p()
+    assert L.tl_cnn_create(None, None) == -1
+    assert L.tl_cnn_create(ctypes.byref(h), None) == -1 and h.value is None
+    assert L.tl_cnn_destroy(None) == 0
+    assert L.tl_cnn_get_params(None, None) == -1
+    assert L.tl_cnn_set_params(None, None) == -1
+    assert L.tl_cnn_forward(None, None, None, None, None, None, 0, None) == -1
+    assert L.tl_cnn_grad(None, None, None, None, None, None, 0, None, None) == -1
+    assert L.tl_cnn_train_step(None, None, None, None, None, None, 0, None, ctypes.c_float(1e-3), None) == -1
+    assert L.tl_lens_map_cnn(*([None] * 9)) == -1
+    assert tl.CNN_NPARAM == 15142 and tl.CNN_NTRAIN == 15139
