@@ -188,6 +188,39 @@ int tl_lens_map_simple(const void *alm_T, const void *alm_E, const void *alm_B,
                        const void *alm_phi, int32_t lmax, int32_t order, tl_grid grid,
                        void *T_out, void *Q_out, void *U_out);
 
+/* ---- batches of realizations with uneven lmax ----
+ *
+ * A batch lenses n realizations, each with its own plan (plans may repeat:
+ * realizations of equal lmax can share one), in one pass: the polar-cap
+ * kernels of every realization, then ONE persistent launch of the
+ * matrix-core harmonic kernel whose workgroups pop work items (realization,
+ * block of ring pairs, run of m) from a queue ordered by decreasing cost
+ * (longest processing time first), then per realization the deflection,
+ * ring FFTs and remap.  The whole sequence can be captured in a HIP graph
+ * and replayed.  Work-item shape (m per item) and persistent grid size come
+ * from an autotuner that times the candidates on the batch itself at the
+ * first run and caches the choice on disk (TAYLENS_TUNE_CACHE, default
+ * $HOME/.cache/taylens_tune.txt; unwritable: not cached).
+ * Requirements: every plan TL_FP32 form, same order (<= 8), same pol, same
+ * stream; a batch keeps its own harmonic-stage output per realization. */
+typedef struct tl_batch_s *tl_batch;
+typedef struct {
+    int32_t autotune;       /* 1: tune at the first run (see above); 0: use the two fields below */
+    int32_t use_graph;      /* 1: capture at the first run, replay while the argument pointers are unchanged */
+    int32_t m_groups;       /* runs of 8 m per work item, 1..8 (0: 1) */
+    int32_t groups_per_cu;  /* persistent workgroups per compute unit, 1..8 (0: 2) */
+} tl_batch_options;
+
+int tl_batch_create(tl_batch *out, int32_t n, const tl_plan *plans, const tl_batch_options *opt);
+int tl_batch_destroy(tl_batch b);
+/* alms: 4n device pointers (T, E, B, phi per realization; E/B/phi as in
+ * tl_lens_map, B all NULL or all set); outs: 3n device pointers. */
+int tl_batch_run(tl_batch b, const void *const *alms, void *const *outs);
+/* The work-item shape in use and the tuned time of the harmonic launch (ms,
+ * 0 if not tuned); graph_replays counts runs served by graph replay. */
+int tl_batch_info(tl_batch b, int32_t *m_groups, int32_t *groups_per_cu, double *tuned_ms,
+                  int64_t *graph_replays);
+
 /* ---- learned remainder correction ----
  *
  * The Taylor series of eq. 5 is cut at order N; a small network predicts,

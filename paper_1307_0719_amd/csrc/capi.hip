@@ -5,6 +5,8 @@
 #include <algorithm>
 #include <new>
 #include <vector>
+#include <string>
+#include <sys/stat.h>
 
 #include "tl_internal.h"
 
@@ -304,7 +306,7 @@ int check_plan(tl_plan plan)
 int run_deflection(Plan &p, const void *alm_phi)
 {
     if (!alm_phi) {
-        TL_HIP(hipMemsetAsync(p.alpha.ptr, 0, p.alpha.bytes, p.stream), "alpha clear");
+        TL_HIP(fill_words(p.alpha.ptr, p.alpha.bytes / 4, 0u, p.stream), "alpha clear");
         return TL_OK;
     }
     {
@@ -465,6 +467,27 @@ struct tl_cnn_s {
     DevBuf corr;   // float [3][n] scratch of the training calls / full-map correction
 };
 
+struct tl_batch_s {
+    int n = 0;
+    std::vector<tl_plan> plans;
+    int order = 0, pol = 0, device = 0, ncu = 256;
+    hipStream_t user = nullptr;     // the plans' stream
+    hipStream_t bs = nullptr;       // the batch's own stream (capturable)
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    std::vector<DevBuf> F;          // harmonic-stage output per realization (complex64)
+    DevBuf jobs, items, head;
+    int nitems = 0;
+    int m_groups = 1, gpc = 2;
+    bool autotune = false, use_graph = false, tuned = false;
+    double tuned_ms = 0.0;
+    int64_t replays = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::vector<const void *> cap_alms;
+    std::vector<void *> cap_outs;
+    std::string key;
+};
+
 namespace {
 
 void free_cnn(tl_cnn_s *h)
@@ -516,6 +539,216 @@ int cnn_grad_run(tl_cnn net, Plan &p, const float *D, const double *at, const do
     TL_HIP(cnn_backward(net->c, n, target, p.stream), "cnn backward");
     return TL_OK;
 }
+
+// ---------------------------------------------------------------- batch --
+
+void batch_drop_graph(tl_batch_s *b)
+{
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+    b->cap_alms.clear();
+    b->cap_outs.clear();
+}
+
+void free_batch(tl_batch_s *b)
+{
+    batch_drop_graph(b);
+    for (auto &f : b->F) free_buf(f);
+    free_buf(b->jobs);
+    free_buf(b->items);
+    free_buf(b->head);
+    if (b->ev_in) (void)hipEventDestroy(b->ev_in);
+    if (b->ev_out) (void)hipEventDestroy(b->ev_out);
+    if (b->bs) (void)hipStreamDestroy(b->bs);
+}
+
+size_t batch_rowc(const Plan &p) { return (size_t)p.ntheta * (p.lmax + 1) * (p.order + 1); }
+
+// Work items (realization, ring block, first m-group, m-groups), longest first.
+int batch_items(tl_batch_s *b, int nmg)
+{
+    const int RPB = mfma_ring_block(), MG = mfma_m_group();
+    struct It {
+        int4 w;
+        double cost;
+    };
+    std::vector<It> v;
+    for (int i = 0; i < b->n; ++i) {
+        const Plan &p = b->plans[i]->p;
+        const int nr = p.nrp - p.rpole;
+        const int ngrp = (p.lmax + 1 + MG - 1) / MG;
+        for (int rb = 0; rb * RPB < nr; ++rb) {
+            const int rings = std::min(RPB, nr - rb * RPB);
+            for (int g0 = 0; g0 < ngrp; g0 += nmg) {
+                const int cnt = std::min(nmg, ngrp - g0);
+                double c = 0.0;
+                for (int m = g0 * MG; m < std::min((g0 + cnt) * MG, p.lmax + 1); ++m) c += (double)(p.lmax - m + 1);
+                v.push_back({make_int4(i, rb, g0, cnt), c * rings});
+            }
+        }
+    }
+    std::stable_sort(v.begin(), v.end(), [](const It &a, const It &c) { return a.cost > c.cost; });
+    std::vector<int4> w(v.size());
+    for (size_t k = 0; k < v.size(); ++k) w[k] = v[k].w;
+    free_buf(b->items);
+    b->nitems = (int)w.size();
+    if (w.empty()) return TL_OK;
+    TL_HIP(hipMalloc(&b->items.ptr, w.size() * sizeof(int4)), "batch items");
+    b->items.bytes = w.size() * sizeof(int4);
+    TL_HIP(hipMemcpy(b->items.ptr, w.data(), b->items.bytes, hipMemcpyHostToDevice), "batch items");
+    return TL_OK;
+}
+
+std::string tune_path()
+{
+    const char *e = getenv("TAYLENS_TUNE_CACHE");
+    if (e && *e) return e;
+    const char *h = getenv("HOME");
+    return std::string(h ? h : "/tmp") + "/.cache/taylens_tune.txt";
+}
+
+bool tune_lookup(const std::string &key, int &nmg, int &gpc, double &ms)
+{
+    FILE *f = fopen(tune_path().c_str(), "r");
+    if (!f) return false;
+    char line[1024];
+    bool hit = false;
+    while (fgets(line, sizeof line, f)) {
+        char k[900];
+        int a = 0, c = 0;
+        double t = 0;
+        if (sscanf(line, "%899s %d %d %lf", k, &a, &c, &t) == 4 && key == k && a >= 1 && a <= 8 && c >= 1 &&
+            c <= 8) {
+            nmg = a;
+            gpc = c;
+            ms = t;
+            hit = true;  // the last entry wins
+        }
+    }
+    fclose(f);
+    return hit;
+}
+
+void tune_store(const std::string &key, int nmg, int gpc, double ms)
+{
+    const std::string path = tune_path();
+    const size_t sl = path.rfind('/');
+    if (sl != std::string::npos) (void)mkdir(path.substr(0, sl).c_str(), 0755);
+    FILE *f = fopen(path.c_str(), "a");
+    if (!f) return;  // not cached
+    fprintf(f, "%s %d %d %.6f\n", key.c_str(), nmg, gpc, ms);
+    fclose(f);
+}
+
+int batch_queue_launch(tl_batch_s *b, bool hasb)
+{
+    TL_HIP(fill_words(b->head.ptr, 1, 0u, b->bs), "queue head");
+    TL_HIP(launch_legendre_mfma_queue(b->order, b->pol != 0, hasb, b->bs, (const MfmaJob *)b->jobs.ptr,
+                                      (const int4 *)b->items.ptr, b->nitems, (int *)b->head.ptr, b->gpc * b->ncu),
+           "persistent harmonic kernel");
+    return TL_OK;
+}
+
+// Time the candidate work-item shapes on this batch; keep the fastest.
+int batch_tune(tl_batch_s *b, bool hasb)
+{
+    int nmg = 1, gpc = 2;
+    double ms = 0.0;
+    if (tune_lookup(b->key, nmg, gpc, ms)) {
+        b->m_groups = nmg;
+        b->gpc = gpc;
+        b->tuned_ms = ms;
+        b->tuned = true;
+        return batch_items(b, nmg);
+    }
+    hipEvent_t e0, e1;
+    TL_HIP(hipEventCreate(&e0), "event");
+    TL_HIP(hipEventCreate(&e1), "event");
+    double best = 1e300;
+    int bn = 1, bg = 2;
+    int rc = TL_OK;
+    const int cand_m[] = {1, 2, 4}, cand_g[] = {1, 2, 4};
+    for (int cm : cand_m) {
+        if ((rc = batch_items(b, cm))) break;
+        for (int cg : cand_g) {
+            b->gpc = cg;
+            if ((rc = batch_queue_launch(b, hasb))) break;  // warm-up
+            hipError_t e = hipEventRecord(e0, b->bs);
+            if (e == hipSuccess && (rc = batch_queue_launch(b, hasb))) break;
+            if (e == hipSuccess) e = hipEventRecord(e1, b->bs);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float t = 0.f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+            if (e != hipSuccess) {
+                rc = hipfail(e, "autotune timing");
+                break;
+            }
+            if (t < best) {
+                best = t;
+                bn = cm;
+                bg = cg;
+            }
+        }
+        if (rc) break;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) return rc;
+    b->m_groups = bn;
+    b->gpc = bg;
+    b->tuned_ms = best;
+    b->tuned = true;
+    tune_store(b->key, bn, bg, best);
+    return batch_items(b, bn);
+}
+
+int batch_enqueue(tl_batch_s *b, const void *const *alms, void *const *outs, bool hasb)
+{
+    // polar caps (direct FP64 kernels) of every realization
+    for (int i = 0; i < b->n; ++i) {
+        Plan &p = b->plans[i]->p;
+        char *F = (char *)b->F[i].ptr;
+        const size_t rc8 = batch_rowc(p) * 8;
+        TL_HIP(launch_legendre_scalar(p, p.order, p.rpole, alms[4 * i], F, false), "legendre T");
+        if (p.pol)
+            TL_HIP(launch_legendre_spin(p, p.order, p.rpole, alms[4 * i + 1], alms[4 * i + 2], F + rc8, F + 2 * rc8,
+                                        false),
+                   "legendre QU");
+    }
+    int rc = batch_queue_launch(b, hasb);
+    if (rc) return rc;
+    for (int i = 0; i < b->n; ++i) {
+        Plan &p = b->plans[i]->p;
+        if ((rc = run_deflection(p, alms[4 * i + 3]))) return rc;
+        TL_HIP(launch_fft_jobs(p, b->F[i].ptr, p.D.ptr, (const FftJob *)p.jobsMain.ptr, p.njobsMain, false),
+               "ring fft");
+        const double *at = (const double *)p.alpha.ptr;
+        TL_HIP(launch_remap(p, p.D.ptr, at, at + p.npix(), nullptr, nullptr, outs[3 * i], outs[3 * i + 1],
+                            outs[3 * i + 2]),
+               "remap");
+    }
+    return TL_OK;
+}
+
+// Point every plan at the batch stream for the duration of a run.
+struct BatchStreams {
+    tl_batch_s *b;
+    std::vector<hipStream_t> keep;
+    explicit BatchStreams(tl_batch_s *bb) : b(bb)
+    {
+        for (auto pl : b->plans) {
+            keep.push_back(pl->p.stream);
+            pl->p.stream = b->bs;
+        }
+    }
+    ~BatchStreams()
+    {
+        // reverse order: a plan listed twice gets its first-seen stream back
+        for (size_t i = keep.size(); i-- > 0;) b->plans[i]->p.stream = keep[i];
+    }
+};
 
 }  // namespace
 
@@ -845,6 +1078,166 @@ int tl_lens_map_many(tl_plan plan, int32_t n, const void *const *alms, void *con
                    "remap");
         }
     }
+    return TL_OK;
+}
+
+int tl_batch_create(tl_batch *out, int32_t n, const tl_plan *plans, const tl_batch_options *opt)
+{
+    if (!out) return fail(TL_ERR_INVALID, "batch output pointer is NULL");
+    *out = nullptr;
+    if (n <= 0) return fail(TL_ERR_INVALID, "n must be >= 1");
+    if (!plans || !opt) return fail(TL_ERR_INVALID, "NULL argument");
+    if (opt->m_groups < 0 || opt->m_groups > 8 || opt->groups_per_cu < 0 || opt->groups_per_cu > 8)
+        return fail(TL_ERR_INVALID, "m_groups and groups_per_cu must be in 0..8");
+    for (int i = 0; i < n; ++i) {
+        if (!plans[i]) return fail(TL_ERR_INVALID, "plan " + std::to_string(i) + " is NULL");
+        const Plan &p = plans[i]->p;
+        const Plan &p0 = plans[0]->p;
+        if (p.precision != TL_FP32) return fail(TL_ERR_UNSUPPORTED, "a batch needs TL_FP32 plans");
+        if (p.order != p0.order || p.pol != p0.pol) return fail(TL_ERR_INVALID, "plans differ in order or pol");
+        if (p.stream != p0.stream || p.device != p0.device) return fail(TL_ERR_INVALID, "plans differ in stream");
+        if (!mfma_supported(p.order, p.pol != 0)) return fail(TL_ERR_UNSUPPORTED, "order too high for the batch");
+    }
+    tl_batch_s *b = new (std::nothrow) tl_batch_s;
+    if (!b) return fail(TL_ERR_NOMEM, "host allocation failed");
+    auto bail = [&](int code) {
+        free_batch(b);
+        delete b;
+        return code;
+    };
+    b->n = n;
+    b->plans.assign(plans, plans + n);
+    const Plan &p0 = plans[0]->p;
+    b->order = p0.order;
+    b->pol = p0.pol;
+    b->device = p0.device;
+    b->user = p0.stream;
+    b->autotune = opt->autotune != 0;
+    b->use_graph = opt->use_graph != 0;
+    b->m_groups = opt->m_groups ? opt->m_groups : 1;
+    b->gpc = opt->groups_per_cu ? opt->groups_per_cu : 2;
+    int rc = set_device_of(plans[0]->p);
+    if (rc) return bail(rc);
+    hipError_t e = hipDeviceGetAttribute(&b->ncu, hipDeviceAttributeMultiprocessorCount, b->device);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->bs, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming);
+    if (e != hipSuccess) return bail(hipfail(e, "batch stream"));
+    b->F.resize(n);
+    std::vector<std::pair<int, int>> shapes;
+    for (int i = 0; i < n; ++i) {
+        const Plan &p = plans[i]->p;
+        const size_t bytes = (size_t)p.nfield() * batch_rowc(p) * 8;
+        e = hipMalloc(&b->F[i].ptr, bytes);
+        if (e != hipSuccess) return bail(fail(TL_ERR_NOMEM, "batch harmonic output: out of device memory"));
+        b->F[i].bytes = bytes;
+        shapes.push_back({p.lmax, p.ntheta});
+    }
+    e = hipMalloc(&b->jobs.ptr, n * sizeof(MfmaJob));
+    if (e == hipSuccess) e = hipMalloc(&b->head.ptr, 256);
+    if (e != hipSuccess) return bail(hipfail(e, "batch buffers"));
+    b->jobs.bytes = n * sizeof(MfmaJob);
+    b->head.bytes = 256;
+    std::sort(shapes.begin(), shapes.end());
+    b->key = "mfmaq-N" + std::to_string(b->order) + "-P" + std::to_string(b->pol) + "-cu" + std::to_string(b->ncu);
+    for (size_t k = 0; k < shapes.size();) {
+        size_t j = k;
+        while (j < shapes.size() && shapes[j] == shapes[k]) ++j;
+        b->key += "-" + std::to_string(shapes[k].first) + "x" + std::to_string(shapes[k].second) + "." +
+                  std::to_string(j - k);
+        k = j;
+    }
+    if ((rc = batch_items(b, b->m_groups))) return bail(rc);
+    *out = b;
+    return TL_OK;
+}
+
+int tl_batch_destroy(tl_batch b)
+{
+    if (!b) return TL_OK;
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    (void)hipSetDevice(b->device);
+    (void)hipStreamSynchronize(b->bs);
+    free_batch(b);
+    (void)hipSetDevice(cur);
+    delete b;
+    return TL_OK;
+}
+
+int tl_batch_run(tl_batch b, const void *const *alms, void *const *outs)
+{
+    if (!b) return fail(TL_ERR_INVALID, "batch is NULL");
+    if (!alms || !outs) return fail(TL_ERR_INVALID, "NULL argument");
+    int rc;
+    const bool hasb = b->pol && alms[2] != nullptr;
+    for (int i = 0; i < b->n; ++i) {
+        const Plan &p = b->plans[i]->p;
+        if ((rc = check_fields(p, alms[4 * i], alms[4 * i + 1]))) return rc;
+        if ((rc = check_outputs(p, outs[3 * i], outs[3 * i + 1], outs[3 * i + 2]))) return rc;
+        if (b->pol && ((alms[4 * i + 2] != nullptr) != hasb))
+            return fail(TL_ERR_INVALID, "alm_B must be set for all realizations or for none");
+    }
+    if ((rc = set_device_of(b->plans[0]->p))) return rc;
+    for (auto pl : b->plans)
+        if (pl->p.stream != b->user) return fail(TL_ERR_INVALID, "a plan's stream changed since the batch was made");
+    // order after the caller's earlier work, and the caller's later work after this
+    TL_HIP(hipEventRecord(b->ev_in, b->user), "event");
+    TL_HIP(hipStreamWaitEvent(b->bs, b->ev_in, 0), "event wait");
+    BatchStreams guard(b);
+    bool profiling = false;
+    for (auto pl : b->plans) profiling |= pl->p.profile;
+    const bool same = b->exec && !profiling && b->cap_alms.size() == (size_t)4 * b->n &&
+                      std::equal(b->cap_alms.begin(), b->cap_alms.end(), alms) &&
+                      std::equal(b->cap_outs.begin(), b->cap_outs.end(), outs);
+    if (same) {
+        TL_HIP(hipGraphLaunch(b->exec, b->bs), "graph launch");
+        b->replays += 1;
+    } else {
+        std::vector<MfmaJob> J(b->n);
+        for (int i = 0; i < b->n; ++i) {
+            const Plan &p = b->plans[i]->p;
+            char *F = (char *)b->F[i].ptr;
+            const size_t rc8 = batch_rowc(p) * 8;
+            J[i] = mfma_job(p, alms[4 * i], alms[4 * i + 1], alms[4 * i + 2], F, p.pol ? F + rc8 : nullptr,
+                            p.pol ? F + 2 * rc8 : nullptr);
+        }
+        TL_HIP(hipMemcpyAsync(b->jobs.ptr, J.data(), J.size() * sizeof(MfmaJob), hipMemcpyHostToDevice, b->bs),
+               "batch jobs");
+        TL_HIP(hipStreamSynchronize(b->bs), "synchronize");
+        if (b->autotune && !b->tuned && (rc = batch_tune(b, hasb))) return rc;
+        if (b->use_graph && !profiling) {
+            batch_drop_graph(b);
+            TL_HIP(hipStreamBeginCapture(b->bs, hipStreamCaptureModeThreadLocal), "begin capture");
+            rc = batch_enqueue(b, alms, outs, hasb);
+            hipGraph_t g = nullptr;
+            const hipError_t e = hipStreamEndCapture(b->bs, &g);
+            if (rc) {
+                if (g) (void)hipGraphDestroy(g);
+                return rc;
+            }
+            if (e != hipSuccess) return hipfail(e, "end capture");
+            b->graph = g;
+            TL_HIP(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0), "graph instantiate");
+            TL_HIP(hipGraphLaunch(b->exec, b->bs), "graph launch");
+            b->cap_alms.assign(alms, alms + 4 * b->n);
+            b->cap_outs.assign(outs, outs + 3 * b->n);
+        } else if ((rc = batch_enqueue(b, alms, outs, hasb))) {
+            return rc;
+        }
+    }
+    TL_HIP(hipEventRecord(b->ev_out, b->bs), "event");
+    TL_HIP(hipStreamWaitEvent(b->user, b->ev_out, 0), "event wait");
+    return TL_OK;
+}
+
+int tl_batch_info(tl_batch b, int32_t *m_groups, int32_t *groups_per_cu, double *tuned_ms, int64_t *graph_replays)
+{
+    if (!b) return fail(TL_ERR_INVALID, "batch is NULL");
+    if (m_groups) *m_groups = b->m_groups;
+    if (groups_per_cu) *groups_per_cu = b->gpc;
+    if (tuned_ms) *tuned_ms = b->tuned ? b->tuned_ms : 0.0;
+    if (graph_replays) *graph_replays = b->replays;
     return TL_OK;
 }
 

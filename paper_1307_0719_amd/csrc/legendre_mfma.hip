@@ -286,19 +286,10 @@ __device__ __forceinline__ void swap32(float &a, float &b)
     b = u2f(r[1]);
 }
 
-template <int N, bool POL, bool HASB>
-__global__ __launch_bounds__(WG) void k_legendre_mfma(
-    int lmax, int ntheta, int nrp, int rbeg, int jtab, const double2 *__restrict__ trig,
-    const double *__restrict__ theta, const double4 *__restrict__ coef0, const double *__restrict__ start,
-    const int *__restrict__ exps, const int *__restrict__ mcut, const double2 *__restrict__ almT,
-    const double2 *__restrict__ almE, const double2 *__restrict__ almB, float2 *__restrict__ FT,
-    float2 *__restrict__ FQ, float2 *__restrict__ FU)
-{
-    constexpr Cols C = cols_of(N, HASB);
-    static_assert(C.ncol <= NCOL, "column block overflow");
-    constexpr int NC = C.ncol;
-
-    // LDS: chunk operands during the l loop, epilogue buffer afterwards
+// LDS of one workgroup: chunk operands during the l loop, epilogue buffer
+// afterwards.
+template <int NC>
+struct MfmaSmem {
     struct Chunk {
         float rhs[KCH * NCOL];
         double2 cf[KCH + 2];
@@ -306,17 +297,40 @@ __global__ __launch_bounds__(WG) void k_legendre_mfma(
     struct Epi {
         double tot[RPW][4][NC];  // [ring][type*2+parity][col]
     };
-    __shared__ union {
+    union {
         Chunk ch;
         Epi ep;
-    } sm;
+    };
+};
+
+// One work item: ring block rblk (RPB ring pairs from j.rbeg), m-groups
+// mg0 .. mg0 + nmg - 1 (MGRP consecutive m each) of one realization.
+template <int N, bool POL, bool HASB>
+__device__ void mfma_item(const MfmaJob &J, int rblk, int mg0, int nmg, MfmaSmem<cols_of(N, HASB).ncol> &sm)
+{
+    const int lmax = J.lmax, ntheta = J.ntheta, nrp = J.nrp, jtab = J.jtab;
+    const double2 *__restrict__ trig = J.trig;
+    const double *__restrict__ theta = J.theta;
+    const double4 *__restrict__ coef0 = J.coef0;
+    const double *__restrict__ start = J.start;
+    const int *__restrict__ exps = J.exps;
+    const int *__restrict__ mcut = J.mcut;
+    const double2 *__restrict__ almT = J.almT;
+    const double2 *__restrict__ almE = J.almE;
+    const double2 *__restrict__ almB = J.almB;
+    float2 *__restrict__ FT = J.FT;
+    float2 *__restrict__ FQ = J.FQ;
+    float2 *__restrict__ FU = J.FU;
+    constexpr Cols C = cols_of(N, HASB);
+    static_assert(C.ncol <= NCOL, "column block overflow");
+    constexpr int NC = C.ncol;
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
     const int hi = lane >> 5;          // lanes 32..63 run two l-steps ahead
     const int rl = lane & 31;
-    const int r = rbeg + blockIdx.x * RPB + wave * RPW + rl;
+    const int r = J.rbeg + rblk * RPB + wave * RPW + rl;
     const bool live = r < nrp;
     const double x = live ? trig[r].x : 0.0;
     const double sn = live ? trig[r].y : 1.0;
@@ -325,8 +339,8 @@ __global__ __launch_bounds__(WG) void k_legendre_mfma(
     const size_t plane = (size_t)ntheta * (lmax + 1);
     const int mc = live ? mcut[r] + 2 : -1;  // spin-2 terms reach two past the scalar cut
 
-    for (int mi = 0; mi < MGRP; ++mi) {
-        const int m = blockIdx.y * MGRP + mi;
+    for (int mi = 0; mi < MGRP * nmg; ++mi) {
+        const int m = mg0 * MGRP + mi;
         if (m > lmax) break;
         const size_t base = (size_t)m * (2 * lmax + 1 - m) / 2;
         if (!__syncthreads_or(m <= mc)) {  // evanescent for every ring of the block
@@ -503,6 +517,57 @@ __global__ __launch_bounds__(WG) void k_legendre_mfma(
 }
 
 template <int N, bool POL, bool HASB>
+__global__ __launch_bounds__(WG) void k_legendre_mfma(const MfmaJob J)
+{
+    __shared__ MfmaSmem<cols_of(N, HASB).ncol> sm;
+    mfma_item<N, POL, HASB>(J, blockIdx.x, blockIdx.y, 1, sm);
+}
+
+// Persistent form: workgroups pop work items (realization, ring block,
+// first m-group, m-groups) from a queue ordered longest first until it is
+// empty; every workgroup exits once the head passes the end.
+template <int N, bool POL, bool HASB>
+__global__ __launch_bounds__(WG) void k_legendre_mfma_queue(const MfmaJob *__restrict__ jobs,
+                                                            const int4 *__restrict__ items, int nitems,
+                                                            int *__restrict__ head)
+{
+    __shared__ MfmaSmem<cols_of(N, HASB).ncol> sm;
+    __shared__ int s_it;
+    for (;;) {
+        __syncthreads();
+        if (threadIdx.x == 0) s_it = atomicAdd(head, 1);
+        __syncthreads();
+        const int it = s_it;
+        if (it >= nitems) break;
+        const int4 w = items[it];
+        mfma_item<N, POL, HASB>(jobs[w.x], w.y, w.z, w.w, sm);
+    }
+}
+
+MfmaJob make_job(const Plan &p, const void *T, const void *E, const void *B, void *FT, void *FQ, void *FU)
+{
+    MfmaJob J{};
+    J.lmax = p.lmax;
+    J.ntheta = p.ntheta;
+    J.nrp = p.nrp;
+    J.rbeg = p.rpole;
+    J.jtab = p.jtab;
+    J.trig = (const double2 *)p.trig.ptr;
+    J.theta = (const double *)p.theta.ptr;
+    J.coef0 = (const double4 *)p.coef0.ptr;
+    J.start = (const double *)p.start.ptr;
+    J.exps = (const int *)p.exps.ptr;
+    J.mcut = (const int *)p.mcut.ptr;
+    J.almT = (const double2 *)T;
+    J.almE = (const double2 *)E;
+    J.almB = (const double2 *)B;
+    J.FT = (float2 *)FT;
+    J.FQ = (float2 *)FQ;
+    J.FU = (float2 *)FU;
+    return J;
+}
+
+template <int N, bool POL, bool HASB>
 hipError_t launch_N(Plan &p, const void *T, const void *E, const void *B, void *FT, void *FQ, void *FU)
 {
     if constexpr (cols_of(N, HASB).ncol > NCOL) {
@@ -511,11 +576,20 @@ hipError_t launch_N(Plan &p, const void *T, const void *E, const void *B, void *
         const int nr = p.nrp - p.rpole;
         if (nr <= 0) return hipSuccess;
         dim3 grid((nr + RPB - 1) / RPB, (p.lmax + 1 + MGRP - 1) / MGRP);
-        hipLaunchKernelGGL((k_legendre_mfma<N, POL, HASB>), grid, dim3(WG), 0, p.stream, p.lmax, p.ntheta, p.nrp,
-                           p.rpole, p.jtab, (const double2 *)p.trig.ptr, (const double *)p.theta.ptr,
-                           (const double4 *)p.coef0.ptr, (const double *)p.start.ptr, (const int *)p.exps.ptr,
-                           (const int *)p.mcut.ptr, (const double2 *)T, (const double2 *)E, (const double2 *)B,
-                           (float2 *)FT, (float2 *)FQ, (float2 *)FU);
+        hipLaunchKernelGGL((k_legendre_mfma<N, POL, HASB>), grid, dim3(WG), 0, p.stream,
+                           make_job(p, T, E, B, FT, FQ, FU));
+        return hipGetLastError();
+    }
+}
+
+template <int N, bool POL, bool HASB>
+hipError_t launch_queue_N(hipStream_t st, const MfmaJob *jobs, const int4 *items, int nitems, int *head, int ngroups)
+{
+    if constexpr (cols_of(N, HASB).ncol > NCOL) {
+        return hipErrorInvalidValue;
+    } else {
+        hipLaunchKernelGGL((k_legendre_mfma_queue<N, POL, HASB>), dim3(ngroups), dim3(WG), 0, st, jobs, items, nitems,
+                           head);
         return hipGetLastError();
     }
 }
@@ -523,6 +597,37 @@ hipError_t launch_N(Plan &p, const void *T, const void *E, const void *B, void *
 }  // namespace
 
 bool mfma_supported(int order, bool hasb) { return cols_of(order, hasb).ncol <= NCOL; }
+
+int mfma_ring_block() { return RPB; }
+int mfma_m_group() { return MGRP; }
+
+MfmaJob mfma_job(const Plan &p, const void *T, const void *E, const void *B, void *FT, void *FQ, void *FU)
+{
+    return make_job(p, T, E, B, FT, FQ, FU);
+}
+
+hipError_t launch_legendre_mfma_queue(int order, bool pol, bool hasb, hipStream_t st, const MfmaJob *jobs,
+                                      const int4 *items, int nitems, int *head, int ngroups)
+{
+#define TL_CASE(NN)                                                                                    \
+    case NN:                                                                                           \
+        if (!pol) return launch_queue_N<NN, false, false>(st, jobs, items, nitems, head, ngroups);      \
+        if (hasb) return launch_queue_N<NN, true, true>(st, jobs, items, nitems, head, ngroups);       \
+        return launch_queue_N<NN, true, false>(st, jobs, items, nitems, head, ngroups);
+    switch (order) {
+        TL_CASE(0)
+        TL_CASE(1)
+        TL_CASE(2)
+        TL_CASE(3)
+        TL_CASE(4)
+        TL_CASE(5)
+        TL_CASE(6)
+        TL_CASE(7)
+        TL_CASE(8)
+    default: return hipErrorInvalidValue;
+    }
+#undef TL_CASE
+}
 
 hipError_t launch_legendre_mfma(Plan &p, const void *T, const void *E, const void *B, void *FT, void *FQ, void *FU)
 {

@@ -231,7 +231,22 @@ __global__ __launch_bounds__(256) void k_ring_fft(const FftJob *__restrict__ job
     }
 }
 
+__global__ void k_fill_words(uint32_t *__restrict__ x, size_t n, uint32_t v)
+{
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) x[i] = v;
+}
+
 }  // namespace
+
+// Kernel fill of n 32-bit words (usable inside captured graphs, unlike a
+// memset node).
+hipError_t fill_words(void *x, size_t n, uint32_t v, hipStream_t st)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_words, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, (uint32_t *)x, n, v);
+    return hipGetLastError();
+}
 
 // Allow the ping-pong LDS buffers of this plan's FFT length beyond the
 // default 64 KiB dynamic-LDS limit when the device has more.

@@ -153,6 +153,25 @@ hipError_t cnn_adam(const CnnBufs &c, int step, float lr, hipStream_t st);
 hipError_t cnn_zero(float *x, int64_t n, hipStream_t st);
 hipError_t launch_legendre_mfma(Plan &p, const void *T, const void *E, const void *B, void *FT, void *FQ,
                                 void *FU);
+// One realization's arguments of the matrix-core harmonic kernel.
+struct MfmaJob {
+    int lmax, ntheta, nrp, rbeg, jtab;
+    const double2 *trig;
+    const double *theta;
+    const double4 *coef0;
+    const double *start;
+    const int *exps;
+    const int *mcut;
+    const double2 *almT, *almE, *almB;
+    float2 *FT, *FQ, *FU;
+};
+MfmaJob mfma_job(const Plan &p, const void *T, const void *E, const void *B, void *FT, void *FQ, void *FU);
+int mfma_ring_block();  // ring pairs per work item
+int mfma_m_group();     // consecutive m per m-group
+// items[i] = {job, ring block, first m-group, m-groups}; head: queue counter (zero before the launch)
+hipError_t launch_legendre_mfma_queue(int order, bool pol, bool hasb, hipStream_t st, const MfmaJob *jobs,
+                                      const int4 *items, int nitems, int *head, int ngroups);
+hipError_t fill_words(void *x, size_t n, uint32_t v, hipStream_t st);
 hipError_t launch_fft_jobs(Plan &p, const void *Fbase, void *Dbase, const FftJob *jobs, int njobs,
                            bool fp64);
 // corr (optional, FP32 [3][ntheta][nphi]): added to the Taylor sums before the rotation

@@ -33,7 +33,7 @@ EXPORTS = [
     "tl_deflection", "tl_legendre", "tl_synth_derivs", "tl_remap", "tl_lens_map_batch",
     "tl_lens_map_simple", "tl_lens_map_many", "tl_plan_profile", "tl_plan_stage_times", "tl_last_error", "tl_version",
     "tl_cnn_create", "tl_cnn_destroy", "tl_cnn_get_params", "tl_cnn_set_params", "tl_cnn_forward", "tl_cnn_grad",
-    "tl_cnn_train_step", "tl_lens_map_cnn",
+    "tl_cnn_train_step", "tl_lens_map_cnn", "tl_batch_create", "tl_batch_destroy", "tl_batch_run", "tl_batch_info",
 ]
 CNN_NTRAIN = 15139
 CNN_NPARAM = 15142
@@ -61,6 +61,11 @@ class Options(ctypes.Structure):
     _fields_ = [("order", ctypes.c_int32), ("precision", ctypes.c_int32), ("pol", ctypes.c_int32),
                 ("rotate", ctypes.c_int32), ("naive_pos", ctypes.c_int32), ("batch", ctypes.c_int32),
                 ("workspace_cap", ctypes.c_int64)]
+
+
+class BatchOptions(ctypes.Structure):
+    _fields_ = [("autotune", ctypes.c_int32), ("use_graph", ctypes.c_int32), ("m_groups", ctypes.c_int32),
+                ("groups_per_cu", ctypes.c_int32)]
 
 
 _lib = None
@@ -97,6 +102,10 @@ def lib():
         L.tl_cnn_grad.argtypes = [vp, vp, vp, vp, vp, vp, ctypes.c_int64, vp, vp]
         L.tl_cnn_train_step.argtypes = [vp, vp, vp, vp, vp, vp, ctypes.c_int64, vp, ctypes.c_float, vp]
         L.tl_lens_map_cnn.argtypes = [vp] * 9
+        L.tl_batch_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int32, vp, ctypes.POINTER(BatchOptions)]
+        L.tl_batch_destroy.argtypes = [vp]
+        L.tl_batch_run.argtypes = [vp, vp, vp]
+        L.tl_batch_info.argtypes = [vp, vp, vp, vp, vp]
         L.tl_last_error.restype = ctypes.c_char_p
         L.tl_last_error.argtypes = []
         L.tl_version.restype = ctypes.c_int
@@ -381,6 +390,64 @@ class Cnn:
                                      _ptr(out[1]), _ptr(out[2])))
         self._keep = (T, E, B, P)
         return out
+
+
+class Batch:
+    """Realizations of uneven lmax lensed in one pass (one persistent
+    harmonic launch with a longest-first queue, optional HIP-graph replay,
+    autotuned work-item shape).  plans[i] is realization i's plan (FP32 form;
+    plans may repeat)."""
+
+    def __init__(self, plans: Sequence[Plan], autotune: bool = True, use_graph: bool = True, m_groups: int = 0,
+                 groups_per_cu: int = 0):
+        self.plans = list(plans)
+        harr = (ctypes.c_void_p * len(self.plans))(*[p.handle.value for p in self.plans])
+        opt = BatchOptions(int(autotune), int(use_graph), int(m_groups), int(groups_per_cu))
+        h = ctypes.c_void_p()
+        _check(lib().tl_batch_create(ctypes.byref(h), len(self.plans), ctypes.cast(harr, ctypes.c_void_p),
+                                     ctypes.byref(opt)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().tl_batch_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def outputs(self):
+        return [(p._maps(), p._maps() if p.pol else None, p._maps() if p.pol else None) for p in self.plans]
+
+    def run(self, alms: Sequence[tuple], outs=None):
+        """alms[i] = (T, E, B, phi) device tensors (kept at the same addresses
+        for graph replay); returns outs[i] = (T, Q, U)."""
+        n = len(self.plans)
+        if outs is None:
+            outs = self.outputs()
+        keep = []
+        aarr = (ctypes.c_void_p * (4 * n))()
+        oarr = (ctypes.c_void_p * (3 * n))()
+        for i, (p, a) in enumerate(zip(self.plans, alms)):
+            for q, t in enumerate(a):
+                if t is not None and (t.device != p.device or not t.is_contiguous() or t.dtype != torch.complex128):
+                    raise ValueError("batch inputs must be contiguous complex128 tensors on the plan's device")
+                aarr[4 * i + q] = t.data_ptr() if t is not None else None
+            for q, t in enumerate(outs[i]):
+                oarr[3 * i + q] = t.data_ptr() if t is not None else None
+            keep.append(a)
+        _check(lib().tl_batch_run(self._h, ctypes.cast(aarr, ctypes.c_void_p), ctypes.cast(oarr, ctypes.c_void_p)))
+        self._keep = keep
+        return outs
+
+    def info(self):
+        mg, gc = ctypes.c_int32(), ctypes.c_int32()
+        ms, rp = ctypes.c_double(), ctypes.c_int64()
+        _check(lib().tl_batch_info(self._h, ctypes.byref(mg), ctypes.byref(gc), ctypes.byref(ms), ctypes.byref(rp)))
+        return {"m_groups": mg.value, "groups_per_cu": gc.value, "tuned_ms": ms.value, "graph_replays": rp.value}
 
 
 def lens_map_batch(plans: Sequence[Plan], alms: Sequence[tuple], outs: Sequence[tuple]):

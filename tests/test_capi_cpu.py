@@ -84,3 +84,20 @@ def test_cnn_null_arguments(tl):
     assert L.tl_cnn_train_step(None, None, None, None, None, None, 0, None, ctypes.c_float(1e-3), None) == -1
     assert L.tl_lens_map_cnn(*([None] * 9)) == -1
     assert tl.CNN_NPARAM == 15142 and tl.CNN_NTRAIN == 15139
+
+
+def test_batch_null_arguments(tl):
+    L = tl.lib()
+    h = ctypes.c_void_p()
+    o = tl.BatchOptions(1, 1, 0, 0)
+    assert L.tl_batch_create(None, 1, None, ctypes.byref(o)) == -1
+    assert L.tl_batch_create(ctypes.byref(h), 0, None, ctypes.byref(o)) == -1
+    assert L.tl_batch_create(ctypes.byref(h), 2, None, ctypes.byref(o)) == -1
+    bad = tl.BatchOptions(1, 1, 9, 0)
+    arr = (ctypes.c_void_p * 1)(None)
+    assert L.tl_batch_create(ctypes.byref(h), 1, ctypes.cast(arr, ctypes.c_void_p), ctypes.byref(bad)) == -1
+    assert L.tl_batch_create(ctypes.byref(h), 1, ctypes.cast(arr, ctypes.c_void_p), ctypes.byref(o)) == -1
+    assert h.value is None
+    assert L.tl_batch_destroy(None) == 0
+    assert L.tl_batch_run(None, None, None) == -1
+    assert L.tl_batch_info(None, None, None, None, None) == -1

@@ -1,0 +1,150 @@
+"""Batches of realizations with uneven lmax (marked gpu).
+
+The persistent harmonic launch runs the same per-(ring block, m) arithmetic
+as the grid launch, so a batch must reproduce each realization's own
+tl_lens_map bit for bit, eagerly, through graph replays (with other eager
+work and synchronizations between replays, every replay checked), and for
+every work-item shape the autotuner may pick."""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+from paper_1307_0719_amd import skygen
+from tests.gpu_util import need_gpu
+
+pytestmark = pytest.mark.gpu
+
+LMAXES = [48, 96, 64, 96, 48, 128]
+
+
+@pytest.fixture(scope="module")
+def tl():
+    need_gpu()
+    from paper_1307_0719_amd import taylens
+
+    taylens.lib()
+    return taylens
+
+
+def _plans(tl, lmaxes, pol=True, order=4):
+    by = {}
+    for L in sorted(set(lmaxes)):
+        by[L] = tl.Plan(L, L + 1, 2 * L, order, "fp32", pol=pol)
+    return [by[L] for L in lmaxes], by
+
+
+def _alms(lmaxes, seed0, pol=True, with_b=False):
+    out = []
+    for i, L in enumerate(lmaxes):
+        s = skygen.make_sky(L, seed0 + i, pol=pol, rms_arcmin=60.0)
+        d = lambda a: None if a is None else torch.from_numpy(a).cuda()
+        B = d(skygen.random_alm(L, seed0 + 500 + i, lmin=2) * 0.1) if (pol and with_b) else None
+        out.append((d(s.alm_T), d(s.alm_E) if pol else None, B, d(s.alm_phi)))
+    return out
+
+
+def _single(plans, alms):
+    ref = []
+    for p, a in zip(plans, alms):
+        r = p.lens_map(*a)
+        ref.append(tuple(None if x is None else x.clone() for x in r))
+    torch.cuda.synchronize()
+    return ref
+
+
+def _equal(got, ref):
+    for g, r in zip(got, ref):
+        for x, y in zip(g, r):
+            if y is None:
+                continue
+            assert torch.equal(x, y)
+
+
+@pytest.mark.parametrize("m_groups,gpc", [(1, 1), (2, 2), (4, 1), (3, 8)])
+def test_batch_equals_single_calls(tl, m_groups, gpc):
+    plans, _ = _plans(tl, LMAXES)
+    alms = _alms(LMAXES, 300)
+    ref = _single(plans, alms)
+    b = tl.Batch(plans, autotune=False, use_graph=False, m_groups=m_groups, groups_per_cu=gpc)
+    got = b.run(alms)
+    torch.cuda.synchronize()
+    _equal(got, ref)
+    b.close()
+
+
+def test_batch_with_b_and_temperature_only(tl):
+    plans, _ = _plans(tl, LMAXES[:4])
+    alms = _alms(LMAXES[:4], 310, with_b=True)
+    ref = _single(plans, alms)
+    b = tl.Batch(plans, autotune=False, use_graph=True)
+    _equal(b.run(alms), ref)
+    b.close()
+    plansT, _ = _plans(tl, LMAXES[:3], pol=False, order=3)
+    almsT = _alms(LMAXES[:3], 320, pol=False)
+    refT = _single(plansT, almsT)
+    bT = tl.Batch(plansT, autotune=False, use_graph=False)
+    _equal(bT.run(almsT), refT)
+    bT.close()
+
+
+def test_graph_replays_follow_the_inputs(tl):
+    plans, _ = _plans(tl, LMAXES)
+    alms = _alms(LMAXES, 330)
+    b = tl.Batch(plans, autotune=False, use_graph=True)
+    outs = b.outputs()
+    for rep in range(4):
+        # new values in the same buffers, then eager work of our own between replays
+        fresh = _alms(LMAXES, 400 + 10 * rep)
+        for a, f in zip(alms, fresh):
+            for x, y in zip(a, f):
+                if x is not None:
+                    x.copy_(y)
+        ref = _single(plans, alms)
+        b.run(alms, outs)
+        torch.cuda.synchronize()
+        _equal(outs, ref)
+        _ = plans[0].lens_map(*alms[0])  # unrelated eager call on a batch plan
+        torch.cuda.synchronize()
+    assert b.info()["graph_replays"] == 3
+    b.close()
+
+
+def test_autotune_picks_and_caches_a_shape(tl, tmp_path):
+    os.environ["TAYLENS_TUNE_CACHE"] = str(tmp_path / "tune.txt")
+    try:
+        plans, _ = _plans(tl, LMAXES)
+        alms = _alms(LMAXES, 340)
+        ref = _single(plans, alms)
+        b = tl.Batch(plans, autotune=True, use_graph=True)
+        _equal(b.run(alms), ref)
+        info = b.info()
+        assert info["tuned_ms"] > 0 and info["m_groups"] in (1, 2, 4) and info["groups_per_cu"] in (1, 2, 4)
+        lines = open(tmp_path / "tune.txt").read().split("\n")
+        assert any(ln.split()[1:3] == [str(info["m_groups"]), str(info["groups_per_cu"])] for ln in lines if ln)
+        b.close()
+        b2 = tl.Batch(plans, autotune=True, use_graph=False)
+        _equal(b2.run(alms), ref)
+        i2 = b2.info()
+        assert (i2["m_groups"], i2["groups_per_cu"]) == (info["m_groups"], info["groups_per_cu"])
+        assert i2["tuned_ms"] == pytest.approx(info["tuned_ms"], rel=1e-5)
+        b2.close()
+    finally:
+        del os.environ["TAYLENS_TUNE_CACHE"]
+
+
+def test_batch_refuses_mixed_plans(tl):
+    p32 = tl.Plan(48, 49, 96, 4, "fp32", pol=True)
+    p16 = tl.Plan(48, 49, 96, 4, "fp16", pol=True)
+    p3 = tl.Plan(48, 49, 96, 3, "fp32", pol=True)
+    with pytest.raises(tl.TaylensError):
+        tl.Batch([p32, p16])
+    with pytest.raises(tl.TaylensError):
+        tl.Batch([p32, p3])
+    b = tl.Batch([p32, p32], autotune=False)
+    a = _alms([48, 48], 350, with_b=False)
+    a[1] = (a[1][0], a[1][1], torch.zeros_like(a[1][1]), a[1][3])
+    with pytest.raises(tl.TaylensError):
+        b.run(a)
+    b.close()

@@ -1,0 +1,53 @@
+"""What the trained correction gains over the plain order-2 Taylor sum
+(marked gpu).  The judge of both is the method itself at order 6: the RMS of
+(order 2 + correction - order 6) against that of (order 2 - order 6), over
+every pixel of held-out skies (seeds 20000+, never used in training).
+
+cnn_weights.npy was written by ``python -m paper_1307_0719_amd.train_cnn``
+(200 realizations at lmax 2048, 20 Adam steps of 32768 pixels each); that
+run measured a gain of about 7 at lmax 2048 and about 6 at lmax 4096.  The
+thresholds below leave room for the non-deterministic order of the FP32
+gradient sums of a retraining.  A second test trains from scratch on a
+smaller grid to show the training itself works."""
+import os
+
+import numpy as np
+import pytest
+
+from tests.gpu_util import need_gpu
+
+pytestmark = pytest.mark.gpu
+
+WEIGHTS = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_1307_0719_amd",
+                       "cnn_weights.npy")
+
+
+@pytest.fixture(scope="module")
+def tc():
+    need_gpu()
+    from paper_1307_0719_amd import train_cnn
+
+    return train_cnn
+
+
+@pytest.mark.parametrize("lmax,min_gain", [(2048, 4.0), (4096, 3.5)])
+def test_trained_network_gains_over_order2(tc, lmax, min_gain):
+    params = np.load(WEIGHTS)
+    res = tc.evaluate(params, lmax, lmax + 1, 2 * lmax, [20000])
+    print(lmax, res)
+    for f, g in zip("TQU", res["gain"]):
+        assert g > min_gain, (f, g, res)
+
+
+def test_training_from_scratch_reduces_the_remainder(tc):
+    """12 realizations x 20 steps of the stated configuration (the full run
+    reached a loss of 0.16 after 10 realizations, from about 1)."""
+    lmax = 2048
+    params, info = tc.train(lmax, lmax + 1, 2 * lmax, list(range(10000, 10012)), steps_per_real=20,
+                            batch_pixels=32768, lr=2e-3, lr_end=2e-4)
+    h = info["loss_per_realization"]
+    assert np.mean(h[-3:]) < 0.4 * h[0], h
+    res = tc.evaluate(params, lmax, lmax + 1, 2 * lmax, [20001])
+    print(res)
+    for f, g in zip("TQU", res["gain"]):
+        assert g > 1.5, (f, g, res)
