@@ -148,6 +148,101 @@ def run_form(args, w, order, prec, batch, skies_dev):
             "workspace_bytes": ws, "maps0": first}
 
 
+def bench_batch(args, order=4, n=64):
+    """The uneven-lmax batch: n T+Q/U realizations, lmax drawn from
+    {512, 1024, 2048, 3000} (seeded), grids (lmax+1) x 2 lmax, FP32 form, one
+    tl_batch pass per step (persistent harmonic launch, graph replay,
+    autotuned work items; the first run, which tunes and captures, is part of
+    the warm-up)."""
+    import numpy as np
+    import torch
+
+    from paper_1307_0719_amd import skygen, taylens
+
+    lm = skygen.batch_lmaxes(n, seed=3)
+    dev = torch.device("cuda", 0)
+    plans = {L: taylens.Plan(L, L + 1, 2 * L, order, "fp32", pol=True) for L in sorted(set(lm))}
+    alms = []
+    for i, L in enumerate(lm):
+        s = skygen.make_sky(L, 3000 + i, pol=True)
+        alms.append(tuple(None if a is None else torch.from_numpy(a).to(dev)
+                          for a in (s.alm_T, s.alm_E, None, s.alm_phi)))
+    b = taylens.Batch([plans[L] for L in lm], autotune=True, use_graph=True)
+    outs = b.outputs()
+    for _ in range(max(1, args.warmup)):
+        b.run(alms, outs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        b.run(alms, outs)
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / args.steps
+    info = b.info()
+    npix = sum((L + 1) * 2 * L for L in lm)
+    # MFMA work of the persistent launch (useful columns, elements outside the caps)
+    fl = 0.0
+    for L in lm:
+        q = {k: plans[L].query(k) for k in ("elems", "elems_caps")}
+        fl += (q["elems"] - q["elems_caps"]) * 2 * cols(order, True, False) * 2
+    res = {"realizations": n, "lmax_counts": {str(L): lm.count(L) for L in sorted(set(lm))},
+           "pixels_per_step": npix, "ms_per_step": sec * 1e3, "pixels_per_s": npix / sec,
+           "autotuned_item": {"m_per_item": 8 * info["m_groups"], "workgroups_per_cu": info["groups_per_cu"],
+                              "tuned_harmonic_launch_ms": info["tuned_ms"]},
+           "graph_replays": info["graph_replays"],
+           "persistent_launch_fp32_mfma_tflops": fl / (info["tuned_ms"] * 1e-3) / 1e12 if info["tuned_ms"] else None}
+    b.close()
+    for p in plans.values():
+        p.close()
+    torch.cuda.empty_cache()
+    return res
+
+
+def bench_cnn(args, w):
+    """Order 2 + learned correction at the workload's size (weights shipped
+    with the package), its forward kernel against the BF16 matrix peak, and
+    its error against plain order 6 on one held-out sky."""
+    import numpy as np
+    import torch
+
+    from paper_1307_0719_amd import train_cnn, taylens
+
+    here = os.path.dirname(os.path.abspath(__file__))
+    params = np.load(os.path.join(here, "paper_1307_0719_amd", "cnn_weights.npy"))
+    dev = torch.device("cuda", 0)
+    plan = taylens.Plan(w.lmax, w.ntheta, w.nphi, 2, "fp32", pol=True)
+    net = taylens.Cnn(params)
+    from paper_1307_0719_amd import skygen
+
+    s = skygen.make_sky(w.lmax, w.seed, pol=True)
+    a = tuple(None if x is None else torch.from_numpy(x).to(dev) for x in (s.alm_T, s.alm_E, None, s.alm_phi))
+    outs = (plan._maps(), plan._maps(), plan._maps())
+    for _ in range(args.warmup):
+        net.lens_map(plan, *a, out=outs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        net.lens_map(plan, *a, out=outs)
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / args.steps
+    plan.profile(True)
+    for _ in range(args.steps):
+        net.lens_map(plan, *a, out=outs)
+    st = plan.stage_times()
+    plan.profile(False)
+    cnn_ms = st["cnn"][0] / st["cnn"][1]
+    npix = w.ntheta * w.nphi
+    flops = 2 * 61152 * npix  # MACs per pixel of the three layers (useful, unpadded)
+    net.close()
+    plan.close()
+    torch.cuda.empty_cache()
+    ev = train_cnn.evaluate(params, w.lmax, w.ntheta, w.nphi, [20000])
+    return {"pixels_per_s": npix / sec, "ms_per_map": sec * 1e3, "cnn_forward_ms": cnn_ms,
+            "cnn_forward_bf16_tflops": flops / (cnn_ms * 1e-3) / 1e12,
+            "cnn_forward_mfma_frac": flops / (cnn_ms * 1e-3) / PEAK["f16_mfma"],
+            "rms_err_vs_order6": {"order2": ev["rms_err_order2"], "order2_plus_cnn": ev["rms_err_cnn"],
+                                  "gain": ev["gain"], "held_out_seed": 20000}}
+
+
 def copy_calibration(args):
     """A plain device copy of known size, for scaling the HBM byte counters."""
     import torch
@@ -174,6 +269,8 @@ def main():
     ap.add_argument("--cpu-rings", type=int, default=16, help="output rings in the CPU-oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the oracle (no errors, no cpu_baseline)")
     ap.add_argument("--copy-calibration", action="store_true", help="only run a 1 GiB device copy (counter scale)")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the uneven-lmax batch and the learned-correction measurements")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -330,6 +427,9 @@ def main():
     }
     if cpu is not None:
         res["cpu_baseline"] = cpu
+    if not args.no_extras:
+        res["batch_uneven_lmax"] = bench_batch(args, order)
+        res["learned_correction"] = bench_cnn(args, w)
     print(json.dumps(res))
 
 
