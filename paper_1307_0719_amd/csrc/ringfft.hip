@@ -237,6 +237,179 @@ __global__ void k_fill_words(uint32_t *__restrict__ x, size_t n, uint32_t v)
     if (i < n) x[i] = v;
 }
 
+
+// ---- power-of-two lengths M = 512 .. 4096: radix-16 passes ----
+//
+// In-register inverse DFT of size 16 as 4 x 4: y[k1 + 4 k2] =
+// sum_n2 e^{2 pi i n2 k2/4} [e^{2 pi i n2 k1/16} sum_n1 v[4 n1 + n2] e^{2 pi i n1 k1/4}].
+template <typename V>
+__device__ __forceinline__ void dft16(V *v)
+{
+    using R = decltype(V().x);
+    V a[4][4];
+#pragma unroll
+    for (int n2 = 0; n2 < 4; ++n2) {
+        V t[4] = {v[n2], v[n2 + 4], v[n2 + 8], v[n2 + 12]};
+        dft4(t);
+#pragma unroll
+        for (int k1 = 0; k1 < 4; ++k1) a[n2][k1] = t[k1];
+    }
+    // e^{2 pi i j/16}, j = n2 k1
+    const R c1 = (R)0.92387953251128675612818318939678829, s1 = (R)0.38268343236508977172845998403039887;
+    const R h = (R)0.70710678118654752440084436210484904;
+    auto tw = [&](V x, int j) -> V {
+        switch (j) {
+        case 0: return x;
+        case 1: return cmul(x, cmk<V>(c1, s1));
+        case 2: return cmk<V>(h * (x.x - x.y), h * (x.x + x.y));
+        case 3: return cmul(x, cmk<V>(s1, c1));
+        case 4: return cmuli(x);
+        case 6: return cmk<V>(-h * (x.x + x.y), h * (x.x - x.y));
+        case 9: return cmul(x, cmk<V>(-c1, -s1));
+        default: return x;
+        }
+    };
+#pragma unroll
+    for (int n2 = 1; n2 < 4; ++n2)
+#pragma unroll
+        for (int k1 = 1; k1 < 4; ++k1) a[n2][k1] = tw(a[n2][k1], n2 * k1);
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1) {
+        V t[4] = {a[0][k1], a[1][k1], a[2][k1], a[3][k1]};
+        dft4(t);
+#pragma unroll
+        for (int k2 = 0; k2 < 4; ++k2) v[k1 + 4 * k2] = t[k2];
+    }
+}
+
+template <int RX, typename V>
+__device__ __forceinline__ void dftR(V *v)
+{
+    if constexpr (RX == 2) dft2(v);
+    else if constexpr (RX == 4) dft4(v);
+    else if constexpr (RX == 8) dft8(v);
+    else dft16(v);
+}
+
+// LDS index with one pad slot per 32 entries (breaks the power-of-two
+// strides of the butterfly stores across banks).
+__device__ __forceinline__ int lpad(int i) { return i + (i >> 5); }
+
+// Multiply v[s] by e^{2 pi i kk s / (Ns RX)}, s = 1..RX-1: w = e^{2 pi i kk/(Ns RX)}
+// and w^4 from the table, w^s as a product of at most three of w, w^2, w^3,
+// w^4, w^8 (one rounding per product).
+template <int RX, typename V>
+__device__ __forceinline__ void apply_twiddles(V (&v)[RX], const V *__restrict__ twN, int kk, int tstride)
+{
+    const V w1 = twN[kk * tstride];
+    const V w2 = cmul(w1, w1);
+    const V w3 = cmul(w2, w1);
+    V w4 = w2, w8 = w2;
+    if constexpr (RX >= 8) w4 = twN[4 * kk * tstride];
+    if constexpr (RX >= 16) w8 = cmul(w4, w4);
+#pragma unroll
+    for (int s = 1; s < RX; ++s) {
+        const int lo = s & 3, b4 = (s >> 2) & 1, b8 = s >> 3;
+        V w = lo == 1 ? w1 : (lo == 2 ? w2 : w3);
+        if (lo == 0) w = b4 ? w4 : w8;
+        else {
+            if (b4) w = cmul(w, w4);
+            if (b8) w = cmul(w, w8);
+        }
+        if (lo == 0 && b4 && b8) w = cmul(w4, w8);
+        v[s] = cmul(v[s], w);
+    }
+}
+
+// One in-place Stockham pass (radix RX, stride Ns, powers of two) over the
+// padded LDS buffer: butterfly b, kk = b mod Ns reads buf[b + s M/RX], applies
+// e^{2 pi i kk s/(Ns RX)}, transforms, and writes position
+// (b / Ns) Ns RX + kk + s Ns -- into buf, or into the output ring.
+template <int M, int RX, int Ns, bool TO_GLOBAL, typename V>
+__device__ __forceinline__ void pass_p2(V *__restrict__ buf, V *__restrict__ out, int tid,
+                                        const V *__restrict__ twN)
+{
+    constexpr int nb = M / RX;
+    constexpr int N = 2 * M;
+    constexpr int tstride = N / (Ns * RX);
+    static_assert(nb <= 256, "one butterfly per thread");
+    const bool act = tid < nb;
+    const int b = act ? tid : 0;
+    V v[RX];
+#pragma unroll
+    for (int s = 0; s < RX; ++s) v[s] = buf[lpad(b + s * nb)];
+    if (!TO_GLOBAL) __syncthreads();  // every read before the in-place writes
+    if (act) {
+        const int kk = b & (Ns - 1);
+        if constexpr (Ns > 1) apply_twiddles<RX>(v, twN, kk, tstride);
+        dftR<RX>(v);
+        const int base = (b / Ns) * Ns * RX + kk;
+#pragma unroll
+        for (int s = 0; s < RX; ++s) {
+            if constexpr (TO_GLOBAL) out[base + s * Ns] = v[s];
+            else buf[lpad(base + s * Ns)] = v[s];
+        }
+    }
+}
+
+// Length M = 256 RL (RL = 2, 4, 8, 16): 256 threads; passes 16, 16, RL.  Each
+// thread builds Z at m = t + 256 s from F_m and F_{M-m} (L2-resident across the
+// outputs of the job); e^{2 pi i m/N} = e^{2 pi i t/N} e^{2 pi i 256 s/N}.
+template <typename R, int M>
+__global__ __launch_bounds__(256) void k_ring_fft_p2(const FftJob *__restrict__ jobs,
+                                                     const typename C2<R>::T *__restrict__ Fbase,
+                                                     R *__restrict__ Dbase, int lmax,
+                                                     const typename C2<R>::T *__restrict__ twN)
+{
+    using V = typename C2<R>::T;
+    constexpr int RL = M / 256;
+    static_assert(RL == 2 || RL == 4 || RL == 8 || RL == 16, "power-of-two length 512..4096");
+    extern __shared__ unsigned char smem_raw[];
+    V *buf = reinterpret_cast<V *>(smem_raw);
+    const int tid = threadIdx.x;
+    const FftJob &job = jobs[blockIdx.x];
+    const V *F = Fbase + job.src;
+    const int L = lmax;
+
+    const V tb = twN[tid];
+    for (int q = 0; q < job.nk; ++q) {
+        const int k = job.k[q];
+        const R scale = (R)job.scale[q];
+        // X(m) = scale (i m)^k F_m (0 < m < M); X(0) = Re, X(M) = 2 Re
+        auto coefX = [&](int m, V f) -> V {
+            R sc = scale;
+            const R mf = (R)m;
+            for (int t = 0; t < k; ++t) sc *= mf;
+            R re = sc * f.x, im = sc * f.y;
+            switch (k & 3) {
+            case 1: { const R t2 = re; re = -im; im = t2; } break;
+            case 2: re = -re; im = -im; break;
+            case 3: { const R t2 = re; re = im; im = -t2; } break;
+            default: break;
+            }
+            if (m == 0) return cmk<V>(re, 0);
+            if (m == M) return cmk<V>((R)2 * re, 0);
+            return cmk<V>(re, im);
+        };
+#pragma unroll 4
+        for (int s = 0; s < RL; ++s) {
+            const int m = tid + 256 * s;
+            const int mr = M - m;  // 1..M
+            const V xm = coefX(m, (m <= L) ? F[m] : cmk<V>(0, 0));
+            const V xc = cconj(coefX(mr, (mr <= L) ? F[mr] : cmk<V>(0, 0)));
+            const V tw = cmul(tb, twN[256 * s]);  // e^{2 pi i m/N}
+            buf[lpad(m)] = cadd(cadd(xm, xc), cmuli(cmul(tw, csub(xm, xc))));
+        }
+        __syncthreads();
+        pass_p2<M, 16, 1, false>(buf, (V *)nullptr, tid, twN);
+        __syncthreads();
+        pass_p2<M, 16, 16, false>(buf, (V *)nullptr, tid, twN);
+        __syncthreads();
+        // last pass straight to the output ring: out[2n], out[2n+1] = Re, Im z_n
+        pass_p2<M, RL, 256, true>(buf, reinterpret_cast<V *>(Dbase + job.dst[q]), tid, twN);
+        __syncthreads();
+    }
+}
 }  // namespace
 
 // Kernel fill of n 32-bit words (usable inside captured graphs, unlike a
@@ -250,9 +423,27 @@ hipError_t fill_words(void *x, size_t n, uint32_t v, hipStream_t st)
 
 // Allow the ping-pong LDS buffers of this plan's FFT length beyond the
 // default 64 KiB dynamic-LDS limit when the device has more.
+template <typename R, int M>
+hipError_t prep_p2()
+{
+    using V = typename C2<R>::T;
+    const size_t b = (size_t)(M + M / 32) * sizeof(V);
+    if (b <= 65536) return hipSuccess;
+    return hipFuncSetAttribute(reinterpret_cast<const void *>(&k_ring_fft_p2<R, M>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)b);
+}
+
 hipError_t fft_prepare(Plan &p)
 {
     const size_t M = (size_t)p.nphi / 2;
+    if (M == 4096) {
+        hipError_t e = prep_p2<double, 4096>();
+        if (e == hipSuccess) e = prep_p2<float, 4096>();
+        if (e != hipSuccess) return e;
+    } else if (M == 2048) {
+        hipError_t e = prep_p2<double, 2048>();
+        if (e != hipSuccess) return e;
+    }
     const size_t b64 = 2 * M * sizeof(double2), b32 = 2 * M * sizeof(float2);
     if (b64 > 65536) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_ring_fft<double>),
@@ -267,10 +458,38 @@ hipError_t fft_prepare(Plan &p)
     return hipSuccess;
 }
 
+template <typename R, int M>
+hipError_t launch_p2(Plan &p, const void *Fbase, void *Dbase, const FftJob *jobs, int njobs, const void *tw)
+{
+    using V = typename C2<R>::T;
+    const size_t shm = (size_t)(M + M / 32) * sizeof(V);
+    hipLaunchKernelGGL((k_ring_fft_p2<R, M>), dim3(njobs), dim3(256), shm, p.stream, jobs, (const V *)Fbase,
+                       (R *)Dbase, p.lmax, (const V *)tw);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_p2_R(Plan &p, const void *Fbase, void *Dbase, const FftJob *jobs, int njobs, const void *tw, int M)
+{
+    switch (M) {
+    case 512: return launch_p2<R, 512>(p, Fbase, Dbase, jobs, njobs, tw);
+    case 1024: return launch_p2<R, 1024>(p, Fbase, Dbase, jobs, njobs, tw);
+    case 2048: return launch_p2<R, 2048>(p, Fbase, Dbase, jobs, njobs, tw);
+    case 4096: return launch_p2<R, 4096>(p, Fbase, Dbase, jobs, njobs, tw);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+bool fft_p2(int M) { return M == 512 || M == 1024 || M == 2048 || M == 4096; }
+
 hipError_t launch_fft_jobs(Plan &p, const void *Fbase, void *Dbase, const FftJob *jobs, int njobs, bool fp64)
 {
     if (njobs <= 0) return hipSuccess;
     const int M = p.nphi / 2;
+    if (fft_p2(M)) {
+        if (fp64) return launch_p2_R<double>(p, Fbase, Dbase, jobs, njobs, p.twid64.ptr, M);
+        return launch_p2_R<float>(p, Fbase, Dbase, jobs, njobs, p.twid32.ptr, M);
+    }
     Radices rad;
     rad.n = p.nradix;
     for (int i = 0; i < p.nradix; ++i) rad.r[i] = p.radix[i];

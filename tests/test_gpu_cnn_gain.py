@@ -44,7 +44,7 @@ def test_training_from_scratch_reduces_the_remainder(tc):
     reached a loss of 0.16 after 10 realizations, from about 1)."""
     lmax = 2048
     params, info = tc.train(lmax, lmax + 1, 2 * lmax, list(range(10000, 10012)), steps_per_real=20,
-                            batch_pixels=32768, lr=2e-3, lr_end=2e-4)
+                            batch_pixels=32768, lr=2e-3, lr_end=2e-3)
     h = info["loss_per_realization"]
     assert np.mean(h[-3:]) < 0.4 * h[0], h
     res = tc.evaluate(params, lmax, lmax + 1, 2 * lmax, [20001])
