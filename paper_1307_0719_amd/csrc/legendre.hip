@@ -326,54 +326,127 @@ __device__ __forceinline__ void stage_fill(Stage<NR> &st, int cbase, int lmax, c
 
 // Run one family over l = lmin..lmax, accumulating into accE (l even) and
 // accO (l odd).  rhs pointers and coef are based at (l = 0, m) of the
-// triangular layout.  bsgn multiplies the table's b (spin -2: -1).
-template <int J, int NR>
-__device__ void run_family(int lmin, int lmax, double x, double bsgn, const double (&w)[J + 1][J + 1],
+// triangular layout.  BSGN multiplies the table's b (spin 0: 0, spin +2: +1,
+// spin -2: -1).  The loop walks 64-l chunks staged in LDS; a chunk in which
+// every lane of the wave already has exponent 0 runs without the exponent
+// logic (values stay O(1) from there on), two steps per iteration.
+template <int J, int NR, int BSGN>
+__device__ void run_family(int lmin, int lmax, double x, const double (&w)[J + 1][J + 1],
                            const double4 *__restrict__ coef, const double2 *__restrict__ r0,
                            const double2 *__restrict__ r1, Rec<J> &st, double2 (&accE)[NR][J + 1],
                            double2 (&accO)[NR][J + 1], Stage<NR> &sg)
 {
-    double2 a[NR];
     if (lmin > lmax) return;
+    auto xb = [&](const double4 &cf) -> double {
+        if constexpr (BSGN == 0) return x;
+        else if constexpr (BSGN > 0) return x + cf.y;
+        else return x - cf.y;
+    };
+    auto rhs = [&](double2 (&a)[NR], int q) {
+        a[0] = sg.a[0][q];
+        if constexpr (NR > 1) a[1] = sg.a[1][q];
+    };
     int cb = lmin & ~63;
     stage_fill<NR>(sg, cb, lmax, coef, r0, r1);
-    auto fetch = [&](int l, double4 &cf) {
-        if (l >= cb + 64) {
-            cb = l & ~63;
-            stage_fill<NR>(sg, cb, lmax, coef, r0, r1);
+    if constexpr (J >= 2) {
+        // many derivative orders: the compact loop keeps the register count
+        // (and occupancy) of the larger recursion state low
+        double2 a[NR];
+        auto fetch = [&](int l, double4 &cf) {
+            if (l >= cb + 64) {
+                cb = l & ~63;
+                stage_fill<NR>(sg, cb, lmax, coef, r0, r1);
+            }
+            cf = sg.cf[l - cb];
+            rhs(a, l - cb);
+        };
+        double4 cf;
+        if (st.e == 0) {
+            fetch(lmin, cf);
+            if (lmin & 1) accum<J, NR>(accO, a, st.p1);
+            else accum<J, NR>(accE, a, st.p1);
         }
-        cf = sg.cf[l - cb];
-        a[0] = sg.a[0][l - cb];
-        if constexpr (NR > 1) a[1] = sg.a[1][l - cb];
-    };
-    double4 cf;
-    if (st.e == 0) {
-        fetch(lmin, cf);
-        if (lmin & 1) accum<J, NR>(accO, a, st.p1);
-        else accum<J, NR>(accE, a, st.p1);
+        int l = lmin + 1;
+        if (l <= lmax && (l & 1)) {
+            fetch(l, cf);
+            rec_step<J>(st, cf, xb(cf), w);
+            if (st.e > 0) renorm_down<J>(st);
+            if (st.e == 0) accum<J, NR>(accO, a, st.p1);
+            ++l;
+        }
+        for (; l + 1 <= lmax; l += 2) {
+            fetch(l, cf);
+            rec_step<J>(st, cf, xb(cf), w);
+            if (st.e == 0) accum<J, NR>(accE, a, st.p1);
+            fetch(l + 1, cf);
+            rec_step<J>(st, cf, xb(cf), w);
+            if (st.e == 0) accum<J, NR>(accO, a, st.p1);
+            if (st.e > 0) renorm_down<J>(st);
+        }
+        if (l <= lmax) {
+            fetch(l, cf);
+            rec_step<J>(st, cf, xb(cf), w);
+            if (st.e > 0) renorm_down<J>(st);
+            if (st.e == 0) accum<J, NR>(accE, a, st.p1);
+        }
+        return;
+    }
+    {  // the start value itself (l = lmin)
+        double2 a[NR];
+        rhs(a, lmin - cb);
+        if (st.e == 0) {
+            if (lmin & 1) accum<J, NR>(accO, a, st.p1);
+            else accum<J, NR>(accE, a, st.p1);
+        }
     }
     int l = lmin + 1;
-    if (l <= lmax && (l & 1)) {
-        fetch(l, cf);
-        rec_step<J>(st, cf, x + bsgn * cf.y, w);
-        if (st.e > 0) renorm_down<J>(st);
-        if (st.e == 0) accum<J, NR>(accO, a, st.p1);
-        ++l;
-    }
-    for (; l + 1 <= lmax; l += 2) {
-        fetch(l, cf);
-        rec_step<J>(st, cf, x + bsgn * cf.y, w);
-        if (st.e == 0) accum<J, NR>(accE, a, st.p1);
-        fetch(l + 1, cf);
-        rec_step<J>(st, cf, x + bsgn * cf.y, w);
-        if (st.e == 0) accum<J, NR>(accO, a, st.p1);
-        if (st.e > 0) renorm_down<J>(st);
-    }
-    if (l <= lmax) {
-        fetch(l, cf);
-        rec_step<J>(st, cf, x + bsgn * cf.y, w);
-        if (st.e > 0) renorm_down<J>(st);
-        if (st.e == 0) accum<J, NR>(accE, a, st.p1);
+    while (l <= lmax) {
+        if (l >= cb + 64) {
+            cb += 64;
+            stage_fill<NR>(sg, cb, lmax, coef, r0, r1);
+        }
+        const int end = min(lmax, cb + 63);  // last l of this chunk
+        if (__all(st.e == 0)) {
+            // fast path: align l to even, then (even, odd) pairs
+            auto one = [&](double2 (&A)[NR][J + 1]) {
+                const int q = l - cb;
+                double2 a[NR];
+                const double4 c0 = sg.cf[q];
+                rec_step<J>(st, c0, xb(c0), w);
+                rhs(a, q);
+                accum<J, NR>(A, a, st.p1);
+                ++l;
+            };
+            if ((l & 1) && l <= end) one(accO);
+#pragma unroll 1
+            for (; l + 1 <= end; l += 2) {
+                const int q = l - cb;
+                double2 a[NR];
+                const double4 c0 = sg.cf[q];
+                rec_step<J>(st, c0, xb(c0), w);
+                rhs(a, q);
+                accum<J, NR>(accE, a, st.p1);
+                const double4 c1 = sg.cf[q + 1];
+                rec_step<J>(st, c1, xb(c1), w);
+                rhs(a, q + 1);
+                accum<J, NR>(accO, a, st.p1);
+            }
+            if (l <= end) one(accE);
+        } else {
+#pragma unroll 1
+            for (; l <= end; ++l) {
+                const int q = l - cb;
+                const double4 c0 = sg.cf[q];
+                rec_step<J>(st, c0, xb(c0), w);
+                if (st.e > 0) renorm_down<J>(st);
+                if (st.e == 0) {
+                    double2 a[NR];
+                    rhs(a, q);
+                    if (l & 1) accum<J, NR>(accO, a, st.p1);
+                    else accum<J, NR>(accE, a, st.p1);
+                }
+            }
+        }
     }
 }
 
@@ -449,7 +522,7 @@ __global__ __launch_bounds__(512) void k_legendre_scalar(
 #pragma unroll
     for (int j = 0; j <= J; ++j) accE[0][j] = accO[0][j] = make_double2(0, 0);
     __shared__ Stage<1> sgs[8];
-    run_family<J, 1>(m, lmax, c, 0.0, w, coef0 + base, alm + base, nullptr, st, accE, accO, sgs[wave]);
+    run_family<J, 1, 0>(m, lmax, c, w, coef0 + base, alm + base, nullptr, st, accE, accO, sgs[wave]);
 
     const bool modd = m & 1;
     const size_t plane = (size_t)ntheta * (lmax + 1);
@@ -526,7 +599,7 @@ __global__ __launch_bounds__(512) void k_legendre_spin(
         for (int q = 0; q < NR; ++q)
 #pragma unroll
             for (int j = 0; j <= J; ++j) accE[q][j] = accO[q][j] = make_double2(0, 0);
-        run_family<J, NR>(lmin, lmax, c, 1.0, w, coef2 + base, almE + base, HASB ? almB + base : nullptr,
+        run_family<J, NR, 1>(lmin, lmax, c, w, coef2 + base, almE + base, HASB ? almB + base : nullptr,
                           st, accE, accO, sgs[wave]);
 #pragma unroll
         for (int j = 0; j <= J; ++j) {
@@ -552,7 +625,7 @@ __global__ __launch_bounds__(512) void k_legendre_spin(
         for (int q = 0; q < NR; ++q)
 #pragma unroll
             for (int j = 0; j <= J; ++j) accE[q][j] = accO[q][j] = make_double2(0, 0);
-        run_family<J, NR>(lmin, lmax, c, -1.0, w, coef2 + base, almE + base, HASB ? almB + base : nullptr,
+        run_family<J, NR, -1>(lmin, lmax, c, w, coef2 + base, almE + base, HASB ? almB + base : nullptr,
                           st, accE, accO, sgs[wave]);
 #pragma unroll
         for (int j = 0; j <= J; ++j) {
