@@ -62,7 +62,12 @@ extern "C" {
  *             forms keep hi + lo parts and take hi*hi + hi*lo + lo*hi on the
  *             matrix cores), each call streams the table (up to opt.batch
  *             realizations per pass, tl_lens_map_many); float32 maps.
- *             Orders 0..6.  Tables: about 4 * nrp * lmax^2 bytes (x2 split). */
+ *             Orders 0..6.  Tables: about 4 * nrp * lmax^2 bytes (x2 split).
+ *             With the environment variable TAYLENS_ONTHEFLY=1 at plan
+ *             creation the same forms run without tables: the FP64 recursion
+ *             feeds the 16-bit matrix products directly (up to 4 realizations
+ *             per pass at order 4 with T+E); results agree with the tabulated
+ *             engine to rounding. */
 enum {
     TL_FP64 = 0,
     TL_FP32 = 1,
@@ -86,8 +91,9 @@ typedef struct {
                               (reflected over the poles; pole rings stay geodesic;
                               no rotation).  0: geodesic displacement.             */
     int32_t batch;         /* realizations per harmonic-stage pass for the tabulated
-                              forms (tl_lens_map_many): 0 or 1 = one; at most 5,
-                              fewer for high orders (error if too many).  Must be
+                              forms (tl_lens_map_many): 0 or 1 = one; at most 5
+                              (4 on the fly), fewer for high orders (error if too
+                              many).  Must be
                               0 or 1 for TL_FP64 / TL_FP32.                        */
     int64_t workspace_cap; /* bytes; 0 = no cap.  tl_plan_create fails with
                               TL_ERR_NOMEM if the plan would need more.            */

@@ -170,7 +170,12 @@ Sizes plan_sizes(const Plan &p)
     s.Fphi = 2 * rowc * 16;
     s.alpha = 2 * p.npix() * sizeof(double);
     s.F = (size_t)p.nfield() * (p.order + 1) * rowc * cbytes * (p.tabform() ? p.batch : 1);
-    if (p.tabform()) {
+    if (p.tabform() && !p.tables) {
+        const bool split = p.precision == TL_BF16X3 || p.precision == TL_FP16X2;
+        s.moff = (p.lmax + 2) * sizeof(int64_t);
+        s.rhs = lp_rhs_bytes(p.lmax, split, (int)p.rhs_nb);
+        s.colexp = (size_t)(p.lmax + 1) * 16 * p.rhs_nb * sizeof(float);
+    } else if (p.tabform()) {
         std::vector<int64_t> mo;
         s.tab = tab_bytes(p.lmax, p.ntile, p.precision == TL_BF16X3 || p.precision == TL_FP16X2, mo);
         s.moff = (p.lmax + 2) * sizeof(int64_t);
@@ -183,6 +188,16 @@ Sizes plan_sizes(const Plan &p)
     s.jd = 2 * (size_t)p.ntheta * sizeof(FftJob);
     s.jm = (size_t)p.nfield() * (p.order + 1) * p.ntheta * sizeof(FftJob);
     return s;
+}
+
+// Reduced-precision forms: plan-time lambda tables, unless the environment
+// variable TAYLENS_ONTHEFLY=1 (read at plan creation) selects the on-the-fly
+// recursion (no tables; faster plan creation, less memory, slower per call at
+// lmax 4096).
+bool use_tables()
+{
+    const char *e = getenv("TAYLENS_ONTHEFLY");
+    return !(e && e[0] == '1');
 }
 
 int validate_options(int32_t lmax, tl_grid grid, const tl_options *opt)
@@ -203,9 +218,10 @@ int validate_options(int32_t lmax, tl_grid grid, const tl_options *opt)
     if (opt->naive_pos != 0 && opt->naive_pos != 1) return fail(TL_ERR_INVALID, "naive_pos must be 0 or 1");
     if (opt->batch < 0 || (!tab && opt->batch > 1))
         return fail(TL_ERR_INVALID, "batch must be 0 or 1 for the FP64 / FP32 forms");
-    if (tab && opt->batch > tab_max_batch(opt->order, opt->pol != 0, false))
-        return fail(TL_ERR_INVALID, "batch too large for this order (at most " +
-                                        std::to_string(tab_max_batch(opt->order, opt->pol != 0, false)) + ")");
+    const int bmax = use_tables() ? tab_max_batch(opt->order, opt->pol != 0, false)
+                                  : lp_max_batch(opt->order, opt->pol != 0, false);
+    if (tab && opt->batch > bmax)
+        return fail(TL_ERR_INVALID, "batch too large for this order (at most " + std::to_string(bmax) + ")");
     if (opt->workspace_cap < 0) return fail(TL_ERR_INVALID, "workspace_cap must be >= 0");
     Plan tmp;
     if (!factor_radices(grid.nphi / 2, tmp))
@@ -350,7 +366,7 @@ int run_legendre_many(Plan &p, int n, const void *const *T, const void *const *E
         }
     }
     if (tab) {
-        const int gmax = tab_max_batch(p.order, p.pol != 0, hasb);
+        const int gmax = p.tables ? tab_max_batch(p.order, p.pol != 0, hasb) : lp_max_batch(p.order, p.pol != 0, hasb);
         for (int i0 = 0; i0 < n; i0 += gmax) {
             TabBatch b{};
             b.n = std::min(gmax, n - i0);
@@ -365,10 +381,11 @@ int run_legendre_many(Plan &p, int n, const void *const *T, const void *const *E
             }
             {
                 StageScope sc(p, ST_TAB_RHS);
-                TL_HIP(launch_legendre_tab(p, b, 0), "legendre table right-hand sides");
+                TL_HIP(p.tables ? launch_legendre_tab(p, b, 0) : launch_legendre_lp(p, b, 0),
+                       "legendre right-hand sides");
             }
             StageScope sc(p, ST_TAB_GEMM);
-            TL_HIP(launch_legendre_tab(p, b, 1), "legendre table gemm");
+            TL_HIP(p.tables ? launch_legendre_tab(p, b, 1) : launch_legendre_lp(p, b, 1), "legendre matrix-core stage");
         }
     }
     return TL_OK;
@@ -428,7 +445,7 @@ hipError_t count_work(Plan &p)
         if (r < p.rpole) p.q_elems_caps += n;
     }
     p.q_tab_chunks = p.q_tab_chunk_bytes = 0;
-    if (p.tabform() && p.ntile > 0) {
+    if (p.tabform() && p.tables && p.ntile > 0) {
         const int nspl = (p.precision == TL_BF16X3 || p.precision == TL_FP16X2) ? 2 : 1;
         p.q_tab_chunk_bytes = (int64_t)nspl * 4 * 64 * 16;
         std::vector<int> ks((size_t)(p.lmax + 1) * p.ntile);
@@ -791,7 +808,9 @@ int tl_plan_create(tl_plan *out, int32_t lmax, tl_grid grid, const tl_options *o
     }
     p.batch = opt->batch > 1 ? opt->batch : 1;
     p.ntile = (p.nrp - p.rpole + 31) / 32;
-    if (p.tabform()) p.rhs_nb = tab_rhs_blocks(p.order, p.pol != 0, p.batch);
+    p.tables = p.tabform() && use_tables();
+    if (p.tabform()) p.rhs_nb = p.tables ? tab_rhs_blocks(p.order, p.pol != 0, p.batch)
+                                         : lp_rhs_blocks(p.order, p.pol != 0, p.batch);
 
     Sizes sz = plan_sizes(p);
     if (p.cap > 0 && sz.total() > (size_t)p.cap) {
@@ -848,7 +867,12 @@ int tl_plan_create(tl_plan *out, int32_t lmax, tl_grid grid, const tl_options *o
     e = hipMemsetAsync(p.start.ptr, 0, p.start.bytes, p.stream);
     if (e == hipSuccess) e = hipMemsetAsync(p.exps.ptr, 0, p.exps.bytes, p.stream);
     if (e == hipSuccess) e = launch_tables(p);
-    if (e == hipSuccess && p.tabform() && p.ntile > 0) {
+    if (e == hipSuccess && p.tabform() && !p.tables) {
+        std::vector<int64_t> go;
+        lp_groups(p.lmax, go);
+        e = hipMemcpy(p.moff.ptr, go.data(), go.size() * sizeof(int64_t), hipMemcpyHostToDevice);
+    }
+    if (e == hipSuccess && p.tabform() && p.tables && p.ntile > 0) {
         std::vector<int64_t> mo;
         tab_bytes(p.lmax, p.ntile, p.precision == TL_BF16X3 || p.precision == TL_FP16X2, mo);
         e = hipMemcpy(p.moff.ptr, mo.data(), mo.size() * sizeof(int64_t), hipMemcpyHostToDevice);

@@ -60,6 +60,7 @@ struct Plan {
     int rpole = 0;    // ring pairs kept on the direct FP64 kernel (the polar caps)
     int batch = 1;    // realizations per table-GEMM pass (reduced-precision forms)
     int ntile = 0;    // 32-ring-pair tiles outside the caps (table forms)
+    bool tables = false;  // reduced forms: plan-time tables (else on-the-fly recursion)
     int64_t cap = 0;
     hipStream_t stream = nullptr;
     int device = 0;
@@ -129,6 +130,12 @@ size_t tab_rhs_bytes(int lmax, bool split, int nblocks);
 hipError_t launch_build_tab(Plan &p);
 // part 0: right-hand sides of the batch (k_tab_rhs); part 1: the GEMM
 hipError_t launch_legendre_tab(Plan &p, const TabBatch &b, int part);
+// on-the-fly reduced-precision harmonic kernel (legendre_lp.hip)
+int lp_max_batch(int order, bool pol, bool hasb);
+int lp_rhs_blocks(int order, bool pol, int batch);
+size_t lp_groups(int lmax, std::vector<int64_t> &goff);
+size_t lp_rhs_bytes(int lmax, bool split, int nblocks);
+hipError_t launch_legendre_lp(Plan &p, const TabBatch &b, int part);
 // Stage numbers of the per-kernel profile (one kernel per stage).
 enum Stage { ST_DEFL_LEG = 0, ST_DEFL_FFT, ST_LEG_T, ST_LEG_QU, ST_LEG_MFMA, ST_TAB_RHS, ST_TAB_GEMM, ST_FFT, ST_REMAP, ST_CNN };
 

@@ -80,7 +80,7 @@ def test_tab_lens_map(tl, oracle, precision):
         assert e < MAP_TOL[precision], (f, e)
 
 
-@pytest.mark.parametrize("precision,batch", [("fp16", 3), ("bf16x3", 2), ("fp16", 5)])
+@pytest.mark.parametrize("precision,batch", [("fp16", 3), ("bf16x3", 2), ("fp16", 4), ("bf16", 4)])
 def test_lens_map_many_equals_single_calls(tl, precision, batch):
     lmax, ntheta, nphi, order = 96, 97, 192, 4
     skies = [_sky(lmax, 90 + i) for i in range(batch + 1)]
@@ -108,3 +108,28 @@ def test_tab_TP4096_fp16_sampled(tl, oracle):
     print("fp16 lmax 4096 sampled rel RMS", errs)
     for f, e in errs.items():
         assert e < MAP_TOL["fp16"], (f, e)
+
+
+@pytest.mark.parametrize("precision,batch", [("fp16", 1), ("bf16x3", 2), ("fp16", 4)])
+def test_onthefly_engine_matches_oracle(tl, oracle, precision, batch, monkeypatch):
+    """TAYLENS_ONTHEFLY=1: the same forms without tables, against the oracle
+    (same bars) and against single calls (bit-exact)."""
+    monkeypatch.setenv("TAYLENS_ONTHEFLY", "1")
+    lmax, ntheta, nphi, order = 160, 161, 320, 4
+    skies = [_sky(lmax, 130 + i, rms_pix=1.3, ntheta=ntheta) for i in range(batch)]
+    plan = tl.Plan(lmax, ntheta, nphi, order, precision, pol=True, batch=batch)
+    got = plan.lens_map_many([(s.alm_T, s.alm_E, None, s.alm_phi) for s in skies])
+    torch.cuda.synchronize()
+    s0 = skies[0]
+    ref = oracle.lens_map(lmax, order, ntheta, nphi, s0.alm_T, s0.alm_E, None, s0.alm_phi, nthreads=ORACLE_THREADS)
+    mask = ref["_tie"] > 1e-9
+    errs = {f: rel_rms(t2np(g), ref[f], mask) for f, g in zip("TQU", got[0])}
+    print(precision, batch, "on the fly, map rel RMS", errs)
+    for f, e in errs.items():
+        assert e < MAP_TOL[precision], (f, e)
+    single = tl.Plan(lmax, ntheta, nphi, order, precision, pol=True)
+    for s, g in zip(skies, got):
+        one = single.lens_map(s.alm_T, s.alm_E, None, s.alm_phi)
+        torch.cuda.synchronize()
+        for x, y in zip(one, g):
+            assert torch.equal(x, y)
