@@ -63,9 +63,9 @@ def a3_useful_flops(lmax: int, nrp: int, order: int, pol: bool, hasb: bool):
 
 
 def stage_work(w, order, form, q, hasb, n):
-    """Per-launch algorithmic work of each stage's kernel: (bound, amount,
-    unit, peak).  Harmonic-stage element counts are those below the
-    evanescent cut (plan work counts)."""
+    """Algorithmic work of each stage per step (n realizations, one table
+    pass): (bound, amount, unit, peak).  Harmonic-stage element counts are
+    those below the evanescent cut (plan work counts)."""
     nfield = 3 if w.pol else 1
     ndmap = (order + 1) * (order + 2) // 2
     npix = w.ntheta * w.nphi
@@ -76,17 +76,22 @@ def stage_work(w, order, form, q, hasb, n):
     caps = q["elems"] if fp64 else q["elems_caps"]
     cbytes = 16 if fp64 else 8
     rbytes = 8 if fp64 else 4
+    # with the lensing potential in the table pass, the direct deflection
+    # kernel covers the caps only
+    defl = q["elems_caps"] if q["defl_folded"] else q["elems"]
+    ncol = cols(order, w.pol, hasb) + (2 if q["defl_folded"] else 0)
     out = {
-        "defl_legendre": ("fp64", direct_flops_per_elem(1, False, False) * q["elems"]),
-        "defl_fft": ("hbm", 2 * rowc * 16 + 2 * npix * 8),
-        "legendre_T": ("fp64", direct_flops_per_elem(order, False, False) * caps),
-        "legendre_QU": ("fp64", direct_flops_per_elem(order, True, hasb) * caps),
-        "legendre_mfma": ("fp32_mfma", (q["elems"] - q["elems_caps"]) * 2 * cols(order, w.pol, hasb) * 2),
-        "tab_rhs": ("hbm", n * nlm * 16 * (1 + (2 if hasb else 1) * w.pol)),
+        "defl_legendre": ("fp64", n * direct_flops_per_elem(1, False, False) * defl),
+        "defl_fft": ("hbm", n * (2 * rowc * 16 + 2 * npix * 8)),
+        "legendre_T": ("fp64", n * direct_flops_per_elem(order, False, False) * caps),
+        "legendre_QU": ("fp64", n * direct_flops_per_elem(order, True, hasb) * caps),
+        "legendre_mfma": ("fp32_mfma", n * (q["elems"] - q["elems_caps"]) * 2 * cols(order, w.pol, hasb) * 2),
+        "tab_rhs": ("hbm", n * nlm * 16 * (1 + (2 if hasb else 1) * w.pol + q["defl_folded"])),
         "legendre_tab": ("hbm", q["tab_chunks"] * q["tab_chunk_bytes"]
-                         + n * nfield * (order + 1) * 2 * (w.ntheta // 2 - q["rpole"]) * (w.lmax + 1) * 8),
-        "ring_fft": ("hbm", nfield * (order + 1) * rowc * cbytes + nfield * ndmap * npix * rbytes),
-        "remap": ("hbm", npix * (16 + nfield * 4) + nfield * ndmap * npix * rbytes),
+                         + n * nfield * (order + 1) * 2 * (w.ntheta // 2 - q["rpole"]) * (w.lmax + 1) * 8
+                         + n * q["defl_folded"] * 2 * 2 * (w.ntheta // 2 - q["rpole"]) * (w.lmax + 1) * 16),
+        "ring_fft": ("hbm", n * (nfield * (order + 1) * rowc * cbytes + nfield * ndmap * npix * rbytes)),
+        "remap": ("hbm", n * (npix * (16 + nfield * 4) + nfield * ndmap * npix * rbytes)),
     }
     res = {}
     for k, (res_kind, amount) in out.items():
@@ -94,8 +99,8 @@ def stage_work(w, order, form, q, hasb, n):
         res[k] = (res_kind, float(amount), unit, PEAK[res_kind])
     if tab:
         # the table GEMM also issues f16 MFMA work (useful columns only)
-        res["legendre_tab_mfma"] = ("f16_mfma", float((q["elems"] - q["elems_caps"]) * 2 * n
-                                                     * cols(order, w.pol, hasb) * 2), "TFLOP/s", PEAK["f16_mfma"])
+        res["legendre_tab_mfma"] = ("f16_mfma", float((q["elems"] - q["elems_caps"]) * 2 * n * ncol * 2),
+                                    "TFLOP/s", PEAK["f16_mfma"])
     return res
 
 
@@ -349,6 +354,9 @@ def main():
         leg = sum(r["per_step"].get(k, 0.0) for k in ("legendre_T", "legendre_QU", "legendre_mfma", "tab_rhs",
                                                        "legendre_tab"))
         useful = f[1] * a3_useful_flops(w.lmax, (w.ntheta + 1) // 2, order, w.pol, hasb)
+        if r["q"]["defl_folded"]:
+            # the table pass also synthesizes the deflection's two rows (order 1 of phi)
+            useful += f[1] * a3_useful_flops(w.lmax, (w.ntheta + 1) // 2, 1, False, False)
         tabform = f[0] in ("bf16x3", "fp16x2", "fp16", "bf16")
         pk = PEAK["f16_mfma"] if tabform else (PEAK["fp32_mfma"] if f[0] == "fp32" else PEAK["fp64"])
         ent = {
@@ -370,15 +378,18 @@ def main():
     kind, amount, unit, peak = work[dom]
     from paper_1307_0719_amd import taylens
 
-    avg = H["avg_launch"][dom] * 1e-3
+    # achieved = the stage's work per step over its kernel time per step
+    # (HIP events around every launch); work_per_launch is the mean share of
+    # one launch (the direct kernels take up to four realizations a launch)
+    t = H["per_step"][dom] * 1e-3
     scale = 1e9 if unit == "GB/s" else 1e12
-    # per launch: the deflection, FFT and remap kernels run once per realization
+    nl = H["launches"][dom]
     roof = {
         "kernel": taylens.STAGE_KERNELS[dom], "stage": dom,
         "bound": "hbm" if kind == "hbm" else ("alu" if kind == "fp64" else "mfma"),
-        "achieved": amount / avg / scale,
-        "peak": peak / scale, "unit": unit, "frac": amount / avg / peak, "traffic": None,
-        "work_per_launch": amount, "avg_launch_ms": avg * 1e3, "launches_per_step": H["launches"][dom],
+        "achieved": amount / t / scale,
+        "peak": peak / scale, "unit": unit, "frac": amount / t / peak, "traffic": None,
+        "work_per_launch": amount / nl, "avg_launch_ms": H["avg_launch"][dom], "launches_per_step": nl,
         "peak_note": "FP64 vector peak (ALU-bound recursion)" if kind == "fp64" else None,
     }
     other = {}
@@ -386,12 +397,13 @@ def main():
         if k in work:
             kk, am, un, pk = work[k]
             sc = 1e9 if un == "GB/s" else 1e12
-            a = H["avg_launch"][k] * 1e-3
+            a = H["per_step"][k] * 1e-3
             other[k] = {"kernel": taylens.STAGE_KERNELS[k], "resource": kk, "achieved": am / a / sc, "unit": un,
-                        "frac": am / a / pk, "avg_launch_ms": a * 1e3, "ms_per_step": H["per_step"][k]}
+                        "frac": am / a / pk, "avg_launch_ms": H["avg_launch"][k], "ms_per_step": H["per_step"][k],
+                        "launches_per_step": H["launches"][k]}
     if "legendre_tab" in H["per_step"]:
         kk, am, un, pk = work["legendre_tab_mfma"]
-        a = H["avg_launch"]["legendre_tab"] * 1e-3
+        a = H["per_step"]["legendre_tab"] * 1e-3
         other["legendre_tab"]["mfma_f16_achieved_tflops"] = am / a / 1e12
         other["legendre_tab"]["mfma_f16_frac"] = am / a / pk
 

@@ -124,12 +124,18 @@ int tl_plan_workspace_bytes(tl_plan plan, int64_t *bytes);
  *   TL_Q_TAB_CHUNKS  (m, 32-ring tile, 32-l chunk) table blocks the table
  *                    GEMM streams per pass (tabulated forms; 0 otherwise)
  *   TL_Q_TAB_CHUNK_BYTES  bytes of one such block (both tables, hi and lo)
+ *   TL_Q_DEFL_FOLDED 1 when the table GEMM also carries the lensing
+ *                    potential (tl_lens_map / tl_lens_map_many with alm_phi
+ *                    given: the deflection's harmonic sums outside the caps
+ *                    come from the same pass, the caps from the direct FP64
+ *                    kernel), else 0
  * Returns TL_ERR_INVALID for an unknown key or a NULL value pointer. */
 #define TL_Q_RPOLE 0
 #define TL_Q_ELEMS 1
 #define TL_Q_ELEMS_CAPS 2
 #define TL_Q_TAB_CHUNKS 3
 #define TL_Q_TAB_CHUNK_BYTES 4
+#define TL_Q_DEFL_FOLDED 5
 int tl_plan_query(tl_plan plan, int32_t key, int64_t *value);
 
 /* Lens one realization (the full method, eqs. 1, 2, 5):

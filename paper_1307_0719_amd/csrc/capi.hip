@@ -167,7 +167,7 @@ Sizes plan_sizes(const Plan &p)
     s.start = 3 * (size_t)(p.lmax + 1) * p.jtab * p.nrp * sizeof(double);
     s.exps = 3 * (size_t)(p.lmax + 1) * p.nrp * sizeof(int);
     s.mcut = (size_t)p.nrp * sizeof(int);
-    s.Fphi = 2 * rowc * 16;
+    s.Fphi = 2 * rowc * 16 * (p.tabform() ? p.batch : 1);
     s.alpha = 2 * p.npix() * sizeof(double);
     s.F = (size_t)p.nfield() * (p.order + 1) * rowc * cbytes * (p.tabform() ? p.batch : 1);
     if (p.tabform() && !p.tables) {
@@ -318,25 +318,76 @@ int check_plan(tl_plan plan)
     return TL_OK;
 }
 
-// deflection into plan.alpha (zeros when alm_phi is NULL)
-int run_deflection(Plan &p, const void *alm_phi)
+void *fphi_slot(Plan &p, int q) { return (char *)p.Fphi.ptr + (size_t)q * 2 * p.ntheta * (p.lmax + 1) * 16; }
+
+// lam / lam' sums of the lensing potentials P[0..n) (NULL entries skipped)
+// into fphi_slot(q) on ring pairs [0, rend); realizations share the FP64
+// recursion, several per launch.
+int defl_legendre(Plan &p, int n, const void *const *P, int rend)
+{
+    const int mx = direct_max(1, false, false, true);
+    DirectSet set{};
+    auto flush = [&]() -> int {
+        if (!set.n) return TL_OK;
+        StageScope sc(p, ST_DEFL_LEG);
+        TL_HIP(launch_legendre_scalar_set(p, 1, rend, set, true), "deflection legendre");
+        set = DirectSet{};
+        return TL_OK;
+    };
+    for (int q = 0; q < n; ++q) {
+        if (!P[q]) continue;
+        set.a[set.n] = (const double2 *)P[q];
+        set.F[set.n] = fphi_slot(p, q);
+        if (++set.n == mx) {
+            int rc = flush();
+            if (rc) return rc;
+        }
+    }
+    return flush();
+}
+
+// Deflection of realization q into plan.alpha from fphi_slot(q) (zeros when
+// its alm_phi is NULL).
+int defl_fft(Plan &p, const void *alm_phi, int q)
 {
     if (!alm_phi) {
         TL_HIP(fill_words(p.alpha.ptr, p.alpha.bytes / 4, 0u, p.stream), "alpha clear");
         return TL_OK;
     }
-    {
-        StageScope sc(p, ST_DEFL_LEG);
-        TL_HIP(launch_legendre_scalar(p, 1, p.nrp, alm_phi, p.Fphi.ptr, true), "deflection legendre");
-    }
     StageScope sc(p, ST_DEFL_FFT);
-    TL_HIP(launch_fft_jobs(p, p.Fphi.ptr, p.alpha.ptr, (const FftJob *)p.jobsDefl.ptr, p.njobsDefl, true),
+    TL_HIP(launch_fft_jobs(p, fphi_slot(p, q), p.alpha.ptr, (const FftJob *)p.jobsDefl.ptr, p.njobsDefl, true),
            "deflection fft");
     return TL_OK;
 }
 
+// Deflection of one realization into plan.alpha (zeros when alm_phi is NULL).
+int run_deflection(Plan &p, const void *alm_phi)
+{
+    const void *P[1] = {alm_phi};
+    int rc = defl_legendre(p, 1, P, p.nrp);
+    return rc ? rc : defl_fft(p, alm_phi, 0);
+}
+
+// The split table forms take the lensing potential into their pass (two
+// more right-hand-side columns per realization) when every realization has
+// one.  The single-table FP16 / BF16 forms keep the FP64 deflection: their
+// 16-bit lam rounding (relative 2^-12 per term) would reach the positions,
+// and a displacement of the order of a pixel turns it into map errors
+// against the steep gradients of the band-limited fields.
+bool fold_deflection(const Plan &p, int n, const void *const *P)
+{
+    if (!(p.tables && p.ntile > 0) || !P) return false;
+    if (p.precision != TL_BF16X3 && p.precision != TL_FP16X2) return false;
+    for (int i = 0; i < n; ++i)
+        if (!P[i]) return false;
+    return true;
+}
+
+// Harmonic stage of n realizations (n <= plan batch for the table forms).
+// P (optional): their lensing potentials; when fold_deflection() holds, the
+// lam / lam' sums of phi outside the caps go to fphi_slot(q).
 int run_legendre_many(Plan &p, int n, const void *const *T, const void *const *E, const void *const *B,
-                      void *const *Fout)
+                      void *const *Fout, const void *const *P = nullptr)
 {
     const size_t rowc = (size_t)p.ntheta * (p.lmax + 1) * (p.order + 1);
     const size_t cb = p.fp64() ? 16 : 8;
@@ -347,17 +398,32 @@ int run_legendre_many(Plan &p, int n, const void *const *T, const void *const *E
     const bool mfma = p.precision == TL_FP32 && mfma_supported(p.order, hasb);
     const bool tab = p.tabform() && p.ntile > 0;
     const int rend = (mfma || tab) ? p.rpole : p.nrp;
+    // direct kernels: several realizations per launch share the recursion
+    for (int i0 = 0, mx = direct_max(p.order, false, false, p.fp64()); i0 < n; i0 += mx) {
+        DirectSet set{};
+        set.n = std::min(mx, n - i0);
+        for (int q = 0; q < set.n; ++q) {
+            set.a[q] = (const double2 *)T[i0 + q];
+            set.F[q] = Fout[i0 + q];
+        }
+        StageScope sc(p, ST_LEG_T);
+        TL_HIP(launch_legendre_scalar_set(p, p.order, rend, set, p.fp64()), "legendre T");
+    }
+    for (int i0 = 0, mx = direct_max(p.order, true, hasb, p.fp64()); p.pol && i0 < n; i0 += mx) {
+        DirectSet set{};
+        set.n = std::min(mx, n - i0);
+        for (int q = 0; q < set.n; ++q) {
+            char *F = (char *)Fout[i0 + q];
+            set.a[q] = (const double2 *)E[i0 + q];
+            set.b[q] = hasb ? (const double2 *)B[i0 + q] : nullptr;
+            set.F[q] = F + rowc * cb;
+            set.G[q] = F + 2 * rowc * cb;
+        }
+        StageScope sc(p, ST_LEG_QU);
+        TL_HIP(launch_legendre_spin_set(p, p.order, rend, set, p.fp64()), "legendre QU");
+    }
     for (int i = 0; i < n; ++i) {
         char *F = (char *)Fout[i];
-        {
-            StageScope sc(p, ST_LEG_T);
-            TL_HIP(launch_legendre_scalar(p, p.order, rend, T[i], F, p.fp64()), "legendre T");
-        }
-        if (p.pol) {
-            StageScope sc(p, ST_LEG_QU);
-            TL_HIP(launch_legendre_spin(p, p.order, rend, E[i], B[i], F + rowc * cb, F + 2 * rowc * cb, p.fp64()),
-                   "legendre QU");
-        }
         if (mfma) {
             StageScope sc(p, ST_LEG_MFMA);
             TL_HIP(launch_legendre_mfma(p, T[i], E[i], B[i], F, p.pol ? F + rowc * cb : nullptr,
@@ -378,6 +444,10 @@ int run_legendre_many(Plan &p, int n, const void *const *T, const void *const *E
                 b.FT[q] = (float2 *)F;
                 b.FQ[q] = (float2 *)(F + rowc * cb);
                 b.FU[q] = (float2 *)(F + 2 * rowc * cb);
+                if (fold_deflection(p, n, P)) {
+                    b.P[q] = (const double2 *)P[i0 + q];
+                    b.FP[q] = (double2 *)fphi_slot(p, i0 + q);
+                }
             }
             {
                 StageScope sc(p, ST_TAB_RHS);
@@ -943,6 +1013,11 @@ int tl_plan_query(tl_plan plan, int32_t key, int64_t *value)
     case TL_Q_ELEMS_CAPS: *value = p.q_elems_caps; return TL_OK;
     case TL_Q_TAB_CHUNKS: *value = p.q_tab_chunks; return TL_OK;
     case TL_Q_TAB_CHUNK_BYTES: *value = p.q_tab_chunk_bytes; return TL_OK;
+    case TL_Q_DEFL_FOLDED: {
+        const void *one[1] = {&p};  // any non-NULL potential
+        *value = fold_deflection(p, 1, one) ? 1 : 0;
+        return TL_OK;
+    }
     default: return fail(TL_ERR_INVALID, "unknown query key " + std::to_string(key));
     }
 }
@@ -1013,8 +1088,19 @@ int tl_lens_map(tl_plan plan, const void *alm_T, const void *alm_E, const void *
     if (rc) return rc;
     if ((rc = check_outputs(p, T_out, Q_out, U_out))) return rc;
     if ((rc = set_device_of(p))) return rc;
-    if ((rc = run_deflection(p, alm_phi))) return rc;
-    if ((rc = run_derivs(p, alm_T, alm_E, alm_B, p.D.ptr))) return rc;
+    if (fold_deflection(p, 1, &alm_phi)) {
+        const void *Ts[1] = {alm_T}, *Es[1] = {alm_E}, *Bs[1] = {alm_B}, *Ps[1] = {alm_phi};
+        void *Fs[1] = {p.F.ptr};
+        if ((rc = run_legendre_many(p, 1, Ts, Es, Bs, Fs, Ps))) return rc;
+        if ((rc = defl_legendre(p, 1, Ps, p.rpole))) return rc;
+        if ((rc = defl_fft(p, alm_phi, 0))) return rc;
+        StageScope sc(p, ST_FFT);
+        TL_HIP(launch_fft_jobs(p, p.F.ptr, p.D.ptr, (const FftJob *)p.jobsMain.ptr, p.njobsMain, p.fp64()),
+               "ring fft");
+    } else {
+        if ((rc = run_deflection(p, alm_phi))) return rc;
+        if ((rc = run_derivs(p, alm_T, alm_E, alm_B, p.D.ptr))) return rc;
+    }
     const double *at = (const double *)p.alpha.ptr;
     StageScope sc(p, ST_REMAP);
     TL_HIP(launch_remap(p, p.D.ptr, at, at + p.npix(), nullptr, nullptr, T_out, Q_out, U_out), "remap");
@@ -1079,17 +1165,23 @@ int tl_lens_map_many(tl_plan plan, int32_t n, const void *const *alms, void *con
     const int g = p.tabform() ? p.batch : 1;
     for (int i0 = 0; i0 < n; i0 += g) {
         const int k = std::min(g, n - i0);
-        const void *T[kTabMaxBatch], *E[kTabMaxBatch], *B[kTabMaxBatch];
+        const void *T[kTabMaxBatch], *E[kTabMaxBatch], *B[kTabMaxBatch], *P[kTabMaxBatch];
         void *F[kTabMaxBatch];
         for (int q = 0; q < k; ++q) {
             T[q] = alms[4 * (i0 + q)];
             E[q] = alms[4 * (i0 + q) + 1];
             B[q] = alms[4 * (i0 + q) + 2];
+            P[q] = alms[4 * (i0 + q) + 3];
             F[q] = (char *)p.F.ptr + q * rowbytes;
         }
-        if ((rc = run_legendre_many(p, k, T, E, B, F))) return rc;
+        const bool fold = fold_deflection(p, k, P);
+        if ((rc = run_legendre_many(p, k, T, E, B, F, P))) return rc;
+        // deflection sums of the whole group (outside the caps from the
+        // table pass when folded), then per realization: deflection FFT,
+        // ring FFTs, remap
+        if ((rc = defl_legendre(p, k, P, fold ? p.rpole : p.nrp))) return rc;
         for (int q = 0; q < k; ++q) {
-            if ((rc = run_deflection(p, alms[4 * (i0 + q) + 3]))) return rc;
+            if ((rc = defl_fft(p, P[q], q))) return rc;
             {
                 StageScope sc(p, ST_FFT);
                 TL_HIP(launch_fft_jobs(p, F[q], p.D.ptr, (const FftJob *)p.jobsMain.ptr, p.njobsMain, p.fp64()),

@@ -25,6 +25,8 @@
 //    with an integer e per lane and family; e > 0 means "below 2^-256, not
 //    accumulated"; the start values at l = max(m, |s|) come from a plan-time
 //    table built by an m-recursion with the same scaling.
+#include <type_traits>
+
 #include "tl_internal.h"
 
 namespace tl {
@@ -288,14 +290,6 @@ __device__ __forceinline__ void accum(double2 (&acc)[NR][J + 1], const double2 (
         }
 }
 
-template <int NR>
-__device__ __forceinline__ void load_rhs(double2 (&a)[NR], const double2 *__restrict__ r0,
-                                         const double2 *__restrict__ r1, int l)
-{
-    a[0] = r0[l];
-    if constexpr (NR > 1) a[1] = r1[l];
-}
-
 // Per-wave LDS staging of the recursion coefficients and right-hand sides:
 // chunk k holds l in [64k, 64k + 64); lane q loads entry q with a vector
 // load, the recursion then reads the chunk by broadcast.  Only the owning
@@ -308,7 +302,7 @@ struct Stage {
 
 template <int NR>
 __device__ __forceinline__ void stage_fill(Stage<NR> &st, int cbase, int lmax, const double4 *__restrict__ coef,
-                                           const double2 *__restrict__ r0, const double2 *__restrict__ r1)
+                                           const double2 *const (&rr)[NR])
 {
     const int q = threadIdx.x & 63;
     const int l = cbase + q;
@@ -316,8 +310,8 @@ __device__ __forceinline__ void stage_fill(Stage<NR> &st, int cbase, int lmax, c
     __builtin_amdgcn_wave_barrier();
     if (l <= lmax) {
         st.cf[q] = coef[l];
-        st.a[0][q] = r0[l];
-        if constexpr (NR > 1) st.a[1][q] = r1[l];
+#pragma unroll
+        for (int k = 0; k < NR; ++k) st.a[k][q] = rr[k][l];
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -325,16 +319,16 @@ __device__ __forceinline__ void stage_fill(Stage<NR> &st, int cbase, int lmax, c
 }
 
 // Run one family over l = lmin..lmax, accumulating into accE (l even) and
-// accO (l odd).  rhs pointers and coef are based at (l = 0, m) of the
+// accO (l odd) for NR right-hand sides rr (realizations sharing the
+// recursion).  rhs pointers and coef are based at (l = 0, m) of the
 // triangular layout.  BSGN multiplies the table's b (spin 0: 0, spin +2: +1,
 // spin -2: -1).  The loop walks 64-l chunks staged in LDS; a chunk in which
 // every lane of the wave already has exponent 0 runs without the exponent
 // logic (values stay O(1) from there on), two steps per iteration.
 template <int J, int NR, int BSGN>
 __device__ void run_family(int lmin, int lmax, double x, const double (&w)[J + 1][J + 1],
-                           const double4 *__restrict__ coef, const double2 *__restrict__ r0,
-                           const double2 *__restrict__ r1, Rec<J> &st, double2 (&accE)[NR][J + 1],
-                           double2 (&accO)[NR][J + 1], Stage<NR> &sg)
+                           const double4 *__restrict__ coef, const double2 *const (&rr)[NR], Rec<J> &st,
+                           double2 (&accE)[NR][J + 1], double2 (&accO)[NR][J + 1], Stage<NR> &sg)
 {
     if (lmin > lmax) return;
     auto xb = [&](const double4 &cf) -> double {
@@ -343,11 +337,11 @@ __device__ void run_family(int lmin, int lmax, double x, const double (&w)[J + 1
         else return x - cf.y;
     };
     auto rhs = [&](double2 (&a)[NR], int q) {
-        a[0] = sg.a[0][q];
-        if constexpr (NR > 1) a[1] = sg.a[1][q];
+#pragma unroll
+        for (int k = 0; k < NR; ++k) a[k] = sg.a[k][q];
     };
     int cb = lmin & ~63;
-    stage_fill<NR>(sg, cb, lmax, coef, r0, r1);
+    stage_fill<NR>(sg, cb, lmax, coef, rr);
     if constexpr (J >= 2) {
         // many derivative orders: the compact loop keeps the register count
         // (and occupancy) of the larger recursion state low
@@ -355,7 +349,7 @@ __device__ void run_family(int lmin, int lmax, double x, const double (&w)[J + 1
         auto fetch = [&](int l, double4 &cf) {
             if (l >= cb + 64) {
                 cb = l & ~63;
-                stage_fill<NR>(sg, cb, lmax, coef, r0, r1);
+                stage_fill<NR>(sg, cb, lmax, coef, rr);
             }
             cf = sg.cf[l - cb];
             rhs(a, l - cb);
@@ -403,7 +397,7 @@ __device__ void run_family(int lmin, int lmax, double x, const double (&w)[J + 1
     while (l <= lmax) {
         if (l >= cb + 64) {
             cb += 64;
-            stage_fill<NR>(sg, cb, lmax, coef, r0, r1);
+            stage_fill<NR>(sg, cb, lmax, coef, rr);
         }
         const int end = min(lmax, cb + 63);  // last l of this chunk
         if (__all(st.e == 0)) {
@@ -486,12 +480,13 @@ __device__ __forceinline__ void store_c<float>(float *F, size_t idx, double2 v)
     reinterpret_cast<float2 *>(F)[idx] = make_float2((float)v.x, (float)v.y);
 }
 
-// Scalar field: F[j][ring][m] = sum_l a_lm d^j lambda_lm(theta_ring).
-template <int J, typename FT>
+// Scalar field, NB realizations sharing the recursion:
+//     F_q[j][ring][m] = sum_l a^q_lm d^j lambda_lm(theta_ring).
+template <int J, int NB, typename FT>
 __global__ __launch_bounds__(512) void k_legendre_scalar(
     int lmax, int ntheta, int nrp, int rend, int jtab, const double2 *__restrict__ trig,
     const double4 *__restrict__ coef0, const double *__restrict__ start, const int *__restrict__ exps,
-    const int *__restrict__ mcut, const double2 *__restrict__ alm, FT *__restrict__ F)
+    const int *__restrict__ mcut, const DirectSet set)
 {
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int m = blockIdx.y * 8 + wave;
@@ -500,15 +495,17 @@ __global__ __launch_bounds__(512) void k_legendre_scalar(
     const bool live = r0 < rend;
     const bool active = live && m <= mcut[r0];
     const int r = live ? r0 : 0;  // idle lanes still help fill the LDS chunks
+    const size_t plane = (size_t)ntheta * (lmax + 1);
+    const int rs = ntheta - 1 - r;
     if (!__any(active)) {          // evanescent for the whole wave: zeros
-        if (live) {
-            const size_t plane = (size_t)ntheta * (lmax + 1);
-            const int rs = ntheta - 1 - r;
-            for (int j = 0; j <= J; ++j) {
-                store_c<FT>(F, j * plane + (size_t)r * (lmax + 1) + m, make_double2(0, 0));
-                store_c<FT>(F, j * plane + (size_t)rs * (lmax + 1) + m, make_double2(0, 0));
+        if (live)
+            for (int q = 0; q < NB; ++q) {
+                FT *F = (FT *)set.F[q];
+                for (int j = 0; j <= J; ++j) {
+                    store_c<FT>(F, j * plane + (size_t)r * (lmax + 1) + m, make_double2(0, 0));
+                    store_c<FT>(F, j * plane + (size_t)rs * (lmax + 1) + m, make_double2(0, 0));
+                }
             }
-        }
         return;
     }
     const double c = trig[r].x, s = trig[r].y;
@@ -518,26 +515,33 @@ __global__ __launch_bounds__(512) void k_legendre_scalar(
 
     Rec<J> st;
     load_start<J>(st, start, exps, 0, m, lmax, jtab, nrp, r);
-    double2 accE[1][J + 1], accO[1][J + 1];
+    double2 accE[NB][J + 1], accO[NB][J + 1];
+    const double2 *rr[NB];
 #pragma unroll
-    for (int j = 0; j <= J; ++j) accE[0][j] = accO[0][j] = make_double2(0, 0);
-    __shared__ Stage<1> sgs[8];
-    run_family<J, 1, 0>(m, lmax, c, w, coef0 + base, alm + base, nullptr, st, accE, accO, sgs[wave]);
+    for (int q = 0; q < NB; ++q) {
+        rr[q] = set.a[q] + base;
+#pragma unroll
+        for (int j = 0; j <= J; ++j) accE[q][j] = accO[q][j] = make_double2(0, 0);
+    }
+    __shared__ Stage<NB> sgs[8];
+    run_family<J, NB, 0>(m, lmax, c, w, coef0 + base, rr, st, accE, accO, sgs[wave]);
 
     const bool modd = m & 1;
-    const size_t plane = (size_t)ntheta * (lmax + 1);
-    const int rs = ntheta - 1 - r;
     if (!live) return;
 #pragma unroll
-    for (int j = 0; j <= J; ++j) {
-        double2 ev = modd ? accO[0][j] : accE[0][j];  // l + m even
-        double2 od = modd ? accE[0][j] : accO[0][j];
-        if (!active) ev = od = make_double2(0, 0);
-        store_c<FT>(F, j * plane + (size_t)r * (lmax + 1) + m, make_double2(ev.x + od.x, ev.y + od.y));
-        if (rs != r) {
-            const double sg = (j & 1) ? -1.0 : 1.0;
-            store_c<FT>(F, j * plane + (size_t)rs * (lmax + 1) + m,
-                        make_double2(sg * (ev.x - od.x), sg * (ev.y - od.y)));
+    for (int q = 0; q < NB; ++q) {
+        FT *F = (FT *)set.F[q];
+#pragma unroll
+        for (int j = 0; j <= J; ++j) {
+            double2 ev = modd ? accO[q][j] : accE[q][j];  // l + m even
+            double2 od = modd ? accE[q][j] : accO[q][j];
+            if (!active) ev = od = make_double2(0, 0);
+            store_c<FT>(F, j * plane + (size_t)r * (lmax + 1) + m, make_double2(ev.x + od.x, ev.y + od.y));
+            if (rs != r) {
+                const double sg = (j & 1) ? -1.0 : 1.0;
+                store_c<FT>(F, j * plane + (size_t)rs * (lmax + 1) + m,
+                            make_double2(sg * (ev.x - od.x), sg * (ev.y - od.y)));
+            }
         }
     }
 }
@@ -548,19 +552,37 @@ __device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_doub
 __device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
 __device__ __forceinline__ double2 cscale(double2 a, double s) { return make_double2(a.x * s, a.y * s); }
 
-// Spin-2 field from E (and B): FQ/FU[j][ring][m] = Fourier coefficients of
-// d^j Q and d^j U with
+template <typename FT>
+__device__ __forceinline__ double2 load_c(const FT *F, size_t idx);
+template <>
+__device__ __forceinline__ double2 load_c<double>(const double *F, size_t idx)
+{
+    return reinterpret_cast<const double2 *>(F)[idx];
+}
+template <>
+__device__ __forceinline__ double2 load_c<float>(const float *F, size_t idx)
+{
+    const float2 v = reinterpret_cast<const float2 *>(F)[idx];
+    return make_double2(v.x, v.y);
+}
+
+// Spin-2 field from E (and B), NB realizations sharing the recursion:
+// FQ/FU[j][ring][m] = Fourier coefficients of d^j Q and d^j U with
 //   P_m = -sum (E + iB) 2lam,  M_m = -sum (E - iB) (-2)lam,
 //   Q_m = (P_m + M_m)/2,       U_m = (P_m - M_m)/(2i),
 // and, at the south ring, 2lam^{(j)}(pi - t) = (-1)^{l+m+j} (-2)lam^{(j)}(t).
-template <int J, bool HASB, typename FT>
+// The spin +2 family gives P north and M south, the spin -2 family M north
+// and P south: the first family stores its halves of Q and U, the second
+// adds its halves (the lane re-reads its own stores), so no realization's
+// results wait in registers for the other family.
+template <int J, bool HASB, int NB, typename FT>
 __global__ __launch_bounds__(512) void k_legendre_spin(
     int lmax, int ntheta, int nrp, int rend, int jtab, const double2 *__restrict__ trig,
     const double4 *__restrict__ coef2, const double *__restrict__ start, const int *__restrict__ exps,
-    const int *__restrict__ mcut, const double2 *__restrict__ almE, const double2 *__restrict__ almB,
-    FT *__restrict__ FQ, FT *__restrict__ FU)
+    const int *__restrict__ mcut, const DirectSet set)
 {
-    constexpr int NR = HASB ? 2 : 1;
+    constexpr int PER = HASB ? 2 : 1;  // right-hand sides per realization
+    constexpr int NR = NB * PER;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int m = blockIdx.y * 8 + wave;
     const int r0 = blockIdx.x * 64 + (threadIdx.x & 63);
@@ -569,17 +591,20 @@ __global__ __launch_bounds__(512) void k_legendre_spin(
     // spin-2 functions stay below the scalar cut plus 2 (|m - s| <= m + 2)
     const bool active = live && m <= mcut[r0] + 2;
     const int r = live ? r0 : 0;
+    const size_t plane = (size_t)ntheta * (lmax + 1);
+    const int rs = ntheta - 1 - r;
+    const size_t on = (size_t)r * (lmax + 1) + m, os = (size_t)rs * (lmax + 1) + m;
     if (!__any(active)) {
-        if (live) {
-            const size_t plane = (size_t)ntheta * (lmax + 1);
-            const int rs = ntheta - 1 - r;
-            for (int j = 0; j <= J; ++j) {
-                store_c<FT>(FQ, j * plane + (size_t)r * (lmax + 1) + m, make_double2(0, 0));
-                store_c<FT>(FQ, j * plane + (size_t)rs * (lmax + 1) + m, make_double2(0, 0));
-                store_c<FT>(FU, j * plane + (size_t)r * (lmax + 1) + m, make_double2(0, 0));
-                store_c<FT>(FU, j * plane + (size_t)rs * (lmax + 1) + m, make_double2(0, 0));
+        if (live)
+            for (int q = 0; q < NB; ++q) {
+                FT *FQ = (FT *)set.F[q], *FU = (FT *)set.G[q];
+                for (int j = 0; j <= J; ++j) {
+                    store_c<FT>(FQ, j * plane + on, make_double2(0, 0));
+                    store_c<FT>(FQ, j * plane + os, make_double2(0, 0));
+                    store_c<FT>(FU, j * plane + on, make_double2(0, 0));
+                    store_c<FT>(FU, j * plane + os, make_double2(0, 0));
+                }
             }
-        }
         return;
     }
     const double c = trig[r].x, s = trig[r].y;
@@ -589,77 +614,69 @@ __global__ __launch_bounds__(512) void k_legendre_spin(
     const int lmin = m > 2 ? m : 2;
     const bool modd = m & 1;
     __shared__ Stage<NR> sgs[8];
+    const double2 *rr[NR];
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+        rr[q * PER] = set.a[q] + base;
+        if constexpr (HASB) rr[q * PER + 1] = set.b[q] + base;
+    }
 
-    double2 PN[J + 1], MS[J + 1];
-    {
+#pragma unroll
+    for (int fam = 0; fam < 2; ++fam) {
         Rec<J> st;
-        load_start<J>(st, start, exps, 1, m, lmax, jtab, nrp, r);
+        load_start<J>(st, start, exps, 1 + fam, m, lmax, jtab, nrp, r);
         double2 accE[NR][J + 1], accO[NR][J + 1];
 #pragma unroll
-        for (int q = 0; q < NR; ++q)
+        for (int k = 0; k < NR; ++k)
 #pragma unroll
-            for (int j = 0; j <= J; ++j) accE[q][j] = accO[q][j] = make_double2(0, 0);
-        run_family<J, NR, 1>(lmin, lmax, c, w, coef2 + base, almE + base, HASB ? almB + base : nullptr,
-                          st, accE, accO, sgs[wave]);
+            for (int j = 0; j <= J; ++j) accE[k][j] = accO[k][j] = make_double2(0, 0);
+        if (fam == 0) run_family<J, NR, 1>(lmin, lmax, c, w, coef2 + base, rr, st, accE, accO, sgs[wave]);
+        else run_family<J, NR, -1>(lmin, lmax, c, w, coef2 + base, rr, st, accE, accO, sgs[wave]);
+        if (!live) continue;
 #pragma unroll
-        for (int j = 0; j <= J; ++j) {
-            const double2 Ee = modd ? accO[0][j] : accE[0][j], Eo = modd ? accE[0][j] : accO[0][j];
-            double2 Be = make_double2(0, 0), Bo = make_double2(0, 0);
-            if constexpr (HASB) {
-                Be = modd ? accO[NR - 1][j] : accE[NR - 1][j];
-                Bo = modd ? accE[NR - 1][j] : accO[NR - 1][j];
+        for (int q = 0; q < NB; ++q) {
+            FT *FQ = (FT *)set.F[q], *FU = (FT *)set.G[q];
+#pragma unroll
+            for (int j = 0; j <= J; ++j) {
+                const int kE = q * PER, kB = q * PER + PER - 1;
+                const double2 Ee = modd ? accO[kE][j] : accE[kE][j], Eo = modd ? accE[kE][j] : accO[kE][j];
+                double2 Be = make_double2(0, 0), Bo = make_double2(0, 0);
+                if constexpr (HASB) {
+                    Be = modd ? accO[kB][j] : accE[kB][j];
+                    Bo = modd ? accE[kB][j] : accO[kB][j];
+                }
+                const double sg = (j & 1) ? -1.0 : 1.0;
+                // family +2: P_N = -(SE + i SB), M_S = -(-1)^j [(Ee - Eo) - i (Be - Bo)]
+                // family -2: M_N = -(SE - i SB), P_S = -(-1)^j [(Ee - Eo) + i (Be - Bo)]
+                const double2 sumE = cadd(Ee, Eo), sumB = cadd(Be, Bo);
+                const double2 difE = csub(Ee, Eo), difB = csub(Be, Bo);
+                double2 Pn = make_double2(0, 0), Mn = Pn, Ps = Pn, Ms = Pn;
+                if (fam == 0) {
+                    Pn = cscale(cadd(sumE, mul_i(sumB)), -1.0);
+                    Ms = cscale(csub(difE, mul_i(difB)), -sg);
+                } else {
+                    Mn = cscale(csub(sumE, mul_i(sumB)), -1.0);
+                    Ps = cscale(cadd(difE, mul_i(difB)), -sg);
+                }
+                if (!active) Pn = Mn = Ps = Ms = make_double2(0, 0);
+                // Q = (P + M)/2,  U = -i (P - M)/2
+                double2 qn = cscale(cadd(Pn, Mn), 0.5), un = cscale(mul_i(csub(Pn, Mn)), -0.5);
+                double2 qs = cscale(cadd(Ps, Ms), 0.5), us = cscale(mul_i(csub(Ps, Ms)), -0.5);
+                if (fam == 1) {
+                    qn = cadd(qn, load_c<FT>(FQ, j * plane + on));
+                    un = cadd(un, load_c<FT>(FU, j * plane + on));
+                    if (rs != r) {
+                        qs = cadd(qs, load_c<FT>(FQ, j * plane + os));
+                        us = cadd(us, load_c<FT>(FU, j * plane + os));
+                    }
+                }
+                store_c<FT>(FQ, j * plane + on, qn);
+                store_c<FT>(FU, j * plane + on, un);
+                if (rs != r) {
+                    store_c<FT>(FQ, j * plane + os, qs);
+                    store_c<FT>(FU, j * plane + os, us);
+                }
             }
-            const double sg = (j & 1) ? -1.0 : 1.0;
-            // P_N = -(SE + i SB), SE = Ee + Eo
-            PN[j] = cscale(cadd(cadd(Ee, Eo), mul_i(cadd(Be, Bo))), -1.0);
-            // M_S = -(-1)^j [(Ee - Eo) - i (Be - Bo)]
-            MS[j] = cscale(csub(csub(Ee, Eo), mul_i(csub(Be, Bo))), -sg);
-        }
-    }
-    double2 MN[J + 1], PS[J + 1];
-    {
-        Rec<J> st;
-        load_start<J>(st, start, exps, 2, m, lmax, jtab, nrp, r);
-        double2 accE[NR][J + 1], accO[NR][J + 1];
-#pragma unroll
-        for (int q = 0; q < NR; ++q)
-#pragma unroll
-            for (int j = 0; j <= J; ++j) accE[q][j] = accO[q][j] = make_double2(0, 0);
-        run_family<J, NR, -1>(lmin, lmax, c, w, coef2 + base, almE + base, HASB ? almB + base : nullptr,
-                          st, accE, accO, sgs[wave]);
-#pragma unroll
-        for (int j = 0; j <= J; ++j) {
-            const double2 Ee = modd ? accO[0][j] : accE[0][j], Eo = modd ? accE[0][j] : accO[0][j];
-            double2 Be = make_double2(0, 0), Bo = make_double2(0, 0);
-            if constexpr (HASB) {
-                Be = modd ? accO[NR - 1][j] : accE[NR - 1][j];
-                Bo = modd ? accE[NR - 1][j] : accO[NR - 1][j];
-            }
-            const double sg = (j & 1) ? -1.0 : 1.0;
-            // M_N = -[(SE) - i SB]
-            MN[j] = cscale(csub(cadd(Ee, Eo), mul_i(cadd(Be, Bo))), -1.0);
-            // P_S = -(-1)^j [(Ee - Eo) + i (Be - Bo)]
-            PS[j] = cscale(cadd(csub(Ee, Eo), mul_i(csub(Be, Bo))), -sg);
-        }
-    }
-    const size_t plane = (size_t)ntheta * (lmax + 1);
-    const int rs = ntheta - 1 - r;
-    if (!live) return;
-    if (!active)
-#pragma unroll
-        for (int j = 0; j <= J; ++j) PN[j] = MN[j] = PS[j] = MS[j] = make_double2(0, 0);
-#pragma unroll
-    for (int j = 0; j <= J; ++j) {
-        // Q = (P + M)/2,  U = -i (P - M)/2
-        const double2 qn = cscale(cadd(PN[j], MN[j]), 0.5);
-        const double2 un = cscale(mul_i(csub(PN[j], MN[j])), -0.5);
-        store_c<FT>(FQ, j * plane + (size_t)r * (lmax + 1) + m, qn);
-        store_c<FT>(FU, j * plane + (size_t)r * (lmax + 1) + m, un);
-        if (rs != r) {
-            const double2 qs = cscale(cadd(PS[j], MS[j]), 0.5);
-            const double2 us = cscale(mul_i(csub(PS[j], MS[j])), -0.5);
-            store_c<FT>(FQ, j * plane + (size_t)rs * (lmax + 1) + m, qs);
-            store_c<FT>(FU, j * plane + (size_t)rs * (lmax + 1) + m, us);
         }
     }
 }
@@ -674,28 +691,81 @@ hipError_t start_tables_J(Plan &p)
     return hipGetLastError();
 }
 
-template <int J, typename FT>
-hipError_t scalar_J(Plan &p, int rend, const void *alm, void *F)
+// Right-hand sides one lane of the direct kernels carries (accumulators:
+// 8 (J + 1) VGPRs each) within the 256-VGPR budget of 512-thread workgroups.
+constexpr int rhs_max(int J) { return J == 0 ? 5 : J <= 2 ? 4 : J <= 4 ? 3 : J <= 6 ? 2 : 1; }
+
+template <int J, int NB, typename FT>
+hipError_t scalar_JN(Plan &p, int rend, const DirectSet &set)
 {
-    if (rend <= 0) return hipSuccess;
     dim3 grid((rend + 63) / 64, (p.lmax + 1 + 7) / 8);
-    hipLaunchKernelGGL((k_legendre_scalar<J, FT>), grid, dim3(512), 0, p.stream, p.lmax, p.ntheta, p.nrp, rend,
+    hipLaunchKernelGGL((k_legendre_scalar<J, NB, FT>), grid, dim3(512), 0, p.stream, p.lmax, p.ntheta, p.nrp, rend,
                        p.jtab, (const double2 *)p.trig.ptr, (const double4 *)p.coef0.ptr,
-                       (const double *)p.start.ptr, (const int *)p.exps.ptr, (const int *)p.mcut.ptr,
-                       (const double2 *)alm, (FT *)F);
+                       (const double *)p.start.ptr, (const int *)p.exps.ptr, (const int *)p.mcut.ptr, set);
     return hipGetLastError();
 }
 
-template <int J, bool HASB, typename FT>
-hipError_t spin_J(Plan &p, int rend, const void *E, const void *B, void *FQ, void *FU)
+template <int J, bool HASB, int NB, typename FT>
+hipError_t spin_JN(Plan &p, int rend, const DirectSet &set)
 {
-    if (rend <= 0) return hipSuccess;
     dim3 grid((rend + 63) / 64, (p.lmax + 1 + 7) / 8);
-    hipLaunchKernelGGL((k_legendre_spin<J, HASB, FT>), grid, dim3(512), 0, p.stream, p.lmax, p.ntheta, p.nrp, rend,
-                       p.jtab, (const double2 *)p.trig.ptr, (const double4 *)p.coef2.ptr,
-                       (const double *)p.start.ptr, (const int *)p.exps.ptr, (const int *)p.mcut.ptr,
-                       (const double2 *)E, (const double2 *)B, (FT *)FQ, (FT *)FU);
+    hipLaunchKernelGGL((k_legendre_spin<J, HASB, NB, FT>), grid, dim3(512), 0, p.stream, p.lmax, p.ntheta, p.nrp,
+                       rend, p.jtab, (const double2 *)p.trig.ptr, (const double4 *)p.coef2.ptr,
+                       (const double *)p.start.ptr, (const int *)p.exps.ptr, (const int *)p.mcut.ptr, set);
     return hipGetLastError();
+}
+
+// Realizations per launch: FP32 outputs (the caps of the FP32 and
+// tabulated forms) and the FP64 deflection (J = 1) take several, the FP64
+// form one.
+template <int J, typename FT>
+constexpr int scalar_nb() { return (std::is_same<FT, float>::value || J == 1) ? rhs_max(J) : 1; }
+template <int J, bool HASB, typename FT>
+constexpr int spin_nb()
+{
+    if (!std::is_same<FT, float>::value) return 1;
+    if (!HASB) return J == 1 ? 3 : rhs_max(J);
+    return (rhs_max(J) - 1) / 2 > 1 ? (rhs_max(J) - 1) / 2 : 1;
+}
+
+template <int J, typename FT>
+hipError_t scalar_J(Plan &p, int rend, const DirectSet &set)
+{
+    if (rend <= 0 || set.n <= 0) return hipSuccess;
+    constexpr int MX = scalar_nb<J, FT>();
+    switch (set.n) {
+    case 1: return scalar_JN<J, 1, FT>(p, rend, set);
+    case 2: if constexpr (MX >= 2) return scalar_JN<J, 2, FT>(p, rend, set); break;
+    case 3: if constexpr (MX >= 3) return scalar_JN<J, 3, FT>(p, rend, set); break;
+    case 4: if constexpr (MX >= 4) return scalar_JN<J, 4, FT>(p, rend, set); break;
+    case 5: if constexpr (MX >= 5) return scalar_JN<J, 5, FT>(p, rend, set); break;
+    default: break;
+    }
+    return hipErrorInvalidValue;
+}
+
+template <int J, bool HASB, typename FT>
+hipError_t spin_J(Plan &p, int rend, const DirectSet &set)
+{
+    if (rend <= 0 || set.n <= 0) return hipSuccess;
+    constexpr int MX = spin_nb<J, HASB, FT>();
+    switch (set.n) {
+    case 1: return spin_JN<J, HASB, 1, FT>(p, rend, set);
+    case 2: if constexpr (MX >= 2) return spin_JN<J, HASB, 2, FT>(p, rend, set); break;
+    case 3: if constexpr (MX >= 3) return spin_JN<J, HASB, 3, FT>(p, rend, set); break;
+    case 4: if constexpr (MX >= 4) return spin_JN<J, HASB, 4, FT>(p, rend, set); break;
+    case 5: if constexpr (MX >= 5) return spin_JN<J, HASB, 5, FT>(p, rend, set); break;
+    default: break;
+    }
+    return hipErrorInvalidValue;
+}
+
+template <int J>
+int direct_max_J(bool spin, bool hasb, bool out64)
+{
+    if (!spin) return out64 ? scalar_nb<J, double>() : scalar_nb<J, float>();
+    if (hasb) return out64 ? spin_nb<J, true, double>() : spin_nb<J, true, float>();
+    return out64 ? spin_nb<J, false, double>() : spin_nb<J, false, float>();
 }
 
 }  // namespace
@@ -731,10 +801,26 @@ hipError_t launch_tables(Plan &p)
     return hipGetLastError();
 }
 
-hipError_t launch_legendre_scalar(Plan &p, int J, int rend, const void *alm, void *F, bool out64)
+int direct_max(int J, bool spin, bool hasb, bool out64)
+{
+    switch (J) {
+    case 0: return direct_max_J<0>(spin, hasb, out64);
+    case 1: return direct_max_J<1>(spin, hasb, out64);
+    case 2: return direct_max_J<2>(spin, hasb, out64);
+    case 3: return direct_max_J<3>(spin, hasb, out64);
+    case 4: return direct_max_J<4>(spin, hasb, out64);
+    case 5: return direct_max_J<5>(spin, hasb, out64);
+    case 6: return direct_max_J<6>(spin, hasb, out64);
+    case 7: return direct_max_J<7>(spin, hasb, out64);
+    case 8: return direct_max_J<8>(spin, hasb, out64);
+    default: return 0;
+    }
+}
+
+hipError_t launch_legendre_scalar_set(Plan &p, int J, int rend, const DirectSet &set, bool out64)
 {
 #define TL_CASE(JJ) \
-    case JJ: return out64 ? scalar_J<JJ, double>(p, rend, alm, F) : scalar_J<JJ, float>(p, rend, alm, F);
+    case JJ: return out64 ? scalar_J<JJ, double>(p, rend, set) : scalar_J<JJ, float>(p, rend, set);
     switch (J) {
         TL_CASE(0)
         TL_CASE(1)
@@ -750,16 +836,13 @@ hipError_t launch_legendre_scalar(Plan &p, int J, int rend, const void *alm, voi
 #undef TL_CASE
 }
 
-hipError_t launch_legendre_spin(Plan &p, int J, int rend, const void *almE, const void *almB, void *FQ, void *FU,
-                                bool out64)
+hipError_t launch_legendre_spin_set(Plan &p, int J, int rend, const DirectSet &set, bool out64)
 {
-#define TL_CASE(JJ)                                                                          \
-    case JJ:                                                                                 \
-        if (almB)                                                                            \
-            return out64 ? spin_J<JJ, true, double>(p, rend, almE, almB, FQ, FU)             \
-                         : spin_J<JJ, true, float>(p, rend, almE, almB, FQ, FU);             \
-        return out64 ? spin_J<JJ, false, double>(p, rend, almE, almB, FQ, FU)                \
-                     : spin_J<JJ, false, float>(p, rend, almE, almB, FQ, FU);
+    const bool hasb = set.b[0] != nullptr;
+#define TL_CASE(JJ)                                                                                    \
+    case JJ:                                                                                           \
+        if (hasb) return out64 ? spin_J<JJ, true, double>(p, rend, set) : spin_J<JJ, true, float>(p, rend, set); \
+        return out64 ? spin_J<JJ, false, double>(p, rend, set) : spin_J<JJ, false, float>(p, rend, set);
     switch (J) {
         TL_CASE(0)
         TL_CASE(1)
@@ -773,6 +856,27 @@ hipError_t launch_legendre_spin(Plan &p, int J, int rend, const void *almE, cons
     default: return hipErrorInvalidValue;
     }
 #undef TL_CASE
+}
+
+hipError_t launch_legendre_scalar(Plan &p, int J, int rend, const void *alm, void *F, bool out64)
+{
+    DirectSet set{};
+    set.n = 1;
+    set.a[0] = (const double2 *)alm;
+    set.F[0] = F;
+    return launch_legendre_scalar_set(p, J, rend, set, out64);
+}
+
+hipError_t launch_legendre_spin(Plan &p, int J, int rend, const void *almE, const void *almB, void *FQ, void *FU,
+                                bool out64)
+{
+    DirectSet set{};
+    set.n = 1;
+    set.a[0] = (const double2 *)almE;
+    set.b[0] = (const double2 *)almB;
+    set.F[0] = FQ;
+    set.G[0] = FU;
+    return launch_legendre_spin_set(p, J, rend, set, out64);
 }
 
 }  // namespace tl

@@ -140,7 +140,7 @@ __global__ __launch_bounds__(256) void k_tab_rhs(int lmax, int ntile, const int6
                                                  float *__restrict__ colexp)
 {
     using T = typename H<BF>::T;
-    constexpr Cols C = cols_of(N, POL, HASB);
+    constexpr Cols C = cols_of(N, POL, HASB, true);
     constexpr int NCOLS = NBAT * C.n1;
     constexpr int NB = (NCOLS + 31) / 32;
     constexpr int NSPL = SPLIT ? 2 : 1;
@@ -158,7 +158,7 @@ __global__ __launch_bounds__(256) void k_tab_rhs(int lmax, int ntile, const int6
         __syncthreads();
         for (int idx = tid; idx < (lmax - m + 1) * NCOLS; idx += 256) {
             const int l = m + idx / NCOLS, c = idx % NCOLS;
-            const float v = (float)fabs(rhs_value<N, POL, HASB, NBAT>(batch, base, lmax, l, c));
+            const float v = (float)fabs(rhs_value<N, POL, HASB, NBAT, true>(batch, base, lmax, l, c));
             atomicMax((unsigned *)&s_ex[c], __float_as_uint(v));  // non-negative floats order as uints
         }
         __syncthreads();
@@ -182,7 +182,7 @@ __global__ __launch_bounds__(256) void k_tab_rhs(int lmax, int ntile, const int6
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
             const int l = m + kc * KC + p + 2 * (hh * 8 + k);
-            const float f = opaque((float)(rhs_value<N, POL, HASB, NBAT>(batch, base, lmax, l, col) * sc));
+            const float f = opaque((float)(rhs_value<N, POL, HASB, NBAT, true>(batch, base, lmax, l, col) * sc));
             hi8[k] = (T)f;
             lo8[k] = (T)(f - (float)hi8[k]);
         }
@@ -212,7 +212,7 @@ __global__ __launch_bounds__(256) void k_legendre_tab(
     const TabBatch batch)
 {
     using V = typename H<BF>::V;
-    constexpr Cols C = cols_of(N, POL, HASB);
+    constexpr Cols C = cols_of(N, POL, HASB, true);
     constexpr int NCOLS = NBAT * C.n1;
     constexpr int NB = (NCOLS + 31) / 32;
     constexpr int NSPL = SPLIT ? 2 : 1;
@@ -242,6 +242,10 @@ __global__ __launch_bounds__(256) void k_legendre_tab(
                     for (int f = 0; f < (POL ? 3 : 1); ++f) {
                         F[f][j * plane + (size_t)r * (lmax + 1) + m] = make_float2(0.f, 0.f);
                         if (rs != r) F[f][j * plane + (size_t)rs * (lmax + 1) + m] = make_float2(0.f, 0.f);
+                    }
+                    if (j < 2 && batch.FP[b]) {
+                        batch.FP[b][j * plane + (size_t)r * (lmax + 1) + m] = make_double2(0.0, 0.0);
+                        if (rs != r) batch.FP[b][j * plane + (size_t)rs * (lmax + 1) + m] = make_double2(0.0, 0.0);
                     }
                 }
         return;
@@ -393,6 +397,20 @@ __global__ __launch_bounds__(256) void k_legendre_tab(
                     FT[j * plane + (size_t)rs * (lmax + 1) + m] = make_float2((float)(sg * sre), (float)(sg * sim));
                 }
             }
+            // lensing potential: the lam sums (j = 0) and lam' sums (j = 1)
+            // themselves, in the deflection's FP64 rows
+            if (double2 *FP = batch.FP[bb]) {
+                const int c = C.n1 - C.nP;
+#pragma unroll
+                for (int j = 0; j < 2; ++j) {
+                    FP[j * plane + (size_t)r * (lmax + 1) + m] = make_double2(nsum(j, c), nsum(j, c + 1));
+                    if (rs != r) {
+                        const double sg = j ? -1.0 : 1.0;
+                        FP[j * plane + (size_t)rs * (lmax + 1) + m] =
+                            make_double2(sg * dsum(j, c), sg * dsum(j, c + 1));
+                    }
+                }
+            }
         } else if constexpr (POL) {
             float2 *FQ = batch.FQ[bb], *FU = batch.FU[bb];
             CoefP<N> cf;
@@ -452,7 +470,7 @@ hipError_t build_BS(Plan &p)
 template <bool BF, bool SPLIT, int N, bool POL, bool HASB, int NBAT>
 hipError_t gemm_launch(Plan &p, const TabBatch &b, int part)
 {
-    constexpr int NB = (NBAT * cols_of(N, POL, HASB).n1 + 31) / 32;
+    constexpr int NB = (NBAT * cols_of(N, POL, HASB, true).n1 + 31) / 32;
     if constexpr (NB > 4) {
         return hipErrorInvalidValue;
     } else {
@@ -513,7 +531,7 @@ hipError_t gemm_form(Plan &p, const TabBatch &b, int part)
 int tab_max_batch(int order, bool pol, bool hasb)
 {
     if (order > 6) return 0;
-    const int n1 = cols_of(order, pol, hasb).n1;
+    const int n1 = cols_of(order, pol, hasb, true).n1;
     int nb = 0;
     while (nb < 5 && ((nb + 1) * n1 + 31) / 32 <= 4) ++nb;
     return nb;
@@ -524,7 +542,7 @@ int tab_rhs_blocks(int order, bool pol, int batch)
     int nb = 1;
     for (int hb = 0; hb < 2; ++hb) {
         if (hb && !pol) break;
-        const int n1 = cols_of(order, pol, hb != 0).n1;
+        const int n1 = cols_of(order, pol, hb != 0, true).n1;
         const int g = std::min(std::max(batch, 1), tab_max_batch(order, pol, hb != 0));
         nb = std::max(nb, (g * n1 + 31) / 32);
     }

@@ -36,10 +36,14 @@ struct H<false> {
     using V = halfx8;
 };
 
+// Columns of one realization: T (L^p a^T, p <= PT), E and B (N_l L^p a, p <=
+// PS), then, with def, the lensing potential (a^phi: its lam and lam' sums
+// are the theta-derivatives of order 0 and 1 the deflection needs).  Real and
+// imaginary parts in adjacent columns.
 struct Cols {
-    int PT, PS, nT, nE, nB, n1;
+    int PT, PS, nT, nE, nB, nP, n1;
 };
-__host__ __device__ constexpr Cols cols_of(int N, bool pol, bool hasb)
+__host__ __device__ constexpr Cols cols_of(int N, bool pol, bool hasb, bool def = false)
 {
     Cols c{};
     c.PT = N / 2;
@@ -47,7 +51,8 @@ __host__ __device__ constexpr Cols cols_of(int N, bool pol, bool hasb)
     c.nT = 2 * (c.PT + 1);
     c.nE = pol ? 2 * (c.PS + 1) : 0;
     c.nB = pol && hasb ? 2 * (c.PS + 1) : 0;
-    c.n1 = c.nT + c.nE + c.nB;
+    c.nP = def ? 2 : 0;
+    c.n1 = c.nT + c.nE + c.nB + c.nP;
     return c;
 }
 
@@ -217,13 +222,19 @@ __device__ inline void coefficients_P(double th, int m, CoefP<N> &C)
 
 // Right-hand side value of column c (realization c / n1, local column
 // c % n1) at degree l: {L^p a^T} for T, {N_l L^p a^E}, {N_l L^p a^B} for the
-// spin-2 families, real and imaginary parts in adjacent columns.
-template <int N, bool POL, bool HASB, int NBAT>
+// spin-2 families, a^phi with DEF, real and imaginary parts in adjacent
+// columns.
+template <int N, bool POL, bool HASB, int NBAT, bool DEF = false>
 __device__ __forceinline__ double rhs_value(const TabBatch &batch, size_t base, int lmax, int l, int c)
 {
-    constexpr Cols C = cols_of(N, POL, HASB);
+    constexpr Cols C = cols_of(N, POL, HASB, DEF);
     const int b = c / C.n1, cc = c % C.n1;
     if (b >= NBAT || l > lmax) return 0.0;
+    if (DEF && cc >= C.n1 - C.nP) {
+        if (!batch.P[b]) return 0.0;
+        const double2 a = batch.P[b][base + l];
+        return (cc & 1) ? a.y : a.x;
+    }
     const double L = (double)l * (double)(l + 1);
     if (cc < C.nT) {
         const double2 a = batch.T[b][base + l];

@@ -47,6 +47,10 @@ struct TabBatch {
     float2 *FT[kTabMaxBatch];
     float2 *FQ[kTabMaxBatch];
     float2 *FU[kTabMaxBatch];
+    // lensing potential (table engine; NULL: none): a^phi and the FP64 rows
+    // [2][ntheta][lmax+1] of its lam and lam' sums (the deflection's Fphi)
+    const double2 *P[kTabMaxBatch];
+    double2 *FP[kTabMaxBatch];
 };
 
 struct Plan {
@@ -89,7 +93,7 @@ struct Plan {
     size_t rhs_nb = 0;  // 32-column blocks the rhs buffer holds per chunk
 
     // work buffers
-    DevBuf Fphi;      // complex128 [2][ntheta][lmax+1]
+    DevBuf Fphi;      // complex128 [batch][2][ntheta][lmax+1]
     DevBuf alpha;     // double [2][ntheta][nphi]
     DevBuf F;         // complex (64 or 128) [nfield][N+1][ntheta][lmax+1]
     DevBuf D;         // real [nfield][ndmap][ntheta][nphi]
@@ -117,8 +121,24 @@ struct Plan {
     size_t nalm() const { return (size_t)(lmax + 1) * (size_t)(lmax + 2) / 2; }
 };
 
+// Realizations of one launch of the direct FP64 kernels (they share the
+// recursion): a = a_lm (spin: a^E), b = a^B (spin; all NULL or none), F =
+// output rows (spin: FQ), G = FU.
+constexpr int kDirectMax = 5;
+struct DirectSet {
+    int n;
+    const double2 *a[kDirectMax];
+    const double2 *b[kDirectMax];
+    void *F[kDirectMax];
+    void *G[kDirectMax];
+};
+
 // ---- kernel launchers (return hipError_t) ----
 hipError_t launch_tables(Plan &p);
+// most realizations one direct launch takes at derivative order J
+int direct_max(int J, bool spin, bool hasb, bool out64);
+hipError_t launch_legendre_scalar_set(Plan &p, int J, int rend, const DirectSet &set, bool out64);
+hipError_t launch_legendre_spin_set(Plan &p, int J, int rend, const DirectSet &set, bool out64);
 hipError_t launch_legendre_scalar(Plan &p, int J, int rend, const void *alm, void *F, bool out64);
 hipError_t launch_legendre_spin(Plan &p, int J, int rend, const void *almE, const void *almB, void *FQ,
                                 void *FU, bool out64);

@@ -39,7 +39,7 @@ CNN_NTRAIN = 15139
 CNN_NPARAM = 15142
 STAGES = ["defl_legendre", "defl_fft", "legendre_T", "legendre_QU", "legendre_mfma", "tab_rhs", "legendre_tab",
           "ring_fft", "remap", "cnn"]
-QUERY_KEYS = {"rpole": 0, "elems": 1, "elems_caps": 2, "tab_chunks": 3, "tab_chunk_bytes": 4}
+QUERY_KEYS = {"rpole": 0, "elems": 1, "elems_caps": 2, "tab_chunks": 3, "tab_chunk_bytes": 4, "defl_folded": 5}
 # kernel each stage launches
 STAGE_KERNELS = {"defl_legendre": "k_legendre_scalar", "defl_fft": "k_ring_fft", "legendre_T": "k_legendre_scalar",
                  "legendre_QU": "k_legendre_spin", "legendre_mfma": "k_legendre_mfma", "tab_rhs": "k_tab_rhs",

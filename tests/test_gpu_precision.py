@@ -133,3 +133,12 @@ def test_onthefly_engine_matches_oracle(tl, oracle, precision, batch, monkeypatc
         torch.cuda.synchronize()
         for x, y in zip(one, g):
             assert torch.equal(x, y)
+
+
+def test_deflection_fold_policy(tl):
+    """The split table forms carry the lensing potential in their table pass;
+    the single-table forms and the FP32 form keep the FP64 deflection."""
+    for prec, want in [("bf16x3", 1), ("fp16x2", 1), ("fp16", 0), ("bf16", 0), ("fp32", 0)]:
+        plan = tl.Plan(96, 97, 192, 4, prec, pol=True)
+        assert plan.query("defl_folded") == want, prec
+        plan.close()
