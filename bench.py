@@ -80,6 +80,8 @@ def stage_work(w, order, form, q, hasb, n):
     # kernel covers the caps only
     defl = q["elems_caps"] if q["defl_folded"] else q["elems"]
     ncol = cols(order, w.pol, hasb) + (2 if q["defl_folded"] else 0)
+    nrn = (w.ntheta + 1) // 2 - q["rpole"]  # ring pairs outside the caps
+    colsum = n * (cols(order, w.pol, hasb) + 2) * 4 * 4 * nrn * (w.lmax + 1)
     out = {
         "defl_legendre": ("fp64", n * direct_flops_per_elem(1, False, False) * defl),
         "defl_fft": ("hbm", n * (2 * rowc * 16 + 2 * npix * 8)),
@@ -87,9 +89,11 @@ def stage_work(w, order, form, q, hasb, n):
         "legendre_QU": ("fp64", n * direct_flops_per_elem(order, True, hasb) * caps),
         "legendre_mfma": ("fp32_mfma", n * (q["elems"] - q["elems_caps"]) * 2 * cols(order, w.pol, hasb) * 2),
         "tab_rhs": ("hbm", n * nlm * 16 * (1 + (2 if hasb else 1) * w.pol + q["defl_folded"])),
-        "legendre_tab": ("hbm", q["tab_chunks"] * q["tab_chunk_bytes"]
-                         + n * nfield * (order + 1) * 2 * (w.ntheta // 2 - q["rpole"]) * (w.lmax + 1) * 8
-                         + n * q["defl_folded"] * 2 * 2 * (w.ntheta // 2 - q["rpole"]) * (w.lmax + 1) * 16),
+        # table stream + the FP32 column sums (4 per column: lam / lam' x parity)
+        "legendre_tab": ("hbm", q["tab_chunks"] * q["tab_chunk_bytes"] + colsum),
+        # column sums back in, theta-derivative rows (and the potential's FP64 rows) out
+        "tab_epi": ("hbm", colsum + n * nfield * (order + 1) * 2 * nrn * (w.lmax + 1) * 8
+                    + n * q["defl_folded"] * 2 * 2 * nrn * (w.lmax + 1) * 16),
         "ring_fft": ("hbm", n * (nfield * (order + 1) * rowc * cbytes + nfield * ndmap * npix * rbytes)),
         "remap": ("hbm", n * (npix * (16 + nfield * 4) + nfield * ndmap * npix * rbytes)),
     }
@@ -268,7 +272,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="TP4096")
     ap.add_argument("--order", type=int, default=None)
-    ap.add_argument("--forms", default="fp32,fp16:5",
+    ap.add_argument("--forms", default="fp32,fp16:5,fp16x2:5",
                     help="comma list of precision[:realizations per step]; fp32 is the speed-up reference")
     ap.add_argument("--headline", default=None, help="form reported as value (default: the last of --forms)")
     ap.add_argument("--cpu-rings", type=int, default=16, help="output rings in the CPU-oracle sample")
@@ -352,7 +356,7 @@ def main():
     for f, r in results.items():
         px = f[1] * npix / r["sec"]
         leg = sum(r["per_step"].get(k, 0.0) for k in ("legendre_T", "legendre_QU", "legendre_mfma", "tab_rhs",
-                                                       "legendre_tab"))
+                                                       "legendre_tab", "tab_epi"))
         useful = f[1] * a3_useful_flops(w.lmax, (w.ntheta + 1) // 2, order, w.pol, hasb)
         if r["q"]["defl_folded"]:
             # the table pass also synthesizes the deflection's two rows (order 1 of phi)

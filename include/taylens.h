@@ -299,14 +299,18 @@ int tl_lens_map_cnn(tl_plan plan, tl_cnn net, const void *alm_T, const void *alm
 /* ---- instrumentation ---- */
 
 /* Stages timed by tl_plan_profile, one kernel launch each:
- * 0 harmonic kernel of the deflection (FP64, all rings), 1 its ring FFTs,
+ * 0 harmonic kernel of the deflection (FP64; all rings, or the pole-adjacent
+ * rings when the table GEMM carries the lensing potential), 1 its ring FFTs,
  * 2 direct FP64 harmonic kernel of T, 3 direct FP64 harmonic kernel of Q/U
  * (all rings in the FP64 form, the pole-adjacent rings in the others),
  * 4 matrix-core harmonic kernel of the FP32 form (T and Q/U, the remaining
- * rings), 5 right-hand sides of the tabulated forms, 6 their table GEMM,
- * 7 ring FFTs of the derivative maps, 8 remap + Taylor sum + rotation,
- * 9 the learned correction network (tl_lens_map_cnn). */
-#define TL_NSTAGE 10
+ * rings), 5 right-hand sides of the tabulated forms, 6 their table GEMM
+ * (column sums), 7 ring FFTs of the derivative maps, 8 remap + Taylor sum +
+ * rotation, 9 the learned correction network (tl_lens_map_cnn), 10 the
+ * epilogue of the table GEMM (theta-derivative rows from the column sums).
+ * The direct kernels take several realizations per launch in
+ * tl_lens_map_many. */
+#define TL_NSTAGE 11
 
 /* enable != 0: from now on record a HIP event pair on the plan's stream
  * around every stage of every call (no synchronization is added); 0: stop.

@@ -112,7 +112,7 @@ void free_buf(DevBuf &b)
 void free_plan_buffers(Plan &p)
 {
     DevBuf *bufs[] = {&p.theta, &p.trig, &p.phitab, &p.phival, &p.twid64, &p.twid32, &p.coef0, &p.coef2,
-                      &p.start, &p.exps, &p.mcut, &p.tab, &p.moff, &p.kstart, &p.rhs, &p.colexp, &p.Fphi, &p.alpha, &p.F, &p.D, &p.jobsDefl, &p.jobsMain};
+                      &p.start, &p.exps, &p.mcut, &p.tab, &p.moff, &p.kstart, &p.rhs, &p.colexp, &p.tabsum, &p.Fphi, &p.alpha, &p.F, &p.D, &p.jobsDefl, &p.jobsMain};
     for (DevBuf *b : bufs) free_buf(*b);
 }
 
@@ -142,11 +142,11 @@ double factorial(int n)
 
 struct Sizes {
     size_t theta, trig, phitab, phival, twid64, twid32, coef, start, exps, mcut, Fphi, alpha, F, D, jd, jm;
-    size_t tab = 0, moff = 0, kstart = 0, rhs = 0, colexp = 0;
+    size_t tab = 0, moff = 0, kstart = 0, rhs = 0, colexp = 0, tabsum = 0;
     size_t total() const
     {
         return theta + trig + phitab + phival + twid64 + twid32 + 2 * coef + start + exps + mcut + Fphi + alpha + F +
-               D + jd + jm + tab + moff + kstart + rhs + colexp;
+               D + jd + jm + tab + moff + kstart + rhs + colexp + tabsum;
     }
 };
 
@@ -183,6 +183,7 @@ Sizes plan_sizes(const Plan &p)
         const int nb = tab_rhs_blocks(p.order, p.pol != 0, p.batch);
         s.rhs = tab_rhs_bytes(p.lmax, p.precision == TL_BF16X3 || p.precision == TL_FP16X2, nb);
         s.colexp = (size_t)(p.lmax + 1) * 32 * nb * sizeof(float);
+        s.tabsum = tab_sum_bytes(p.lmax, p.nrp - p.rpole, p.order, p.pol != 0, p.batch);
     }
     s.D = (size_t)p.nfield() * p.ndmap() * p.npix() * rbytes;
     s.jd = 2 * (size_t)p.ntheta * sizeof(FftJob);
@@ -454,8 +455,15 @@ int run_legendre_many(Plan &p, int n, const void *const *T, const void *const *E
                 TL_HIP(p.tables ? launch_legendre_tab(p, b, 0) : launch_legendre_lp(p, b, 0),
                        "legendre right-hand sides");
             }
-            StageScope sc(p, ST_TAB_GEMM);
-            TL_HIP(p.tables ? launch_legendre_tab(p, b, 1) : launch_legendre_lp(p, b, 1), "legendre matrix-core stage");
+            {
+                StageScope sc(p, ST_TAB_GEMM);
+                TL_HIP(p.tables ? launch_legendre_tab(p, b, 1) : launch_legendre_lp(p, b, 1),
+                       "legendre matrix-core stage");
+            }
+            if (p.tables) {
+                StageScope sc(p, ST_TAB_EPI);
+                TL_HIP(launch_legendre_tab(p, b, 2), "legendre table epilogue");
+            }
         }
     }
     return TL_OK;
@@ -917,7 +925,8 @@ int tl_plan_create(tl_plan *out, int32_t lmax, tl_grid grid, const tl_options *o
                 {&p.exps, sz.exps, "exps"},      {&p.mcut, sz.mcut, "mcut"},       {&p.Fphi, sz.Fphi, "Fphi"},       {&p.alpha, sz.alpha, "alpha"},
                 {&p.F, sz.F, "F"},               {&p.D, sz.D, "D"},                {&p.jobsDefl, sz.jd, "jobsDefl"},
                 {&p.jobsMain, sz.jm, "jobsMain"}, {&p.tab, sz.tab, "tab"},        {&p.moff, sz.moff, "moff"},
-                {&p.kstart, sz.kstart, "kstart"}, {&p.rhs, sz.rhs, "rhs"},          {&p.colexp, sz.colexp, "colexp"}};
+                {&p.kstart, sz.kstart, "kstart"}, {&p.rhs, sz.rhs, "rhs"},          {&p.colexp, sz.colexp, "colexp"},
+                {&p.tabsum, sz.tabsum, "tabsum"}};
     for (auto &it : list) {
         if (it.n == 0) continue;
         rc = alloc(p, *it.b, it.n, it.name);

@@ -203,13 +203,16 @@ __global__ __launch_bounds__(256) void k_tab_rhs(int lmax, int ntile, const int6
 // by k_tab_rhs) are shared by all its tiles, and the workgroups of one m run
 // on one XCD (m = xcd + 8 i) so they are read from HBM once.  Each wave walks
 // its own tile from its first non-empty chunk; nothing in the main loop
-// synchronizes the workgroup.
+// synchronizes the workgroup.  The column sums, scaled back by the column
+// powers of two, go to HBM straight from the accumulators (lanes hold
+// consecutive columns): sums[m][ring pair - rbeg][realization][type*2 +
+// parity][column of the realization]; k_tab_epi turns them into the rows.
 template <bool BF, bool SPLIT, int N, bool POL, bool HASB, int NBAT>
-__global__ __launch_bounds__(256) void k_legendre_tab(
-    int lmax, int ntheta, int nrp, int rbeg, int ntile, int ngrp, const double *__restrict__ theta,
-    const int *__restrict__ mcut, const int64_t *__restrict__ moff, const uint4 *__restrict__ tab,
-    const int *__restrict__ kstart, const uint4 *__restrict__ rhs, const float *__restrict__ colexp,
-    const TabBatch batch)
+__global__ __launch_bounds__(256) void k_legendre_tab(int lmax, int nrp, int rbeg, int ntile, int ngrp,
+                                                      const int *__restrict__ mcut, const int64_t *__restrict__ moff,
+                                                      const uint4 *__restrict__ tab, const int *__restrict__ kstart,
+                                                      const uint4 *__restrict__ rhs, const float *__restrict__ colexp,
+                                                      float *__restrict__ sums)
 {
     using V = typename H<BF>::V;
     constexpr Cols C = cols_of(N, POL, HASB, true);
@@ -217,8 +220,6 @@ __global__ __launch_bounds__(256) void k_legendre_tab(
     constexpr int NB = (NCOLS + 31) / 32;
     constexpr int NSPL = SPLIT ? 2 : 1;
     constexpr int RCH = NSPL * NB * 128;
-
-    __shared__ float s_tr[4][32][4][33];  // epilogue transposition, per wave [ring][type*2+par][col]
 
     const int xcd = blockIdx.x & 7, q = blockIdx.x >> 3;
     const int m = xcd + 8 * (q / ngrp);
@@ -229,27 +230,11 @@ __global__ __launch_bounds__(256) void k_legendre_tab(
     const int r = rbeg + tile * TILE + rl;
     const bool live = (tile < ntile) && (r < nrp);
     const int nk = (lmax - m + 1 + KC - 1) / KC;
-    const size_t plane = (size_t)ntheta * (lmax + 1);
 
-    // evanescent for every ring of the block: zeros
+    // evanescent for every ring of the block: nothing to sum (the epilogue
+    // writes zeros past each ring's cut)
     const int mc = live ? mcut[r] + 2 : -1;
-    if (!__syncthreads_or(m <= mc)) {
-        if (live && hl == 0)
-            for (int b = 0; b < NBAT; ++b)
-                for (int j = 0; j <= N; ++j) {
-                    const int rs = ntheta - 1 - r;
-                    float2 *F[3] = {batch.FT[b], batch.FQ[b], batch.FU[b]};
-                    for (int f = 0; f < (POL ? 3 : 1); ++f) {
-                        F[f][j * plane + (size_t)r * (lmax + 1) + m] = make_float2(0.f, 0.f);
-                        if (rs != r) F[f][j * plane + (size_t)rs * (lmax + 1) + m] = make_float2(0.f, 0.f);
-                    }
-                    if (j < 2 && batch.FP[b]) {
-                        batch.FP[b][j * plane + (size_t)r * (lmax + 1) + m] = make_double2(0.0, 0.0);
-                        if (rs != r) batch.FP[b][j * plane + (size_t)rs * (lmax + 1) + m] = make_double2(0.0, 0.0);
-                    }
-                }
-        return;
-    }
+    if (!__syncthreads_or(m <= mc)) return;
 
     floatx16 acc[NB][2][2];
 #pragma unroll
@@ -262,17 +247,18 @@ __global__ __launch_bounds__(256) void k_legendre_tab(
                 for (int v = 0; v < 16; ++v) acc[b][t][p][v] = 0.f;
 
     if (tile < ntile) {
-        // The table streams with PF chunks in flight per wave (the loop is
-        // bound by HBM, not by the matrix cores); the right-hand sides of
-        // the next chunk are fetched one chunk ahead.
-        constexpr int PF = SPLIT ? 2 : 4;
+        // The table and the right-hand sides stream with PF chunks in flight
+        // per wave (the loop is bound by memory latency, not by the matrix
+        // cores): loads retire in order, so the chunk consumed now must be
+        // the oldest one in flight, for both operands.
+        constexpr int PF = SPLIT ? 2 : (NB >= 3 ? 3 : 4);
         constexpr int AW = NSPL * 4;  // uint4 per lane per chunk
         const int ks = __builtin_amdgcn_readfirstlane(kstart[(size_t)m * ntile + tile]);
         const uint4 *blk = tab + (moff[m] + (int64_t)tile * nk * AW * 64) + lane;
         const int64_t cum = moff[m] / ((int64_t)ntile * NSPL * 256);
         const uint4 *rb = rhs + cum * RCH + lane;
         uint4 Ab[PF][AW];
-        uint4 Bb[2][NSPL][NB][2];
+        uint4 Bb[PF][NSPL][NB][2];
         auto loadA = [&](uint4 (&dst)[AW], int kc) {
             const uint4 *cb = blk + (int64_t)kc * AW * 64;
 #pragma unroll
@@ -292,109 +278,141 @@ __global__ __launch_bounds__(256) void k_legendre_tab(
         };
 #pragma unroll
         for (int u = 0; u < PF; ++u)
-            if (ks + u < nk) loadA(Ab[u], ks + u);
-        if (ks < nk) loadB(Bb[0], ks);
-        for (int k0 = ks; k0 < nk; k0 += PF) {
+            if (ks + u < nk) {
+                loadA(Ab[u], ks + u);
+                loadB(Bb[u], ks + u);
+            }
+        // one chunk: operands from slot u, refill the slot PF chunks ahead
+        auto chunk = [&](const uint4 (&Au)[AW], const uint4 (&Bu)[NSPL][NB][2]) {
+            V A[NSPL][2][2], Bv[NSPL][NB][2];
 #pragma unroll
-            for (int u = 0; u < PF; ++u) {
-                const int kc = k0 + u;
-                if (kc >= nk) break;
-                if (kc + 1 < nk) loadB(Bb[(u + 1) & 1], kc + 1);
-                V A[NSPL][2][2];
+            for (int sp = 0; sp < NSPL; ++sp) {
 #pragma unroll
-                for (int sp = 0; sp < NSPL; ++sp)
+                for (int t = 0; t < 2; ++t)
 #pragma unroll
-                    for (int t = 0; t < 2; ++t)
+                    for (int p = 0; p < 2; ++p) __builtin_memcpy(&A[sp][t][p], &Au[(sp * 2 + t) * 2 + p], 16);
 #pragma unroll
-                        for (int p = 0; p < 2; ++p) __builtin_memcpy(&A[sp][t][p], &Ab[u][(sp * 2 + t) * 2 + p], 16);
-                if (kc + PF < nk) loadA(Ab[u], kc + PF);
+                for (int b = 0; b < NB; ++b)
+#pragma unroll
+                    for (int p = 0; p < 2; ++p) __builtin_memcpy(&Bv[sp][b][p], &Bu[sp][b][p], 16);
+            }
+            return [=](floatx16 (&ac)[NB][2][2]) {
 #pragma unroll
                 for (int b = 0; b < NB; ++b)
 #pragma unroll
                     for (int p = 0; p < 2; ++p) {
-                        V Bh, Bl;
-                        __builtin_memcpy(&Bh, &Bb[u & 1][0][b][p], 16);
-                        if constexpr (SPLIT) __builtin_memcpy(&Bl, &Bb[u & 1][NSPL - 1][b][p], 16);
+                        const V Bh = Bv[0][b][p];
+                        const V Bl = Bv[NSPL - 1][b][p];
 #pragma unroll
                         for (int t = 0; t < 2; ++t) {
                             if constexpr (BF) {
-                                acc[b][t][p] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[0][t][p], Bh, acc[b][t][p], 0, 0, 0);
+                                ac[b][t][p] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[0][t][p], Bh, ac[b][t][p], 0, 0, 0);
                                 if constexpr (SPLIT) {
-                                    acc[b][t][p] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[0][t][p], Bl, acc[b][t][p], 0, 0, 0);
-                                    acc[b][t][p] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[NSPL - 1][t][p], Bh, acc[b][t][p], 0, 0, 0);
+                                    ac[b][t][p] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[0][t][p], Bl, ac[b][t][p], 0, 0, 0);
+                                    ac[b][t][p] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[NSPL - 1][t][p], Bh, ac[b][t][p], 0, 0, 0);
                                 }
                             } else {
-                                acc[b][t][p] = __builtin_amdgcn_mfma_f32_32x32x16_f16(A[0][t][p], Bh, acc[b][t][p], 0, 0, 0);
+                                ac[b][t][p] = __builtin_amdgcn_mfma_f32_32x32x16_f16(A[0][t][p], Bh, ac[b][t][p], 0, 0, 0);
                                 if constexpr (SPLIT) {
-                                    acc[b][t][p] = __builtin_amdgcn_mfma_f32_32x32x16_f16(A[0][t][p], Bl, acc[b][t][p], 0, 0, 0);
-                                    acc[b][t][p] = __builtin_amdgcn_mfma_f32_32x32x16_f16(A[NSPL - 1][t][p], Bh, acc[b][t][p], 0, 0, 0);
+                                    ac[b][t][p] = __builtin_amdgcn_mfma_f32_32x32x16_f16(A[0][t][p], Bl, ac[b][t][p], 0, 0, 0);
+                                    ac[b][t][p] = __builtin_amdgcn_mfma_f32_32x32x16_f16(A[NSPL - 1][t][p], Bh, ac[b][t][p], 0, 0, 0);
                                 }
                             }
                         }
                     }
+            };
+        };
+        // whole groups of PF chunks (one back edge), then the tail
+        int k0 = ks;
+        for (; k0 + PF <= nk; k0 += PF) {
+#pragma unroll
+            for (int u = 0; u < PF; ++u) {
+                auto mm = chunk(Ab[u], Bb[u]);
+                if (k0 + u + PF < nk) {
+                    loadA(Ab[u], k0 + u + PF);
+                    loadB(Bb[u], k0 + u + PF);
+                }
+                mm(acc);
             }
         }
+#pragma unroll
+        for (int u = 0; u < PF; ++u)
+            if (k0 + u < nk) chunk(Ab[u], Bb[u])(acc);
     }
 
-    // ---- epilogue: per wave, transpose one 32-column block at a time ----
-    const int rs = ntheta - 1 - r;
-    const double dsc = BF ? 1.0 : 1.0 / kDerivScale;
+    if (tile >= ntile) return;
+    const int nrn = nrp - rbeg;
+    const float dsc = BF ? 1.f : (float)(1.0 / kDerivScale);
     const float *cex = colexp + (size_t)m * NB * 32;
-    // output accumulators for this lane's ring: lanes 0..31 T, lanes 32..63 Q/U
-    for (int bb = 0; bb < NBAT; ++bb) {
-        // sums S[type*2+par][cc] of realization bb, gathered block by block
-        // (exact in FP32: the accumulators times powers of two)
-        float S[4][C.n1];
+    const int rp0 = tile * TILE + 4 * hl;  // ring pair of accumulator slot 0
+    constexpr int RSTR = NBAT * 4 * C.n1;  // floats per ring pair
 #pragma unroll
-        for (int q4 = 0; q4 < 4; ++q4)
+    for (int b = 0; b < NB; ++b) {
+        const int col = b * 32 + rl;
+        if (col >= NCOLS) continue;
+        const int bb = col / C.n1, c = col % C.n1;
+        const float isc = exp2f(-cex[col]);  // exact: powers of two
+        float *base = sums + ((size_t)m * nrn + rp0) * RSTR + bb * 4 * C.n1 + c;
 #pragma unroll
-            for (int c = 0; c < C.n1; ++c) S[q4][c] = 0.f;
-#pragma unroll
-        for (int b = 0; b < NB; ++b) {
-            const int c0 = b * 32;
-            if (c0 + 32 <= bb * C.n1 || c0 >= (bb + 1) * C.n1) continue;
-            wave_sync();
+        for (int v = 0; v < 16; ++v) {
+            const int row = 8 * (v >> 2) + (v & 3);
+            if (rp0 + row >= nrn) continue;
 #pragma unroll
             for (int t = 0; t < 2; ++t)
 #pragma unroll
                 for (int p = 0; p < 2; ++p)
-#pragma unroll
-                    for (int vv = 0; vv < 16; ++vv) {
-                        const int row = 8 * (vv >> 2) + 4 * hl + (vv & 3);
-                        s_tr[wave][row][t * 2 + p][rl] = acc[b][t][p][vv];
-                    }
-            wave_sync();
-#pragma unroll
-            for (int c = 0; c < C.n1; ++c) {
-                const int col = bb * C.n1 + c;
-                if (col < c0 || col >= c0 + 32) continue;
-                const float isc = exp2f(-cex[col]);
-#pragma unroll
-                for (int q4 = 0; q4 < 4; ++q4)
-                    S[q4][c] = s_tr[wave][rl][q4][col - c0] * isc * ((q4 >> 1) ? (float)dsc : 1.f);
-            }
+                    base[row * RSTR + (t * 2 + p) * C.n1] = acc[b][t][p][v] * isc * (t ? dsc : 1.f);
         }
-        if (!live) continue;
-        auto nsum = [&](int type, int c) { return (double)S[type * 2][c] + (double)S[type * 2 + 1][c]; };
-        auto dsum = [&](int type, int c) { return (double)S[type * 2][c] - (double)S[type * 2 + 1][c]; };
-        float2 *FT = batch.FT[bb];
-        if (hl == 0) {
-            CoefT<N> cf;
-            coefficients_T<N>(theta[r], m, cf);
+    }
+}
+
+// Epilogue of the table GEMM: one thread per (m, ring pair), consecutive m
+// across a wave (coalesced row writes).  The FP64 coefficients of a (ring,
+// m) are formed once and applied to every realization's column sums: T and
+// the lensing potential below the ring's cut, Q/U two past it (spin-2
+// functions reach |m - 2|); zeros beyond.
+template <int N, bool POL, bool HASB, int NBAT>
+__global__ __launch_bounds__(256) void k_tab_epi(int lmax, int ntheta, int nrp, int rbeg,
+                                                 const double *__restrict__ theta, const int *__restrict__ mcut,
+                                                 const float *__restrict__ sums, const TabBatch batch)
+{
+    constexpr Cols C = cols_of(N, POL, HASB, true);
+    const int m = blockIdx.x * 64 + (threadIdx.x & 63);
+    const int r = rbeg + blockIdx.y * 4 + (threadIdx.x >> 6);
+    if (m > lmax || r >= nrp) return;
+    const int nrn = nrp - rbeg;
+    const size_t plane = (size_t)ntheta * (lmax + 1);
+    const int rs = ntheta - 1 - r;
+    const size_t on = (size_t)r * (lmax + 1) + m, os = (size_t)rs * (lmax + 1) + m;
+    const float *S0 = sums + ((size_t)m * nrn + (r - rbeg)) * NBAT * 4 * C.n1;
+    const int mc = mcut[r];
+    const double th = theta[r];
+
+    {   // T and the lensing potential
+        const bool act = m <= mc;
+        CoefT<N> cf;
+        if (act) coefficients_T<N>(th, m, cf);
+        for (int bb = 0; bb < NBAT; ++bb) {
+            const float *S = S0 + (size_t)bb * 4 * C.n1;
+            auto nsum = [&](int type, int c) { return (double)S[type * 2 * C.n1 + c] + (double)S[(type * 2 + 1) * C.n1 + c]; };
+            auto dsum = [&](int type, int c) { return (double)S[type * 2 * C.n1 + c] - (double)S[(type * 2 + 1) * C.n1 + c]; };
+            float2 *FT = batch.FT[bb];
 #pragma unroll
             for (int j = 0; j <= N; ++j) {
                 double nre = 0, nim = 0, sre = 0, sim = 0;
+                if (act) {
 #pragma unroll
-                for (int p = 0; p <= C.PT; ++p) {
-                    nre += cf.ta[j][p] * nsum(0, 2 * p) + cf.tb[j][p] * nsum(1, 2 * p);
-                    nim += cf.ta[j][p] * nsum(0, 2 * p + 1) + cf.tb[j][p] * nsum(1, 2 * p + 1);
-                    sre += cf.ta[j][p] * dsum(0, 2 * p) + cf.tb[j][p] * dsum(1, 2 * p);
-                    sim += cf.ta[j][p] * dsum(0, 2 * p + 1) + cf.tb[j][p] * dsum(1, 2 * p + 1);
+                    for (int p = 0; p <= C.PT; ++p) {
+                        nre += cf.ta[j][p] * nsum(0, 2 * p) + cf.tb[j][p] * nsum(1, 2 * p);
+                        nim += cf.ta[j][p] * nsum(0, 2 * p + 1) + cf.tb[j][p] * nsum(1, 2 * p + 1);
+                        sre += cf.ta[j][p] * dsum(0, 2 * p) + cf.tb[j][p] * dsum(1, 2 * p);
+                        sim += cf.ta[j][p] * dsum(0, 2 * p + 1) + cf.tb[j][p] * dsum(1, 2 * p + 1);
+                    }
                 }
-                FT[j * plane + (size_t)r * (lmax + 1) + m] = make_float2((float)nre, (float)nim);
+                FT[j * plane + on] = make_float2((float)nre, (float)nim);
                 if (rs != r) {
                     const double sg = (j & 1) ? -1.0 : 1.0;
-                    FT[j * plane + (size_t)rs * (lmax + 1) + m] = make_float2((float)(sg * sre), (float)(sg * sim));
+                    FT[j * plane + os] = make_float2((float)(sg * sre), (float)(sg * sim));
                 }
             }
             // lensing potential: the lam sums (j = 0) and lam' sums (j = 1)
@@ -403,39 +421,48 @@ __global__ __launch_bounds__(256) void k_legendre_tab(
                 const int c = C.n1 - C.nP;
 #pragma unroll
                 for (int j = 0; j < 2; ++j) {
-                    FP[j * plane + (size_t)r * (lmax + 1) + m] = make_double2(nsum(j, c), nsum(j, c + 1));
+                    FP[j * plane + on] = act ? make_double2(nsum(j, c), nsum(j, c + 1)) : make_double2(0.0, 0.0);
                     if (rs != r) {
                         const double sg = j ? -1.0 : 1.0;
-                        FP[j * plane + (size_t)rs * (lmax + 1) + m] =
-                            make_double2(sg * dsum(j, c), sg * dsum(j, c + 1));
+                        FP[j * plane + os] =
+                            act ? make_double2(sg * dsum(j, c), sg * dsum(j, c + 1)) : make_double2(0.0, 0.0);
                     }
                 }
             }
-        } else if constexpr (POL) {
+        }
+    }
+    if constexpr (POL) {
+        const bool act = m <= mc + 2;
+        CoefP<N> cf;
+        if (act) coefficients_P<N>(th, m, cf);
+        for (int bb = 0; bb < NBAT; ++bb) {
+            const float *S = S0 + (size_t)bb * 4 * C.n1;
+            auto nsum = [&](int type, int c) { return (double)S[type * 2 * C.n1 + c] + (double)S[(type * 2 + 1) * C.n1 + c]; };
+            auto dsum = [&](int type, int c) { return (double)S[type * 2 * C.n1 + c] - (double)S[(type * 2 + 1) * C.n1 + c]; };
             float2 *FQ = batch.FQ[bb], *FU = batch.FU[bb];
-            CoefP<N> cf;
-            coefficients_P<N>(theta[r], m, cf);
 #pragma unroll
             for (int j = 0; j <= N; ++j) {
                 double ewn[2] = {0, 0}, exn[2] = {0, 0}, bwn[2] = {0, 0}, bxn[2] = {0, 0};
                 double ews[2] = {0, 0}, exs[2] = {0, 0}, bws[2] = {0, 0}, bxs[2] = {0, 0};
+                if (act) {
 #pragma unroll
-                for (int p = 0; p <= C.PS; ++p)
+                    for (int p = 0; p <= C.PS; ++p)
 #pragma unroll
-                    for (int ri = 0; ri < 2; ++ri) {
-                        const int ce = C.nT + 2 * p + ri;
-                        ewn[ri] += cf.wa[j][p] * nsum(0, ce) + cf.wb[j][p] * nsum(1, ce);
-                        exn[ri] += cf.xa[j][p] * nsum(0, ce) + cf.xb[j][p] * nsum(1, ce);
-                        ews[ri] += cf.wa[j][p] * dsum(0, ce) + cf.wb[j][p] * dsum(1, ce);
-                        exs[ri] += cf.xa[j][p] * dsum(0, ce) + cf.xb[j][p] * dsum(1, ce);
-                        if constexpr (HASB) {
-                            const int cb_ = C.nT + C.nE + 2 * p + ri;
-                            bwn[ri] += cf.wa[j][p] * nsum(0, cb_) + cf.wb[j][p] * nsum(1, cb_);
-                            bxn[ri] += cf.xa[j][p] * nsum(0, cb_) + cf.xb[j][p] * nsum(1, cb_);
-                            bws[ri] += cf.wa[j][p] * dsum(0, cb_) + cf.wb[j][p] * dsum(1, cb_);
-                            bxs[ri] += cf.xa[j][p] * dsum(0, cb_) + cf.xb[j][p] * dsum(1, cb_);
+                        for (int ri = 0; ri < 2; ++ri) {
+                            const int ce = C.nT + 2 * p + ri;
+                            ewn[ri] += cf.wa[j][p] * nsum(0, ce) + cf.wb[j][p] * nsum(1, ce);
+                            exn[ri] += cf.xa[j][p] * nsum(0, ce) + cf.xb[j][p] * nsum(1, ce);
+                            ews[ri] += cf.wa[j][p] * dsum(0, ce) + cf.wb[j][p] * dsum(1, ce);
+                            exs[ri] += cf.xa[j][p] * dsum(0, ce) + cf.xb[j][p] * dsum(1, ce);
+                            if constexpr (HASB) {
+                                const int cb_ = C.nT + C.nE + 2 * p + ri;
+                                bwn[ri] += cf.wa[j][p] * nsum(0, cb_) + cf.wb[j][p] * nsum(1, cb_);
+                                bxn[ri] += cf.xa[j][p] * nsum(0, cb_) + cf.xb[j][p] * nsum(1, cb_);
+                                bws[ri] += cf.wa[j][p] * dsum(0, cb_) + cf.wb[j][p] * dsum(1, cb_);
+                                bxs[ri] += cf.xa[j][p] * dsum(0, cb_) + cf.xb[j][p] * dsum(1, cb_);
+                            }
                         }
-                    }
+                }
                 const double sg = (j & 1) ? -1.0 : 1.0;
 #pragma unroll
                 for (int ri = 0; ri < 2; ++ri) {
@@ -444,13 +471,11 @@ __global__ __launch_bounds__(256) void k_legendre_tab(
                     exs[ri] *= -sg;
                     bxs[ri] *= -sg;
                 }
-                const size_t on = j * plane + (size_t)r * (lmax + 1) + m;
-                FQ[on] = make_float2((float)(-(ewn[0] - bxn[1])), (float)(-(ewn[1] + bxn[0])));
-                FU[on] = make_float2((float)(-exn[1] - bwn[0]), (float)(exn[0] - bwn[1]));
+                FQ[j * plane + on] = make_float2((float)(-(ewn[0] - bxn[1])), (float)(-(ewn[1] + bxn[0])));
+                FU[j * plane + on] = make_float2((float)(-exn[1] - bwn[0]), (float)(exn[0] - bwn[1]));
                 if (rs != r) {
-                    const size_t os = j * plane + (size_t)rs * (lmax + 1) + m;
-                    FQ[os] = make_float2((float)(-(ews[0] - bxs[1])), (float)(-(ews[1] + bxs[0])));
-                    FU[os] = make_float2((float)(-exs[1] - bws[0]), (float)(exs[0] - bws[1]));
+                    FQ[j * plane + os] = make_float2((float)(-(ews[0] - bxs[1])), (float)(-(ews[1] + bxs[0])));
+                    FU[j * plane + os] = make_float2((float)(-exs[1] - bws[0]), (float)(exs[0] - bws[1]));
                 }
             }
         }
@@ -481,12 +506,22 @@ hipError_t gemm_launch(Plan &p, const TabBatch &b, int part)
                                (float *)p.colexp.ptr);
             return hipGetLastError();
         }
-        const int ngrp = (p.ntile + 3) / 4;
-        const int m8 = (p.lmax + 1 + 7) / 8;
-        hipLaunchKernelGGL((k_legendre_tab<BF, SPLIT, N, POL, HASB, NBAT>), dim3(8 * m8 * ngrp), dim3(256), 0,
-                           p.stream, p.lmax, p.ntheta, p.nrp, p.rpole, p.ntile, ngrp, (const double *)p.theta.ptr,
-                           (const int *)p.mcut.ptr, (const int64_t *)p.moff.ptr, (const uint4 *)p.tab.ptr,
-                           (const int *)p.kstart.ptr, (const uint4 *)p.rhs.ptr, (const float *)p.colexp.ptr, b);
+        if (part == 1) {
+            const int ngrp = (p.ntile + 3) / 4;
+            const int m8 = (p.lmax + 1 + 7) / 8;
+            hipLaunchKernelGGL((k_legendre_tab<BF, SPLIT, N, POL, HASB, NBAT>), dim3(8 * m8 * ngrp), dim3(256), 0,
+                               p.stream, p.lmax, p.nrp, p.rpole, p.ntile, ngrp, (const int *)p.mcut.ptr,
+                               (const int64_t *)p.moff.ptr, (const uint4 *)p.tab.ptr, (const int *)p.kstart.ptr,
+                               (const uint4 *)p.rhs.ptr, (const float *)p.colexp.ptr, (float *)p.tabsum.ptr);
+            return hipGetLastError();
+        }
+        const int nrn = p.nrp - p.rpole;
+        if ((size_t)(p.lmax + 1) * nrn * NBAT * 4 * cols_of(N, POL, HASB, true).n1 * sizeof(float) > p.tabsum.bytes)
+            return hipErrorInvalidValue;
+        dim3 grid((p.lmax + 1 + 63) / 64, (nrn + 3) / 4);
+        hipLaunchKernelGGL((k_tab_epi<N, POL, HASB, NBAT>), grid, dim3(256), 0, p.stream, p.lmax, p.ntheta, p.nrp,
+                           p.rpole, (const double *)p.theta.ptr, (const int *)p.mcut.ptr,
+                           (const float *)p.tabsum.ptr, b);
         return hipGetLastError();
     }
 }
@@ -547,6 +582,17 @@ int tab_rhs_blocks(int order, bool pol, int batch)
         nb = std::max(nb, (g * n1 + 31) / 32);
     }
     return nb;
+}
+
+size_t tab_sum_bytes(int lmax, int nrn, int order, bool pol, int batch)
+{
+    size_t cols = 0;
+    for (int hb = 0; hb < 2; ++hb) {
+        if (hb && !pol) break;
+        const int g = std::min(std::max(batch, 1), tab_max_batch(order, pol, hb != 0));
+        cols = std::max(cols, (size_t)g * cols_of(order, pol, hb != 0, true).n1);
+    }
+    return (size_t)(lmax + 1) * (size_t)(nrn > 0 ? nrn : 0) * 4 * cols * sizeof(float);
 }
 
 size_t tab_rhs_bytes(int lmax, bool split, int nblocks)

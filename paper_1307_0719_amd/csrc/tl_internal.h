@@ -90,6 +90,7 @@ struct Plan {
     DevBuf kstart;    // int [lmax+1][ntile] first non-empty 32-l chunk
     DevBuf rhs;       // table-GEMM right-hand sides of one call, B-operand layout
     DevBuf colexp;    // float [lmax+1][32 * rhs_nb] power-of-two column scales (FP16)
+    DevBuf tabsum;    // float column sums of the table GEMM [lmax+1][nrp-rpole][batch][4][n1]
     size_t rhs_nb = 0;  // 32-column blocks the rhs buffer holds per chunk
 
     // work buffers
@@ -147,8 +148,10 @@ int tab_max_batch(int order, bool pol, bool hasb);
 size_t tab_bytes(int lmax, int ntile, bool split, std::vector<int64_t> &moff);
 int tab_rhs_blocks(int order, bool pol, int batch);
 size_t tab_rhs_bytes(int lmax, bool split, int nblocks);
+size_t tab_sum_bytes(int lmax, int nrn, int order, bool pol, int batch);
 hipError_t launch_build_tab(Plan &p);
 // part 0: right-hand sides of the batch (k_tab_rhs); part 1: the GEMM
+// (column sums); part 2: its epilogue (rows of the theta-derivatives)
 hipError_t launch_legendre_tab(Plan &p, const TabBatch &b, int part);
 // on-the-fly reduced-precision harmonic kernel (legendre_lp.hip)
 int lp_max_batch(int order, bool pol, bool hasb);
@@ -157,7 +160,10 @@ size_t lp_groups(int lmax, std::vector<int64_t> &goff);
 size_t lp_rhs_bytes(int lmax, bool split, int nblocks);
 hipError_t launch_legendre_lp(Plan &p, const TabBatch &b, int part);
 // Stage numbers of the per-kernel profile (one kernel per stage).
-enum Stage { ST_DEFL_LEG = 0, ST_DEFL_FFT, ST_LEG_T, ST_LEG_QU, ST_LEG_MFMA, ST_TAB_RHS, ST_TAB_GEMM, ST_FFT, ST_REMAP, ST_CNN };
+enum Stage {
+    ST_DEFL_LEG = 0, ST_DEFL_FFT, ST_LEG_T, ST_LEG_QU, ST_LEG_MFMA, ST_TAB_RHS, ST_TAB_GEMM, ST_FFT, ST_REMAP, ST_CNN,
+    ST_TAB_EPI
+};
 
 // ---- learned remainder correction (cnn.hip) ----
 constexpr int kCnnTrain = 32 * 20 * 9 + 32 + 32 * 32 * 9 + 32 + 3 * 32 + 3;  // trainable parameters

@@ -38,13 +38,13 @@ EXPORTS = [
 CNN_NTRAIN = 15139
 CNN_NPARAM = 15142
 STAGES = ["defl_legendre", "defl_fft", "legendre_T", "legendre_QU", "legendre_mfma", "tab_rhs", "legendre_tab",
-          "ring_fft", "remap", "cnn"]
+          "ring_fft", "remap", "cnn", "tab_epi"]
 QUERY_KEYS = {"rpole": 0, "elems": 1, "elems_caps": 2, "tab_chunks": 3, "tab_chunk_bytes": 4, "defl_folded": 5}
 # kernel each stage launches
 STAGE_KERNELS = {"defl_legendre": "k_legendre_scalar", "defl_fft": "k_ring_fft", "legendre_T": "k_legendre_scalar",
                  "legendre_QU": "k_legendre_spin", "legendre_mfma": "k_legendre_mfma", "tab_rhs": "k_tab_rhs",
                  "legendre_tab": "k_legendre_tab", "ring_fft": "k_ring_fft", "remap": "k_remap",
-                 "cnn": "k_cnn_forward"}
+                 "cnn": "k_cnn_forward", "tab_epi": "k_tab_epi"}
 
 
 class TaylensError(RuntimeError):
