@@ -128,10 +128,51 @@ __global__ __launch_bounds__(64) void k_build_tab(int lmax, int nrp, int rbeg, i
     atomicMin(&kstart[(size_t)m * ntile + tile], first);
 }
 
+// All columns of realization b at degree l (layout of cols_of: T, E, B,
+// the lensing potential), from the per-l factors L = l(l+1) and N_l.
+template <int N, bool POL, bool HASB>
+__device__ __forceinline__ void rhs_row(const TabBatch &batch, int b, size_t idx, double L, double nl,
+                                        double (&v)[cols_of(N, POL, HASB, true).n1])
+{
+    constexpr Cols C = cols_of(N, POL, HASB, true);
+    {
+        const double2 a = batch.T[b][idx];
+        double w = 1.0;
+#pragma unroll
+        for (int p = 0; p <= C.PT; ++p, w *= L) {
+            v[2 * p] = w * a.x;
+            v[2 * p + 1] = w * a.y;
+        }
+    }
+    if constexpr (POL) {
+        const double2 a = batch.E[b][idx];
+        double w = nl;
+#pragma unroll
+        for (int p = 0; p <= C.PS; ++p, w *= L) {
+            v[C.nT + 2 * p] = w * a.x;
+            v[C.nT + 2 * p + 1] = w * a.y;
+        }
+        if constexpr (HASB) {
+            const double2 e = batch.B[b][idx];
+            double u = nl;
+#pragma unroll
+            for (int p = 0; p <= C.PS; ++p, u *= L) {
+                v[C.nT + C.nE + 2 * p] = u * e.x;
+                v[C.nT + C.nE + 2 * p + 1] = u * e.y;
+            }
+        }
+    }
+    const double2 f = batch.P[b] ? batch.P[b][idx] : make_double2(0.0, 0.0);
+    v[C.n1 - 2] = f.x;
+    v[C.n1 - 1] = f.y;
+}
+
 // Right-hand sides of one call, built once per m (one workgroup per m) in
 // the B-operand layout of v_mfma_f32_32x32x16: per (m, 32-l chunk) the blocks
 // [split][column block][parity][k-half][column] of 8 values, so that lane i of
-// a wave loads entry i of a block.  FP16: every column of a given m is
+// a wave loads entry i of a block.  A thread takes one l (the factors L and
+// N_l once) for half of the realizations; 128-l slices pass through LDS to
+// be regrouped into the 8-value entries.  FP16: every column of a given m is
 // scaled by the power of two 2^e that brings its largest |value| to
 // [2^13, 2^14); e goes to colexp[m][column].
 template <bool BF, bool SPLIT, int N, bool POL, bool HASB, int NBAT>
@@ -145,21 +186,43 @@ __global__ __launch_bounds__(256) void k_tab_rhs(int lmax, int ntile, const int6
     constexpr int NB = (NCOLS + 31) / 32;
     constexpr int NSPL = SPLIT ? 2 : 1;
     constexpr int RCH = NSPL * NB * 128;  // uint4 per chunk
+    constexpr int LCH = 128;              // l per LDS slice (four chunks)
+    constexpr int CW = NB * 32 + 2;       // LDS row (columns, padded)
     __shared__ float s_ex[NB * 32];
+    __shared__ T s_v[NSPL][LCH][CW];
     const int m = blockIdx.x;
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63;
     const size_t base = (size_t)m * (2 * lmax + 1 - m) / 2;
     const int nk = (lmax - m + 1 + KC - 1) / KC;
     const int64_t cum = moff[m] / ((int64_t)ntile * NSPL * 256);  // chunks of all m' < m
     uint4 *out = rhs + cum * RCH;
+    auto factors = [&](int l, double &L, double &nl) {
+        L = (double)l * (double)(l + 1);
+        nl = (POL && l >= 2) ? 1.0 / sqrt((double)(l - 1) * l * (double)(l + 1) * (double)(l + 2)) : 0.0;
+    };
 
-    if (!BF) {
-        for (int c = tid; c < NB * 32; c += 256) s_ex[c] = 0.f;
-        __syncthreads();
-        for (int idx = tid; idx < (lmax - m + 1) * NCOLS; idx += 256) {
-            const int l = m + idx / NCOLS, c = idx % NCOLS;
-            const float v = (float)fabs(rhs_value<N, POL, HASB, NBAT, true>(batch, base, lmax, l, c));
-            atomicMax((unsigned *)&s_ex[c], __float_as_uint(v));  // non-negative floats order as uints
+    for (int c = tid; c < NB * 32; c += 256) s_ex[c] = 0.f;
+    __syncthreads();
+    if constexpr (!BF) {
+        // column maxima: per-thread running maxima, wave reduction, LDS max
+        for (int b0 = tid >> 7; b0 < NBAT; b0 += 2) {
+            float mx[C.n1];
+#pragma unroll
+            for (int c = 0; c < C.n1; ++c) mx[c] = 0.f;
+            for (int l = m + (tid & 127); l <= lmax; l += 128) {
+                double L, nl, v[C.n1];
+                factors(l, L, nl);
+                rhs_row<N, POL, HASB>(batch, b0, base + l, L, nl, v);
+#pragma unroll
+                for (int c = 0; c < C.n1; ++c) mx[c] = fmaxf(mx[c], (float)fabs(v[c]));
+            }
+#pragma unroll
+            for (int c = 0; c < C.n1; ++c) {
+                float x = mx[c];
+#pragma unroll
+                for (int off = 32; off > 0; off >>= 1) x = fmaxf(x, __shfl_xor(x, off));
+                if (lane == 0) atomicMax((unsigned *)&s_ex[b0 * C.n1 + c], __float_as_uint(x));  // x >= 0
+            }
         }
         __syncthreads();
         for (int c = tid; c < NB * 32; c += 256) {
@@ -168,31 +231,53 @@ __global__ __launch_bounds__(256) void k_tab_rhs(int lmax, int ntile, const int6
             if (mx > 0.f) frexpf(mx, &ex);  // mx in [2^(ex-1), 2^ex)
             s_ex[c] = (float)(14 - ex);     // stored = value * 2^(14 - ex) < 2^14
         }
-    } else {
-        for (int c = tid; c < NB * 32; c += 256) s_ex[c] = 0.f;
+        __syncthreads();
     }
-    __syncthreads();
     for (int c = tid; c < NB * 32; c += 256) colexp[(size_t)m * NB * 32 + c] = s_ex[c];
 
-    for (int idx = tid; idx < nk * NB * 128; idx += 256) {
-        const int c = idx & 31, hh = (idx >> 5) & 1, p = (idx >> 6) & 1, b = (idx >> 7) % NB, kc = idx / (NB * 128);
-        const int col = b * 32 + c;
-        const double sc = exp2((double)s_ex[col]);
-        T hi8[8], lo8[8];
+    for (int l0 = m; l0 <= lmax; l0 += LCH) {
+        __syncthreads();
+        {
+            const int li = tid & (LCH - 1), l = l0 + li;
+            for (int b0 = tid >> 7; b0 < NBAT; b0 += 2) {
+                double v[C.n1];
+                if (l <= lmax) {
+                    double L, nl;
+                    factors(l, L, nl);
+                    rhs_row<N, POL, HASB>(batch, b0, base + l, L, nl, v);
+                } else {
 #pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            const int l = m + kc * KC + p + 2 * (hh * 8 + k);
-            const float f = opaque((float)(rhs_value<N, POL, HASB, NBAT, true>(batch, base, lmax, l, col) * sc));
-            hi8[k] = (T)f;
-            lo8[k] = (T)(f - (float)hi8[k]);
+                    for (int c = 0; c < C.n1; ++c) v[c] = 0.0;
+                }
+#pragma unroll
+                for (int c = 0; c < C.n1; ++c) {
+                    const int col = b0 * C.n1 + c;
+                    const float f = opaque((float)(v[c] * exp2((double)s_ex[col])));
+                    const T hi = (T)f;
+                    s_v[0][li][col] = hi;
+                    if constexpr (SPLIT) s_v[1][li][col] = (T)(f - (float)hi);
+                }
+            }
+            if (tid < LCH)
+                for (int col = NCOLS; col < NB * 32; ++col)
+#pragma unroll
+                    for (int sp = 0; sp < NSPL; ++sp) s_v[sp][tid][col] = (T)0.f;
         }
-        uint4 w;
-        uint4 *dst = out + (int64_t)kc * RCH + ((b * 2 + p) * 2 + hh) * 32 + c;
-        __builtin_memcpy(&w, hi8, 16);
-        dst[0] = w;
-        if constexpr (SPLIT) {
-            __builtin_memcpy(&w, lo8, 16);
-            dst[NB * 128] = w;
+        __syncthreads();
+        const int kc0 = (l0 - m) / KC;
+        constexpr int PER = RCH;  // uint4 entries per chunk
+        for (int idx = tid; idx < (LCH / KC) * PER; idx += 256) {
+            const int q = idx / PER, w = idx % PER;
+            const int kc = kc0 + q;
+            if (kc >= nk) continue;
+            const int c = w & 31, hh = (w >> 5) & 1, p = (w >> 6) & 1, rest = w >> 7;
+            const int b = rest % NB, sp = rest / NB;
+            T v8[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) v8[k] = s_v[sp][q * KC + p + 2 * (hh * 8 + k)][b * 32 + c];
+            uint4 wv;
+            __builtin_memcpy(&wv, v8, 16);
+            out[(int64_t)kc * RCH + w] = wv;
         }
     }
 }
