@@ -157,7 +157,8 @@ int tl_lens_map_pos(tl_plan plan, const void *alm_T, const void *alm_E, const vo
 
 /* Deflection alpha = grad phi on the grid (Sec. II.A):
  * alpha_theta = d_theta phi, alpha_phi = d_phi phi / sin theta, with the
- * limits +- d_theta d_phi phi on the pole rings.  float64 [ntheta][nphi]. */
+ * limits +- d_theta d_phi phi on the pole rings.  float64 [ntheta][nphi];
+ * direct FP64 recursion and contraction in every precision form. */
 int tl_deflection(tl_plan plan, const void *alm_phi, double *alpha_theta, double *alpha_phi);
 
 /* Harmonic stage: per-ring Fourier coefficients of the theta-derivatives,

@@ -322,10 +322,12 @@ int check_plan(tl_plan plan)
 void *fphi_slot(Plan &p, int q) { return (char *)p.Fphi.ptr + (size_t)q * 2 * p.ntheta * (p.lmax + 1) * 16; }
 
 // lam / lam' sums of the lensing potentials P[0..n) (NULL entries skipped)
-// into fphi_slot(q) on ring pairs [0, rend); realizations share the FP64
-// recursion, several per launch.
-int defl_legendre(Plan &p, int n, const void *const *P, int rend)
+// into fphi_slot(q) by the direct FP64 kernel, realizations sharing the
+// recursion, several per launch: every ring, or with caps_only the polar
+// caps (the table pass has filled the other rings).
+int defl_legendre(Plan &p, int n, const void *const *P, bool caps_only)
 {
+    const int rend = caps_only ? p.rpole : p.nrp;
     const int mx = direct_max(1, false, false, true);
     DirectSet set{};
     auto flush = [&]() -> int {
@@ -365,7 +367,7 @@ int defl_fft(Plan &p, const void *alm_phi, int q)
 int run_deflection(Plan &p, const void *alm_phi)
 {
     const void *P[1] = {alm_phi};
-    int rc = defl_legendre(p, 1, P, p.nrp);
+    int rc = defl_legendre(p, 1, P, false);
     return rc ? rc : defl_fft(p, alm_phi, 0);
 }
 
@@ -1101,7 +1103,7 @@ int tl_lens_map(tl_plan plan, const void *alm_T, const void *alm_E, const void *
         const void *Ts[1] = {alm_T}, *Es[1] = {alm_E}, *Bs[1] = {alm_B}, *Ps[1] = {alm_phi};
         void *Fs[1] = {p.F.ptr};
         if ((rc = run_legendre_many(p, 1, Ts, Es, Bs, Fs, Ps))) return rc;
-        if ((rc = defl_legendre(p, 1, Ps, p.rpole))) return rc;
+        if ((rc = defl_legendre(p, 1, Ps, true))) return rc;
         if ((rc = defl_fft(p, alm_phi, 0))) return rc;
         StageScope sc(p, ST_FFT);
         TL_HIP(launch_fft_jobs(p, p.F.ptr, p.D.ptr, (const FftJob *)p.jobsMain.ptr, p.njobsMain, p.fp64()),
@@ -1188,7 +1190,7 @@ int tl_lens_map_many(tl_plan plan, int32_t n, const void *const *alms, void *con
         // deflection sums of the whole group (outside the caps from the
         // table pass when folded), then per realization: deflection FFT,
         // ring FFTs, remap
-        if ((rc = defl_legendre(p, k, P, fold ? p.rpole : p.nrp))) return rc;
+        if ((rc = defl_legendre(p, k, P, fold))) return rc;
         for (int q = 0; q < k; ++q) {
             if ((rc = defl_fft(p, P[q], q))) return rc;
             {

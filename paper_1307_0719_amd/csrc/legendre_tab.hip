@@ -473,14 +473,33 @@ __global__ __launch_bounds__(256) void k_tab_epi(int lmax, int ntheta, int nrp, 
     const int mc = mcut[r];
     const double th = theta[r];
 
+    // A thread's column sums of one realization: [type*2+parity][column],
+    // read as float2 (columns come in Re / Im pairs) for the columns a phase
+    // needs: [c0, c0 + nc) and, with tail, the potential's last two.
+    constexpr int NT2 = C.nT / 2, NQ2 = (C.nE + C.nB) / 2;
+    auto load_cols = [&](const float *S, int c0, auto &dst, bool tail) {
+        constexpr int W = sizeof(dst[0]) / sizeof(float2);
+#pragma unroll
+        for (int q4 = 0; q4 < 4; ++q4) {
+#pragma unroll
+            for (int i = 0; i < W - (tail ? 1 : 0); ++i)
+                dst[q4][i] = *reinterpret_cast<const float2 *>(S + q4 * C.n1 + c0 + 2 * i);
+            if (tail) dst[q4][W - 1] = *reinterpret_cast<const float2 *>(S + q4 * C.n1 + C.n1 - 2);
+        }
+    };
     {   // T and the lensing potential
         const bool act = m <= mc;
         CoefT<N> cf;
         if (act) coefficients_T<N>(th, m, cf);
         for (int bb = 0; bb < NBAT; ++bb) {
-            const float *S = S0 + (size_t)bb * 4 * C.n1;
-            auto nsum = [&](int type, int c) { return (double)S[type * 2 * C.n1 + c] + (double)S[(type * 2 + 1) * C.n1 + c]; };
-            auto dsum = [&](int type, int c) { return (double)S[type * 2 * C.n1 + c] - (double)S[(type * 2 + 1) * C.n1 + c]; };
+            float2 R[4][NT2 + 1];  // T columns, then the potential's
+            if (act) load_cols(S0 + (size_t)bb * 4 * C.n1, 0, R, true);
+            auto val = [&](int q4, int c) -> double {
+                const int i = c < C.nT ? c >> 1 : NT2;
+                return (c & 1) ? (double)R[q4][i].y : (double)R[q4][i].x;
+            };
+            auto nsum = [&](int type, int c) { return val(type * 2, c) + val(type * 2 + 1, c); };
+            auto dsum = [&](int type, int c) { return val(type * 2, c) - val(type * 2 + 1, c); };
             float2 *FT = batch.FT[bb];
 #pragma unroll
             for (int j = 0; j <= N; ++j) {
@@ -521,9 +540,14 @@ __global__ __launch_bounds__(256) void k_tab_epi(int lmax, int ntheta, int nrp, 
         CoefP<N> cf;
         if (act) coefficients_P<N>(th, m, cf);
         for (int bb = 0; bb < NBAT; ++bb) {
-            const float *S = S0 + (size_t)bb * 4 * C.n1;
-            auto nsum = [&](int type, int c) { return (double)S[type * 2 * C.n1 + c] + (double)S[(type * 2 + 1) * C.n1 + c]; };
-            auto dsum = [&](int type, int c) { return (double)S[type * 2 * C.n1 + c] - (double)S[(type * 2 + 1) * C.n1 + c]; };
+            float2 R[4][NQ2];  // E (and B) columns
+            if (act) load_cols(S0 + (size_t)bb * 4 * C.n1, C.nT, R, false);
+            auto val = [&](int q4, int c) -> double {
+                const int i = (c - C.nT) >> 1;
+                return (c & 1) ? (double)R[q4][i].y : (double)R[q4][i].x;
+            };
+            auto nsum = [&](int type, int c) { return val(type * 2, c) + val(type * 2 + 1, c); };
+            auto dsum = [&](int type, int c) { return val(type * 2, c) - val(type * 2 + 1, c); };
             float2 *FQ = batch.FQ[bb], *FU = batch.FU[bb];
 #pragma unroll
             for (int j = 0; j <= N; ++j) {

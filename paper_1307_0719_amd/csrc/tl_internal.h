@@ -78,8 +78,8 @@ struct Plan {
     DevBuf trig;      // double2 {cos, sin} [nrp] (north rings)
     DevBuf phitab;    // double2 {cos phi_k, sin phi_k} [nphi] + double phi_k [nphi]
     DevBuf phival;    // double [nphi]
-    DevBuf twid64;    // double2 [M]  e^{2 pi i t / M}
-    DevBuf twid32;    // float2  [M]
+    DevBuf twid64;    // double2 [nphi]  e^{2 pi i t / nphi}
+    DevBuf twid32;    // float2  [nphi]
     DevBuf coef0;     // double4 {a, b, c, 0} spin 0, triangular
     DevBuf coef2;     // double4 {a, b(+2), c, 0} spin 2, triangular
     DevBuf start;     // double [3][lmax+1][jtab][nrp]

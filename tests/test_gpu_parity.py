@@ -59,6 +59,25 @@ def test_deflection_fp64(tl, oracle, lmax, ntheta, nphi):
     assert max_rel(t2np(ap), op) < 1e-11
 
 
+@pytest.mark.parametrize("precision", ["fp32", "fp16"])
+@pytest.mark.parametrize("lmax,ntheta,nphi", [(40, 41, 80), (130, 131, 270), (300, 301, 600), (257, 200, 540)])
+def test_deflection_other_forms(tl, oracle, precision, lmax, ntheta, nphi):
+    """Plans of the FP32 and tabulated forms: the deflection entry point keeps
+    the FP64 arithmetic (several ring blocks, a ragged last one).  Bars:
+    relative RMS 3e-6 and max |err| / RMS 5e-5 (the FP32 harmonic-stage bars,
+    far above what FP64 reaches)."""
+    sky = _sky(lmax, 6, rms_pix=2.0, ntheta=ntheta)
+    plan = tl.Plan(lmax, ntheta, nphi, 2, precision, pol=False)
+    at, ap = plan.deflection(sky.alm_phi)
+    ot, op = oracle.deflection_rings(lmax, sky.alm_phi, ntheta, nphi, np.arange(ntheta), ORACLE_THREADS)
+    for g, ref in ((t2np(at), ot), (t2np(ap), op)):
+        err = g - ref
+        rms = np.sqrt(np.mean(ref ** 2))
+        print(precision, lmax, ntheta, "rel RMS", np.sqrt(np.mean(err ** 2)) / rms, "max/RMS", np.abs(err).max() / rms)
+        assert np.sqrt(np.mean(err ** 2)) / rms < 3e-6
+        assert np.abs(err).max() / rms < 5e-5
+
+
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 @pytest.mark.parametrize("lmax,ntheta,order,with_b", [
     (37, 38, 3, True), (37, 75, 5, False), (130, 129, 4, True), (70, 200, 8, True), (3, 5, 2, True),
