@@ -108,6 +108,41 @@ def stage_work(w, order, form, q, hasb, n):
     return res
 
 
+def sources_digest():
+    """sha256 over the kernel sources (file name, then bytes, sorted)."""
+    import glob
+    import hashlib
+
+    h = hashlib.sha256()
+    for fn in sorted(glob.glob(os.path.join(os.path.dirname(os.path.abspath(__file__)),
+                                            "paper_1307_0719_amd", "csrc", "*"))):
+        h.update(os.path.basename(fn).encode())
+        with open(fn, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(w, form, batch, kernel):
+    """HBM bytes per dispatch of `kernel` from the committed rocprofv3 counter
+    summary of this workload and form (FETCH_SIZE and WRITE_SIZE, each scaled
+    by what they read for a copy of known size), or None when there is no
+    summary, when it names no single matching kernel, or when the kernel
+    sources changed since the counters were taken."""
+    import re
+
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
+                        f"hbm_traffic_{w}_order4_{form}x{batch}.md")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    m = re.search(r"sha256 over paper_1307_0719_amd/csrc/\*[^`]*`([0-9a-f]{64})`", text)
+    if not m or m.group(1) != sources_digest():
+        return None
+    rows = re.findall(r"^\| `(" + re.escape(kernel) + r"<[^`]*)` \| \d+ \| [\d.]+ \| [\d.]+ \| ([\d.e+]+) \|$",
+                      text, re.M)
+    return float(rows[0][1]) if len(rows) == 1 else None
+
+
 def parse_form(s: str):
     prec, _, b = s.partition(":")
     return prec, int(b) if b else 1
@@ -392,7 +427,8 @@ def main():
         "kernel": taylens.STAGE_KERNELS[dom], "stage": dom,
         "bound": "hbm" if kind == "hbm" else ("alu" if kind == "fp64" else "mfma"),
         "achieved": amount / t / scale,
-        "peak": peak / scale, "unit": unit, "frac": amount / t / peak, "traffic": None,
+        "peak": peak / scale, "unit": unit, "frac": amount / t / peak,
+        "traffic": measured_traffic(args.workload, headline[0], headline[1], taylens.STAGE_KERNELS[dom]),
         "work_per_launch": amount / nl, "avg_launch_ms": H["avg_launch"][dom], "launches_per_step": nl,
         "peak_note": "FP64 vector peak (ALU-bound recursion)" if kind == "fp64" else None,
     }
