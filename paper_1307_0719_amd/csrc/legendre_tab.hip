@@ -336,7 +336,7 @@ __global__ __launch_bounds__(256) void k_legendre_tab(int lmax, int nrp, int rbe
         // per wave (the loop is bound by memory latency, not by the matrix
         // cores): loads retire in order, so the chunk consumed now must be
         // the oldest one in flight, for both operands.
-        constexpr int PF = SPLIT ? (NB >= 3 ? 1 : 2) : (NB >= 3 ? 3 : 4);
+        constexpr int PF = SPLIT ? 1 : (NB >= 3 ? 3 : 4);
         constexpr int AW = NSPL * 4;  // uint4 per lane per chunk
         const int ks = __builtin_amdgcn_readfirstlane(kstart[(size_t)m * ntile + tile]);
         const uint4 *blk = tab + (moff[m] + (int64_t)tile * nk * AW * 64) + lane;

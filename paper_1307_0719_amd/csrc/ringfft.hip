@@ -352,14 +352,46 @@ __device__ __forceinline__ void pass_p2(V *__restrict__ buf, V *__restrict__ out
     }
 }
 
-// Length M = 256 RL (RL = 2, 4, 8, 16): 256 threads; passes 16, 16, RL.  Each
-// thread builds Z at m = t + 256 s from F_m and F_{M-m} (L2-resident across the
-// outputs of the job); e^{2 pi i m/N} = e^{2 pi i t/N} e^{2 pi i 256 s/N}.
+// Z at m = t + 256 s (s < RL) from F_m and F_{M-m} (L2-resident across the
+// outputs of the job) for the phi-derivative order K, a compile-time
+// constant: X(m) = scale (i m)^K F_m (0 < m < M), X(0) = Re, X(M) = 2 Re;
+// e^{2 pi i m/N} = e^{2 pi i t/N} e^{2 pi i 256 s/N}.
+template <int K, int M, typename R, typename V>
+__device__ __forceinline__ void build_z(V *__restrict__ buf, const V *__restrict__ F, int L, R scale, V tb,
+                                        const V *__restrict__ twN, int tid)
+{
+    constexpr int RL = M / 256;
+    auto coefX = [&](int m, V f) -> V {
+        R sc = scale;
+        const R mf = (R)m;
+#pragma unroll
+        for (int t = 0; t < K; ++t) sc *= mf;
+        R re = sc * f.x, im = sc * f.y;
+        if constexpr ((K & 3) == 1) { const R t2 = re; re = -im; im = t2; }
+        else if constexpr ((K & 3) == 2) { re = -re; im = -im; }
+        else if constexpr ((K & 3) == 3) { const R t2 = re; re = im; im = -t2; }
+        if (m == 0) return cmk<V>(re, 0);
+        if (m == M) return cmk<V>((R)2 * re, 0);
+        return cmk<V>(re, im);
+    };
+#pragma unroll 2
+    for (int s = 0; s < RL; ++s) {
+        const int m = tid + 256 * s;
+        const int mr = M - m;  // 1..M
+        const V xm = coefX(m, (m <= L) ? F[m] : cmk<V>(0, 0));
+        const V xc = cconj(coefX(mr, (mr <= L) ? F[mr] : cmk<V>(0, 0)));
+        const V tw = cmul(tb, twN[256 * s]);  // e^{2 pi i m/N}
+        buf[lpad(m)] = cadd(cadd(xm, xc), cmuli(cmul(tw, csub(xm, xc))));
+    }
+}
+
+// Length M = 256 RL (RL = 2, 4, 8, 16): 256 threads; passes 16, 16, RL.  The
+// spectrum of each output is built by the code for its phi-derivative order.
+// FP32: four waves per SIMD (the LDS buffer allows four workgroups per CU).
 template <typename R, int M>
-__global__ __launch_bounds__(256) void k_ring_fft_p2(const FftJob *__restrict__ jobs,
-                                                     const typename C2<R>::T *__restrict__ Fbase,
-                                                     R *__restrict__ Dbase, int lmax,
-                                                     const typename C2<R>::T *__restrict__ twN)
+__global__ __launch_bounds__(256, sizeof(R) == 4 ? 4 : 2) void k_ring_fft_p2(
+    const FftJob *__restrict__ jobs, const typename C2<R>::T *__restrict__ Fbase, R *__restrict__ Dbase, int lmax,
+    const typename C2<R>::T *__restrict__ twN)
 {
     using V = typename C2<R>::T;
     constexpr int RL = M / 256;
@@ -373,32 +405,17 @@ __global__ __launch_bounds__(256) void k_ring_fft_p2(const FftJob *__restrict__ 
 
     const V tb = twN[tid];
     for (int q = 0; q < job.nk; ++q) {
-        const int k = job.k[q];
         const R scale = (R)job.scale[q];
-        // X(m) = scale (i m)^k F_m (0 < m < M); X(0) = Re, X(M) = 2 Re
-        auto coefX = [&](int m, V f) -> V {
-            R sc = scale;
-            const R mf = (R)m;
-            for (int t = 0; t < k; ++t) sc *= mf;
-            R re = sc * f.x, im = sc * f.y;
-            switch (k & 3) {
-            case 1: { const R t2 = re; re = -im; im = t2; } break;
-            case 2: re = -re; im = -im; break;
-            case 3: { const R t2 = re; re = im; im = -t2; } break;
-            default: break;
-            }
-            if (m == 0) return cmk<V>(re, 0);
-            if (m == M) return cmk<V>((R)2 * re, 0);
-            return cmk<V>(re, im);
-        };
-#pragma unroll 4
-        for (int s = 0; s < RL; ++s) {
-            const int m = tid + 256 * s;
-            const int mr = M - m;  // 1..M
-            const V xm = coefX(m, (m <= L) ? F[m] : cmk<V>(0, 0));
-            const V xc = cconj(coefX(mr, (mr <= L) ? F[mr] : cmk<V>(0, 0)));
-            const V tw = cmul(tb, twN[256 * s]);  // e^{2 pi i m/N}
-            buf[lpad(m)] = cadd(cadd(xm, xc), cmuli(cmul(tw, csub(xm, xc))));
+        switch (job.k[q]) {  // uniform
+        case 0: build_z<0, M>(buf, F, L, scale, tb, twN, tid); break;
+        case 1: build_z<1, M>(buf, F, L, scale, tb, twN, tid); break;
+        case 2: build_z<2, M>(buf, F, L, scale, tb, twN, tid); break;
+        case 3: build_z<3, M>(buf, F, L, scale, tb, twN, tid); break;
+        case 4: build_z<4, M>(buf, F, L, scale, tb, twN, tid); break;
+        case 5: build_z<5, M>(buf, F, L, scale, tb, twN, tid); break;
+        case 6: build_z<6, M>(buf, F, L, scale, tb, twN, tid); break;
+        case 7: build_z<7, M>(buf, F, L, scale, tb, twN, tid); break;
+        default: build_z<8, M>(buf, F, L, scale, tb, twN, tid); break;
         }
         __syncthreads();
         pass_p2<M, 16, 1, false>(buf, (V *)nullptr, tid, twN);
