@@ -879,14 +879,10 @@ int tl_plan_create(tl_plan *out, int32_t lmax, tl_grid grid, const tl_options *o
     p.stream = (hipStream_t)hip_stream;
     factor_radices(p.nphi / 2, p);
     {
-        // polar caps stay on the direct FP64 kernel: the csc and cot jets of
-        // the L-power epilogue amplify the rounding of the contraction there.
-        // sin theta < 0.15 for the FP32 form and the single 16-bit tables;
-        // the split tables (22- or 16-bit operands, hi and lo) hold their
-        // bars down to sin theta = 0.05 up to order 4 (the amplification
-        // grows with the derivative order).
-        const bool split_tab = (p.precision == TL_BF16X3 || p.precision == TL_FP16X2) && use_tables();
-        const double smin = (split_tab && p.order <= 4) ? 0.05 : 0.15;
+        // polar caps (sin theta < 0.15) stay on the direct FP64 kernel: the
+        // csc and cot jets of the L-power epilogue amplify the rounding of the
+        // contraction there
+        const double smin = 0.15;
         int rp = 1;
         while (rp < p.nrp && std::sin(M_PI * (double)rp / (double)(p.ntheta - 1)) < smin) ++rp;
         p.rpole = rp;

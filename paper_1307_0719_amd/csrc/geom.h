@@ -60,9 +60,10 @@ __device__ __forceinline__ PixLoc locate_pixel(int i, int k, int ntheta, int nph
             const double x0 = st * cp, x1 = st * sp, x2 = ct;
             const double et0 = ct * cp, et1 = ct * sp, et2 = -st;
             const double ep0 = -sp, ep1 = cp;
-            const double u0 = (a_t * et0 + a_p * ep0) / d;
-            const double u1 = (a_t * et1 + a_p * ep1) / d;
-            const double u2 = (a_t * et2) / d;
+            const double id = 1.0 / d;
+            const double u0 = (a_t * et0 + a_p * ep0) * id;
+            const double u1 = (a_t * et1 + a_p * ep1) * id;
+            const double u2 = (a_t * et2) * id;
             double sd, cd;
             sincos(d, &sd, &cd);
             const double y0 = cd * x0 + sd * u0, y1 = cd * x1 + sd * u1, y2 = cd * x2 + sd * u2;
@@ -75,8 +76,9 @@ __device__ __forceinline__ PixLoc locate_pixel(int i, int k, int ntheta, int nph
                 const double t0 = -sd * x0 + cd * u0, t1 = -sd * x1 + cd * u1, t2 = -sd * x2 + cd * u2;
                 double cpp = 1.0, spp = 0.0;
                 if (rho > 0.0) {
-                    cpp = y0 / rho;
-                    spp = y1 / rho;
+                    const double ir = 1.0 / rho;
+                    cpp = y0 * ir;
+                    spp = y1 * ir;
                 }
                 const double ctp = y2, stp = rho;
                 const double tt = t0 * ctp * cpp + t1 * ctp * spp - t2 * stp;  // t . e_theta(x')
@@ -84,9 +86,9 @@ __device__ __forceinline__ PixLoc locate_pixel(int i, int k, int ntheta, int nph
                 // e^{i gamma} = (a_t + i a_p)(tt - i tp) / (d |t|)
                 const double gr = a_t * tt + a_p * tp;
                 const double gi = a_p * tt - a_t * tp;
-                const double nrm = gr * gr + gi * gi;
-                L.cg = (gr * gr - gi * gi) / nrm;
-                L.sg = 2.0 * gr * gi / nrm;
+                const double inrm = 1.0 / (gr * gr + gi * gi);
+                L.cg = (gr * gr - gi * gi) * inrm;
+                L.sg = 2.0 * gr * gi * inrm;
             }
         }
     }

@@ -36,15 +36,13 @@ __global__ __launch_bounds__(256) void k_remap(int ntheta, int nphi, const doubl
     if (k >= nphi) return;
     const size_t idx = (size_t)i * nphi + k;
     const double TWO_PI = 6.283185307179586476925286766559;
-    const double dth_grid = M_PI / (double)(ntheta - 1);
-    const double dph_grid = TWO_PI / (double)nphi;
 
     const PixLoc L = locate_pixel(i, k, ntheta, nphi, theta, trig, phitrig, phival, thsrc ? 0.0 : at[idx],
                                   thsrc ? 0.0 : ap[idx], thsrc, phsrc, idx, naive != 0, POL && rotate);
     const double cg = L.cg, sg = L.sg;
     const int i0 = L.i0, k0 = L.k0;
-    const R u = (R)((L.thp - theta[i0]) / dth_grid);
-    const R v = (R)((L.php - phival[L.kh]) / dph_grid);
+    const R u = (R)((L.thp - theta[i0]) * ((double)(ntheta - 1) / M_PI));
+    const R v = (R)((L.php - phival[L.kh]) * ((double)nphi / TWO_PI));
 
     const size_t plane = (size_t)ntheta * nphi;
     const size_t pix0 = (size_t)i0 * nphi + k0;

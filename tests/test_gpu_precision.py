@@ -142,3 +142,19 @@ def test_deflection_fold_policy(tl):
         plan = tl.Plan(96, 97, 192, 4, prec, pol=True)
         assert plan.query("defl_folded") == want, prec
         plan.close()
+
+
+
+def test_polar_cap_policy(tl):
+    """Ring pairs kept on the direct FP64 kernels: sin theta < 0.15 in every
+    reduced form and order."""
+    def rpole(prec, order):
+        plan = tl.Plan(160, 161, 320, order, prec, pol=True)
+        r = plan.query("rpole")
+        plan.close()
+        return r
+
+    # sin(pi r / 160) < 0.15 for r < 8
+    for prec in ("fp32", "fp16", "fp16x2", "bf16x3"):
+        for order in (2, 4, 6):
+            assert rpole(prec, order) == 8, (prec, order)
