@@ -21,6 +21,7 @@ Prints ONE JSON line.
 from __future__ import annotations
 
 import argparse
+import math
 import json
 import os
 import sys
@@ -310,7 +311,7 @@ def main():
     ap.add_argument("--forms", default="fp32,fp16:5,fp16x2:5",
                     help="comma list of precision[:realizations per step]; fp32 is the speed-up reference")
     ap.add_argument("--headline", default=None, help="form reported as value (default: the last of --forms)")
-    ap.add_argument("--cpu-rings", type=int, default=16, help="output rings in the CPU-oracle sample")
+    ap.add_argument("--cpu-rings", type=int, default=32, help="output rings in the CPU-oracle sample (four bands)")
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the oracle (no errors, no cpu_baseline)")
     ap.add_argument("--copy-calibration", action="store_true", help="only run a 1 GiB device copy (counter scale)")
     ap.add_argument("--no-extras", action="store_true",
@@ -347,15 +348,23 @@ def main():
                  for s in skies]
     npix = w.ntheta * w.nphi
 
-    # oracle on a band of equatorial output rings of realization 0
-    ref, rings, cpu = None, None, None
+    # oracle on four bands of output rings of realization 0: inside the polar
+    # cap (direct FP64 kernels), across the cap boundary (sin theta = 0.15,
+    # where the reduced forms' epilogue amplifies most), mid-latitude, equator
+    ref, rings, cpu, bands = None, None, None, None
     if not args.no_cpu_baseline:
         from oracle import taylens_oracle as orc
 
         ncores = min(16, os.cpu_count() or 1)
-        nr = max(1, args.cpu_rings)
-        c = w.ntheta // 2
-        rings = np.arange(c - nr // 2, c - nr // 2 + nr)
+        nb = max(1, args.cpu_rings // 4)
+        edge = 1
+        while edge < w.ntheta // 2 and math.sin(math.pi * edge / (w.ntheta - 1)) < 0.15:
+            edge += 1
+        starts = {"cap": min(4, edge - nb) if edge > nb else 0, "cap_edge": max(0, edge - nb // 2),
+                  "mid_latitude": w.ntheta // 4, "equator": w.ntheta // 2 - nb // 2}
+        bands = {k: np.arange(v, v + nb) for k, v in starts.items()}
+        rings = np.unique(np.concatenate(list(bands.values())))
+        nr = len(rings)
         s0 = skies[0]
         o0 = time.perf_counter()
         ref = orc.lens_rings(w.lmax, order, w.ntheta, w.nphi, rings, s0.alm_T, s0.alm_E, s0.alm_B, s0.alm_phi,
@@ -363,7 +372,8 @@ def main():
         o1 = time.perf_counter()
         cpu = {
             "value": nr * w.nphi / (o1 - o0), "unit": "pixels/s", "cores": ncores, "kind": "oracle",
-            "sample": f"{nr} output rings ({rings[0]}..{rings[-1]}) of realization 0: deflection on those rings, "
+            "sample": f"{nr} output rings of realization 0 in four bands of {nb} "
+                      f"({', '.join(f'{k} from {v}' for k, v in starts.items())}): deflection on those rings, "
                       f"derivative maps of every source ring they need, remap, Taylor sum, rotation; "
                       f"{o1 - o0:.1f} s, FP64",
         }
@@ -381,6 +391,19 @@ def main():
                 y = ref[f][mask]
                 errs[f] = float(np.sqrt(np.mean((x - y) ** 2)) / np.sqrt(np.mean(y ** 2)))
             r["errs"] = errs
+            # per band (largest field error)
+            r["errs_band"] = {}
+            for bname, br in bands.items():
+                sel = np.isin(rings, br)
+                e = 0.0
+                for f, g in zip(("T", "Q", "U"), r["maps0"]):
+                    if g is None:
+                        continue
+                    mk = mask[sel]
+                    x = g[rings[sel]][mk]
+                    y = ref[f][sel][mk]
+                    e = max(e, float(np.sqrt(np.mean((x - y) ** 2)) / np.sqrt(np.mean(y ** 2))))
+                r["errs_band"][bname] = e
         results[(prec, batch)] = r
 
     def name(f):
@@ -403,6 +426,7 @@ def main():
             "ms_per_map": r["sec"] * 1e3 / f[1],
             "speedup_vs_fp32": (px / (npix / fp32["sec"])) if fp32 else None,
             "rel_rms_err_vs_oracle": r.get("errs"),
+            "rel_rms_err_max_field_by_band": r.get("errs_band"),
             "stages_ms_per_step": {k: round(v, 3) for k, v in r["per_step"].items()},
             "legendre_ms_per_step": leg,
             "legendre_a3_useful_tflops": useful / (leg * 1e-3) / 1e12 if leg else None,
