@@ -275,17 +275,6 @@ __device__ void epilogue(const double (*S)[cols_of(N, HASB).ncol], int half, int
     }
 }
 
-__device__ __forceinline__ unsigned f2u(float x) { return __float_as_uint(x); }
-__device__ __forceinline__ float u2f(unsigned x) { return __uint_as_float(x); }
-
-// Swap upper half of a with lower half of b: a' = [a_lo, b_lo], b' = [a_hi, b_hi].
-__device__ __forceinline__ void swap32(float &a, float &b)
-{
-    auto r = __builtin_amdgcn_permlane32_swap(f2u(a), f2u(b), false, false);
-    a = u2f(r[0]);
-    b = u2f(r[1]);
-}
-
 // LDS of one workgroup: chunk operands during the l loop, epilogue buffer
 // afterwards.
 template <int NC>

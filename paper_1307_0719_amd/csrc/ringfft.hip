@@ -361,8 +361,11 @@ __device__ __forceinline__ void build_z(V *__restrict__ buf, const V *__restrict
                                         const V *__restrict__ twN, int tid)
 {
     constexpr int RL = M / 256;
-    auto coefX = [&](int m, V f) -> V {
-        R sc = scale;
+    // branch-free: loads from a clamped index (inside the row), zeros and the
+    // m = 0 / m = M rules by selects
+    auto coefX = [&](int m) -> V {
+        const V f = F[m <= L ? m : L];
+        R sc = m <= L ? scale : (R)0;
         const R mf = (R)m;
 #pragma unroll
         for (int t = 0; t < K; ++t) sc *= mf;
@@ -370,16 +373,16 @@ __device__ __forceinline__ void build_z(V *__restrict__ buf, const V *__restrict
         if constexpr ((K & 3) == 1) { const R t2 = re; re = -im; im = t2; }
         else if constexpr ((K & 3) == 2) { re = -re; im = -im; }
         else if constexpr ((K & 3) == 3) { const R t2 = re; re = im; im = -t2; }
-        if (m == 0) return cmk<V>(re, 0);
-        if (m == M) return cmk<V>((R)2 * re, 0);
+        im = (m == 0 || m == M) ? (R)0 : im;
+        re = (m == M) ? (R)2 * re : re;
         return cmk<V>(re, im);
     };
 #pragma unroll 2
     for (int s = 0; s < RL; ++s) {
         const int m = tid + 256 * s;
         const int mr = M - m;  // 1..M
-        const V xm = coefX(m, (m <= L) ? F[m] : cmk<V>(0, 0));
-        const V xc = cconj(coefX(mr, (mr <= L) ? F[mr] : cmk<V>(0, 0)));
+        const V xm = coefX(m);
+        const V xc = cconj(coefX(mr));
         const V tw = cmul(tb, twN[256 * s]);  // e^{2 pi i m/N}
         buf[lpad(m)] = cadd(cadd(xm, xc), cmuli(cmul(tw, csub(xm, xc))));
     }
