@@ -468,6 +468,9 @@ __global__ __launch_bounds__(256) void k_tab_epi(int lmax, int ntheta, int nrp, 
     const int nrn = nrp - rbeg;
     const size_t plane = (size_t)ntheta * (lmax + 1);
     const int rs = ntheta - 1 - r;
+    // south ring row; on the equator ring (rs == r) the north value is
+    // stored there again (a select, not a branch around the stores)
+    const bool eq = rs == r;
     const size_t on = (size_t)r * (lmax + 1) + m, os = (size_t)rs * (lmax + 1) + m;
     const float *S0 = sums + ((size_t)m * nrn + (r - rbeg)) * NBAT * 4 * C.n1;
     const int mc = mcut[r];
@@ -513,11 +516,10 @@ __global__ __launch_bounds__(256) void k_tab_epi(int lmax, int ntheta, int nrp, 
                         sim += cf.ta[j][p] * dsum(0, 2 * p + 1) + cf.tb[j][p] * dsum(1, 2 * p + 1);
                     }
                 }
-                FT[j * plane + on] = make_float2((float)nre, (float)nim);
-                if (rs != r) {
-                    const double sg = (j & 1) ? -1.0 : 1.0;
-                    FT[j * plane + os] = make_float2((float)(sg * sre), (float)(sg * sim));
-                }
+                const float2 vn = make_float2((float)nre, (float)nim);
+                const double sg = (j & 1) ? -1.0 : 1.0;
+                FT[j * plane + on] = vn;
+                FT[j * plane + os] = eq ? vn : make_float2((float)(sg * sre), (float)(sg * sim));
             }
             // lensing potential: the lam sums (j = 0) and lam' sums (j = 1)
             // themselves, in the deflection's FP64 rows
@@ -525,12 +527,12 @@ __global__ __launch_bounds__(256) void k_tab_epi(int lmax, int ntheta, int nrp, 
                 const int c = C.n1 - C.nP;
 #pragma unroll
                 for (int j = 0; j < 2; ++j) {
-                    FP[j * plane + on] = act ? make_double2(nsum(j, c), nsum(j, c + 1)) : make_double2(0.0, 0.0);
-                    if (rs != r) {
-                        const double sg = j ? -1.0 : 1.0;
-                        FP[j * plane + os] =
-                            act ? make_double2(sg * dsum(j, c), sg * dsum(j, c + 1)) : make_double2(0.0, 0.0);
-                    }
+                    const double2 vn = act ? make_double2(nsum(j, c), nsum(j, c + 1)) : make_double2(0.0, 0.0);
+                    const double sg = j ? -1.0 : 1.0;
+                    const double2 vs =
+                        act ? make_double2(sg * dsum(j, c), sg * dsum(j, c + 1)) : make_double2(0.0, 0.0);
+                    FP[j * plane + on] = vn;
+                    FP[j * plane + os] = eq ? vn : vs;
                 }
             }
         }
@@ -580,12 +582,12 @@ __global__ __launch_bounds__(256) void k_tab_epi(int lmax, int ntheta, int nrp, 
                     exs[ri] *= -sg;
                     bxs[ri] *= -sg;
                 }
-                FQ[j * plane + on] = make_float2((float)(-(ewn[0] - bxn[1])), (float)(-(ewn[1] + bxn[0])));
-                FU[j * plane + on] = make_float2((float)(-exn[1] - bwn[0]), (float)(exn[0] - bwn[1]));
-                if (rs != r) {
-                    FQ[j * plane + os] = make_float2((float)(-(ews[0] - bxs[1])), (float)(-(ews[1] + bxs[0])));
-                    FU[j * plane + os] = make_float2((float)(-exs[1] - bws[0]), (float)(exs[0] - bws[1]));
-                }
+                const float2 qn = make_float2((float)(-(ewn[0] - bxn[1])), (float)(-(ewn[1] + bxn[0])));
+                const float2 un = make_float2((float)(-exn[1] - bwn[0]), (float)(exn[0] - bwn[1]));
+                FQ[j * plane + on] = qn;
+                FU[j * plane + on] = un;
+                FQ[j * plane + os] = eq ? qn : make_float2((float)(-(ews[0] - bxs[1])), (float)(-(ews[1] + bxs[0])));
+                FU[j * plane + os] = eq ? un : make_float2((float)(-exs[1] - bws[0]), (float)(exs[0] - bws[1]));
             }
         }
     }
