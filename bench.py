@@ -82,7 +82,7 @@ def stage_work(w, order, form, q, hasb, n):
     defl = q["elems_caps"] if q["defl_folded"] else q["elems"]
     ncol = cols(order, w.pol, hasb) + (2 if q["defl_folded"] else 0)
     nrn = (w.ntheta + 1) // 2 - q["rpole"]  # ring pairs outside the caps
-    colsum = n * (cols(order, w.pol, hasb) + 2) * 4 * 4 * nrn * (w.lmax + 1)
+    colsum = n * ncol * 4 * 4 * nrn * (w.lmax + 1)
     out = {
         "defl_legendre": ("fp64", n * direct_flops_per_elem(1, False, False) * defl),
         "defl_fft": ("hbm", n * (2 * rowc * 16 + 2 * npix * 8)),
