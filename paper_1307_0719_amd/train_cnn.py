@@ -9,7 +9,7 @@ Evaluation lenses held-out realizations with order 2 + correction and with
 plain order 6, rotation on, and reports the RMS of each against order 6.
 
 ``python -m paper_1307_0719_amd.train_cnn`` runs the stated configuration:
-200 realizations at lmax 2048 (2049 x 4096 grid, seeds 10000..10199), judged
+200 realizations at lmax 2048 (2049 x 4096 grid, seeds 10000..10199), evaluated
 at lmax 4096 (4097 x 8192, seeds 20000..20009); writes the weights with
 numpy.save.
 """
@@ -137,8 +137,8 @@ def main():
     ap.add_argument("--steps-per-real", type=int, default=20)
     ap.add_argument("--batch-pixels", type=int, default=32768)
     ap.add_argument("--lr", type=float, default=2e-3)
-    ap.add_argument("--judge-lmax", type=int, default=4096)
-    ap.add_argument("--judge-nreal", type=int, default=10)
+    ap.add_argument("--eval-lmax", type=int, default=4096)
+    ap.add_argument("--eval-nreal", type=int, default=10)
     ap.add_argument("--out", default=os.path.join(os.path.dirname(os.path.abspath(__file__)), "cnn_weights.npy"))
     a = ap.parse_args()
     say = lambda m: print(m, flush=True)
@@ -150,13 +150,13 @@ def main():
     res = {"train": {"lmax": a.lmax, "realizations": a.nreal, "steps": a.nreal * a.steps_per_real,
                      "batch_pixels": a.batch_pixels, "seconds": t_train, "final_loss": info["loss_per_realization"][-1],
                      "scales": info["scales"]}}
-    same = evaluate(params, a.lmax, a.lmax + 1, 2 * a.lmax, list(range(20000, 20000 + min(3, a.judge_nreal))))
+    same = evaluate(params, a.lmax, a.lmax + 1, 2 * a.lmax, list(range(20000, 20000 + min(3, a.eval_nreal))))
     res["held_out_same_grid"] = same
     say(json.dumps({"held_out_same_grid": same}))
-    if a.judge_lmax:
-        J = a.judge_lmax
-        res["judge"] = evaluate(params, J, J + 1, 2 * J, list(range(20000, 20000 + a.judge_nreal)))
-        res["judge"]["lmax"] = J
+    if a.eval_lmax:
+        J = a.eval_lmax
+        res["eval"] = evaluate(params, J, J + 1, 2 * J, list(range(20000, 20000 + a.eval_nreal)))
+        res["eval"]["lmax"] = J
     print(json.dumps(res))
 
 

@@ -1,5 +1,5 @@
 """What the trained correction gains over the plain order-2 Taylor sum
-(marked gpu).  The judge of both is the method itself at order 6: the RMS of
+(marked gpu).  Both are measured against the method itself at order 6: the RMS of
 (order 2 + correction - order 6) against that of (order 2 - order 6), over
 every pixel of held-out skies (seeds 20000+, never used in training).
 
