@@ -308,7 +308,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="TP4096")
     ap.add_argument("--order", type=int, default=None)
-    ap.add_argument("--forms", default="fp32,fp16:5,fp16x2:5",
+    ap.add_argument("--forms", default="fp32,fp16:6,fp16x2:6",
                     help="comma list of precision[:realizations per step]; fp32 is the speed-up reference")
     ap.add_argument("--headline", default=None, help="form reported as value (default: the last of --forms)")
     ap.add_argument("--cpu-rings", type=int, default=32, help="output rings in the CPU-oracle sample (four bands)")

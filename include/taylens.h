@@ -91,7 +91,7 @@ typedef struct {
                               (reflected over the poles; pole rings stay geodesic;
                               no rotation).  0: geodesic displacement.             */
     int32_t batch;         /* realizations per harmonic-stage pass for the tabulated
-                              forms (tl_lens_map_many): 0 or 1 = one; at most 5
+                              forms (tl_lens_map_many): 0 or 1 = one; at most 6
                               (4 on the fly), fewer for high orders (error if too
                               many).  Must be
                               0 or 1 for TL_FP64 / TL_FP32.                        */

@@ -8,11 +8,12 @@
 // FP16/BF16 (optionally as hi + lo), and store it in HBM already arranged as
 // v_mfma_f32_32x32x16 operands: per (m, 32-ring tile, 32-l chunk, type,
 // parity) one 1 KiB block whose lane i holds the 8 values of ring i % 32 at
-// l = l0 + par + 2 (8 (i / 32) + q), q = 0..7.  Each call then streams the
-// blocks (coalesced 16-byte lane loads) against right-hand sides computed in
-// LDS, for up to TL_TAB_MAXBATCH realizations at once -- the FP64 recursion is
-// paid once per plan, the table once per batch.  The epilogue is the FP64
-// L-power epilogue of the FP32 form.
+// l = l0 + par + 2 (8 (i / 32) + q), q = 0..7.  Each call builds the
+// right-hand sides of up to six realizations (k_tab_rhs), streams the blocks
+// against them (k_legendre_tab, coalesced 16-byte lane loads; column sums to
+// HBM) and turns the sums into rows with the FP64 L-power epilogue
+// (k_tab_epi) -- the FP64 recursion is paid once per plan, the table once per
+// batch.
 //
 // Precision forms: FP16 / BF16 store one table and take one MFMA per
 // product; BF16X3 / FP16X2 store hi and lo tables and take hi*hi + hi*lo +
@@ -646,6 +647,7 @@ hipError_t gemm_nbat(Plan &p, const TabBatch &b, int part)
     case 3: return gemm_launch<BF, SPLIT, N, POL, HASB, 3>(p, b, part);
     case 4: return gemm_launch<BF, SPLIT, N, POL, HASB, 4>(p, b, part);
     case 5: return gemm_launch<BF, SPLIT, N, POL, HASB, 5>(p, b, part);
+    case 6: return gemm_launch<BF, SPLIT, N, POL, HASB, 6>(p, b, part);
     default: return hipErrorInvalidValue;
     }
 }
@@ -679,7 +681,7 @@ int tab_max_batch(int order, bool pol, bool hasb)
     if (order > 6) return 0;
     const int n1 = cols_of(order, pol, hasb, true).n1;
     int nb = 0;
-    while (nb < 5 && ((nb + 1) * n1 + 31) / 32 <= 4) ++nb;
+    while (nb < kTabMaxBatch && ((nb + 1) * n1 + 31) / 32 <= 4) ++nb;
     return nb;
 }
 

@@ -38,7 +38,7 @@ struct FftJob {
 };
 
 // Realizations handled by one pass of the table GEMM (reduced-precision forms).
-constexpr int kTabMaxBatch = 5;
+constexpr int kTabMaxBatch = 6;
 struct TabBatch {
     int n;
     const double2 *T[kTabMaxBatch];

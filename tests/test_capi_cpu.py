@@ -42,7 +42,7 @@ def _create(tl, lmax, ntheta, nphi, order=3, prec=1, pol=1, rotate=1, naive=0, b
 
 @pytest.mark.parametrize("args,code", [
     ((-1, 3, 4), -1), ((10, 1, 20), -1), ((10, 11, 19), -1), ((10, 11, 18), -1), ((10, 11, 22), -2),
-    ((10, 11, 20, 9), -1), ((10, 11, 20, -1), -1), ((10, 11, 20, 3, 7), -1), ((10, 11, 20, 7, 4), -2), ((10, 11, 20, 4, 4, 1, 1, 0, 6), -1),
+    ((10, 11, 20, 9), -1), ((10, 11, 20, -1), -1), ((10, 11, 20, 3, 7), -1), ((10, 11, 20, 7, 4), -2), ((10, 11, 20, 4, 4, 1, 1, 0, 7), -1),
     ((10, 11, 20, 3, 1, 2), -1), ((10, 11, 20, 3, 1, 1, 5), -1), ((10, 11, 20, 3, 1, 1, 1, 3), -1),
     ((10, 11, 20, 3, 1, 1, 0, 0, 2), -1), ((10, 11, 20, 3, 1, 1, 0, 0, 0, -5), -1),
     ((64, 65, 128, 3, 1, 1, 1, 0, 0, 1000), -4)])

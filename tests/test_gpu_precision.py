@@ -80,7 +80,7 @@ def test_tab_lens_map(tl, oracle, precision):
         assert e < MAP_TOL[precision], (f, e)
 
 
-@pytest.mark.parametrize("precision,batch", [("fp16", 3), ("bf16x3", 2), ("fp16", 4), ("bf16", 4)])
+@pytest.mark.parametrize("precision,batch", [("fp16", 3), ("bf16x3", 2), ("fp16", 4), ("bf16", 4), ("fp16x2", 6)])
 def test_lens_map_many_equals_single_calls(tl, precision, batch):
     lmax, ntheta, nphi, order = 96, 97, 192, 4
     skies = [_sky(lmax, 90 + i) for i in range(batch + 1)]
