@@ -352,47 +352,77 @@ __device__ __forceinline__ void pass_p2(V *__restrict__ buf, V *__restrict__ out
     }
 }
 
-// Z at m = t + 256 s (s < RL) from F_m and F_{M-m} (L2-resident across the
-// outputs of the job) for the phi-derivative order K, a compile-time
-// constant: X(m) = scale (i m)^K F_m (0 < m < M), X(0) = Re, X(M) = 2 Re;
-// e^{2 pi i m/N} = e^{2 pi i t/N} e^{2 pi i 256 s/N}.
+// X(m) = scale (i m)^K F_m for 0 < m < M, X(0) = Re, X(M) = 2 Re, zero past
+// the row end L (f holds F at the clamped index), for the phi-derivative order
+// K, a compile-time constant.
 template <int K, int M, typename R, typename V>
-__device__ __forceinline__ void build_z(V *__restrict__ buf, const V *__restrict__ F, int L, R scale, V tb,
-                                        const V *__restrict__ twN, int tid)
+__device__ __forceinline__ V coef_x(V f, int m, int L, R scale)
 {
-    constexpr int RL = M / 256;
-    // branch-free: loads from a clamped index (inside the row), zeros and the
-    // m = 0 / m = M rules by selects
-    auto coefX = [&](int m) -> V {
-        const V f = F[m <= L ? m : L];
-        R sc = m <= L ? scale : (R)0;
-        const R mf = (R)m;
+    R sc = m <= L ? scale : (R)0;
+    const R mf = (R)m;
 #pragma unroll
-        for (int t = 0; t < K; ++t) sc *= mf;
-        R re = sc * f.x, im = sc * f.y;
-        if constexpr ((K & 3) == 1) { const R t2 = re; re = -im; im = t2; }
-        else if constexpr ((K & 3) == 2) { re = -re; im = -im; }
-        else if constexpr ((K & 3) == 3) { const R t2 = re; re = im; im = -t2; }
-        im = (m == 0 || m == M) ? (R)0 : im;
-        re = (m == M) ? (R)2 * re : re;
-        return cmk<V>(re, im);
-    };
-#pragma unroll 2
-    for (int s = 0; s < RL; ++s) {
+    for (int t = 0; t < K; ++t) sc *= mf;
+    R re = sc * f.x, im = sc * f.y;
+    if constexpr ((K & 3) == 1) { const R t2 = re; re = -im; im = t2; }
+    else if constexpr ((K & 3) == 2) { re = -re; im = -im; }
+    else if constexpr ((K & 3) == 3) { const R t2 = re; re = im; im = -t2; }
+    im = (m == 0 || m == M) ? (R)0 : im;
+    re = (m == M) ? (R)2 * re : re;
+    return cmk<V>(re, im);
+}
+
+// The row values a thread needs: F at m = t + 256 s and at M - m for s < RL/2
+// (clamped to the row end), and F_{M/2}.
+template <int M, typename V>
+__device__ __forceinline__ void load_pairs(V (&f)[M / 256], V &fmid, const V *__restrict__ F, int L, int tid)
+{
+    constexpr int H = M / 512;
+#pragma unroll
+    for (int s = 0; s < H; ++s) {
+        const int m = tid + 256 * s, mr = M - m;
+        f[s] = F[m <= L ? m : L];
+        f[H + s] = F[mr <= L ? mr : L];
+    }
+    fmid = F[M / 2 <= L ? M / 2 : L];
+}
+
+// Z(m) = (X(m) + conj X(M-m)) + i w^m (X(m) - conj X(M-m)), w = e^{2 pi i/N}:
+// the thread of m < M/2 also writes Z(M - m) (from the same two coefficients,
+// with w^{M-m} = -conj w^m), and thread 0 writes Z(M/2).  The row values come
+// from registers loaded once per job (CACHE) or from the row itself.
+template <int K, int M, bool CACHE, typename R, typename V>
+__device__ __forceinline__ void build_z(V *__restrict__ buf, const V (&f)[M / 256], V fmid, const V *__restrict__ F,
+                                        int L, R scale, V tb, const V *__restrict__ twN, int tid)
+{
+    constexpr int H = M / 512;
+#pragma unroll(CACHE ? H : 2)
+    for (int s = 0; s < H; ++s) {
         const int m = tid + 256 * s;
-        const int mr = M - m;  // 1..M
-        const V xm = coefX(m);
-        const V xc = cconj(coefX(mr));
+        const int mr = M - m;  // M/2 + 1 .. M
+        const V fm = CACHE ? f[s] : F[m <= L ? m : L];
+        const V fr = CACHE ? f[H + s] : F[mr <= L ? mr : L];
+        const V xm = coef_x<K, M>(fm, m, L, scale);
+        const V xr = coef_x<K, M>(fr, mr, L, scale);
         const V tw = cmul(tb, twN[256 * s]);  // e^{2 pi i m/N}
+        const V xc = cconj(xr);
         buf[lpad(m)] = cadd(cadd(xm, xc), cmuli(cmul(tw, csub(xm, xc))));
+        const V xc2 = cconj(xm);
+        const V tw2 = cmk<V>(-tw.x, tw.y);  // e^{2 pi i (M-m)/N}
+        if (m > 0) buf[lpad(mr)] = cadd(cadd(xr, xc2), cmuli(cmul(tw2, csub(xr, xc2))));
+    }
+    if (tid == 0) {
+        const V xh = coef_x<K, M>(CACHE ? fmid : F[M / 2 <= L ? M / 2 : L], M / 2, L, scale);
+        const V xc = cconj(xh);
+        buf[lpad(M / 2)] = cadd(cadd(xh, xc), cmuli(cmul(twN[M / 2], csub(xh, xc))));
     }
 }
 
 // Length M = 256 RL (RL = 2, 4, 8, 16): 256 threads; passes 16, 16, RL.  The
 // spectrum of each output is built by the code for its phi-derivative order.
-// FP32: four waves per SIMD (the LDS buffer allows four workgroups per CU).
+// Two waves per SIMD: the register budget holds an FP32 row for the whole job
+// (its re-reads, once per output, cost more than the lost occupancy).
 template <typename R, int M>
-__global__ __launch_bounds__(256, sizeof(R) == 4 ? 4 : 2) void k_ring_fft_p2(
+__global__ __launch_bounds__(256, 2) void k_ring_fft_p2(
     const FftJob *__restrict__ jobs, const typename C2<R>::T *__restrict__ Fbase, R *__restrict__ Dbase, int lmax,
     const typename C2<R>::T *__restrict__ twN)
 {
@@ -407,18 +437,23 @@ __global__ __launch_bounds__(256, sizeof(R) == 4 ? 4 : 2) void k_ring_fft_p2(
     const int L = lmax;
 
     const V tb = twN[tid];
+    // FP32: the row is read once per job and kept in registers for all of its
+    // outputs; FP64 reads it again per output (register budget)
+    constexpr bool CACHE = sizeof(R) == 4;
+    V f[RL], fmid;
+    if constexpr (CACHE) load_pairs<M>(f, fmid, F, L, tid);
     for (int q = 0; q < job.nk; ++q) {
         const R scale = (R)job.scale[q];
         switch (job.k[q]) {  // uniform
-        case 0: build_z<0, M>(buf, F, L, scale, tb, twN, tid); break;
-        case 1: build_z<1, M>(buf, F, L, scale, tb, twN, tid); break;
-        case 2: build_z<2, M>(buf, F, L, scale, tb, twN, tid); break;
-        case 3: build_z<3, M>(buf, F, L, scale, tb, twN, tid); break;
-        case 4: build_z<4, M>(buf, F, L, scale, tb, twN, tid); break;
-        case 5: build_z<5, M>(buf, F, L, scale, tb, twN, tid); break;
-        case 6: build_z<6, M>(buf, F, L, scale, tb, twN, tid); break;
-        case 7: build_z<7, M>(buf, F, L, scale, tb, twN, tid); break;
-        default: build_z<8, M>(buf, F, L, scale, tb, twN, tid); break;
+        case 0: build_z<0, M, CACHE>(buf, f, fmid, F, L, scale, tb, twN, tid); break;
+        case 1: build_z<1, M, CACHE>(buf, f, fmid, F, L, scale, tb, twN, tid); break;
+        case 2: build_z<2, M, CACHE>(buf, f, fmid, F, L, scale, tb, twN, tid); break;
+        case 3: build_z<3, M, CACHE>(buf, f, fmid, F, L, scale, tb, twN, tid); break;
+        case 4: build_z<4, M, CACHE>(buf, f, fmid, F, L, scale, tb, twN, tid); break;
+        case 5: build_z<5, M, CACHE>(buf, f, fmid, F, L, scale, tb, twN, tid); break;
+        case 6: build_z<6, M, CACHE>(buf, f, fmid, F, L, scale, tb, twN, tid); break;
+        case 7: build_z<7, M, CACHE>(buf, f, fmid, F, L, scale, tb, twN, tid); break;
+        default: build_z<8, M, CACHE>(buf, f, fmid, F, L, scale, tb, twN, tid); break;
         }
         __syncthreads();
         pass_p2<M, 16, 1, false>(buf, (V *)nullptr, tid, twN);
