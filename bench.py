@@ -144,6 +144,26 @@ def measured_traffic(w, form, batch, kernel):
     return float(rows[0][1]) if len(rows) == 1 else None
 
 
+def measured_mfma_busy(w, form, kernel):
+    """Matrix-core busy percentage of `kernel` (rocprofv3's MfmaUtil:
+    SQ_VALU_MFMA_BUSY_CYCLES over the active cycles of all SIMDs) for this
+    workload and form from the committed counter summary, or None when there
+    is none, when it names no single matching row, or when the kernel sources
+    changed since the counters were taken."""
+    import re
+
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", f"mfma_{w}_order4.md")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    m = re.search(r"sha256 over paper_1307_0719_amd/csrc/\*[^`]*`([0-9a-f]{64})`", text)
+    if not m or m.group(1) != sources_digest():
+        return None
+    rows = re.findall(r"^\| " + re.escape(form) + r" \| `" + re.escape(kernel) + r"<[^`]*` \| \d+ \| [\d.]+ \| [\d.]+ \| ([\d.]+) \|",
+                      text, re.M)
+    return float(rows[0]) if len(rows) == 1 else None
+
+
 def parse_form(s: str):
     prec, _, b = s.partition(":")
     return prec, int(b) if b else 1
@@ -495,6 +515,9 @@ def main():
             "rel_rms_err_vs_oracle": hf["rel_rms_err_vs_oracle"],
             "speedup_vs_fp32": hf["speedup_vs_fp32"],
             "legendre_mfma_util_pct": hf["legendre_mfma_util_pct"],
+            "legendre_mfma_busy_pct_counters": next(
+                (measured_mfma_busy(args.workload, name(headline), taylens.STAGE_KERNELS[st])
+                 for st in ("legendre_tab", "legendre_mfma") if st in H["per_step"]), None),
             "pixels": npix,
         },
         "roofline": roof,
