@@ -147,8 +147,14 @@ int tl_lens_map(tl_plan plan, const void *alm_T, const void *alm_E, const void *
                 const void *alm_phi, void *T_out, void *Q_out, void *U_out);
 
 /* Same remap + Taylor sum at caller-given source positions theta_src,
- * phi_src ([ntheta][nphi] float64, theta in [0, pi], any real phi).  No
- * rotation is applied (the positions do not define a transport path). */
+ * phi_src ([ntheta][nphi] float64, theta in [0, pi], any real phi): output
+ * pixel x takes the order-N Taylor series of eq. 5 about the pixel centre
+ * nearest to its source position, in the residual (theta' - theta_i0,
+ * phi' - phi_k0) (Sec. II.B; the nearest-pixel rule of Sec. II.A/B).  No
+ * rotation is applied (the positions do not define a transport path).
+ * Outputs as in tl_lens_map; the call fails with TL_ERR_INVALID before any
+ * launch if a position pointer is NULL.  Positions outside [0, pi] are
+ * clamped to the first / last ring; phi is wrapped. */
 int tl_lens_map_pos(tl_plan plan, const void *alm_T, const void *alm_E, const void *alm_B,
                     const double *theta_src, const double *phi_src, void *T_out, void *Q_out,
                     void *U_out);
@@ -161,29 +167,47 @@ int tl_lens_map_pos(tl_plan plan, const void *alm_T, const void *alm_E, const vo
  * direct FP64 recursion and contraction in every precision form. */
 int tl_deflection(tl_plan plan, const void *alm_phi, double *alpha_theta, double *alpha_phi);
 
-/* Harmonic stage: per-ring Fourier coefficients of the theta-derivatives,
+/* Harmonic stage: per-ring Fourier coefficients of the theta-derivatives
+ * that the Taylor series of eq. 5 needs (its d^j_theta factors; Sec. II.B
+ * obtains the same derivatives by repeated transforms),
  * F[field][j][ring][m] complex (complex128 for TL_FP64, complex64 otherwise),
  * field in (T) or (T, Q, U), j = 0..order, m = 0..lmax:
  *   F^{(j)}_m(theta_i) = sum_l a_lm d^j/dtheta^j lambda_lm(theta_i)   (T)
- * and the Fourier coefficients of the real Q and U maps likewise. */
+ * and the Fourier coefficients of the real Q and U maps likewise
+ * (sum over m of F_m e^{i m phi}, m < 0 by the real-field symmetry).
+ * F_out: caller-owned device buffer of nfield*(order+1)*ntheta*(lmax+1)
+ * complex entries.  NULL alm_T (or alm_E on a polarized plan) or F_out:
+ * TL_ERR_INVALID. */
 int tl_legendre(tl_plan plan, const void *alm_T, const void *alm_E, const void *alm_B,
                 void *F_out);
 
-/* Derivative maps: D[field][jk][ring][pix] (float64 / float32), jk running
+/* Derivative maps, the coefficients of the Taylor series of eq. 5 at every
+ * pixel centre (Sec. II.B: derivatives of T, Q, U up to the chosen order):
+ * D[field][jk][ring][pix] (float64 / float32), jk running
  * over (j, k) with j + k <= order, j-major (j = 0: k = 0..N; j = 1: k = 0..N-1;
  * ...), each map SCALED by dtheta^j dphi^k / (j! k!) with dtheta = pi/(ntheta-1),
- * dphi = 2 pi/nphi:  D = dtheta^j dphi^k/(j!k!) d^j_theta d^k_phi s. */
+ * dphi = 2 pi/nphi:  D = dtheta^j dphi^k/(j!k!) d^j_theta d^k_phi s.
+ * D_out: caller-owned device buffer of nfield*ndmap*ntheta*nphi values,
+ * ndmap = (order+1)(order+2)/2.  NULL inputs: TL_ERR_INVALID. */
 int tl_synth_derivs(tl_plan plan, const void *alm_T, const void *alm_E, const void *alm_B,
                     void *D_out);
 
 /* Remap + Taylor sum + rotation from given scaled derivative maps (layout of
- * tl_synth_derivs) and deflection maps (layout of tl_deflection). */
+ * tl_synth_derivs) and deflection maps (layout of tl_deflection): the source
+ * position x' of each pixel (geodesic displacement by alpha, Sec. II.A, or
+ * the naive rule), its nearest pixel centre and the order-N sum of eq. 5 in
+ * the residual (Sec. II.B), then Q' + iU' = e^{2i gamma}(Q + iU), the
+ * parallel-transport rotation R of eq. 2.  All pointers are caller-owned
+ * device buffers; NULL: TL_ERR_INVALID. */
 int tl_remap(tl_plan plan, const void *D, const double *alpha_theta, const double *alpha_phi,
              void *T_out, void *Q_out, void *U_out);
 
-/* Lens n realizations, plans[i] with coefficient pointers alms[4i..4i+3]
- * (T, E, B, phi) and outputs outs[3i..3i+2] (T, Q, U).  Plans may differ in
- * lmax and grid.  Queued on plans[0]'s stream in one pass. */
+/* Lens n realizations (each as tl_lens_map: eqs. 1, 2, 5), plans[i] with
+ * coefficient pointers alms[4i..4i+3] (T, E, B, phi) and outputs
+ * outs[3i..3i+2] (T, Q, U).  Plans may differ in lmax and grid.  Queued on
+ * plans[0]'s stream in one pass; that stream first waits for the work
+ * already queued on every other plan's stream, and each of those streams
+ * then waits for the pass, so workspace and outputs stay ordered. */
 int tl_lens_map_batch(int32_t n, const tl_plan *plans, const void *const *alms,
                       void *const *outs);
 

@@ -1146,16 +1146,44 @@ int tl_lens_map_batch(int32_t n, const tl_plan *plans, const void *const *alms, 
         if ((rc = check_outputs(plans[i]->p, outs[3 * i], outs[3 * i + 1], outs[3 * i + 2]))) return rc;
     }
     hipStream_t s0 = plans[0]->p.stream;
+    // Every plan's workspace is used on s0 for this pass: s0 first waits for
+    // the work already queued on each other plan stream, and afterwards each
+    // of those streams waits for s0 (outputs and workspace reuse).
+    std::vector<hipStream_t> others;
     for (int i = 0; i < n; ++i) {
+        hipStream_t s = plans[i]->p.stream;
+        if (s != s0 && std::find(others.begin(), others.end(), s) == others.end()) others.push_back(s);
+    }
+    int rc = set_device_of(plans[0]->p);
+    if (rc) return rc;
+    hipEvent_t ev = nullptr;
+    if (!others.empty()) {
+        TL_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming), "event");
+        for (hipStream_t s : others) {
+            hipError_t e = hipEventRecord(ev, s);
+            if (e == hipSuccess) e = hipStreamWaitEvent(s0, ev, 0);
+            if (e != hipSuccess) {
+                (void)hipEventDestroy(ev);
+                return hipfail(e, "stream ordering");
+            }
+        }
+    }
+    for (int i = 0; i < n && rc == TL_OK; ++i) {
         Plan &p = plans[i]->p;
         hipStream_t keep = p.stream;
         p.stream = s0;
-        int rc = tl_lens_map(plans[i], alms[4 * i], alms[4 * i + 1], alms[4 * i + 2], alms[4 * i + 3], outs[3 * i],
-                             outs[3 * i + 1], outs[3 * i + 2]);
+        rc = tl_lens_map(plans[i], alms[4 * i], alms[4 * i + 1], alms[4 * i + 2], alms[4 * i + 3], outs[3 * i],
+                         outs[3 * i + 1], outs[3 * i + 2]);
         p.stream = keep;
-        if (rc) return rc;
     }
-    return TL_OK;
+    if (ev) {
+        // also on failure: work queued before it must still order the streams
+        hipError_t e = hipEventRecord(ev, s0);
+        for (size_t k = 0; e == hipSuccess && k < others.size(); ++k) e = hipStreamWaitEvent(others[k], ev, 0);
+        (void)hipEventDestroy(ev);
+        if (e != hipSuccess && rc == TL_OK) return hipfail(e, "stream ordering");
+    }
+    return rc;
 }
 
 int tl_lens_map_many(tl_plan plan, int32_t n, const void *const *alms, void *const *outs)
@@ -1322,6 +1350,9 @@ int tl_batch_run(tl_batch b, const void *const *alms, void *const *outs)
         TL_HIP(hipGraphLaunch(b->exec, b->bs), "graph launch");
         b->replays += 1;
     } else {
+        // the captured graph's persistent kernel reads b->jobs, rewritten
+        // below: it no longer describes these arguments
+        batch_drop_graph(b);
         std::vector<MfmaJob> J(b->n);
         for (int i = 0; i < b->n; ++i) {
             const Plan &p = b->plans[i]->p;

@@ -148,3 +148,64 @@ def test_batch_refuses_mixed_plans(tl):
     with pytest.raises(tl.TaylensError):
         b.run(a)
     b.close()
+
+
+def test_profiled_eager_run_does_not_leave_a_stale_graph(tl):
+    """A run with profiling on goes eager and rewrites the batch's job table;
+    a later run with the inputs of the captured graph must not replay that
+    graph against the rewritten table."""
+    plans, by = _plans(tl, LMAXES[:4])
+    alms_a = _alms(LMAXES[:4], 360)
+    alms_b = _alms(LMAXES[:4], 370)
+    ref_a = _single(plans, alms_a)
+    ref_b = _single(plans, alms_b)
+    b = tl.Batch(plans, autotune=False, use_graph=True)
+    outs = b.outputs()
+    b.run(alms_a, outs)                  # captures the graph for alms_a
+    torch.cuda.synchronize()
+    _equal(outs, ref_a)
+    for p in by.values():
+        p.profile(True)
+    b.run(alms_b, outs)                  # eager: job table now describes alms_b
+    torch.cuda.synchronize()
+    _equal(outs, ref_b)
+    for p in by.values():
+        p.profile(False)
+    b.run(alms_a, outs)                  # same pointers as the capture
+    torch.cuda.synchronize()
+    _equal(outs, ref_a)
+    b.close()
+
+
+def test_lens_map_batch_orders_other_plan_streams(tl):
+    """Plans on their own streams: the pass on the first plan's stream waits
+    for work queued on the others, and they wait for the pass."""
+    lm = [48, 64]
+    s1 = torch.cuda.Stream()
+    s2 = torch.cuda.Stream()
+    p1 = tl.Plan(lm[0], lm[0] + 1, 2 * lm[0], 3, "fp32", pol=True, stream=s1)
+    p2 = tl.Plan(lm[1], lm[1] + 1, 2 * lm[1], 3, "fp32", pol=True, stream=s2)
+    alms = _alms(lm, 380)
+    ref = []
+    for p, a in zip((p1, p2), alms):
+        r = p.lens_map(*a)
+        torch.cuda.synchronize()
+        ref.append(tuple(x.clone() for x in r))
+    outs = [tuple(torch.empty(L + 1, 2 * L, device="cuda") for _ in range(3)) for L in lm]
+    torch.cuda.synchronize()
+    # work already queued on the second plan's stream that the pass must
+    # follow: a few large products, then a fill of its outputs
+    x = torch.randn(4096, 4096, device="cuda")
+    torch.cuda.synchronize()
+    with torch.cuda.stream(s2):
+        for _ in range(8):
+            x = torch.tanh(x @ x * 1e-2)
+        for o in outs[1]:
+            o.fill_(float("nan"))
+    tl.lens_map_batch([p1, p2], alms, outs)
+    with torch.cuda.stream(s2):
+        keep = [o.clone() for o in outs[1]]   # ordered after the pass
+    torch.cuda.synchronize()
+    _equal(outs, ref)
+    for a, b in zip(keep, ref[1]):
+        assert torch.equal(a, b)

@@ -272,3 +272,78 @@ def test_p9_pole_ring_shares_one_position(oracle):
     at_eps = oracle.phi_synth(F[:, 1, :], 0, nphi)[0]
     np.testing.assert_allclose(ap_eps, a_p[0], atol=1e-5 * np.max(np.abs(a_p[0])))
     np.testing.assert_allclose(at_eps, a_t[0], atol=1e-5 * np.max(np.abs(a_t[0])))
+
+
+def test_p9_naive_rule_reflects_over_the_poles_like_the_meridian(oracle):
+    """With alpha_phi = 0 the displacement runs along the meridian, which is
+    a great circle: pushed across a pole, the naive rule (coordinate
+    addition, reflected) and the geodesic rule must land on the same point,
+    theta' = |theta + a_t| (or 2 pi - (theta + a_t)) on the meridian phi + pi."""
+    rng = np.random.default_rng(12)
+    n = 2000
+    th_n = rng.uniform(0.01, 0.05, n)                 # near the north pole
+    at_n = -th_n - rng.uniform(0.01, 0.05, n)         # crosses it
+    th_s = math.pi - rng.uniform(0.01, 0.05, n)       # near the south pole
+    at_s = (math.pi - th_s) + rng.uniform(0.01, 0.05, n)
+    # and points that do not cross, either way
+    th_m = rng.uniform(0.2, math.pi - 0.2, n)
+    at_m = rng.normal(0, 0.05, n)
+    theta = np.concatenate([th_n, th_s, th_m])
+    a_t = np.concatenate([at_n, at_s, at_m])
+    phi = rng.uniform(0, 2 * math.pi, theta.size)
+    a_p = np.zeros_like(theta)
+    nt, npp = oracle.naive_positions(theta, phi, a_t, a_p)
+    gt, gp, _, _, _ = oracle.geodesic_positions(theta, phi, a_t, a_p)
+    np.testing.assert_allclose(nt, gt, rtol=0, atol=4e-16 * math.pi)
+    dphi = np.angle(np.exp(1j * (npp - gp)))
+    assert np.max(np.abs(dphi)) < 3e-15
+    # the crossing points end on the opposite meridian at the stated colatitude
+    k = slice(0, n)
+    np.testing.assert_allclose(nt[k], -(th_n + at_n), rtol=0, atol=1e-16)
+    np.testing.assert_allclose(np.angle(np.exp(1j * (npp[k] - phi[k] - math.pi))), 0.0, atol=3e-15)
+    k = slice(n, 2 * n)
+    np.testing.assert_allclose(nt[k], 2 * math.pi - (th_s + at_s), rtol=0, atol=1e-15)
+    np.testing.assert_allclose(np.angle(np.exp(1j * (npp[k] - phi[k] - math.pi))), 0.0, atol=3e-15)
+    k = slice(2 * n, 3 * n)
+    np.testing.assert_allclose(nt[k], th_m + at_m, rtol=0, atol=1e-15)
+
+
+@pytest.mark.parametrize("lmax,pol", [(1024, True), (1536, False)])
+def test_p3_high_l_theta_derivatives_from_the_doubled_circle(oracle, lmax, pol):
+    """theta-derivatives j <= 6 of the harmonic sums at high l, against the
+    spectral derivative of the oracle's own j = 0 sums (pinned by the
+    addition theorem and scipy) on the doubled circle: each F_m(theta),
+    continued over the poles as F_m(2 pi - t) = (-1)^m F_m(t) (spin 0 and,
+    for Q/U, spin 2), is a trig polynomial of degree <= lmax, so with
+    ntheta = lmax + 3 rings its Fourier series and all its derivatives are
+    exact.  Rings near both poles (the exponent-scaled underflow range), at
+    mid-latitude and at the equator."""
+    ntheta = lmax + 3
+    nd = 2 * (ntheta - 1)
+    th = oracle.grid_theta(ntheta)
+    aT = skygen.random_alm(lmax, 31)
+    aE = skygen.random_alm(lmax, 32, lmin=2) if pol else None
+    aB = skygen.random_alm(lmax, 33, lmin=2) * 0.5 if pol else None
+    F0 = oracle.ring_coeffs(lmax, 0, th, aT, aE, aB)
+    rings = np.array([1, 2, 3, 5, 9, 17, 40, ntheta // 4, ntheta // 2 - 1, ntheta // 2,
+                      3 * ntheta // 4, ntheta - 10, ntheta - 3, ntheta - 2])
+    J = 6
+    Fj = oracle.ring_coeffs(lmax, J, th[rings], aT, aE, aB)
+    m = np.arange(lmax + 1)
+    p = np.fft.fftfreq(nd, d=1.0 / nd)
+    E = np.exp(1j * np.multiply.outer(th[rings], p))           # [ring, q]
+    worst = 0.0
+    for f in F0:
+        dbl = np.zeros((nd, lmax + 1), np.complex128)
+        dbl[:ntheta] = F0[f][:, 0, :]
+        dbl[ntheta:] = ((-1.0) ** m) * F0[f][nd - np.arange(ntheta, nd), 0, :]
+        c = np.fft.fft(dbl, axis=0) / nd
+        assert np.max(np.abs(c[np.abs(p) > lmax])) < 1e-12 * np.max(np.abs(c))
+        for j in range(J + 1):
+            exact = (E * (1j * p) ** j) @ c                    # [ring, m]
+            got = Fj[f][:, j, :]
+            scale = np.max(np.abs(exact))
+            err = np.max(np.abs(got - exact)) / scale
+            worst = max(worst, err)
+            assert err < 5e-12, (f, j, err)
+    print("worst relative derivative error", worst)
