@@ -890,6 +890,18 @@ int tl_plan_create(tl_plan *out, int32_t lmax, tl_grid grid, const tl_options *o
     p.batch = opt->batch > 1 ? opt->batch : 1;
     p.ntile = (p.nrp - p.rpole + 31) / 32;
     p.tables = p.tabform() && use_tables();
+    if (p.precision == TL_FP16 || p.precision == TL_FP16X2) {
+        // Addition theorem: sum_m |Y_lm|^2 = (2l+1)/4pi and, differentiated
+        // twice at coincident points, sum_m |d_theta Y_lm|^2 = (2l+1)/4pi *
+        // l(l+1)/2, so |lam_lm| and |lam'_lm| stay below these at every theta.
+        // FP16 hi + lo holds 22 bits only while the lo part is normal, i.e.
+        // for |value| >= 2^-3: scale both so their bound sits just below 2^15.
+        const double L = (double)p.lmax;
+        const double b0 = std::sqrt((2.0 * L + 1.0) / (4.0 * M_PI));
+        const double b1 = std::sqrt((2.0 * L + 1.0) / (4.0 * M_PI) * L * (L + 1.0) * 0.5);
+        p.lam_e0 = (int)std::floor(std::log2(32768.0 / b0));
+        p.lam_e1 = b1 > 0.0 ? (int)std::floor(std::log2(32768.0 / b1)) : p.lam_e0;
+    }
     if (p.tabform()) p.rhs_nb = p.tables ? tab_rhs_blocks(p.order, p.pol != 0, p.batch)
                                          : lp_rhs_blocks(p.order, p.pol != 0, p.batch);
 

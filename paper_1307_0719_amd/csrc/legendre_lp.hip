@@ -14,7 +14,8 @@
 // 16..31, zero elsewhere -- and a 32x32 accumulator holds 16 columns for each
 // of the 64 rings.  Products run in FP16 or BF16 (optionally hi + lo split,
 // three products) with FP32 accumulation; FP16 values carry power-of-two
-// scales (lam' x 2^-7, each column of an m scaled into [2^13, 2^14)).  The
+// scales (lam x 2^lam_e0, lam' x 2^lam_e1 from the plan, each column of an m
+// scaled into [2^13, 2^14)).  The
 // per-(ring, m) epilogue applies the FP64 L-power coefficients.  No tables:
 // the recursion costs the same FP64 work per call as the FP32 form, while the
 // matrix work grows with the number of realizations.
@@ -29,7 +30,6 @@ using namespace lp;
 
 constexpr double kHi = 0x1p256;
 constexpr double kDown = 0x1p-512;
-constexpr double kDerivScale = 0x1p-7;  // lam' scale in FP16 operands
 constexpr int GL = 16;                  // l-steps per group (8 per parity)
 constexpr int RPW = 64;                 // ring pairs per wave
 constexpr int WPG = 4;                  // waves per workgroup
@@ -135,7 +135,7 @@ __device__ __forceinline__ floatx16 mma(uint4 a, uint4 b, floatx16 c)
 }
 
 struct LpArgs {
-    int lmax, ntheta, nrp, rbeg, nrb, jtab;
+    int lmax, ntheta, nrp, rbeg, nrb, jtab, e0, e1;
     const double2 *trig;
     const double *theta;
     const double4 *coef0;
@@ -201,7 +201,7 @@ __global__ __launch_bounds__(256) void k_legendre_lp(const LpArgs A, const TabBa
     double l2 = 0.0, d2 = 0.0;
     int e = A.exps[(size_t)m * nrp + rr];
     const size_t base = (size_t)m * (2 * lmax + 1 - m) / 2;
-    const float fscale = BF ? 1.f : (float)kDerivScale;
+    const double lscale = ldexp(1.0, A.e0), fscale = ldexp(1.0, A.e1);
 
     floatx16 acc[NBLK][2][2];
 #pragma unroll
@@ -260,8 +260,8 @@ __global__ __launch_bounds__(256) void k_legendre_lp(const LpArgs A, const TabBa
             if (__all(e == 0)) {
 #pragma unroll
                 for (int s = 0; s < GL; ++s) {
-                    va[s & 1][s >> 1] = (float)l1;
-                    vd[s & 1][s >> 1] = (float)d1 * fscale;
+                    va[s & 1][s >> 1] = (float)(l1 * lscale);
+                    vd[s & 1][s >> 1] = (float)(d1 * fscale);
                     const double nl1 = cfv[s].x * (x * l1) - cfv[s].y * l2;
                     const double nd1 = cfv[s].x * fma(x, d1, -sn * l1) - cfv[s].y * d2;
                     l2 = l1;
@@ -273,8 +273,8 @@ __global__ __launch_bounds__(256) void k_legendre_lp(const LpArgs A, const TabBa
 #pragma unroll
                 for (int s = 0; s < GL; ++s) {
                     const bool use = e == 0;
-                    va[s & 1][s >> 1] = use ? (float)l1 : 0.f;
-                    vd[s & 1][s >> 1] = use ? (float)d1 * fscale : 0.f;
+                    va[s & 1][s >> 1] = use ? (float)(l1 * lscale) : 0.f;
+                    vd[s & 1][s >> 1] = use ? (float)(d1 * fscale) : 0.f;
                     const double nl1 = cfv[s].x * (x * l1) - cfv[s].y * l2;
                     const double nd1 = cfv[s].x * fma(x, d1, -sn * l1) - cfv[s].y * d2;
                     l2 = l1;
@@ -323,7 +323,7 @@ __global__ __launch_bounds__(256) void k_legendre_lp(const LpArgs A, const TabBa
     }
 
     // ---- epilogue: lane = ring; blocks transposed through wave-private LDS ----
-    const double dsc = BF ? 1.0 : 1.0 / kDerivScale;
+    const float usc[2] = {ldexpf(1.f, -A.e0), ldexpf(1.f, -A.e1)};  // exact: powers of two
     const float *cex = A.colexp + (size_t)m * NBLK * 16;
     const double th = A.theta[rr];
     // sums S[type*2+par][c - c0] of global columns c0 .. c0 + NC - 1
@@ -351,7 +351,7 @@ __global__ __launch_bounds__(256) void k_legendre_lp(const LpArgs A, const TabBa
                 const float isc = exp2f(-cex[gc]);
 #pragma unroll
                 for (int q4 = 0; q4 < 4; ++q4)
-                    Sv[q4][c] = sm.tr[wave][lane][q4][gc - b * 16] * isc * ((q4 >> 1) ? (float)dsc : 1.f);
+                    Sv[q4][c] = sm.tr[wave][lane][q4][gc - b * 16] * isc * usc[q4 >> 1];
             }
         }
     };
@@ -456,6 +456,8 @@ hipError_t lp_launch(Plan &p, const TabBatch &b, int part)
         A.rbeg = p.rpole;
         A.nrb = (nr + RPG - 1) / RPG;
         A.jtab = p.jtab;
+        A.e0 = p.lam_e0;
+        A.e1 = p.lam_e1;
         A.trig = (const double2 *)p.trig.ptr;
         A.theta = (const double *)p.theta.ptr;
         A.coef0 = (const double4 *)p.coef0.ptr;

@@ -19,7 +19,9 @@
 // product; BF16X3 / FP16X2 store hi and lo tables and take hi*hi + hi*lo +
 // lo*hi.  FP16 operands are scaled by powers of two: lam' by 2^-7 in the
 // table, every right-hand-side column of a given m by the power of two that
-// brings its largest entry to [2^13, 2^14).
+// brings its largest entry to [2^13, 2^14); lam and lam' by the plan's powers
+// of two 2^lam_e0, 2^lam_e1 (their bounds just below 2^15, so that the lo part
+// of a split value stays a normal FP16 number).
 #include <algorithm>
 
 #include "lpower.h"
@@ -37,14 +39,13 @@ constexpr double kHi = 0x1p256;
 constexpr double kDown = 0x1p-512;
 constexpr int KC = 32;          // l values per table chunk (16 per parity)
 constexpr int TILE = 32;        // ring pairs per table tile
-constexpr double kDerivScale = 0x1p-7;  // lam' scale in FP16 tables
 
 // ------------------------------------------------------------ builder ----
 // One lane per ring pair, 64 lanes = two 32-ring tiles of one m.  Writes, for
 // every 32-l chunk, the blocks [type][parity] (and [hi/lo] when split), and
 // the first chunk holding a non-zero value per (m, tile).
 template <bool BF, bool SPLIT>
-__global__ __launch_bounds__(64) void k_build_tab(int lmax, int nrp, int rbeg, int ntile, int jtab,
+__global__ __launch_bounds__(64) void k_build_tab(int lmax, int nrp, int rbeg, int ntile, int jtab, int e0, int e1,
                                                   const double2 *__restrict__ trig, const double4 *__restrict__ coef0,
                                                   const double *__restrict__ start, const int *__restrict__ exps,
                                                   const int64_t *__restrict__ moff, uint4 *__restrict__ tab,
@@ -64,7 +65,7 @@ __global__ __launch_bounds__(64) void k_build_tab(int lmax, int nrp, int rbeg, i
     constexpr int NSPL = SPLIT ? 2 : 1;
     // block of (m, tile): nk chunks x NSPL x 2 types x 2 parities x 64 lanes x 16 B
     uint4 *blk = tab + (moff[m] + (int64_t)tile * nk * NSPL * 4 * 64);
-    const double dscale = BF ? 1.0 : kDerivScale;
+    const double lscale = ldexp(1.0, e0), dscale = ldexp(1.0, e1);
 
     double l1 = 0, l2 = 0, d1 = 0, d2 = 0;
     int e = 1;
@@ -98,7 +99,7 @@ __global__ __launch_bounds__(64) void k_build_tab(int lmax, int nrp, int rbeg, i
                 e -= 1;
             }
             const bool use = (e == 0) && (l <= lmax);
-            v[0][s & 1][s >> 1] = use ? (float)l1 : 0.0f;
+            v[0][s & 1][s >> 1] = use ? (float)(l1 * lscale) : 0.0f;
             v[1][s & 1][s >> 1] = use ? (float)(d1 * dscale) : 0.0f;
             any |= use && (l1 != 0.0 || d1 != 0.0);
         }
@@ -294,7 +295,7 @@ __global__ __launch_bounds__(256) void k_tab_rhs(int lmax, int ntile, const int6
 // consecutive columns): sums[m][ring pair - rbeg][realization][type*2 +
 // parity][column of the realization]; k_tab_epi turns them into the rows.
 template <bool BF, bool SPLIT, int N, bool POL, bool HASB, int NBAT>
-__global__ __launch_bounds__(256) void k_legendre_tab(int lmax, int nrp, int rbeg, int ntile, int ngrp,
+__global__ __launch_bounds__(256) void k_legendre_tab(int lmax, int nrp, int rbeg, int ntile, int ngrp, int e0, int e1,
                                                       const int *__restrict__ mcut, const int64_t *__restrict__ moff,
                                                       const uint4 *__restrict__ tab, const int *__restrict__ kstart,
                                                       const uint4 *__restrict__ rhs, const float *__restrict__ colexp,
@@ -428,7 +429,7 @@ __global__ __launch_bounds__(256) void k_legendre_tab(int lmax, int nrp, int rbe
 
     if (tile >= ntile) return;
     const int nrn = nrp - rbeg;
-    const float dsc = BF ? 1.f : (float)(1.0 / kDerivScale);
+    const float usc[2] = {ldexpf(1.f, -e0), ldexpf(1.f, -e1)};  // exact: powers of two
     const float *cex = colexp + (size_t)m * NB * 32;
     const int rp0 = tile * TILE + 4 * hl;  // ring pair of accumulator slot 0
     constexpr int RSTR = NBAT * 4 * C.n1;  // floats per ring pair
@@ -447,7 +448,7 @@ __global__ __launch_bounds__(256) void k_legendre_tab(int lmax, int nrp, int rbe
             for (int t = 0; t < 2; ++t)
 #pragma unroll
                 for (int p = 0; p < 2; ++p)
-                    base[row * RSTR + (t * 2 + p) * C.n1] = acc[b][t][p][v] * isc * (t ? dsc : 1.f);
+                    base[row * RSTR + (t * 2 + p) * C.n1] = acc[b][t][p][v] * isc * usc[t];
         }
     }
 }
@@ -599,6 +600,7 @@ hipError_t build_BS(Plan &p)
 {
     dim3 grid((p.ntile + 1) / 2, p.lmax + 1);
     hipLaunchKernelGGL((k_build_tab<BF, SPLIT>), grid, dim3(64), 0, p.stream, p.lmax, p.nrp, p.rpole, p.ntile, p.jtab,
+                       p.lam_e0, p.lam_e1,
                        (const double2 *)p.trig.ptr, (const double4 *)p.coef0.ptr, (const double *)p.start.ptr,
                        (const int *)p.exps.ptr, (const int64_t *)p.moff.ptr, (uint4 *)p.tab.ptr, (int *)p.kstart.ptr);
     return hipGetLastError();
@@ -622,7 +624,8 @@ hipError_t gemm_launch(Plan &p, const TabBatch &b, int part)
             const int ngrp = (p.ntile + 3) / 4;
             const int m8 = (p.lmax + 1 + 7) / 8;
             hipLaunchKernelGGL((k_legendre_tab<BF, SPLIT, N, POL, HASB, NBAT>), dim3(8 * m8 * ngrp), dim3(256), 0,
-                               p.stream, p.lmax, p.nrp, p.rpole, p.ntile, ngrp, (const int *)p.mcut.ptr,
+                               p.stream, p.lmax, p.nrp, p.rpole, p.ntile, ngrp, p.lam_e0, p.lam_e1,
+                               (const int *)p.mcut.ptr,
                                (const int64_t *)p.moff.ptr, (const uint4 *)p.tab.ptr, (const int *)p.kstart.ptr,
                                (const uint4 *)p.rhs.ptr, (const float *)p.colexp.ptr, (float *)p.tabsum.ptr);
             return hipGetLastError();

@@ -65,6 +65,10 @@ struct Plan {
     int batch = 1;    // realizations per table-GEMM pass (reduced-precision forms)
     int ntile = 0;    // 32-ring-pair tiles outside the caps (table forms)
     bool tables = false;  // reduced forms: plan-time tables (else on-the-fly recursion)
+    // FP16 operand scales of lambda and lambda' (powers of two, 2^lam_e0 and
+    // 2^lam_e1; 0 for BF16): the largest value either can take at this lmax
+    // stays below 2^15, so every value that matters keeps a normal lo part
+    int lam_e0 = 0, lam_e1 = 0;
     int64_t cap = 0;
     hipStream_t stream = nullptr;
     int device = 0;

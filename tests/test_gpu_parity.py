@@ -231,15 +231,17 @@ def test_lens_TP_whole_map(tl, oracle, precision, tol):
     _check_maps(got, ref, ["T", "Q", "U"], *tol)
 
 
-@pytest.mark.parametrize("order", [1, 3, 5])
+@pytest.mark.parametrize("order", [1, 2, 3, 4, 5])
 def test_lens_TP2048_fp32_sampled_rings(tl, oracle, order):
-    """T+Q/U lmax=2048 on 2049 x 4096 rings, FP32, sampled output rings
-    (poles, pole-adjacent, mid-latitude, equator) vs the oracle."""
+    """T+Q/U lmax=2048 on 2049 x 4096 rings, FP32, orders 1-5, sampled output
+    rings (poles, pole-adjacent, both sides of the polar-cap boundary,
+    mid-latitude, equator) vs the oracle."""
     w = skygen.WORKLOADS["TP2048"]
     sky = skygen.make_sky(w.lmax, w.seed, pol=True)
     plan = tl.Plan(w.lmax, w.ntheta, w.nphi, order, "fp32", pol=True)
     got = [t2np(x) for x in plan.lens_map(sky.alm_T, sky.alm_E, sky.alm_B, sky.alm_phi)]
-    rings = np.array([0, 1, 3, 700, 1024, 2045, 2048])
+    rp = plan.query("rpole")
+    rings = np.array([0, 1, 3, rp - 2, rp - 1, rp, rp + 1, 700, 1024, w.ntheta - 1 - rp, 2045, 2048])
     ref = oracle.lens_rings(w.lmax, order, w.ntheta, w.nphi, rings, sky.alm_T, sky.alm_E, sky.alm_B,
                             sky.alm_phi, nthreads=ORACLE_THREADS)
     _check_maps([g[rings] for g in got], ref, ["T", "Q", "U"], 1e-5, 1e-4)
@@ -252,7 +254,8 @@ def test_lens_TP4096_fp32_sampled_rings(tl, oracle):
     sky = skygen.make_sky(w.lmax, w.seed, pol=True)
     plan = tl.Plan(w.lmax, w.ntheta, w.nphi, w.order, "fp32", pol=True)
     got = [t2np(x) for x in plan.lens_map(sky.alm_T, sky.alm_E, sky.alm_B, sky.alm_phi)]
-    rings = np.array([0, 2, 1500, 2048, 4096])
+    rp = plan.query("rpole")
+    rings = np.array([0, 2, rp - 1, rp, rp + 1, 1500, 2048, w.ntheta - 1 - rp, 4096])
     ref = oracle.lens_rings(w.lmax, w.order, w.ntheta, w.nphi, rings, sky.alm_T, sky.alm_E, sky.alm_B,
                             sky.alm_phi, nthreads=ORACLE_THREADS)
     _check_maps([g[rings] for g in got], ref, ["T", "Q", "U"], 1e-5, 1e-4)

@@ -100,7 +100,8 @@ def test_tab_TP4096_fp16_sampled(tl, oracle):
     sky = skygen.make_sky(w.lmax, w.seed, pol=True)
     plan = tl.Plan(w.lmax, w.ntheta, w.nphi, w.order, "fp16", pol=True)
     got = [t2np(x) for x in plan.lens_map(sky.alm_T, sky.alm_E, None, sky.alm_phi)]
-    rings = np.array([0, 3, 400, 1500, 2048])
+    rp = plan.query("rpole")
+    rings = np.array([0, 3, rp - 1, rp, rp + 1, 400, 1500, 2048])
     ref = oracle.lens_rings(w.lmax, w.order, w.ntheta, w.nphi, rings, sky.alm_T, sky.alm_E, sky.alm_B,
                             sky.alm_phi, nthreads=ORACLE_THREADS)
     mask = ref["_tie"] > 1e-9
