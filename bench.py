@@ -174,7 +174,11 @@ def run_form(args, w, order, prec, batch, skies_dev):
 
     from paper_1307_0719_amd import taylens
 
+    torch.cuda.synchronize()
+    b0 = time.perf_counter()
     plan = taylens.Plan(w.lmax, w.ntheta, w.nphi, order, prec, pol=w.pol, batch=batch if batch > 1 else 0)
+    torch.cuda.synchronize()
+    plan_s = time.perf_counter() - b0
     q = {k: plan.query(k) for k in taylens.QUERY_KEYS}
     outs = [(plan._maps(), plan._maps() if w.pol else None, plan._maps() if w.pol else None) for _ in range(batch)]
     alms = skies_dev[:batch]
@@ -188,13 +192,19 @@ def run_form(args, w, order, prec, batch, skies_dev):
 
     for _ in range(args.warmup):
         step()
-    # timed region: K whole steps
+    # timed region: K whole steps, an event pair around each on the plan's
+    # stream (torch's current stream); ms per step = the median
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    ev[0].record()
+    for i in range(args.steps):
         step()
+        ev[i + 1].record()
     torch.cuda.synchronize()
-    sec = (time.perf_counter() - t0) / args.steps
+    wall = (time.perf_counter() - t0) / args.steps
+    per = sorted(ev[i].elapsed_time(ev[i + 1]) * 1e-3 for i in range(args.steps))
+    sec = per[len(per) // 2] if len(per) % 2 else 0.5 * (per[len(per) // 2 - 1] + per[len(per) // 2])
     # the same K steps again with a HIP event pair around every kernel launch
     plan.profile(True)
     for _ in range(args.steps):
@@ -209,8 +219,9 @@ def run_form(args, w, order, prec, batch, skies_dev):
     del outs
     plan.close()
     torch.cuda.empty_cache()
-    return {"sec": sec, "per_step": per_step, "avg_launch": avg_launch, "launches": launches, "q": q,
-            "workspace_bytes": ws, "maps0": first}
+    return {"sec": sec, "wall_mean_sec": wall, "step_sec_min_max": (per[0], per[-1]), "per_step": per_step,
+            "avg_launch": avg_launch, "launches": launches, "q": q, "workspace_bytes": ws, "plan_build_s": plan_s,
+            "maps0": first}
 
 
 def bench_batch(args, order=4, n=64):
@@ -308,6 +319,76 @@ def bench_cnn(args, w):
                                   "gain": ev["gain"], "held_out_seed": 20000}}
 
 
+def deflection_check(w, skies, skies_dev):
+    """The deflection field of the step's realizations, from the library's
+    deflection entry point (direct FP64 synthesis of grad phi): its RMS |alpha|
+    over the sphere (ring weights sin theta) against the value Parseval's
+    identity gives for each realization's a_lm, sum_lm l(l+1)|phi_lm|^2 / 4 pi,
+    and the mean over the realizations against the 2.5' the spectra are scaled
+    to (the harness assertion: within 2 %).  Then the residual distribution
+    of realization 0 (the paper's interpolation-distance diagnostic): the
+    displaced position of every pixel relative to its nearest pixel centre,
+    |dtheta|/dtheta_grid and |dphi|/dphi_grid, histogrammed in ten bins of
+    [0, 1/2]; the share of pixels whose nearest centre is another pixel; the
+    99 % quantile of |alpha|."""
+    import numpy as np
+    import torch
+
+    from paper_1307_0719_amd import skygen, taylens
+
+    dev = torch.device("cuda", 0)
+    plan = taylens.Plan(w.lmax, w.ntheta, w.nphi, 1, "fp64", pol=False)
+    th = torch.arange(w.ntheta, device=dev, dtype=torch.float64) * (math.pi / (w.ntheta - 1))
+    wt = torch.sin(th)[:, None]
+    ls, ms = skygen.lm_arrays(w.lmax)
+    mult = np.where(ms == 0, 1.0, 2.0) * ls * (ls + 1.0)
+    rows = []
+    hist = None
+    for i, (s, a) in enumerate(zip(skies, skies_dev)):
+        at, ap = plan.deflection(a[3])
+        a2 = at * at + ap * ap
+        rms = math.sqrt(float((a2 * wt).sum() / (wt.sum() * w.nphi))) / skygen.ARCMIN
+        pars = math.sqrt(float(np.sum(mult * np.abs(s.alm_phi) ** 2)) / (4 * math.pi)) / skygen.ARCMIN
+        rows.append({"seed": s.seed, "rms_arcmin": rms, "parseval_arcmin": pars})
+        if i == 0:
+            ph = torch.arange(w.nphi, device=dev, dtype=torch.float64) * (2 * math.pi / w.nphi)
+            st, ct = torch.sin(th)[:, None], torch.cos(th)[:, None]
+            sp, cp = torch.sin(ph)[None, :], torch.cos(ph)[None, :]
+            d = torch.sqrt(a2)
+            sd = torch.where(d > 0, torch.sin(d) / torch.where(d > 0, d, torch.ones_like(d)), torch.ones_like(d))
+            cd = torch.cos(d)
+            # x' = cos d x + sin d (a_t e_t + a_p e_p) / d
+            xx = cd * st * cp + sd * (at * ct * cp - ap * sp)
+            yy = cd * st * sp + sd * (at * ct * sp + ap * cp)
+            zz = cd * ct - sd * at * st
+            thp = torch.atan2(torch.hypot(xx, yy), zz)
+            php = torch.remainder(torch.atan2(yy, xx), 2 * math.pi)
+            tt = thp / (math.pi / (w.ntheta - 1))
+            tp = php / (2 * math.pi / w.nphi)
+            it, ip = torch.floor(tt + 0.5), torch.floor(tp + 0.5)
+            ut, up = (tt - it).abs(), (tp - ip).abs()
+            moved = ((it != torch.arange(w.ntheta, device=dev)[:, None])
+                     | (torch.remainder(ip, w.nphi) != torch.arange(w.nphi, device=dev)[None, :]))
+            edges = [0.05 * k for k in range(11)]
+            hist = {"bin_edges": edges,
+                    "dtheta_over_pixel": [float(x) for x in torch.histc(ut.float(), 10, 0.0, 0.5).cpu() / ut.numel()],
+                    "dphi_over_pixel": [float(x) for x in torch.histc(up.float(), 10, 0.0, 0.5).cpu() / up.numel()],
+                    "share_moved_to_another_pixel": float(moved.double().mean()),
+                    "alpha_q99_arcmin": float(torch.quantile(d.flatten()[::97].float(), 0.99)) / skygen.ARCMIN,
+                    "max_residual_over_pixel": [float(ut.max()), float(up.max())]}
+            del xx, yy, zz, thp, php, tt, tp, it, ip, ut, up, moved, d
+        del at, ap, a2
+    plan.close()
+    torch.cuda.empty_cache()
+    mean = sum(r["rms_arcmin"] for r in rows) / len(rows)
+    quad_ok = all(abs(r["rms_arcmin"] / r["parseval_arcmin"] - 1) < 5e-3 for r in rows)
+    target_ok = abs(mean / skygen.DEFLECTION_RMS_ARCMIN - 1) <= 0.02
+    res = {"target_arcmin": skygen.DEFLECTION_RMS_ARCMIN, "mean_rms_arcmin": mean, "per_realization": rows,
+           "within_2pct_of_target": target_ok, "matches_parseval_0p5pct": quad_ok, "residuals_realization0": hist}
+    assert quad_ok and target_ok, ("deflection RMS check failed", res)
+    return res
+
+
 def copy_calibration(args):
     """A plain device copy of known size, for scaling the HBM byte counters."""
     import torch
@@ -324,11 +405,11 @@ def copy_calibration(args):
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="TP4096")
     ap.add_argument("--order", type=int, default=None)
-    ap.add_argument("--forms", default="fp32,fp16:6,fp16x2:6",
+    ap.add_argument("--forms", default="fp32,bf16:6,fp16:6,bf16x3:6,fp16x2:6",
                     help="comma list of precision[:realizations per step]; fp32 is the speed-up reference")
     ap.add_argument("--headline", default=None, help="form reported as value (default: the last of --forms)")
     ap.add_argument("--cpu-rings", type=int, default=32, help="output rings in the CPU-oracle sample (four bands)")
@@ -375,7 +456,11 @@ def main():
     if not args.no_cpu_baseline:
         from oracle import taylens_oracle as orc
 
-        ncores = min(16, os.cpu_count() or 1)
+        try:
+            nproc = len(os.sched_getaffinity(0))
+        except AttributeError:
+            nproc = os.cpu_count() or 1
+        ncores = min(16, nproc)
         nb = max(1, args.cpu_rings // 4)
         edge = 1
         while edge < w.ntheta // 2 and math.sin(math.pi * edge / (w.ntheta - 1)) < 0.15:
@@ -390,13 +475,25 @@ def main():
         ref = orc.lens_rings(w.lmax, order, w.ntheta, w.nphi, rings, s0.alm_T, s0.alm_E, s0.alm_B, s0.alm_phi,
                              nthreads=ncores)
         o1 = time.perf_counter()
+        # the same oracle on one thread, on the first four equator rings
+        r1 = bands["equator"][:4]
+        orc.lens_rings(w.lmax, order, w.ntheta, w.nphi, r1, s0.alm_T, s0.alm_E, s0.alm_B, s0.alm_phi, nthreads=1)
+        o2 = time.perf_counter()
         cpu = {
             "value": nr * w.nphi / (o1 - o0), "unit": "pixels/s", "cores": ncores, "kind": "oracle",
+            "nproc": nproc, "os_cpu_count": os.cpu_count(),
             "sample": f"{nr} output rings of realization 0 in four bands of {nb} "
                       f"({', '.join(f'{k} from {v}' for k, v in starts.items())}): deflection on those rings, "
                       f"derivative maps of every source ring they need, remap, Taylor sum, rotation; "
-                      f"{o1 - o0:.1f} s, FP64",
+                      f"{o1 - o0:.1f} s, FP64, {ncores} threads",
+            "value_1core": len(r1) * w.nphi / (o2 - o1),
+            "sample_1core": f"rings {int(r1[0])}..{int(r1[-1])} of the same realization on one thread, "
+                            f"{o2 - o1:.1f} s",
         }
+
+    # the harness assertion on the deflection scale, and the residual
+    # distribution, before anything is timed
+    defl = deflection_check(w, skies[:nmax], skies_dev[:nmax])
 
     results = {}
     for prec, batch in forms:
@@ -451,7 +548,14 @@ def main():
             "legendre_ms_per_step": leg,
             "legendre_a3_useful_tflops": useful / (leg * 1e-3) / 1e12 if leg else None,
             "legendre_mfma_util_pct": 100.0 * useful / (leg * 1e-3) / pk if leg else None,
+            "legendre_mfma_util_pct_after_skip": (100.0 * useful * r["q"]["elems"]
+                                                  / ((w.lmax + 1) * (w.lmax + 2) // 2 * ((w.ntheta + 1) // 2))
+                                                  / (leg * 1e-3) / pk) if leg else None,
             "workspace_gib": r["workspace_bytes"] / 2**30,
+            "workspace_gib_per_map": r["workspace_bytes"] / 2**30 / f[1],
+            "plan_build_s": r["plan_build_s"],
+            "ms_per_step_wall_mean": r["wall_mean_sec"] * 1e3,
+            "ms_per_step_min_max": [x * 1e3 for x in r["step_sec_min_max"]],
         }
         forms_out[name(f)] = ent
 
@@ -461,21 +565,52 @@ def main():
     kind, amount, unit, peak = work[dom]
     from paper_1307_0719_amd import taylens
 
-    # achieved = the stage's work per step over its kernel time per step
-    # (HIP events around every launch); work_per_launch is the mean share of
-    # one launch (the direct kernels take up to four realizations a launch)
+    # achieved = the stage's algorithmic work per step over its kernel time
+    # per step (HIP events around every launch); work_per_launch is the mean
+    # share of one launch (the direct kernels take up to four realizations a
+    # launch).  The matrix-core harmonic kernels count the useful flops of the
+    # plain contraction, 2 (N+1) R per (l, m, ring pair) and realization
+    # (R = 2 + 8 real right-hand sides for T + Q/U; two more rows of the
+    # lensing potential when it rides in the pass), over the elements they
+    # cover below the evanescent cut; "frac_dense" counts every (l, m).
     t = H["per_step"][dom] * 1e-3
-    scale = 1e9 if unit == "GB/s" else 1e12
     nl = H["launches"][dom]
-    roof = {
-        "kernel": taylens.STAGE_KERNELS[dom], "stage": dom,
-        "bound": "hbm" if kind == "hbm" else ("alu" if kind == "fp64" else "mfma"),
-        "achieved": amount / t / scale,
-        "peak": peak / scale, "unit": unit, "frac": amount / t / peak,
-        "traffic": measured_traffic(args.workload, headline[0], headline[1], taylens.STAGE_KERNELS[dom]),
-        "work_per_launch": amount / nl, "avg_launch_ms": H["avg_launch"][dom], "launches_per_step": nl,
-        "peak_note": "FP64 vector peak (ALU-bound recursion)" if kind == "fp64" else None,
-    }
+    kname = taylens.STAGE_KERNELS[dom]
+    if dom == "legendre_tab" and os.environ.get("TAYLENS_ONTHEFLY") == "1":
+        kname = "k_legendre_lp"
+    nrn = (w.ntheta + 1) // 2 - H["q"]["rpole"]
+    if dom in ("legendre_tab", "legendre_mfma"):
+        n = headline[1]
+        per_elem = 2 * (order + 1) * (2 + ((16 if hasb else 8) if w.pol else 0))
+        if H["q"]["defl_folded"]:
+            per_elem += 2 * 2 * 2
+        elems = H["q"]["elems"] - H["q"]["elems_caps"]
+        nlm = (w.lmax + 1) * (w.lmax + 2) // 2
+        useful = n * per_elem * elems
+        pk = PEAK["f16_mfma"] if dom == "legendre_tab" else PEAK["fp32_mfma"]
+        roof = {
+            "kernel": kname, "stage": dom, "bound": "mfma",
+            "achieved": useful / t / 1e12, "peak": pk / 1e12, "unit": "TFLOP/s", "frac": useful / t / pk,
+            "frac_dense": n * per_elem * nlm * nrn / t / pk,
+            "traffic": measured_traffic(args.workload, headline[0], headline[1], kname),
+            "work_per_launch": useful / nl, "work_unit": f"useful flop: {per_elem} per (l, m, ring pair) "
+                                                         f"below the cut outside the caps, x {n} realizations",
+            "avg_launch_ms": H["avg_launch"][dom], "launches_per_step": nl,
+        }
+        if dom == "legendre_tab":
+            roof["hbm_table_stream"] = {"achieved": amount / t / 1e9, "unit": "GB/s", "frac": amount / t / PEAK["hbm"],
+                                        "bytes_per_launch": amount / nl}
+    else:
+        scale = 1e9 if unit == "GB/s" else 1e12
+        roof = {
+            "kernel": kname, "stage": dom,
+            "bound": "hbm" if kind == "hbm" else ("alu" if kind == "fp64" else "mfma"),
+            "achieved": amount / t / scale,
+            "peak": peak / scale, "unit": unit, "frac": amount / t / peak,
+            "traffic": measured_traffic(args.workload, headline[0], headline[1], kname),
+            "work_per_launch": amount / nl, "avg_launch_ms": H["avg_launch"][dom], "launches_per_step": nl,
+            "peak_note": "FP64 vector peak (ALU-bound recursion)" if kind == "fp64" else None,
+        }
     other = {}
     for k in H["per_step"]:
         if k in work:
@@ -514,7 +649,11 @@ def main():
             "precision_form": headline[0], "realizations_per_step": headline[1],
             "rel_rms_err_vs_oracle": hf["rel_rms_err_vs_oracle"],
             "speedup_vs_fp32": hf["speedup_vs_fp32"],
+            "timing": f"median of {args.steps} steps (HIP events on the plan's stream); "
+                      f"wall-clock mean {hf['ms_per_step_wall_mean']:.2f} ms",
+            "plan_build_s": hf["plan_build_s"], "workspace_gib_per_map": hf["workspace_gib_per_map"],
             "legendre_mfma_util_pct": hf["legendre_mfma_util_pct"],
+            "legendre_mfma_util_pct_after_skip": hf["legendre_mfma_util_pct_after_skip"],
             "legendre_mfma_busy_pct_counters": next(
                 (measured_mfma_busy(args.workload, name(headline), taylens.STAGE_KERNELS[st])
                  for st in ("legendre_tab", "legendre_mfma") if st in H["per_step"]), None),
@@ -526,6 +665,7 @@ def main():
     }
     if cpu is not None:
         res["cpu_baseline"] = cpu
+    res["deflection"] = defl
     if not args.no_extras:
         res["batch_uneven_lmax"] = bench_batch(args, order)
         res["learned_correction"] = bench_cnn(args, w)

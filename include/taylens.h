@@ -53,7 +53,8 @@ extern "C" {
 
 /* Contraction precision of the harmonic (Legendre) stage.  The recursion of
  * the Legendre functions is always FP64, and so are the positions, the
- * rotation angle and the polar caps (sin theta < 0.15).
+ * rotation angle and the polar caps (sin theta < 0.15; < 0.05 for
+ * TL_FP16X2).
  *   TL_FP64   FP64 throughout; maps are float64.
  *   TL_FP32   FP32 matrix-core contraction (L-power form), FP32 derivative maps
  *             and Taylor sum; float32 maps.

@@ -879,10 +879,13 @@ int tl_plan_create(tl_plan *out, int32_t lmax, tl_grid grid, const tl_options *o
     p.stream = (hipStream_t)hip_stream;
     factor_radices(p.nphi / 2, p);
     {
-        // polar caps (sin theta < 0.15) stay on the direct FP64 kernel: the
-        // csc and cot jets of the L-power epilogue amplify the rounding of the
-        // contraction there
-        const double smin = 0.15;
+        // polar caps stay on the direct FP64 kernel: the csc and cot jets of
+        // the L-power epilogue amplify the rounding of the contraction there.
+        // sin theta < 0.15 in general; 0.05 for the split FP16 form, whose
+        // scaled 22-bit operands keep the first ring outside its caps at
+        // about 5e-6 of the map RMS at lmax 4096 (4e-6 at 0.08, 1.6e-6 at
+        // 0.15, 1e-5 at 0.03)
+        const double smin = p.precision == TL_FP16X2 ? 0.05 : 0.15;
         int rp = 1;
         while (rp < p.nrp && std::sin(M_PI * (double)rp / (double)(p.ntheta - 1)) < smin) ++rp;
         p.rpole = rp;

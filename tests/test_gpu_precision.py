@@ -148,17 +148,21 @@ def test_deflection_fold_policy(tl):
 
 def test_polar_cap_policy(tl):
     """Ring pairs kept on the direct FP64 kernels: sin theta < 0.15 in every
-    reduced form and order."""
-    def rpole(prec, order):
-        plan = tl.Plan(160, 161, 320, order, prec, pol=True)
+    form and order but the split FP16 one, sin theta < 0.05 there."""
+    def rpole(prec, order, lmax=160):
+        plan = tl.Plan(lmax, lmax + 1, 2 * lmax, order, prec, pol=True)
         r = plan.query("rpole")
         plan.close()
         return r
 
-    # sin(pi r / 160) < 0.15 for r < 8
-    for prec in ("fp32", "fp16", "fp16x2", "bf16x3"):
+    # sin(pi r / 160) < 0.15 for r < 8, < 0.05 for r < 3
+    for prec in ("fp32", "fp16", "bf16", "bf16x3"):
         for order in (2, 4, 6):
             assert rpole(prec, order) == 8, (prec, order)
+    for order in (2, 4, 6):
+        assert rpole("fp16x2", order) == 3, order
+    # lmax 4096 on 4097 rings: sin(pi r / 4096) < 0.05 for r < 66
+    assert rpole("fp16x2", 4, 4096) == 66
 
 
 @pytest.mark.parametrize("precision,batch", [("fp16x2", 3), ("fp16", 2)])
