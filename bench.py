@@ -412,7 +412,7 @@ def main():
     ap.add_argument("--forms", default="fp32,bf16:6,fp16:6,bf16x3:6,fp16x2:6",
                     help="comma list of precision[:realizations per step]; fp32 is the speed-up reference")
     ap.add_argument("--headline", default=None, help="form reported as value (default: the last of --forms)")
-    ap.add_argument("--cpu-rings", type=int, default=32, help="output rings in the CPU-oracle sample (four bands)")
+    ap.add_argument("--cpu-rings", type=int, default=40, help="output rings in the CPU-oracle sample (five bands)")
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the oracle (no errors, no cpu_baseline)")
     ap.add_argument("--copy-calibration", action="store_true", help="only run a 1 GiB device copy (counter scale)")
     ap.add_argument("--no-extras", action="store_true",
@@ -449,7 +449,7 @@ def main():
                  for s in skies]
     npix = w.ntheta * w.nphi
 
-    # oracle on four bands of output rings of realization 0: inside the polar
+    # oracle on five bands of output rings of realization 0: inside the polar
     # cap (direct FP64 kernels), across the cap boundary (sin theta = 0.15,
     # where the reduced forms' epilogue amplifies most), mid-latitude, equator
     ref, rings, cpu, bands = None, None, None, None
@@ -461,11 +461,18 @@ def main():
         except AttributeError:
             nproc = os.cpu_count() or 1
         ncores = min(16, nproc)
-        nb = max(1, args.cpu_rings // 4)
-        edge = 1
-        while edge < w.ntheta // 2 and math.sin(math.pi * edge / (w.ntheta - 1)) < 0.15:
-            edge += 1
-        starts = {"cap": min(4, edge - nb) if edge > nb else 0, "cap_edge": max(0, edge - nb // 2),
+        nb = max(1, args.cpu_rings // 5)
+
+        def first_ring(smin):
+            e = 1
+            while e < w.ntheta // 2 and math.sin(math.pi * e / (w.ntheta - 1)) < smin:
+                e += 1
+            return e
+
+        # caps end at sin theta 0.05 (split FP16 form) or 0.15 (the others)
+        e1, e2 = first_ring(0.05), first_ring(0.15)
+        starts = {"cap": min(4, e1 - nb) if e1 > nb else 0, "cap_edge_0.05": max(0, e1 - nb // 2),
+                  "cap_edge_0.15": max(0, e2 - nb // 2),
                   "mid_latitude": w.ntheta // 4, "equator": w.ntheta // 2 - nb // 2}
         bands = {k: np.arange(v, v + nb) for k, v in starts.items()}
         rings = np.unique(np.concatenate(list(bands.values())))
@@ -482,7 +489,7 @@ def main():
         cpu = {
             "value": nr * w.nphi / (o1 - o0), "unit": "pixels/s", "cores": ncores, "kind": "oracle",
             "nproc": nproc, "os_cpu_count": os.cpu_count(),
-            "sample": f"{nr} output rings of realization 0 in four bands of {nb} "
+            "sample": f"{nr} output rings of realization 0 in five bands of {nb} "
                       f"({', '.join(f'{k} from {v}' for k, v in starts.items())}): deflection on those rings, "
                       f"derivative maps of every source ring they need, remap, Taylor sum, rotation; "
                       f"{o1 - o0:.1f} s, FP64, {ncores} threads",
