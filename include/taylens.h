@@ -226,6 +226,24 @@ int tl_lens_map_simple(const void *alm_T, const void *alm_E, const void *alm_B,
                        const void *alm_phi, int32_t lmax, int32_t order, tl_grid grid,
                        void *T_out, void *Q_out, void *U_out);
 
+/* Allocation-free form of tl_lens_map_simple, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): same arguments, kernels and results, but
+ * the plan's workspace (tables, start values, harmonic output, derivative
+ * and deflection maps) lives in a static device array of 128 MiB that the
+ * library holds on every device it runs on until the process ends; no
+ * hipMalloc, hipFree or allocating library call is made.  The array's
+ * address is looked up once per device (with that device current).  The
+ * call works on the current device and the null stream, which it
+ * synchronizes before returning.  A size whose workspace exceeds 128 MiB
+ * (T+Q/U order 4 fits up to lmax ~ 256 on 513 x 1024 rings) fails with
+ * TL_ERR_NOMEM before any device work.  Every call on one device uses the
+ * same array: calls that overlap on one device (several host threads) race
+ * and must be serialized by the caller. */
+int tl_lens_map_simple_noalloc(const void *alm_T, const void *alm_E, const void *alm_B,
+                               const void *alm_phi, int32_t lmax, int32_t order, tl_grid grid,
+                               void *T_out, void *Q_out, void *U_out);
+
 /* ---- batches of realizations with uneven lmax ----
  *
  * A batch lenses n realizations, each with its own plan (plans may repeat:

@@ -6,6 +6,7 @@
 #include <new>
 #include <vector>
 #include <string>
+#include <mutex>
 #include <sys/stat.h>
 
 #include "tl_internal.h"
@@ -847,24 +848,9 @@ struct BatchStreams {
     }
 };
 
-}  // namespace
-
-extern "C" {
-
-int tl_version(void) { return TL_VERSION; }
-
-const char *tl_last_error(void) { return g_err.c_str(); }
-
-int tl_plan_create(tl_plan *out, int32_t lmax, tl_grid grid, const tl_options *opt, void *hip_stream)
+// Plan fields from validated options (no device work).
+void plan_fields(Plan &p, int32_t lmax, tl_grid grid, const tl_options *opt, void *hip_stream)
 {
-    if (!out) return fail(TL_ERR_INVALID, "plan output pointer is NULL");
-    *out = nullptr;
-    int rc = validate_options(lmax, grid, opt);
-    if (rc) return rc;
-
-    tl_plan_s *h = new (std::nothrow) tl_plan_s();
-    if (!h) return fail(TL_ERR_NOMEM, "host allocation failed");
-    Plan &p = h->p;
     p.lmax = lmax;
     p.ntheta = grid.ntheta;
     p.nphi = grid.nphi;
@@ -907,61 +893,50 @@ int tl_plan_create(tl_plan *out, int32_t lmax, tl_grid grid, const tl_options *o
     }
     if (p.tabform()) p.rhs_nb = p.tables ? tab_rhs_blocks(p.order, p.pol != 0, p.batch)
                                          : lp_rhs_blocks(p.order, p.pol != 0, p.batch);
+}
 
-    Sizes sz = plan_sizes(p);
-    if (p.cap > 0 && sz.total() > (size_t)p.cap) {
-        delete h;
-        return fail(TL_ERR_NOMEM, "plan needs " + std::to_string(sz.total()) + " bytes, above workspace_cap " +
-                                      std::to_string(p.cap));
-    }
-    hipError_t e = hipGetDevice(&p.device);
-    if (e != hipSuccess) {
-        delete h;
-        return hipfail(e, "hipGetDevice");
-    }
-    {
-        int smem = 0;
-        e = hipDeviceGetAttribute(&smem, hipDeviceAttributeMaxSharedMemoryPerBlock, p.device);
-        if (e != hipSuccess) {
-            delete h;
-            return hipfail(e, "hipDeviceGetAttribute");
-        }
-        const size_t need64 = 2 * (size_t)(p.nphi / 2) * sizeof(double2);
-        if (need64 > (size_t)smem) {
-            delete h;
-            return fail(TL_ERR_UNSUPPORTED, "nphi too large for the FP64 ring FFT in LDS on this device (" +
-                                                std::to_string(need64) + " > " + std::to_string(smem) + " bytes)");
-        }
-    }
-    struct {
-        DevBuf *b;
-        size_t n;
-        const char *name;
-    } list[] = {{&p.theta, sz.theta, "theta"},   {&p.trig, sz.trig, "trig"},       {&p.phitab, sz.phitab, "phitab"},
-                {&p.phival, sz.phival, "phival"}, {&p.twid64, sz.twid64, "twid64"}, {&p.twid32, sz.twid32, "twid32"},
-                {&p.coef0, sz.coef, "coef0"},    {&p.coef2, sz.coef, "coef2"},     {&p.start, sz.start, "start"},
-                {&p.exps, sz.exps, "exps"},      {&p.mcut, sz.mcut, "mcut"},       {&p.Fphi, sz.Fphi, "Fphi"},       {&p.alpha, sz.alpha, "alpha"},
-                {&p.F, sz.F, "F"},               {&p.D, sz.D, "D"},                {&p.jobsDefl, sz.jd, "jobsDefl"},
-                {&p.jobsMain, sz.jm, "jobsMain"}, {&p.tab, sz.tab, "tab"},        {&p.moff, sz.moff, "moff"},
-                {&p.kstart, sz.kstart, "kstart"}, {&p.rhs, sz.rhs, "rhs"},          {&p.colexp, sz.colexp, "colexp"},
-                {&p.tabsum, sz.tabsum, "tabsum"}};
-    for (auto &it : list) {
-        if (it.n == 0) continue;
-        rc = alloc(p, *it.b, it.n, it.name);
-        if (rc) {
-            free_plan_buffers(p);
-            delete h;
-            return rc;
-        }
-    }
-    auto bail = [&](int code) {
-        free_plan_buffers(p);
-        delete h;
-        return code;
-    };
-    if ((rc = upload_tables(p))) return bail(rc);
-    if ((rc = build_jobs(p))) return bail(rc);
-    e = hipMemsetAsync(p.start.ptr, 0, p.start.bytes, p.stream);
+// The current device, and whether the FP64 ring FFT of this nphi fits in LDS.
+int plan_device_checks(Plan &p)
+{
+    TL_HIP(hipGetDevice(&p.device), "hipGetDevice");
+    int smem = 0;
+    TL_HIP(hipDeviceGetAttribute(&smem, hipDeviceAttributeMaxSharedMemoryPerBlock, p.device),
+           "hipDeviceGetAttribute");
+    const size_t need64 = 2 * (size_t)(p.nphi / 2) * sizeof(double2);
+    if (need64 > (size_t)smem)
+        return fail(TL_ERR_UNSUPPORTED, "nphi too large for the FP64 ring FFT in LDS on this device (" +
+                                            std::to_string(need64) + " > " + std::to_string(smem) + " bytes)");
+    return TL_OK;
+}
+
+struct BufItem {
+    DevBuf *b;
+    size_t n;
+    const char *name;
+};
+
+std::vector<BufItem> plan_buffer_list(Plan &p, const Sizes &sz)
+{
+    return {{&p.theta, sz.theta, "theta"},   {&p.trig, sz.trig, "trig"},       {&p.phitab, sz.phitab, "phitab"},
+            {&p.phival, sz.phival, "phival"}, {&p.twid64, sz.twid64, "twid64"}, {&p.twid32, sz.twid32, "twid32"},
+            {&p.coef0, sz.coef, "coef0"},    {&p.coef2, sz.coef, "coef2"},     {&p.start, sz.start, "start"},
+            {&p.exps, sz.exps, "exps"},      {&p.mcut, sz.mcut, "mcut"},       {&p.Fphi, sz.Fphi, "Fphi"},
+            {&p.alpha, sz.alpha, "alpha"},   {&p.F, sz.F, "F"},                {&p.D, sz.D, "D"},
+            {&p.jobsDefl, sz.jd, "jobsDefl"}, {&p.jobsMain, sz.jm, "jobsMain"}, {&p.tab, sz.tab, "tab"},
+            {&p.moff, sz.moff, "moff"},      {&p.kstart, sz.kstart, "kstart"}, {&p.rhs, sz.rhs, "rhs"},
+            {&p.colexp, sz.colexp, "colexp"}, {&p.tabsum, sz.tabsum, "tabsum"}};
+}
+
+// Everything a plan computes into its buffers once they exist: angle and
+// twiddle tables, FFT jobs, recursion coefficients, start values and the
+// evanescent cut, the lambda tables of the tabulated forms; waits for them
+// and counts the work.
+int plan_setup(Plan &p)
+{
+    int rc;
+    if ((rc = upload_tables(p))) return rc;
+    if ((rc = build_jobs(p))) return rc;
+    hipError_t e = hipMemsetAsync(p.start.ptr, 0, p.start.bytes, p.stream);
     if (e == hipSuccess) e = hipMemsetAsync(p.exps.ptr, 0, p.exps.bytes, p.stream);
     if (e == hipSuccess) e = launch_tables(p);
     if (e == hipSuccess && p.tabform() && !p.tables) {
@@ -979,7 +954,112 @@ int tl_plan_create(tl_plan *out, int32_t lmax, tl_grid grid, const tl_options *o
     if (e == hipSuccess) e = fft_prepare(p);
     if (e == hipSuccess) e = hipStreamSynchronize(p.stream);
     if (e == hipSuccess) e = count_work(p);
-    if (e != hipSuccess) return bail(hipfail(e, "plan tables"));
+    if (e != hipSuccess) return hipfail(e, "plan tables");
+    return TL_OK;
+}
+
+// The whole path for one realization on a plan whose arguments are checked.
+int lens_map_core(Plan &p, const void *alm_T, const void *alm_E, const void *alm_B, const void *alm_phi,
+                  void *T_out, void *Q_out, void *U_out)
+{
+    int rc;
+    if (fold_deflection(p, 1, &alm_phi)) {
+        const void *Ts[1] = {alm_T}, *Es[1] = {alm_E}, *Bs[1] = {alm_B}, *Ps[1] = {alm_phi};
+        void *Fs[1] = {p.F.ptr};
+        if ((rc = run_legendre_many(p, 1, Ts, Es, Bs, Fs, Ps))) return rc;
+        if ((rc = defl_legendre(p, 1, Ps, true))) return rc;
+        if ((rc = defl_fft(p, alm_phi, 0))) return rc;
+        StageScope sc(p, ST_FFT);
+        TL_HIP(launch_fft_jobs(p, p.F.ptr, p.D.ptr, (const FftJob *)p.jobsMain.ptr, p.njobsMain, p.fp64()),
+               "ring fft");
+    } else {
+        if ((rc = run_deflection(p, alm_phi))) return rc;
+        if ((rc = run_derivs(p, alm_T, alm_E, alm_B, p.D.ptr))) return rc;
+    }
+    const double *at = (const double *)p.alpha.ptr;
+    StageScope sc(p, ST_REMAP);
+    TL_HIP(launch_remap(p, p.D.ptr, at, at + p.npix(), nullptr, nullptr, T_out, Q_out, U_out), "remap");
+    return TL_OK;
+}
+
+// ---- allocation-free lensing: the workspace in a static device array ----
+
+// Largest workspace of tl_lens_map_simple_noalloc (128 MiB): T+Q/U at order 4
+// up to lmax ~ 256 on the 513 x 1024 grid, T-only larger.  Each device the
+// library runs on holds its own copy until the process ends.
+constexpr size_t kScratchBytes = (size_t)128 << 20;
+
+std::mutex g_scratch_mu;
+constexpr int kScratchDevices = 64;
+void *g_scratch_ptr[kScratchDevices] = {};
+
+}  // namespace
+
+// Device copy of the workspace.  Its name is only a host-side handle: host
+// code uses the address hipGetSymbolAddress returns for the current device.
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+
+// Address of `scratch` on device dev (current), looked up once per device.
+int scratch_address(int dev, void **out)
+{
+    if (dev < 0 || dev >= kScratchDevices) return fail(TL_ERR_UNSUPPORTED, "device ordinal above 63");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hipfail(e, "hipGetSymbolAddress(scratch)");
+        if (!ptr) return fail(TL_ERR_HIP, "hipGetSymbolAddress(scratch) returned NULL");
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return TL_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int tl_version(void) { return TL_VERSION; }
+
+const char *tl_last_error(void) { return g_err.c_str(); }
+
+int tl_plan_create(tl_plan *out, int32_t lmax, tl_grid grid, const tl_options *opt, void *hip_stream)
+{
+    if (!out) return fail(TL_ERR_INVALID, "plan output pointer is NULL");
+    *out = nullptr;
+    int rc = validate_options(lmax, grid, opt);
+    if (rc) return rc;
+
+    tl_plan_s *h = new (std::nothrow) tl_plan_s();
+    if (!h) return fail(TL_ERR_NOMEM, "host allocation failed");
+    Plan &p = h->p;
+    plan_fields(p, lmax, grid, opt, hip_stream);
+    Sizes sz = plan_sizes(p);
+    if (p.cap > 0 && sz.total() > (size_t)p.cap) {
+        delete h;
+        return fail(TL_ERR_NOMEM, "plan needs " + std::to_string(sz.total()) + " bytes, above workspace_cap " +
+                                      std::to_string(p.cap));
+    }
+    if ((rc = plan_device_checks(p))) {
+        delete h;
+        return rc;
+    }
+    for (auto &it : plan_buffer_list(p, sz)) {
+        if (it.n == 0) continue;
+        rc = alloc(p, *it.b, it.n, it.name);
+        if (rc) {
+            free_plan_buffers(p);
+            delete h;
+            return rc;
+        }
+    }
+    if ((rc = plan_setup(p))) {
+        free_plan_buffers(p);
+        delete h;
+        return rc;
+    }
     *out = h;
     return TL_OK;
 }
@@ -1115,23 +1195,7 @@ int tl_lens_map(tl_plan plan, const void *alm_T, const void *alm_E, const void *
     if (rc) return rc;
     if ((rc = check_outputs(p, T_out, Q_out, U_out))) return rc;
     if ((rc = set_device_of(p))) return rc;
-    if (fold_deflection(p, 1, &alm_phi)) {
-        const void *Ts[1] = {alm_T}, *Es[1] = {alm_E}, *Bs[1] = {alm_B}, *Ps[1] = {alm_phi};
-        void *Fs[1] = {p.F.ptr};
-        if ((rc = run_legendre_many(p, 1, Ts, Es, Bs, Fs, Ps))) return rc;
-        if ((rc = defl_legendre(p, 1, Ps, true))) return rc;
-        if ((rc = defl_fft(p, alm_phi, 0))) return rc;
-        StageScope sc(p, ST_FFT);
-        TL_HIP(launch_fft_jobs(p, p.F.ptr, p.D.ptr, (const FftJob *)p.jobsMain.ptr, p.njobsMain, p.fp64()),
-               "ring fft");
-    } else {
-        if ((rc = run_deflection(p, alm_phi))) return rc;
-        if ((rc = run_derivs(p, alm_T, alm_E, alm_B, p.D.ptr))) return rc;
-    }
-    const double *at = (const double *)p.alpha.ptr;
-    StageScope sc(p, ST_REMAP);
-    TL_HIP(launch_remap(p, p.D.ptr, at, at + p.npix(), nullptr, nullptr, T_out, Q_out, U_out), "remap");
-    return TL_OK;
+    return lens_map_core(p, alm_T, alm_E, alm_B, alm_phi, T_out, Q_out, U_out);
 }
 
 int tl_lens_map_pos(tl_plan plan, const void *alm_T, const void *alm_E, const void *alm_B, const double *theta_src,
@@ -1585,6 +1649,52 @@ int tl_lens_map_simple(const void *alm_T, const void *alm_E, const void *alm_B, 
         if (e != hipSuccess) rc = hipfail(e, "synchronize");
     }
     tl_plan_destroy(plan);
+    return rc;
+}
+
+int tl_lens_map_simple_noalloc(const void *alm_T, const void *alm_E, const void *alm_B, const void *alm_phi,
+                               int32_t lmax, int32_t order, tl_grid grid, void *T_out, void *Q_out, void *U_out)
+{
+    tl_options o{};
+    o.order = order;
+    o.precision = TL_FP32;
+    o.pol = alm_E != nullptr;
+    o.rotate = 1;
+    int rc = validate_options(lmax, grid, &o);
+    if (rc) return rc;
+    Plan p;
+    plan_fields(p, lmax, grid, &o, nullptr);
+    if ((rc = check_fields(p, alm_T, alm_E))) return rc;
+    if ((rc = check_outputs(p, T_out, Q_out, U_out))) return rc;
+    // the plan's buffers, each 256-byte aligned, carved from the array
+    const Sizes sz = plan_sizes(p);
+    std::vector<BufItem> items = plan_buffer_list(p, sz);
+    size_t need = 0;
+    for (auto &it : items)
+        if (it.n) need += (it.n + 255) & ~(size_t)255;
+    if (need > kScratchBytes)
+        return fail(TL_ERR_NOMEM, "tl_lens_map_simple_noalloc: this lmax, grid and order need " +
+                                      std::to_string(need) + " bytes of workspace, above its static " +
+                                      std::to_string(kScratchBytes) + "-byte array");
+    if ((rc = plan_device_checks(p))) return rc;
+    void *base = nullptr;
+    if ((rc = scratch_address(p.device, &base))) return rc;
+    size_t off = 0;
+    for (auto &it : items) {
+        if (!it.n) continue;
+        it.b->ptr = (char *)base + off;
+        it.b->bytes = it.n;
+        off += (it.n + 255) & ~(size_t)255;
+    }
+    p.total_bytes = off;
+    // tables and start values into the array, then the path; everything on
+    // the null stream, which is synchronized before returning
+    if ((rc = plan_setup(p))) return rc;
+    rc = lens_map_core(p, alm_T, alm_E, alm_B, alm_phi, T_out, Q_out, U_out);
+    if (rc == TL_OK) {
+        const hipError_t e = hipStreamSynchronize(nullptr);
+        if (e != hipSuccess) rc = hipfail(e, "synchronize");
+    }
     return rc;
 }
 

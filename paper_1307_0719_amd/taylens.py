@@ -34,6 +34,7 @@ EXPORTS = [
     "tl_lens_map_simple", "tl_lens_map_many", "tl_plan_profile", "tl_plan_stage_times", "tl_last_error", "tl_version",
     "tl_cnn_create", "tl_cnn_destroy", "tl_cnn_get_params", "tl_cnn_set_params", "tl_cnn_forward", "tl_cnn_grad",
     "tl_cnn_train_step", "tl_lens_map_cnn", "tl_batch_create", "tl_batch_destroy", "tl_batch_run", "tl_batch_info",
+    "tl_lens_map_simple_noalloc",
 ]
 CNN_NTRAIN = 15139
 CNN_NPARAM = 15142
@@ -91,6 +92,7 @@ def lib():
         L.tl_remap.argtypes = [vp] * 7
         L.tl_lens_map_batch.argtypes = [ctypes.c_int32, vp, vp, vp]
         L.tl_lens_map_simple.argtypes = [vp, vp, vp, vp, ctypes.c_int32, ctypes.c_int32, Grid, vp, vp, vp]
+        L.tl_lens_map_simple_noalloc.argtypes = [vp, vp, vp, vp, ctypes.c_int32, ctypes.c_int32, Grid, vp, vp, vp]
         L.tl_lens_map_many.argtypes = [vp, ctypes.c_int32, vp, vp]
         L.tl_plan_profile.argtypes = [vp, ctypes.c_int32]
         L.tl_plan_stage_times.argtypes = [vp, vp, vp]
@@ -471,21 +473,26 @@ def lens_map_batch(plans: Sequence[Plan], alms: Sequence[tuple], outs: Sequence[
     return keep
 
 
-def lens_map(alm_T, alm_E, alm_B, alm_phi, lmax: int, order: int, ntheta: int, nphi: int):
+def lens_map(alm_T, alm_E, alm_B, alm_phi, lmax: int, order: int, ntheta: int, nphi: int, out=None,
+             noalloc: bool = False):
     """lens_map(alm_T, alm_E, alm_B, alm_phi, lmax, order, grid) -> T', Q', U'
-    (FP32, rotation on; Q'/U' None without alm_E).  Synchronizes."""
+    (FP32, rotation on; Q'/U' None without alm_E).  Synchronizes.
+    noalloc=True calls the allocation-free entry point (workspace in the
+    library's static device array; out = preallocated (T, Q, U) maps, else
+    they are allocated here by torch)."""
     dev = torch.device("cuda", torch.cuda.current_device())
     T = _alm(alm_T, "alm_T", dev, lmax)
     E = _alm(alm_E, "alm_E", dev, lmax)
     B = _alm(alm_B, "alm_B", dev, lmax)
     P = _alm(alm_phi, "alm_phi", dev, lmax)
-    mk = lambda: torch.empty((ntheta, nphi), dtype=torch.float32, device=dev)
-    To = mk()
-    Qo = mk() if E is not None else None
-    Uo = mk() if E is not None else None
+    if out is None:
+        mk = lambda: torch.empty((ntheta, nphi), dtype=torch.float32, device=dev)
+        out = (mk(), mk() if E is not None else None, mk() if E is not None else None)
+    To, Qo, Uo = out
     torch.cuda.synchronize()
-    _check(lib().tl_lens_map_simple(_ptr(T), _ptr(E), _ptr(B), _ptr(P), int(lmax), int(order),
-                                    Grid(ntheta, nphi), _ptr(To), _ptr(Qo), _ptr(Uo)))
+    fn = lib().tl_lens_map_simple_noalloc if noalloc else lib().tl_lens_map_simple
+    _check(fn(_ptr(T), _ptr(E), _ptr(B), _ptr(P), int(lmax), int(order), Grid(ntheta, nphi), _ptr(To), _ptr(Qo),
+              _ptr(Uo)))
     return To, Qo, Uo
 
 
