@@ -273,50 +273,131 @@ def bench_batch(args, order=4, n=64):
     return res
 
 
-def bench_cnn(args, w):
+def bench_cnn(args, w, precision="fp16x2"):
     """Order 2 + learned correction at the workload's size (weights shipped
-    with the package), its forward kernel against the BF16 matrix peak, and
-    its error against plain order 6 on one held-out sky."""
+    with the package) in the given precision form, its forward kernel against
+    the BF16 matrix peak, beside plain orders 2, 3, 4 and 6 in the same form
+    (ms per map, one realization per call), and the RMS error of each against
+    plain order 6 (FP32 form) on two held-out skies."""
     import numpy as np
     import torch
 
-    from paper_1307_0719_amd import train_cnn, taylens
+    from paper_1307_0719_amd import skygen, train_cnn, taylens
 
     here = os.path.dirname(os.path.abspath(__file__))
     params = np.load(os.path.join(here, "paper_1307_0719_amd", "cnn_weights.npy"))
     dev = torch.device("cuda", 0)
-    plan = taylens.Plan(w.lmax, w.ntheta, w.nphi, 2, "fp32", pol=True)
-    net = taylens.Cnn(params)
-    from paper_1307_0719_amd import skygen
-
     s = skygen.make_sky(w.lmax, w.seed, pol=True)
     a = tuple(None if x is None else torch.from_numpy(x).to(dev) for x in (s.alm_T, s.alm_E, None, s.alm_phi))
+    npix = w.ntheta * w.nphi
+
+    def timed(run):
+        for _ in range(args.warmup):
+            run()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            run()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / args.steps
+
+    ms = {}
+    plan = taylens.Plan(w.lmax, w.ntheta, w.nphi, 2, precision, pol=True)
+    net = taylens.Cnn(params)
     outs = (plan._maps(), plan._maps(), plan._maps())
-    for _ in range(args.warmup):
-        net.lens_map(plan, *a, out=outs)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        net.lens_map(plan, *a, out=outs)
-    torch.cuda.synchronize()
-    sec = (time.perf_counter() - t0) / args.steps
+    sec = timed(lambda: net.lens_map(plan, *a, out=outs))
     plan.profile(True)
     for _ in range(args.steps):
         net.lens_map(plan, *a, out=outs)
     st = plan.stage_times()
     plan.profile(False)
     cnn_ms = st["cnn"][0] / st["cnn"][1]
-    npix = w.ntheta * w.nphi
-    flops = 2 * 61152 * npix  # MACs per pixel of the three layers (useful, unpadded)
+    ms["order2_plus_cnn"] = sec * 1e3
+    ms["order2"] = timed(lambda: plan.lens_map(*a, out=outs)) * 1e3
     net.close()
     plan.close()
+    del outs
     torch.cuda.empty_cache()
-    ev = train_cnn.evaluate(params, w.lmax, w.ntheta, w.nphi, [20000])
-    return {"pixels_per_s": npix / sec, "ms_per_map": sec * 1e3, "cnn_forward_ms": cnn_ms,
+    for N in (3, 4, 6):
+        pn = taylens.Plan(w.lmax, w.ntheta, w.nphi, N, precision, pol=True)
+        o = (pn._maps(), pn._maps(), pn._maps())
+        ms[f"order{N}"] = timed(lambda: pn.lens_map(*a, out=o)) * 1e3
+        pn.close()
+        del o
+        torch.cuda.empty_cache()
+    flops = 2 * 61152 * npix  # MACs per pixel of the three layers (useful, unpadded)
+    ev = train_cnn.evaluate(params, w.lmax, w.ntheta, w.nphi, [20000, 20001], precision=precision,
+                            plain_orders=(3, 4))
+    errs = {"order2": ev["rms_err_order2"], "order2_plus_cnn": ev["rms_err_cnn"],
+            "order3": ev["rms_err_order3"], "order4": ev["rms_err_order4"]}
+    return {"precision_form": precision, "pixels_per_s": npix / (ms["order2_plus_cnn"] * 1e-3),
+            "ms_per_map": ms, "cnn_forward_ms": cnn_ms,
             "cnn_forward_bf16_tflops": flops / (cnn_ms * 1e-3) / 1e12,
             "cnn_forward_mfma_frac": flops / (cnn_ms * 1e-3) / PEAK["f16_mfma"],
-            "rms_err_vs_order6": {"order2": ev["rms_err_order2"], "order2_plus_cnn": ev["rms_err_cnn"],
-                                  "gain": ev["gain"], "held_out_seed": 20000}}
+            "rms_err_vs_order6": errs, "rms_signal": ev["rms_signal"], "gain_over_order2": ev["gain"],
+            "held_out_seeds": ev["seeds"]}
+
+
+def bench_healpix(args, with_oracle, precision="fp16x2", nside=2048, lmax=3072, order=2, batch=6):
+    """Lensing onto and from HEALPix rings (the paper's pixelization): nside
+    2048, lmax 3072, order 2 -- a row of the paper's fastest-settings table
+    (32.5 CPU-minutes per map on 8-core Xeon E5540 nodes; at lmax 4096 the
+    split tables of 8191 HEALPix rings would exceed one GPU's memory) -- six
+    realizations per table pass.  Rate in lensed HEALPix pixels per second;
+    error against the HEALPix oracle on two sampled rings (a 4-pixel polar ring
+    and the equator) of realization 0."""
+    import numpy as np
+    import torch
+
+    from paper_1307_0719_amd import skygen, taylens
+
+    dev = torch.device("cuda", 0)
+    skies = [skygen.make_sky(lmax, 2 + i, pol=True) for i in range(batch)]
+    skies_dev = [tuple(None if x is None else torch.from_numpy(x).to(dev) for x in (s.alm_T, s.alm_E, None, s.alm_phi))
+                 for s in skies]
+    plan = taylens.Plan(lmax, 0, 0, order, precision, pol=True, nside=nside, batch=batch if batch > 1 else 0)
+    outs = [(plan._maps(), plan._maps(), plan._maps()) for _ in range(batch)]
+    alms = skies_dev[:batch]
+    for _ in range(args.warmup):
+        plan.lens_map_many(alms, outs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        plan.lens_map_many(alms, outs)
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / args.steps
+    plan.profile(True)
+    for _ in range(args.steps):
+        plan.lens_map_many(alms, outs)
+    st = plan.stage_times()
+    plan.profile(False)
+    npix = 12 * nside * nside
+    res = {"nside": nside, "lmax": lmax, "order": order, "precision_form": precision,
+           "realizations_per_step": batch, "ms_per_step": sec * 1e3, "pixels_per_s": batch * npix / sec,
+           "stages_ms_per_step": {k: round(v[0] / args.steps, 3) for k, v in st.items() if v[1]},
+           "paper_context": "Taylens at nside 2048, lmax 3072, order 2: 32.5 CPU-minutes per map on 8-core "
+                            "Xeon E5540 nodes (25,811 pixels per CPU-second)"}
+    if with_oracle:
+        from oracle import healpix_oracle as hp
+
+        ncores = min(16, os.cpu_count() or 1)
+        rings = np.array([0, 2 * nside - 1])
+        pix = hp.ring_pixels(nside, rings)
+        s0 = skies[0]
+        ref = hp.lens_pixels(lmax, order, nside, pix, s0.alm_T, s0.alm_E, s0.alm_B, s0.alm_phi, nthreads=ncores)
+        ok = hp.ang2pix(nside, ref["_thp"] + 1e-12, ref["_php"] + 1e-12) == ref["_src"]
+        idx = torch.from_numpy(pix).to(outs[0][0].device)
+        errs = {}
+        for f, g in zip("TQU", outs[0]):
+            x = g[idx].cpu().numpy()[ok]
+            y = ref[f][ok]
+            errs[f] = float(np.sqrt(np.mean((x - y) ** 2)) / np.sqrt(np.mean(y ** 2)))
+        res["rel_rms_err_vs_oracle"] = errs
+        res["oracle_sample"] = f"rings {rings.tolist()} ({pix.size} pixels) of realization 0"
+    del outs
+    plan.close()
+    torch.cuda.empty_cache()
+    return res
 
 
 def deflection_check(w, skies, skies_dev):
@@ -674,6 +755,7 @@ def main():
         res["cpu_baseline"] = cpu
     res["deflection"] = defl
     if not args.no_extras:
+        res["healpix"] = bench_healpix(args, ref is not None)
         res["batch_uneven_lmax"] = bench_batch(args, order)
         res["learned_correction"] = bench_cnn(args, w)
     print(json.dumps(res))

@@ -93,8 +93,9 @@ typedef struct {
                               no rotation).  0: geodesic displacement.             */
     int32_t batch;         /* realizations per harmonic-stage pass for the tabulated
                               forms (tl_lens_map_many): 0 or 1 = one; at most 6
-                              (4 on the fly), fewer for high orders (error if too
-                              many).  Must be
+                              with tables (up to 128 right-hand-side columns: 6
+                              at order 4 with T + E, fewer with B or at high
+                              orders; error if too many), 4 on the fly.  Must be
                               0 or 1 for TL_FP64 / TL_FP32.                        */
     int64_t workspace_cap; /* bytes; 0 = no cap.  tl_plan_create fails with
                               TL_ERR_NOMEM if the plan would need more.            */
@@ -108,6 +109,22 @@ typedef struct tl_plan_s *tl_plan;
  * set to NULL. */
 int tl_plan_create(tl_plan *plan, int32_t lmax, tl_grid grid, const tl_options *opt,
                    void *hip_stream);
+
+/* Plan on HEALPix rings (RING order, npix = 12 nside^2; the pixelization of
+ * the paper's simulations, Sec. II.A-B) instead of the equal-theta grid:
+ * output pixels are the HEALPix centres, the derivative maps live on them, and
+ * the remap expands about the centre of the pixel that CONTAINS the displaced
+ * position (the paper's ang2pix / pix2ang step, Sec. II.B), in the offsets
+ * (theta' - theta0, phi' - phi0) of eq. 5.  Ring syntheses fold the band
+ * limit onto each ring's own pixel count and phase, so lmax is free.  Maps
+ * (outputs of tl_lens_map, tl_lens_map_many; alpha of tl_deflection) are
+ * [npix] in RING order; derivative maps (tl_synth_derivs, tl_remap) are
+ * [field][jk][npix] scaled by delta^(j+k) / (j! k!), delta = pi / (4 nside);
+ * positions for tl_lens_map_pos are [npix].  1 <= nside <= 2048.  Batches
+ * (tl_batch_*), tl_lens_map_batch of mixed grids aside, and the correction
+ * network take equal-theta plans only (TL_ERR_UNSUPPORTED). */
+int tl_plan_create_healpix(tl_plan *plan, int32_t lmax, int32_t nside, const tl_options *opt,
+                           void *hip_stream);
 
 /* Release a plan and its workspace (NULL is accepted).  Waits for the plan's
  * stream first. */

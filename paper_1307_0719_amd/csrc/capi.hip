@@ -113,7 +113,7 @@ void free_buf(DevBuf &b)
 void free_plan_buffers(Plan &p)
 {
     DevBuf *bufs[] = {&p.theta, &p.trig, &p.phitab, &p.phival, &p.twid64, &p.twid32, &p.coef0, &p.coef2,
-                      &p.start, &p.exps, &p.mcut, &p.tab, &p.moff, &p.kstart, &p.rhs, &p.colexp, &p.tabsum, &p.Fphi, &p.alpha, &p.F, &p.D, &p.jobsDefl, &p.jobsMain};
+                      &p.start, &p.exps, &p.mcut, &p.tab, &p.moff, &p.kstart, &p.rhs, &p.colexp, &p.tabsum, &p.Fphi, &p.alpha, &p.F, &p.D, &p.jobsDefl, &p.jobsMain, &p.hring};
     for (DevBuf *b : bufs) free_buf(*b);
 }
 
@@ -141,13 +141,50 @@ double factorial(int n)
     return r;
 }
 
+// HEALPix rings (RING order, the published geometry of Gorski et al. 2005):
+// ring i = 1 .. 4 nside - 1 with colatitude from z = 1 - i^2/(3 nside^2) in
+// the polar caps (through sin(theta/2), exact near the poles) and
+// z = 4/3 - 2 i/(3 nside) in the belt, 4 i resp. 4 nside pixels, the first at
+// phi0 = pi/(4 i) in the caps and pi s/(4 nside), s = (i - nside + 1) mod 2, in
+// the belt; sigma = e^{i nphi phi0} = -1 for shifted rings, +1 otherwise.
+void healpix_rings(int nside, std::vector<double> &th, std::vector<HRing> &hr)
+{
+    const int nr = 4 * nside - 1;
+    th.assign(nr, 0.0);
+    hr.assign(nr, HRing{});
+    int64_t start = 0;
+    for (int r = 0; r < nr; ++r) {
+        const int i = r + 1;
+        const bool north = i <= 2 * nside;
+        const int ii = north ? i : 4 * nside - i;
+        double t, p0;
+        int n, sig;
+        if (ii < nside) {
+            t = 2.0 * std::asin((double)ii / (std::sqrt(6.0) * nside));
+            if (!north) t = M_PI - t;
+            n = 4 * ii;
+            p0 = M_PI / (4.0 * ii);
+            sig = -1;
+        } else {
+            t = std::acos(4.0 / 3.0 - 2.0 * i / (3.0 * nside));
+            n = 4 * nside;
+            const int sh = (i - nside + 1) % 2;
+            p0 = M_PI * sh / (4.0 * nside);
+            sig = sh ? -1 : 1;
+        }
+        th[r] = t;
+        hr[r] = HRing{start, n, sig, p0};
+        start += n;
+    }
+}
+
 struct Sizes {
     size_t theta, trig, phitab, phival, twid64, twid32, coef, start, exps, mcut, Fphi, alpha, F, D, jd, jm;
-    size_t tab = 0, moff = 0, kstart = 0, rhs = 0, colexp = 0, tabsum = 0;
+    size_t tab = 0, moff = 0, kstart = 0, rhs = 0, colexp = 0, tabsum = 0, hring = 0;
     size_t total() const
     {
         return theta + trig + phitab + phival + twid64 + twid32 + 2 * coef + start + exps + mcut + Fphi + alpha + F +
-               D + jd + jm + tab + moff + kstart + rhs + colexp + tabsum;
+               D + jd + jm + tab + moff + kstart + rhs + colexp + tabsum + hring;
     }
 };
 
@@ -162,8 +199,11 @@ Sizes plan_sizes(const Plan &p)
     s.trig = p.ntheta * sizeof(double2);
     s.phitab = p.nphi * sizeof(double2);
     s.phival = (p.nphi + 1) * sizeof(double);
-    s.twid64 = p.nphi * sizeof(double2);
-    s.twid32 = p.nphi * sizeof(float2);
+    // twiddles e^{2 pi i t / N}: one length, or every HEALPix ring length 4 i
+    const size_t ntw = p.nside ? (size_t)2 * p.nside * (p.nside + 1) : (size_t)p.nphi;
+    s.twid64 = ntw * sizeof(double2);
+    s.twid32 = ntw * sizeof(float2);
+    s.hring = p.nside ? (size_t)p.ntheta * sizeof(HRing) : 0;
     s.coef = nalm * sizeof(double4);
     s.start = 3 * (size_t)(p.lmax + 1) * p.jtab * p.nrp * sizeof(double);
     s.exps = 3 * (size_t)(p.lmax + 1) * p.nrp * sizeof(int);
@@ -231,8 +271,63 @@ int validate_options(int32_t lmax, tl_grid grid, const tl_options *opt)
     return TL_OK;
 }
 
+// FFT jobs of a HEALPix plan: rows to rings of their own length (pad = the
+// ring), pixel offsets of RING order; derivative maps scaled by
+// delta^(j+k) / (j! k!), delta = pi / (4 nside) (the remap's residual unit).
+int build_jobs_healpix(Plan &p)
+{
+    const int N = p.order;
+    const size_t row = (size_t)(p.lmax + 1);
+    std::vector<double> th;
+    std::vector<HRing> hr;
+    healpix_rings(p.nside, th, hr);
+    const size_t np = p.npix();
+    std::vector<FftJob> jd(2 * (size_t)p.ntheta);
+    for (int i = 0; i < p.ntheta; ++i) {
+        FftJob a{};
+        a.src = (int64_t)((size_t)(1 * p.ntheta + i) * row);  // d_theta phi
+        a.nk = 1;
+        a.pad = i;
+        a.k[0] = 0;
+        a.dst[0] = hr[i].start;
+        a.scale[0] = 1.0;
+        jd[2 * i] = a;
+        FftJob b{};
+        b.src = (int64_t)((size_t)i * row);                   // d_phi phi / sin theta
+        b.nk = 1;
+        b.pad = i;
+        b.k[0] = 1;
+        b.dst[0] = (int64_t)np + hr[i].start;
+        b.scale[0] = 1.0 / std::sin(th[i]);
+        jd[2 * i + 1] = b;
+    }
+    p.njobsDefl = (int)jd.size();
+    const double del = M_PI / (4.0 * p.nside);
+    std::vector<FftJob> jm((size_t)p.nfield() * (N + 1) * p.ntheta);
+    size_t q = 0;
+    for (int f = 0; f < p.nfield(); ++f)
+        for (int j = 0; j <= N; ++j)
+            for (int i = 0; i < p.ntheta; ++i) {
+                FftJob a{};
+                a.src = (int64_t)((((size_t)f * (N + 1) + j) * p.ntheta + i) * row);
+                a.nk = N - j + 1;
+                a.pad = i;
+                for (int k = 0; k <= N - j; ++k) {
+                    a.k[k] = k;
+                    a.dst[k] = (int64_t)(((size_t)f * p.ndmap() + dmap_index(N, j, k)) * np + hr[i].start);
+                    a.scale[k] = std::pow(del, j + k) / (factorial(j) * factorial(k));
+                }
+                jm[q++] = a;
+            }
+    p.njobsMain = (int)jm.size();
+    TL_HIP(hipMemcpy(p.jobsDefl.ptr, jd.data(), jd.size() * sizeof(FftJob), hipMemcpyHostToDevice), "jobs copy");
+    TL_HIP(hipMemcpy(p.jobsMain.ptr, jm.data(), jm.size() * sizeof(FftJob), hipMemcpyHostToDevice), "jobs copy");
+    return TL_OK;
+}
+
 int build_jobs(Plan &p)
 {
+    if (p.nside) return build_jobs_healpix(p);
     const int N = p.order;
     const double dth = M_PI / (double)(p.ntheta - 1);
     const double dph = 2.0 * M_PI / (double)p.nphi;
@@ -287,9 +382,28 @@ int upload_tables(Plan &p)
 {
     std::vector<double> th(p.ntheta);
     std::vector<double2> tr(p.ntheta);
+    std::vector<HRing> hr;
+    if (p.nside) healpix_rings(p.nside, th, hr);
     for (int i = 0; i < p.ntheta; ++i) {
-        th[i] = M_PI * (double)i / (double)(p.ntheta - 1);
+        if (!p.nside) th[i] = M_PI * (double)i / (double)(p.ntheta - 1);
         tr[i] = make_double2(std::cos(th[i]), std::sin(th[i]));
+    }
+    if (p.nside) {
+        TL_HIP(hipMemcpy(p.hring.ptr, hr.data(), hr.size() * sizeof(HRing), hipMemcpyHostToDevice), "ring copy");
+        // twiddles of every ring length N = 4 i at offset 2 i (i - 1)
+        std::vector<double2> t64((size_t)2 * p.nside * (p.nside + 1));
+        std::vector<float2> t32(t64.size());
+        for (int i = 1; i <= p.nside; ++i) {
+            const int N = 4 * i;
+            const size_t off = (size_t)2 * i * (i - 1);
+            for (int t = 0; t < N; ++t) {
+                long double a = 2.0L * 3.141592653589793238462643383279502884L * (long double)t / (long double)N;
+                t64[off + t] = make_double2((double)cosl(a), (double)sinl(a));
+                t32[off + t] = make_float2((float)cosl(a), (float)sinl(a));
+            }
+        }
+        TL_HIP(hipMemcpy(p.twid64.ptr, t64.data(), t64.size() * sizeof(double2), hipMemcpyHostToDevice), "tw");
+        TL_HIP(hipMemcpy(p.twid32.ptr, t32.data(), t32.size() * sizeof(float2), hipMemcpyHostToDevice), "tw");
     }
     std::vector<double2> pt(p.nphi);
     std::vector<double> pv(p.nphi + 1);
@@ -297,6 +411,11 @@ int upload_tables(Plan &p)
         pv[k] = 2.0 * M_PI * (double)k / (double)p.nphi;
         if (k < p.nphi) pt[k] = make_double2(std::cos(pv[k]), std::sin(pv[k]));
     }
+    TL_HIP(hipMemcpy(p.theta.ptr, th.data(), th.size() * sizeof(double), hipMemcpyHostToDevice), "table copy");
+    TL_HIP(hipMemcpy(p.trig.ptr, tr.data(), tr.size() * sizeof(double2), hipMemcpyHostToDevice), "table copy");
+    TL_HIP(hipMemcpy(p.phitab.ptr, pt.data(), pt.size() * sizeof(double2), hipMemcpyHostToDevice), "table copy");
+    TL_HIP(hipMemcpy(p.phival.ptr, pv.data(), pv.size() * sizeof(double), hipMemcpyHostToDevice), "table copy");
+    if (p.nside) return TL_OK;
     const int N = p.nphi;  // FFT twiddles e^{2 pi i t / nphi}
     std::vector<double2> t64(N);
     std::vector<float2> t32(N);
@@ -305,10 +424,6 @@ int upload_tables(Plan &p)
         t64[t] = make_double2((double)cosl(a), (double)sinl(a));
         t32[t] = make_float2((float)cosl(a), (float)sinl(a));
     }
-    TL_HIP(hipMemcpy(p.theta.ptr, th.data(), th.size() * sizeof(double), hipMemcpyHostToDevice), "table copy");
-    TL_HIP(hipMemcpy(p.trig.ptr, tr.data(), tr.size() * sizeof(double2), hipMemcpyHostToDevice), "table copy");
-    TL_HIP(hipMemcpy(p.phitab.ptr, pt.data(), pt.size() * sizeof(double2), hipMemcpyHostToDevice), "table copy");
-    TL_HIP(hipMemcpy(p.phival.ptr, pv.data(), pv.size() * sizeof(double), hipMemcpyHostToDevice), "table copy");
     TL_HIP(hipMemcpy(p.twid64.ptr, t64.data(), t64.size() * sizeof(double2), hipMemcpyHostToDevice), "table copy");
     TL_HIP(hipMemcpy(p.twid32.ptr, t32.data(), t32.size() * sizeof(float2), hipMemcpyHostToDevice), "table copy");
     return TL_OK;
@@ -611,8 +726,9 @@ int cnn_check_plan(tl_plan plan, tl_cnn net)
     if (!plan) return fail(TL_ERR_INVALID, "plan is NULL");
     if (!net) return fail(TL_ERR_INVALID, "network is NULL");
     const Plan &p = plan->p;
-    if (p.order != 2 || !p.pol || p.fp64())
-        return fail(TL_ERR_UNSUPPORTED, "the correction network needs an order-2 polarized plan with float maps");
+    if (p.order != 2 || !p.pol || p.fp64() || p.nside)
+        return fail(TL_ERR_UNSUPPORTED,
+                    "the correction network needs an order-2 polarized equal-theta plan with float maps");
     return TL_OK;
 }
 
@@ -849,9 +965,14 @@ struct BatchStreams {
 };
 
 // Plan fields from validated options (no device work).
-void plan_fields(Plan &p, int32_t lmax, tl_grid grid, const tl_options *opt, void *hip_stream)
+void plan_fields(Plan &p, int32_t lmax, tl_grid grid, const tl_options *opt, void *hip_stream, int nside = 0)
 {
     p.lmax = lmax;
+    p.nside = nside;
+    if (nside) {
+        grid.ntheta = 4 * nside - 1;  // HEALPix rings; nphi = the longest ring
+        grid.nphi = 4 * nside;
+    }
     p.ntheta = grid.ntheta;
     p.nphi = grid.nphi;
     p.nrp = (grid.ntheta + 1) / 2;
@@ -872,8 +993,16 @@ void plan_fields(Plan &p, int32_t lmax, tl_grid grid, const tl_options *opt, voi
         // about 5e-6 of the map RMS at lmax 4096 (4e-6 at 0.08, 1.6e-6 at
         // 0.15, 1e-5 at 0.03)
         const double smin = p.precision == TL_FP16X2 ? 0.05 : 0.15;
-        int rp = 1;
-        while (rp < p.nrp && std::sin(M_PI * (double)rp / (double)(p.ntheta - 1)) < smin) ++rp;
+        std::vector<double> th;
+        std::vector<HRing> hr;
+        if (p.nside) healpix_rings(p.nside, th, hr);
+        auto sin_ring = [&](int r) {
+            return p.nside ? std::sin(th[r]) : std::sin(M_PI * (double)r / (double)(p.ntheta - 1));
+        };
+        // the equal-theta grid's pole ring always stays direct (its deflection
+        // is a limit); HEALPix has no pole ring
+        int rp = p.nside ? 0 : 1;
+        while (rp < p.nrp && sin_ring(rp) < smin) ++rp;
         p.rpole = rp;
     }
     p.batch = opt->batch > 1 ? opt->batch : 1;
@@ -902,7 +1031,8 @@ int plan_device_checks(Plan &p)
     int smem = 0;
     TL_HIP(hipDeviceGetAttribute(&smem, hipDeviceAttributeMaxSharedMemoryPerBlock, p.device),
            "hipDeviceGetAttribute");
-    const size_t need64 = 2 * (size_t)(p.nphi / 2) * sizeof(double2);
+    // ring FFT buffers in LDS: 2 M (equal-theta) or 2 M + 1 (HEALPix, M = 2 nside)
+    const size_t need64 = (2 * (size_t)(p.nphi / 2) + (p.nside ? 1 : 0)) * sizeof(double2);
     if (need64 > (size_t)smem)
         return fail(TL_ERR_UNSUPPORTED, "nphi too large for the FP64 ring FFT in LDS on this device (" +
                                             std::to_string(need64) + " > " + std::to_string(smem) + " bytes)");
@@ -924,7 +1054,7 @@ std::vector<BufItem> plan_buffer_list(Plan &p, const Sizes &sz)
             {&p.alpha, sz.alpha, "alpha"},   {&p.F, sz.F, "F"},                {&p.D, sz.D, "D"},
             {&p.jobsDefl, sz.jd, "jobsDefl"}, {&p.jobsMain, sz.jm, "jobsMain"}, {&p.tab, sz.tab, "tab"},
             {&p.moff, sz.moff, "moff"},      {&p.kstart, sz.kstart, "kstart"}, {&p.rhs, sz.rhs, "rhs"},
-            {&p.colexp, sz.colexp, "colexp"}, {&p.tabsum, sz.tabsum, "tabsum"}};
+            {&p.colexp, sz.colexp, "colexp"}, {&p.tabsum, sz.tabsum, "tabsum"}, {&p.hring, sz.hring, "hring"}};
 }
 
 // Everything a plan computes into its buffers once they exist: angle and
@@ -1036,6 +1166,51 @@ int tl_plan_create(tl_plan *out, int32_t lmax, tl_grid grid, const tl_options *o
     if (!h) return fail(TL_ERR_NOMEM, "host allocation failed");
     Plan &p = h->p;
     plan_fields(p, lmax, grid, opt, hip_stream);
+    Sizes sz = plan_sizes(p);
+    if (p.cap > 0 && sz.total() > (size_t)p.cap) {
+        delete h;
+        return fail(TL_ERR_NOMEM, "plan needs " + std::to_string(sz.total()) + " bytes, above workspace_cap " +
+                                      std::to_string(p.cap));
+    }
+    if ((rc = plan_device_checks(p))) {
+        delete h;
+        return rc;
+    }
+    for (auto &it : plan_buffer_list(p, sz)) {
+        if (it.n == 0) continue;
+        rc = alloc(p, *it.b, it.n, it.name);
+        if (rc) {
+            free_plan_buffers(p);
+            delete h;
+            return rc;
+        }
+    }
+    if ((rc = plan_setup(p))) {
+        free_plan_buffers(p);
+        delete h;
+        return rc;
+    }
+    *out = h;
+    return TL_OK;
+}
+
+int tl_plan_create_healpix(tl_plan *out, int32_t lmax, int32_t nside, const tl_options *opt, void *hip_stream)
+{
+    if (!out) return fail(TL_ERR_INVALID, "plan output pointer is NULL");
+    *out = nullptr;
+    if (nside < 1) return fail(TL_ERR_INVALID, "nside must be >= 1");
+    if (nside > 2048) return fail(TL_ERR_UNSUPPORTED, "nside above 2048 is not supported (FP64 ring FFT in LDS)");
+    // the options and lmax as for the equal-theta grid; the ring lengths of a
+    // HEALPix grid need no relation to lmax (the ring synthesis folds m)
+    int32_t n2 = 8;  // a power of two >= 2 lmax stands in for the ring length
+    while (n2 < 2 * (int64_t)lmax && n2 < (1 << 30)) n2 *= 2;
+    tl_grid g{3, n2};
+    int rc = validate_options(lmax, g, opt);
+    if (rc) return rc;
+    tl_plan_s *h = new (std::nothrow) tl_plan_s();
+    if (!h) return fail(TL_ERR_NOMEM, "host allocation failed");
+    Plan &p = h->p;
+    plan_fields(p, lmax, g, opt, hip_stream, nside);
     Sizes sz = plan_sizes(p);
     if (p.cap > 0 && sz.total() > (size_t)p.cap) {
         delete h;
@@ -1329,6 +1504,7 @@ int tl_batch_create(tl_batch *out, int32_t n, const tl_plan *plans, const tl_bat
         const Plan &p = plans[i]->p;
         const Plan &p0 = plans[0]->p;
         if (p.precision != TL_FP32) return fail(TL_ERR_UNSUPPORTED, "a batch needs TL_FP32 plans");
+        if (p.nside) return fail(TL_ERR_UNSUPPORTED, "a batch needs equal-theta plans");
         if (p.order != p0.order || p.pol != p0.pol) return fail(TL_ERR_INVALID, "plans differ in order or pol");
         if (p.stream != p0.stream || p.device != p0.device) return fail(TL_ERR_INVALID, "plans differ in stream");
         if (!mfma_supported(p.order, p.pol != 0)) return fail(TL_ERR_UNSUPPORTED, "order too high for the batch");

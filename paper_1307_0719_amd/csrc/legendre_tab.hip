@@ -177,20 +177,20 @@ __device__ __forceinline__ void rhs_row(const TabBatch &batch, int b, size_t idx
 // be regrouped into the 8-value entries.  FP16: every column of a given m is
 // scaled by the power of two 2^e that brings its largest |value| to
 // [2^13, 2^14); e goes to colexp[m][column].
-template <bool BF, bool SPLIT, int N, bool POL, bool HASB, int NBAT>
-__global__ __launch_bounds__(256) void k_tab_rhs(int lmax, int ntile, const int64_t *__restrict__ moff,
+template <bool BF, bool SPLIT, int N, bool POL, bool HASB, int NBMAX>
+__global__ __launch_bounds__(256) void k_tab_rhs(int lmax, int ntile, int NBAT, const int64_t *__restrict__ moff,
                                                  const TabBatch batch, uint4 *__restrict__ rhs,
                                                  float *__restrict__ colexp)
 {
     using T = typename H<BF>::T;
     constexpr Cols C = cols_of(N, POL, HASB, true);
-    constexpr int NCOLS = NBAT * C.n1;
-    constexpr int NB = (NCOLS + 31) / 32;
+    const int NCOLS = NBAT * C.n1;
+    const int NB = (NCOLS + 31) / 32;
     constexpr int NSPL = SPLIT ? 2 : 1;
-    constexpr int RCH = NSPL * NB * 128;  // uint4 per chunk
-    constexpr int LCH = 128;              // l per LDS slice (four chunks)
-    constexpr int CW = NB * 32 + 2;       // LDS row (columns, padded)
-    __shared__ float s_ex[NB * 32];
+    const int RCH = NSPL * NB * 128;                // uint4 per chunk
+    constexpr int LCH = NBMAX <= 4 ? 128 : 32;      // l per LDS slice
+    constexpr int CW = NBMAX * 32 + 2;              // LDS row (columns, padded)
+    __shared__ float s_ex[NBMAX * 32];
     __shared__ T s_v[NSPL][LCH][CW];
     const int m = blockIdx.x;
     const int tid = threadIdx.x, lane = tid & 63;
@@ -241,7 +241,7 @@ __global__ __launch_bounds__(256) void k_tab_rhs(int lmax, int ntile, const int6
         __syncthreads();
         {
             const int li = tid & (LCH - 1), l = l0 + li;
-            for (int b0 = tid >> 7; b0 < NBAT; b0 += 2) {
+            for (int b0 = tid / LCH; b0 < NBAT; b0 += 256 / LCH) {
                 double v[C.n1];
                 if (l <= lmax) {
                     double L, nl;
@@ -267,7 +267,7 @@ __global__ __launch_bounds__(256) void k_tab_rhs(int lmax, int ntile, const int6
         }
         __syncthreads();
         const int kc0 = (l0 - m) / KC;
-        constexpr int PER = RCH;  // uint4 entries per chunk
+        const int PER = RCH;  // uint4 entries per chunk
         for (int idx = tid; idx < (LCH / KC) * PER; idx += 256) {
             const int q = idx / PER, w = idx % PER;
             const int kc = kc0 + q;
@@ -284,6 +284,14 @@ __global__ __launch_bounds__(256) void k_tab_rhs(int lmax, int ntile, const int6
     }
 }
 
+// Column sums of a table pass with nbat realizations, [m][ring pair - rbeg]
+// [realization][type * 2 + parity][column of the realization]: the blocks a
+// wave writes for one (m, ring pair) share cache lines.
+__device__ __forceinline__ size_t colsum_offset(int bb, int rp, int m, int nrn, int nbat, int n1)
+{
+    return (((size_t)m * nrn + rp) * nbat + bb) * 4 * n1;
+}
+
 // Batched GEMM: one workgroup = 4 waves = 4 tiles of 32 ring pairs at one m;
 // NBAT realizations, NB = ceil(NBAT * n1 / 32) column blocks in one pass.  The
 // table streams from HBM once per pass; the right-hand sides of one m (built
@@ -294,17 +302,14 @@ __global__ __launch_bounds__(256) void k_tab_rhs(int lmax, int ntile, const int6
 // powers of two, go to HBM straight from the accumulators (lanes hold
 // consecutive columns): sums[m][ring pair - rbeg][realization][type*2 +
 // parity][column of the realization]; k_tab_epi turns them into the rows.
-template <bool BF, bool SPLIT, int N, bool POL, bool HASB, int NBAT>
+template <bool BF, bool SPLIT, int NB>
 __global__ __launch_bounds__(256) void k_legendre_tab(int lmax, int nrp, int rbeg, int ntile, int ngrp, int e0, int e1,
-                                                      const int *__restrict__ mcut, const int64_t *__restrict__ moff,
-                                                      const uint4 *__restrict__ tab, const int *__restrict__ kstart,
-                                                      const uint4 *__restrict__ rhs, const float *__restrict__ colexp,
-                                                      float *__restrict__ sums)
+                                                      int n1, int NCOLS, const int *__restrict__ mcut,
+                                                      const int64_t *__restrict__ moff, const uint4 *__restrict__ tab,
+                                                      const int *__restrict__ kstart, const uint4 *__restrict__ rhs,
+                                                      const float *__restrict__ colexp, float *__restrict__ sums)
 {
     using V = typename H<BF>::V;
-    constexpr Cols C = cols_of(N, POL, HASB, true);
-    constexpr int NCOLS = NBAT * C.n1;
-    constexpr int NB = (NCOLS + 31) / 32;
     constexpr int NSPL = SPLIT ? 2 : 1;
     constexpr int RCH = NSPL * NB * 128;
 
@@ -432,23 +437,21 @@ __global__ __launch_bounds__(256) void k_legendre_tab(int lmax, int nrp, int rbe
     const float usc[2] = {ldexpf(1.f, -e0), ldexpf(1.f, -e1)};  // exact: powers of two
     const float *cex = colexp + (size_t)m * NB * 32;
     const int rp0 = tile * TILE + 4 * hl;  // ring pair of accumulator slot 0
-    constexpr int RSTR = NBAT * 4 * C.n1;  // floats per ring pair
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
         const int col = b * 32 + rl;
         if (col >= NCOLS) continue;
-        const int bb = col / C.n1, c = col % C.n1;
+        const int bb = col / n1, c = col % n1;
         const float isc = exp2f(-cex[col]);  // exact: powers of two
-        float *base = sums + ((size_t)m * nrn + rp0) * RSTR + bb * 4 * C.n1 + c;
 #pragma unroll
         for (int v = 0; v < 16; ++v) {
-            const int row = 8 * (v >> 2) + (v & 3);
-            if (rp0 + row >= nrn) continue;
+            const int rp = rp0 + 8 * (v >> 2) + (v & 3);
+            if (rp >= nrn) continue;
+            float *base = sums + colsum_offset(bb, rp, m, nrn, NCOLS / n1, n1) + c;
 #pragma unroll
             for (int t = 0; t < 2; ++t)
 #pragma unroll
-                for (int p = 0; p < 2; ++p)
-                    base[row * RSTR + (t * 2 + p) * C.n1] = acc[b][t][p][v] * isc * usc[t];
+                for (int p = 0; p < 2; ++p) base[(t * 2 + p) * n1] = acc[b][t][p][v] * isc * usc[t];
         }
     }
 }
@@ -458,8 +461,8 @@ __global__ __launch_bounds__(256) void k_legendre_tab(int lmax, int nrp, int rbe
 // m) are formed once and applied to every realization's column sums: T and
 // the lensing potential below the ring's cut, Q/U two past it (spin-2
 // functions reach |m - 2|); zeros beyond.
-template <int N, bool POL, bool HASB, int NBAT>
-__global__ __launch_bounds__(256) void k_tab_epi(int lmax, int ntheta, int nrp, int rbeg,
+template <int N, bool POL, bool HASB>
+__global__ __launch_bounds__(256) void k_tab_epi(int lmax, int ntheta, int nrp, int rbeg, int NBAT,
                                                  const double *__restrict__ theta, const int *__restrict__ mcut,
                                                  const float *__restrict__ sums, const TabBatch batch)
 {
@@ -474,7 +477,8 @@ __global__ __launch_bounds__(256) void k_tab_epi(int lmax, int ntheta, int nrp, 
     // stored there again (a select, not a branch around the stores)
     const bool eq = rs == r;
     const size_t on = (size_t)r * (lmax + 1) + m, os = (size_t)rs * (lmax + 1) + m;
-    const float *S0 = sums + ((size_t)m * nrn + (r - rbeg)) * NBAT * 4 * C.n1;
+    const size_t sstride = (size_t)4 * C.n1;  // one realization's sums
+    const float *S0 = sums + colsum_offset(0, r - rbeg, m, nrn, NBAT, C.n1);
     const int mc = mcut[r];
     const double th = theta[r];
 
@@ -498,7 +502,7 @@ __global__ __launch_bounds__(256) void k_tab_epi(int lmax, int ntheta, int nrp, 
         if (act) coefficients_T<N>(th, m, cf);
         for (int bb = 0; bb < NBAT; ++bb) {
             float2 R[4][NT2 + 1];  // T columns, then the potential's
-            if (act) load_cols(S0 + (size_t)bb * 4 * C.n1, 0, R, true);
+            if (act) load_cols(S0 + (size_t)bb * sstride, 0, R, true);
             auto val = [&](int q4, int c) -> double {
                 const int i = c < C.nT ? c >> 1 : NT2;
                 return (c & 1) ? (double)R[q4][i].y : (double)R[q4][i].x;
@@ -545,7 +549,7 @@ __global__ __launch_bounds__(256) void k_tab_epi(int lmax, int ntheta, int nrp, 
         if (act) coefficients_P<N>(th, m, cf);
         for (int bb = 0; bb < NBAT; ++bb) {
             float2 R[4][NQ2];  // E (and B) columns
-            if (act) load_cols(S0 + (size_t)bb * 4 * C.n1, C.nT, R, false);
+            if (act) load_cols(S0 + (size_t)bb * sstride, C.nT, R, false);
             auto val = [&](int q4, int c) -> double {
                 const int i = (c - C.nT) >> 1;
                 return (c & 1) ? (double)R[q4][i].y : (double)R[q4][i].x;
@@ -606,53 +610,49 @@ hipError_t build_BS(Plan &p)
     return hipGetLastError();
 }
 
-template <bool BF, bool SPLIT, int N, bool POL, bool HASB, int NBAT>
-hipError_t gemm_launch(Plan &p, const TabBatch &b, int part)
+// The table pass over NB column blocks (ncols columns, n1 per realization).
+template <bool BF, bool SPLIT, int NB>
+hipError_t gemm_pass(Plan &p, int n1, int ncols)
 {
-    constexpr int NB = (NBAT * cols_of(N, POL, HASB, true).n1 + 31) / 32;
-    if constexpr (NB > 4) {
-        return hipErrorInvalidValue;
-    } else {
-        if ((size_t)NB > p.rhs_nb) return hipErrorInvalidValue;  // buffers sized at plan time
-        if (part == 0) {
-            hipLaunchKernelGGL((k_tab_rhs<BF, SPLIT, N, POL, HASB, NBAT>), dim3(p.lmax + 1), dim3(256), 0, p.stream,
-                               p.lmax, p.ntile, (const int64_t *)p.moff.ptr, b, (uint4 *)p.rhs.ptr,
-                               (float *)p.colexp.ptr);
-            return hipGetLastError();
-        }
-        if (part == 1) {
-            const int ngrp = (p.ntile + 3) / 4;
-            const int m8 = (p.lmax + 1 + 7) / 8;
-            hipLaunchKernelGGL((k_legendre_tab<BF, SPLIT, N, POL, HASB, NBAT>), dim3(8 * m8 * ngrp), dim3(256), 0,
-                               p.stream, p.lmax, p.nrp, p.rpole, p.ntile, ngrp, p.lam_e0, p.lam_e1,
-                               (const int *)p.mcut.ptr,
-                               (const int64_t *)p.moff.ptr, (const uint4 *)p.tab.ptr, (const int *)p.kstart.ptr,
-                               (const uint4 *)p.rhs.ptr, (const float *)p.colexp.ptr, (float *)p.tabsum.ptr);
-            return hipGetLastError();
-        }
-        const int nrn = p.nrp - p.rpole;
-        if ((size_t)(p.lmax + 1) * nrn * NBAT * 4 * cols_of(N, POL, HASB, true).n1 * sizeof(float) > p.tabsum.bytes)
-            return hipErrorInvalidValue;
-        dim3 grid((p.lmax + 1 + 63) / 64, (nrn + 3) / 4);
-        hipLaunchKernelGGL((k_tab_epi<N, POL, HASB, NBAT>), grid, dim3(256), 0, p.stream, p.lmax, p.ntheta, p.nrp,
-                           p.rpole, (const double *)p.theta.ptr, (const int *)p.mcut.ptr,
-                           (const float *)p.tabsum.ptr, b);
-        return hipGetLastError();
-    }
+    const int m8 = (p.lmax + 1 + 7) / 8;
+    const int ngrp = (p.ntile + 3) / 4;
+    hipLaunchKernelGGL((k_legendre_tab<BF, SPLIT, NB>), dim3(8 * m8 * ngrp), dim3(256), 0, p.stream, p.lmax, p.nrp,
+                       p.rpole, p.ntile, ngrp, p.lam_e0, p.lam_e1, n1, ncols, (const int *)p.mcut.ptr,
+                       (const int64_t *)p.moff.ptr, (const uint4 *)p.tab.ptr, (const int *)p.kstart.ptr,
+                       (const uint4 *)p.rhs.ptr, (const float *)p.colexp.ptr, (float *)p.tabsum.ptr);
+    return hipGetLastError();
 }
 
 template <bool BF, bool SPLIT, int N, bool POL, bool HASB>
-hipError_t gemm_nbat(Plan &p, const TabBatch &b, int part)
+hipError_t gemm_launch(Plan &p, const TabBatch &b, int part)
 {
-    switch (b.n) {
-    case 1: return gemm_launch<BF, SPLIT, N, POL, HASB, 1>(p, b, part);
-    case 2: return gemm_launch<BF, SPLIT, N, POL, HASB, 2>(p, b, part);
-    case 3: return gemm_launch<BF, SPLIT, N, POL, HASB, 3>(p, b, part);
-    case 4: return gemm_launch<BF, SPLIT, N, POL, HASB, 4>(p, b, part);
-    case 5: return gemm_launch<BF, SPLIT, N, POL, HASB, 5>(p, b, part);
-    case 6: return gemm_launch<BF, SPLIT, N, POL, HASB, 6>(p, b, part);
-    default: return hipErrorInvalidValue;
+    constexpr int n1 = cols_of(N, POL, HASB, true).n1;
+    const int nbat = b.n;
+    const int ncols = nbat * n1;
+    const int NB = (ncols + 31) / 32;
+    if (nbat < 1 || nbat > kTabMaxBatch || NB > kTabMaxBlocks) return hipErrorInvalidValue;
+    if ((size_t)NB > p.rhs_nb) return hipErrorInvalidValue;  // buffers sized at plan time
+    if (part == 0) {
+        hipLaunchKernelGGL((k_tab_rhs<BF, SPLIT, N, POL, HASB, kTabMaxBlocks>), dim3(p.lmax + 1), dim3(256), 0,
+                           p.stream, p.lmax, p.ntile, nbat, (const int64_t *)p.moff.ptr, b, (uint4 *)p.rhs.ptr,
+                           (float *)p.colexp.ptr);
+        return hipGetLastError();
     }
+    if (part == 1) {
+        switch (NB) {
+        case 1: return gemm_pass<BF, SPLIT, 1>(p, n1, ncols);
+        case 2: return gemm_pass<BF, SPLIT, 2>(p, n1, ncols);
+        case 3: return gemm_pass<BF, SPLIT, 3>(p, n1, ncols);
+        case 4: return gemm_pass<BF, SPLIT, 4>(p, n1, ncols);
+        default: return hipErrorInvalidValue;
+        }
+    }
+    const int nrn = p.nrp - p.rpole;
+    if ((size_t)(p.lmax + 1) * nrn * ncols * 4 * sizeof(float) > p.tabsum.bytes) return hipErrorInvalidValue;
+    dim3 grid((p.lmax + 1 + 63) / 64, (nrn + 3) / 4);
+    hipLaunchKernelGGL((k_tab_epi<N, POL, HASB>), grid, dim3(256), 0, p.stream, p.lmax, p.ntheta, p.nrp, p.rpole, nbat,
+                       (const double *)p.theta.ptr, (const int *)p.mcut.ptr, (const float *)p.tabsum.ptr, b);
+    return hipGetLastError();
 }
 
 template <bool BF, bool SPLIT>
@@ -661,9 +661,9 @@ hipError_t gemm_form(Plan &p, const TabBatch &b, int part)
     const bool hasb = p.pol && b.B[0] != nullptr;
 #define TL_CASE(NN)                                                              \
     case NN:                                                                     \
-        if (!p.pol) return gemm_nbat<BF, SPLIT, NN, false, false>(p, b, part);   \
-        if (hasb) return gemm_nbat<BF, SPLIT, NN, true, true>(p, b, part);       \
-        return gemm_nbat<BF, SPLIT, NN, true, false>(p, b, part);
+        if (!p.pol) return gemm_launch<BF, SPLIT, NN, false, false>(p, b, part); \
+        if (hasb) return gemm_launch<BF, SPLIT, NN, true, true>(p, b, part);     \
+        return gemm_launch<BF, SPLIT, NN, true, false>(p, b, part);
     switch (p.order) {
         TL_CASE(0)
         TL_CASE(1)
@@ -684,7 +684,7 @@ int tab_max_batch(int order, bool pol, bool hasb)
     if (order > 6) return 0;
     const int n1 = cols_of(order, pol, hasb, true).n1;
     int nb = 0;
-    while (nb < kTabMaxBatch && ((nb + 1) * n1 + 31) / 32 <= 4) ++nb;
+    while (nb < kTabMaxBatch && ((nb + 1) * n1 + 31) / 32 <= kTabMaxBlocks) ++nb;
     return nb;
 }
 

@@ -73,11 +73,90 @@ __global__ __launch_bounds__(256) void k_remap(int ntheta, int nphi, const doubl
     }
 }
 
+// HEALPix output and source pixels (RING order; the paper's own grid, Sec.
+// II.B): output pixel n of ring r at (theta_r, phi0_r + 2 pi n / nphi_r), its
+// displaced position x', the pixel containing x' and that pixel's centre x0';
+// the Taylor series about x0' in u = (theta' - theta0') / delta,
+// v = (phi' - phi0') / delta (wrapped to (-pi, pi]), delta = pi / (4 nside),
+// the scale of the derivative maps; then the rotation R.
+template <typename R, int N, bool POL>
+__global__ __launch_bounds__(256) void k_remap_hpx(int nside, const double *__restrict__ theta,
+                                                   const double2 *__restrict__ trig, const HRing *__restrict__ hring,
+                                                   size_t npix, const R *__restrict__ D, const double *__restrict__ at,
+                                                   const double *__restrict__ ap, const double *__restrict__ thsrc,
+                                                   const double *__restrict__ phsrc, int rotate, int naive,
+                                                   R *__restrict__ To, R *__restrict__ Qo, R *__restrict__ Uo)
+{
+    constexpr int ND = (N + 1) * (N + 2) / 2;
+    const double TWO_PI = 6.283185307179586476925286766559;
+    const int r = blockIdx.y;
+    const HRing hr = hring[r];
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= hr.nphi) return;
+    const size_t idx = (size_t)hr.start + k;
+    double thp, php, cg = 1.0, sg = 0.0;
+    if (thsrc) {
+        thp = thsrc[idx];
+        php = phsrc[idx];
+        php = php - floor(php / TWO_PI) * TWO_PI;
+        thp = thp < 0.0 ? 0.0 : (thp > M_PI ? M_PI : thp);
+    } else {
+        const double ph = hr.phi0 + TWO_PI * (double)k / (double)hr.nphi;
+        double sp, cp;
+        sincos(ph, &sp, &cp);
+        displace(theta[r], ph, trig[r].x, trig[r].y, cp, sp, at[idx], ap[idx], naive != 0, false,
+                 POL && rotate, thp, php, cg, sg);
+    }
+    int r0, k0;
+    healpix_locate(nside, thp, php, r0, k0);
+    const HRing h0 = hring[r0];
+    const double ph0 = h0.phi0 + TWO_PI * (double)k0 / (double)h0.nphi;
+    double dph = php - ph0;
+    dph -= TWO_PI * floor(dph / TWO_PI + 0.5);
+    const double idel = 4.0 * nside / M_PI;
+    const R u = (R)((thp - theta[r0]) * idel);
+    const R v = (R)(dph * idel);
+    const size_t pix0 = (size_t)h0.start + k0;
+    R res[POL ? 3 : 1];
+#pragma unroll
+    for (int f = 0; f < (POL ? 3 : 1); ++f) {
+        const R *Df = D + (size_t)f * ND * npix + pix0;
+        R acc = 0;
+#pragma unroll
+        for (int j = N; j >= 0; --j) {
+            const int base = j * (N + 1) - j * (j - 1) / 2;
+            R inner = 0;
+#pragma unroll
+            for (int kk = N - j; kk >= 0; --kk) inner = inner * v + Df[(size_t)(base + kk) * npix];
+            acc = acc * u + inner;
+        }
+        res[f] = acc;
+    }
+    To[idx] = res[0];
+    if constexpr (POL) {
+        const R q = res[1], uu = res[2];
+        Qo[idx] = (R)(cg * (double)q - sg * (double)uu);
+        Uo[idx] = (R)(sg * (double)q + cg * (double)uu);
+    }
+}
+
 template <typename R, int N>
 hipError_t remap_N(Plan &p, const void *D, const double *at, const double *ap, const double *ths,
                    const double *phs, const float *corr, void *T, void *Q, void *U)
 {
     dim3 grid((p.nphi + 255) / 256, p.ntheta);
+    if (p.nside) {
+        if (corr) return hipErrorInvalidValue;
+        if (p.pol)
+            hipLaunchKernelGGL((k_remap_hpx<R, N, true>), grid, dim3(256), 0, p.stream, p.nside,
+                               (const double *)p.theta.ptr, (const double2 *)p.trig.ptr, (const HRing *)p.hring.ptr,
+                               p.npix(), (const R *)D, at, ap, ths, phs, p.rotate, p.naive, (R *)T, (R *)Q, (R *)U);
+        else
+            hipLaunchKernelGGL((k_remap_hpx<R, N, false>), grid, dim3(256), 0, p.stream, p.nside,
+                               (const double *)p.theta.ptr, (const double2 *)p.trig.ptr, (const HRing *)p.hring.ptr,
+                               p.npix(), (const R *)D, at, ap, ths, phs, p.rotate, p.naive, (R *)T, (R *)Q, (R *)U);
+        return hipGetLastError();
+    }
     if (p.pol)
         hipLaunchKernelGGL((k_remap<R, N, true>), grid, dim3(256), 0, p.stream, p.ntheta, p.nphi,
                            (const double *)p.theta.ptr, (const double2 *)p.trig.ptr,

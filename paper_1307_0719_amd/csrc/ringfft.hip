@@ -231,6 +231,147 @@ __global__ __launch_bounds__(256) void k_ring_fft(const FftJob *__restrict__ job
     }
 }
 
+// ---- HEALPix rings: ring-dependent length and phase ----
+//
+// Ring r of a HEALPix grid has N = nphi_r pixels at phi_n = phi0_r + 2 pi n / N,
+// and lmax may exceed N / 2 (the polar rings hold 4, 8, ... pixels), so the
+// coefficients fold onto the N frequencies of the ring:
+//     X_q = e^{i q phi0} sum_{m = q mod N, |m| <= lmax} sigma^{(m - q) / N} c_m,
+// c_m = scale (i m)^k F_m, c_{-m} = conj c_m, c_0 = Re c_0, sigma = e^{i N phi0}
+// = +-1.  X is Hermitian, so the half-length transform above applies (M = N/2),
+// with a Stockham FFT over the radices of M = 2 i, any i: passes of radix 2, 3,
+// 4, 5, 8 as above, other primes p by a direct p-point sum per output (M p
+// operations per pass).  Twiddles e^{2 pi i t / N} of every length N = 4 i,
+// i = 1..nside, at offset 2 i (i - 1) of one table.
+
+// One Stockham pass of any radix RX, one output per thread and step.
+template <typename V>
+__device__ __forceinline__ void stockham_any(const V *__restrict__ src, V *__restrict__ dst, int M, int Ns, int N,
+                                             int RX, int tid, int T, const V *__restrict__ twN)
+{
+    const int nb = M / RX;
+    const int tstride = N / (Ns * RX);
+    const int np = N / RX;
+    for (int idx = tid; idx < M; idx += T) {
+        const int b = idx / RX, t = idx - b * RX;
+        const int kk = b % Ns;
+        // exponent of output t: s (kk tstride + t N / RX) for the input s
+        const int step = kk * tstride + t * np;  // < N
+        V y = cmk<V>(0, 0);
+        int e = 0;
+        for (int s2 = 0; s2 < RX; ++s2) {
+            y = cadd(y, cmul(src[b + s2 * nb], twN[e]));
+            e += step;
+            if (e >= N) e -= N;
+        }
+        dst[(b / Ns) * Ns * RX + kk + t * Ns] = y;
+    }
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_ring_fft_hpx(const FftJob *__restrict__ jobs,
+                                                      const typename C2<R>::T *__restrict__ Fbase,
+                                                      R *__restrict__ Dbase, int lmax,
+                                                      const HRing *__restrict__ hring,
+                                                      const typename C2<R>::T *__restrict__ twAll)
+{
+    using V = typename C2<R>::T;
+    extern __shared__ unsigned char smem_raw[];
+    __shared__ int s_rad[24];
+    __shared__ int s_nrad;
+    const int tid = threadIdx.x, T = blockDim.x;
+    const FftJob &job = jobs[blockIdx.x];
+    const HRing hr = hring[job.pad];
+    const int N = hr.nphi, M = N / 2, L = lmax;
+    const int i4 = N / 4;
+    const V *twN = twAll + (size_t)2 * i4 * (i4 - 1);
+    V *bufA = reinterpret_cast<V *>(smem_raw);  // M entries
+    V *bufB = bufA + M;                           // M + 1 entries (X_0 .. X_M)
+    const V *F = Fbase + job.src;
+    if (tid == 0) {
+        // radices of M: 8, 4, 2, 5, 3, then the remaining primes ascending
+        int n = M, c = 0;
+        const int small[5] = {8, 4, 2, 5, 3};
+        for (int a = 0; a < 5; ++a)
+            while (n % small[a] == 0 && n > 1) {
+                s_rad[c++] = small[a];
+                n /= small[a];
+            }
+        for (int pr = 7; n > 1; pr += 2)
+            while (n % pr == 0) {
+                s_rad[c++] = pr;
+                n /= pr;
+            }
+        s_nrad = c;
+    }
+    for (int q = 0; q < job.nk; ++q) {
+        const int k = job.k[q];
+        const double scale = job.scale[q];
+        auto coef = [&](int m) -> double2 {  // scale (i m)^k F_m, m >= 0
+            const V f = F[m];
+            double mk = 1.0;
+            for (int t = 0; t < k; ++t) mk *= (double)m;
+            const double s = scale * mk;
+            double re = s * (double)f.x, im = m == 0 ? 0.0 : s * (double)f.y;
+            switch (k & 3) {
+            case 1: { const double t2 = re; re = -im; im = t2; } break;
+            case 2: re = -re; im = -im; break;
+            case 3: { const double t2 = re; re = im; im = -t2; } break;
+            default: break;
+            }
+            return make_double2(re, im);
+        };
+        // folded half spectrum X_0 .. X_M
+        for (int qq = tid; qq <= M; qq += T) {
+            double re = 0.0, im = 0.0, sg = 1.0;
+            for (int m = qq; m <= L; m += N, sg *= hr.sigma) {
+                const double2 c = coef(m);
+                re += sg * c.x;
+                im += sg * c.y;
+            }
+            sg = hr.sigma;
+            for (int m = N - qq; m <= L; m += N, sg *= hr.sigma) {  // m = -(t N - qq), t >= 1
+                const double2 c = coef(m);
+                re += sg * c.x;
+                im -= sg * c.y;
+            }
+            double sn, cs;
+            sincos((double)qq * hr.phi0, &sn, &cs);
+            double xr = re * cs - im * sn, xi = re * sn + im * cs;
+            if (qq == 0 || qq == M) xi = 0.0;  // real by Hermitian symmetry
+            bufB[qq] = cmk<V>((R)xr, (R)xi);
+        }
+        __syncthreads();
+        for (int m = tid; m < M; m += T) {
+            const V xm = bufB[m];
+            const V xc = cconj(bufB[M - m]);
+            bufA[m] = cadd(cadd(xm, xc), cmuli(cmul(twN[m], csub(xm, xc))));
+        }
+        __syncthreads();
+        V *src = bufA, *dst = bufB;
+        int Ns = 1;
+        for (int pi = 0; pi < s_nrad; ++pi) {
+            const int r = s_rad[pi];
+            switch (r) {
+            case 2: stockham_pass<2, V>(src, dst, M, Ns, N, tid, T, twN); break;
+            case 3: stockham_pass<3, V>(src, dst, M, Ns, N, tid, T, twN); break;
+            case 4: stockham_pass<4, V>(src, dst, M, Ns, N, tid, T, twN); break;
+            case 5: stockham_pass<5, V>(src, dst, M, Ns, N, tid, T, twN); break;
+            case 8: stockham_pass<8, V>(src, dst, M, Ns, N, tid, T, twN); break;
+            default: stockham_any<V>(src, dst, M, Ns, N, r, tid, T, twN); break;
+            }
+            __syncthreads();
+            V *t2 = src;
+            src = dst;
+            dst = t2;
+            Ns *= r;
+        }
+        R *out = Dbase + job.dst[q];
+        for (int n = tid; n < M; n += T) reinterpret_cast<V *>(out)[n] = src[n];
+        __syncthreads();
+    }
+}
+
 __global__ void k_fill_words(uint32_t *__restrict__ x, size_t n, uint32_t v)
 {
     const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -490,6 +631,18 @@ hipError_t prep_p2()
 
 hipError_t fft_prepare(Plan &p)
 {
+    if (p.nside) {
+        const size_t M = 2 * (size_t)p.nside;
+        const size_t b64 = (2 * M + 1) * sizeof(double2), b32 = (2 * M + 1) * sizeof(float2);
+        hipError_t e = hipSuccess;
+        if (b64 > 65536)
+            e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_ring_fft_hpx<double>),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)b64);
+        if (e == hipSuccess && b32 > 65536)
+            e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_ring_fft_hpx<float>),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)b32);
+        return e;
+    }
     const size_t M = (size_t)p.nphi / 2;
     if (M == 4096) {
         hipError_t e = prep_p2<double, 4096>();
@@ -540,6 +693,18 @@ bool fft_p2(int M) { return M == 512 || M == 1024 || M == 2048 || M == 4096; }
 hipError_t launch_fft_jobs(Plan &p, const void *Fbase, void *Dbase, const FftJob *jobs, int njobs, bool fp64)
 {
     if (njobs <= 0) return hipSuccess;
+    if (p.nside) {
+        const size_t M = 2 * (size_t)p.nside;
+        if (fp64)
+            hipLaunchKernelGGL(k_ring_fft_hpx<double>, dim3(njobs), dim3(256), (2 * M + 1) * sizeof(double2),
+                               p.stream, jobs, (const double2 *)Fbase, (double *)Dbase, p.lmax,
+                               (const HRing *)p.hring.ptr, (const double2 *)p.twid64.ptr);
+        else
+            hipLaunchKernelGGL(k_ring_fft_hpx<float>, dim3(njobs), dim3(256), (2 * M + 1) * sizeof(float2),
+                               p.stream, jobs, (const float2 *)Fbase, (float *)Dbase, p.lmax,
+                               (const HRing *)p.hring.ptr, (const float2 *)p.twid32.ptr);
+        return hipGetLastError();
+    }
     const int M = p.nphi / 2;
     if (fft_p2(M)) {
         if (fp64) return launch_p2_R<double>(p, Fbase, Dbase, jobs, njobs, p.twid64.ptr, M);

@@ -38,7 +38,8 @@ struct FftJob {
 };
 
 // Realizations handled by one pass of the table GEMM (reduced-precision forms).
-constexpr int kTabMaxBatch = 6;
+constexpr int kTabMaxBatch = 6;   // realizations per table pass
+constexpr int kTabMaxBlocks = 4;   // 32-column blocks per table pass
 struct TabBatch {
     int n;
     const double2 *T[kTabMaxBatch];
@@ -53,8 +54,18 @@ struct TabBatch {
     double2 *FP[kTabMaxBatch];
 };
 
+// One ring of a HEALPix grid (RING order): first pixel, pixel count, the
+// phase e^{i nphi phi0} (+-1) and phi of the first pixel.
+struct HRing {
+    int64_t start;
+    int32_t nphi;
+    int32_t sigma;
+    double phi0;
+};
+
 struct Plan {
     int lmax = 0;
+    int nside = 0;    // > 0: HEALPix rings (RING order) instead of the equal-theta grid
     int ntheta = 0, nphi = 0;
     int nrp = 0;      // ring pairs = ceil(ntheta/2)
     int order = 0;    // N
@@ -89,6 +100,7 @@ struct Plan {
     DevBuf start;     // double [3][lmax+1][jtab][nrp]
     DevBuf exps;      // int    [3][lmax+1][nrp]
     DevBuf mcut;      // int    [nrp]  largest significant m per ring pair
+    DevBuf hring;     // HRing [ntheta] (HEALPix plans)
     DevBuf tab;       // lambda / lambda' tables in MFMA operand layout (reduced-precision forms)
     DevBuf moff;      // int64 [lmax+2] offsets (16-byte units) of each m in tab
     DevBuf kstart;    // int [lmax+1][ntile] first non-empty 32-l chunk
@@ -122,7 +134,7 @@ struct Plan {
     int ndmap() const { return (order + 1) * (order + 2) / 2; }
     bool fp64() const { return precision == TL_FP64; }
     bool tabform() const { return precision >= TL_BF16X3; }
-    size_t npix() const { return (size_t)ntheta * (size_t)nphi; }
+    size_t npix() const { return nside ? (size_t)12 * nside * nside : (size_t)ntheta * (size_t)nphi; }
     size_t nalm() const { return (size_t)(lmax + 1) * (size_t)(lmax + 2) / 2; }
 };
 

@@ -34,7 +34,7 @@ EXPORTS = [
     "tl_lens_map_simple", "tl_lens_map_many", "tl_plan_profile", "tl_plan_stage_times", "tl_last_error", "tl_version",
     "tl_cnn_create", "tl_cnn_destroy", "tl_cnn_get_params", "tl_cnn_set_params", "tl_cnn_forward", "tl_cnn_grad",
     "tl_cnn_train_step", "tl_lens_map_cnn", "tl_batch_create", "tl_batch_destroy", "tl_batch_run", "tl_batch_info",
-    "tl_lens_map_simple_noalloc",
+    "tl_lens_map_simple_noalloc", "tl_plan_create_healpix",
 ]
 CNN_NTRAIN = 15139
 CNN_NPARAM = 15142
@@ -81,6 +81,8 @@ def lib():
         L = ctypes.CDLL(LIB_PATH)
         vp = ctypes.c_void_p
         L.tl_plan_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int32, Grid, ctypes.POINTER(Options), vp]
+        L.tl_plan_create_healpix.argtypes = [ctypes.POINTER(vp), ctypes.c_int32, ctypes.c_int32,
+                                             ctypes.POINTER(Options), vp]
         L.tl_plan_destroy.argtypes = [vp]
         L.tl_plan_workspace_bytes.argtypes = [vp, ctypes.POINTER(ctypes.c_int64)]
         L.tl_plan_query.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64)]
@@ -148,8 +150,14 @@ class Plan:
     def __init__(self, lmax: int, ntheta: int, nphi: int, order: int, precision: str = "fp32",
                  pol: bool = True, rotate: bool = True, naive_pos: bool = False, workspace_cap: int = 0,
                  device: Optional[torch.device] = None, stream: Optional[torch.cuda.Stream] = None,
-                 batch: int = 1):
+                 batch: int = 1, nside: int = 0):
+        """ntheta x nphi equal-theta grid, or with nside > 0 HEALPix rings
+        (ntheta, nphi ignored; maps are [12 nside^2] in RING order)."""
+        self.nside = int(nside)
+        if self.nside:
+            ntheta, nphi = 4 * self.nside - 1, 4 * self.nside
         self.lmax, self.ntheta, self.nphi, self.order = int(lmax), int(ntheta), int(nphi), int(order)
+        self.npix = 12 * self.nside ** 2 if self.nside else self.ntheta * self.nphi
         self.precision = precision
         self.pol = bool(pol)
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
@@ -161,8 +169,12 @@ class Plan:
         self.batch = int(batch)
         h = ctypes.c_void_p()
         with torch.cuda.device(self.device):
-            _check(lib().tl_plan_create(ctypes.byref(h), self.lmax, Grid(self.ntheta, self.nphi),
-                                        ctypes.byref(opt), ctypes.c_void_p(self.stream.cuda_stream)))
+            if self.nside:
+                _check(lib().tl_plan_create_healpix(ctypes.byref(h), self.lmax, self.nside, ctypes.byref(opt),
+                                                    ctypes.c_void_p(self.stream.cuda_stream)))
+            else:
+                _check(lib().tl_plan_create(ctypes.byref(h), self.lmax, Grid(self.ntheta, self.nphi),
+                                            ctypes.byref(opt), ctypes.c_void_p(self.stream.cuda_stream)))
         self._h = h
         self.real_dtype = torch.float64 if precision == "fp64" else torch.float32
         self.cplx_dtype = torch.complex128 if precision == "fp64" else torch.complex64
@@ -214,8 +226,12 @@ class Plan:
         except Exception:
             pass
 
+    @property
+    def map_shape(self):
+        return (self.npix,) if self.nside else (self.ntheta, self.nphi)
+
     def _maps(self, n=None):
-        shape = (self.ntheta, self.nphi) if n is None else (n, self.ntheta, self.nphi)
+        shape = self.map_shape if n is None else (n, *self.map_shape)
         return torch.empty(shape, dtype=self.real_dtype, device=self.device)
 
     def _inputs(self, alm_T, alm_E, alm_B):
@@ -270,7 +286,7 @@ class Plan:
 
     def deflection(self, alm_phi):
         P = _alm(alm_phi, "alm_phi", self.device, self.lmax)
-        at = torch.empty((self.ntheta, self.nphi), dtype=torch.float64, device=self.device)
+        at = torch.empty(self.map_shape, dtype=torch.float64, device=self.device)
         ap = torch.empty_like(at)
         _check(lib().tl_deflection(self._h, _ptr(P), _ptr(at), _ptr(ap)))
         self._keep = (P,)
@@ -288,8 +304,7 @@ class Plan:
     def synth_derivs(self, alm_T, alm_E=None, alm_B=None):
         """Scaled derivative maps D[field][jk][ring][pix]."""
         T, E, B = self._inputs(alm_T, alm_E, alm_B)
-        D = torch.empty((self.nfield, self.ndmap, self.ntheta, self.nphi), dtype=self.real_dtype,
-                        device=self.device)
+        D = torch.empty((self.nfield, self.ndmap, *self.map_shape), dtype=self.real_dtype, device=self.device)
         _check(lib().tl_synth_derivs(self._h, _ptr(T), _ptr(E), _ptr(B), _ptr(D)))
         self._keep = (T, E, B)
         return D
@@ -298,7 +313,7 @@ class Plan:
         D = D.to(self.device, self.real_dtype).contiguous()
         at = alpha_theta.to(self.device, torch.float64).contiguous()
         ap = alpha_phi.to(self.device, torch.float64).contiguous()
-        if D.numel() != self.nfield * self.ndmap * self.ntheta * self.nphi:
+        if D.numel() != self.nfield * self.ndmap * self.npix:
             raise ValueError("D has the wrong size for this plan")
         out = (self._maps(), self._maps() if self.pol else None, self._maps() if self.pol else None)
         _check(lib().tl_remap(self._h, _ptr(D), _ptr(at), _ptr(ap), _ptr(out[0]), _ptr(out[1]), _ptr(out[2])))

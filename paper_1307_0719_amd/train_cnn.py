@@ -105,28 +105,49 @@ def train(lmax, ntheta, nphi, seeds, steps_per_real=20, batch_pixels=32768, lr=2
     return params, {"loss_per_realization": hist, "scales": scales.tolist()}
 
 
-def evaluate(params, lmax, ntheta, nphi, seeds):
-    """RMS (over all pixels and the given seeds) of order-2 and order-2 +
-    correction against order 6, per field, rotation on."""
-    p2 = taylens.Plan(lmax, ntheta, nphi, 2, "fp32", pol=True)
+def evaluate(params, lmax, ntheta, nphi, seeds, precision="fp32", plain_orders=()):
+    """RMS (over all pixels and the given seeds) against plain order 6 in the
+    FP32 form (rotation on), per field, of: order 2 and order 2 + correction
+    in the given precision form, and the plain orders in plain_orders (same
+    form).  Plans are made one at a time (a tabulated plan at lmax 4096 holds
+    its tables)."""
+    dev = torch.device("cuda", torch.cuda.current_device())
+    skies = []
+    judge = []
     p6 = taylens.Plan(lmax, ntheta, nphi, 6, "fp32", pol=True)
-    net = taylens.Cnn(params)
-    dev = p2.device
-    acc = {"order2": np.zeros(3), "cnn": np.zeros(3), "signal": np.zeros(3)}
     for sd in seeds:
         s = skygen.make_sky(lmax, sd, pol=True)
-        T, E, P = _dev(s.alm_T, dev), _dev(s.alm_E, dev), _dev(s.alm_phi, dev)
-        m6 = torch.stack(p6.lens_map(T, E, None, P)).reshape(3, -1).double().clone()
-        m2 = torch.stack(p2.lens_map(T, E, None, P)).reshape(3, -1).double().clone()
-        mc = torch.stack(net.lens_map(p2, T, E, None, P)).reshape(3, -1).double()
-        acc["order2"] += torch.mean((m2 - m6) ** 2, dim=1).cpu().numpy()
-        acc["cnn"] += torch.mean((mc - m6) ** 2, dim=1).cpu().numpy()
-        acc["signal"] += torch.mean(m6 ** 2, dim=1).cpu().numpy()
-    out = {k: np.sqrt(v / len(seeds)) for k, v in acc.items()}
+        a = (_dev(s.alm_T, dev), _dev(s.alm_E, dev), None, _dev(s.alm_phi, dev))
+        skies.append(a)
+        judge.append(torch.stack(p6.lens_map(*a)).reshape(3, -1).cpu())
+    p6.close()
+    torch.cuda.empty_cache()
+
+    def rms_against_judge(run):
+        acc = np.zeros(3)
+        for a, m6 in zip(skies, judge):
+            m = run(a).reshape(3, -1).double()
+            acc += torch.mean((m - m6.to(dev).double()) ** 2, dim=1).cpu().numpy()
+        return np.sqrt(acc / len(seeds))
+
+    p2 = taylens.Plan(lmax, ntheta, nphi, 2, precision, pol=True)
+    net = taylens.Cnn(params)
+    out = {"order2": rms_against_judge(lambda a: torch.stack(p2.lens_map(*a))),
+           "cnn": rms_against_judge(lambda a: torch.stack(net.lens_map(p2, *a)))}
+    net.close()
+    p2.close()
+    torch.cuda.empty_cache()
+    for N in plain_orders:
+        pn = taylens.Plan(lmax, ntheta, nphi, N, precision, pol=True)
+        out[f"order{N}"] = rms_against_judge(lambda a: torch.stack(pn.lens_map(*a)))
+        pn.close()
+        torch.cuda.empty_cache()
+    signal = np.sqrt(sum(torch.mean(m6.double() ** 2, dim=1).numpy() for m6 in judge) / len(seeds))
     res = {"rms_err_order2": out["order2"].tolist(), "rms_err_cnn": out["cnn"].tolist(),
-           "rms_signal": out["signal"].tolist(), "gain": (out["order2"] / out["cnn"]).tolist()}
-    for x in (p2, p6, net):
-        x.close()
+           "rms_signal": signal.tolist(), "gain": (out["order2"] / out["cnn"]).tolist(),
+           "precision": precision, "seeds": list(seeds)}
+    for N in plain_orders:
+        res[f"rms_err_order{N}"] = out[f"order{N}"].tolist()
     return res
 
 

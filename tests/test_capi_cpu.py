@@ -101,3 +101,16 @@ def test_batch_null_arguments(tl):
     assert L.tl_batch_destroy(None) == 0
     assert L.tl_batch_run(None, None, None) == -1
     assert L.tl_batch_info(None, None, None, None, None) == -1
+
+
+def test_healpix_plan_arguments(tl):
+    """HEALPix plans validate nside before any device call."""
+    L = tl.lib()
+    h = ctypes.c_void_p()
+    o = tl.Options(3, 1, 1, 1, 0, 0, 0)
+    assert L.tl_plan_create_healpix(None, 16, 4, ctypes.byref(o), None) == tl.TL_ERR_INVALID
+    assert L.tl_plan_create_healpix(ctypes.byref(h), 16, 0, ctypes.byref(o), None) == tl.TL_ERR_INVALID
+    assert L.tl_plan_create_healpix(ctypes.byref(h), 16, 4096, ctypes.byref(o), None) == tl.TL_ERR_UNSUPPORTED
+    bad = tl.Options(9, 1, 1, 1, 0, 0, 0)
+    assert L.tl_plan_create_healpix(ctypes.byref(h), 16, 4, ctypes.byref(bad), None) == tl.TL_ERR_INVALID
+    assert not h.value

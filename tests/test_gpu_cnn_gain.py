@@ -30,13 +30,21 @@ def tc():
     return train_cnn
 
 
-@pytest.mark.parametrize("lmax,min_gain", [(2048, 4.0), (4096, 3.5)])
-def test_trained_network_gains_over_order2(tc, lmax, min_gain):
+@pytest.mark.parametrize("lmax,min_gain,seeds,precision", [(2048, 4.0, [20000, 20001, 20002], "fp32"),
+                                                            (4096, 3.5, [20000, 20001], "fp32"),
+                                                            (4096, 3.5, [20002], "fp16x2")])
+def test_trained_network_gains_over_order2(tc, lmax, min_gain, seeds, precision):
+    """Gain over plain order 2 on held-out seeds, in the FP32 form and on the
+    split FP16 tables; plain orders 3 and 4 are reported beside it (their
+    error against order 6 is what the correction competes with)."""
     params = np.load(WEIGHTS)
-    res = tc.evaluate(params, lmax, lmax + 1, 2 * lmax, [20000])
-    print(lmax, res)
+    res = tc.evaluate(params, lmax, lmax + 1, 2 * lmax, seeds, precision=precision, plain_orders=(3, 4))
+    print(lmax, precision, res)
     for f, g in zip("TQU", res["gain"]):
         assert g > min_gain, (f, g, res)
+    # the plain series converges: order 4 is closer to order 6 than order 2
+    for f in range(3):
+        assert res["rms_err_order4"][f] < res["rms_err_order2"][f]
 
 
 def test_training_from_scratch_reduces_the_remainder(tc):

@@ -27,6 +27,7 @@ from tests.gpu_util import ORACLE_THREADS, need_gpu, rel_rms, t2np
 pytestmark = pytest.mark.gpu
 
 MAP_TOL = {"fp32": 1e-5, "fp16x2": 1e-5, "bf16x3": 3e-5, "fp16": 1e-3, "bf16": 1e-2}
+HEADLINE_BATCH = 6
 
 
 @pytest.fixture(scope="module")
@@ -73,27 +74,28 @@ def headline(tl):
     the lmax 4096 workload per table pass."""
     w = skygen.WORKLOADS["TP4096"]
     dev = torch.device("cuda", 0)
-    skies = [skygen.make_sky(w.lmax, w.seed + i, pol=True) for i in range(6)]
-    plan = tl.Plan(w.lmax, w.ntheta, w.nphi, w.order, "fp16x2", pol=True, batch=6)
+    skies = [skygen.make_sky(w.lmax, w.seed + i, pol=True) for i in range(HEADLINE_BATCH)]
+    plan = tl.Plan(w.lmax, w.ntheta, w.nphi, w.order, "fp16x2", pol=True, batch=HEADLINE_BATCH)
     rpole = plan.query("rpole")
     bands = sample_bands(w.ntheta, rpole)
     rings = np.unique(np.concatenate(list(bands.values())))
     outs = plan.lens_map_many([_to_dev(s, dev) for s in skies])
     torch.cuda.synchronize()
-    rows = [[t2np(x[torch.from_numpy(rings).to(dev)]) for x in o] for o in outs]
+    idx = torch.from_numpy(rings).to(dev)
+    rows = [[t2np(x[idx]) for x in o] for o in outs]
     del outs
     plan.close()
     torch.cuda.empty_cache()
     return w, skies, rings, bands, rows
 
 
-@pytest.mark.parametrize("q", range(6))
-def test_headline_fp16x2_six_per_pass_every_realization(oracle, headline, q):
+@pytest.mark.parametrize("q", range(HEADLINE_BATCH))
+def test_headline_fp16x2_every_realization_of_the_pass(oracle, headline, q):
     w, skies, rings, bands, rows = headline
     s = skies[q]
     ref = oracle.lens_rings(w.lmax, w.order, w.ntheta, w.nphi, rings, s.alm_T, s.alm_E, s.alm_B, s.alm_phi,
                             nthreads=ORACLE_THREADS)
-    check_bands(rows[q], ref, rings, bands, MAP_TOL["fp16x2"], f"fp16x2 x6 realization {q}")
+    check_bands(rows[q], ref, rings, bands, MAP_TOL["fp16x2"], f"fp16x2 x{HEADLINE_BATCH} realization {q}")
 
 
 @pytest.mark.parametrize("precision", ["bf16x3", "bf16"])

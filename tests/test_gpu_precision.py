@@ -80,8 +80,11 @@ def test_tab_lens_map(tl, oracle, precision):
         assert e < MAP_TOL[precision], (f, e)
 
 
-@pytest.mark.parametrize("precision,batch", [("fp16", 3), ("bf16x3", 2), ("fp16", 4), ("bf16", 4), ("fp16x2", 6)])
+@pytest.mark.parametrize("precision,batch", [("fp16", 3), ("bf16x3", 2), ("fp16", 4), ("bf16", 4), ("fp16x2", 6),
+                                             ("bf16x3", 6), ("fp16", 6), ("bf16", 5)])
 def test_lens_map_many_equals_single_calls(tl, precision, batch):
+    """Realizations in one table pass give what single calls give, bit for
+    bit; one more realization than the batch makes a second, smaller pass."""
     lmax, ntheta, nphi, order = 96, 97, 192, 4
     skies = [_sky(lmax, 90 + i) for i in range(batch + 1)]
     single = tl.Plan(lmax, ntheta, nphi, order, precision, pol=True)
@@ -165,7 +168,7 @@ def test_polar_cap_policy(tl):
     assert rpole("fp16x2", 4, 4096) == 66
 
 
-@pytest.mark.parametrize("precision,batch", [("fp16x2", 3), ("fp16", 2)])
+@pytest.mark.parametrize("precision,batch", [("fp16x2", 3), ("fp16", 2), ("fp16x2", 5)])
 def test_lens_map_many_with_b(tl, oracle, precision, batch):
     """B modes present: the table pass carries T, E, B (and, split forms, the
     lensing potential) columns, the direct spin kernel two right-hand sides
