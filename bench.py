@@ -342,8 +342,8 @@ def bench_healpix(args, with_oracle, precision="fp16x2", nside=2048, lmax=3072, 
     """Lensing onto and from HEALPix rings (the paper's pixelization): nside
     2048, lmax 3072, order 2 -- a row of the paper's fastest-settings table
     (32.5 CPU-minutes per map on 8-core Xeon E5540 nodes; at lmax 4096 the
-    split tables of 8191 HEALPix rings would exceed one GPU's memory) -- six
-    realizations per table pass.  Rate in lensed HEALPix pixels per second;
+    split tables of 8191 HEALPix rings take 258 GiB, too much beside six
+    realizations' work buffers) -- six realizations per table pass.  Rate in lensed HEALPix pixels per second;
     error against the HEALPix oracle on two sampled rings (a 4-pixel polar ring
     and the equator) of realization 0."""
     import numpy as np

@@ -113,7 +113,8 @@ void free_buf(DevBuf &b)
 void free_plan_buffers(Plan &p)
 {
     DevBuf *bufs[] = {&p.theta, &p.trig, &p.phitab, &p.phival, &p.twid64, &p.twid32, &p.coef0, &p.coef2,
-                      &p.start, &p.exps, &p.mcut, &p.tab, &p.moff, &p.kstart, &p.rhs, &p.colexp, &p.tabsum, &p.Fphi, &p.alpha, &p.F, &p.D, &p.jobsDefl, &p.jobsMain, &p.hring};
+                      &p.start, &p.exps, &p.mcut, &p.tab, &p.moff, &p.kstart, &p.rhs, &p.colexp, &p.tabsum, &p.Fphi, &p.alpha, &p.F, &p.D, &p.jobsDefl, &p.jobsMain, &p.hring,
+                      &p.twP64, &p.twP32, &p.bhat64, &p.bhat32};
     for (DevBuf *b : bufs) free_buf(*b);
 }
 
@@ -147,7 +148,23 @@ double factorial(int n)
 // z = 4/3 - 2 i/(3 nside) in the belt, 4 i resp. 4 nside pixels, the first at
 // phi0 = pi/(4 i) in the caps and pi s/(4 nside), s = (i - nside + 1) mod 2, in
 // the belt; sigma = e^{i nphi phi0} = -1 for shifted rings, +1 otherwise.
-void healpix_rings(int nside, std::vector<double> &th, std::vector<HRing> &hr)
+// Ring FFT of half length M: 0 = mixed radix (M <= 32), else the Bluestein
+// length P (power of two >= 2 M - 1, >= 256).
+int healpix_blue_P(int M)
+{
+    if (M <= 32) return 0;
+    int P = 256;
+    while (P < 2 * M - 1) P <<= 1;
+    return P;
+}
+
+// HEALPix rings (Gorski et al. 2005, RING order): colatitude, first pixel,
+// pixel count, phase; the FFT class of each ring (power-of-two lengths 1024 ..
+// 8192 with lmax < N take the radix-16 kernel), and (items) the distinct
+// Bluestein lengths {M, P, offset, 0} sorted by P, with their chirp-table
+// total (nbhat elements).
+void healpix_rings(int nside, int lmax, std::vector<double> &th, std::vector<HRing> &hr,
+                   std::vector<int4> *items = nullptr, size_t *nbhat = nullptr)
 {
     const int nr = 4 * nside - 1;
     th.assign(nr, 0.0);
@@ -158,33 +175,59 @@ void healpix_rings(int nside, std::vector<double> &th, std::vector<HRing> &hr)
         const bool north = i <= 2 * nside;
         const int ii = north ? i : 4 * nside - i;
         double t, p0;
-        int n, sig;
+        int n, sig, sh;
         if (ii < nside) {
             t = 2.0 * std::asin((double)ii / (std::sqrt(6.0) * nside));
             if (!north) t = M_PI - t;
             n = 4 * ii;
             p0 = M_PI / (4.0 * ii);
             sig = -1;
+            sh = 1;
         } else {
             t = std::acos(4.0 / 3.0 - 2.0 * i / (3.0 * nside));
             n = 4 * nside;
-            const int sh = (i - nside + 1) % 2;
+            sh = (i - nside + 1) % 2;
             p0 = M_PI * sh / (4.0 * nside);
             sig = sh ? -1 : 1;
         }
         th[r] = t;
-        hr[r] = HRing{start, n, sig, p0};
+        hr[r] = HRing{start, n, sig, p0, 0, 0, sh};
         start += n;
     }
+    // distinct Bluestein half lengths M = 2 i (i = 1 .. nside), by P then M
+    std::vector<int4> it;
+    for (int i = 1; i <= nside; ++i) {
+        const int P = healpix_blue_P(2 * i);
+        if (P) it.push_back(make_int4(2 * i, P, 0, 0));
+    }
+    std::stable_sort(it.begin(), it.end(), [](const int4 &a, const int4 &b) { return a.y < b.y; });
+    std::vector<int64_t> off((size_t)2 * nside + 1, -1);
+    int64_t tot = 0;
+    for (int4 &x : it) {
+        x.z = (int)tot;
+        off[x.x] = tot;
+        tot += x.y;
+    }
+    for (HRing &h : hr) {
+        const int M = h.nphi / 2;
+        // belt rings only: the class runs one kernel instance, of one length
+        const bool pow2 = h.nphi == 4 * nside && (M == 512 || M == 1024 || M == 2048 || M == 4096) && lmax < h.nphi;
+        h.P = pow2 ? 0 : healpix_blue_P(M);
+        h.boff = h.P ? off[M] : 0;
+        h.cls = pow2 ? kHpxPow2 : (h.P ? hpx_class_of_P(h.P) : 0);
+    }
+    if (items) *items = it;
+    if (nbhat) *nbhat = (size_t)tot;
 }
 
 struct Sizes {
     size_t theta, trig, phitab, phival, twid64, twid32, coef, start, exps, mcut, Fphi, alpha, F, D, jd, jm;
     size_t tab = 0, moff = 0, kstart = 0, rhs = 0, colexp = 0, tabsum = 0, hring = 0;
+    size_t twP64 = 0, twP32 = 0, bhat64 = 0, bhat32 = 0;
     size_t total() const
     {
         return theta + trig + phitab + phival + twid64 + twid32 + 2 * coef + start + exps + mcut + Fphi + alpha + F +
-               D + jd + jm + tab + moff + kstart + rhs + colexp + tabsum + hring;
+               D + jd + jm + tab + moff + kstart + rhs + colexp + tabsum + hring + twP64 + twP32 + bhat64 + bhat32;
     }
 };
 
@@ -204,6 +247,16 @@ Sizes plan_sizes(const Plan &p)
     s.twid64 = ntw * sizeof(double2);
     s.twid32 = ntw * sizeof(float2);
     s.hring = p.nside ? (size_t)p.ntheta * sizeof(HRing) : 0;
+    if (p.nside && p.hmax_P > 0) {
+        std::vector<double> th;
+        std::vector<HRing> hr;
+        size_t nb = 0;
+        healpix_rings(p.nside, p.lmax, th, hr, nullptr, &nb);
+        s.twP64 = 8192 * sizeof(double2);
+        s.twP32 = 8192 * sizeof(float2);
+        s.bhat64 = nb * sizeof(double2);
+        s.bhat32 = nb * sizeof(float2);
+    }
     s.coef = nalm * sizeof(double4);
     s.start = 3 * (size_t)(p.lmax + 1) * p.jtab * p.nrp * sizeof(double);
     s.exps = 3 * (size_t)(p.lmax + 1) * p.nrp * sizeof(int);
@@ -280,7 +333,7 @@ int build_jobs_healpix(Plan &p)
     const size_t row = (size_t)(p.lmax + 1);
     std::vector<double> th;
     std::vector<HRing> hr;
-    healpix_rings(p.nside, th, hr);
+    healpix_rings(p.nside, p.lmax, th, hr);
     const size_t np = p.npix();
     std::vector<FftJob> jd(2 * (size_t)p.ntheta);
     for (int i = 0; i < p.ntheta; ++i) {
@@ -320,6 +373,15 @@ int build_jobs_healpix(Plan &p)
                 jm[q++] = a;
             }
     p.njobsMain = (int)jm.size();
+    // each list by FFT class: mixed radix first, then Bluestein by P
+    auto by_class = [&](std::vector<FftJob> &v, int *cnt) {
+        auto cls = [&](const FftJob &j) { return (int)hr[j.pad].cls; };
+        std::stable_sort(v.begin(), v.end(), [&](const FftJob &a, const FftJob &b) { return cls(a) < cls(b); });
+        for (int c = 0; c < kHpxClasses; ++c) cnt[c] = 0;
+        for (const FftJob &j : v) ++cnt[cls(j)];
+    };
+    by_class(jd, p.hjobs[0]);
+    by_class(jm, p.hjobs[1]);
     TL_HIP(hipMemcpy(p.jobsDefl.ptr, jd.data(), jd.size() * sizeof(FftJob), hipMemcpyHostToDevice), "jobs copy");
     TL_HIP(hipMemcpy(p.jobsMain.ptr, jm.data(), jm.size() * sizeof(FftJob), hipMemcpyHostToDevice), "jobs copy");
     return TL_OK;
@@ -383,7 +445,7 @@ int upload_tables(Plan &p)
     std::vector<double> th(p.ntheta);
     std::vector<double2> tr(p.ntheta);
     std::vector<HRing> hr;
-    if (p.nside) healpix_rings(p.nside, th, hr);
+    if (p.nside) healpix_rings(p.nside, p.lmax, th, hr);
     for (int i = 0; i < p.ntheta; ++i) {
         if (!p.nside) th[i] = M_PI * (double)i / (double)(p.ntheta - 1);
         tr[i] = make_double2(std::cos(th[i]), std::sin(th[i]));
@@ -404,6 +466,24 @@ int upload_tables(Plan &p)
         }
         TL_HIP(hipMemcpy(p.twid64.ptr, t64.data(), t64.size() * sizeof(double2), hipMemcpyHostToDevice), "tw");
         TL_HIP(hipMemcpy(p.twid32.ptr, t32.data(), t32.size() * sizeof(float2), hipMemcpyHostToDevice), "tw");
+        if (p.hmax_P > 0) {
+            // twiddles of the power-of-two Bluestein transforms, then the
+            // chirp spectra of every Bluestein ring length
+            std::vector<double2> w64(8192);
+            std::vector<float2> w32(8192);
+            for (int t = 0; t < 8192; ++t) {
+                long double a = 2.0L * 3.141592653589793238462643383279502884L * (long double)t / 8192.0L;
+                w64[t] = make_double2((double)cosl(a), (double)sinl(a));
+                w32[t] = make_float2((float)cosl(a), (float)sinl(a));
+            }
+            TL_HIP(hipMemcpy(p.twP64.ptr, w64.data(), w64.size() * sizeof(double2), hipMemcpyHostToDevice), "tw");
+            TL_HIP(hipMemcpy(p.twP32.ptr, w32.data(), w32.size() * sizeof(float2), hipMemcpyHostToDevice), "tw");
+            std::vector<double> th2;
+            std::vector<HRing> hr2;
+            std::vector<int4> items;
+            healpix_rings(p.nside, p.lmax, th2, hr2, &items);
+            TL_HIP(launch_bluestein_tables(p, items), "chirp tables");
+        }
     }
     std::vector<double2> pt(p.nphi);
     std::vector<double> pv(p.nphi + 1);
@@ -474,7 +554,7 @@ int defl_fft(Plan &p, const void *alm_phi, int q)
         return TL_OK;
     }
     StageScope sc(p, ST_DEFL_FFT);
-    TL_HIP(launch_fft_jobs(p, fphi_slot(p, q), p.alpha.ptr, (const FftJob *)p.jobsDefl.ptr, p.njobsDefl, true),
+    TL_HIP(launch_fft_jobs(p, fphi_slot(p, q), p.alpha.ptr, (const FftJob *)p.jobsDefl.ptr, p.njobsDefl, true, 0),
            "deflection fft");
     return TL_OK;
 }
@@ -599,7 +679,7 @@ int run_derivs(Plan &p, const void *T, const void *E, const void *B, void *Dout)
     int rc = run_legendre(p, T, E, B, p.F.ptr);
     if (rc) return rc;
     StageScope sc(p, ST_FFT);
-    TL_HIP(launch_fft_jobs(p, p.F.ptr, Dout, (const FftJob *)p.jobsMain.ptr, p.njobsMain, p.fp64()), "ring fft");
+    TL_HIP(launch_fft_jobs(p, p.F.ptr, Dout, (const FftJob *)p.jobsMain.ptr, p.njobsMain, p.fp64(), 1), "ring fft");
     return TL_OK;
 }
 
@@ -936,7 +1016,7 @@ int batch_enqueue(tl_batch_s *b, const void *const *alms, void *const *outs, boo
     for (int i = 0; i < b->n; ++i) {
         Plan &p = b->plans[i]->p;
         if ((rc = run_deflection(p, alms[4 * i + 3]))) return rc;
-        TL_HIP(launch_fft_jobs(p, b->F[i].ptr, p.D.ptr, (const FftJob *)p.jobsMain.ptr, p.njobsMain, false),
+        TL_HIP(launch_fft_jobs(p, b->F[i].ptr, p.D.ptr, (const FftJob *)p.jobsMain.ptr, p.njobsMain, false, 1),
                "ring fft");
         const double *at = (const double *)p.alpha.ptr;
         TL_HIP(launch_remap(p, p.D.ptr, at, at + p.npix(), nullptr, nullptr, outs[3 * i], outs[3 * i + 1],
@@ -995,7 +1075,17 @@ void plan_fields(Plan &p, int32_t lmax, tl_grid grid, const tl_options *opt, voi
         const double smin = p.precision == TL_FP16X2 ? 0.05 : 0.15;
         std::vector<double> th;
         std::vector<HRing> hr;
-        if (p.nside) healpix_rings(p.nside, th, hr);
+        if (p.nside) {
+            healpix_rings(p.nside, lmax, th, hr);
+            p.hmax_direct = 0;
+            p.hmax_P = 0;
+            p.hmax_pow2 = 0;
+            for (const HRing &h : hr) {
+                if (h.cls == kHpxPow2) p.hmax_pow2 = std::max(p.hmax_pow2, h.nphi / 2);
+                else if (h.P) p.hmax_P = std::max(p.hmax_P, (int)h.P);
+                else p.hmax_direct = std::max(p.hmax_direct, h.nphi / 2);
+            }
+        }
         auto sin_ring = [&](int r) {
             return p.nside ? std::sin(th[r]) : std::sin(M_PI * (double)r / (double)(p.ntheta - 1));
         };
@@ -1031,8 +1121,12 @@ int plan_device_checks(Plan &p)
     int smem = 0;
     TL_HIP(hipDeviceGetAttribute(&smem, hipDeviceAttributeMaxSharedMemoryPerBlock, p.device),
            "hipDeviceGetAttribute");
-    // ring FFT buffers in LDS: 2 M (equal-theta) or 2 M + 1 (HEALPix, M = 2 nside)
-    const size_t need64 = (2 * (size_t)(p.nphi / 2) + (p.nside ? 1 : 0)) * sizeof(double2);
+    // ring FFT buffers in LDS: 2 M (equal-theta); HEALPix: 2 M + 1 for the
+    // mixed-radix rings, P + P / 32 for the Bluestein ones
+    const size_t need64 = p.nside ? std::max({2 * (size_t)p.hmax_direct + 1, (size_t)(p.hmax_P + p.hmax_P / 32),
+                                              (size_t)(p.hmax_pow2 + p.hmax_pow2 / 32)}) *
+                                        sizeof(double2)
+                                  : 2 * (size_t)(p.nphi / 2) * sizeof(double2);
     if (need64 > (size_t)smem)
         return fail(TL_ERR_UNSUPPORTED, "nphi too large for the FP64 ring FFT in LDS on this device (" +
                                             std::to_string(need64) + " > " + std::to_string(smem) + " bytes)");
@@ -1054,7 +1148,9 @@ std::vector<BufItem> plan_buffer_list(Plan &p, const Sizes &sz)
             {&p.alpha, sz.alpha, "alpha"},   {&p.F, sz.F, "F"},                {&p.D, sz.D, "D"},
             {&p.jobsDefl, sz.jd, "jobsDefl"}, {&p.jobsMain, sz.jm, "jobsMain"}, {&p.tab, sz.tab, "tab"},
             {&p.moff, sz.moff, "moff"},      {&p.kstart, sz.kstart, "kstart"}, {&p.rhs, sz.rhs, "rhs"},
-            {&p.colexp, sz.colexp, "colexp"}, {&p.tabsum, sz.tabsum, "tabsum"}, {&p.hring, sz.hring, "hring"}};
+            {&p.colexp, sz.colexp, "colexp"}, {&p.tabsum, sz.tabsum, "tabsum"}, {&p.hring, sz.hring, "hring"},
+            {&p.twP64, sz.twP64, "twP64"},   {&p.twP32, sz.twP32, "twP32"},   {&p.bhat64, sz.bhat64, "bhat64"},
+            {&p.bhat32, sz.bhat32, "bhat32"}};
 }
 
 // Everything a plan computes into its buffers once they exist: angle and
@@ -1100,7 +1196,7 @@ int lens_map_core(Plan &p, const void *alm_T, const void *alm_E, const void *alm
         if ((rc = defl_legendre(p, 1, Ps, true))) return rc;
         if ((rc = defl_fft(p, alm_phi, 0))) return rc;
         StageScope sc(p, ST_FFT);
-        TL_HIP(launch_fft_jobs(p, p.F.ptr, p.D.ptr, (const FftJob *)p.jobsMain.ptr, p.njobsMain, p.fp64()),
+        TL_HIP(launch_fft_jobs(p, p.F.ptr, p.D.ptr, (const FftJob *)p.jobsMain.ptr, p.njobsMain, p.fp64(), 1),
                "ring fft");
     } else {
         if ((rc = run_deflection(p, alm_phi))) return rc;
@@ -1478,7 +1574,7 @@ int tl_lens_map_many(tl_plan plan, int32_t n, const void *const *alms, void *con
             if ((rc = defl_fft(p, P[q], q))) return rc;
             {
                 StageScope sc(p, ST_FFT);
-                TL_HIP(launch_fft_jobs(p, F[q], p.D.ptr, (const FftJob *)p.jobsMain.ptr, p.njobsMain, p.fp64()),
+                TL_HIP(launch_fft_jobs(p, F[q], p.D.ptr, (const FftJob *)p.jobsMain.ptr, p.njobsMain, p.fp64(), 1),
                        "ring fft");
             }
             const double *at = (const double *)p.alpha.ptr;

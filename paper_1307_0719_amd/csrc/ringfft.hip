@@ -335,8 +335,8 @@ __global__ __launch_bounds__(256) void k_ring_fft_hpx(const FftJob *__restrict__
                 re += sg * c.x;
                 im -= sg * c.y;
             }
-            double sn, cs;
-            sincos((double)qq * hr.phi0, &sn, &cs);
+            double sn = 0.0, cs = 1.0;  // e^{i qq phi0}, phi0 = pi shift / N
+            if (hr.shift) sincospi((double)qq / (double)N, &sn, &cs);
             double xr = re * cs - im * sn, xi = re * sn + im * cs;
             if (qq == 0 || qq == M) xi = 0.0;  // real by Hermitian symmetry
             bufB[qq] = cmk<V>((R)xr, (R)xi);
@@ -606,6 +606,326 @@ __global__ __launch_bounds__(256, 2) void k_ring_fft_p2(
         __syncthreads();
     }
 }
+
+// ---- HEALPix rings of power-of-two length N = 2 M, lmax < N ----
+//
+// The radix-16 kernel above with the ring's phase and one fold term: for
+// 0 <= m <= M, X_m = e^{i pi m shift / N} (c_m + sigma conj c_{N - m}) (terms
+// beyond lmax are zero; lmax < N leaves no other alias), X_0 and X_M real.
+__device__ __forceinline__ void sc_pi(float x, float *sn, float *cs) { sincospif(x, sn, cs); }
+__device__ __forceinline__ void sc_pi(double x, double *sn, double *cs) { sincospi(x, sn, cs); }
+
+template <int K, typename R, typename V>
+__device__ __forceinline__ V coef_h(V f, int m, int L, R scale)
+{
+    R sc = m <= L ? scale : (R)0;
+    const R mf = (R)m;
+#pragma unroll
+    for (int t = 0; t < K; ++t) sc *= mf;
+    R re = sc * f.x, im = m == 0 ? (R)0 : sc * f.y;
+    if constexpr ((K & 3) == 1) { const R t2 = re; re = -im; im = t2; }
+    else if constexpr ((K & 3) == 2) { re = -re; im = -im; }
+    else if constexpr ((K & 3) == 3) { const R t2 = re; re = im; im = -t2; }
+    return cmk<V>(re, im);
+}
+
+// X_m from the cached F_m, the mirror F_{N - m} read when N - m <= lmax, and
+// the phase e^{i pi m shift / N}.
+template <int K, int M, typename R, typename V>
+__device__ __forceinline__ V xh(V f, int m, const V *__restrict__ F, int L, R scale, R sigma, V ph)
+{
+    constexpr int N = 2 * M;
+    V x = coef_h<K, R, V>(f, m, L, scale);
+    const int mm = N - m;
+    if (mm <= L) {
+        const V c = coef_h<K, R, V>(F[mm], mm, L, scale);
+        x = cmk<V>(x.x + sigma * c.x, x.y - sigma * c.y);
+    }
+    x = cmul(x, ph);
+    if (m == 0 || m == M) x.y = (R)0;
+    return x;
+}
+
+template <int K, int M, bool CACHE, typename R, typename V>
+__device__ __forceinline__ void build_z_h(V *__restrict__ buf, const V (&f)[M / 256], V fmid, const V (&ph)[M / 512],
+                                          V phmid, bool shift, const V *__restrict__ F, int L, R scale, R sigma,
+                                          V tb, const V *__restrict__ twN, int tid)
+{
+    constexpr int H = M / 512;
+#pragma unroll(CACHE ? H : 2)
+    for (int s = 0; s < H; ++s) {
+        const int m = tid + 256 * s;
+        const int mr = M - m;
+        const V fm = CACHE ? f[s] : F[m <= L ? m : L];
+        const V fr = CACHE ? f[H + s] : F[mr <= L ? mr : L];
+        const V phr = shift ? cmk<V>(ph[s].y, ph[s].x) : ph[s];
+        const V xm = xh<K, M>(fm, m, F, L, scale, sigma, ph[s]);
+        const V xr = xh<K, M>(fr, mr, F, L, scale, sigma, phr);
+        const V tw = cmul(tb, twN[256 * s]);  // e^{2 pi i m/N}
+        const V xc = cconj(xr);
+        buf[lpad(m)] = cadd(cadd(xm, xc), cmuli(cmul(tw, csub(xm, xc))));
+        const V xc2 = cconj(xm);
+        const V tw2 = cmk<V>(-tw.x, tw.y);  // e^{2 pi i (M-m)/N}
+        if (m > 0) buf[lpad(mr)] = cadd(cadd(xr, xc2), cmuli(cmul(tw2, csub(xr, xc2))));
+    }
+    if (tid == 0) {
+        const V xhm = xh<K, M>(CACHE ? fmid : F[M / 2 <= L ? M / 2 : L], M / 2, F, L, scale, sigma, phmid);
+        const V xc = cconj(xhm);
+        buf[lpad(M / 2)] = cadd(cadd(xhm, xc), cmuli(cmul(twN[M / 2], csub(xhm, xc))));
+    }
+}
+
+template <typename R, int M>
+__global__ __launch_bounds__(256, 2) void k_ring_fft_hpx_p2(
+    const FftJob *__restrict__ jobs, const typename C2<R>::T *__restrict__ Fbase, R *__restrict__ Dbase, int lmax,
+    const HRing *__restrict__ hring, const typename C2<R>::T *__restrict__ twAll)
+{
+    using V = typename C2<R>::T;
+    constexpr int RL = M / 256;
+    constexpr int H = M / 512;
+    constexpr int N = 2 * M;
+    extern __shared__ unsigned char smem_raw[];
+    V *buf = reinterpret_cast<V *>(smem_raw);
+    const int tid = threadIdx.x;
+    const FftJob &job = jobs[blockIdx.x];
+    const HRing hr = hring[job.pad];
+    const V *twN = twAll + (size_t)2 * (M / 2) * (M / 2 - 1);  // N = 4 i, i = M / 2
+    const V *F = Fbase + job.src;
+    const int L = lmax;
+    const R sigma = (R)hr.sigma;
+    const V tb = twN[tid];
+    // phases e^{i pi m shift / N} of the thread's m (that of M - m is
+    // e^{i pi / 2} conj of it: swap the parts) and (thread 0) of M / 2
+    V ph[H], phmid = cmk<V>((R)1, (R)0);
+#pragma unroll
+    for (int s = 0; s < H; ++s) {
+        const int m = tid + 256 * s;
+        ph[s] = cmk<V>((R)1, (R)0);
+        if (hr.shift) {
+            R sn, cs;
+            sc_pi((R)m / (R)N, &sn, &cs);
+            ph[s] = cmk<V>(cs, sn);
+        }
+    }
+    if (hr.shift) {
+        R sn, cs;
+        sc_pi((R)(M / 2) / (R)N, &sn, &cs);
+        phmid = cmk<V>(cs, sn);
+    }
+    constexpr bool CACHE = sizeof(R) == 4;
+    const bool shift = hr.shift != 0;
+    V f[RL], fmid;
+    if constexpr (CACHE) load_pairs<M>(f, fmid, F, L, tid);
+    for (int q = 0; q < job.nk; ++q) {
+        const R scale = (R)job.scale[q];
+        switch (job.k[q]) {  // uniform
+        case 0: build_z_h<0, M, CACHE>(buf, f, fmid, ph, phmid, shift, F, L, scale, sigma, tb, twN, tid); break;
+        case 1: build_z_h<1, M, CACHE>(buf, f, fmid, ph, phmid, shift, F, L, scale, sigma, tb, twN, tid); break;
+        case 2: build_z_h<2, M, CACHE>(buf, f, fmid, ph, phmid, shift, F, L, scale, sigma, tb, twN, tid); break;
+        case 3: build_z_h<3, M, CACHE>(buf, f, fmid, ph, phmid, shift, F, L, scale, sigma, tb, twN, tid); break;
+        case 4: build_z_h<4, M, CACHE>(buf, f, fmid, ph, phmid, shift, F, L, scale, sigma, tb, twN, tid); break;
+        case 5: build_z_h<5, M, CACHE>(buf, f, fmid, ph, phmid, shift, F, L, scale, sigma, tb, twN, tid); break;
+        case 6: build_z_h<6, M, CACHE>(buf, f, fmid, ph, phmid, shift, F, L, scale, sigma, tb, twN, tid); break;
+        case 7: build_z_h<7, M, CACHE>(buf, f, fmid, ph, phmid, shift, F, L, scale, sigma, tb, twN, tid); break;
+        default: build_z_h<8, M, CACHE>(buf, f, fmid, ph, phmid, shift, F, L, scale, sigma, tb, twN, tid); break;
+        }
+        __syncthreads();
+        pass_p2<M, 16, 1, false>(buf, (V *)nullptr, tid, twN);
+        __syncthreads();
+        pass_p2<M, 16, 16, false>(buf, (V *)nullptr, tid, twN);
+        __syncthreads();
+        pass_p2<M, RL, 256, true>(buf, reinterpret_cast<V *>(Dbase + job.dst[q]), tid, twN);
+        __syncthreads();
+    }
+}
+
+// ---- HEALPix rings of awkward length: Bluestein's chirp transform ----
+//
+// A ring whose half length M has a prime factor above 13 takes the length-M
+// inverse DFT z_n = sum_k Z_k e^{2 pi i n k / M} as a convolution: with
+// w = e^{i pi / M} and n k = (n^2 + k^2 - (n - k)^2) / 2,
+//     z_n = w^{n^2} sum_k (Z_k w^{k^2}) w^{-(n - k)^2},
+// a circular convolution of length P (a power of two >= 2 M - 1, so the
+// negative lags do not wrap onto positive ones): a_k = Z_k w^{k^2} padded with
+// zeros, b_j = w^{-j^2} at j and P - j.  c = IDFT_P(DFT_P(a) DFT_P(b)) / P,
+// with DFT_P(b) / P from the plan (b is even, so its forward and inverse
+// sums agree), DFT_P(a) = conj(IDFT_P(conj a)).  w^t = e^{2 pi i t / N}
+// (N = 2 M) comes from the ring's twiddle table at t = k^2 mod N.  The
+// length-P transforms run in place in LDS (radix-16 Stockham passes, the
+// last of radix P / 4096 .. 16, every value of a pass read into registers
+// before any is written).  Every ring of half length M > 32 outside the
+// power-of-two class takes this path: smooth lengths too (a generic
+// mixed-radix pass with run-time radices and strides is slower than the two
+// fixed power-of-two transforms).
+
+// One in-place Stockham pass of radix RX (stride Ns) over P points, T
+// threads: each thread reads all of its butterflies' inputs, the workgroup
+// syncs, then transforms and writes.  Twiddles e^{2 pi i t / 8192} from twP.
+template <int P, int RX, int Ns, int T, typename V>
+__device__ __forceinline__ void ipass(V *__restrict__ buf, int tid, const V *__restrict__ twP)
+{
+    constexpr int nb = P / RX;
+    constexpr int U = (nb + T - 1) / T;
+    constexpr int tstride = 8192 / (Ns * RX);
+    V v[U][RX];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int b = tid + T * u;
+        if (nb % T == 0 || b < nb) {
+#pragma unroll
+            for (int s = 0; s < RX; ++s) v[u][s] = buf[lpad(b + s * nb)];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int b = tid + T * u;
+        if (nb % T == 0 || b < nb) {
+            const int kk = b & (Ns - 1);
+            if constexpr (Ns > 1) apply_twiddles<RX>(v[u], twP, kk, tstride);
+            dftR<RX>(v[u]);
+            const int base = (b / Ns) * Ns * RX + kk;
+#pragma unroll
+            for (int s = 0; s < RX; ++s) buf[lpad(base + s * Ns)] = v[u][s];
+        }
+    }
+    __syncthreads();
+}
+
+// In-place inverse DFT of P = 256 .. 8192 points (sign +, unnormalized);
+// the caller syncs before (inputs written) and the last pass syncs after.
+template <int P, int T, typename V>
+__device__ __forceinline__ void fft_inplace(V *__restrict__ buf, int tid, const V *__restrict__ twP)
+{
+    static_assert(P >= 256 && P <= 8192 && (P & (P - 1)) == 0, "power of two 256..8192");
+    ipass<P, 16, 1, T>(buf, tid, twP);
+    ipass<P, 16, 16, T>(buf, tid, twP);
+    if constexpr (P > 256) {
+        constexpr int R3 = P / 256 < 16 ? P / 256 : 16;
+        ipass<P, R3, 256, T>(buf, tid, twP);
+    }
+    if constexpr (P == 8192) ipass<P, 2, 4096, T>(buf, tid, twP);
+}
+
+// Threads of the Bluestein kernels: 512 for P = 8192 (one radix-16
+// butterfly per thread and pass), else 256.
+template <int P>
+constexpr int blue_threads() { return P == 8192 ? 512 : 256; }
+
+// Chirp spectra of the plan (FP64, once per plan): one workgroup per ring
+// length, item {M, P, boff, 0}; out[boff + k] = DFT_P(b)_k / P.
+template <int P>
+__global__ __launch_bounds__(blue_threads<P>()) void k_bluestein_table(const int4 *__restrict__ items, const double2 *__restrict__ twAll,
+                                                         const double2 *__restrict__ twP, double2 *__restrict__ out64,
+                                                         float2 *__restrict__ out32)
+{
+    using V = double2;
+    extern __shared__ unsigned char smem_raw[];
+    V *buf = reinterpret_cast<V *>(smem_raw);
+    const int tid = threadIdx.x;
+    const int4 it = items[blockIdx.x];
+    const int M = it.x, N = 2 * M, i4 = N / 4;
+    const int64_t boff = it.z;
+    const V *twN = twAll + (size_t)2 * i4 * (i4 - 1);
+    constexpr int T = blue_threads<P>();
+    for (int j = tid; j < P; j += T) {
+        V b = cmk<V>(0.0, 0.0);
+        const int jj = j < M ? j : (j > P - M ? P - j : -1);
+        if (jj >= 0) b = cconj(twN[(int)(((int64_t)jj * jj) % N)]);  // w^{-j^2}
+        buf[lpad(j)] = b;
+    }
+    __syncthreads();
+    fft_inplace<P, T>(buf, tid, twP);
+    const double inv = 1.0 / (double)P;
+    for (int k = tid; k < P; k += T) {
+        const V x = buf[lpad(k)];
+        out64[boff + k] = cmk<V>(x.x * inv, x.y * inv);
+        out32[boff + k] = make_float2((float)(x.x * inv), (float)(x.y * inv));
+    }
+}
+
+// Ring syntheses of the Bluestein rings (class P): per output, the folded
+// half spectrum X_0 .. X_M into the upper half of the buffer (X_0 and X_M,
+// both real, share slot M), Z_k as in the mixed-radix kernel, a_k = conj(Z_k
+// w^{k^2}), the two transforms around the product with the chirp spectrum,
+// and out[2n], out[2n + 1] = Re, Im (w^{n^2} c_n).
+// FP32: at most 128 VGPRs (four waves per SIMD; a few spills cost less than
+// the lost occupancy); FP64 keeps its registers.
+template <typename R, int P>
+__global__ __launch_bounds__(blue_threads<P>()) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 4 : 1)))
+void k_ring_fft_blue(
+    const FftJob *__restrict__ jobs, const typename C2<R>::T *__restrict__ Fbase, R *__restrict__ Dbase, int lmax,
+    const HRing *__restrict__ hring, const typename C2<R>::T *__restrict__ twAll,
+    const typename C2<R>::T *__restrict__ twP, const typename C2<R>::T *__restrict__ bhat)
+{
+    using V = typename C2<R>::T;
+    constexpr int T = blue_threads<P>();
+    extern __shared__ unsigned char smem_raw[];
+    V *buf = reinterpret_cast<V *>(smem_raw);
+    const int tid = threadIdx.x;
+    const FftJob &job = jobs[blockIdx.x];
+    const HRing hr = hring[job.pad];
+    const int N = hr.nphi, M = N / 2, L = lmax, i4 = N / 4;
+    const R sigma = (R)hr.sigma;
+    const V *twN = twAll + (size_t)2 * i4 * (i4 - 1);
+    const V *bh = bhat + hr.boff;
+    const V *F = Fbase + job.src;
+    for (int q = 0; q < job.nk; ++q) {
+        const int k = job.k[q];
+        const R scale = (R)job.scale[q];
+        auto coef = [&](int m) -> V {  // scale (i m)^k F_m, m >= 0
+            const V f = F[m];
+            R mk = scale;
+            for (int t = 0; t < k; ++t) mk *= (R)m;
+            R re = mk * f.x, im = m == 0 ? (R)0 : mk * f.y;
+            switch (k & 3) {
+            case 1: { const R t2 = re; re = -im; im = t2; } break;
+            case 2: re = -re; im = -im; break;
+            case 3: { const R t2 = re; re = im; im = -t2; } break;
+            default: break;
+            }
+            return cmk<V>(re, im);
+        };
+        // X_qq = e^{i qq phi0} sum over m = qq mod N (with sigma per wrap)
+        auto fold = [&](int qq) -> V {
+            R re = 0, im = 0, sg = 1;
+            for (int m = qq; m <= L; m += N, sg *= sigma) {
+                const V c = coef(m);
+                re += sg * c.x;
+                im += sg * c.y;
+            }
+            sg = sigma;
+            for (int m = N - qq; m <= L; m += N, sg *= sigma) {
+                const V c = coef(m);
+                re += sg * c.x;
+                im -= sg * c.y;
+            }
+            R sn = 0, cs = 1;
+            if (hr.shift) sc_pi((R)qq / (R)N, &sn, &cs);
+            return cmk<V>(re * cs - im * sn, re * sn + im * cs);
+        };
+        for (int t = tid; t < M; t += T) buf[lpad(M + t)] = t == 0 ? cmk<V>(fold(0).x, fold(M).x) : fold(t);
+        __syncthreads();
+        for (int t = tid; t < M; t += T) {
+            const V s0 = buf[lpad(M)];
+            const V xm = t == 0 ? cmk<V>(s0.x, (R)0) : buf[lpad(M + t)];
+            const V xr = t == 0 ? cmk<V>(s0.y, (R)0) : buf[lpad(M + M - t)];
+            const V xc = cconj(xr);
+            const V z = cadd(cadd(xm, xc), cmuli(cmul(twN[t], csub(xm, xc))));
+            buf[lpad(t)] = cconj(cmul(z, twN[(int)(((int64_t)t * t) % N)]));
+        }
+        __syncthreads();
+        for (int t = M + tid; t < P; t += T) buf[lpad(t)] = cmk<V>((R)0, (R)0);
+        __syncthreads();
+        fft_inplace<P, T>(buf, tid, twP);
+        for (int t = tid; t < P; t += T) buf[lpad(t)] = cmul(cconj(buf[lpad(t)]), bh[t]);
+        __syncthreads();
+        fft_inplace<P, T>(buf, tid, twP);
+        V *out = reinterpret_cast<V *>(Dbase + job.dst[q]);
+        for (int n = tid; n < M; n += T) out[n] = cmul(buf[lpad(n)], twN[(int)(((int64_t)n * n) % N)]);
+        __syncthreads();
+    }
+}
 }  // namespace
 
 // Kernel fill of n 32-bit words (usable inside captured graphs, unlike a
@@ -629,10 +949,154 @@ hipError_t prep_p2()
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)b);
 }
 
+// LDS of one Bluestein buffer of P points (padded)
+template <typename V>
+constexpr size_t blue_lds(int P) { return (size_t)(P + P / 32) * sizeof(V); }
+
+template <typename R, int P>
+hipError_t blue_attr()
+{
+    const size_t b = blue_lds<typename C2<R>::T>(P);
+    if (b <= 65536) return hipSuccess;
+    return hipFuncSetAttribute(reinterpret_cast<const void *>(&k_ring_fft_blue<R, P>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)b);
+}
+
+template <typename R>
+hipError_t blue_prepare()
+{
+    hipError_t e = blue_attr<R, 4096>();
+    if (e == hipSuccess) e = blue_attr<R, 8192>();
+    if (e == hipSuccess && sizeof(R) == 8) {
+        const size_t b4 = blue_lds<double2>(4096), b8 = blue_lds<double2>(8192);
+        e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_bluestein_table<4096>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)b4);
+        if (e == hipSuccess)
+            e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_bluestein_table<8192>),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)b8);
+    }
+    return e;
+}
+
+template <int P>
+void launch_blue_table(Plan &p, const int4 *items, int n)
+{
+    hipLaunchKernelGGL(k_bluestein_table<P>, dim3(n), dim3(blue_threads<P>()), blue_lds<double2>(P), p.stream, items,
+                       (const double2 *)p.twid64.ptr, (const double2 *)p.twP64.ptr, (double2 *)p.bhat64.ptr,
+                       (float2 *)p.bhat32.ptr);
+}
+
+hipError_t launch_bluestein_tables(Plan &p, const std::vector<int4> &items)
+{
+    if (items.empty()) return hipSuccess;
+    hipError_t e = blue_prepare<double>();
+    if (e != hipSuccess) return e;
+    int4 *d = nullptr;
+    e = hipMalloc(&d, items.size() * sizeof(int4));
+    if (e != hipSuccess) return e;
+    e = hipMemcpy(d, items.data(), items.size() * sizeof(int4), hipMemcpyHostToDevice);
+    // items come sorted by P: one launch per class
+    size_t a = 0;
+    while (e == hipSuccess && a < items.size()) {
+        size_t b = a;
+        while (b < items.size() && items[b].y == items[a].y) ++b;
+        const int n = (int)(b - a);
+        switch (items[a].y) {
+        case 256: launch_blue_table<256>(p, d + a, n); break;
+        case 512: launch_blue_table<512>(p, d + a, n); break;
+        case 1024: launch_blue_table<1024>(p, d + a, n); break;
+        case 2048: launch_blue_table<2048>(p, d + a, n); break;
+        case 4096: launch_blue_table<4096>(p, d + a, n); break;
+        case 8192: launch_blue_table<8192>(p, d + a, n); break;
+        default: e = hipErrorInvalidValue; break;
+        }
+        if (e == hipSuccess) e = hipGetLastError();
+        a = b;
+    }
+    const hipError_t e2 = hipStreamSynchronize(p.stream);
+    (void)hipFree(d);
+    return e != hipSuccess ? e : e2;
+}
+
+template <typename R, int P>
+void launch_blue(Plan &p, const void *Fbase, void *Dbase, const FftJob *jobs, int n)
+{
+    using V = typename C2<R>::T;
+    const bool f64 = sizeof(R) == 8;
+    hipLaunchKernelGGL((k_ring_fft_blue<R, P>), dim3(n), dim3(blue_threads<P>()), blue_lds<V>(P), p.stream, jobs,
+                       (const V *)Fbase,
+                       (R *)Dbase, p.lmax, (const HRing *)p.hring.ptr,
+                       (const V *)(f64 ? p.twid64.ptr : p.twid32.ptr), (const V *)(f64 ? p.twP64.ptr : p.twP32.ptr),
+                       (const V *)(f64 ? p.bhat64.ptr : p.bhat32.ptr));
+}
+
+template <typename R, int M>
+void launch_hpx_p2(Plan &p, const void *Fbase, void *Dbase, const FftJob *jobs, int n)
+{
+    using V = typename C2<R>::T;
+    const bool f64 = sizeof(R) == 8;
+    hipLaunchKernelGGL((k_ring_fft_hpx_p2<R, M>), dim3(n), dim3(256), (size_t)(M + M / 32) * sizeof(V), p.stream, jobs,
+                       (const V *)Fbase, (R *)Dbase, p.lmax, (const HRing *)p.hring.ptr,
+                       (const V *)(f64 ? p.twid64.ptr : p.twid32.ptr));
+}
+
+template <typename R, int M>
+hipError_t hpx_p2_attr()
+{
+    using V = typename C2<R>::T;
+    const size_t b = (size_t)(M + M / 32) * sizeof(V);
+    if (b <= 65536) return hipSuccess;
+    return hipFuncSetAttribute(reinterpret_cast<const void *>(&k_ring_fft_hpx_p2<R, M>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)b);
+}
+
+// The job classes of one HEALPix list: mixed radix, Bluestein by P, then the
+// power-of-two rings.
+template <typename R>
+hipError_t launch_hpx(Plan &p, const void *Fbase, void *Dbase, const FftJob *jobs, int njobs, int list)
+{
+    using V = typename C2<R>::T;
+    const int *cnt = p.hjobs[list];
+    int a = 0;
+    if (cnt[0] > 0) {
+        const size_t M = (size_t)p.hmax_direct;
+        hipLaunchKernelGGL(k_ring_fft_hpx<R>, dim3(cnt[0]), dim3(256), (2 * M + 1) * sizeof(V), p.stream, jobs,
+                           (const V *)Fbase, (R *)Dbase, p.lmax, (const HRing *)p.hring.ptr,
+                           (const V *)(sizeof(R) == 8 ? p.twid64.ptr : p.twid32.ptr));
+        a = cnt[0];
+    }
+    for (int c = 1; c < kHpxClasses; ++c) {
+        const int n = cnt[c];
+        if (n <= 0) continue;
+        if (c == kHpxPow2) {
+            switch (p.hmax_pow2) {
+            case 512: launch_hpx_p2<R, 512>(p, Fbase, Dbase, jobs + a, n); break;
+            case 1024: launch_hpx_p2<R, 1024>(p, Fbase, Dbase, jobs + a, n); break;
+            case 2048: launch_hpx_p2<R, 2048>(p, Fbase, Dbase, jobs + a, n); break;
+            case 4096: launch_hpx_p2<R, 4096>(p, Fbase, Dbase, jobs + a, n); break;
+            default: return hipErrorInvalidValue;
+            }
+            a += n;
+            continue;
+        }
+        switch (c) {
+        case 1: launch_blue<R, 256>(p, Fbase, Dbase, jobs + a, n); break;
+        case 2: launch_blue<R, 512>(p, Fbase, Dbase, jobs + a, n); break;
+        case 3: launch_blue<R, 1024>(p, Fbase, Dbase, jobs + a, n); break;
+        case 4: launch_blue<R, 2048>(p, Fbase, Dbase, jobs + a, n); break;
+        case 5: launch_blue<R, 4096>(p, Fbase, Dbase, jobs + a, n); break;
+        default: launch_blue<R, 8192>(p, Fbase, Dbase, jobs + a, n); break;
+        }
+        a += n;
+    }
+    if (a != njobs) return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
 hipError_t fft_prepare(Plan &p)
 {
     if (p.nside) {
-        const size_t M = 2 * (size_t)p.nside;
+        const size_t M = (size_t)p.hmax_direct;
         const size_t b64 = (2 * M + 1) * sizeof(double2), b32 = (2 * M + 1) * sizeof(float2);
         hipError_t e = hipSuccess;
         if (b64 > 65536)
@@ -641,6 +1105,11 @@ hipError_t fft_prepare(Plan &p)
         if (e == hipSuccess && b32 > 65536)
             e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_ring_fft_hpx<float>),
                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)b32);
+        if (e == hipSuccess) e = blue_prepare<double>();
+        if (e == hipSuccess) e = blue_prepare<float>();
+        if (e == hipSuccess && p.hmax_pow2 == 4096) e = hpx_p2_attr<double, 4096>();
+        if (e == hipSuccess && p.hmax_pow2 == 4096) e = hpx_p2_attr<float, 4096>();
+        if (e == hipSuccess && p.hmax_pow2 == 2048) e = hpx_p2_attr<double, 2048>();
         return e;
     }
     const size_t M = (size_t)p.nphi / 2;
@@ -690,20 +1159,14 @@ hipError_t launch_p2_R(Plan &p, const void *Fbase, void *Dbase, const FftJob *jo
 
 bool fft_p2(int M) { return M == 512 || M == 1024 || M == 2048 || M == 4096; }
 
-hipError_t launch_fft_jobs(Plan &p, const void *Fbase, void *Dbase, const FftJob *jobs, int njobs, bool fp64)
+hipError_t launch_fft_jobs(Plan &p, const void *Fbase, void *Dbase, const FftJob *jobs, int njobs, bool fp64,
+                           int list)
 {
     if (njobs <= 0) return hipSuccess;
     if (p.nside) {
-        const size_t M = 2 * (size_t)p.nside;
-        if (fp64)
-            hipLaunchKernelGGL(k_ring_fft_hpx<double>, dim3(njobs), dim3(256), (2 * M + 1) * sizeof(double2),
-                               p.stream, jobs, (const double2 *)Fbase, (double *)Dbase, p.lmax,
-                               (const HRing *)p.hring.ptr, (const double2 *)p.twid64.ptr);
-        else
-            hipLaunchKernelGGL(k_ring_fft_hpx<float>, dim3(njobs), dim3(256), (2 * M + 1) * sizeof(float2),
-                               p.stream, jobs, (const float2 *)Fbase, (float *)Dbase, p.lmax,
-                               (const HRing *)p.hring.ptr, (const float2 *)p.twid32.ptr);
-        return hipGetLastError();
+        if (list < 0 || list > 1) return hipErrorInvalidValue;
+        return fp64 ? launch_hpx<double>(p, Fbase, Dbase, jobs, njobs, list)
+                    : launch_hpx<float>(p, Fbase, Dbase, jobs, njobs, list);
     }
     const int M = p.nphi / 2;
     if (fft_p2(M)) {

@@ -55,13 +55,36 @@ struct TabBatch {
 };
 
 // One ring of a HEALPix grid (RING order): first pixel, pixel count, the
-// phase e^{i nphi phi0} (+-1) and phi of the first pixel.
+// phase e^{i nphi phi0} (+-1), phi of the first pixel (phi0 = pi shift / nphi,
+// shift 0 or 1), and how its ring FFT runs: P = 0, mixed radix; else
+// Bluestein's chirp transform of padded length P, with the spectrum of the
+// chirp at element offset boff of the plan's chirp tables.
 struct HRing {
     int64_t start;
     int32_t nphi;
     int32_t sigma;
     double phi0;
+    int64_t boff;
+    int32_t P;
+    int32_t shift;
+    int32_t cls;      // FFT job class (below)
+    int32_t pad;
 };
+
+// HEALPix ring FFT job classes: 0 = mixed radix, 1..6 = Bluestein with
+// P = 2^(c + 7) (256 .. 8192), 7 = power-of-two length 1024..8192 with
+// lmax < N (the belt of nside 256..2048: the radix-16 kernel).
+constexpr int kHpxClasses = 8;
+constexpr int kHpxPow2 = 7;
+inline int hpx_class_of_P(int P)
+{
+    int c = 0;
+    while (P > 128) {
+        P >>= 1;
+        ++c;
+    }
+    return c;
+}
 
 struct Plan {
     int lmax = 0;
@@ -101,6 +124,15 @@ struct Plan {
     DevBuf exps;      // int    [3][lmax+1][nrp]
     DevBuf mcut;      // int    [nrp]  largest significant m per ring pair
     DevBuf hring;     // HRing [ntheta] (HEALPix plans)
+    DevBuf twP64;     // double2 [8192] e^{2 pi i t / 8192} (HEALPix plans with Bluestein rings)
+    DevBuf twP32;     // float2  [8192]
+    DevBuf bhat64;    // double2 chirp spectra of the Bluestein ring lengths (HEALPix)
+    DevBuf bhat32;    // float2 copy
+    // HEALPix FFT jobs per class (deflection list, main list), in list order
+    int hjobs[2][kHpxClasses] = {};
+    int hmax_direct = 0;  // largest half length M of the mixed-radix rings
+    int hmax_P = 0;       // largest Bluestein length
+    int hmax_pow2 = 0;    // half length M of the power-of-two class (0: none)
     DevBuf tab;       // lambda / lambda' tables in MFMA operand layout (reduced-precision forms)
     DevBuf moff;      // int64 [lmax+2] offsets (16-byte units) of each m in tab
     DevBuf kstart;    // int [lmax+1][ntile] first non-empty 32-l chunk
@@ -221,8 +253,12 @@ int mfma_m_group();     // consecutive m per m-group
 hipError_t launch_legendre_mfma_queue(int order, bool pol, bool hasb, hipStream_t st, const MfmaJob *jobs,
                                       const int4 *items, int nitems, int *head, int ngroups);
 hipError_t fill_words(void *x, size_t n, uint32_t v, hipStream_t st);
+// list: 0 = the deflection jobs, 1 = the main jobs (HEALPix plans launch each
+// job class of the list on its own)
 hipError_t launch_fft_jobs(Plan &p, const void *Fbase, void *Dbase, const FftJob *jobs, int njobs,
-                           bool fp64);
+                           bool fp64, int list);
+// HEALPix: chirp spectra of the Bluestein ring lengths (items {M, class P, boff})
+hipError_t launch_bluestein_tables(Plan &p, const std::vector<int4> &items);
 // corr (optional, FP32 [3][ntheta][nphi]): added to the Taylor sums before the rotation
 hipError_t launch_remap(Plan &p, const void *D, const double *at, const double *ap,
                         const double *thsrc, const double *phsrc, void *T, void *Q, void *U,

@@ -8,7 +8,8 @@ Taylor series about its centre, rotation) in every precision form at small
 nside, with lmax from nside to 3 nside (polar rings of 4, 8, ... pixels far
 below the band limit), with B modes, naive positions, zero deflection and
 caller positions; then nside 2048 at full size on sampled rings (lmax 4096,
-order 3 in the FP32 form; lmax 3072, order 2 on split FP16 tables).
+order 3 in the FP32 form; lmax 3072, order 2 on split FP16 tables, six
+realizations per pass).
 Bars as on the equal-theta grid: FP64 1e-11 (1e-10 on the maximum),
 FP32 and split FP16 1e-5, FP16 1e-3 (relative RMS per field)."""
 import math
@@ -134,34 +135,70 @@ def test_healpix_refusals(tl):
     assert e.value.code == tl.TL_ERR_UNSUPPORTED
 
 
-@pytest.mark.parametrize("precision,lmax,order", [("fp32", 4096, 3), ("fp16x2", 3072, 2)])
-def test_healpix_nside2048_sampled_rings(tl, precision, lmax, order):
-    """nside 2048 at lmax 4096, order 3 (FP32 form) and lmax 3072, order 2
-    (split FP16 tables, six per pass in the benchmark): rows of the paper's
-    fastest-settings table at full size (the split tables of lmax 4096 on
-    8191 rings would not fit one GPU)."""
-    nside = 2048
-    sky = skygen.make_sky(lmax, 2, pol=True)
+@pytest.mark.parametrize("nside,lmax,precision", [(256, 400, "fp64"), (256, 600, "fp64"), (256, 1100, "fp64"),
+                                                   (512, 1536, "fp32"), (128, 300, "fp16x2")])
+def test_healpix_ring_fft_classes(tl, nside, lmax, precision):
+    """Every ring FFT class on sampled rings against the oracle: the belt of
+    nside 256 and 512 (power-of-two length N = 4 nside; lmax below N / 2, up
+    to N - 1 with the mirror term c_{N - m}, and lmax >= N, which folds more
+    and takes the mixed-radix kernel), cap rings of smooth length (mixed
+    radix) and of lengths with a large prime factor (Bluestein: 4 i pixels
+    with i = 17, 37, 101, 127, 251, 509)."""
+    order = 3
     dev = torch.device("cuda", 0)
+    sky = _sky(lmax, nside, 41 + nside + lmax)
     plan = tl.Plan(lmax, 0, 0, order, precision, pol=True, nside=nside)
     got = plan.lens_map(*(torch.from_numpy(a).to(dev) if a is not None else None
-                          for a in (sky.alm_T, sky.alm_E, None, sky.alm_phi)))
+                          for a in (sky.alm_T, sky.alm_E, sky.alm_B, sky.alm_phi)))
     torch.cuda.synchronize()
-    _, nphi, _, start = hp.ring_geometry(nside)
+    caps = [i for i in (1, 2, 16, 17, 24, 37, 101, 127, 251, 509) if i < nside]
+    rings = np.array(sorted(set([i - 1 for i in caps] + [4 * nside - 1 - i for i in caps[:4]]
+                                + [nside - 1, nside, nside + 1, 2 * nside - 1, 3 * nside - 1])))
+    pix = hp.ring_pixels(nside, rings)
+    rows = [t2np(x[torch.from_numpy(pix).to(dev)]) for x in got]
+    plan.close()
+    ref = hp.lens_pixels(lmax, order, nside, pix, sky.alm_T, sky.alm_E, sky.alm_B, sky.alm_phi,
+                         nthreads=ORACLE_THREADS)
+    ok = hp.ang2pix(nside, ref["_thp"] + 1e-12, ref["_php"] + 1e-12) == ref["_src"]
+    tr, tm = TOL[precision]
+    for name, g in zip("TQU", rows):
+        e1, e2 = rel_rms(g, ref[name], ok), max_rel(g, ref[name], ok)
+        print(precision, nside, lmax, name, f"{e1:.2e} {e2:.2e}")
+        assert e1 < tr and e2 < tm, (name, e1, e2)
+
+
+@pytest.mark.parametrize("precision,lmax,order,batch", [("fp32", 4096, 3, 1), ("fp16x2", 3072, 2, 6)])
+def test_healpix_nside2048_sampled_rings(tl, precision, lmax, order, batch):
+    """nside 2048 at lmax 4096, order 3 (FP32 form) and at lmax 3072, order 2
+    on split FP16 tables with six realizations per table pass (the launch the
+    benchmark times; the first and last realization of the pass checked): rows of the paper's
+    fastest-settings table at full size.  The split tables of lmax 4096 on
+    8191 HEALPix rings take 258 GiB, too much beside six realizations' work
+    buffers."""
+    nside = 2048
+    dev = torch.device("cuda", 0)
+    skies = [skygen.make_sky(lmax, 2 + i, pol=True) for i in range(batch)]
+    plan = tl.Plan(lmax, 0, 0, order, precision, pol=True, nside=nside, batch=batch if batch > 1 else 0)
+    alms = [tuple(torch.from_numpy(a).to(dev) if a is not None else None
+                  for a in (s.alm_T, s.alm_E, None, s.alm_phi)) for s in skies]
+    outs = plan.lens_map_many(alms) if batch > 1 else [plan.lens_map(*alms[0])]
+    torch.cuda.synchronize()
     # polar rings of 4 and 8 pixels, the cap rows next to the belt, the first
     # belt ring, mid-latitude, equator, the southmost ring
     rings = np.array([0, 1, 200, nside - 2, nside - 1, nside, 3 * nside // 2, 2 * nside - 1, 4 * nside - 2])
     pix = hp.ring_pixels(nside, rings)
-    rows = [t2np(x[torch.from_numpy(pix).to(dev)]) for x in got]
-    del got
+    idx = torch.from_numpy(pix).to(dev)
+    rows = [[t2np(x[idx]) for x in o] for o in outs]
+    del outs, alms
     plan.close()
     torch.cuda.empty_cache()
-    ref = hp.lens_pixels(lmax, order, nside, pix, sky.alm_T, sky.alm_E, sky.alm_B, sky.alm_phi,
-                         nthreads=ORACLE_THREADS)
-    nudged = hp.ang2pix(nside, ref["_thp"] + 1e-12, ref["_php"] + 1e-12)
-    ok = nudged == ref["_src"]
     tr, tm = TOL[precision]
-    for name, g in zip("TQU", rows):
-        e1, e2 = rel_rms(g, ref[name], ok), max_rel(g, ref[name], ok)
-        print(precision, "nside 2048", name, f"{e1:.2e} {e2:.2e}")
-        assert e1 < tr and e2 < tm, (name, e1, e2)
+    for q in sorted({0, batch - 1}):
+        s = skies[q]
+        ref = hp.lens_pixels(lmax, order, nside, pix, s.alm_T, s.alm_E, s.alm_B, s.alm_phi,
+                             nthreads=ORACLE_THREADS)
+        ok = hp.ang2pix(nside, ref["_thp"] + 1e-12, ref["_php"] + 1e-12) == ref["_src"]
+        for name, g in zip("TQU", rows[q]):
+            e1, e2 = rel_rms(g, ref[name], ok), max_rel(g, ref[name], ok)
+            print(precision, "nside 2048 realization", q, name, f"{e1:.2e} {e2:.2e}")
+            assert e1 < tr and e2 < tm, (q, name, e1, e2)
