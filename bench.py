@@ -63,7 +63,7 @@ def a3_useful_flops(lmax: int, nrp: int, order: int, pol: bool, hasb: bool):
     return 2 * nlm * nrp * (order + 1) * R
 
 
-def stage_work(w, order, form, q, hasb, n):
+def stage_work(w, order, form, q, hasb, n, maps16=False):
     """Algorithmic work of each stage per step (n realizations, one table
     pass): (bound, amount, unit, peak).  Harmonic-stage element counts are
     those below the evanescent cut (plan work counts)."""
@@ -74,9 +74,11 @@ def stage_work(w, order, form, q, hasb, n):
     nlm = (w.lmax + 1) * (w.lmax + 2) // 2
     fp64 = form == "fp64"
     tab = form in ("bf16x3", "fp16x2", "fp16", "bf16")
+    # derivative-map bytes per pixel and field (maps16: D_jk with j + k >= 3
+    # in FP16, orders >= 3)
+    dbytes = ndmap * 8 if fp64 else (6 * 4 + (ndmap - 6) * 2 if maps16 and order >= 3 else ndmap * 4)
     caps = q["elems"] if fp64 else q["elems_caps"]
     cbytes = 16 if fp64 else 8
-    rbytes = 8 if fp64 else 4
     # with the lensing potential in the table pass, the direct deflection
     # kernel covers the caps only
     defl = q["elems_caps"] if q["defl_folded"] else q["elems"]
@@ -88,6 +90,11 @@ def stage_work(w, order, form, q, hasb, n):
         "defl_fft": ("hbm", n * (2 * rowc * 16 + 2 * npix * 8)),
         "legendre_T": ("fp64", n * direct_flops_per_elem(order, False, False) * caps),
         "legendre_QU": ("fp64", n * direct_flops_per_elem(order, True, hasb) * caps),
+        # the caps in one launch: T, Q/U and (folded) the deflection
+        "legendre_caps": ("fp64", n * q["elems_caps"] * (direct_flops_per_elem(order, False, False)
+                                                         + (direct_flops_per_elem(order, True, hasb) if w.pol else 0)
+                                                         + (direct_flops_per_elem(1, False, False)
+                                                            if q["defl_folded"] else 0))),
         "legendre_mfma": ("fp32_mfma", n * (q["elems"] - q["elems_caps"]) * 2 * cols(order, w.pol, hasb) * 2),
         "tab_rhs": ("hbm", n * nlm * 16 * (1 + (2 if hasb else 1) * w.pol + q["defl_folded"])),
         # table stream + the FP32 column sums (4 per column: lam / lam' x parity)
@@ -95,8 +102,8 @@ def stage_work(w, order, form, q, hasb, n):
         # column sums back in, theta-derivative rows (and the potential's FP64 rows) out
         "tab_epi": ("hbm", colsum + n * nfield * (order + 1) * 2 * nrn * (w.lmax + 1) * 8
                     + n * q["defl_folded"] * 2 * 2 * nrn * (w.lmax + 1) * 16),
-        "ring_fft": ("hbm", n * (nfield * (order + 1) * rowc * cbytes + nfield * ndmap * npix * rbytes)),
-        "remap": ("hbm", n * (npix * (16 + nfield * 4) + nfield * ndmap * npix * rbytes)),
+        "ring_fft": ("hbm", n * (nfield * (order + 1) * rowc * cbytes + nfield * npix * dbytes)),
+        "remap": ("hbm", n * (npix * (16 + nfield * 4) + nfield * npix * dbytes)),
     }
     res = {}
     for k, (res_kind, amount) in out.items():
@@ -123,7 +130,7 @@ def sources_digest():
     return h.hexdigest()
 
 
-def measured_traffic(w, form, batch, kernel):
+def measured_traffic(w, fname, kernel):
     """HBM bytes per dispatch of `kernel` from the committed rocprofv3 counter
     summary of this workload and form (FETCH_SIZE and WRITE_SIZE, each scaled
     by what they read for a copy of known size), or None when there is no
@@ -132,7 +139,7 @@ def measured_traffic(w, form, batch, kernel):
     import re
 
     path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
-                        f"hbm_traffic_{w}_order4_{form}x{batch}.md")
+                        f"hbm_traffic_{w}_order4_{fname.replace(':', 'x').replace('+', '_')}.md")
     if not os.path.exists(path):
         return None
     text = open(path).read()
@@ -165,18 +172,27 @@ def measured_mfma_busy(w, form, kernel):
 
 
 def parse_form(s: str):
+    """'prec[:batch][+m16]' -> (prec, batch, maps16)."""
+    s, plus, opt = s.partition("+")
+    if plus and opt != "m16":
+        raise ValueError(f"unknown form option +{opt}")
     prec, _, b = s.partition(":")
-    return prec, int(b) if b else 1
+    return prec, int(b) if b else 1, bool(plus)
 
 
-def run_form(args, w, order, prec, batch, skies_dev):
+def form_name(f):
+    return (f[0] if f[1] == 1 else f"{f[0]}:{f[1]}") + ("+m16" if f[2] else "")
+
+
+def run_form(args, w, order, prec, batch, skies_dev, maps16=False):
     import torch
 
     from paper_1307_0719_amd import taylens
 
     torch.cuda.synchronize()
     b0 = time.perf_counter()
-    plan = taylens.Plan(w.lmax, w.ntheta, w.nphi, order, prec, pol=w.pol, batch=batch if batch > 1 else 0)
+    plan = taylens.Plan(w.lmax, w.ntheta, w.nphi, order, prec, pol=w.pol, batch=batch if batch > 1 else 0,
+                        maps16=maps16)
     torch.cuda.synchronize()
     plan_s = time.perf_counter() - b0
     q = {k: plan.query(k) for k in taylens.QUERY_KEYS}
@@ -490,8 +506,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="TP4096")
     ap.add_argument("--order", type=int, default=None)
-    ap.add_argument("--forms", default="fp32,bf16:6,fp16:6,bf16x3:6,fp16x2:6",
-                    help="comma list of precision[:realizations per step]; fp32 is the speed-up reference")
+    ap.add_argument("--forms", default="fp32,bf16:6,fp16:6,bf16x3:6,fp16x2:6,fp16x2:6+m16",
+                    help="comma list of precision[:realizations per step][+m16 (FP16 maps of order >= 3)]; "
+                         "fp32 is the speed-up reference")
     ap.add_argument("--headline", default=None, help="form reported as value (default: the last of --forms)")
     ap.add_argument("--cpu-rings", type=int, default=40, help="output rings in the CPU-oracle sample (five bands)")
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the oracle (no errors, no cpu_baseline)")
@@ -519,7 +536,7 @@ def main():
     headline = parse_form(args.headline) if args.headline else forms[-1]
     if headline not in forms:
         forms.append(headline)
-    nmax = max(b for _, b in forms)
+    nmax = max(f[1] for f in forms)
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
     skies = [skygen.make_sky(w.lmax, w.seed + i, pol=w.pol) for i in range(nmax)]
@@ -584,8 +601,8 @@ def main():
     defl = deflection_check(w, skies[:nmax], skies_dev[:nmax])
 
     results = {}
-    for prec, batch in forms:
-        r = run_form(args, w, order, prec, batch, skies_dev)
+    for prec, batch, m16 in forms:
+        r = run_form(args, w, order, prec, batch, skies_dev, m16)
         if ref is not None:
             mask = ref["_tie"] > 1e-9
             errs = {}
@@ -609,17 +626,15 @@ def main():
                     y = ref[f][sel][mk]
                     e = max(e, float(np.sqrt(np.mean((x - y) ** 2)) / np.sqrt(np.mean(y ** 2))))
                 r["errs_band"][bname] = e
-        results[(prec, batch)] = r
+        results[(prec, batch, m16)] = r
 
-    def name(f):
-        return f[0] if f[1] == 1 else f"{f[0]}:{f[1]}"
-
-    fp32 = results.get(("fp32", 1))
+    name = form_name
+    fp32 = results.get(("fp32", 1, False))
     forms_out = {}
     for f, r in results.items():
         px = f[1] * npix / r["sec"]
         leg = sum(r["per_step"].get(k, 0.0) for k in ("legendre_T", "legendre_QU", "legendre_mfma", "tab_rhs",
-                                                       "legendre_tab", "tab_epi"))
+                                                       "legendre_tab", "tab_epi", "legendre_caps"))
         useful = f[1] * a3_useful_flops(w.lmax, (w.ntheta + 1) // 2, order, w.pol, hasb)
         if r["q"]["defl_folded"]:
             # the table pass also synthesizes the deflection's two rows (order 1 of phi)
@@ -648,7 +663,7 @@ def main():
         forms_out[name(f)] = ent
 
     H = results[headline]
-    work = stage_work(w, order, headline[0], H["q"], hasb, headline[1])
+    work = stage_work(w, order, headline[0], H["q"], hasb, headline[1], headline[2])
     dom = max(H["per_step"], key=lambda k: H["per_step"][k])
     kind, amount, unit, peak = work[dom]
     from paper_1307_0719_amd import taylens
@@ -680,7 +695,7 @@ def main():
             "kernel": kname, "stage": dom, "bound": "mfma",
             "achieved": useful / t / 1e12, "peak": pk / 1e12, "unit": "TFLOP/s", "frac": useful / t / pk,
             "frac_dense": n * per_elem * nlm * nrn / t / pk,
-            "traffic": measured_traffic(args.workload, headline[0], headline[1], kname),
+            "traffic": measured_traffic(args.workload, name(headline), kname),
             "work_per_launch": useful / nl, "work_unit": f"useful flop: {per_elem} per (l, m, ring pair) "
                                                          f"below the cut outside the caps, x {n} realizations",
             "avg_launch_ms": H["avg_launch"][dom], "launches_per_step": nl,
@@ -695,7 +710,7 @@ def main():
             "bound": "hbm" if kind == "hbm" else ("alu" if kind == "fp64" else "mfma"),
             "achieved": amount / t / scale,
             "peak": peak / scale, "unit": unit, "frac": amount / t / peak,
-            "traffic": measured_traffic(args.workload, headline[0], headline[1], kname),
+            "traffic": measured_traffic(args.workload, name(headline), kname),
             "work_per_launch": amount / nl, "avg_launch_ms": H["avg_launch"][dom], "launches_per_step": nl,
             "peak_note": "FP64 vector peak (ALU-bound recursion)" if kind == "fp64" else None,
         }
@@ -732,9 +747,10 @@ def main():
         "config": {
             "workload": f"T+Q/U lmax={w.lmax}, {w.ntheta}x{w.nphi} equal-theta rings, Taylor order {order}, "
                         f"{headline[1]} realization(s) per step, {headline[0]} harmonic-stage contraction "
-                        f"(FP64 recursion, positions and rotation)",
+                        f"(FP64 recursion, positions and rotation)"
+                        + (", derivative maps of order j+k >= 3 stored in FP16" if headline[2] else ""),
             "lmax": w.lmax, "ntheta": w.ntheta, "nphi": w.nphi, "order": order, "fields": "TQU" if w.pol else "T",
-            "precision_form": headline[0], "realizations_per_step": headline[1],
+            "precision_form": headline[0], "realizations_per_step": headline[1], "maps16": headline[2],
             "rel_rms_err_vs_oracle": hf["rel_rms_err_vs_oracle"],
             "speedup_vs_fp32": hf["speedup_vs_fp32"],
             "timing": f"median of {args.steps} steps (HIP events on the plan's stream); "

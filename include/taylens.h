@@ -99,6 +99,17 @@ typedef struct {
                               0 or 1 for TL_FP64 / TL_FP32.                        */
     int64_t workspace_cap; /* bytes; 0 = no cap.  tl_plan_create fails with
                               TL_ERR_NOMEM if the plan would need more.            */
+    int32_t maps16;        /* 1: the plan's internal derivative maps D_jk with
+                              j + k >= 3 are FP16 (orders >= 3 of the non-FP64
+                              forms on the equal-theta grid; ignored elsewhere):
+                              30 % less map traffic at order 4.  The remap
+                              multiplies them by |u|^j |v|^k <= 1/8 in pixel
+                              units, so their rounding costs about 1e-6 of the
+                              map RMS for skies whose power falls off well
+                              before the band limit (the lensed CMB at lmax
+                              4096), but up to ~1e-4 for power at the grid's
+                              band limit.  0: FP32 maps.  tl_synth_derivs
+                              always returns FP32 maps.                          */
 } tl_options;
 
 typedef struct tl_plan_s *tl_plan;
@@ -368,10 +379,14 @@ int tl_lens_map_cnn(tl_plan plan, tl_cnn net, const void *alm_T, const void *alm
  * rings), 5 right-hand sides of the tabulated forms, 6 their table GEMM
  * (column sums), 7 ring FFTs of the derivative maps, 8 remap + Taylor sum +
  * rotation, 9 the learned correction network (tl_lens_map_cnn), 10 the
- * epilogue of the table GEMM (theta-derivative rows from the column sums).
- * The direct kernels take several realizations per launch in
+ * epilogue of the table GEMM (theta-derivative rows from the column sums),
+ * 11 the polar caps of the FP32 and tabulated forms in one launch: the
+ * direct FP64 recursion for T, for each spin family of Q/U and (when the
+ * table GEMM carries the lensing potential) for the deflection, every
+ * realization of the pass (stages 0, 2 and 3 then cover only what this one
+ * does not).  The direct kernels take several realizations per launch in
  * tl_lens_map_many. */
-#define TL_NSTAGE 11
+#define TL_NSTAGE 12
 
 /* enable != 0: from now on record a HIP event pair on the plan's stream
  * around every stage of every call (no synchronization is added); 0: stop.

@@ -113,7 +113,7 @@ void free_buf(DevBuf &b)
 void free_plan_buffers(Plan &p)
 {
     DevBuf *bufs[] = {&p.theta, &p.trig, &p.phitab, &p.phival, &p.twid64, &p.twid32, &p.coef0, &p.coef2,
-                      &p.start, &p.exps, &p.mcut, &p.tab, &p.moff, &p.kstart, &p.rhs, &p.colexp, &p.tabsum, &p.Fphi, &p.alpha, &p.F, &p.D, &p.jobsDefl, &p.jobsMain, &p.hring,
+                      &p.start, &p.exps, &p.mcut, &p.tab, &p.moff, &p.kstart, &p.rhs, &p.colexp, &p.tabsum, &p.Fphi, &p.alpha, &p.F, &p.D, &p.jobsDefl, &p.jobsMain, &p.jobsInt, &p.hring,
                       &p.twP64, &p.twP32, &p.bhat64, &p.bhat32};
     for (DevBuf *b : bufs) free_buf(*b);
 }
@@ -223,11 +223,11 @@ void healpix_rings(int nside, int lmax, std::vector<double> &th, std::vector<HRi
 struct Sizes {
     size_t theta, trig, phitab, phival, twid64, twid32, coef, start, exps, mcut, Fphi, alpha, F, D, jd, jm;
     size_t tab = 0, moff = 0, kstart = 0, rhs = 0, colexp = 0, tabsum = 0, hring = 0;
-    size_t twP64 = 0, twP32 = 0, bhat64 = 0, bhat32 = 0;
+    size_t twP64 = 0, twP32 = 0, bhat64 = 0, bhat32 = 0, jx = 0;
     size_t total() const
     {
         return theta + trig + phitab + phival + twid64 + twid32 + 2 * coef + start + exps + mcut + Fphi + alpha + F +
-               D + jd + jm + tab + moff + kstart + rhs + colexp + tabsum + hring + twP64 + twP32 + bhat64 + bhat32;
+               D + jd + jm + tab + moff + kstart + rhs + colexp + tabsum + hring + twP64 + twP32 + bhat64 + bhat32 + jx;
     }
 };
 
@@ -279,9 +279,11 @@ Sizes plan_sizes(const Plan &p)
         s.colexp = (size_t)(p.lmax + 1) * 32 * nb * sizeof(float);
         s.tabsum = tab_sum_bytes(p.lmax, p.nrp - p.rpole, p.order, p.pol != 0, p.batch);
     }
-    s.D = (size_t)p.nfield() * p.ndmap() * p.npix() * rbytes;
+    s.D = p.mix16 ? (size_t)p.nfield() * (mix_n32() * p.dstride * 4 + (p.ndmap() - mix_n32()) * p.dstride16 * 2)
+                  : (size_t)p.nfield() * p.ndmap() * p.dstride * rbytes;
     s.jd = 2 * (size_t)p.ntheta * sizeof(FftJob);
     s.jm = (size_t)p.nfield() * (p.order + 1) * p.ntheta * sizeof(FftJob);
+    s.jx = s.jm;
     return s;
 }
 
@@ -311,6 +313,7 @@ int validate_options(int32_t lmax, tl_grid grid, const tl_options *opt)
     if (opt->pol != 0 && opt->pol != 1) return fail(TL_ERR_INVALID, "pol must be 0 or 1");
     if (opt->rotate != 0 && opt->rotate != 1) return fail(TL_ERR_INVALID, "rotate must be 0 or 1");
     if (opt->naive_pos != 0 && opt->naive_pos != 1) return fail(TL_ERR_INVALID, "naive_pos must be 0 or 1");
+    if (opt->maps16 != 0 && opt->maps16 != 1) return fail(TL_ERR_INVALID, "maps16 must be 0 or 1");
     if (opt->batch < 0 || (!tab && opt->batch > 1))
         return fail(TL_ERR_INVALID, "batch must be 0 or 1 for the FP64 / FP32 forms");
     const int bmax = use_tables() ? tab_max_batch(opt->order, opt->pol != 0, false)
@@ -322,6 +325,30 @@ int validate_options(int32_t lmax, tl_grid grid, const tl_options *opt)
     if (!factor_radices(grid.nphi / 2, tmp))
         return fail(TL_ERR_UNSUPPORTED, "nphi/2 must be a product of 2, 3 and 5");
     return TL_OK;
+}
+
+// The job of field f, theta-derivative row j into the plan's own maps:
+// planes of dstride elements, [field][ndmap][plane]; with mix16, outputs with
+// j + k < kMix16 to the FP32 maps [field][6][plane], the others (bit set in
+// h16) to the FP16 maps [field][ndmap - 6][plane of dstride16] after them.
+// off = the ring's first pixel.
+FftJob int_job(const Plan &p, FftJob a, int f, int j, int64_t off)
+{
+    const int N = p.order, n16 = p.ndmap() - mix_n32();
+    const int64_t s32 = (int64_t)p.dstride, s16 = (int64_t)p.dstride16;
+    a.h16 = 0;
+    for (int q = 0; q < a.nk; ++q) {
+        const int k = a.k[q];
+        if (!p.mix16) {
+            a.dst[q] = ((int64_t)f * p.ndmap() + dmap_index(N, j, k)) * s32 + off;
+        } else if (j + k >= kMix16) {
+            a.h16 |= 1 << q;
+            a.dst[q] = ((int64_t)f * n16 + mix_idx16(N, j, k)) * s16 + off;
+        } else {
+            a.dst[q] = ((int64_t)f * mix_n32() + mix_idx32(j, k)) * s32 + off;
+        }
+    }
+    return a;
 }
 
 // FFT jobs of a HEALPix plan: rows to rings of their own length (pad = the
@@ -357,6 +384,7 @@ int build_jobs_healpix(Plan &p)
     p.njobsDefl = (int)jd.size();
     const double del = M_PI / (4.0 * p.nside);
     std::vector<FftJob> jm((size_t)p.nfield() * (N + 1) * p.ntheta);
+    std::vector<FftJob> jx(jm.size());
     size_t q = 0;
     for (int f = 0; f < p.nfield(); ++f)
         for (int j = 0; j <= N; ++j)
@@ -370,6 +398,7 @@ int build_jobs_healpix(Plan &p)
                     a.dst[k] = (int64_t)(((size_t)f * p.ndmap() + dmap_index(N, j, k)) * np + hr[i].start);
                     a.scale[k] = std::pow(del, j + k) / (factorial(j) * factorial(k));
                 }
+                jx[q] = int_job(p, a, f, j, hr[i].start);
                 jm[q++] = a;
             }
     p.njobsMain = (int)jm.size();
@@ -382,8 +411,13 @@ int build_jobs_healpix(Plan &p)
     };
     by_class(jd, p.hjobs[0]);
     by_class(jm, p.hjobs[1]);
+    {
+        int cnt[kHpxClasses];
+        by_class(jx, cnt);  // the same stable permutation as jm
+    }
     TL_HIP(hipMemcpy(p.jobsDefl.ptr, jd.data(), jd.size() * sizeof(FftJob), hipMemcpyHostToDevice), "jobs copy");
     TL_HIP(hipMemcpy(p.jobsMain.ptr, jm.data(), jm.size() * sizeof(FftJob), hipMemcpyHostToDevice), "jobs copy");
+    TL_HIP(hipMemcpy(p.jobsInt.ptr, jx.data(), jx.size() * sizeof(FftJob), hipMemcpyHostToDevice), "jobs copy");
     return TL_OK;
 }
 
@@ -420,6 +454,7 @@ int build_jobs(Plan &p)
     }
     p.njobsDefl = (int)jd.size();
     std::vector<FftJob> jm((size_t)p.nfield() * (N + 1) * p.ntheta);
+    std::vector<FftJob> jx(jm.size());
     size_t q = 0;
     for (int f = 0; f < p.nfield(); ++f)
         for (int j = 0; j <= N; ++j)
@@ -432,12 +467,24 @@ int build_jobs(Plan &p)
                     a.dst[k] = (int64_t)((((size_t)f * p.ndmap() + dmap_index(N, j, k)) * p.ntheta + i) * p.nphi);
                     a.scale[k] = std::pow(dth, j) * std::pow(dph, k) / (factorial(j) * factorial(k));
                 }
+                jx[q] = int_job(p, a, f, j, (int64_t)i * p.nphi);
                 jm[q++] = a;
             }
     p.njobsMain = (int)jm.size();
     TL_HIP(hipMemcpy(p.jobsDefl.ptr, jd.data(), jd.size() * sizeof(FftJob), hipMemcpyHostToDevice), "jobs copy");
     TL_HIP(hipMemcpy(p.jobsMain.ptr, jm.data(), jm.size() * sizeof(FftJob), hipMemcpyHostToDevice), "jobs copy");
+    TL_HIP(hipMemcpy(p.jobsInt.ptr, jx.data(), jx.size() * sizeof(FftJob), hipMemcpyHostToDevice), "jobs copy");
     return TL_OK;
+}
+
+// Ring FFTs of the main rows F into the maps Dout: the plan's own maps
+// (padded planes, mixed precision when mix16) or a caller's (plain layout).
+hipError_t launch_main_fft(Plan &p, const void *F, void *Dout)
+{
+    if (Dout == p.D.ptr)
+        return launch_fft_jobs(p, F, Dout, (const FftJob *)p.jobsInt.ptr, p.njobsMain, p.fp64(), 1,
+                               p.mix16 ? p.d16() : nullptr);
+    return launch_fft_jobs(p, F, Dout, (const FftJob *)p.jobsMain.ptr, p.njobsMain, p.fp64(), 1);
 }
 
 int upload_tables(Plan &p)
@@ -582,6 +629,47 @@ bool fold_deflection(const Plan &p, int n, const void *const *P)
     return true;
 }
 
+// Whether the polar caps of n realizations of this FP32-row plan take the
+// one combined launch (orders up to 6; caps present).
+bool caps_one_launch(const Plan &p, int n, bool hasb)
+{
+    return !p.fp64() && p.rpole > 0 && n >= 1 && n <= kTabMaxBatch && caps_nb(1, p.order, hasb) > 0;
+}
+
+// Polar caps (ring pairs below rpole) of n realizations in one launch: T,
+// both spin families of Q/U and, with P, the lensing potential's FP64 rows
+// (fphi_slot) -- FP32 rows Fout[q] laid out [field][N + 1][ring][m].
+int run_caps(Plan &p, int n, const void *const *T, const void *const *E, const void *const *B, const void *const *P,
+             void *const *Fout, bool hasb)
+{
+    const size_t rowc = (size_t)p.ntheta * (p.lmax + 1) * (p.order + 1);
+    CapsArgs a{};
+    auto add = [&](int kind) {
+        const int nb = caps_nb(kind, p.order, hasb);
+        for (int i0 = 0; i0 < n; i0 += nb) a.task[a.ntask++] = make_int4(kind, i0, std::min(nb, n - i0), 0);
+    };
+    for (int q = 0; q < n; ++q) {
+        char *F = (char *)Fout[q];
+        a.T[q] = (const double2 *)T[q];
+        a.E[q] = p.pol ? (const double2 *)E[q] : nullptr;
+        a.B[q] = hasb ? (const double2 *)B[q] : nullptr;
+        a.P[q] = P ? (const double2 *)P[q] : nullptr;
+        a.FT[q] = F;
+        a.FQ[q] = p.pol ? F + rowc * 8 : nullptr;
+        a.FU[q] = p.pol ? F + 2 * rowc * 8 : nullptr;
+        a.FP[q] = P ? fphi_slot(p, q) : nullptr;
+    }
+    if (P) add(0);
+    add(1);
+    if (p.pol) {
+        add(2);
+        add(3);
+    }
+    StageScope sc(p, ST_CAPS);
+    TL_HIP(launch_legendre_caps(p, p.rpole, a, p.pol ? n : 0, hasb), "legendre caps");
+    return TL_OK;
+}
+
 // Harmonic stage of n realizations (n <= plan batch for the table forms).
 // P (optional): their lensing potentials; when fold_deflection() holds, the
 // lam / lam' sums of phi outside the caps go to fphi_slot(q).
@@ -597,8 +685,16 @@ int run_legendre_many(Plan &p, int n, const void *const *T, const void *const *E
     const bool mfma = p.precision == TL_FP32 && mfma_supported(p.order, hasb);
     const bool tab = p.tabform() && p.ntile > 0;
     const int rend = (mfma || tab) ? p.rpole : p.nrp;
+    p.caps_defl_done = false;
+    const bool caps1 = (mfma || tab) && caps_one_launch(p, n, hasb);
+    if (caps1) {
+        const bool defl = fold_deflection(p, n, P);
+        int rc = run_caps(p, n, T, E, B, defl ? P : nullptr, Fout, hasb);
+        if (rc) return rc;
+        p.caps_defl_done = defl;
+    }
     // direct kernels: several realizations per launch share the recursion
-    for (int i0 = 0, mx = direct_max(p.order, false, false, p.fp64()); i0 < n; i0 += mx) {
+    for (int i0 = 0, mx = direct_max(p.order, false, false, p.fp64()); !caps1 && i0 < n; i0 += mx) {
         DirectSet set{};
         set.n = std::min(mx, n - i0);
         for (int q = 0; q < set.n; ++q) {
@@ -608,7 +704,7 @@ int run_legendre_many(Plan &p, int n, const void *const *T, const void *const *E
         StageScope sc(p, ST_LEG_T);
         TL_HIP(launch_legendre_scalar_set(p, p.order, rend, set, p.fp64()), "legendre T");
     }
-    for (int i0 = 0, mx = direct_max(p.order, true, hasb, p.fp64()); p.pol && i0 < n; i0 += mx) {
+    for (int i0 = 0, mx = direct_max(p.order, true, hasb, p.fp64()); !caps1 && p.pol && i0 < n; i0 += mx) {
         DirectSet set{};
         set.n = std::min(mx, n - i0);
         for (int q = 0; q < set.n; ++q) {
@@ -679,7 +775,7 @@ int run_derivs(Plan &p, const void *T, const void *E, const void *B, void *Dout)
     int rc = run_legendre(p, T, E, B, p.F.ptr);
     if (rc) return rc;
     StageScope sc(p, ST_FFT);
-    TL_HIP(launch_fft_jobs(p, p.F.ptr, Dout, (const FftJob *)p.jobsMain.ptr, p.njobsMain, p.fp64(), 1), "ring fft");
+    TL_HIP(launch_main_fft(p, p.F.ptr, Dout), "ring fft");
     return TL_OK;
 }
 
@@ -1005,6 +1101,12 @@ int batch_enqueue(tl_batch_s *b, const void *const *alms, void *const *outs, boo
         Plan &p = b->plans[i]->p;
         char *F = (char *)b->F[i].ptr;
         const size_t rc8 = batch_rowc(p) * 8;
+        if (caps_one_launch(p, 1, hasb)) {  // as a single call of the plan does
+            void *Fs[1] = {F};
+            const int rc = run_caps(p, 1, &alms[4 * i], &alms[4 * i + 1], &alms[4 * i + 2], nullptr, Fs, hasb);
+            if (rc) return rc;
+            continue;
+        }
         TL_HIP(launch_legendre_scalar(p, p.order, p.rpole, alms[4 * i], F, false), "legendre T");
         if (p.pol)
             TL_HIP(launch_legendre_spin(p, p.order, p.rpole, alms[4 * i + 1], alms[4 * i + 2], F + rc8, F + 2 * rc8,
@@ -1016,7 +1118,7 @@ int batch_enqueue(tl_batch_s *b, const void *const *alms, void *const *outs, boo
     for (int i = 0; i < b->n; ++i) {
         Plan &p = b->plans[i]->p;
         if ((rc = run_deflection(p, alms[4 * i + 3]))) return rc;
-        TL_HIP(launch_fft_jobs(p, b->F[i].ptr, p.D.ptr, (const FftJob *)p.jobsMain.ptr, p.njobsMain, false, 1),
+        TL_HIP(launch_main_fft(p, b->F[i].ptr, p.D.ptr),
                "ring fft");
         const double *at = (const double *)p.alpha.ptr;
         TL_HIP(launch_remap(p, p.D.ptr, at, at + p.npix(), nullptr, nullptr, outs[3 * i], outs[3 * i + 1],
@@ -1093,9 +1195,33 @@ void plan_fields(Plan &p, int32_t lmax, tl_grid grid, const tl_options *opt, voi
         // is a limit); HEALPix has no pole ring
         int rp = p.nside ? 0 : 1;
         while (rp < p.nrp && sin_ring(rp) < smin) ++rp;
+        // Large caps fill whole 64-lane waves of the direct kernels (a wave
+        // walks the whole l recursion for its 64 ring pairs, however few are
+        // live): down to a multiple of 64 when that gives up at most 1/16 of
+        // the cap, else up (more rings on the direct FP64 kernels, in the
+        // same wall time).
+        if (rp >= 48) {
+            const int dn = rp / 64 * 64;
+            rp = (dn >= 64 && rp - dn <= rp / 16) ? dn : std::min(p.nrp, (rp + 63) / 64 * 64);
+        }
         p.rpole = rp;
     }
     p.batch = opt->batch > 1 ? opt->batch : 1;
+    // maps16: orders >= 3 of the FP32-map forms on the equal-theta grid keep
+    // D_jk with j + k >= 3 in FP16 (the remap scales them by |u|^j |v|^k <=
+    // 1/8: 6e-7 to 1.2e-6 of the map RMS for the lensed CMB at lmax 4096, up
+    // to ~1e-4 for power at the band limit).  Not on HEALPix rings, whose
+    // offsets in units of delta reach nside / i on polar ring i.
+    p.mix16 = opt->maps16 == 1 && !p.fp64() && p.order >= kMix16 && p.nside == 0;
+    {
+        auto padded = [](size_t n, size_t q) {
+            const size_t b = (n + q - 1) / q;
+            return (b | 1) * q;
+        };
+        const size_t np = nside ? (size_t)12 * nside * nside : (size_t)grid.ntheta * grid.nphi;
+        p.dstride = padded(np, p.fp64() ? 32 : 64);  // 256-byte units
+        p.dstride16 = padded(np, 128);
+    }
     p.ntile = (p.nrp - p.rpole + 31) / 32;
     p.tables = p.tabform() && use_tables();
     if (p.precision == TL_FP16 || p.precision == TL_FP16X2) {
@@ -1146,7 +1272,8 @@ std::vector<BufItem> plan_buffer_list(Plan &p, const Sizes &sz)
             {&p.coef0, sz.coef, "coef0"},    {&p.coef2, sz.coef, "coef2"},     {&p.start, sz.start, "start"},
             {&p.exps, sz.exps, "exps"},      {&p.mcut, sz.mcut, "mcut"},       {&p.Fphi, sz.Fphi, "Fphi"},
             {&p.alpha, sz.alpha, "alpha"},   {&p.F, sz.F, "F"},                {&p.D, sz.D, "D"},
-            {&p.jobsDefl, sz.jd, "jobsDefl"}, {&p.jobsMain, sz.jm, "jobsMain"}, {&p.tab, sz.tab, "tab"},
+            {&p.jobsDefl, sz.jd, "jobsDefl"}, {&p.jobsMain, sz.jm, "jobsMain"}, {&p.jobsInt, sz.jx, "jobsInt"},
+            {&p.tab, sz.tab, "tab"},
             {&p.moff, sz.moff, "moff"},      {&p.kstart, sz.kstart, "kstart"}, {&p.rhs, sz.rhs, "rhs"},
             {&p.colexp, sz.colexp, "colexp"}, {&p.tabsum, sz.tabsum, "tabsum"}, {&p.hring, sz.hring, "hring"},
             {&p.twP64, sz.twP64, "twP64"},   {&p.twP32, sz.twP32, "twP32"},   {&p.bhat64, sz.bhat64, "bhat64"},
@@ -1193,10 +1320,10 @@ int lens_map_core(Plan &p, const void *alm_T, const void *alm_E, const void *alm
         const void *Ts[1] = {alm_T}, *Es[1] = {alm_E}, *Bs[1] = {alm_B}, *Ps[1] = {alm_phi};
         void *Fs[1] = {p.F.ptr};
         if ((rc = run_legendre_many(p, 1, Ts, Es, Bs, Fs, Ps))) return rc;
-        if ((rc = defl_legendre(p, 1, Ps, true))) return rc;
+        if (!p.caps_defl_done && (rc = defl_legendre(p, 1, Ps, true))) return rc;
         if ((rc = defl_fft(p, alm_phi, 0))) return rc;
         StageScope sc(p, ST_FFT);
-        TL_HIP(launch_fft_jobs(p, p.F.ptr, p.D.ptr, (const FftJob *)p.jobsMain.ptr, p.njobsMain, p.fp64(), 1),
+        TL_HIP(launch_main_fft(p, p.F.ptr, p.D.ptr),
                "ring fft");
     } else {
         if ((rc = run_deflection(p, alm_phi))) return rc;
@@ -1569,12 +1696,12 @@ int tl_lens_map_many(tl_plan plan, int32_t n, const void *const *alms, void *con
         // deflection sums of the whole group (outside the caps from the
         // table pass when folded), then per realization: deflection FFT,
         // ring FFTs, remap
-        if ((rc = defl_legendre(p, k, P, fold))) return rc;
+        if (!(fold && p.caps_defl_done) && (rc = defl_legendre(p, k, P, fold))) return rc;
         for (int q = 0; q < k; ++q) {
             if ((rc = defl_fft(p, P[q], q))) return rc;
             {
                 StageScope sc(p, ST_FFT);
-                TL_HIP(launch_fft_jobs(p, F[q], p.D.ptr, (const FftJob *)p.jobsMain.ptr, p.njobsMain, p.fp64(), 1),
+                TL_HIP(launch_main_fft(p, F[q], p.D.ptr),
                        "ring fft");
             }
             const double *at = (const double *)p.alpha.ptr;

@@ -105,6 +105,7 @@ struct Grid {
     const double *theta;
     const double2 *trig, *phitrig;
     const double *phival;
+    size_t ds;  // plane stride of the derivative maps (elements)
 };
 
 struct TrainBufs {
@@ -153,7 +154,7 @@ __global__ __launch_bounds__(64) void k_cnn_forward(Grid G, const float *__restr
         for (int f = 0; f < 3; ++f)
 #pragma unroll
             for (int q = 0; q < 6; ++q) {
-                const float x = D[(size_t)(6 * f + q) * npix + o];
+                const float x = D[(size_t)(6 * f + q) * G.ds + o];
                 ss[f] = fmaf(x, x, ss[f]);
             }
     }
@@ -171,7 +172,7 @@ __global__ __launch_bounds__(64) void k_cnn_forward(Grid G, const float *__restr
 #pragma unroll
         for (int f = 0; f < 3; ++f)
 #pragma unroll
-            for (int q = 0; q < 6; ++q) c24[6 * f + q] = D[(size_t)(6 * f + q) * npix + o] * inv[f];
+            for (int q = 0; q < 6; ++q) c24[6 * f + q] = D[(size_t)(6 * f + q) * G.ds + o] * inv[f];
         c24[18] = u;
         c24[19] = v;
 #pragma unroll
@@ -435,8 +436,10 @@ hipError_t cnn_forward(const Plan &p, const CnnBufs &c, const float *D, const do
                        const int64_t *pix, int64_t n, float *corr, bool train, hipStream_t st)
 {
     if (n <= 0) return hipSuccess;
+    // the plan's own maps have padded planes; a caller's are [field][map][pixel]
     Grid G{p.ntheta, p.nphi, (const double *)p.theta.ptr, (const double2 *)p.trig.ptr,
-           (const double2 *)p.phitab.ptr, (const double *)p.phival.ptr};
+           (const double2 *)p.phitab.ptr, (const double *)p.phival.ptr,
+           D == (const float *)p.D.ptr ? p.dstride : p.npix()};
     TrainBufs tb{};
     if (train) {
         char *b = (char *)c.work;

@@ -482,15 +482,13 @@ __device__ __forceinline__ void store_c<float>(float *F, size_t idx, double2 v)
 
 // Scalar field, NB realizations sharing the recursion:
 //     F_q[j][ring][m] = sum_l a^q_lm d^j lambda_lm(theta_ring).
+// One wave: 64 ring pairs at one m (outputs with a NULL F are skipped).
 template <int J, int NB, typename FT>
-__global__ __launch_bounds__(512) void k_legendre_scalar(
-    int lmax, int ntheta, int nrp, int rend, int jtab, const double2 *__restrict__ trig,
-    const double4 *__restrict__ coef0, const double *__restrict__ start, const int *__restrict__ exps,
-    const int *__restrict__ mcut, const DirectSet set)
+__device__ __forceinline__ void body_scalar(int m, int r0, int lmax, int ntheta, int nrp, int rend, int jtab,
+                                            const double2 *__restrict__ trig, const double4 *__restrict__ coef0,
+                                            const double *__restrict__ start, const int *__restrict__ exps,
+                                            const int *__restrict__ mcut, const DirectSet &set, Stage<NB> &sgw)
 {
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int m = blockIdx.y * 8 + wave;
-    const int r0 = blockIdx.x * 64 + (threadIdx.x & 63);
     if (m > lmax) return;  // whole wave
     const bool live = r0 < rend;
     const bool active = live && m <= mcut[r0];
@@ -501,6 +499,7 @@ __global__ __launch_bounds__(512) void k_legendre_scalar(
         if (live)
             for (int q = 0; q < NB; ++q) {
                 FT *F = (FT *)set.F[q];
+                if (!F) continue;
                 for (int j = 0; j <= J; ++j) {
                     store_c<FT>(F, j * plane + (size_t)r * (lmax + 1) + m, make_double2(0, 0));
                     store_c<FT>(F, j * plane + (size_t)rs * (lmax + 1) + m, make_double2(0, 0));
@@ -523,14 +522,14 @@ __global__ __launch_bounds__(512) void k_legendre_scalar(
 #pragma unroll
         for (int j = 0; j <= J; ++j) accE[q][j] = accO[q][j] = make_double2(0, 0);
     }
-    __shared__ Stage<NB> sgs[8];
-    run_family<J, NB, 0>(m, lmax, c, w, coef0 + base, rr, st, accE, accO, sgs[wave]);
+    run_family<J, NB, 0>(m, lmax, c, w, coef0 + base, rr, st, accE, accO, sgw);
 
     const bool modd = m & 1;
     if (!live) return;
 #pragma unroll
     for (int q = 0; q < NB; ++q) {
         FT *F = (FT *)set.F[q];
+        if (!F) continue;
 #pragma unroll
         for (int j = 0; j <= J; ++j) {
             double2 ev = modd ? accO[q][j] : accE[q][j];  // l + m even
@@ -546,11 +545,31 @@ __global__ __launch_bounds__(512) void k_legendre_scalar(
     }
 }
 
+template <int J, int NB, typename FT>
+__global__ __launch_bounds__(512) void k_legendre_scalar(
+    int lmax, int ntheta, int nrp, int rend, int jtab, const double2 *__restrict__ trig,
+    const double4 *__restrict__ coef0, const double *__restrict__ start, const int *__restrict__ exps,
+    const int *__restrict__ mcut, const DirectSet set)
+{
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    __shared__ Stage<NB> sgs[8];
+    body_scalar<J, NB, FT>(blockIdx.y * 8 + wave, blockIdx.x * 64 + (threadIdx.x & 63), lmax, ntheta, nrp, rend,
+                           jtab, trig, coef0, start, exps, mcut, set, sgs[wave]);
+}
+
 // i * z
 __device__ __forceinline__ double2 mul_i(double2 z) { return make_double2(-z.y, z.x); }
 __device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
 __device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
 __device__ __forceinline__ double2 cscale(double2 a, double s) { return make_double2(a.x * s, a.y * s); }
+
+// Atomic add of a complex value (two independent real adds).
+template <typename FT>
+__device__ __forceinline__ void add_c(FT *F, size_t idx, double2 v)
+{
+    atomicAdd(F + 2 * idx, (FT)v.x);
+    atomicAdd(F + 2 * idx + 1, (FT)v.y);
+}
 
 template <typename FT>
 __device__ __forceinline__ double2 load_c(const FT *F, size_t idx);
@@ -575,17 +594,19 @@ __device__ __forceinline__ double2 load_c<float>(const float *F, size_t idx)
 // and P south: the first family stores its halves of Q and U, the second
 // adds its halves (the lane re-reads its own stores), so no realization's
 // results wait in registers for the other family.
-template <int J, bool HASB, int NB, typename FT>
-__global__ __launch_bounds__(512) void k_legendre_spin(
-    int lmax, int ntheta, int nrp, int rend, int jtab, const double2 *__restrict__ trig,
-    const double4 *__restrict__ coef2, const double *__restrict__ start, const int *__restrict__ exps,
-    const int *__restrict__ mcut, const DirectSet set)
+//
+// SPLIT (the polar caps, where few waves run): the wave runs the one family
+// fam0 and adds its halves of Q and U atomically into rows the caller has
+// zeroed (a sum of two terms: the same in either order).
+template <int J, bool HASB, int NB, typename FT, bool SPLIT>
+__device__ __forceinline__ void body_spin(int m, int r0, int fam0, int lmax, int ntheta, int nrp, int rend, int jtab,
+                                          const double2 *__restrict__ trig, const double4 *__restrict__ coef2,
+                                          const double *__restrict__ start, const int *__restrict__ exps,
+                                          const int *__restrict__ mcut, const DirectSet &set,
+                                          Stage<NB *(HASB ? 2 : 1)> &sgw)
 {
     constexpr int PER = HASB ? 2 : 1;  // right-hand sides per realization
     constexpr int NR = NB * PER;
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int m = blockIdx.y * 8 + wave;
-    const int r0 = blockIdx.x * 64 + (threadIdx.x & 63);
     if (m > lmax) return;  // whole wave
     const bool live = r0 < rend;
     // spin-2 functions stay below the scalar cut plus 2 (|m - s| <= m + 2)
@@ -595,9 +616,10 @@ __global__ __launch_bounds__(512) void k_legendre_spin(
     const int rs = ntheta - 1 - r;
     const size_t on = (size_t)r * (lmax + 1) + m, os = (size_t)rs * (lmax + 1) + m;
     if (!__any(active)) {
-        if (live)
+        if (live && !SPLIT)  // (split: the rows are zero already)
             for (int q = 0; q < NB; ++q) {
                 FT *FQ = (FT *)set.F[q], *FU = (FT *)set.G[q];
+                if (!FQ) continue;
                 for (int j = 0; j <= J; ++j) {
                     store_c<FT>(FQ, j * plane + on, make_double2(0, 0));
                     store_c<FT>(FQ, j * plane + os, make_double2(0, 0));
@@ -613,7 +635,6 @@ __global__ __launch_bounds__(512) void k_legendre_spin(
     const size_t base = (size_t)m * (2 * lmax + 1 - m) / 2;
     const int lmin = m > 2 ? m : 2;
     const bool modd = m & 1;
-    __shared__ Stage<NR> sgs[8];
     const double2 *rr[NR];
 #pragma unroll
     for (int q = 0; q < NB; ++q) {
@@ -623,6 +644,7 @@ __global__ __launch_bounds__(512) void k_legendre_spin(
 
 #pragma unroll
     for (int fam = 0; fam < 2; ++fam) {
+        if (SPLIT && fam != fam0) continue;
         Rec<J> st;
         load_start<J>(st, start, exps, 1 + fam, m, lmax, jtab, nrp, r);
         double2 accE[NR][J + 1], accO[NR][J + 1];
@@ -630,12 +652,13 @@ __global__ __launch_bounds__(512) void k_legendre_spin(
         for (int k = 0; k < NR; ++k)
 #pragma unroll
             for (int j = 0; j <= J; ++j) accE[k][j] = accO[k][j] = make_double2(0, 0);
-        if (fam == 0) run_family<J, NR, 1>(lmin, lmax, c, w, coef2 + base, rr, st, accE, accO, sgs[wave]);
-        else run_family<J, NR, -1>(lmin, lmax, c, w, coef2 + base, rr, st, accE, accO, sgs[wave]);
+        if (fam == 0) run_family<J, NR, 1>(lmin, lmax, c, w, coef2 + base, rr, st, accE, accO, sgw);
+        else run_family<J, NR, -1>(lmin, lmax, c, w, coef2 + base, rr, st, accE, accO, sgw);
         if (!live) continue;
 #pragma unroll
         for (int q = 0; q < NB; ++q) {
             FT *FQ = (FT *)set.F[q], *FU = (FT *)set.G[q];
+            if (!FQ) continue;
 #pragma unroll
             for (int j = 0; j <= J; ++j) {
                 const int kE = q * PER, kB = q * PER + PER - 1;
@@ -662,6 +685,15 @@ __global__ __launch_bounds__(512) void k_legendre_spin(
                 // Q = (P + M)/2,  U = -i (P - M)/2
                 double2 qn = cscale(cadd(Pn, Mn), 0.5), un = cscale(mul_i(csub(Pn, Mn)), -0.5);
                 double2 qs = cscale(cadd(Ps, Ms), 0.5), us = cscale(mul_i(csub(Ps, Ms)), -0.5);
+                if constexpr (SPLIT) {
+                    add_c<FT>(FQ, j * plane + on, qn);
+                    add_c<FT>(FU, j * plane + on, un);
+                    if (rs != r) {
+                        add_c<FT>(FQ, j * plane + os, qs);
+                        add_c<FT>(FU, j * plane + os, us);
+                    }
+                    continue;
+                }
                 if (fam == 1) {
                     qn = cadd(qn, load_c<FT>(FQ, j * plane + on));
                     un = cadd(un, load_c<FT>(FU, j * plane + on));
@@ -679,6 +711,18 @@ __global__ __launch_bounds__(512) void k_legendre_spin(
             }
         }
     }
+}
+
+template <int J, bool HASB, int NB, typename FT>
+__global__ __launch_bounds__(512) void k_legendre_spin(
+    int lmax, int ntheta, int nrp, int rend, int jtab, const double2 *__restrict__ trig,
+    const double4 *__restrict__ coef2, const double *__restrict__ start, const int *__restrict__ exps,
+    const int *__restrict__ mcut, const DirectSet set)
+{
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    __shared__ Stage<NB *(HASB ? 2 : 1)> sgs[8];
+    body_spin<J, HASB, NB, FT, false>(blockIdx.y * 8 + wave, blockIdx.x * 64 + (threadIdx.x & 63), 0, lmax, ntheta,
+                                      nrp, rend, jtab, trig, coef2, start, exps, mcut, set, sgs[wave]);
 }
 
 template <int J>
@@ -726,6 +770,99 @@ constexpr int spin_nb()
     if (!std::is_same<FT, float>::value) return 1;
     if (!HASB) return J == 1 ? 3 : rhs_max(J);
     return (rhs_max(J) - 1) / 2 > 1 ? (rhs_max(J) - 1) / 2 : 1;
+}
+
+// ---- polar caps in one launch ----
+//
+// The caps hold few ring pairs, so a launch per field and realization group
+// leaves most SIMDs idle while each wave walks its l recursion; here every
+// (task, m, ring block) is a wave of one launch: the deflection, T, and the
+// two spin families of Q/U (split across waves, adding into zeroed rows) of
+// every realization group run side by side.
+template <int J, bool HASB>
+constexpr int caps_nrmax()
+{
+    constexpr int a = scalar_nb<1, double>(), b = scalar_nb<J, float>(), c = spin_nb<J, HASB, float>() * (HASB ? 2 : 1);
+    return a > b ? (a > c ? a : c) : (b > c ? b : c);
+}
+
+template <int J, bool HASB>
+__global__ __launch_bounds__(512) void k_legendre_caps(int lmax, int ntheta, int nrp, int rend, int jtab,
+                                                       const double2 *__restrict__ trig,
+                                                       const double4 *__restrict__ coef0,
+                                                       const double4 *__restrict__ coef2,
+                                                       const double *__restrict__ start, const int *__restrict__ exps,
+                                                       const int *__restrict__ mcut, const CapsArgs args)
+{
+    constexpr int NBD = scalar_nb<1, double>(), NBT = scalar_nb<J, float>(), NBS = spin_nb<J, HASB, float>();
+    constexpr int NRM = caps_nrmax<J, HASB>();
+    __shared__ Stage<NRM> sgs[8];
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int m = blockIdx.y * 8 + wave;
+    const int r0 = blockIdx.x * 64 + (threadIdx.x & 63);
+    const int4 t = args.task[blockIdx.z];
+    // members past the task's count repeat its last realization (valid
+    // reads) and store nothing
+    auto member = [&](int q) { return t.y + (q < t.z ? q : t.z - 1); };
+    DirectSet set{};
+    if (t.x == 0) {
+#pragma unroll
+        for (int q = 0; q < NBD; ++q) {
+            set.a[q] = args.P[member(q)];
+            set.F[q] = q < t.z ? args.FP[member(q)] : nullptr;
+        }
+        body_scalar<1, NBD, double>(m, r0, lmax, ntheta, nrp, rend, jtab, trig, coef0, start, exps, mcut, set,
+                                    reinterpret_cast<Stage<NBD> &>(sgs[wave]));
+    } else if (t.x == 1) {
+#pragma unroll
+        for (int q = 0; q < NBT; ++q) {
+            set.a[q] = args.T[member(q)];
+            set.F[q] = q < t.z ? args.FT[member(q)] : nullptr;
+        }
+        body_scalar<J, NBT, float>(m, r0, lmax, ntheta, nrp, rend, jtab, trig, coef0, start, exps, mcut, set,
+                                   reinterpret_cast<Stage<NBT> &>(sgs[wave]));
+    } else {
+#pragma unroll
+        for (int q = 0; q < NBS; ++q) {
+            set.a[q] = args.E[member(q)];
+            set.b[q] = HASB ? args.B[member(q)] : nullptr;
+            set.F[q] = q < t.z ? args.FQ[member(q)] : nullptr;
+            set.G[q] = q < t.z ? args.FU[member(q)] : nullptr;
+        }
+        body_spin<J, HASB, NBS, float, true>(m, r0, t.x - 2, lmax, ntheta, nrp, rend, jtab, trig, coef2, start, exps,
+                                             mcut, set, reinterpret_cast<Stage<NBS *(HASB ? 2 : 1)> &>(sgs[wave]));
+    }
+}
+
+// Zero the cap rows [0, rend) and [ntheta - rend, ntheta) of the J + 1
+// derivative planes of FQ and FU (FP32 complex) of each realization:
+// blockIdx.y = plane * 2 + side, blockIdx.z = realization * 2 + field.
+__global__ void k_zero_cap_rows(const CapsArgs args, int ntheta, int lmax, int rend)
+{
+    const int rr = blockIdx.z >> 1, fld = blockIdx.z & 1;
+    const int plane = blockIdx.y >> 1, side = blockIdx.y & 1;
+    float *F = (float *)(fld ? args.FU[rr] : args.FQ[rr]);
+    const size_t row = (size_t)(lmax + 1) * 2;  // floats per ring row
+    const size_t seg = (size_t)rend * row;
+    float *base = F + (size_t)plane * ntheta * row + (side ? (size_t)(ntheta - rend) * row : 0);
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < seg; i += (size_t)gridDim.x * blockDim.x)
+        base[i] = 0.f;
+}
+
+template <int J, bool HASB>
+hipError_t caps_JH(Plan &p, int rend, const CapsArgs &a, int nreal)
+{
+    if (p.pol && nreal > 0) {
+        hipLaunchKernelGGL(k_zero_cap_rows, dim3(256, 2 * (J + 1), 2 * nreal), dim3(256), 0, p.stream, a, p.ntheta,
+                           p.lmax, rend);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    dim3 grid((rend + 63) / 64, (p.lmax + 1 + 7) / 8, a.ntask);
+    hipLaunchKernelGGL((k_legendre_caps<J, HASB>), grid, dim3(512), 0, p.stream, p.lmax, p.ntheta, p.nrp, rend, p.jtab,
+                       (const double2 *)p.trig.ptr, (const double4 *)p.coef0.ptr, (const double4 *)p.coef2.ptr,
+                       (const double *)p.start.ptr, (const int *)p.exps.ptr, (const int *)p.mcut.ptr, a);
+    return hipGetLastError();
 }
 
 template <int J, typename FT>
@@ -815,6 +952,45 @@ int direct_max(int J, bool spin, bool hasb, bool out64)
     case 8: return direct_max_J<8>(spin, hasb, out64);
     default: return 0;
     }
+}
+
+int caps_nb(int kind, int J, bool hasb)
+{
+#define TL_NB(JJ)                                                                                 \
+    case JJ:                                                                                      \
+        return kind == 0   ? scalar_nb<1, double>()                                               \
+               : kind == 1 ? scalar_nb<JJ, float>()                                               \
+                           : (hasb ? spin_nb<JJ, true, float>() : spin_nb<JJ, false, float>());
+    switch (J) {
+        TL_NB(0)
+        TL_NB(1)
+        TL_NB(2)
+        TL_NB(3)
+        TL_NB(4)
+        TL_NB(5)
+        TL_NB(6)
+    default: return 0;
+    }
+#undef TL_NB
+}
+
+hipError_t launch_legendre_caps(Plan &p, int rend, const CapsArgs &a, int nreal, bool hasb)
+{
+    if (rend <= 0 || a.ntask <= 0) return hipSuccess;
+    if (a.ntask > kCapsMaxTasks) return hipErrorInvalidValue;
+#define TL_CAPS(JJ) \
+    case JJ: return hasb ? caps_JH<JJ, true>(p, rend, a, nreal) : caps_JH<JJ, false>(p, rend, a, nreal);
+    switch (p.order) {
+        TL_CAPS(0)
+        TL_CAPS(1)
+        TL_CAPS(2)
+        TL_CAPS(3)
+        TL_CAPS(4)
+        TL_CAPS(5)
+        TL_CAPS(6)
+    default: return hipErrorInvalidValue;
+    }
+#undef TL_CAPS
 }
 
 hipError_t launch_legendre_scalar_set(Plan &p, int J, int rend, const DirectSet &set, bool out64)

@@ -14,6 +14,8 @@
 // Positions, residuals and the rotation angle are FP64; the sum uses R (FP32 or
 // FP64).  Neighbouring lanes gather neighbouring source pixels, so the gathers
 // from each derivative map are mostly coalesced.
+#include <hip/hip_fp16.h>
+
 #include "geom.h"
 #include "tl_internal.h"
 
@@ -21,16 +23,16 @@ namespace tl {
 
 namespace {
 
-template <typename R, int N, bool POL>
+template <typename R, int N, bool POL, bool MIX>
 __global__ __launch_bounds__(256) void k_remap(int ntheta, int nphi, const double *__restrict__ theta,
                                                const double2 *__restrict__ trig, const double2 *__restrict__ phitrig,
                                                const double *__restrict__ phival, const R *__restrict__ D,
+                                               const __half *__restrict__ D16, size_t ds, size_t ds16,
                                                const double *__restrict__ at, const double *__restrict__ ap,
                                                const double *__restrict__ thsrc, const double *__restrict__ phsrc,
                                                int rotate, int naive, const float *__restrict__ corr,
                                                R *__restrict__ To, R *__restrict__ Qo, R *__restrict__ Uo)
 {
-    constexpr int ND = (N + 1) * (N + 2) / 2;
     const int i = blockIdx.y;
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= nphi) return;
@@ -49,14 +51,23 @@ __global__ __launch_bounds__(256) void k_remap(int ntheta, int nphi, const doubl
     R res[POL ? 3 : 1];
 #pragma unroll
     for (int f = 0; f < (POL ? 3 : 1); ++f) {
-        const R *Df = D + (size_t)f * ND * plane + pix0;
+        // Horner in v then u over the maps at pix0: the plain layout
+        // [field][ND][ds], or (MIX) FP32 maps of j + k < kMix16 then FP16 maps
+        constexpr int ND = (N + 1) * (N + 2) / 2;
+        const R *Df = D + (size_t)f * (MIX ? mix_n32() : ND) * ds + pix0;
+        const __half *Hf = D16 + (MIX ? (size_t)f * (ND - mix_n32()) * ds16 + pix0 : 0);
         R acc = 0;
 #pragma unroll
         for (int j = N; j >= 0; --j) {
             const int base = j * (N + 1) - j * (j - 1) / 2;  // index of (j, 0)
             R inner = 0;
 #pragma unroll
-            for (int kk = N - j; kk >= 0; --kk) inner = inner * v + Df[(size_t)(base + kk) * plane];
+            for (int kk = N - j; kk >= 0; --kk) {
+                R d;
+                if (MIX && j + kk >= kMix16) d = (R)__half2float(Hf[(size_t)mix_idx16(N, j, kk) * ds16]);
+                else d = Df[(size_t)(MIX ? mix_idx32(j, kk) : base + kk) * ds];
+                inner = inner * v + d;
+            }
             acc = acc * u + inner;
         }
         res[f] = acc;
@@ -79,15 +90,16 @@ __global__ __launch_bounds__(256) void k_remap(int ntheta, int nphi, const doubl
 // the Taylor series about x0' in u = (theta' - theta0') / delta,
 // v = (phi' - phi0') / delta (wrapped to (-pi, pi]), delta = pi / (4 nside),
 // the scale of the derivative maps; then the rotation R.
-template <typename R, int N, bool POL>
+template <typename R, int N, bool POL, bool MIX>
 __global__ __launch_bounds__(256) void k_remap_hpx(int nside, const double *__restrict__ theta,
                                                    const double2 *__restrict__ trig, const HRing *__restrict__ hring,
-                                                   size_t npix, const R *__restrict__ D, const double *__restrict__ at,
+                                                   size_t npix, const R *__restrict__ D,
+                                                   const __half *__restrict__ D16, size_t ds, size_t ds16,
+                                                   const double *__restrict__ at,
                                                    const double *__restrict__ ap, const double *__restrict__ thsrc,
                                                    const double *__restrict__ phsrc, int rotate, int naive,
                                                    R *__restrict__ To, R *__restrict__ Qo, R *__restrict__ Uo)
 {
-    constexpr int ND = (N + 1) * (N + 2) / 2;
     const double TWO_PI = 6.283185307179586476925286766559;
     const int r = blockIdx.y;
     const HRing hr = hring[r];
@@ -120,14 +132,23 @@ __global__ __launch_bounds__(256) void k_remap_hpx(int nside, const double *__re
     R res[POL ? 3 : 1];
 #pragma unroll
     for (int f = 0; f < (POL ? 3 : 1); ++f) {
-        const R *Df = D + (size_t)f * ND * npix + pix0;
+        // Horner in v then u over the maps at pix0: the plain layout
+        // [field][ND][ds], or (MIX) FP32 maps of j + k < kMix16 then FP16 maps
+        constexpr int ND = (N + 1) * (N + 2) / 2;
+        const R *Df = D + (size_t)f * (MIX ? mix_n32() : ND) * ds + pix0;
+        const __half *Hf = D16 + (MIX ? (size_t)f * (ND - mix_n32()) * ds16 + pix0 : 0);
         R acc = 0;
 #pragma unroll
         for (int j = N; j >= 0; --j) {
-            const int base = j * (N + 1) - j * (j - 1) / 2;
+            const int base = j * (N + 1) - j * (j - 1) / 2;  // index of (j, 0)
             R inner = 0;
 #pragma unroll
-            for (int kk = N - j; kk >= 0; --kk) inner = inner * v + Df[(size_t)(base + kk) * npix];
+            for (int kk = N - j; kk >= 0; --kk) {
+                R d;
+                if (MIX && j + kk >= kMix16) d = (R)__half2float(Hf[(size_t)mix_idx16(N, j, kk) * ds16]);
+                else d = Df[(size_t)(MIX ? mix_idx32(j, kk) : base + kk) * ds];
+                inner = inner * v + d;
+            }
             acc = acc * u + inner;
         }
         res[f] = acc;
@@ -140,34 +161,52 @@ __global__ __launch_bounds__(256) void k_remap_hpx(int nside, const double *__re
     }
 }
 
+template <typename R, int N, bool MIX>
+hipError_t remap_NM(Plan &p, const void *D, const double *at, const double *ap, const double *ths,
+                    const double *phs, const float *corr, void *T, void *Q, void *U)
+{
+    dim3 grid((p.nphi + 255) / 256, p.ntheta);
+    const __half *D16 = MIX ? (const __half *)p.d16() : nullptr;
+    // the plan's own maps have padded planes; a caller's are [field][map][pixel]
+    const bool own = D == p.D.ptr;
+    const size_t ds = own ? p.dstride : p.npix(), ds16 = p.dstride16;
+    if (p.nside) {
+        if (corr) return hipErrorInvalidValue;
+        if (p.pol)
+            hipLaunchKernelGGL((k_remap_hpx<R, N, true, MIX>), grid, dim3(256), 0, p.stream, p.nside,
+                               (const double *)p.theta.ptr, (const double2 *)p.trig.ptr, (const HRing *)p.hring.ptr,
+                               p.npix(), (const R *)D, D16, ds, ds16, at, ap, ths, phs, p.rotate, p.naive, (R *)T, (R *)Q,
+                               (R *)U);
+        else
+            hipLaunchKernelGGL((k_remap_hpx<R, N, false, MIX>), grid, dim3(256), 0, p.stream, p.nside,
+                               (const double *)p.theta.ptr, (const double2 *)p.trig.ptr, (const HRing *)p.hring.ptr,
+                               p.npix(), (const R *)D, D16, ds, ds16, at, ap, ths, phs, p.rotate, p.naive, (R *)T, (R *)Q,
+                               (R *)U);
+        return hipGetLastError();
+    }
+    if (p.pol)
+        hipLaunchKernelGGL((k_remap<R, N, true, MIX>), grid, dim3(256), 0, p.stream, p.ntheta, p.nphi,
+                           (const double *)p.theta.ptr, (const double2 *)p.trig.ptr,
+                           (const double2 *)p.phitab.ptr, (const double *)p.phival.ptr, (const R *)D, D16, ds, ds16, at, ap,
+                           ths, phs, p.rotate, p.naive, corr, (R *)T, (R *)Q, (R *)U);
+    else
+        hipLaunchKernelGGL((k_remap<R, N, false, MIX>), grid, dim3(256), 0, p.stream, p.ntheta, p.nphi,
+                           (const double *)p.theta.ptr, (const double2 *)p.trig.ptr,
+                           (const double2 *)p.phitab.ptr, (const double *)p.phival.ptr, (const R *)D, D16, ds, ds16, at, ap,
+                           ths, phs, p.rotate, p.naive, corr, (R *)T, (R *)Q, (R *)U);
+    return hipGetLastError();
+}
+
+// The plan's own maps are mixed precision when mix16 (orders >= 3 of the
+// FP32 forms); maps elsewhere are plain.
 template <typename R, int N>
 hipError_t remap_N(Plan &p, const void *D, const double *at, const double *ap, const double *ths,
                    const double *phs, const float *corr, void *T, void *Q, void *U)
 {
-    dim3 grid((p.nphi + 255) / 256, p.ntheta);
-    if (p.nside) {
-        if (corr) return hipErrorInvalidValue;
-        if (p.pol)
-            hipLaunchKernelGGL((k_remap_hpx<R, N, true>), grid, dim3(256), 0, p.stream, p.nside,
-                               (const double *)p.theta.ptr, (const double2 *)p.trig.ptr, (const HRing *)p.hring.ptr,
-                               p.npix(), (const R *)D, at, ap, ths, phs, p.rotate, p.naive, (R *)T, (R *)Q, (R *)U);
-        else
-            hipLaunchKernelGGL((k_remap_hpx<R, N, false>), grid, dim3(256), 0, p.stream, p.nside,
-                               (const double *)p.theta.ptr, (const double2 *)p.trig.ptr, (const HRing *)p.hring.ptr,
-                               p.npix(), (const R *)D, at, ap, ths, phs, p.rotate, p.naive, (R *)T, (R *)Q, (R *)U);
-        return hipGetLastError();
+    if constexpr (N >= kMix16 && sizeof(R) == 4) {
+        if (p.mix16 && D == p.D.ptr) return remap_NM<R, N, true>(p, D, at, ap, ths, phs, corr, T, Q, U);
     }
-    if (p.pol)
-        hipLaunchKernelGGL((k_remap<R, N, true>), grid, dim3(256), 0, p.stream, p.ntheta, p.nphi,
-                           (const double *)p.theta.ptr, (const double2 *)p.trig.ptr,
-                           (const double2 *)p.phitab.ptr, (const double *)p.phival.ptr, (const R *)D, at, ap,
-                           ths, phs, p.rotate, p.naive, corr, (R *)T, (R *)Q, (R *)U);
-    else
-        hipLaunchKernelGGL((k_remap<R, N, false>), grid, dim3(256), 0, p.stream, p.ntheta, p.nphi,
-                           (const double *)p.theta.ptr, (const double2 *)p.trig.ptr,
-                           (const double2 *)p.phitab.ptr, (const double *)p.phival.ptr, (const R *)D, at, ap,
-                           ths, phs, p.rotate, p.naive, corr, (R *)T, (R *)Q, (R *)U);
-    return hipGetLastError();
+    return remap_NM<R, N, false>(p, D, at, ap, ths, phs, corr, T, Q, U);
 }
 
 template <typename R>

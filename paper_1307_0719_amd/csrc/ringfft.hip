@@ -14,6 +14,8 @@
 // the length-M inverse DFT z = IDFT_M(Z) gives out[2n] = Re z_n, out[2n+1] = Im z_n.
 // The length-M transform is a Stockham autosort FFT in LDS (ping-pong
 // buffers, radices 8, 4, 2, 5, 3), twiddles from a table e^{2 pi i t/N}.
+#include <hip/hip_fp16.h>
+
 #include "tl_internal.h"
 
 namespace tl {
@@ -49,6 +51,26 @@ template <typename V>
 __device__ __forceinline__ V cmuli(V a) { return cmk<V>(-a.y, a.x); }   // i a
 template <typename V>
 __device__ __forceinline__ V cconj(V a) { return cmk<V>(a.x, -a.y); }
+
+// Store of one complex output: as it is, or rounded to FP16 (the mixed maps).
+template <typename V>
+__device__ __forceinline__ void put(V *o, size_t i, V v) { o[i] = v; }
+template <typename V>
+__device__ __forceinline__ void put(__half2 *o, size_t i, V v) { o[i] = __floats2half2_rn((float)v.x, (float)v.y); }
+
+// Output q of a job: FP32/FP64 ring in Dbase, or (bit q of h16, FP32 kernels)
+// an FP16 ring in D16.
+template <typename R, typename F>
+__device__ __forceinline__ void with_out(const FftJob &job, int q, R *Dbase, __half *D16, F &&f)
+{
+    if constexpr (sizeof(R) == 4) {
+        if ((job.h16 >> q) & 1) {
+            f(reinterpret_cast<__half2 *>(D16 + job.dst[q]));
+            return;
+        }
+    }
+    f(reinterpret_cast<typename C2<R>::T *>(Dbase + job.dst[q]));
+}
 
 // In-register inverse DFT of size r (sign +): y_s = sum_q v_q e^{+2 pi i q s / r}.
 template <typename V>
@@ -162,7 +184,7 @@ struct Radices {
 template <typename R>
 __global__ __launch_bounds__(256) void k_ring_fft(const FftJob *__restrict__ jobs,
                                                   const typename C2<R>::T *__restrict__ Fbase,
-                                                  R *__restrict__ Dbase, int lmax, int M,
+                                                  R *__restrict__ Dbase, __half *__restrict__ D16, int lmax, int M,
                                                   const typename C2<R>::T *__restrict__ twN, Radices rad)
 {
     using V = typename C2<R>::T;
@@ -225,8 +247,9 @@ __global__ __launch_bounds__(256) void k_ring_fft(const FftJob *__restrict__ job
             dst = t;
             Ns *= r;
         }
-        R *out = Dbase + job.dst[q];
-        for (int n = tid; n < M; n += T) reinterpret_cast<V *>(out)[n] = src[n];
+        with_out<R>(job, q, Dbase, D16, [&](auto *out) {
+            for (int n = tid; n < M; n += T) put(out, n, src[n]);
+        });
         __syncthreads();
     }
 }
@@ -271,7 +294,7 @@ __device__ __forceinline__ void stockham_any(const V *__restrict__ src, V *__res
 template <typename R>
 __global__ __launch_bounds__(256) void k_ring_fft_hpx(const FftJob *__restrict__ jobs,
                                                       const typename C2<R>::T *__restrict__ Fbase,
-                                                      R *__restrict__ Dbase, int lmax,
+                                                      R *__restrict__ Dbase, __half *__restrict__ D16, int lmax,
                                                       const HRing *__restrict__ hring,
                                                       const typename C2<R>::T *__restrict__ twAll)
 {
@@ -366,8 +389,9 @@ __global__ __launch_bounds__(256) void k_ring_fft_hpx(const FftJob *__restrict__
             dst = t2;
             Ns *= r;
         }
-        R *out = Dbase + job.dst[q];
-        for (int n = tid; n < M; n += T) reinterpret_cast<V *>(out)[n] = src[n];
+        with_out<R>(job, q, Dbase, D16, [&](auto *out) {
+            for (int n = tid; n < M; n += T) put(out, n, src[n]);
+        });
         __syncthreads();
     }
 }
@@ -466,8 +490,8 @@ __device__ __forceinline__ void apply_twiddles(V (&v)[RX], const V *__restrict__
 // padded LDS buffer: butterfly b, kk = b mod Ns reads buf[b + s M/RX], applies
 // e^{2 pi i kk s/(Ns RX)}, transforms, and writes position
 // (b / Ns) Ns RX + kk + s Ns -- into buf, or into the output ring.
-template <int M, int RX, int Ns, bool TO_GLOBAL, typename V>
-__device__ __forceinline__ void pass_p2(V *__restrict__ buf, V *__restrict__ out, int tid,
+template <int M, int RX, int Ns, bool TO_GLOBAL, typename V, typename O>
+__device__ __forceinline__ void pass_p2(V *__restrict__ buf, O *__restrict__ out, int tid,
                                         const V *__restrict__ twN)
 {
     constexpr int nb = M / RX;
@@ -487,7 +511,7 @@ __device__ __forceinline__ void pass_p2(V *__restrict__ buf, V *__restrict__ out
         const int base = (b / Ns) * Ns * RX + kk;
 #pragma unroll
         for (int s = 0; s < RX; ++s) {
-            if constexpr (TO_GLOBAL) out[base + s * Ns] = v[s];
+            if constexpr (TO_GLOBAL) put(out, base + s * Ns, v[s]);
             else buf[lpad(base + s * Ns)] = v[s];
         }
     }
@@ -564,7 +588,7 @@ __device__ __forceinline__ void build_z(V *__restrict__ buf, const V (&f)[M / 25
 // (its re-reads, once per output, cost more than the lost occupancy).
 template <typename R, int M>
 __global__ __launch_bounds__(256, 2) void k_ring_fft_p2(
-    const FftJob *__restrict__ jobs, const typename C2<R>::T *__restrict__ Fbase, R *__restrict__ Dbase, int lmax,
+    const FftJob *__restrict__ jobs, const typename C2<R>::T *__restrict__ Fbase, R *__restrict__ Dbase, __half *__restrict__ D16, int lmax,
     const typename C2<R>::T *__restrict__ twN)
 {
     using V = typename C2<R>::T;
@@ -602,7 +626,7 @@ __global__ __launch_bounds__(256, 2) void k_ring_fft_p2(
         pass_p2<M, 16, 16, false>(buf, (V *)nullptr, tid, twN);
         __syncthreads();
         // last pass straight to the output ring: out[2n], out[2n+1] = Re, Im z_n
-        pass_p2<M, RL, 256, true>(buf, reinterpret_cast<V *>(Dbase + job.dst[q]), tid, twN);
+        with_out<R>(job, q, Dbase, D16, [&](auto *out) { pass_p2<M, RL, 256, true>(buf, out, tid, twN); });
         __syncthreads();
     }
 }
@@ -677,7 +701,7 @@ __device__ __forceinline__ void build_z_h(V *__restrict__ buf, const V (&f)[M / 
 
 template <typename R, int M>
 __global__ __launch_bounds__(256, 2) void k_ring_fft_hpx_p2(
-    const FftJob *__restrict__ jobs, const typename C2<R>::T *__restrict__ Fbase, R *__restrict__ Dbase, int lmax,
+    const FftJob *__restrict__ jobs, const typename C2<R>::T *__restrict__ Fbase, R *__restrict__ Dbase, __half *__restrict__ D16, int lmax,
     const HRing *__restrict__ hring, const typename C2<R>::T *__restrict__ twAll)
 {
     using V = typename C2<R>::T;
@@ -734,7 +758,7 @@ __global__ __launch_bounds__(256, 2) void k_ring_fft_hpx_p2(
         __syncthreads();
         pass_p2<M, 16, 16, false>(buf, (V *)nullptr, tid, twN);
         __syncthreads();
-        pass_p2<M, RL, 256, true>(buf, reinterpret_cast<V *>(Dbase + job.dst[q]), tid, twN);
+        with_out<R>(job, q, Dbase, D16, [&](auto *out) { pass_p2<M, RL, 256, true>(buf, out, tid, twN); });
         __syncthreads();
     }
 }
@@ -854,7 +878,7 @@ __global__ __launch_bounds__(blue_threads<P>()) void k_bluestein_table(const int
 template <typename R, int P>
 __global__ __launch_bounds__(blue_threads<P>()) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 4 : 1)))
 void k_ring_fft_blue(
-    const FftJob *__restrict__ jobs, const typename C2<R>::T *__restrict__ Fbase, R *__restrict__ Dbase, int lmax,
+    const FftJob *__restrict__ jobs, const typename C2<R>::T *__restrict__ Fbase, R *__restrict__ Dbase, __half *__restrict__ D16, int lmax,
     const HRing *__restrict__ hring, const typename C2<R>::T *__restrict__ twAll,
     const typename C2<R>::T *__restrict__ twP, const typename C2<R>::T *__restrict__ bhat)
 {
@@ -921,8 +945,9 @@ void k_ring_fft_blue(
         for (int t = tid; t < P; t += T) buf[lpad(t)] = cmul(cconj(buf[lpad(t)]), bh[t]);
         __syncthreads();
         fft_inplace<P, T>(buf, tid, twP);
-        V *out = reinterpret_cast<V *>(Dbase + job.dst[q]);
-        for (int n = tid; n < M; n += T) out[n] = cmul(buf[lpad(n)], twN[(int)(((int64_t)n * n) % N)]);
+        with_out<R>(job, q, Dbase, D16, [&](auto *out) {
+            for (int n = tid; n < M; n += T) put(out, n, cmul(buf[lpad(n)], twN[(int)(((int64_t)n * n) % N)]));
+        });
         __syncthreads();
     }
 }
@@ -1019,24 +1044,24 @@ hipError_t launch_bluestein_tables(Plan &p, const std::vector<int4> &items)
 }
 
 template <typename R, int P>
-void launch_blue(Plan &p, const void *Fbase, void *Dbase, const FftJob *jobs, int n)
+void launch_blue(Plan &p, const void *Fbase, void *Dbase, void *D16, const FftJob *jobs, int n)
 {
     using V = typename C2<R>::T;
     const bool f64 = sizeof(R) == 8;
     hipLaunchKernelGGL((k_ring_fft_blue<R, P>), dim3(n), dim3(blue_threads<P>()), blue_lds<V>(P), p.stream, jobs,
                        (const V *)Fbase,
-                       (R *)Dbase, p.lmax, (const HRing *)p.hring.ptr,
+                       (R *)Dbase, (__half *)D16, p.lmax, (const HRing *)p.hring.ptr,
                        (const V *)(f64 ? p.twid64.ptr : p.twid32.ptr), (const V *)(f64 ? p.twP64.ptr : p.twP32.ptr),
                        (const V *)(f64 ? p.bhat64.ptr : p.bhat32.ptr));
 }
 
 template <typename R, int M>
-void launch_hpx_p2(Plan &p, const void *Fbase, void *Dbase, const FftJob *jobs, int n)
+void launch_hpx_p2(Plan &p, const void *Fbase, void *Dbase, void *D16, const FftJob *jobs, int n)
 {
     using V = typename C2<R>::T;
     const bool f64 = sizeof(R) == 8;
     hipLaunchKernelGGL((k_ring_fft_hpx_p2<R, M>), dim3(n), dim3(256), (size_t)(M + M / 32) * sizeof(V), p.stream, jobs,
-                       (const V *)Fbase, (R *)Dbase, p.lmax, (const HRing *)p.hring.ptr,
+                       (const V *)Fbase, (R *)Dbase, (__half *)D16, p.lmax, (const HRing *)p.hring.ptr,
                        (const V *)(f64 ? p.twid64.ptr : p.twid32.ptr));
 }
 
@@ -1053,7 +1078,7 @@ hipError_t hpx_p2_attr()
 // The job classes of one HEALPix list: mixed radix, Bluestein by P, then the
 // power-of-two rings.
 template <typename R>
-hipError_t launch_hpx(Plan &p, const void *Fbase, void *Dbase, const FftJob *jobs, int njobs, int list)
+hipError_t launch_hpx(Plan &p, const void *Fbase, void *Dbase, void *D16, const FftJob *jobs, int njobs, int list)
 {
     using V = typename C2<R>::T;
     const int *cnt = p.hjobs[list];
@@ -1061,7 +1086,7 @@ hipError_t launch_hpx(Plan &p, const void *Fbase, void *Dbase, const FftJob *job
     if (cnt[0] > 0) {
         const size_t M = (size_t)p.hmax_direct;
         hipLaunchKernelGGL(k_ring_fft_hpx<R>, dim3(cnt[0]), dim3(256), (2 * M + 1) * sizeof(V), p.stream, jobs,
-                           (const V *)Fbase, (R *)Dbase, p.lmax, (const HRing *)p.hring.ptr,
+                           (const V *)Fbase, (R *)Dbase, (__half *)D16, p.lmax, (const HRing *)p.hring.ptr,
                            (const V *)(sizeof(R) == 8 ? p.twid64.ptr : p.twid32.ptr));
         a = cnt[0];
     }
@@ -1070,22 +1095,22 @@ hipError_t launch_hpx(Plan &p, const void *Fbase, void *Dbase, const FftJob *job
         if (n <= 0) continue;
         if (c == kHpxPow2) {
             switch (p.hmax_pow2) {
-            case 512: launch_hpx_p2<R, 512>(p, Fbase, Dbase, jobs + a, n); break;
-            case 1024: launch_hpx_p2<R, 1024>(p, Fbase, Dbase, jobs + a, n); break;
-            case 2048: launch_hpx_p2<R, 2048>(p, Fbase, Dbase, jobs + a, n); break;
-            case 4096: launch_hpx_p2<R, 4096>(p, Fbase, Dbase, jobs + a, n); break;
+            case 512: launch_hpx_p2<R, 512>(p, Fbase, Dbase, D16, jobs + a, n); break;
+            case 1024: launch_hpx_p2<R, 1024>(p, Fbase, Dbase, D16, jobs + a, n); break;
+            case 2048: launch_hpx_p2<R, 2048>(p, Fbase, Dbase, D16, jobs + a, n); break;
+            case 4096: launch_hpx_p2<R, 4096>(p, Fbase, Dbase, D16, jobs + a, n); break;
             default: return hipErrorInvalidValue;
             }
             a += n;
             continue;
         }
         switch (c) {
-        case 1: launch_blue<R, 256>(p, Fbase, Dbase, jobs + a, n); break;
-        case 2: launch_blue<R, 512>(p, Fbase, Dbase, jobs + a, n); break;
-        case 3: launch_blue<R, 1024>(p, Fbase, Dbase, jobs + a, n); break;
-        case 4: launch_blue<R, 2048>(p, Fbase, Dbase, jobs + a, n); break;
-        case 5: launch_blue<R, 4096>(p, Fbase, Dbase, jobs + a, n); break;
-        default: launch_blue<R, 8192>(p, Fbase, Dbase, jobs + a, n); break;
+        case 1: launch_blue<R, 256>(p, Fbase, Dbase, D16, jobs + a, n); break;
+        case 2: launch_blue<R, 512>(p, Fbase, Dbase, D16, jobs + a, n); break;
+        case 3: launch_blue<R, 1024>(p, Fbase, Dbase, D16, jobs + a, n); break;
+        case 4: launch_blue<R, 2048>(p, Fbase, Dbase, D16, jobs + a, n); break;
+        case 5: launch_blue<R, 4096>(p, Fbase, Dbase, D16, jobs + a, n); break;
+        default: launch_blue<R, 8192>(p, Fbase, Dbase, D16, jobs + a, n); break;
         }
         a += n;
     }
@@ -1136,23 +1161,23 @@ hipError_t fft_prepare(Plan &p)
 }
 
 template <typename R, int M>
-hipError_t launch_p2(Plan &p, const void *Fbase, void *Dbase, const FftJob *jobs, int njobs, const void *tw)
+hipError_t launch_p2(Plan &p, const void *Fbase, void *Dbase, void *D16, const FftJob *jobs, int njobs, const void *tw)
 {
     using V = typename C2<R>::T;
     const size_t shm = (size_t)(M + M / 32) * sizeof(V);
     hipLaunchKernelGGL((k_ring_fft_p2<R, M>), dim3(njobs), dim3(256), shm, p.stream, jobs, (const V *)Fbase,
-                       (R *)Dbase, p.lmax, (const V *)tw);
+                       (R *)Dbase, (__half *)D16, p.lmax, (const V *)tw);
     return hipGetLastError();
 }
 
 template <typename R>
-hipError_t launch_p2_R(Plan &p, const void *Fbase, void *Dbase, const FftJob *jobs, int njobs, const void *tw, int M)
+hipError_t launch_p2_R(Plan &p, const void *Fbase, void *Dbase, void *D16, const FftJob *jobs, int njobs, const void *tw, int M)
 {
     switch (M) {
-    case 512: return launch_p2<R, 512>(p, Fbase, Dbase, jobs, njobs, tw);
-    case 1024: return launch_p2<R, 1024>(p, Fbase, Dbase, jobs, njobs, tw);
-    case 2048: return launch_p2<R, 2048>(p, Fbase, Dbase, jobs, njobs, tw);
-    case 4096: return launch_p2<R, 4096>(p, Fbase, Dbase, jobs, njobs, tw);
+    case 512: return launch_p2<R, 512>(p, Fbase, Dbase, D16, jobs, njobs, tw);
+    case 1024: return launch_p2<R, 1024>(p, Fbase, Dbase, D16, jobs, njobs, tw);
+    case 2048: return launch_p2<R, 2048>(p, Fbase, Dbase, D16, jobs, njobs, tw);
+    case 4096: return launch_p2<R, 4096>(p, Fbase, Dbase, D16, jobs, njobs, tw);
     default: return hipErrorInvalidValue;
     }
 }
@@ -1160,18 +1185,18 @@ hipError_t launch_p2_R(Plan &p, const void *Fbase, void *Dbase, const FftJob *jo
 bool fft_p2(int M) { return M == 512 || M == 1024 || M == 2048 || M == 4096; }
 
 hipError_t launch_fft_jobs(Plan &p, const void *Fbase, void *Dbase, const FftJob *jobs, int njobs, bool fp64,
-                           int list)
+                           int list, void *D16)
 {
     if (njobs <= 0) return hipSuccess;
     if (p.nside) {
         if (list < 0 || list > 1) return hipErrorInvalidValue;
-        return fp64 ? launch_hpx<double>(p, Fbase, Dbase, jobs, njobs, list)
-                    : launch_hpx<float>(p, Fbase, Dbase, jobs, njobs, list);
+        return fp64 ? launch_hpx<double>(p, Fbase, Dbase, D16, jobs, njobs, list)
+                    : launch_hpx<float>(p, Fbase, Dbase, D16, jobs, njobs, list);
     }
     const int M = p.nphi / 2;
     if (fft_p2(M)) {
-        if (fp64) return launch_p2_R<double>(p, Fbase, Dbase, jobs, njobs, p.twid64.ptr, M);
-        return launch_p2_R<float>(p, Fbase, Dbase, jobs, njobs, p.twid32.ptr, M);
+        if (fp64) return launch_p2_R<double>(p, Fbase, Dbase, D16, jobs, njobs, p.twid64.ptr, M);
+        return launch_p2_R<float>(p, Fbase, Dbase, D16, jobs, njobs, p.twid32.ptr, M);
     }
     Radices rad;
     rad.n = p.nradix;
@@ -1179,12 +1204,12 @@ hipError_t launch_fft_jobs(Plan &p, const void *Fbase, void *Dbase, const FftJob
     if (fp64) {
         size_t shm = 2 * (size_t)M * sizeof(double2);
         hipLaunchKernelGGL(k_ring_fft<double>, dim3(njobs), dim3(256), shm, p.stream, jobs,
-                           (const double2 *)Fbase, (double *)Dbase, p.lmax, M,
+                           (const double2 *)Fbase, (double *)Dbase, (__half *)D16, p.lmax, M,
                            (const double2 *)p.twid64.ptr, rad);
     } else {
         size_t shm = 2 * (size_t)M * sizeof(float2);
         hipLaunchKernelGGL(k_ring_fft<float>, dim3(njobs), dim3(256), shm, p.stream, jobs,
-                           (const float2 *)Fbase, (float *)Dbase, p.lmax, M, (const float2 *)p.twid32.ptr,
+                           (const float2 *)Fbase, (float *)Dbase, (__half *)D16, p.lmax, M, (const float2 *)p.twid32.ptr,
                            rad);
     }
     return hipGetLastError();

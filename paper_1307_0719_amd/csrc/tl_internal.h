@@ -30,12 +30,27 @@ constexpr int kMaxJobK = kMaxOrder + 1;
 struct FftJob {
     int64_t src;                 // element offset (complex) of F_0 of the row
     int32_t nk;                  // number of outputs
-    int32_t pad;
+    int32_t pad;                 // (HEALPix: the ring)
     int32_t k[kMaxJobK];         // phi-derivative order of each output
-    int32_t pad2;
+    int32_t h16;                 // bit q: output q is FP16, dst[q] counts from the FP16 maps
     int64_t dst[kMaxJobK];       // element offset (real) of each output ring
     double scale[kMaxJobK];      // multiplier of each output
 };
+
+// Mixed-precision derivative maps (FP32 forms' internal maps, order >= 3):
+// D_jk with j + k < kMix16 in FP32, [field][6][pixel]; the higher orders,
+// which the remap multiplies by |u|^j |v|^k <= 2^-(j+k), in FP16 after them,
+// [field][ndmap - 6][pixel], both j-major.
+constexpr int kMix16 = 3;
+__host__ __device__ constexpr int mix_n32() { return 6; }
+__host__ __device__ constexpr int mix_idx32(int j, int k) { return j == 0 ? k : (j == 1 ? 3 + k : 5); }
+__host__ __device__ constexpr int mix_kmin16(int j) { return j >= kMix16 ? 0 : kMix16 - j; }
+__host__ __device__ constexpr int mix_idx16(int N, int j, int k)
+{
+    int s = 0;
+    for (int jj = 0; jj < j; ++jj) s += N - jj - mix_kmin16(jj) + 1;
+    return s + k - mix_kmin16(j);
+}
 
 // Realizations handled by one pass of the table GEMM (reduced-precision forms).
 constexpr int kTabMaxBatch = 6;   // realizations per table pass
@@ -133,6 +148,7 @@ struct Plan {
     int hmax_direct = 0;  // largest half length M of the mixed-radix rings
     int hmax_P = 0;       // largest Bluestein length
     int hmax_pow2 = 0;    // half length M of the power-of-two class (0: none)
+    bool caps_defl_done = false;  // the last harmonic stage also ran the deflection's caps
     DevBuf tab;       // lambda / lambda' tables in MFMA operand layout (reduced-precision forms)
     DevBuf moff;      // int64 [lmax+2] offsets (16-byte units) of each m in tab
     DevBuf kstart;    // int [lmax+1][ntile] first non-empty 32-l chunk
@@ -148,7 +164,13 @@ struct Plan {
     DevBuf D;         // real [nfield][ndmap][ntheta][nphi]
     DevBuf jobsDefl;  // FftJob [ntheta * 2]
     DevBuf jobsMain;  // FftJob [nfield * (N+1) * ntheta]
+    DevBuf jobsInt;   // the same jobs into the plan's own maps D (padded planes, mix16)
     int njobsDefl = 0, njobsMain = 0;
+    bool mix16 = false;  // the plan's own maps D are mixed precision
+    // plane strides (elements) of the plan's own maps: the pixel count
+    // rounded up to an odd multiple of 256 bytes, so that the maps a remap
+    // lane gathers at one pixel do not all share their low address bits
+    size_t dstride = 0, dstride16 = 0;
 
     size_t total_bytes = 0;
     // work counts (tl_plan_query)
@@ -164,6 +186,8 @@ struct Plan {
 
     int nfield() const { return pol ? 3 : 1; }
     int ndmap() const { return (order + 1) * (order + 2) / 2; }
+    // FP16 maps of the mixed layout start after the FP32 ones
+    void *d16() const { return (char *)D.ptr + (size_t)nfield() * mix_n32() * dstride * 4; }
     bool fp64() const { return precision == TL_FP64; }
     bool tabform() const { return precision >= TL_BF16X3; }
     size_t npix() const { return nside ? (size_t)12 * nside * nside : (size_t)ntheta * (size_t)nphi; }
@@ -210,8 +234,26 @@ hipError_t launch_legendre_lp(Plan &p, const TabBatch &b, int part);
 // Stage numbers of the per-kernel profile (one kernel per stage).
 enum Stage {
     ST_DEFL_LEG = 0, ST_DEFL_FFT, ST_LEG_T, ST_LEG_QU, ST_LEG_MFMA, ST_TAB_RHS, ST_TAB_GEMM, ST_FFT, ST_REMAP, ST_CNN,
-    ST_TAB_EPI
+    ST_TAB_EPI, ST_CAPS
 };
+
+// Polar caps of the FP32 and tabulated forms in one launch (FP32 rows):
+// task {kind, first realization, count, 0}, kind 0 = deflection (FP64 rows
+// of the potential, J = 1), 1 = T, 2 = spin +2 family of Q/U, 3 = spin -2
+// family; pointers per realization of the pass.
+constexpr int kCapsMaxTasks = 32;
+struct CapsArgs {
+    int ntask;
+    int4 task[kCapsMaxTasks];
+    const double2 *T[kTabMaxBatch], *E[kTabMaxBatch], *B[kTabMaxBatch], *P[kTabMaxBatch];
+    void *FT[kTabMaxBatch], *FQ[kTabMaxBatch], *FU[kTabMaxBatch], *FP[kTabMaxBatch];
+};
+// realizations one task of this kind takes (0: the combined launch does not
+// cover this order)
+int caps_nb(int kind, int J, bool hasb);
+// zeroes the Q/U cap rows of realizations [0, nreal) (spin families add
+// into them), then launches the tasks over ring pairs [0, rend)
+hipError_t launch_legendre_caps(Plan &p, int rend, const CapsArgs &a, int nreal, bool hasb);
 
 // ---- learned remainder correction (cnn.hip) ----
 constexpr int kCnnTrain = 32 * 20 * 9 + 32 + 32 * 32 * 9 + 32 + 3 * 32 + 3;  // trainable parameters
@@ -256,9 +298,10 @@ hipError_t fill_words(void *x, size_t n, uint32_t v, hipStream_t st);
 // list: 0 = the deflection jobs, 1 = the main jobs (HEALPix plans launch each
 // job class of the list on its own)
 hipError_t launch_fft_jobs(Plan &p, const void *Fbase, void *Dbase, const FftJob *jobs, int njobs,
-                           bool fp64, int list);
+                           bool fp64, int list, void *D16 = nullptr);
 // HEALPix: chirp spectra of the Bluestein ring lengths (items {M, class P, boff})
 hipError_t launch_bluestein_tables(Plan &p, const std::vector<int4> &items);
+// D: the plan's own maps (padded, maybe mixed) or a caller's ([field][map][pixel]);
 // corr (optional, FP32 [3][ntheta][nphi]): added to the Taylor sums before the rotation
 hipError_t launch_remap(Plan &p, const void *D, const double *at, const double *ap,
                         const double *thsrc, const double *phsrc, void *T, void *Q, void *U,

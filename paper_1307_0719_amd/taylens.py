@@ -39,13 +39,13 @@ EXPORTS = [
 CNN_NTRAIN = 15139
 CNN_NPARAM = 15142
 STAGES = ["defl_legendre", "defl_fft", "legendre_T", "legendre_QU", "legendre_mfma", "tab_rhs", "legendre_tab",
-          "ring_fft", "remap", "cnn", "tab_epi"]
+          "ring_fft", "remap", "cnn", "tab_epi", "legendre_caps"]
 QUERY_KEYS = {"rpole": 0, "elems": 1, "elems_caps": 2, "tab_chunks": 3, "tab_chunk_bytes": 4, "defl_folded": 5}
 # kernel each stage launches
 STAGE_KERNELS = {"defl_legendre": "k_legendre_scalar", "defl_fft": "k_ring_fft", "legendre_T": "k_legendre_scalar",
                  "legendre_QU": "k_legendre_spin", "legendre_mfma": "k_legendre_mfma", "tab_rhs": "k_tab_rhs",
                  "legendre_tab": "k_legendre_tab", "ring_fft": "k_ring_fft", "remap": "k_remap",
-                 "cnn": "k_cnn_forward", "tab_epi": "k_tab_epi"}
+                 "cnn": "k_cnn_forward", "tab_epi": "k_tab_epi", "legendre_caps": "k_legendre_caps"}
 
 
 class TaylensError(RuntimeError):
@@ -61,7 +61,7 @@ class Grid(ctypes.Structure):
 class Options(ctypes.Structure):
     _fields_ = [("order", ctypes.c_int32), ("precision", ctypes.c_int32), ("pol", ctypes.c_int32),
                 ("rotate", ctypes.c_int32), ("naive_pos", ctypes.c_int32), ("batch", ctypes.c_int32),
-                ("workspace_cap", ctypes.c_int64)]
+                ("workspace_cap", ctypes.c_int64), ("maps16", ctypes.c_int32)]
 
 
 class BatchOptions(ctypes.Structure):
@@ -150,9 +150,10 @@ class Plan:
     def __init__(self, lmax: int, ntheta: int, nphi: int, order: int, precision: str = "fp32",
                  pol: bool = True, rotate: bool = True, naive_pos: bool = False, workspace_cap: int = 0,
                  device: Optional[torch.device] = None, stream: Optional[torch.cuda.Stream] = None,
-                 batch: int = 1, nside: int = 0):
+                 batch: int = 1, nside: int = 0, maps16: bool = False):
         """ntheta x nphi equal-theta grid, or with nside > 0 HEALPix rings
-        (ntheta, nphi ignored; maps are [12 nside^2] in RING order)."""
+        (ntheta, nphi ignored; maps are [12 nside^2] in RING order).  maps16:
+        internal derivative maps of order j + k >= 3 in FP16 (see tl_options)."""
         self.nside = int(nside)
         if self.nside:
             ntheta, nphi = 4 * self.nside - 1, 4 * self.nside
@@ -165,7 +166,7 @@ class Plan:
         if precision not in PRECISIONS:
             raise ValueError(f"unknown precision {precision}")
         opt = Options(order, PRECISIONS[precision], int(pol), int(rotate), int(naive_pos), int(batch),
-                      int(workspace_cap))
+                      int(workspace_cap), int(maps16))
         self.batch = int(batch)
         h = ctypes.c_void_p()
         with torch.cuda.device(self.device):

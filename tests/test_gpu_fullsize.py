@@ -2,8 +2,9 @@
 configurations the benchmark times (marked gpu).
 
 * T+Q/U, lmax 4096 on 4097 x 8192 rings, order 4, the split FP16 form with
-  six realizations per table pass (tl_lens_map_many, seeds 2..7: the
-  benchmark's headline step): every realization against the oracle;
+  six realizations per table pass and FP16 derivative maps of order >= 3
+  (tl_lens_map_many, seeds 2..7: the benchmark's headline step): every
+  realization against the oracle;
 * the same workload in the BF16 split and single BF16 forms;
 * the uneven-lmax batch (persistent launch, graph, autotuner): one
   realization of every lmax, including lmax 3000 on 3001 x 6000 rings (a
@@ -71,11 +72,12 @@ def _to_dev(s, dev):
 @pytest.fixture(scope="module")
 def headline(tl):
     """The benchmark's headline step: split FP16 tables, six realizations of
-    the lmax 4096 workload per table pass."""
+    the lmax 4096 workload per table pass, derivative maps of order >= 3 in
+    FP16."""
     w = skygen.WORKLOADS["TP4096"]
     dev = torch.device("cuda", 0)
     skies = [skygen.make_sky(w.lmax, w.seed + i, pol=True) for i in range(HEADLINE_BATCH)]
-    plan = tl.Plan(w.lmax, w.ntheta, w.nphi, w.order, "fp16x2", pol=True, batch=HEADLINE_BATCH)
+    plan = tl.Plan(w.lmax, w.ntheta, w.nphi, w.order, "fp16x2", pol=True, batch=HEADLINE_BATCH, maps16=True)
     rpole = plan.query("rpole")
     bands = sample_bands(w.ntheta, rpole)
     rings = np.unique(np.concatenate(list(bands.values())))

@@ -22,7 +22,7 @@ from tests.gpu_util import ORACLE_THREADS, need_gpu, rel_rms, smooth_nphi, t2np
 
 pytestmark = pytest.mark.gpu
 
-MAP_TOL = {"bf16x3": 3e-5, "fp16x2": 1e-5, "fp16": 1e-3, "bf16": 1e-2}
+MAP_TOL = {"fp32": 1e-5, "bf16x3": 3e-5, "fp16x2": 1e-5, "fp16": 1e-3, "bf16": 1e-2}
 STAGE_TOL = {"bf16x3": 1.5e-4, "fp16x2": 1e-4, "fp16": 1e-2, "bf16": 5e-2}
 
 
@@ -151,7 +151,9 @@ def test_deflection_fold_policy(tl):
 
 def test_polar_cap_policy(tl):
     """Ring pairs kept on the direct FP64 kernels: sin theta < 0.15 in every
-    form and order but the split FP16 one, sin theta < 0.05 there."""
+    form and order but the split FP16 one, sin theta < 0.05 there; caps of 48
+    ring pairs or more rounded to whole 64-lane waves (down when that gives
+    up at most 1/16 of the cap, else up)."""
     def rpole(prec, order, lmax=160):
         plan = tl.Plan(lmax, lmax + 1, 2 * lmax, order, prec, pol=True)
         r = plan.query("rpole")
@@ -164,8 +166,11 @@ def test_polar_cap_policy(tl):
             assert rpole(prec, order) == 8, (prec, order)
     for order in (2, 4, 6):
         assert rpole("fp16x2", order) == 3, order
-    # lmax 4096 on 4097 rings: sin(pi r / 4096) < 0.05 for r < 66
-    assert rpole("fp16x2", 4, 4096) == 66
+    # lmax 4096 on 4097 rings: sin(pi r / 4096) < 0.05 for r < 66 -> 64;
+    # < 0.15 for r < 197 -> 192; lmax 3000: < 0.15 for r < 144 -> 192
+    assert rpole("fp16x2", 4, 4096) == 64
+    assert rpole("fp16", 4, 4096) == 192
+    assert rpole("fp32", 4, 3000) == 192
 
 
 @pytest.mark.parametrize("precision,batch", [("fp16x2", 3), ("fp16", 2), ("fp16x2", 5)])
@@ -191,3 +196,66 @@ def test_lens_map_many_with_b(tl, oracle, precision, batch):
     print(precision, batch, "with B, map rel RMS", errs)
     for f, e in errs.items():
         assert e < MAP_TOL[precision], (f, e)
+
+
+# ------------------------------------------------ FP16 derivative maps --
+
+def test_maps16_on_a_damped_sky(tl, oracle):
+    """maps16 (D_jk with j + k >= 3 in FP16) on the lmax 2048 workload, whose
+    power falls off well before the band limit: sampled rings at the FP32
+    form's bar, in the FP32 and split FP16 forms, orders 3 and 5."""
+    w = skygen.WORKLOADS["TP2048"]
+    sky = skygen.make_sky(w.lmax, w.seed, pol=True)
+    rings = np.array([0, 2, 40, 700, 1024, 2046])
+    for order in (3, 5):
+        ref = oracle.lens_rings(w.lmax, order, w.ntheta, w.nphi, rings, sky.alm_T, sky.alm_E, sky.alm_B,
+                                sky.alm_phi, nthreads=ORACLE_THREADS)
+        mask = ref["_tie"] > 1e-9
+        for prec in ("fp32", "fp16x2"):
+            plan = tl.Plan(w.lmax, w.ntheta, w.nphi, order, prec, pol=True, maps16=True)
+            got = [t2np(x)[rings] for x in plan.lens_map(sky.alm_T, sky.alm_E, None, sky.alm_phi)]
+            plan.close()
+            for f, g in zip("TQU", got):
+                e = rel_rms(g, ref[f], mask)
+                print("maps16", prec, order, f, f"{e:.2e}")
+                assert e < MAP_TOL[prec], (prec, order, f, e)
+
+
+def test_maps16_with_power_at_the_band_limit(tl, oracle):
+    """The documented limit of maps16: a sky with its power up to the grid's
+    band limit (lmax 128 on 129 x 256 rings, deflection 1.2 pixels RMS) makes
+    the third-order Taylor terms a sizable part of the field, and their FP16
+    rounding shows (the plain form stays at its bar)."""
+    lmax, ntheta, nphi, order = 128, 129, 256, 4
+    spacing = math.pi / (ntheta - 1)
+    sky = skygen.make_sky(lmax, 17, pol=True, rms_arcmin=1.2 * spacing / skygen.ARCMIN)
+    ref = oracle.lens_map(lmax, order, ntheta, nphi, sky.alm_T, sky.alm_E, None, sky.alm_phi,
+                          nthreads=ORACLE_THREADS)
+    mask = ref["_tie"] > 1e-9
+    errs = {}
+    for m16 in (False, True):
+        plan = tl.Plan(lmax, ntheta, nphi, order, "fp32", pol=True, maps16=m16)
+        got = plan.lens_map(sky.alm_T, sky.alm_E, None, sky.alm_phi)
+        errs[m16] = max(rel_rms(t2np(g), ref[f], mask) for f, g in zip("TQU", got))
+        plan.close()
+    print("band-limit sky, worst field rel RMS: plain %.2e, maps16 %.2e" % (errs[False], errs[True]))
+    assert errs[False] < 1e-5
+    assert errs[False] < errs[True] < 1e-3
+
+
+def test_maps16_is_ignored_where_it_does_not_apply(tl):
+    """FP64 plans, orders below 3 and HEALPix plans keep FP32/FP64 maps:
+    maps16 changes nothing there (bit for bit)."""
+    sky = skygen.make_sky(32, 5, pol=True)
+    cases = [dict(lmax=32, ntheta=33, nphi=64, order=4, precision="fp64"),
+             dict(lmax=32, ntheta=33, nphi=64, order=2, precision="fp32"),
+             dict(lmax=32, ntheta=0, nphi=0, order=4, precision="fp32", nside=16)]
+    for c in cases:
+        outs = []
+        for m16 in (False, True):
+            plan = tl.Plan(c["lmax"], c["ntheta"], c["nphi"], c["order"], c["precision"], pol=True,
+                           nside=c.get("nside", 0), maps16=m16)
+            outs.append([x.clone() for x in plan.lens_map(sky.alm_T, sky.alm_E, None, sky.alm_phi)])
+            plan.close()
+        for x, y in zip(*outs):
+            assert torch.equal(x, y), c
