@@ -26,11 +26,21 @@ def test_traffic_summary_parsed_only_for_its_sources(bench, monkeypatch):
     digest, text = _recorded_digest("hbm_traffic_TP4096_order4_fp16x2x6.md")
     row = re.search(r"^\| `k_legendre_tab<[^`]*>` \| \d+ \| [\d.]+ \| [\d.]+ \| ([\d.e+]+) \|$", text, re.M)
     monkeypatch.setattr(bench, "sources_digest", lambda: digest)
-    assert bench.measured_traffic("TP4096", "fp16x2", 6, "k_legendre_tab") == float(row.group(1))
-    assert bench.measured_traffic("TP4096", "fp16x2", 5, "k_legendre_tab") is None  # no summary
-    assert bench.measured_traffic("TP4096", "fp16x2", 6, "k_no_such_kernel") is None
+    assert bench.measured_traffic("TP4096", "fp16x2:6", "k_legendre_tab") == float(row.group(1))
+    assert bench.measured_traffic("TP4096", "fp16x2:5", "k_legendre_tab") is None  # no summary
+    assert bench.measured_traffic("TP4096", "fp16x2:6", "k_no_such_kernel") is None
     monkeypatch.setattr(bench, "sources_digest", lambda: "0" * 64)
-    assert bench.measured_traffic("TP4096", "fp16x2", 6, "k_legendre_tab") is None
+    assert bench.measured_traffic("TP4096", "fp16x2:6", "k_legendre_tab") is None
+
+
+def test_form_names(bench):
+    """Form strings of --forms: precision, realizations per pass, +m16."""
+    assert bench.parse_form("fp16x2:6+m16") == ("fp16x2", 6, True)
+    assert bench.parse_form("fp32") == ("fp32", 1, False)
+    assert bench.form_name(("fp16x2", 6, True)) == "fp16x2:6+m16"
+    assert bench.form_name(("bf16", 1, False)) == "bf16"
+    with pytest.raises(ValueError):
+        bench.parse_form("fp16x2:6+x")
 
 
 def test_mfma_summary_parsed_only_for_its_sources(bench, monkeypatch):
