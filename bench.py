@@ -513,6 +513,9 @@ def main():
     ap.add_argument("--cpu-rings", type=int, default=40, help="output rings in the CPU-oracle sample (five bands)")
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the oracle (no errors, no cpu_baseline)")
     ap.add_argument("--copy-calibration", action="store_true", help="only run a 1 GiB device copy (counter scale)")
+    ap.add_argument("--healpix-only", action="store_true",
+                    help="only the HEALPix leg (nside 2048, lmax 3072, order 2, split FP16, six per pass), "
+                         "without the oracle; one JSON line")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the uneven-lmax batch and the learned-correction measurements")
     args = ap.parse_args()
@@ -523,6 +526,9 @@ def main():
         sys.exit(2)
     if args.copy_calibration:
         copy_calibration(args)
+        return
+    if args.healpix_only:
+        print(json.dumps(bench_healpix(args, False)))
         return
 
     import numpy as np

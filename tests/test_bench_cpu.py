@@ -23,14 +23,14 @@ def _recorded_digest(name):
 
 
 def test_traffic_summary_parsed_only_for_its_sources(bench, monkeypatch):
-    digest, text = _recorded_digest("hbm_traffic_TP4096_order4_fp16x2x6.md")
+    digest, text = _recorded_digest("hbm_traffic_TP4096_order4_fp16x2x6_m16.md")
     row = re.search(r"^\| `k_legendre_tab<[^`]*>` \| \d+ \| [\d.]+ \| [\d.]+ \| ([\d.e+]+) \|$", text, re.M)
     monkeypatch.setattr(bench, "sources_digest", lambda: digest)
-    assert bench.measured_traffic("TP4096", "fp16x2:6", "k_legendre_tab") == float(row.group(1))
+    assert bench.measured_traffic("TP4096", "fp16x2:6+m16", "k_legendre_tab") == float(row.group(1))
     assert bench.measured_traffic("TP4096", "fp16x2:5", "k_legendre_tab") is None  # no summary
-    assert bench.measured_traffic("TP4096", "fp16x2:6", "k_no_such_kernel") is None
+    assert bench.measured_traffic("TP4096", "fp16x2:6+m16", "k_no_such_kernel") is None
     monkeypatch.setattr(bench, "sources_digest", lambda: "0" * 64)
-    assert bench.measured_traffic("TP4096", "fp16x2:6", "k_legendre_tab") is None
+    assert bench.measured_traffic("TP4096", "fp16x2:6+m16", "k_legendre_tab") is None
 
 
 def test_form_names(bench):
@@ -46,11 +46,11 @@ def test_form_names(bench):
 def test_mfma_summary_parsed_only_for_its_sources(bench, monkeypatch):
     digest, text = _recorded_digest("mfma_TP4096_order4.md")
     monkeypatch.setattr(bench, "sources_digest", lambda: digest)
-    for form, kernel in [("fp16x2:6", "k_legendre_tab"), ("fp16:6", "k_legendre_tab"), ("fp32", "k_legendre_mfma")]:
+    for form, kernel in [("fp16x2:6+m16", "k_legendre_tab"), ("fp16:6", "k_legendre_tab"), ("fp32", "k_legendre_mfma")]:
         row = re.search(r"^\| " + re.escape(form) + r" \| `" + kernel + r"<[^`]*>` \| \d+ \| [\d.]+ \| [\d.]+ \| ([\d.]+) \|",
                         text, re.M)
         got = bench.measured_mfma_busy("TP4096", form, kernel)
         assert got == float(row.group(1)) and 0.0 < got <= 100.0
-    assert bench.measured_mfma_busy("TP4096", "fp16x2:6", "k_legendre_mfma") is None
+    assert bench.measured_mfma_busy("TP4096", "fp16x2:6+m16", "k_legendre_mfma") is None
     monkeypatch.setattr(bench, "sources_digest", lambda: "0" * 64)
-    assert bench.measured_mfma_busy("TP4096", "fp16x2:6", "k_legendre_tab") is None
+    assert bench.measured_mfma_busy("TP4096", "fp16x2:6+m16", "k_legendre_tab") is None
