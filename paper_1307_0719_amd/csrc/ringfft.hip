@@ -53,10 +53,21 @@ template <typename V>
 __device__ __forceinline__ V cconj(V a) { return cmk<V>(a.x, -a.y); }
 
 // Store of one complex output: as it is, or rounded to FP16 (the mixed maps).
+// Non-temporal: the maps are written once and read by the next kernel
+// (measured 3 % faster ring FFTs than plain stores; non-temporal loads in the
+// remap were slower).
 template <typename V>
-__device__ __forceinline__ void put(V *o, size_t i, V v) { o[i] = v; }
+__device__ __forceinline__ void put(V *o, size_t i, V v)
+{
+    __builtin_nontemporal_store(v.x, &o[i].x);
+    __builtin_nontemporal_store(v.y, &o[i].y);
+}
 template <typename V>
-__device__ __forceinline__ void put(__half2 *o, size_t i, V v) { o[i] = __floats2half2_rn((float)v.x, (float)v.y); }
+__device__ __forceinline__ void put(__half2 *o, size_t i, V v)
+{
+    const __half2 h = __floats2half2_rn((float)v.x, (float)v.y);
+    __builtin_nontemporal_store(*reinterpret_cast<const unsigned *>(&h), reinterpret_cast<unsigned *>(&o[i]));
+}
 
 // Output q of a job: FP32/FP64 ring in Dbase, or (bit q of h16, FP32 kernels)
 // an FP16 ring in D16.
