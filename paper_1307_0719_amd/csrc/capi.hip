@@ -330,22 +330,29 @@ int validate_options(int32_t lmax, tl_grid grid, const tl_options *opt)
 // The job of field f, theta-derivative row j into the plan's own maps:
 // planes of dstride elements, [field][ndmap][plane]; with mix16, outputs with
 // j + k < kMix16 to the FP32 maps [field][6][plane], the others (bit set in
-// h16) to the FP16 maps [field][ndmap - 6][plane of dstride16] after them.
-// off = the ring's first pixel.
+// h16) to the FP16 maps [field][ndmap - 6][plane of dstride16] after them,
+// single or paired (Plan::paired, bit q of pair).  off = the ring's first
+// pixel.
 FftJob int_job(const Plan &p, FftJob a, int f, int j, int64_t off)
 {
     const int N = p.order, n16 = p.ndmap() - mix_n32();
     const int64_t s32 = (int64_t)p.dstride, s16 = (int64_t)p.dstride16;
     a.h16 = 0;
+    a.pair = 0;
     for (int q = 0; q < a.nk; ++q) {
         const int k = a.k[q];
+        // paired planes: the pair's plane starts at the slot of its first map
+        const int pos = p.paired ? pair_pos(N, p.mix16, j, k) : 0;
+        const int k0 = pos == 2 ? k - 1 : k;
+        const int64_t o = pos ? 2 * off : off;
+        if (pos == 1) a.pair |= 1 << q;
         if (!p.mix16) {
-            a.dst[q] = ((int64_t)f * p.ndmap() + dmap_index(N, j, k)) * s32 + off;
+            a.dst[q] = ((int64_t)f * p.ndmap() + dmap_index(N, j, k0)) * s32 + o;
         } else if (j + k >= kMix16) {
             a.h16 |= 1 << q;
-            a.dst[q] = ((int64_t)f * n16 + mix_idx16(N, j, k)) * s16 + off;
+            a.dst[q] = ((int64_t)f * n16 + mix_idx16(N, j, k0)) * s16 + o;
         } else {
-            a.dst[q] = ((int64_t)f * mix_n32() + mix_idx32(j, k)) * s32 + off;
+            a.dst[q] = ((int64_t)f * mix_n32() + mix_idx32(j, k0)) * s32 + o;
         }
     }
     return a;
@@ -1213,6 +1220,8 @@ void plan_fields(Plan &p, int32_t lmax, tl_grid grid, const tl_options *opt, voi
     // to ~1e-4 for power at the band limit).  Not on HEALPix rings, whose
     // offsets in units of delta reach nside / i on polar ring i.
     p.mix16 = opt->maps16 == 1 && !p.fp64() && p.order >= kMix16 && p.nside == 0;
+    // paired FP16 planes where the ring FFT runs in one workgroup (pow2 rings)
+    p.paired = p.mix16 && grid.nphi % 2 == 0 && fft_p2(grid.nphi / 2);
     {
         auto padded = [](size_t n, size_t q) {
             const size_t b = (n + q - 1) / q;

@@ -23,7 +23,7 @@ namespace tl {
 
 namespace {
 
-template <typename R, int N, bool POL, bool MIX>
+template <typename R, int N, bool POL, bool MIX, bool PAIRED>
 __global__ __launch_bounds__(256) void k_remap(int ntheta, int nphi, const double *__restrict__ theta,
                                                const double2 *__restrict__ trig, const double2 *__restrict__ phitrig,
                                                const double *__restrict__ phival, const R *__restrict__ D,
@@ -61,11 +61,25 @@ __global__ __launch_bounds__(256) void k_remap(int ntheta, int nphi, const doubl
         for (int j = N; j >= 0; --j) {
             const int base = j * (N + 1) - j * (j - 1) / 2;  // index of (j, 0)
             R inner = 0;
+            float2 pr = make_float2(0.f, 0.f);  // a paired plane's two values, read at its second map
 #pragma unroll
             for (int kk = N - j; kk >= 0; --kk) {
                 R d;
-                if (MIX && j + kk >= kMix16) d = (R)__half2float(Hf[(size_t)mix_idx16(N, j, kk) * ds16]);
-                else d = Df[(size_t)(MIX ? mix_idx32(j, kk) : base + kk) * ds];
+                const bool h = MIX && j + kk >= kMix16;
+                const int pos = PAIRED ? pair_pos(N, MIX, j, kk) : 0;
+                const size_t slot = h ? (size_t)mix_idx16(N, j, kk) : (size_t)(MIX ? mix_idx32(j, kk) : base + kk);
+                if (pos == 2) {
+                    // the plane of slot - 1 holds (D_{j,kk-1}, D_{j,kk}) at 2 pix0
+                    if (h) pr = __half22float2(*reinterpret_cast<const __half2 *>(Hf + (slot - 1) * ds16 + pix0));
+                    else pr = *reinterpret_cast<const float2 *>(Df + (slot - 1) * ds + pix0);
+                    d = (R)pr.y;
+                } else if (pos == 1) {
+                    d = (R)pr.x;
+                } else if (h) {
+                    d = (R)__half2float(Hf[slot * ds16]);
+                } else {
+                    d = Df[slot * ds];
+                }
                 inner = inner * v + d;
             }
             acc = acc * u + inner;
@@ -184,17 +198,18 @@ hipError_t remap_NM(Plan &p, const void *D, const double *at, const double *ap, 
                                (R *)U);
         return hipGetLastError();
     }
-    if (p.pol)
-        hipLaunchKernelGGL((k_remap<R, N, true, MIX>), grid, dim3(256), 0, p.stream, p.ntheta, p.nphi,
-                           (const double *)p.theta.ptr, (const double2 *)p.trig.ptr,
-                           (const double2 *)p.phitab.ptr, (const double *)p.phival.ptr, (const R *)D, D16, ds, ds16, at, ap,
-                           ths, phs, p.rotate, p.naive, corr, (R *)T, (R *)Q, (R *)U);
-    else
-        hipLaunchKernelGGL((k_remap<R, N, false, MIX>), grid, dim3(256), 0, p.stream, p.ntheta, p.nphi,
-                           (const double *)p.theta.ptr, (const double2 *)p.trig.ptr,
-                           (const double2 *)p.phitab.ptr, (const double *)p.phival.ptr, (const R *)D, D16, ds, ds16, at, ap,
-                           ths, phs, p.rotate, p.naive, corr, (R *)T, (R *)Q, (R *)U);
-    return hipGetLastError();
+    auto launch = [&](auto kernel) {
+        hipLaunchKernelGGL(kernel, grid, dim3(256), 0, p.stream, p.ntheta, p.nphi, (const double *)p.theta.ptr,
+                           (const double2 *)p.trig.ptr, (const double2 *)p.phitab.ptr, (const double *)p.phival.ptr,
+                           (const R *)D, D16, ds, ds16, at, ap, ths, phs, p.rotate, p.naive, corr, (R *)T, (R *)Q,
+                           (R *)U);
+        return hipGetLastError();
+    };
+    if constexpr (sizeof(R) == 4) {
+        if (own && p.paired)
+            return p.pol ? launch(k_remap<R, N, true, MIX, true>) : launch(k_remap<R, N, false, MIX, true>);
+    }
+    return p.pol ? launch(k_remap<R, N, true, MIX, false>) : launch(k_remap<R, N, false, MIX, false>);
 }
 
 // The plan's own maps are mixed precision when mix16 (orders >= 3 of the

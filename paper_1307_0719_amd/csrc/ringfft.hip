@@ -593,8 +593,35 @@ __device__ __forceinline__ void build_z(V *__restrict__ buf, const V (&f)[M / 25
     }
 }
 
+// The last pass of pass_p2 (Ns = 256, RX = RL) kept in registers: v[s] holds
+// the pair of output pixels tid + 256 s.
+template <int M, typename V>
+__device__ __forceinline__ void last_pass_regs(const V *__restrict__ buf, V (&v)[M / 256], int tid,
+                                               const V *__restrict__ twN)
+{
+    constexpr int RL = M / 256;
+#pragma unroll
+    for (int s = 0; s < RL; ++s) v[s] = buf[lpad(tid + s * 256)];
+    apply_twiddles<RL>(v, twN, tid, 2 * M / (256 * RL));
+    dftR<RL>(v);
+}
+
+// Two FP16 outputs a, b of one job into their paired plane: pixel n of a at
+// 2n, of b at 2n + 1; ha holds a's pixel pair i (rounded to FP16), y is b's.
+// Written once, read by the remap: the stores bypass the caches.
+__device__ __forceinline__ void put_pair(__half *o, size_t i, __half2 ha, float2 y)
+{
+    typedef unsigned u2 __attribute__((ext_vector_type(2)));
+    const __half2 h0 = __halves2half2(__low2half(ha), __float2half_rn(y.x));
+    const __half2 h1 = __halves2half2(__high2half(ha), __float2half_rn(y.y));
+    const u2 w = {*reinterpret_cast<const unsigned *>(&h0), *reinterpret_cast<const unsigned *>(&h1)};
+    __builtin_nontemporal_store(w, reinterpret_cast<u2 *>(o) + i);
+}
+
 // Length M = 256 RL (RL = 2, 4, 8, 16): 256 threads; passes 16, 16, RL.  The
 // spectrum of each output is built by the code for its phi-derivative order.
+// FP32 jobs may pair consecutive FP16 outputs (bit q of job.pair): the first
+// one's last pass waits in LDS, in FP16, until the second one's is done.
 // Two waves per SIMD: the register budget holds an FP32 row for the whole job
 // (its re-reads, once per output, cost more than the lost occupancy).
 template <typename R, int M>
@@ -618,6 +645,8 @@ __global__ __launch_bounds__(256, 2) void k_ring_fft_p2(
     constexpr bool CACHE = sizeof(R) == 4;
     V f[RL], fmid;
     if constexpr (CACHE) load_pairs<M>(f, fmid, F, L, tid);
+    // the first output of a pair, after the FFT buffer (FP32 kernels)
+    __half2 *held = reinterpret_cast<__half2 *>(smem_raw + (size_t)(M + M / 32) * sizeof(V));
     for (int q = 0; q < job.nk; ++q) {
         const R scale = (R)job.scale[q];
         switch (job.k[q]) {  // uniform
@@ -637,7 +666,23 @@ __global__ __launch_bounds__(256, 2) void k_ring_fft_p2(
         pass_p2<M, 16, 16, false>(buf, (V *)nullptr, tid, twN);
         __syncthreads();
         // last pass straight to the output ring: out[2n], out[2n+1] = Re, Im z_n
-        with_out<R>(job, q, Dbase, D16, [&](auto *out) { pass_p2<M, RL, 256, true>(buf, out, tid, twN); });
+        if constexpr (sizeof(R) == 4) {
+            if ((job.pair >> q) & 1) {
+                V v[RL];
+                last_pass_regs<M>(buf, v, tid, twN);
+#pragma unroll
+                for (int s = 0; s < RL; ++s) held[tid + 256 * s] = __floats2half2_rn(v[s].x, v[s].y);
+            } else if (q > 0 && ((job.pair >> (q - 1)) & 1)) {
+                V v[RL];
+                last_pass_regs<M>(buf, v, tid, twN);
+#pragma unroll
+                for (int s = 0; s < RL; ++s) put_pair(D16 + job.dst[q - 1], tid + 256 * s, held[tid + 256 * s], v[s]);
+            } else {
+                with_out<R>(job, q, Dbase, D16, [&](auto *out) { pass_p2<M, RL, 256, true>(buf, out, tid, twN); });
+            }
+        } else {
+            with_out<R>(job, q, Dbase, D16, [&](auto *out) { pass_p2<M, RL, 256, true>(buf, out, tid, twN); });
+        }
         __syncthreads();
     }
 }
@@ -975,11 +1020,18 @@ hipError_t fill_words(void *x, size_t n, uint32_t v, hipStream_t st)
 
 // Allow the ping-pong LDS buffers of this plan's FFT length beyond the
 // default 64 KiB dynamic-LDS limit when the device has more.
+// LDS of the radix-16 kernel: the padded buffer, and for FP32 the FP16
+// first outputs of pairs
+template <typename R>
+constexpr size_t p2_lds(int M)
+{
+    return (size_t)(M + M / 32) * sizeof(typename C2<R>::T) + (sizeof(R) == 4 ? (size_t)M * sizeof(__half2) : 0);
+}
+
 template <typename R, int M>
 hipError_t prep_p2()
 {
-    using V = typename C2<R>::T;
-    const size_t b = (size_t)(M + M / 32) * sizeof(V);
+    const size_t b = p2_lds<R>(M);
     if (b <= 65536) return hipSuccess;
     return hipFuncSetAttribute(reinterpret_cast<const void *>(&k_ring_fft_p2<R, M>),
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)b);
@@ -1175,7 +1227,7 @@ template <typename R, int M>
 hipError_t launch_p2(Plan &p, const void *Fbase, void *Dbase, void *D16, const FftJob *jobs, int njobs, const void *tw)
 {
     using V = typename C2<R>::T;
-    const size_t shm = (size_t)(M + M / 32) * sizeof(V);
+    const size_t shm = p2_lds<R>(M);
     hipLaunchKernelGGL((k_ring_fft_p2<R, M>), dim3(njobs), dim3(256), shm, p.stream, jobs, (const V *)Fbase,
                        (R *)Dbase, (__half *)D16, p.lmax, (const V *)tw);
     return hipGetLastError();

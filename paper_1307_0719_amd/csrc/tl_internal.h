@@ -33,6 +33,8 @@ struct FftJob {
     int32_t pad;                 // (HEALPix: the ring)
     int32_t k[kMaxJobK];         // phi-derivative order of each output
     int32_t h16;                 // bit q: output q is FP16, dst[q] counts from the FP16 maps
+    int32_t pair;                // bit q: outputs q and q + 1 share a paired plane at dst[q]
+                                 // (pixel n of output q at 2n, of output q + 1 at 2n + 1)
     int64_t dst[kMaxJobK];       // element offset (real) of each output ring
     double scale[kMaxJobK];      // multiplier of each output
 };
@@ -50,6 +52,24 @@ __host__ __device__ constexpr int mix_idx16(int N, int j, int k)
     int s = 0;
     for (int jj = 0; jj < j; ++jj) s += N - jj - mix_kmin16(jj) + 1;
     return s + k - mix_kmin16(j);
+}
+
+// Paired planes of the plan's own FP16 maps (mixed layout on equal-theta
+// rings whose FFT runs in one workgroup): along each row j, FP16 maps k and
+// k + 1 share one plane of two values per pixel, taken greedily from the
+// first FP16 map, so a remap lane reads both with one load.  Returns 0 for a
+// map on its own plane, 1 for the first of a pair, 2 for the second.
+__host__ __device__ constexpr bool map_is16(bool mix, int j, int k) { return mix && j + k >= kMix16; }
+__host__ __device__ constexpr int pair_pos(int N, bool mix, int j, int k)
+{
+    int kk = 0;
+    while (kk <= N - j) {
+        const bool pr = kk + 1 <= N - j && map_is16(mix, j, kk) && map_is16(mix, j, kk + 1);
+        if (k == kk) return pr ? 1 : 0;
+        if (pr && k == kk + 1) return 2;
+        kk += pr ? 2 : 1;
+    }
+    return 0;
 }
 
 // Realizations handled by one pass of the table GEMM (reduced-precision forms).
@@ -171,6 +191,9 @@ struct Plan {
     // rounded up to an odd multiple of 256 bytes, so that the maps a remap
     // lane gathers at one pixel do not all share their low address bits
     size_t dstride = 0, dstride16 = 0;
+    // the plan's own FP16 maps use paired planes (pair_pos); slots s and
+    // s + 1 of a pair together hold 2 dstride16 elements
+    bool paired = false;
 
     size_t total_bytes = 0;
     // work counts (tl_plan_query)
@@ -297,6 +320,7 @@ hipError_t launch_legendre_mfma_queue(int order, bool pol, bool hasb, hipStream_
 hipError_t fill_words(void *x, size_t n, uint32_t v, hipStream_t st);
 // list: 0 = the deflection jobs, 1 = the main jobs (HEALPix plans launch each
 // job class of the list on its own)
+bool fft_p2(int M);  // rings of 2 M points take the one-workgroup radix-16 kernel
 hipError_t launch_fft_jobs(Plan &p, const void *Fbase, void *Dbase, const FftJob *jobs, int njobs,
                            bool fp64, int list, void *D16 = nullptr);
 // HEALPix: chirp spectra of the Bluestein ring lengths (items {M, class P, boff})
