@@ -343,14 +343,16 @@ __global__ __launch_bounds__(256) void k_legendre_tab(int lmax, int nrp, int rbe
         // per wave (the loop is bound by memory latency, not by the matrix
         // cores): loads retire in order, so the chunk consumed now must be
         // the oldest one in flight, for both operands.
-        constexpr int PF = SPLIT ? 1 : (NB >= 3 ? 3 : 4);
+        constexpr int PFA = SPLIT ? 2 : (NB >= 3 ? 3 : 4);  // table chunks in flight
+        constexpr int PFB = SPLIT ? 1 : PFA;                 // right-hand-side chunks (from L2)
+        constexpr int PG = PFA;  // PFB divides PFA
         constexpr int AW = NSPL * 4;  // uint4 per lane per chunk
         const int ks = __builtin_amdgcn_readfirstlane(kstart[(size_t)m * ntile + tile]);
         const uint4 *blk = tab + (moff[m] + (int64_t)tile * nk * AW * 64) + lane;
         const int64_t cum = moff[m] / ((int64_t)ntile * NSPL * 256);
         const uint4 *rb = rhs + cum * RCH + lane;
-        uint4 Ab[PF][AW];
-        uint4 Bb[PF][NSPL][NB][2];
+        uint4 Ab[PFA][AW];
+        uint4 Bb[PFB][NSPL][NB][2];
         auto loadA = [&](uint4 (&dst)[AW], int kc) {
             const uint4 *cb = blk + (int64_t)kc * AW * 64;
 #pragma unroll
@@ -368,13 +370,13 @@ __global__ __launch_bounds__(256) void k_legendre_tab(int lmax, int nrp, int rbe
 #pragma unroll
                     for (int p = 0; p < 2; ++p) dst[sp][b][p] = rc[((sp * NB + b) * 2 + p) * 64];
         };
+        // issue order B(k), A(k) for the first chunks, as in the loop
 #pragma unroll
-        for (int u = 0; u < PF; ++u)
-            if (ks + u < nk) {
-                loadA(Ab[u], ks + u);
-                loadB(Bb[u], ks + u);
-            }
-        // one chunk: operands from slot u, refill the slot PF chunks ahead
+        for (int u = 0; u < PFA; ++u) {
+            if (u < PFB && ks + u < nk) loadB(Bb[u], ks + u);
+            if (ks + u < nk) loadA(Ab[u], ks + u);
+        }
+        // one chunk: operands from slot u, refill the slots PFB / PFA chunks ahead
         auto chunk = [&](const uint4 (&Au)[AW], const uint4 (&Bu)[NSPL][NB][2]) {
             V A[NSPL][2][2], Bv[NSPL][NB][2];
 #pragma unroll
@@ -414,22 +416,24 @@ __global__ __launch_bounds__(256) void k_legendre_tab(int lmax, int nrp, int rbe
                     }
             };
         };
-        // whole groups of PF chunks (one back edge), then the tail
+        // whole groups of PG chunks (one back edge), then the tail
         int k0 = ks;
-        for (; k0 + PF <= nk; k0 += PF) {
+        for (; k0 + PG <= nk; k0 += PG) {
 #pragma unroll
-            for (int u = 0; u < PF; ++u) {
-                auto mm = chunk(Ab[u], Bb[u]);
-                if (k0 + u + PF < nk) {
-                    loadA(Ab[u], k0 + u + PF);
-                    loadB(Bb[u], k0 + u + PF);
-                }
+            for (int u = 0; u < PG; ++u) {
+                auto mm = chunk(Ab[u % PFA], Bb[u % PFB]);
+                if (k0 + u + PFB < nk) loadB(Bb[u % PFB], k0 + u + PFB);
+                if (k0 + u + PFA < nk) loadA(Ab[u % PFA], k0 + u + PFA);
                 mm(acc);
             }
         }
 #pragma unroll
-        for (int u = 0; u < PF; ++u)
-            if (k0 + u < nk) chunk(Ab[u], Bb[u])(acc);
+        for (int u = 0; u < PG; ++u)
+            if (k0 + u < nk) {
+                auto mm = chunk(Ab[u % PFA], Bb[u % PFB]);
+                if (k0 + u + PFB < nk) loadB(Bb[u % PFB], k0 + u + PFB);
+                mm(acc);
+            }
     }
 
     if (tile >= ntile) return;
