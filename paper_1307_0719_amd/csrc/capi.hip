@@ -114,8 +114,16 @@ void free_plan_buffers(Plan &p)
 {
     DevBuf *bufs[] = {&p.theta, &p.trig, &p.phitab, &p.phival, &p.twid64, &p.twid32, &p.coef0, &p.coef2,
                       &p.start, &p.exps, &p.mcut, &p.tab, &p.moff, &p.kstart, &p.rhs, &p.colexp, &p.tabsum, &p.Fphi, &p.alpha, &p.F, &p.D, &p.jobsDefl, &p.jobsMain, &p.jobsInt, &p.hring,
-                      &p.twP64, &p.twP32, &p.bhat64, &p.bhat32};
+                      &p.twP64, &p.twP32, &p.bhat64, &p.bhat32, &p.D2, &p.alpha2};
     for (DevBuf *b : bufs) free_buf(*b);
+    if (p.side) (void)hipStreamSynchronize(p.side);
+    for (int i = 0; i < 2; ++i) {
+        if (p.ev_fft[i]) (void)hipEventDestroy(p.ev_fft[i]);
+        if (p.ev_remap[i]) (void)hipEventDestroy(p.ev_remap[i]);
+        p.ev_fft[i] = p.ev_remap[i] = nullptr;
+    }
+    if (p.side) (void)hipStreamDestroy(p.side);
+    p.side = nullptr;
 }
 
 int alloc(Plan &p, DevBuf &b, size_t bytes, const char *name)
@@ -223,11 +231,12 @@ void healpix_rings(int nside, int lmax, std::vector<double> &th, std::vector<HRi
 struct Sizes {
     size_t theta, trig, phitab, phival, twid64, twid32, coef, start, exps, mcut, Fphi, alpha, F, D, jd, jm;
     size_t tab = 0, moff = 0, kstart = 0, rhs = 0, colexp = 0, tabsum = 0, hring = 0;
-    size_t twP64 = 0, twP32 = 0, bhat64 = 0, bhat32 = 0, jx = 0;
+    size_t twP64 = 0, twP32 = 0, bhat64 = 0, bhat32 = 0, jx = 0, D2 = 0, alpha2 = 0;
     size_t total() const
     {
         return theta + trig + phitab + phival + twid64 + twid32 + 2 * coef + start + exps + mcut + Fphi + alpha + F +
-               D + jd + jm + tab + moff + kstart + rhs + colexp + tabsum + hring + twP64 + twP32 + bhat64 + bhat32 + jx;
+               D + jd + jm + tab + moff + kstart + rhs + colexp + tabsum + hring + twP64 + twP32 + bhat64 + bhat32 + jx +
+               D2 + alpha2;
     }
 };
 
@@ -281,6 +290,10 @@ Sizes plan_sizes(const Plan &p)
     }
     s.D = p.mix16 ? (size_t)p.nfield() * (mix_n32() * p.dstride * 4 + (p.ndmap() - mix_n32()) * p.dstride16 * 2)
                   : (size_t)p.nfield() * p.ndmap() * p.dstride * rbytes;
+    if (p.tabform() && p.batch > 1) {  // the second set of maps and deflections
+        s.D2 = s.D;
+        s.alpha2 = s.alpha;
+    }
     s.jd = 2 * (size_t)p.ntheta * sizeof(FftJob);
     s.jm = (size_t)p.nfield() * (p.order + 1) * p.ntheta * sizeof(FftJob);
     s.jx = s.jm;
@@ -488,9 +501,9 @@ int build_jobs(Plan &p)
 // (padded planes, mixed precision when mix16) or a caller's (plain layout).
 hipError_t launch_main_fft(Plan &p, const void *F, void *Dout)
 {
-    if (Dout == p.D.ptr)
+    if (p.own(Dout))
         return launch_fft_jobs(p, F, Dout, (const FftJob *)p.jobsInt.ptr, p.njobsMain, p.fp64(), 1,
-                               p.mix16 ? p.d16() : nullptr);
+                               p.mix16 ? p.d16_of(Dout) : nullptr);
     return launch_fft_jobs(p, F, Dout, (const FftJob *)p.jobsMain.ptr, p.njobsMain, p.fp64(), 1);
 }
 
@@ -599,16 +612,17 @@ int defl_legendre(Plan &p, int n, const void *const *P, bool caps_only)
     return flush();
 }
 
-// Deflection of realization q into plan.alpha from fphi_slot(q) (zeros when
+// Deflection of realization q into alpha (default plan.alpha) from fphi_slot(q) (zeros when
 // its alm_phi is NULL).
-int defl_fft(Plan &p, const void *alm_phi, int q)
+int defl_fft(Plan &p, const void *alm_phi, int q, void *alpha = nullptr)
 {
+    if (!alpha) alpha = p.alpha.ptr;
     if (!alm_phi) {
-        TL_HIP(fill_words(p.alpha.ptr, p.alpha.bytes / 4, 0u, p.stream), "alpha clear");
+        TL_HIP(fill_words(alpha, p.alpha.bytes / 4, 0u, p.stream), "alpha clear");
         return TL_OK;
     }
     StageScope sc(p, ST_DEFL_FFT);
-    TL_HIP(launch_fft_jobs(p, fphi_slot(p, q), p.alpha.ptr, (const FftJob *)p.jobsDefl.ptr, p.njobsDefl, true, 0),
+    TL_HIP(launch_fft_jobs(p, fphi_slot(p, q), alpha, (const FftJob *)p.jobsDefl.ptr, p.njobsDefl, true, 0),
            "deflection fft");
     return TL_OK;
 }
@@ -1286,7 +1300,7 @@ std::vector<BufItem> plan_buffer_list(Plan &p, const Sizes &sz)
             {&p.moff, sz.moff, "moff"},      {&p.kstart, sz.kstart, "kstart"}, {&p.rhs, sz.rhs, "rhs"},
             {&p.colexp, sz.colexp, "colexp"}, {&p.tabsum, sz.tabsum, "tabsum"}, {&p.hring, sz.hring, "hring"},
             {&p.twP64, sz.twP64, "twP64"},   {&p.twP32, sz.twP32, "twP32"},   {&p.bhat64, sz.bhat64, "bhat64"},
-            {&p.bhat32, sz.bhat32, "bhat32"}};
+            {&p.bhat32, sz.bhat32, "bhat32"}, {&p.D2, sz.D2, "D2"},       {&p.alpha2, sz.alpha2, "alpha2"}};
 }
 
 // Everything a plan computes into its buffers once they exist: angle and
@@ -1296,6 +1310,14 @@ std::vector<BufItem> plan_buffer_list(Plan &p, const Sizes &sz)
 int plan_setup(Plan &p)
 {
     int rc;
+    if (p.D2.ptr) {  // the second stream of a tabulated batch (default priority)
+        hipError_t e = hipStreamCreateWithFlags(&p.side, hipStreamNonBlocking);
+        for (int i = 0; i < 2 && e == hipSuccess; ++i) {
+            e = hipEventCreateWithFlags(&p.ev_fft[i], hipEventDisableTiming);
+            if (e == hipSuccess) e = hipEventCreateWithFlags(&p.ev_remap[i], hipEventDisableTiming);
+        }
+        if (e != hipSuccess) return hipfail(e, "second stream");
+    }
     if ((rc = upload_tables(p))) return rc;
     if ((rc = build_jobs(p))) return rc;
     hipError_t e = hipMemsetAsync(p.start.ptr, 0, p.start.bytes, p.stream);
@@ -1689,6 +1711,8 @@ int tl_lens_map_many(tl_plan plan, int32_t n, const void *const *alms, void *con
     if ((rc = set_device_of(p))) return rc;
     const size_t rowbytes = (size_t)p.nfield() * (p.order + 1) * p.ntheta * (p.lmax + 1) * (p.fp64() ? 16 : 8);
     const int g = p.tabform() ? p.batch : 1;
+    const bool ovl = p.overlap() && n > 1;
+    int u = 0;  // realizations launched
     for (int i0 = 0; i0 < n; i0 += g) {
         const int k = std::min(g, n - i0);
         const void *T[kTabMaxBatch], *E[kTabMaxBatch], *B[kTabMaxBatch], *P[kTabMaxBatch];
@@ -1706,20 +1730,33 @@ int tl_lens_map_many(tl_plan plan, int32_t n, const void *const *alms, void *con
         // table pass when folded), then per realization: deflection FFT,
         // ring FFTs, remap
         if (!(fold && p.caps_defl_done) && (rc = defl_legendre(p, k, P, fold))) return rc;
-        for (int q = 0; q < k; ++q) {
-            if ((rc = defl_fft(p, P[q], q))) return rc;
+        for (int q = 0; q < k; ++q, ++u) {
+            // realization u uses set u % 2 of maps and deflections (overlap)
+            const int st = ovl ? (u & 1) : 0;
+            void *D = st ? p.D2.ptr : p.D.ptr, *alpha = st ? p.alpha2.ptr : p.alpha.ptr;
+            if (ovl && u >= 2) TL_HIP(hipStreamWaitEvent(p.stream, p.ev_remap[st], 0), "stream order");
+            if ((rc = defl_fft(p, P[q], q, alpha))) return rc;
             {
                 StageScope sc(p, ST_FFT);
-                TL_HIP(launch_main_fft(p, F[q], p.D.ptr),
-                       "ring fft");
+                TL_HIP(launch_main_fft(p, F[q], D), "ring fft");
             }
-            const double *at = (const double *)p.alpha.ptr;
-            StageScope sc(p, ST_REMAP);
-            TL_HIP(launch_remap(p, p.D.ptr, at, at + p.npix(), nullptr, nullptr, outs[3 * (i0 + q)],
-                                outs[3 * (i0 + q) + 1], outs[3 * (i0 + q) + 2]),
-                   "remap");
+            const double *at = (const double *)alpha;
+            void *To = outs[3 * (i0 + q)], *Qo = outs[3 * (i0 + q) + 1], *Uo = outs[3 * (i0 + q) + 2];
+            if (ovl) {
+                // the remap on the second stream, after this realization's FFTs
+                TL_HIP(hipEventRecord(p.ev_fft[st], p.stream), "stream order");
+                TL_HIP(hipStreamWaitEvent(p.side, p.ev_fft[st], 0), "stream order");
+                TL_HIP(launch_remap(p, D, at, at + p.npix(), nullptr, nullptr, To, Qo, Uo, nullptr, p.side),
+                       "remap");
+                TL_HIP(hipEventRecord(p.ev_remap[st], p.side), "stream order");
+            } else {
+                StageScope sc(p, ST_REMAP);
+                TL_HIP(launch_remap(p, D, at, at + p.npix(), nullptr, nullptr, To, Qo, Uo), "remap");
+            }
         }
     }
+    // the plan's stream waits for the last remap (the second stream runs in order)
+    if (ovl && u > 0) TL_HIP(hipStreamWaitEvent(p.stream, p.ev_remap[(u - 1) & 1], 0), "stream order");
     return TL_OK;
 }
 

@@ -177,29 +177,29 @@ __global__ __launch_bounds__(256) void k_remap_hpx(int nside, const double *__re
 
 template <typename R, int N, bool MIX>
 hipError_t remap_NM(Plan &p, const void *D, const double *at, const double *ap, const double *ths,
-                    const double *phs, const float *corr, void *T, void *Q, void *U)
+                    const double *phs, const float *corr, void *T, void *Q, void *U, hipStream_t st)
 {
     dim3 grid((p.nphi + 255) / 256, p.ntheta);
-    const __half *D16 = MIX ? (const __half *)p.d16() : nullptr;
+    const __half *D16 = MIX ? (const __half *)p.d16_of(D) : nullptr;
     // the plan's own maps have padded planes; a caller's are [field][map][pixel]
-    const bool own = D == p.D.ptr;
+    const bool own = p.own(D);
     const size_t ds = own ? p.dstride : p.npix(), ds16 = p.dstride16;
     if (p.nside) {
         if (corr) return hipErrorInvalidValue;
         if (p.pol)
-            hipLaunchKernelGGL((k_remap_hpx<R, N, true, MIX>), grid, dim3(256), 0, p.stream, p.nside,
+            hipLaunchKernelGGL((k_remap_hpx<R, N, true, MIX>), grid, dim3(256), 0, st, p.nside,
                                (const double *)p.theta.ptr, (const double2 *)p.trig.ptr, (const HRing *)p.hring.ptr,
                                p.npix(), (const R *)D, D16, ds, ds16, at, ap, ths, phs, p.rotate, p.naive, (R *)T, (R *)Q,
                                (R *)U);
         else
-            hipLaunchKernelGGL((k_remap_hpx<R, N, false, MIX>), grid, dim3(256), 0, p.stream, p.nside,
+            hipLaunchKernelGGL((k_remap_hpx<R, N, false, MIX>), grid, dim3(256), 0, st, p.nside,
                                (const double *)p.theta.ptr, (const double2 *)p.trig.ptr, (const HRing *)p.hring.ptr,
                                p.npix(), (const R *)D, D16, ds, ds16, at, ap, ths, phs, p.rotate, p.naive, (R *)T, (R *)Q,
                                (R *)U);
         return hipGetLastError();
     }
     auto launch = [&](auto kernel) {
-        hipLaunchKernelGGL(kernel, grid, dim3(256), 0, p.stream, p.ntheta, p.nphi, (const double *)p.theta.ptr,
+        hipLaunchKernelGGL(kernel, grid, dim3(256), 0, st, p.ntheta, p.nphi, (const double *)p.theta.ptr,
                            (const double2 *)p.trig.ptr, (const double2 *)p.phitab.ptr, (const double *)p.phival.ptr,
                            (const R *)D, D16, ds, ds16, at, ap, ths, phs, p.rotate, p.naive, corr, (R *)T, (R *)Q,
                            (R *)U);
@@ -216,28 +216,28 @@ hipError_t remap_NM(Plan &p, const void *D, const double *at, const double *ap, 
 // FP32 forms); maps elsewhere are plain.
 template <typename R, int N>
 hipError_t remap_N(Plan &p, const void *D, const double *at, const double *ap, const double *ths,
-                   const double *phs, const float *corr, void *T, void *Q, void *U)
+                   const double *phs, const float *corr, void *T, void *Q, void *U, hipStream_t st)
 {
     if constexpr (N >= kMix16 && sizeof(R) == 4) {
-        if (p.mix16 && D == p.D.ptr) return remap_NM<R, N, true>(p, D, at, ap, ths, phs, corr, T, Q, U);
+        if (p.mix16 && p.own(D)) return remap_NM<R, N, true>(p, D, at, ap, ths, phs, corr, T, Q, U, st);
     }
-    return remap_NM<R, N, false>(p, D, at, ap, ths, phs, corr, T, Q, U);
+    return remap_NM<R, N, false>(p, D, at, ap, ths, phs, corr, T, Q, U, st);
 }
 
 template <typename R>
 hipError_t remap_R(Plan &p, const void *D, const double *at, const double *ap, const double *ths,
-                   const double *phs, const float *corr, void *T, void *Q, void *U)
+                   const double *phs, const float *corr, void *T, void *Q, void *U, hipStream_t st)
 {
     switch (p.order) {
-    case 0: return remap_N<R, 0>(p, D, at, ap, ths, phs, corr, T, Q, U);
-    case 1: return remap_N<R, 1>(p, D, at, ap, ths, phs, corr, T, Q, U);
-    case 2: return remap_N<R, 2>(p, D, at, ap, ths, phs, corr, T, Q, U);
-    case 3: return remap_N<R, 3>(p, D, at, ap, ths, phs, corr, T, Q, U);
-    case 4: return remap_N<R, 4>(p, D, at, ap, ths, phs, corr, T, Q, U);
-    case 5: return remap_N<R, 5>(p, D, at, ap, ths, phs, corr, T, Q, U);
-    case 6: return remap_N<R, 6>(p, D, at, ap, ths, phs, corr, T, Q, U);
-    case 7: return remap_N<R, 7>(p, D, at, ap, ths, phs, corr, T, Q, U);
-    case 8: return remap_N<R, 8>(p, D, at, ap, ths, phs, corr, T, Q, U);
+    case 0: return remap_N<R, 0>(p, D, at, ap, ths, phs, corr, T, Q, U, st);
+    case 1: return remap_N<R, 1>(p, D, at, ap, ths, phs, corr, T, Q, U, st);
+    case 2: return remap_N<R, 2>(p, D, at, ap, ths, phs, corr, T, Q, U, st);
+    case 3: return remap_N<R, 3>(p, D, at, ap, ths, phs, corr, T, Q, U, st);
+    case 4: return remap_N<R, 4>(p, D, at, ap, ths, phs, corr, T, Q, U, st);
+    case 5: return remap_N<R, 5>(p, D, at, ap, ths, phs, corr, T, Q, U, st);
+    case 6: return remap_N<R, 6>(p, D, at, ap, ths, phs, corr, T, Q, U, st);
+    case 7: return remap_N<R, 7>(p, D, at, ap, ths, phs, corr, T, Q, U, st);
+    case 8: return remap_N<R, 8>(p, D, at, ap, ths, phs, corr, T, Q, U, st);
     default: return hipErrorInvalidValue;
     }
 }
@@ -245,10 +245,11 @@ hipError_t remap_R(Plan &p, const void *D, const double *at, const double *ap, c
 }  // namespace
 
 hipError_t launch_remap(Plan &p, const void *D, const double *at, const double *ap, const double *thsrc,
-                        const double *phsrc, void *T, void *Q, void *U, const float *corr)
+                        const double *phsrc, void *T, void *Q, void *U, const float *corr, hipStream_t st)
 {
-    if (p.fp64()) return remap_R<double>(p, D, at, ap, thsrc, phsrc, corr, T, Q, U);
-    return remap_R<float>(p, D, at, ap, thsrc, phsrc, corr, T, Q, U);
+    if (!st) st = p.stream;
+    if (p.fp64()) return remap_R<double>(p, D, at, ap, thsrc, phsrc, corr, T, Q, U, st);
+    return remap_R<float>(p, D, at, ap, thsrc, phsrc, corr, T, Q, U, st);
 }
 
 }  // namespace tl

@@ -194,6 +194,15 @@ struct Plan {
     // the plan's own FP16 maps use paired planes (pair_pos); slots s and
     // s + 1 of a pair together hold 2 dstride16 elements
     bool paired = false;
+    // Tabulated plans of several realizations per pass: the realizations of
+    // a pass alternate between two sets of maps and deflection fields (D,
+    // alpha and D2, alpha2), so that the remap of one runs on a second
+    // stream (side, default priority) while the ring FFTs of the next run
+    // on the plan's stream; ev_fft[s] / ev_remap[s] order the uses of set s.
+    DevBuf D2, alpha2;
+    hipStream_t side = nullptr;
+    hipEvent_t ev_fft[2] = {nullptr, nullptr}, ev_remap[2] = {nullptr, nullptr};
+    bool overlap() const { return side != nullptr && !profile; }
 
     size_t total_bytes = 0;
     // work counts (tl_plan_query)
@@ -210,7 +219,10 @@ struct Plan {
     int nfield() const { return pol ? 3 : 1; }
     int ndmap() const { return (order + 1) * (order + 2) / 2; }
     // FP16 maps of the mixed layout start after the FP32 ones
-    void *d16() const { return (char *)D.ptr + (size_t)nfield() * mix_n32() * dstride * 4; }
+    void *d16() const { return d16_of(D.ptr); }
+    void *d16_of(const void *maps) const { return (char *)maps + (size_t)nfield() * mix_n32() * dstride * 4; }
+    // the plan's own maps (either set)
+    bool own(const void *maps) const { return maps && (maps == D.ptr || maps == D2.ptr); }
     bool fp64() const { return precision == TL_FP64; }
     bool tabform() const { return precision >= TL_BF16X3; }
     size_t npix() const { return nside ? (size_t)12 * nside * nside : (size_t)ntheta * (size_t)nphi; }
@@ -326,9 +338,10 @@ hipError_t launch_fft_jobs(Plan &p, const void *Fbase, void *Dbase, const FftJob
 // HEALPix: chirp spectra of the Bluestein ring lengths (items {M, class P, boff})
 hipError_t launch_bluestein_tables(Plan &p, const std::vector<int4> &items);
 // D: the plan's own maps (padded, maybe mixed) or a caller's ([field][map][pixel]);
-// corr (optional, FP32 [3][ntheta][nphi]): added to the Taylor sums before the rotation
+// corr (optional, FP32 [3][ntheta][nphi]): added to the Taylor sums before the rotation;
+// st: the stream (default: the plan's)
 hipError_t launch_remap(Plan &p, const void *D, const double *at, const double *ap,
                         const double *thsrc, const double *phsrc, void *T, void *Q, void *U,
-                        const float *corr = nullptr);
+                        const float *corr = nullptr, hipStream_t st = nullptr);
 
 }  // namespace tl
