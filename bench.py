@@ -416,6 +416,130 @@ def bench_healpix(args, with_oracle, precision="fp16x2", nside=2048, lmax=3072, 
     return res
 
 
+def sweep_sample(lmax: int, nring: int = 16, ncol: int = 32):
+    """Sky positions of the accuracy sweep, as (ring, column) on the grid of
+    oversampling 1 (lmax + 1 rings of 2 lmax pixels): nring rings from the
+    second ring to the equator and beyond, ncol columns each.  On the grid of
+    oversampling g the same positions are (g ring, g column)."""
+    import numpy as np
+
+    nt = lmax + 1
+    rings = np.unique(np.round(np.linspace(1, nt - 2, nring)).astype(np.int64))
+    cols = (np.arange(ncol) * (2 * lmax) // ncol + 3) % (2 * lmax)
+    R, C = np.meshgrid(rings, cols, indexing="ij")
+    return R.ravel(), C.ravel()
+
+
+def sweep_best(rows, targets=(1e-2, 1e-3, 1e-4, 1e-5, 1e-6)):
+    """For each lmax and error target, the fastest row (time per map) whose
+    worst field error is within the target: the structure of the paper's
+    fastest-settings table."""
+    out = []
+    for lmax in sorted({r["lmax"] for r in rows}):
+        for t in targets:
+            ok = [r for r in rows if r["lmax"] == lmax and r["rel_rms_err_max"] <= t]
+            if not ok:
+                out.append({"lmax": lmax, "target": t, "row": None})
+                continue
+            b = min(ok, key=lambda r: r["ms_per_map"])
+            out.append({"lmax": lmax, "target": t, "row": {k: b[k] for k in
+                                                           ("oversampling", "order", "form", "ms_per_map",
+                                                            "rel_rms_err_max")}})
+    return out
+
+
+def bench_sweep(args):
+    """Accuracy against time on the GPU (the structure of the paper's timing
+    sweep and fastest-settings table, Sec. III.B): for each lmax, grid
+    oversampling g (g lmax + 1 rings of 2 g lmax pixels) and Taylor order,
+    the time per lensed T+Q/U map of the FP32 form and, on g = 1, of the
+    split-FP16 form with six realizations per table pass (FP16 maps of order
+    >= 3), and the relative RMS error of realization 0 against the exact
+    lensed field (the unlensed field synthesized at each displaced position,
+    rotated) at a fixed sample of sky positions shared by every grid."""
+    import numpy as np
+    import torch
+
+    from oracle import taylens_oracle as orc
+    from paper_1307_0719_amd import skygen, taylens
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    try:
+        nproc = len(os.sched_getaffinity(0))
+    except AttributeError:
+        nproc = os.cpu_count() or 1
+    ncores = min(16, nproc)
+    lmaxes = [int(x) for x in args.sweep_lmax.split(",")]
+    gs = [int(x) for x in args.sweep_oversampling.split(",")]
+    orders = [int(x) for x in args.sweep_orders.split(",")]
+    rows = []
+    for lmax in lmaxes:
+        skies = [skygen.make_sky(lmax, 30 + i, pol=True) for i in range(6)]
+        to_dev = lambda a: None if a is None else torch.from_numpy(a).to(dev)
+        sdev = [(to_dev(s.alm_T), to_dev(s.alm_E), None, to_dev(s.alm_phi)) for s in skies]
+        R, C = sweep_sample(lmax)
+        s0 = skies[0]
+        o0 = time.perf_counter()
+        ex = orc.exact_lensed_pixels(lmax, lmax + 1, 2 * lmax, R, C, s0.alm_T, s0.alm_E, None, s0.alm_phi,
+                                     nthreads=ncores)
+        oracle_s = time.perf_counter() - o0
+        print(f"sweep lmax {lmax}: exact reference at {R.size} positions in {oracle_s:.1f} s", file=sys.stderr,
+              flush=True)
+        for g in gs:
+            nt, nph = g * lmax + 1, 2 * g * lmax
+            idx = torch.from_numpy(g * R * nph + g * C).to(dev)
+            forms = [("fp32", 1)] + ([("fp16x2", 6)] if g == 1 else [])
+            for order in orders:
+                for prec, batch in forms:
+                    try:
+                        plan = taylens.Plan(lmax, nt, nph, order, prec, pol=True, batch=batch if batch > 1 else 0,
+                                            maps16=prec != "fp32")
+                    except taylens.TaylensError as e:
+                        rows.append({"lmax": lmax, "oversampling": g, "order": order, "form": prec,
+                                     "skipped": str(e)})
+                        continue
+                    outs = [(plan._maps(), plan._maps(), plan._maps()) for _ in range(batch)]
+
+                    def step():
+                        if batch == 1:
+                            a = sdev[0]
+                            plan.lens_map(a[0], a[1], a[2], a[3], out=outs[0])
+                        else:
+                            plan.lens_map_many(sdev[:batch], outs)
+
+                    step()
+                    ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+                    torch.cuda.synchronize()
+                    ev[0].record()
+                    for i in range(args.steps):
+                        step()
+                        ev[i + 1].record()
+                    torch.cuda.synchronize()
+                    per = sorted(ev[i].elapsed_time(ev[i + 1]) for i in range(args.steps))
+                    ms = per[len(per) // 2]
+                    errs = {}
+                    for f, t in zip("TQU", outs[0]):
+                        x = t.view(-1)[idx].double().cpu().numpy()
+                        y = ex[f]
+                        errs[f] = float(np.sqrt(np.mean((x - y) ** 2)) / np.sqrt(np.mean(y ** 2)))
+                    rows.append({"lmax": lmax, "oversampling": g, "ntheta": nt, "nphi": nph, "order": order,
+                                 "form": prec if batch == 1 else f"{prec}:{batch}+m16",
+                                 "ms_per_map": ms / batch, "pixels_per_s": batch * nt * nph / (ms * 1e-3),
+                                 "rel_rms_err": errs, "rel_rms_err_max": max(errs.values())})
+                    print(f"sweep lmax {lmax} g {g} order {order} {rows[-1]['form']}: {ms / batch:.2f} ms/map, "
+                          f"err {rows[-1]['rel_rms_err_max']:.2e}", file=sys.stderr, flush=True)
+                    del outs
+                    plan.close()
+                    torch.cuda.empty_cache()
+    return {"metric": "accuracy vs time per lensed map (T+Q/U)", "unit": "ms per map",
+            "reference": "exact lensed field at the sampled positions (unlensed field synthesized at each "
+                         "displaced position, rotated), FP64 oracle",
+            "sample": "16 rings x 32 columns on the oversampling-1 grid, the same sky positions on every grid",
+            "deflection_rms_arcmin": skygen.DEFLECTION_RMS_ARCMIN, "steps": args.steps,
+            "rows": rows, "fastest": sweep_best([r for r in rows if "skipped" not in r])}
+
+
 def deflection_check(w, skies, skies_dev):
     """The deflection field of the step's realizations, from the library's
     deflection entry point (direct FP64 synthesis of grad phi): its RMS |alpha|
@@ -518,6 +642,12 @@ def main():
                          "without the oracle; one JSON line")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the uneven-lmax batch and the learned-correction measurements")
+    ap.add_argument("--sweep", action="store_true",
+                    help="only the accuracy-vs-time sweep (lmax x grid oversampling x order against the exact "
+                         "lensed field); one JSON line")
+    ap.add_argument("--sweep-lmax", default="1024,2048,4096")
+    ap.add_argument("--sweep-oversampling", default="1,2")
+    ap.add_argument("--sweep-orders", default="1,2,3,4,5,6")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -529,6 +659,9 @@ def main():
         return
     if args.healpix_only:
         print(json.dumps(bench_healpix(args, False)))
+        return
+    if args.sweep:
+        print(json.dumps(bench_sweep(args)))
         return
 
     import numpy as np

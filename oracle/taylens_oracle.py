@@ -30,6 +30,9 @@ What it computes, in the order the paper gives (Sec. II, eqs. 1, 2, 4, 5):
    Q(e'_t e'_t^T - e'_p e'_p^T) + U(e'_t e'_p^T + e'_p e'_t^T) at x' is
    carried to x by the rotation about x' cross x through the angle between
    them, and read back as Q = e_t^T P e_t, U = e_t^T P e_p.
+7. The exact lensed field (no Taylor series), the reference of accuracy
+   measurements: the unlensed field synthesized directly at x' (eq. 1),
+   then rotated as in 6.
 
 Everything is float64 (the harmonic sums long double).  Speed is not a goal.
 """
@@ -416,6 +419,45 @@ def lens_at_positions(lmax, order, ntheta, nphi, thp, php, alm_T, alm_E=None, al
         Df = D[f]
         res[f] = taylor_sum(lambda j, k: Df[(j, k)][pos, k0], dth, dph, order)
     res["_tie"] = tie
+    return res
+
+
+def exact_lensed_pixels(lmax, ntheta, nphi, rings, cols, alm_T, alm_E=None, alm_B=None, alm_phi=None,
+                        rotate=True, nthreads: int = 0) -> dict:
+    """The lensed field with no Taylor series: at output pixel (rings[p],
+    cols[p]) of the grid, the unlensed field synthesized directly at the
+    displaced position x' (Sec. II.A: the deflection, the geodesic rule,
+    eq. 1), then carried back to x by the rotation of eq. 2.  The limit of
+    the Taylor remap (eq. 5) as the order grows; what the accuracy of an
+    order and grid is measured against.
+
+    The unlensed field at x' is sum_m w_m Re[F_m(theta') e^{i m phi'}], with
+    F_m(theta') from the exact recursions at theta' itself.  Returns
+    {'T', 'Q', 'U': [n] float64, '_thp', '_php': the positions}."""
+    rings = np.asarray(rings, dtype=np.int64)
+    cols = np.asarray(cols, dtype=np.int64)
+    th = grid_theta(ntheta)[rings]
+    ph = grid_phi(nphi)[cols]
+    if alm_phi is None:
+        a_t = np.zeros(rings.size)
+        a_p = np.zeros(rings.size)
+    else:
+        ur, inv = np.unique(rings, return_inverse=True)
+        at_r, ap_r = deflection_rings(lmax, alm_phi, ntheta, nphi, ur, nthreads)
+        a_t = at_r[inv, cols]
+        a_p = ap_r[inv, cols]
+    thp, php, xp, dist, _ = geodesic_positions(th, ph, a_t, a_p)
+    F = ring_coeffs(lmax, 0, thp, alm_T, alm_E, alm_B, nthreads)
+    m = np.arange(lmax + 1)
+    w = np.where(m == 0, 1.0, 2.0)
+    e = np.exp(1j * np.multiply.outer(php, m))
+    res = {f: np.real(np.sum(w * arr[:, 0, :] * e, axis=-1)) for f, arr in F.items()}
+    if "Q" in res and rotate:
+        Qr, Ur = rotate_pol_3d(res["Q"], res["U"], th, ph, thp, php, xp)
+        res["Q"] = np.where(dist > 0, Qr, res["Q"])
+        res["U"] = np.where(dist > 0, Ur, res["U"])
+    res["_thp"] = thp
+    res["_php"] = php
     return res
 
 

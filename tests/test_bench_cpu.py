@@ -54,3 +54,35 @@ def test_mfma_summary_parsed_only_for_its_sources(bench, monkeypatch):
     assert bench.measured_mfma_busy("TP4096", "fp16x2:6+m16", "k_legendre_mfma") is None
     monkeypatch.setattr(bench, "sources_digest", lambda: "0" * 64)
     assert bench.measured_mfma_busy("TP4096", "fp16x2:6+m16", "k_legendre_tab") is None
+
+
+def test_sweep_sample_is_shared_by_every_grid(bench):
+    """The sweep's sky positions: (ring, column) on the oversampling-1 grid of
+    lmax + 1 rings and 2 lmax columns, distinct, off the pole rings; the
+    same angles are (g ring, g column) on the grid of oversampling g."""
+    import math
+
+    import numpy as np
+
+    lmax = 64
+    R, C = bench.sweep_sample(lmax)
+    assert R.size == C.size == 16 * 32
+    assert R.min() >= 1 and R.max() <= lmax - 1 and C.min() >= 0 and C.max() < 2 * lmax
+    assert len(set(zip(R.tolist(), C.tolist()))) == R.size
+    for g in (1, 2, 3):
+        th1, th_g = math.pi * R / lmax, math.pi * (g * R) / (g * lmax)
+        ph1, ph_g = 2 * math.pi * C / (2 * lmax), 2 * math.pi * (g * C) / (2 * g * lmax)
+        assert np.allclose(th1, th_g) and np.allclose(ph1, ph_g)
+
+
+def test_sweep_fastest_settings(bench):
+    """For each lmax and target, the fastest row within the target; None
+    where no row reaches it."""
+    rows = [{"lmax": 8, "oversampling": 1, "order": o, "form": "fp32", "ms_per_map": 1.0 + o,
+             "rel_rms_err_max": 10.0 ** (-o)} for o in range(1, 5)]
+    rows.append({"lmax": 8, "oversampling": 2, "order": 2, "form": "fp32", "ms_per_map": 3.5,
+                 "rel_rms_err_max": 1e-4})
+    best = {b["target"]: b["row"] for b in bench.sweep_best(rows, targets=(1e-2, 1e-4, 1e-6))}
+    assert best[1e-2]["order"] == 2 and best[1e-2]["oversampling"] == 1
+    assert best[1e-4]["oversampling"] == 2 and best[1e-4]["ms_per_map"] == 3.5
+    assert best[1e-6] is None

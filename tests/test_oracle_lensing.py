@@ -9,7 +9,9 @@ P3  a constant theta shift, exact via the doubled-circle Fourier series;
 P4  alpha = 0 gives back the unlensed map bit for bit;
 P8  the rotation equals the closed-form angle 2 gamma, is unitary, and obeys
     the pole-ring invariants;
-P9  the positions lie at great-circle distance |alpha| in direction psi.
+P9  the positions lie at great-circle distance |alpha| in direction psi;
+P10 the exact lensed field (no Taylor series) is the brute-force sum at the
+    displaced positions and the limit of the Taylor remap.
 """
 import math
 
@@ -347,3 +349,32 @@ def test_p3_high_l_theta_derivatives_from_the_doubled_circle(oracle, lmax, pol):
             worst = max(worst, err)
             assert err < 5e-12, (f, j, err)
     print("worst relative derivative error", worst)
+
+
+def test_p10_exact_lensing_is_the_brute_force_sum_at_the_displaced_positions(oracle, small_sky):
+    """exact_lensed_pixels (the reference of the accuracy-vs-time sweep)
+    against sum a_lm Y_lm(x') by scipy / Goldberg at its own positions, and
+    against the order-14 Taylor remap, which P1 pins to the same sums."""
+    lmax, ntheta, nphi, sky, almB = small_sky
+    rng = np.random.default_rng(5)
+    rings = rng.integers(0, ntheta, 60)
+    cols = rng.integers(0, nphi, 60)
+    ex = oracle.exact_lensed_pixels(lmax, ntheta, nphi, rings, cols, sky.alm_T, sky.alm_E, almB, sky.alm_phi,
+                                    rotate=False)
+    supT = _sup_bound_T(sky.alm_T, lmax)
+    supP = _sup_bound_P(sky.alm_E, almB, lmax)
+    bT = pinlib.brute_T(sky.alm_T, lmax, ex["_thp"], ex["_php"])
+    bQ, bU = pinlib.brute_QU(sky.alm_E, almB, lmax, ex["_thp"], ex["_php"])
+    assert np.max(np.abs(ex["T"] - bT)) < 1e-12 * supT
+    assert np.max(np.abs(ex["Q"] - bQ)) < 1e-12 * supP
+    assert np.max(np.abs(ex["U"] - bU)) < 1e-12 * supP
+    # with the rotation: the converged Taylor remap on the same pixels
+    exr = oracle.exact_lensed_pixels(lmax, ntheta, nphi, rings, cols, sky.alm_T, sky.alm_E, almB, sky.alm_phi)
+    tay = oracle.lens_map(lmax, 14, ntheta, nphi, sky.alm_T, sky.alm_E, almB, sky.alm_phi)
+    for f, sup in (("T", supT), ("Q", supP), ("U", supP)):
+        assert np.max(np.abs(exr[f] - tay[f][rings, cols])) < 1e-12 * sup, f
+    # no deflection: the unlensed map itself
+    z = oracle.exact_lensed_pixels(lmax, ntheta, nphi, rings, cols, sky.alm_T, sky.alm_E, almB, None)
+    un = oracle.unlensed_map(lmax, ntheta, nphi, sky.alm_T, sky.alm_E, almB)
+    for f in "TQU":
+        np.testing.assert_allclose(z[f], un[f][rings, cols], rtol=0, atol=1e-13 * supT)
