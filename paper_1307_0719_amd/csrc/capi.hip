@@ -122,6 +122,9 @@ void free_plan_buffers(Plan &p)
         if (p.ev_remap[i]) (void)hipEventDestroy(p.ev_remap[i]);
         p.ev_fft[i] = p.ev_remap[i] = nullptr;
     }
+    if (p.ev_gemm) (void)hipEventDestroy(p.ev_gemm);
+    if (p.ev_caps) (void)hipEventDestroy(p.ev_caps);
+    p.ev_gemm = p.ev_caps = nullptr;
     if (p.side) (void)hipStreamDestroy(p.side);
     p.side = nullptr;
 }
@@ -661,7 +664,7 @@ bool caps_one_launch(const Plan &p, int n, bool hasb)
 // both spin families of Q/U and, with P, the lensing potential's FP64 rows
 // (fphi_slot) -- FP32 rows Fout[q] laid out [field][N + 1][ring][m].
 int run_caps(Plan &p, int n, const void *const *T, const void *const *E, const void *const *B, const void *const *P,
-             void *const *Fout, bool hasb)
+             void *const *Fout, bool hasb, hipStream_t st = nullptr)
 {
     const size_t rowc = (size_t)p.ntheta * (p.lmax + 1) * (p.order + 1);
     CapsArgs a{};
@@ -687,7 +690,7 @@ int run_caps(Plan &p, int n, const void *const *T, const void *const *E, const v
         add(3);
     }
     StageScope sc(p, ST_CAPS);
-    TL_HIP(launch_legendre_caps(p, p.rpole, a, p.pol ? n : 0, hasb), "legendre caps");
+    TL_HIP(launch_legendre_caps(p, p.rpole, a, p.pol ? n : 0, hasb, st), "legendre caps");
     return TL_OK;
 }
 
@@ -708,11 +711,19 @@ int run_legendre_many(Plan &p, int n, const void *const *T, const void *const *E
     const int rend = (mfma || tab) ? p.rpole : p.nrp;
     p.caps_defl_done = false;
     const bool caps1 = (mfma || tab) && caps_one_launch(p, n, hasb);
-    if (caps1) {
+    // tabulated passes with a second stream: the caps run there, beside the
+    // table epilogue (they write only the cap rings' rows)
+    const bool side_caps = caps1 && tab && p.tables && p.overlap();
+    bool caps_pending = side_caps;
+    auto caps = [&](hipStream_t st) -> int {
         const bool defl = fold_deflection(p, n, P);
-        int rc = run_caps(p, n, T, E, B, defl ? P : nullptr, Fout, hasb);
+        int rc = run_caps(p, n, T, E, B, defl ? P : nullptr, Fout, hasb, st);
+        if (!rc) p.caps_defl_done = defl;
+        return rc;
+    };
+    if (caps1 && !side_caps) {
+        int rc = caps(p.stream);
         if (rc) return rc;
-        p.caps_defl_done = defl;
     }
     // direct kernels: several realizations per launch share the recursion
     for (int i0 = 0, mx = direct_max(p.order, false, false, p.fp64()); !caps1 && i0 < n; i0 += mx) {
@@ -775,12 +786,21 @@ int run_legendre_many(Plan &p, int n, const void *const *T, const void *const *E
                 TL_HIP(p.tables ? launch_legendre_tab(p, b, 1) : launch_legendre_lp(p, b, 1),
                        "legendre matrix-core stage");
             }
+            if (caps_pending) {
+                TL_HIP(hipEventRecord(p.ev_gemm, p.stream), "stream order");
+                TL_HIP(hipStreamWaitEvent(p.side, p.ev_gemm, 0), "stream order");
+                const int rc = caps(p.side);
+                if (rc) return rc;
+                TL_HIP(hipEventRecord(p.ev_caps, p.side), "stream order");
+                caps_pending = false;
+            }
             if (p.tables) {
                 StageScope sc(p, ST_TAB_EPI);
                 TL_HIP(launch_legendre_tab(p, b, 2), "legendre table epilogue");
             }
         }
     }
+    if (side_caps) TL_HIP(hipStreamWaitEvent(p.stream, p.ev_caps, 0), "stream order");
     return TL_OK;
 }
 
@@ -1316,6 +1336,8 @@ int plan_setup(Plan &p)
             e = hipEventCreateWithFlags(&p.ev_fft[i], hipEventDisableTiming);
             if (e == hipSuccess) e = hipEventCreateWithFlags(&p.ev_remap[i], hipEventDisableTiming);
         }
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&p.ev_gemm, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&p.ev_caps, hipEventDisableTiming);
         if (e != hipSuccess) return hipfail(e, "second stream");
     }
     if ((rc = upload_tables(p))) return rc;

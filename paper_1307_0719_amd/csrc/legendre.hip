@@ -850,16 +850,16 @@ __global__ void k_zero_cap_rows(const CapsArgs args, int ntheta, int lmax, int r
 }
 
 template <int J, bool HASB>
-hipError_t caps_JH(Plan &p, int rend, const CapsArgs &a, int nreal)
+hipError_t caps_JH(Plan &p, int rend, const CapsArgs &a, int nreal, hipStream_t st)
 {
     if (p.pol && nreal > 0) {
-        hipLaunchKernelGGL(k_zero_cap_rows, dim3(256, 2 * (J + 1), 2 * nreal), dim3(256), 0, p.stream, a, p.ntheta,
+        hipLaunchKernelGGL(k_zero_cap_rows, dim3(256, 2 * (J + 1), 2 * nreal), dim3(256), 0, st, a, p.ntheta,
                            p.lmax, rend);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
     dim3 grid((rend + 63) / 64, (p.lmax + 1 + 7) / 8, a.ntask);
-    hipLaunchKernelGGL((k_legendre_caps<J, HASB>), grid, dim3(512), 0, p.stream, p.lmax, p.ntheta, p.nrp, rend, p.jtab,
+    hipLaunchKernelGGL((k_legendre_caps<J, HASB>), grid, dim3(512), 0, st, p.lmax, p.ntheta, p.nrp, rend, p.jtab,
                        (const double2 *)p.trig.ptr, (const double4 *)p.coef0.ptr, (const double4 *)p.coef2.ptr,
                        (const double *)p.start.ptr, (const int *)p.exps.ptr, (const int *)p.mcut.ptr, a);
     return hipGetLastError();
@@ -974,12 +974,13 @@ int caps_nb(int kind, int J, bool hasb)
 #undef TL_NB
 }
 
-hipError_t launch_legendre_caps(Plan &p, int rend, const CapsArgs &a, int nreal, bool hasb)
+hipError_t launch_legendre_caps(Plan &p, int rend, const CapsArgs &a, int nreal, bool hasb, hipStream_t st)
 {
+    if (!st) st = p.stream;
     if (rend <= 0 || a.ntask <= 0) return hipSuccess;
     if (a.ntask > kCapsMaxTasks) return hipErrorInvalidValue;
 #define TL_CAPS(JJ) \
-    case JJ: return hasb ? caps_JH<JJ, true>(p, rend, a, nreal) : caps_JH<JJ, false>(p, rend, a, nreal);
+    case JJ: return hasb ? caps_JH<JJ, true>(p, rend, a, nreal, st) : caps_JH<JJ, false>(p, rend, a, nreal, st);
     switch (p.order) {
         TL_CAPS(0)
         TL_CAPS(1)

@@ -202,6 +202,10 @@ struct Plan {
     DevBuf D2, alpha2;
     hipStream_t side = nullptr;
     hipEvent_t ev_fft[2] = {nullptr, nullptr}, ev_remap[2] = {nullptr, nullptr};
+    // the polar caps of a tabulated pass run on the second stream beside the
+    // table epilogue: ev_gemm (plan's stream, after the table GEMM) starts
+    // them, ev_caps (second stream) holds back what follows the epilogue
+    hipEvent_t ev_gemm = nullptr, ev_caps = nullptr;
     bool overlap() const { return side != nullptr && !profile; }
 
     size_t total_bytes = 0;
@@ -288,7 +292,8 @@ struct CapsArgs {
 int caps_nb(int kind, int J, bool hasb);
 // zeroes the Q/U cap rows of realizations [0, nreal) (spin families add
 // into them), then launches the tasks over ring pairs [0, rend)
-hipError_t launch_legendre_caps(Plan &p, int rend, const CapsArgs &a, int nreal, bool hasb);
+hipError_t launch_legendre_caps(Plan &p, int rend, const CapsArgs &a, int nreal, bool hasb,
+                                hipStream_t st = nullptr);  // st: default the plan's stream
 
 // ---- learned remainder correction (cnn.hip) ----
 constexpr int kCnnTrain = 32 * 20 * 9 + 32 + 32 * 32 * 9 + 32 + 3 * 32 + 3;  // trainable parameters
