@@ -259,3 +259,32 @@ def test_maps16_is_ignored_where_it_does_not_apply(tl):
             plan.close()
         for x, y in zip(*outs):
             assert torch.equal(x, y), c
+
+
+def test_paired_fp16_maps_across_table_passes(tl, oracle):
+    """maps16 on rings of 1024 points (paired FP16 planes, the radix-16
+    FFT at M = 512) with seven realizations on a plan of six per pass: the
+    second set of maps and the second stream alternate across the two passes.
+    Every realization equals a single call on the same plan bit for bit, and
+    the first and last match the oracle within 3e-5 (storing the maps of
+    order >= 3 in FP16 costs 5-6e-6 on this sky, one-pixel deflections, by a
+    CPU estimate with the oracle's maps rounded to FP16)."""
+    lmax, ntheta, nphi, order = 300, 301, 1024, 4
+    skies = [_sky(lmax, 300 + i, rms_pix=1.0, ntheta=ntheta) for i in range(7)]
+    plan = tl.Plan(lmax, ntheta, nphi, order, "fp16x2", pol=True, batch=6, maps16=True)
+    got = [tuple(x.clone() for x in o) for o in plan.lens_map_many([(s.alm_T, s.alm_E, None, s.alm_phi)
+                                                                    for s in skies])]
+    single = [tuple(x.clone() for x in plan.lens_map(s.alm_T, s.alm_E, None, s.alm_phi)) for s in skies]
+    torch.cuda.synchronize()
+    for a, b in zip(got, single):
+        for x, y in zip(a, b):
+            assert torch.equal(x, y)
+    for i in (0, 6):
+        s = skies[i]
+        ref = oracle.lens_map(lmax, order, ntheta, nphi, s.alm_T, s.alm_E, None, s.alm_phi, nthreads=ORACLE_THREADS)
+        mask = ref["_tie"] > 1e-9
+        for f, g in zip("TQU", got[i]):
+            e = rel_rms(t2np(g), ref[f], mask)
+            print("paired maps16", i, f, f"{e:.2e}")
+            assert e < 3e-5, (i, f, e)
+    plan.close()
