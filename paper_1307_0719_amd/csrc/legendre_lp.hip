@@ -88,7 +88,7 @@ __global__ __launch_bounds__(256) void k_lp_rhs(int lmax, const int64_t *__restr
         const int h = lane >> 5, col = lane & 31;
         const int gc = blk * 16 + (col & 15);
         const bool on = (h == (col >= 16 ? 1 : 0)) && gc < NCOL;
-        const double sc = on ? exp2((double)s_ex[gc]) : 0.0;
+        const double sc = on ? ldexp(1.0, (int)s_ex[gc]) : 0.0;
         T hi8[8], lo8[8];
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
@@ -348,7 +348,7 @@ __global__ __launch_bounds__(256) void k_legendre_lp(const LpArgs A, const TabBa
                 if (c >= nc) break;
                 const int gc = c0 + c;
                 if (gc < b * 16 || gc >= b * 16 + 16) continue;
-                const float isc = exp2f(-cex[gc]);
+                const float isc = ldexpf(1.f, -(int)cex[gc]);
 #pragma unroll
                 for (int q4 = 0; q4 < 4; ++q4)
                     Sv[q4][c] = sm.tr[wave][lane][q4][gc - b * 16] * isc * usc[q4 >> 1];

@@ -254,7 +254,8 @@ __global__ __launch_bounds__(256) void k_tab_rhs(int lmax, int ntile, int NBAT, 
 #pragma unroll
                 for (int c = 0; c < C.n1; ++c) {
                     const int col = b0 * C.n1 + c;
-                    const float f = opaque((float)(v[c] * exp2((double)s_ex[col])));
+                    // the column's power of two, applied exactly (s_ex holds integers)
+                    const float f = opaque((float)ldexp(v[c], (int)s_ex[col]));
                     const T hi = (T)f;
                     s_v[0][li][col] = hi;
                     if constexpr (SPLIT) s_v[1][li][col] = (T)(f - (float)hi);
@@ -446,7 +447,7 @@ __global__ __launch_bounds__(256) void k_legendre_tab(int lmax, int nrp, int rbe
         const int col = b * 32 + rl;
         if (col >= NCOLS) continue;
         const int bb = col / n1, c = col % n1;
-        const float isc = exp2f(-cex[col]);  // exact: powers of two
+        const float isc = ldexpf(1.f, -(int)cex[col]);  // exact: powers of two
 #pragma unroll
         for (int v = 0; v < 16; ++v) {
             const int rp = rp0 + 8 * (v >> 2) + (v & 3);
