@@ -26,6 +26,10 @@
  * plan owns only its workspace (allocated at tl_plan_create, released by
  * tl_plan_destroy).  All work is queued on the plan's HIP stream; no call
  * synchronizes the stream except tl_plan_create (which builds its tables).
+ * Tabulated plans with opt.batch > 1 also own a second stream (default
+ * priority) that runs part of a call's work; it is ordered after the plan's
+ * stream by events, and the plan's stream waits for it before the call
+ * returns, so the caller still orders everything through the plan's stream.
  * A plan is not thread-safe: use one plan per host thread / stream.
  *
  * Errors: every function returns TL_OK (0) or a negative code; arguments are
@@ -243,7 +247,11 @@ int tl_lens_map_batch(int32_t n, const tl_plan *plans, const void *const *alms,
 /* Lens n realizations on ONE plan (all share lmax, grid, order, precision):
  * alms[4i..4i+3] = (T, E, B, phi), outs[3i..3i+2] = (T, Q, U).  For the
  * tabulated forms the harmonic stage runs opt.batch realizations per pass over
- * the lambda tables; the other stages run per realization. */
+ * the lambda tables; the other stages run per realization, alternating
+ * between two sets of the plan's maps so that one realization's remap (and a
+ * pass's polar caps) run on the plan's second stream beside the next
+ * realization's ring FFTs (and the pass's table epilogue).  Results are
+ * those of n single tl_lens_map calls, bit for bit. */
 int tl_lens_map_many(tl_plan plan, int32_t n, const void *const *alms, void *const *outs);
 
 /* Convenience form with the signature
