@@ -288,3 +288,43 @@ def test_paired_fp16_maps_across_table_passes(tl, oracle):
             print("paired maps16", i, f, f"{e:.2e}")
             assert e < 3e-5, (i, f, e)
     plan.close()
+
+
+def test_lens_map_many_replays_from_a_hip_graph(tl):
+    """tl_lens_map_many captured in a HIP graph on the plan's stream (its
+    second stream joins the capture through the call's events) and replayed
+    three times, with eager calls and synchronizations between the replays:
+    every replay reproduces the eager result bit for bit.  Four realizations
+    on a plan of three per pass (two passes), paired FP16 planes."""
+    dev = torch.device("cuda", 0)
+    lmax, ntheta, nphi, order = 96, 97, 1024, 4
+    skies = [_sky(lmax, 500 + i) for i in range(5)]
+    to = lambda a: None if a is None else torch.from_numpy(a).to(dev)
+    alms = [(to(s.alm_T), to(s.alm_E), None, to(s.alm_phi)) for s in skies[:4]]
+    other = (to(skies[4].alm_T), to(skies[4].alm_E), None, to(skies[4].alm_phi))
+    st = torch.cuda.Stream(dev)
+    plan = tl.Plan(lmax, ntheta, nphi, order, "fp16x2", pol=True, batch=3, maps16=True, stream=st)
+    mk = lambda: [tuple(torch.empty((ntheta, nphi), dtype=torch.float32, device=dev) for _ in range(3))
+                  for _ in alms]
+    eager, outs = mk(), mk()
+    with torch.cuda.stream(st):
+        plan.lens_map_many(alms, eager)
+        plan.lens_map_many(alms, outs)  # warm-up before the capture
+    st.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=st):
+        plan.lens_map_many(alms, outs)
+    for rep in range(3):
+        for o in outs:
+            for t in o:
+                t.fill_(float("nan"))
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for a, b in zip(eager, outs):
+            for x, y in zip(a, b):
+                assert torch.equal(x, y), rep
+        with torch.cuda.stream(st):  # eager work of the same plan between the replays
+            plan.lens_map(*other)
+        st.synchronize()
+    plan.close()
