@@ -114,6 +114,15 @@ typedef struct {
                               4096), but up to ~1e-4 for power at the grid's
                               band limit.  0: FP32 maps.  tl_synth_derivs
                               always returns FP32 maps.                          */
+    int32_t lmax_phi;      /* band limit of the lensing potential (Sec. II.A: the
+                              deflection is synthesized to its own, higher band
+                              limit than the fields): 0 = lmax; otherwise
+                              lmax <= lmax_phi <= 16384 and nphi >= 2 lmax_phi,
+                              equal-theta plans only (TL_ERR_UNSUPPORTED for
+                              HEALPix rings unless 0 or lmax).  alm_phi then holds
+                              (lmax_phi + 1)(lmax_phi + 2)/2 coefficients; the
+                              deflection takes the direct FP64 recursion on
+                              every ring (not the tables of the tabulated forms). */
 } tl_options;
 
 typedef struct tl_plan_s *tl_plan;

@@ -196,10 +196,22 @@ def derivative_rings(lmax: int, order: int, ntheta: int, nphi: int, rings,
     return out
 
 
+def lmax_of(alm) -> int:
+    """Band limit L of a triangular coefficient array of (L+1)(L+2)/2 entries."""
+    n = int(np.asarray(alm).size)
+    L = int(round((math.sqrt(8 * n + 1) - 3) / 2))
+    if (L + 1) * (L + 2) // 2 != n:
+        raise ValueError(f"{n} coefficients is not a triangular a_lm array")
+    return L
+
+
 def deflection_rings(lmax: int, alm_phi, ntheta: int, nphi: int, rings, nthreads: int = 0):
-    """alpha_theta, alpha_phi on the given rings ([nring, nphi] each)."""
+    """alpha_theta, alpha_phi on the given rings ([nring, nphi] each).  The
+    lensing potential's band limit is that of alm_phi itself, which may exceed
+    the fields' lmax (Sec. II.A); the ring sums need it below nphi / 2 + 1."""
     rings = np.atleast_1d(np.asarray(rings, dtype=np.int64))
     th = grid_theta(ntheta)[rings]
+    lmax = lmax_of(alm_phi)
     F = ring_coeffs(lmax, 1, th, alm_T=alm_phi, nthreads=nthreads)["T"]
     a_t = phi_synth(F[:, 1, :], 0, nphi)
     dphi = phi_synth(F[:, 0, :], 1, nphi)

@@ -114,7 +114,8 @@ void free_plan_buffers(Plan &p)
 {
     DevBuf *bufs[] = {&p.theta, &p.trig, &p.phitab, &p.phival, &p.twid64, &p.twid32, &p.coef0, &p.coef2,
                       &p.start, &p.exps, &p.mcut, &p.tab, &p.moff, &p.kstart, &p.rhs, &p.colexp, &p.tabsum, &p.Fphi, &p.alpha, &p.F, &p.D, &p.jobsDefl, &p.jobsMain, &p.jobsInt, &p.hring,
-                      &p.twP64, &p.twP32, &p.bhat64, &p.bhat32, &p.D2, &p.alpha2};
+                      &p.twP64, &p.twP32, &p.bhat64, &p.bhat32, &p.D2, &p.alpha2, &p.coefP0, &p.coefP2,
+                      &p.startP, &p.expsP, &p.mcutP};
     for (DevBuf *b : bufs) free_buf(*b);
     if (p.side) (void)hipStreamSynchronize(p.side);
     for (int i = 0; i < 2; ++i) {
@@ -235,11 +236,12 @@ struct Sizes {
     size_t theta, trig, phitab, phival, twid64, twid32, coef, start, exps, mcut, Fphi, alpha, F, D, jd, jm;
     size_t tab = 0, moff = 0, kstart = 0, rhs = 0, colexp = 0, tabsum = 0, hring = 0;
     size_t twP64 = 0, twP32 = 0, bhat64 = 0, bhat32 = 0, jx = 0, D2 = 0, alpha2 = 0;
+    size_t coefP = 0, startP = 0, expsP = 0, mcutP = 0;
     size_t total() const
     {
         return theta + trig + phitab + phival + twid64 + twid32 + 2 * coef + start + exps + mcut + Fphi + alpha + F +
                D + jd + jm + tab + moff + kstart + rhs + colexp + tabsum + hring + twP64 + twP32 + bhat64 + bhat32 + jx +
-               D2 + alpha2;
+               D2 + alpha2 + 2 * coefP + startP + expsP + mcutP;
     }
 };
 
@@ -273,7 +275,14 @@ Sizes plan_sizes(const Plan &p)
     s.start = 3 * (size_t)(p.lmax + 1) * p.jtab * p.nrp * sizeof(double);
     s.exps = 3 * (size_t)(p.lmax + 1) * p.nrp * sizeof(int);
     s.mcut = (size_t)p.nrp * sizeof(int);
-    s.Fphi = 2 * rowc * 16 * (p.tabform() ? p.batch : 1);
+    s.Fphi = 2 * (size_t)p.ntheta * (p.lmax_phi + 1) * 16 * (p.tabform() ? p.batch : 1);
+    if (p.phi_tables()) {  // the lensing potential's recursion tables (spin 0, J = 1)
+        const size_t L = (size_t)p.lmax_phi;
+        s.coefP = (L + 1) * (L + 2) / 2 * sizeof(double4);
+        s.startP = 3 * (L + 1) * 2 * p.nrp * sizeof(double);
+        s.expsP = 3 * (L + 1) * p.nrp * sizeof(int);
+        s.mcutP = (size_t)p.nrp * sizeof(int);
+    }
     s.alpha = 2 * p.npix() * sizeof(double);
     s.F = (size_t)p.nfield() * (p.order + 1) * rowc * cbytes * (p.tabform() ? p.batch : 1);
     if (p.tabform() && !p.tables) {
@@ -337,6 +346,12 @@ int validate_options(int32_t lmax, tl_grid grid, const tl_options *opt)
     if (tab && opt->batch > bmax)
         return fail(TL_ERR_INVALID, "batch too large for this order (at most " + std::to_string(bmax) + ")");
     if (opt->workspace_cap < 0) return fail(TL_ERR_INVALID, "workspace_cap must be >= 0");
+    if (opt->lmax_phi != 0) {
+        if (opt->lmax_phi < lmax) return fail(TL_ERR_INVALID, "lmax_phi must be 0 or >= lmax");
+        if (opt->lmax_phi > 16384) return fail(TL_ERR_UNSUPPORTED, "lmax_phi above 16384 is not supported");
+        if ((int64_t)grid.nphi < 2 * (int64_t)opt->lmax_phi)
+            return fail(TL_ERR_INVALID, "nphi must be >= 2*lmax_phi (band limit of the deflection on each ring)");
+    }
     Plan tmp;
     if (!factor_radices(grid.nphi / 2, tmp))
         return fail(TL_ERR_UNSUPPORTED, "nphi/2 must be a product of 2, 3 and 5");
@@ -451,12 +466,13 @@ int build_jobs(Plan &p)
     const double dth = M_PI / (double)(p.ntheta - 1);
     const double dph = 2.0 * M_PI / (double)p.nphi;
     const size_t row = (size_t)(p.lmax + 1);
+    const size_t rowp = (size_t)(p.lmax_phi + 1);  // the deflection's rows
     // deflection: alpha_theta = d_theta phi (j=1, k=0); alpha_phi = d_phi phi / sin theta
     // (j=0, k=1), on the pole rings +- d_theta d_phi phi (j=1, k=1).
     std::vector<FftJob> jd(2 * (size_t)p.ntheta);
     for (int i = 0; i < p.ntheta; ++i) {
         FftJob a{};
-        a.src = (int64_t)((size_t)(1 * p.ntheta + i) * row);
+        a.src = (int64_t)((size_t)(1 * p.ntheta + i) * rowp);
         a.nk = 1;
         a.k[0] = 0;
         a.dst[0] = (int64_t)i * p.nphi;
@@ -467,10 +483,10 @@ int build_jobs(Plan &p)
         b.k[0] = 1;
         b.dst[0] = (int64_t)((size_t)p.ntheta + i) * p.nphi;
         if (i == 0 || i == p.ntheta - 1) {
-            b.src = (int64_t)((size_t)(1 * p.ntheta + i) * row);
+            b.src = (int64_t)((size_t)(1 * p.ntheta + i) * rowp);
             b.scale[0] = (i == 0) ? 1.0 : -1.0;
         } else {
-            b.src = (int64_t)((size_t)(0 * p.ntheta + i) * row);
+            b.src = (int64_t)((size_t)(0 * p.ntheta + i) * rowp);
             b.scale[0] = 1.0 / std::sin(M_PI * (double)i / (double)(p.ntheta - 1));
         }
         jd[2 * i + 1] = b;
@@ -585,7 +601,7 @@ int check_plan(tl_plan plan)
     return TL_OK;
 }
 
-void *fphi_slot(Plan &p, int q) { return (char *)p.Fphi.ptr + (size_t)q * 2 * p.ntheta * (p.lmax + 1) * 16; }
+void *fphi_slot(Plan &p, int q) { return (char *)p.Fphi.ptr + (size_t)q * 2 * p.ntheta * (p.lmax_phi + 1) * 16; }
 
 // lam / lam' sums of the lensing potentials P[0..n) (NULL entries skipped)
 // into fphi_slot(q) by the direct FP64 kernel, realizations sharing the
@@ -599,7 +615,7 @@ int defl_legendre(Plan &p, int n, const void *const *P, bool caps_only)
     auto flush = [&]() -> int {
         if (!set.n) return TL_OK;
         StageScope sc(p, ST_DEFL_LEG);
-        TL_HIP(launch_legendre_scalar_set(p, 1, rend, set, true), "deflection legendre");
+        TL_HIP(launch_legendre_scalar_set(p, 1, rend, set, true, true), "deflection legendre");
         set = DirectSet{};
         return TL_OK;
     };
@@ -625,7 +641,8 @@ int defl_fft(Plan &p, const void *alm_phi, int q, void *alpha = nullptr)
         return TL_OK;
     }
     StageScope sc(p, ST_DEFL_FFT);
-    TL_HIP(launch_fft_jobs(p, fphi_slot(p, q), alpha, (const FftJob *)p.jobsDefl.ptr, p.njobsDefl, true, 0),
+    TL_HIP(launch_fft_jobs(p, fphi_slot(p, q), alpha, (const FftJob *)p.jobsDefl.ptr, p.njobsDefl, true, 0, nullptr,
+                           p.lmax_phi),
            "deflection fft");
     return TL_OK;
 }
@@ -646,7 +663,7 @@ int run_deflection(Plan &p, const void *alm_phi)
 // against the steep gradients of the band-limited fields.
 bool fold_deflection(const Plan &p, int n, const void *const *P)
 {
-    if (!(p.tables && p.ntile > 0) || !P) return false;
+    if (!(p.tables && p.ntile > 0) || !P || p.phi_tables()) return false;
     if (p.precision != TL_BF16X3 && p.precision != TL_FP16X2) return false;
     for (int i = 0; i < n; ++i)
         if (!P[i]) return false;
@@ -1191,6 +1208,7 @@ struct BatchStreams {
 void plan_fields(Plan &p, int32_t lmax, tl_grid grid, const tl_options *opt, void *hip_stream, int nside = 0)
 {
     p.lmax = lmax;
+    p.lmax_phi = opt->lmax_phi > 0 ? opt->lmax_phi : lmax;
     p.nside = nside;
     if (nside) {
         grid.ntheta = 4 * nside - 1;  // HEALPix rings; nphi = the longest ring
@@ -1320,7 +1338,9 @@ std::vector<BufItem> plan_buffer_list(Plan &p, const Sizes &sz)
             {&p.moff, sz.moff, "moff"},      {&p.kstart, sz.kstart, "kstart"}, {&p.rhs, sz.rhs, "rhs"},
             {&p.colexp, sz.colexp, "colexp"}, {&p.tabsum, sz.tabsum, "tabsum"}, {&p.hring, sz.hring, "hring"},
             {&p.twP64, sz.twP64, "twP64"},   {&p.twP32, sz.twP32, "twP32"},   {&p.bhat64, sz.bhat64, "bhat64"},
-            {&p.bhat32, sz.bhat32, "bhat32"}, {&p.D2, sz.D2, "D2"},       {&p.alpha2, sz.alpha2, "alpha2"}};
+            {&p.bhat32, sz.bhat32, "bhat32"}, {&p.D2, sz.D2, "D2"},       {&p.alpha2, sz.alpha2, "alpha2"},
+            {&p.coefP0, sz.coefP, "coefP0"}, {&p.coefP2, sz.coefP, "coefP2"}, {&p.startP, sz.startP, "startP"},
+            {&p.expsP, sz.expsP, "expsP"},   {&p.mcutP, sz.mcutP, "mcutP"}};
 }
 
 // Everything a plan computes into its buffers once they exist: angle and
@@ -1481,6 +1501,8 @@ int tl_plan_create_healpix(tl_plan *out, int32_t lmax, int32_t nside, const tl_o
     int32_t n2 = 8;  // a power of two >= 2 lmax stands in for the ring length
     while (n2 < 2 * (int64_t)lmax && n2 < (1 << 30)) n2 *= 2;
     tl_grid g{3, n2};
+    if (opt && opt->lmax_phi != 0 && opt->lmax_phi != lmax)
+        return fail(TL_ERR_UNSUPPORTED, "a separate lmax_phi is not supported on HEALPix rings");
     int rc = validate_options(lmax, g, opt);
     if (rc) return rc;
     tl_plan_s *h = new (std::nothrow) tl_plan_s();

@@ -739,13 +739,29 @@ hipError_t start_tables_J(Plan &p)
 // 8 (J + 1) VGPRs each) within the 256-VGPR budget of 512-thread workgroups.
 constexpr int rhs_max(int J) { return J == 0 ? 5 : J <= 2 ? 4 : J <= 4 ? 3 : J <= 6 ? 2 : 1; }
 
-template <int J, int NB, typename FT>
-hipError_t scalar_JN(Plan &p, int rend, const DirectSet &set)
+// The recursion tables a direct spin-0 launch walks: the plan's, or the
+// lensing potential's own (band limit lmax_phi, derivative entries of J = 1).
+struct RecTab {
+    int lmax, jtab;
+    const double4 *coef0;
+    const double *start;
+    const int *exps, *mcut;
+};
+RecTab rec_tab(const Plan &p, bool phi)
 {
-    dim3 grid((rend + 63) / 64, (p.lmax + 1 + 7) / 8);
-    hipLaunchKernelGGL((k_legendre_scalar<J, NB, FT>), grid, dim3(512), 0, p.stream, p.lmax, p.ntheta, p.nrp, rend,
-                       p.jtab, (const double2 *)p.trig.ptr, (const double4 *)p.coef0.ptr,
-                       (const double *)p.start.ptr, (const int *)p.exps.ptr, (const int *)p.mcut.ptr, set);
+    if (phi && p.phi_tables())
+        return RecTab{p.lmax_phi, 2, (const double4 *)p.coefP0.ptr, (const double *)p.startP.ptr,
+                      (const int *)p.expsP.ptr, (const int *)p.mcutP.ptr};
+    return RecTab{p.lmax, p.jtab, (const double4 *)p.coef0.ptr, (const double *)p.start.ptr, (const int *)p.exps.ptr,
+                  (const int *)p.mcut.ptr};
+}
+
+template <int J, int NB, typename FT>
+hipError_t scalar_JN(Plan &p, int rend, const DirectSet &set, const RecTab &t)
+{
+    dim3 grid((rend + 63) / 64, (t.lmax + 1 + 7) / 8);
+    hipLaunchKernelGGL((k_legendre_scalar<J, NB, FT>), grid, dim3(512), 0, p.stream, t.lmax, p.ntheta, p.nrp, rend,
+                       t.jtab, (const double2 *)p.trig.ptr, t.coef0, t.start, t.exps, t.mcut, set);
     return hipGetLastError();
 }
 
@@ -866,16 +882,16 @@ hipError_t caps_JH(Plan &p, int rend, const CapsArgs &a, int nreal, hipStream_t 
 }
 
 template <int J, typename FT>
-hipError_t scalar_J(Plan &p, int rend, const DirectSet &set)
+hipError_t scalar_J(Plan &p, int rend, const DirectSet &set, const RecTab &t)
 {
     if (rend <= 0 || set.n <= 0) return hipSuccess;
     constexpr int MX = scalar_nb<J, FT>();
     switch (set.n) {
-    case 1: return scalar_JN<J, 1, FT>(p, rend, set);
-    case 2: if constexpr (MX >= 2) return scalar_JN<J, 2, FT>(p, rend, set); break;
-    case 3: if constexpr (MX >= 3) return scalar_JN<J, 3, FT>(p, rend, set); break;
-    case 4: if constexpr (MX >= 4) return scalar_JN<J, 4, FT>(p, rend, set); break;
-    case 5: if constexpr (MX >= 5) return scalar_JN<J, 5, FT>(p, rend, set); break;
+    case 1: return scalar_JN<J, 1, FT>(p, rend, set, t);
+    case 2: if constexpr (MX >= 2) return scalar_JN<J, 2, FT>(p, rend, set, t); break;
+    case 3: if constexpr (MX >= 3) return scalar_JN<J, 3, FT>(p, rend, set, t); break;
+    case 4: if constexpr (MX >= 4) return scalar_JN<J, 4, FT>(p, rend, set, t); break;
+    case 5: if constexpr (MX >= 5) return scalar_JN<J, 5, FT>(p, rend, set, t); break;
     default: break;
     }
     return hipErrorInvalidValue;
@@ -935,6 +951,20 @@ hipError_t launch_tables(Plan &p)
     hipLaunchKernelGGL(k_mcut, grid, dim3(256), 0, p.stream, p.lmax, p.nrp, p.jtab, (const double2 *)p.trig.ptr,
                        (const double4 *)p.coef0.ptr, (const double *)p.start.ptr, (const int *)p.exps.ptr,
                        (int *)p.mcut.ptr);
+    e = hipGetLastError();
+    if (e != hipSuccess || !p.phi_tables()) return e;
+    // the lensing potential's tables at its own band limit (spin 0, J = 1)
+    const int L = p.lmax_phi;
+    hipLaunchKernelGGL(k_coef, dim3((L + 1 + 255) / 256, L + 1), dim3(256), 0, p.stream, L, (double4 *)p.coefP0.ptr,
+                       (double4 *)p.coefP2.ptr);
+    hipLaunchKernelGGL((k_start<1>), dim3((p.nrp + 63) / 64, 3), dim3(64), 0, p.stream, L, p.nrp, 2,
+                       (const double2 *)p.trig.ptr, (const double *)p.theta.ptr, (double *)p.startP.ptr,
+                       (int *)p.expsP.ptr);
+    e = hipMemsetAsync(p.mcutP.ptr, 0xff, p.mcutP.bytes, p.stream);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_mcut, dim3((p.nrp + 255) / 256, L + 1), dim3(256), 0, p.stream, L, p.nrp, 2,
+                       (const double2 *)p.trig.ptr, (const double4 *)p.coefP0.ptr, (const double *)p.startP.ptr,
+                       (const int *)p.expsP.ptr, (int *)p.mcutP.ptr);
     return hipGetLastError();
 }
 
@@ -994,10 +1024,12 @@ hipError_t launch_legendre_caps(Plan &p, int rend, const CapsArgs &a, int nreal,
 #undef TL_CAPS
 }
 
-hipError_t launch_legendre_scalar_set(Plan &p, int J, int rend, const DirectSet &set, bool out64)
+hipError_t launch_legendre_scalar_set(Plan &p, int J, int rend, const DirectSet &set, bool out64, bool phi)
 {
+    const RecTab t = rec_tab(p, phi);
+    if (phi && p.phi_tables() && J > 1) return hipErrorInvalidValue;  // its tables hold J <= 1
 #define TL_CASE(JJ) \
-    case JJ: return out64 ? scalar_J<JJ, double>(p, rend, set) : scalar_J<JJ, float>(p, rend, set);
+    case JJ: return out64 ? scalar_J<JJ, double>(p, rend, set, t) : scalar_J<JJ, float>(p, rend, set, t);
     switch (J) {
         TL_CASE(0)
         TL_CASE(1)

@@ -1224,23 +1224,25 @@ hipError_t fft_prepare(Plan &p)
 }
 
 template <typename R, int M>
-hipError_t launch_p2(Plan &p, const void *Fbase, void *Dbase, void *D16, const FftJob *jobs, int njobs, const void *tw)
+hipError_t launch_p2(Plan &p, const void *Fbase, void *Dbase, void *D16, const FftJob *jobs, int njobs, const void *tw,
+                     int L)
 {
     using V = typename C2<R>::T;
     const size_t shm = p2_lds<R>(M);
     hipLaunchKernelGGL((k_ring_fft_p2<R, M>), dim3(njobs), dim3(256), shm, p.stream, jobs, (const V *)Fbase,
-                       (R *)Dbase, (__half *)D16, p.lmax, (const V *)tw);
+                       (R *)Dbase, (__half *)D16, L, (const V *)tw);
     return hipGetLastError();
 }
 
 template <typename R>
-hipError_t launch_p2_R(Plan &p, const void *Fbase, void *Dbase, void *D16, const FftJob *jobs, int njobs, const void *tw, int M)
+hipError_t launch_p2_R(Plan &p, const void *Fbase, void *Dbase, void *D16, const FftJob *jobs, int njobs, const void *tw,
+                       int M, int L)
 {
     switch (M) {
-    case 512: return launch_p2<R, 512>(p, Fbase, Dbase, D16, jobs, njobs, tw);
-    case 1024: return launch_p2<R, 1024>(p, Fbase, Dbase, D16, jobs, njobs, tw);
-    case 2048: return launch_p2<R, 2048>(p, Fbase, Dbase, D16, jobs, njobs, tw);
-    case 4096: return launch_p2<R, 4096>(p, Fbase, Dbase, D16, jobs, njobs, tw);
+    case 512: return launch_p2<R, 512>(p, Fbase, Dbase, D16, jobs, njobs, tw, L);
+    case 1024: return launch_p2<R, 1024>(p, Fbase, Dbase, D16, jobs, njobs, tw, L);
+    case 2048: return launch_p2<R, 2048>(p, Fbase, Dbase, D16, jobs, njobs, tw, L);
+    case 4096: return launch_p2<R, 4096>(p, Fbase, Dbase, D16, jobs, njobs, tw, L);
     default: return hipErrorInvalidValue;
     }
 }
@@ -1248,9 +1250,10 @@ hipError_t launch_p2_R(Plan &p, const void *Fbase, void *Dbase, void *D16, const
 bool fft_p2(int M) { return M == 512 || M == 1024 || M == 2048 || M == 4096; }
 
 hipError_t launch_fft_jobs(Plan &p, const void *Fbase, void *Dbase, const FftJob *jobs, int njobs, bool fp64,
-                           int list, void *D16)
+                           int list, void *D16, int L)
 {
     if (njobs <= 0) return hipSuccess;
+    if (L < 0) L = p.lmax;
     if (p.nside) {
         if (list < 0 || list > 1) return hipErrorInvalidValue;
         return fp64 ? launch_hpx<double>(p, Fbase, Dbase, D16, jobs, njobs, list)
@@ -1258,8 +1261,8 @@ hipError_t launch_fft_jobs(Plan &p, const void *Fbase, void *Dbase, const FftJob
     }
     const int M = p.nphi / 2;
     if (fft_p2(M)) {
-        if (fp64) return launch_p2_R<double>(p, Fbase, Dbase, D16, jobs, njobs, p.twid64.ptr, M);
-        return launch_p2_R<float>(p, Fbase, Dbase, D16, jobs, njobs, p.twid32.ptr, M);
+        if (fp64) return launch_p2_R<double>(p, Fbase, Dbase, D16, jobs, njobs, p.twid64.ptr, M, L);
+        return launch_p2_R<float>(p, Fbase, Dbase, D16, jobs, njobs, p.twid32.ptr, M, L);
     }
     Radices rad;
     rad.n = p.nradix;
@@ -1267,12 +1270,12 @@ hipError_t launch_fft_jobs(Plan &p, const void *Fbase, void *Dbase, const FftJob
     if (fp64) {
         size_t shm = 2 * (size_t)M * sizeof(double2);
         hipLaunchKernelGGL(k_ring_fft<double>, dim3(njobs), dim3(256), shm, p.stream, jobs,
-                           (const double2 *)Fbase, (double *)Dbase, (__half *)D16, p.lmax, M,
+                           (const double2 *)Fbase, (double *)Dbase, (__half *)D16, L, M,
                            (const double2 *)p.twid64.ptr, rad);
     } else {
         size_t shm = 2 * (size_t)M * sizeof(float2);
         hipLaunchKernelGGL(k_ring_fft<float>, dim3(njobs), dim3(256), shm, p.stream, jobs,
-                           (const float2 *)Fbase, (float *)Dbase, (__half *)D16, p.lmax, M, (const float2 *)p.twid32.ptr,
+                           (const float2 *)Fbase, (float *)Dbase, (__half *)D16, L, M, (const float2 *)p.twid32.ptr,
                            rad);
     }
     return hipGetLastError();

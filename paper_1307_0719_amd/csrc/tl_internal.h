@@ -123,6 +123,7 @@ inline int hpx_class_of_P(int P)
 
 struct Plan {
     int lmax = 0;
+    int lmax_phi = 0;  // band limit of the lensing potential (>= lmax)
     int nside = 0;    // > 0: HEALPix rings (RING order) instead of the equal-theta grid
     int ntheta = 0, nphi = 0;
     int nrp = 0;      // ring pairs = ceil(ntheta/2)
@@ -158,6 +159,10 @@ struct Plan {
     DevBuf start;     // double [3][lmax+1][jtab][nrp]
     DevBuf exps;      // int    [3][lmax+1][nrp]
     DevBuf mcut;      // int    [nrp]  largest significant m per ring pair
+    // the same recursion tables for the lensing potential when lmax_phi >
+    // lmax (spin 0, derivative entries of J = 1: jtab 2)
+    DevBuf coefP0, coefP2, startP, expsP, mcutP;
+    bool phi_tables() const { return lmax_phi != lmax; }
     DevBuf hring;     // HRing [ntheta] (HEALPix plans)
     DevBuf twP64;     // double2 [8192] e^{2 pi i t / 8192} (HEALPix plans with Bluestein rings)
     DevBuf twP32;     // float2  [8192]
@@ -249,7 +254,9 @@ struct DirectSet {
 hipError_t launch_tables(Plan &p);
 // most realizations one direct launch takes at derivative order J
 int direct_max(int J, bool spin, bool hasb, bool out64);
-hipError_t launch_legendre_scalar_set(Plan &p, int J, int rend, const DirectSet &set, bool out64);
+// phi: the lensing potential's band limit and tables (Plan::phi_tables)
+hipError_t launch_legendre_scalar_set(Plan &p, int J, int rend, const DirectSet &set, bool out64,
+                                      bool phi = false);
 hipError_t launch_legendre_spin_set(Plan &p, int J, int rend, const DirectSet &set, bool out64);
 hipError_t launch_legendre_scalar(Plan &p, int J, int rend, const void *alm, void *F, bool out64);
 hipError_t launch_legendre_spin(Plan &p, int J, int rend, const void *almE, const void *almB, void *FQ,
@@ -338,8 +345,10 @@ hipError_t fill_words(void *x, size_t n, uint32_t v, hipStream_t st);
 // list: 0 = the deflection jobs, 1 = the main jobs (HEALPix plans launch each
 // job class of the list on its own)
 bool fft_p2(int M);  // rings of 2 M points take the one-workgroup radix-16 kernel
+// L: band limit of the rows (default the plan's lmax; the deflection's rows
+// have lmax_phi + 1 entries); equal-theta plans
 hipError_t launch_fft_jobs(Plan &p, const void *Fbase, void *Dbase, const FftJob *jobs, int njobs,
-                           bool fp64, int list, void *D16 = nullptr);
+                           bool fp64, int list, void *D16 = nullptr, int L = -1);
 // HEALPix: chirp spectra of the Bluestein ring lengths (items {M, class P, boff})
 hipError_t launch_bluestein_tables(Plan &p, const std::vector<int4> &items);
 // D: the plan's own maps (padded, maybe mixed) or a caller's ([field][map][pixel]);

@@ -61,7 +61,7 @@ class Grid(ctypes.Structure):
 class Options(ctypes.Structure):
     _fields_ = [("order", ctypes.c_int32), ("precision", ctypes.c_int32), ("pol", ctypes.c_int32),
                 ("rotate", ctypes.c_int32), ("naive_pos", ctypes.c_int32), ("batch", ctypes.c_int32),
-                ("workspace_cap", ctypes.c_int64), ("maps16", ctypes.c_int32)]
+                ("workspace_cap", ctypes.c_int64), ("maps16", ctypes.c_int32), ("lmax_phi", ctypes.c_int32)]
 
 
 class BatchOptions(ctypes.Structure):
@@ -150,14 +150,16 @@ class Plan:
     def __init__(self, lmax: int, ntheta: int, nphi: int, order: int, precision: str = "fp32",
                  pol: bool = True, rotate: bool = True, naive_pos: bool = False, workspace_cap: int = 0,
                  device: Optional[torch.device] = None, stream: Optional[torch.cuda.Stream] = None,
-                 batch: int = 1, nside: int = 0, maps16: bool = False):
+                 batch: int = 1, nside: int = 0, maps16: bool = False, lmax_phi: int = 0):
         """ntheta x nphi equal-theta grid, or with nside > 0 HEALPix rings
         (ntheta, nphi ignored; maps are [12 nside^2] in RING order).  maps16:
-        internal derivative maps of order j + k >= 3 in FP16 (see tl_options)."""
+        internal derivative maps of order j + k >= 3 in FP16; lmax_phi: band
+        limit of the lensing potential, 0 = lmax (see tl_options)."""
         self.nside = int(nside)
         if self.nside:
             ntheta, nphi = 4 * self.nside - 1, 4 * self.nside
         self.lmax, self.ntheta, self.nphi, self.order = int(lmax), int(ntheta), int(nphi), int(order)
+        self.lmax_phi = int(lmax_phi) if lmax_phi else self.lmax
         self.npix = 12 * self.nside ** 2 if self.nside else self.ntheta * self.nphi
         self.precision = precision
         self.pol = bool(pol)
@@ -166,7 +168,7 @@ class Plan:
         if precision not in PRECISIONS:
             raise ValueError(f"unknown precision {precision}")
         opt = Options(order, PRECISIONS[precision], int(pol), int(rotate), int(naive_pos), int(batch),
-                      int(workspace_cap), int(maps16))
+                      int(workspace_cap), int(maps16), int(lmax_phi))
         self.batch = int(batch)
         h = ctypes.c_void_p()
         with torch.cuda.device(self.device):
@@ -245,7 +247,7 @@ class Plan:
     def lens_map(self, alm_T, alm_E=None, alm_B=None, alm_phi=None, out=None):
         """Lensed (T, Q, U) maps; Q/U are None for a T-only plan."""
         T, E, B = self._inputs(alm_T, alm_E, alm_B)
-        P = _alm(alm_phi, "alm_phi", self.device, self.lmax)
+        P = _alm(alm_phi, "alm_phi", self.device, self.lmax_phi)
         if out is None:
             out = (self._maps(), self._maps() if self.pol else None, self._maps() if self.pol else None)
         _check(lib().tl_lens_map(self._h, _ptr(T), _ptr(E), _ptr(B), _ptr(P), _ptr(out[0]), _ptr(out[1]),
@@ -264,7 +266,7 @@ class Plan:
                     for _ in range(n)]
         for i, a in enumerate(alms):
             T, E, B = self._inputs(a[0], a[1], a[2])
-            P = _alm(a[3], "alm_phi", self.device, self.lmax)
+            P = _alm(a[3], "alm_phi", self.device, self.lmax_phi)
             keep.append((T, E, B, P))
             for q, t in enumerate((T, E, B, P)):
                 aarr[4 * i + q] = t.data_ptr() if t is not None else None
@@ -286,7 +288,7 @@ class Plan:
         return out
 
     def deflection(self, alm_phi):
-        P = _alm(alm_phi, "alm_phi", self.device, self.lmax)
+        P = _alm(alm_phi, "alm_phi", self.device, self.lmax_phi)
         at = torch.empty(self.map_shape, dtype=torch.float64, device=self.device)
         ap = torch.empty_like(at)
         _check(lib().tl_deflection(self._h, _ptr(P), _ptr(at), _ptr(ap)))
@@ -401,7 +403,7 @@ class Cnn:
     def lens_map(self, plan: Plan, alm_T, alm_E, alm_B, alm_phi, out=None):
         """Order-2 lensing of plan with the network's correction."""
         T, E, B = plan._inputs(alm_T, alm_E, alm_B)
-        P = _alm(alm_phi, "alm_phi", plan.device, plan.lmax)
+        P = _alm(alm_phi, "alm_phi", plan.device, plan.lmax_phi)
         if out is None:
             out = (plan._maps(), plan._maps(), plan._maps())
         _check(lib().tl_lens_map_cnn(plan.handle, self._h, _ptr(T), _ptr(E), _ptr(B), _ptr(P), _ptr(out[0]),
@@ -478,7 +480,7 @@ def lens_map_batch(plans: Sequence[Plan], alms: Sequence[tuple], outs: Sequence[
     oarr = (ctypes.c_void_p * (3 * n))()
     for i, (p, a, o) in enumerate(zip(plans, alms, outs)):
         T, E, B = p._inputs(a[0], a[1], a[2])
-        P = _alm(a[3], "alm_phi", p.device, p.lmax)
+        P = _alm(a[3], "alm_phi", p.device, p.lmax_phi)
         keep.append((T, E, B, P))
         for q, t in enumerate((T, E, B, P)):
             aarr[4 * i + q] = t.data_ptr() if t is not None else None

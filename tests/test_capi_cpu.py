@@ -33,9 +33,9 @@ def test_every_declared_symbol_is_exported(tl):
     assert tl.version() == 10000
 
 
-def _create(tl, lmax, ntheta, nphi, order=3, prec=1, pol=1, rotate=1, naive=0, batch=0, cap=0, maps16=0):
+def _create(tl, lmax, ntheta, nphi, order=3, prec=1, pol=1, rotate=1, naive=0, batch=0, cap=0, maps16=0, lmax_phi=0):
     h = ctypes.c_void_p(123)
-    o = tl.Options(order, prec, pol, rotate, naive, batch, cap, maps16)
+    o = tl.Options(order, prec, pol, rotate, naive, batch, cap, maps16, lmax_phi)
     rc = tl.lib().tl_plan_create(ctypes.byref(h), lmax, tl.Grid(ntheta, nphi), ctypes.byref(o), None)
     return rc, h, tl.lib().tl_last_error().decode()
 
@@ -45,7 +45,9 @@ def _create(tl, lmax, ntheta, nphi, order=3, prec=1, pol=1, rotate=1, naive=0, b
     ((10, 11, 20, 9), -1), ((10, 11, 20, -1), -1), ((10, 11, 20, 3, 7), -1), ((10, 11, 20, 7, 4), -2), ((10, 11, 20, 4, 4, 1, 1, 0, 7), -1),
     ((10, 11, 20, 3, 1, 2), -1), ((10, 11, 20, 3, 1, 1, 5), -1), ((10, 11, 20, 3, 1, 1, 1, 3), -1),
     ((10, 11, 20, 3, 1, 1, 0, 0, 2), -1), ((10, 11, 20, 3, 1, 1, 0, 0, 0, -5), -1),
-    ((64, 65, 128, 3, 1, 1, 1, 0, 0, 1000), -4), ((10, 11, 20, 3, 1, 1, 1, 0, 0, 0, 2), -1)])
+    ((64, 65, 128, 3, 1, 1, 1, 0, 0, 1000), -4), ((10, 11, 20, 3, 1, 1, 1, 0, 0, 0, 2), -1),
+    ((10, 11, 20, 3, 1, 1, 1, 0, 0, 0, 0, 9), -1), ((10, 11, 20, 3, 1, 1, 1, 0, 0, 0, 0, 11), -1),
+    ((10, 11, 40000, 3, 1, 1, 1, 0, 0, 0, 0, 20000), -2)])
 def test_invalid_plan_arguments(tl, args, code):
     rc, h, msg = _create(tl, *args)
     assert rc == code, msg
@@ -113,4 +115,7 @@ def test_healpix_plan_arguments(tl):
     assert L.tl_plan_create_healpix(ctypes.byref(h), 16, 4096, ctypes.byref(o), None) == tl.TL_ERR_UNSUPPORTED
     bad = tl.Options(9, 1, 1, 1, 0, 0, 0)
     assert L.tl_plan_create_healpix(ctypes.byref(h), 16, 4, ctypes.byref(bad), None) == tl.TL_ERR_INVALID
+    # the potential's own band limit is an equal-theta feature
+    sep = tl.Options(3, 1, 1, 1, 0, 0, 0, 0, 24)
+    assert L.tl_plan_create_healpix(ctypes.byref(h), 16, 4, ctypes.byref(sep), None) == tl.TL_ERR_UNSUPPORTED
     assert not h.value

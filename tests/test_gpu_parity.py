@@ -350,3 +350,36 @@ def test_invalid_arguments_report_errors(tl):
     with pytest.raises(tl.TaylensError) as e:
         tl.Plan(64, 65, 128, 3, "fp32", workspace_cap=1000)
     assert e.value.code == tl.TL_ERR_NOMEM
+
+
+@pytest.mark.parametrize("precision,batch,nphi", [("fp64", 1, 192), ("fp32", 1, 192), ("fp16x2", 2, 192),
+                                                  ("fp32", 1, 1024), ("fp16x2", 3, 1024)])
+def test_deflection_band_limit_above_the_fields(tl, oracle, precision, batch, nphi):
+    """A lensing potential of lmax_phi = 80 beside fields of lmax 48 (Sec.
+    II.A): the deflection (the direct FP64 recursion at the potential's own
+    band limit on every ring, also for the tabulated forms) and the lensed
+    maps against the oracle, on ring lengths of the mixed-radix and the
+    radix-16 FFTs; realizations of one table pass agree with single calls."""
+    lmax, lmax_phi, ntheta, order = 48, 80, 49, 3
+    rms = 1.5 * (math.pi / (ntheta - 1)) / skygen.ARCMIN
+    skies = [skygen.make_sky(lmax, 70 + i, pol=True, rms_arcmin=rms) for i in range(batch)]
+    phis = [skygen.make_sky(lmax_phi, 80 + i, pol=False, rms_arcmin=rms).alm_phi for i in range(batch)]
+    plan = tl.Plan(lmax, ntheta, nphi, order, precision, pol=True, batch=batch, lmax_phi=lmax_phi)
+    at, ap = plan.deflection(phis[0])
+    ot, op = oracle.deflection_rings(lmax, phis[0], ntheta, nphi, np.arange(ntheta), ORACLE_THREADS)
+    assert max_rel(t2np(at), ot) < 1e-11 and max_rel(t2np(ap), op) < 1e-11
+    alms = [(s.alm_T, s.alm_E, None, ph) for s, ph in zip(skies, phis)]
+    got = plan.lens_map_many(alms) if batch > 1 else [plan.lens_map(*alms[0])]
+    tol = {"fp64": 1e-11, "fp32": 1e-5, "fp16x2": 1e-5}[precision]
+    for i in (0, batch - 1):
+        ref = oracle.lens_map(lmax, order, ntheta, nphi, skies[i].alm_T, skies[i].alm_E, None, phis[i],
+                              nthreads=ORACLE_THREADS)
+        mask = ref["_tie"] > 1e-9
+        for f, g in zip("TQU", got[i]):
+            e = rel_rms(t2np(g), ref[f], mask)
+            assert e < tol, (precision, i, f, e)
+    if batch > 1:
+        for a, s in zip(got, alms):
+            for x, y in zip(a, plan.lens_map(*s)):
+                assert torch.equal(x, y)
+    plan.close()

@@ -378,3 +378,37 @@ def test_p10_exact_lensing_is_the_brute_force_sum_at_the_displaced_positions(ora
     un = oracle.unlensed_map(lmax, ntheta, nphi, sky.alm_T, sky.alm_E, almB)
     for f in "TQU":
         np.testing.assert_allclose(z[f], un[f][rings, cols], rtol=0, atol=1e-13 * supT)
+
+
+def test_p11_deflection_band_limit_above_the_fields(oracle):
+    """A lensing potential of higher band limit than the fields (Sec. II.A):
+    lensing fields of lmax 24 with a potential of lmax 40 equals lensing the
+    same fields zero-padded to lmax 40, bit for bit; the deflection takes the
+    potential's own band limit, which lmax_of reads from the array (and
+    refuses for a non-triangular length)."""
+    L, Lp = 24, 40
+    ntheta, nphi = 2 * Lp + 1, 2 * Lp + 16
+    sky = skygen.make_sky(L, 61, pol=True, rms_arcmin=1.5 * (math.pi / (ntheta - 1)) / skygen.ARCMIN)
+    phi = skygen.make_sky(Lp, 62, pol=False, rms_arcmin=1.5 * (math.pi / (ntheta - 1)) / skygen.ARCMIN).alm_phi
+
+    def pad(a):
+        out = np.zeros((Lp + 1) * (Lp + 2) // 2, np.complex128)
+        for m in range(L + 1):
+            out[m * (2 * Lp + 1 - m) // 2 + m: m * (2 * Lp + 1 - m) // 2 + L + 1] = \
+                a[m * (2 * L + 1 - m) // 2 + m: m * (2 * L + 1 - m) // 2 + L + 1]
+        return out
+
+    assert oracle.lmax_of(phi) == Lp and oracle.lmax_of(sky.alm_T) == L
+    with pytest.raises(ValueError):
+        oracle.lmax_of(np.zeros(7))
+    a = oracle.lens_map(L, 3, ntheta, nphi, sky.alm_T, sky.alm_E, None, phi)
+    b = oracle.lens_map(Lp, 3, ntheta, nphi, pad(sky.alm_T), pad(sky.alm_E), None, phi)
+    for f in "TQU":
+        np.testing.assert_array_equal(a[f], b[f])
+    # the potential's modes above the fields' band limit move pixels
+    cut = phi.copy()
+    for m in range(Lp + 1):
+        for l in range(max(m, L + 1), Lp + 1):
+            cut[m * (2 * Lp + 1 - m) // 2 + l] = 0
+    c = oracle.lens_map(L, 3, ntheta, nphi, sky.alm_T, sky.alm_E, None, cut)
+    assert np.max(np.abs(c["_alpha_theta"] - a["_alpha_theta"])) > 1e-3 * np.max(np.abs(a["_alpha_theta"]))
