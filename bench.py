@@ -431,20 +431,20 @@ def sweep_sample(lmax: int, nring: int = 16, ncol: int = 32):
 
 
 def sweep_best(rows, targets=(1e-2, 1e-3, 1e-4, 1e-5, 1e-6)):
-    """For each lmax and error target, the fastest row (time per map) whose
-    worst field error is within the target: the structure of the paper's
-    fastest-settings table."""
+    """For each lmax (and band limit of the potential) and error target,
+    the fastest row (time per map) whose worst field error is within the
+    target: the structure of the paper's fastest-settings table."""
     out = []
-    for lmax in sorted({r["lmax"] for r in rows}):
+    key = lambda r: (r["lmax"], r.get("lmax_phi", r["lmax"]))
+    for lmax, lphi in sorted({key(r) for r in rows}):
         for t in targets:
-            ok = [r for r in rows if r["lmax"] == lmax and r["rel_rms_err_max"] <= t]
+            ok = [r for r in rows if key(r) == (lmax, lphi) and r["rel_rms_err_max"] <= t]
             if not ok:
-                out.append({"lmax": lmax, "target": t, "row": None})
+                out.append({"lmax": lmax, "lmax_phi": lphi, "target": t, "row": None})
                 continue
             b = min(ok, key=lambda r: r["ms_per_map"])
-            out.append({"lmax": lmax, "target": t, "row": {k: b[k] for k in
-                                                           ("oversampling", "order", "form", "ms_per_map",
-                                                            "rel_rms_err_max")}})
+            out.append({"lmax": lmax, "lmax_phi": lphi, "target": t,
+                        "row": {k: b[k] for k in ("oversampling", "order", "form", "ms_per_map", "rel_rms_err_max")}})
     return out
 
 
@@ -456,7 +456,10 @@ def bench_sweep(args):
     form with six realizations per table pass (FP16 maps of order >= 3;
     skipped where its tables do not fit), and the relative RMS error of realization 0 against the exact
     lensed field (the unlensed field synthesized at each displaced position,
-    rotated) at a fixed sample of sky positions shared by every grid."""
+    rotated) at a fixed sample of sky positions shared by every grid.  With
+    a phi factor F > 1 the lensing potential has its own band limit F lmax
+    (lmax_phi, on grids of oversampling >= F), the paper's higher band limit
+    of the deflection."""
     import numpy as np
     import torch
 
@@ -473,20 +476,30 @@ def bench_sweep(args):
     lmaxes = [int(x) for x in args.sweep_lmax.split(",")]
     gs = [int(x) for x in args.sweep_oversampling.split(",")]
     orders = [int(x) for x in args.sweep_orders.split(",")]
+    phifs = [int(x) for x in args.sweep_phi_factor.split(",")]
     rows = []
-    for lmax in lmaxes:
+    for lmax, fphi in [(l, f) for l in lmaxes for f in phifs]:
+        lphi = fphi * lmax  # the potential's band limit: rings of 2 g lmax >= 2 lmax_phi points
+        gl = [g for g in gs if g >= fphi]
+        if not gl:
+            continue
         skies = [skygen.make_sky(lmax, 30 + i, pol=True) for i in range(6)]
+        if fphi > 1:
+            for i, s in enumerate(skies):
+                s.alm_phi = skygen.make_sky(lphi, 40 + i, pol=False).alm_phi
         to_dev = lambda a: None if a is None else torch.from_numpy(a).to(dev)
         sdev = [(to_dev(s.alm_T), to_dev(s.alm_E), None, to_dev(s.alm_phi)) for s in skies]
         R, C = sweep_sample(lmax)
         s0 = skies[0]
         o0 = time.perf_counter()
-        ex = orc.exact_lensed_pixels(lmax, lmax + 1, 2 * lmax, R, C, s0.alm_T, s0.alm_E, None, s0.alm_phi,
-                                     nthreads=ncores)
+        # the same sky positions on the coarsest grid that carries the potential
+        g0 = min(gl)
+        ex = orc.exact_lensed_pixels(lmax, g0 * lmax + 1, 2 * g0 * lmax, g0 * R, g0 * C, s0.alm_T, s0.alm_E, None,
+                                     s0.alm_phi, nthreads=ncores)
         oracle_s = time.perf_counter() - o0
-        print(f"sweep lmax {lmax}: exact reference at {R.size} positions in {oracle_s:.1f} s", file=sys.stderr,
-              flush=True)
-        for g in gs:
+        print(f"sweep lmax {lmax} lmax_phi {lphi}: exact reference at {R.size} positions in {oracle_s:.1f} s",
+              file=sys.stderr, flush=True)
+        for g in gl:
             nt, nph = g * lmax + 1, 2 * g * lmax
             idx = torch.from_numpy(g * R * nph + g * C).to(dev)
             forms = [("fp32", 1), ("fp16x2", 6)]
@@ -494,9 +507,9 @@ def bench_sweep(args):
                 for prec, batch in forms:
                     try:
                         plan = taylens.Plan(lmax, nt, nph, order, prec, pol=True, batch=batch if batch > 1 else 0,
-                                            maps16=prec != "fp32")
+                                            maps16=prec != "fp32", lmax_phi=lphi)
                     except taylens.TaylensError as e:
-                        rows.append({"lmax": lmax, "oversampling": g, "order": order, "form": prec,
+                        rows.append({"lmax": lmax, "lmax_phi": lphi, "oversampling": g, "order": order, "form": prec,
                                      "skipped": str(e)})
                         continue
                     outs = [(plan._maps(), plan._maps(), plan._maps()) for _ in range(batch)]
@@ -523,11 +536,12 @@ def bench_sweep(args):
                         x = t.view(-1)[idx].double().cpu().numpy()
                         y = ex[f]
                         errs[f] = float(np.sqrt(np.mean((x - y) ** 2)) / np.sqrt(np.mean(y ** 2)))
-                    rows.append({"lmax": lmax, "oversampling": g, "ntheta": nt, "nphi": nph, "order": order,
+                    rows.append({"lmax": lmax, "lmax_phi": lphi, "oversampling": g, "ntheta": nt, "nphi": nph,
+                                 "order": order,
                                  "form": prec if batch == 1 else f"{prec}:{batch}+m16",
                                  "ms_per_map": ms / batch, "pixels_per_s": batch * nt * nph / (ms * 1e-3),
                                  "rel_rms_err": errs, "rel_rms_err_max": max(errs.values())})
-                    print(f"sweep lmax {lmax} g {g} order {order} {rows[-1]['form']}: {ms / batch:.2f} ms/map, "
+                    print(f"sweep lmax {lmax}/{lphi} g {g} order {order} {rows[-1]['form']}: {ms / batch:.2f} ms/map, "
                           f"err {rows[-1]['rel_rms_err_max']:.2e}", file=sys.stderr, flush=True)
                     del outs
                     plan.close()
@@ -648,6 +662,8 @@ def main():
     ap.add_argument("--sweep-lmax", default="1024,2048,4096")
     ap.add_argument("--sweep-oversampling", default="1,2")
     ap.add_argument("--sweep-orders", default="1,2,3,4,5,6")
+    ap.add_argument("--sweep-phi-factor", default="1,2",
+                    help="lmax_phi / lmax of the lensing potential (rows on grids of oversampling >= the factor)")
     args = ap.parse_args()
 
     if args.gpus != 1:

@@ -86,3 +86,11 @@ def test_sweep_fastest_settings(bench):
     assert best[1e-2]["order"] == 2 and best[1e-2]["oversampling"] == 1
     assert best[1e-4]["oversampling"] == 2 and best[1e-4]["ms_per_map"] == 3.5
     assert best[1e-6] is None
+
+
+def test_sweep_fastest_settings_per_potential_band_limit(bench):
+    """Rows of a potential with its own band limit form their own table rows."""
+    rows = [{"lmax": 8, "lmax_phi": lp, "oversampling": 2, "order": 3, "form": "fp32", "ms_per_map": t,
+             "rel_rms_err_max": 1e-3} for lp, t in ((8, 1.0), (16, 2.0))]
+    best = bench.sweep_best(rows, targets=(1e-2,))
+    assert [(b["lmax_phi"], b["row"]["ms_per_map"]) for b in best] == [(8, 1.0), (16, 2.0)]
