@@ -115,7 +115,7 @@ void free_plan_buffers(Plan &p)
     DevBuf *bufs[] = {&p.theta, &p.trig, &p.phitab, &p.phival, &p.twid64, &p.twid32, &p.coef0, &p.coef2,
                       &p.start, &p.exps, &p.mcut, &p.tab, &p.moff, &p.kstart, &p.rhs, &p.colexp, &p.tabsum, &p.Fphi, &p.alpha, &p.F, &p.D, &p.jobsDefl, &p.jobsMain, &p.jobsInt, &p.hring,
                       &p.twP64, &p.twP32, &p.bhat64, &p.bhat32, &p.D2, &p.alpha2, &p.coefP0, &p.coefP2,
-                      &p.startP, &p.expsP, &p.mcutP};
+                      &p.startP, &p.expsP, &p.mcutP, &p.dscratch};
     for (DevBuf *b : bufs) free_buf(*b);
     if (p.side) (void)hipStreamSynchronize(p.side);
     for (int i = 0; i < 2; ++i) {
@@ -236,14 +236,22 @@ struct Sizes {
     size_t theta, trig, phitab, phival, twid64, twid32, coef, start, exps, mcut, Fphi, alpha, F, D, jd, jm;
     size_t tab = 0, moff = 0, kstart = 0, rhs = 0, colexp = 0, tabsum = 0, hring = 0;
     size_t twP64 = 0, twP32 = 0, bhat64 = 0, bhat32 = 0, jx = 0, D2 = 0, alpha2 = 0;
-    size_t coefP = 0, startP = 0, expsP = 0, mcutP = 0;
+    size_t coefP = 0, startP = 0, expsP = 0, mcutP = 0, dscratch = 0;
     size_t total() const
     {
         return theta + trig + phitab + phival + twid64 + twid32 + 2 * coef + start + exps + mcut + Fphi + alpha + F +
                D + jd + jm + tab + moff + kstart + rhs + colexp + tabsum + hring + twP64 + twP32 + bhat64 + bhat32 + jx +
-               D2 + alpha2 + 2 * coefP + startP + expsP + mcutP;
+               D2 + alpha2 + 2 * coefP + startP + expsP + mcutP + dscratch;
     }
 };
+
+// Whether a plan's workspace holds the scratch of FP32 deflection FFTs:
+// plans of FP32 maps on equal-theta rings whose FP64 transform (two buffers
+// of nphi / 2 complex) exceeds the 160 KiB of LDS of a gfx950 workgroup.
+bool defl32_sized(const Plan &p)
+{
+    return !p.nside && !p.fp64() && 2 * (size_t)(p.nphi / 2) * sizeof(double2) > (size_t)160 * 1024;
+}
 
 Sizes plan_sizes(const Plan &p)
 {
@@ -302,6 +310,8 @@ Sizes plan_sizes(const Plan &p)
     }
     s.D = p.mix16 ? (size_t)p.nfield() * (mix_n32() * p.dstride * 4 + (p.ndmap() - mix_n32()) * p.dstride16 * 2)
                   : (size_t)p.nfield() * p.ndmap() * p.dstride * rbytes;
+    if (defl32_sized(p))  // FP32 rows and deflection of the FP32 deflection FFTs
+        s.dscratch = (size_t)2 * p.ntheta * (p.lmax_phi + 1) * 2 * sizeof(float) + 2 * p.npix() * sizeof(float);
     if (p.tabform() && p.batch > 1) {  // the second set of maps and deflections
         s.D2 = s.D;
         s.alpha2 = s.alpha;
@@ -641,6 +651,10 @@ int defl_fft(Plan &p, const void *alm_phi, int q, void *alpha = nullptr)
         return TL_OK;
     }
     StageScope sc(p, ST_DEFL_FFT);
+    if (p.defl32) {
+        TL_HIP(launch_defl_fft32(p, fphi_slot(p, q), alpha, p.lmax_phi), "deflection fft");
+        return TL_OK;
+    }
     TL_HIP(launch_fft_jobs(p, fphi_slot(p, q), alpha, (const FftJob *)p.jobsDefl.ptr, p.njobsDefl, true, 0, nullptr,
                            p.lmax_phi),
            "deflection fft");
@@ -1314,7 +1328,11 @@ int plan_device_checks(Plan &p)
                                               (size_t)(p.hmax_pow2 + p.hmax_pow2 / 32)}) *
                                         sizeof(double2)
                                   : 2 * (size_t)(p.nphi / 2) * sizeof(double2);
-    if (need64 > (size_t)smem)
+    // equal-theta rings too long for the FP64 transform: plans of FP32 maps
+    // take the deflection's ring FFTs in FP32 as well
+    const size_t need32 = 2 * (size_t)(p.nphi / 2) * sizeof(float2);
+    p.defl32 = defl32_sized(p) && need64 > (size_t)smem && need32 <= (size_t)smem;
+    if (need64 > (size_t)smem && !p.defl32)
         return fail(TL_ERR_UNSUPPORTED, "nphi too large for the FP64 ring FFT in LDS on this device (" +
                                             std::to_string(need64) + " > " + std::to_string(smem) + " bytes)");
     return TL_OK;
@@ -1340,7 +1358,7 @@ std::vector<BufItem> plan_buffer_list(Plan &p, const Sizes &sz)
             {&p.twP64, sz.twP64, "twP64"},   {&p.twP32, sz.twP32, "twP32"},   {&p.bhat64, sz.bhat64, "bhat64"},
             {&p.bhat32, sz.bhat32, "bhat32"}, {&p.D2, sz.D2, "D2"},       {&p.alpha2, sz.alpha2, "alpha2"},
             {&p.coefP0, sz.coefP, "coefP0"}, {&p.coefP2, sz.coefP, "coefP2"}, {&p.startP, sz.startP, "startP"},
-            {&p.expsP, sz.expsP, "expsP"},   {&p.mcutP, sz.mcutP, "mcutP"}};
+            {&p.expsP, sz.expsP, "expsP"},   {&p.mcutP, sz.mcutP, "mcutP"},   {&p.dscratch, sz.dscratch, "dscratch"}};
 }
 
 // Everything a plan computes into its buffers once they exist: angle and

@@ -413,6 +413,18 @@ __global__ void k_fill_words(uint32_t *__restrict__ x, size_t n, uint32_t v)
     if (i < n) x[i] = v;
 }
 
+// FP64 -> FP32 and FP32 -> FP64 copies of n values (grid-stride)
+__global__ void k_to_f32(const double *__restrict__ x, float *__restrict__ y, size_t n)
+{
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        y[i] = (float)x[i];
+}
+__global__ void k_to_f64(const float *__restrict__ x, double *__restrict__ y, size_t n)
+{
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        y[i] = (double)x[i];
+}
+
 
 // ---- power-of-two lengths M = 512 .. 4096: radix-16 passes ----
 //
@@ -1011,6 +1023,25 @@ void k_ring_fft_blue(
 
 // Kernel fill of n 32-bit words (usable inside captured graphs, unlike a
 // memset node).
+// Deflection ring FFTs in FP32 for rings whose FP64 transform does not fit
+// in LDS: the FP64 rows (2 x ntheta x (L + 1) complex) to FP32 in the
+// scratch, the FP32 transform into the scratch after them, then the
+// deflection back to FP64 in alpha.
+hipError_t launch_defl_fft32(Plan &p, const void *rows64, void *alpha, int L)
+{
+    const size_t nrow = (size_t)2 * p.ntheta * (L + 1) * 2;  // real values of the rows
+    const size_t na = (size_t)2 * p.npix();
+    float *rows32 = (float *)p.dscratch.ptr, *a32 = rows32 + nrow;
+    const unsigned nb = 2048;
+    hipLaunchKernelGGL(k_to_f32, dim3(nb), dim3(256), 0, p.stream, (const double *)rows64, rows32, nrow);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess)
+        e = launch_fft_jobs(p, rows32, a32, (const FftJob *)p.jobsDefl.ptr, p.njobsDefl, false, 0, nullptr, L);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_to_f64, dim3(nb), dim3(256), 0, p.stream, a32, (double *)alpha, na);
+    return hipGetLastError();
+}
+
 hipError_t fill_words(void *x, size_t n, uint32_t v, hipStream_t st)
 {
     if (n == 0) return hipSuccess;
@@ -1210,7 +1241,7 @@ hipError_t fft_prepare(Plan &p)
         if (e != hipSuccess) return e;
     }
     const size_t b64 = 2 * M * sizeof(double2), b32 = 2 * M * sizeof(float2);
-    if (b64 > 65536) {
+    if (b64 > 65536 && !p.defl32) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_ring_fft<double>),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)b64);
         if (e != hipSuccess) return e;

@@ -163,6 +163,10 @@ struct Plan {
     // lmax (spin 0, derivative entries of J = 1: jtab 2)
     DevBuf coefP0, coefP2, startP, expsP, mcutP;
     bool phi_tables() const { return lmax_phi != lmax; }
+    // deflection ring FFTs in FP32 (non-FP64 plans whose rings are too long
+    // for the FP64 transform in LDS): FP32 rows and deflection in dscratch
+    bool defl32 = false;
+    DevBuf dscratch;
     DevBuf hring;     // HRing [ntheta] (HEALPix plans)
     DevBuf twP64;     // double2 [8192] e^{2 pi i t / 8192} (HEALPix plans with Bluestein rings)
     DevBuf twP32;     // float2  [8192]
@@ -342,6 +346,9 @@ int mfma_m_group();     // consecutive m per m-group
 hipError_t launch_legendre_mfma_queue(int order, bool pol, bool hasb, hipStream_t st, const MfmaJob *jobs,
                                       const int4 *items, int nitems, int *head, int ngroups);
 hipError_t fill_words(void *x, size_t n, uint32_t v, hipStream_t st);
+// the deflection's ring FFTs in FP32 (Plan::defl32) from the FP64 rows at
+// band limit L into the FP64 deflection alpha
+hipError_t launch_defl_fft32(Plan &p, const void *rows64, void *alpha, int L);
 // list: 0 = the deflection jobs, 1 = the main jobs (HEALPix plans launch each
 // job class of the list on its own)
 bool fft_p2(int M);  // rings of 2 M points take the one-workgroup radix-16 kernel

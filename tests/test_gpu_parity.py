@@ -383,3 +383,31 @@ def test_deflection_band_limit_above_the_fields(tl, oracle, precision, batch, np
             for x, y in zip(a, plan.lens_map(*s)):
                 assert torch.equal(x, y)
     plan.close()
+
+
+def test_rings_too_long_for_the_fp64_fft_in_lds(tl, oracle):
+    """Rings of 16384 pixels: the FP64 ring transform (two buffers of 8192
+    complex) does not fit in a workgroup's LDS, so FP32-map plans take the
+    deflection's ring FFTs in FP32 too (FP64 rows and result); the FP64 form
+    is refused.  Deflection (potential of lmax_phi 300) and lensed rings of
+    the FP32 and split FP16 forms against the oracle."""
+    lmax, lmax_phi, ntheta, nphi, order = 64, 300, 65, 16384, 3
+    with pytest.raises(tl.TaylensError) as e:
+        tl.Plan(lmax, ntheta, nphi, order, "fp64")
+    assert e.value.code == tl.TL_ERR_UNSUPPORTED
+    rms = 1.5 * (math.pi / (ntheta - 1)) / skygen.ARCMIN
+    sky = skygen.make_sky(lmax, 91, pol=True, rms_arcmin=rms)
+    phi = skygen.make_sky(lmax_phi, 92, pol=False, rms_arcmin=rms).alm_phi
+    rings = np.array([0, 1, 17, 32, 63, 64])
+    ref = oracle.lens_rings(lmax, order, ntheta, nphi, rings, sky.alm_T, sky.alm_E, None, phi, nthreads=ORACLE_THREADS)
+    mask = ref["_tie"] > 1e-9
+    for precision in ("fp32", "fp16x2"):
+        plan = tl.Plan(lmax, ntheta, nphi, order, precision, pol=True, lmax_phi=lmax_phi)
+        at, ap = plan.deflection(phi)
+        assert max_rel(t2np(at)[rings], ref["_alpha_theta"]) < 5e-6
+        assert max_rel(t2np(ap)[rings], ref["_alpha_phi"]) < 5e-6
+        got = plan.lens_map(sky.alm_T, sky.alm_E, None, phi)
+        for f, g in zip("TQU", got):
+            e = rel_rms(t2np(g)[rings], ref[f], mask)
+            assert e < 1e-5, (precision, f, e)
+        plan.close()
