@@ -554,6 +554,51 @@ def bench_sweep(args):
             "rows": rows, "fastest": sweep_best([r for r in rows if "skipped" not in r])}
 
 
+def bench_theta_fft(args, lmax=4095, ntheta=4097, nphi=8192, order=4, reps=7):
+    """Theta-derivatives by FFT along the great circles through both poles
+    (tl_theta_derivs) on the 4097 x 8192 grid of lmax 4095: the j >= 1
+    derivative maps of one field at order 4 (10 maps, from D_{0,k}, k <= 3),
+    FP32 and FP64 maps; median of reps, the algorithmic HBM bytes (inputs
+    read once, outputs written once) and their rate against 8 TB/s."""
+    import statistics
+
+    import torch
+
+    from paper_1307_0719_amd import taylens as tl
+
+    res = {"workload": f"{ntheta} x {nphi} rings (lmax {lmax}), order {order}: the {order * (order + 1) // 2} "
+                       f"maps D_jk, j >= 1, of one field from its D_0k, k < {order}"}
+    for prec in ("fp32", "fp64"):
+        plan = tl.Plan(lmax, ntheta, nphi, 1, prec, pol=False)
+        g = torch.Generator(device="cuda").manual_seed(5)
+        maps = torch.randn((order, ntheta, nphi), generator=g, dtype=plan.real_dtype, device="cuda")
+        outs = []
+
+        def step():
+            outs.clear()
+            for k in range(order):
+                outs.append(plan.theta_derivs(maps[k], order - k))
+
+        step()
+        torch.cuda.synchronize()
+        times = []
+        for _ in range(reps):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(plan.stream)
+            step()
+            b.record(plan.stream)
+            b.synchronize()
+            times.append(a.elapsed_time(b))
+        ms = statistics.median(times)
+        nout = order * (order + 1) // 2
+        nbytes = (order + nout) * ntheta * nphi * maps.element_size()
+        res[prec] = {"ms": round(ms, 4), "maps_in": order, "maps_out": nout, "algorithmic_bytes": nbytes,
+                     "hbm_gbs": round(nbytes / ms / 1e6, 1), "frac_of_8tbs": round(nbytes / ms / 1e6 / 8000.0, 4)}
+        del plan, maps, outs
+        torch.cuda.empty_cache()
+    return res
+
+
 def deflection_check(w, skies, skies_dev):
     """The deflection field of the step's realizations, from the library's
     deflection entry point (direct FP64 synthesis of grad phi): its RMS |alpha|
@@ -654,6 +699,8 @@ def main():
     ap.add_argument("--healpix-only", action="store_true",
                     help="only the HEALPix leg (nside 2048, lmax 3072, order 2, split FP16, six per pass), "
                          "without the oracle; one JSON line")
+    ap.add_argument("--theta-fft-only", action="store_true",
+                    help="only the theta-derivative FFTs (tl_theta_derivs) on the 4097 x 8192 grid; one JSON line")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the uneven-lmax batch and the learned-correction measurements")
     ap.add_argument("--sweep", action="store_true",
@@ -678,6 +725,9 @@ def main():
         return
     if args.sweep:
         print(json.dumps(bench_sweep(args)))
+        return
+    if args.theta_fft_only:
+        print(json.dumps(bench_theta_fft(args)))
         return
 
     import numpy as np
@@ -929,6 +979,7 @@ def main():
         res["healpix"] = bench_healpix(args, ref is not None)
         res["batch_uneven_lmax"] = bench_batch(args, order)
         res["learned_correction"] = bench_cnn(args, w)
+        res["theta_fft"] = bench_theta_fft(args)
     print(json.dumps(res))
 
 

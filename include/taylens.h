@@ -244,6 +244,31 @@ int tl_synth_derivs(tl_plan plan, const void *alm_T, const void *alm_E, const vo
 int tl_remap(tl_plan plan, const void *D, const double *alpha_theta, const double *alpha_phi,
              void *T_out, void *Q_out, void *U_out);
 
+/* Theta-derivatives by FFT instead of the harmonic recursion: the route that
+ * the conclusion (Sec. IV) opens by moving to equal-theta (equirectangular)
+ * pixels.  Meridian phi_c and its opposite phi_c + pi form one great circle
+ * through both poles, sampled at P = 2 (ntheta - 1) equal steps of
+ * dtheta = pi / (ntheta - 1); along it T, Q and U (components in the
+ * (e_theta, e_phi) basis) of fields of band limit lmax are trigonometric
+ * polynomials of degree <= lmax, so for lmax < P / 2 their theta-derivatives
+ * follow exactly from the circle's DFT (theta runs against the circle on the
+ * opposite meridian: odd orders change sign there).
+ *   maps: nmaps maps [ntheta][nphi] in the plan's real type (float64 for
+ *         TL_FP64, float32 otherwise), e.g. the j = 0 maps D_0k of
+ *         tl_synth_derivs (any k: d_phi commutes with d_theta);
+ *   out:  nmaps * jmax maps, out[i][j - 1] = dtheta^j / j! d^j_theta maps[i]
+ *         for j = 1..jmax (the scaling of tl_synth_derivs, so that D_0k in
+ *         gives D_jk out).
+ * Arithmetic FP64 (the transform of each pair of circles in LDS).  Input
+ * content above degree P / 2 - 1 along the circle aliases; the Nyquist
+ * degree keeps its even derivatives only.  Requirements: an equal-theta
+ * plan with ntheta - 1 a power of two, 2 <= ntheta - 1 <= 4096, and
+ * lmax <= ntheta - 2 (TL_ERR_UNSUPPORTED otherwise); 1 <= jmax <= 8,
+ * nmaps >= 0, maps and out caller-owned device buffers aligned to two
+ * values and not overlapping (TL_ERR_INVALID otherwise).  Queued on the
+ * plan's stream. */
+int tl_theta_derivs(tl_plan plan, const void *maps, int32_t nmaps, int32_t jmax, void *out);
+
 /* Lens n realizations (each as tl_lens_map: eqs. 1, 2, 5), plans[i] with
  * coefficient pointers alms[4i..4i+3] (T, E, B, phi) and outputs
  * outs[3i..3i+2] (T, Q, U).  Plans may differ in lmax and grid.  Queued on

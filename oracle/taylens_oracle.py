@@ -33,6 +33,13 @@ What it computes, in the order the paper gives (Sec. II, eqs. 1, 2, 4, 5):
 7. The exact lensed field (no Taylor series), the reference of accuracy
    measurements: the unlensed field synthesized directly at x' (eq. 1),
    then rotated as in 6.
+8. Theta-derivatives by FFT (the route the conclusion, Sec. IV, says the
+   equirectangular grid opens; an alternative to step 1's recursion for j > 0):
+   meridian phi_c and its opposite phi_c + pi form one great circle through
+   both poles, sampled at P = 2 (ntheta - 1) steps of dtheta; the derivative
+   is that of the circle's trigonometric interpolant (DFT coefficient kappa,
+   |kappa| <= P/2, times (i kappa)^j; the Nyquist term keeps even j only),
+   read back on the opposite meridian with theta running against the circle.
 
 Everything is float64 (the harmonic sums long double).  Speed is not a goal.
 """
@@ -476,3 +483,47 @@ def exact_lensed_pixels(lmax, ntheta, nphi, rings, cols, alm_T, alm_E=None, alm_
 def unlensed_map(lmax, ntheta, nphi, alm_T, alm_E=None, alm_B=None, nthreads: int = 0):
     D = derivative_rings(lmax, 0, ntheta, nphi, np.arange(ntheta), alm_T, alm_E, alm_B, nthreads)
     return {f: D[f][(0, 0)] for f in D}
+
+
+# ------------------------------------- theta-derivatives by FFT (step 8) -----
+
+def theta_derivs_fft(maps, jmax: int, cols=None) -> np.ndarray:
+    """Scaled theta-derivatives dtheta^j / j! d^j_theta of equal-theta maps,
+    j = 1..jmax, from the trigonometric interpolant along each great circle
+    through both poles (meridian phi_c followed by meridian phi_c + pi run
+    from the south pole back to the north pole).
+
+    maps: [..., ntheta, nphi] (nphi even).  cols: circle indices c < nphi/2
+    (default all); the result holds the columns c and c + nphi/2 of every
+    circle, in the order [c..., c + nphi/2...].
+    Returns [..., jmax, ntheta, ncols] float64.  Exact for maps whose
+    restriction to every circle has degree < P/2 = ntheta - 1 (fields of band
+    limit lmax <= ntheta - 2)."""
+    a = np.asarray(maps, dtype=np.float64)
+    ntheta, nphi = a.shape[-2], a.shape[-1]
+    if nphi % 2:
+        raise ValueError("nphi must be even")
+    hp = nphi // 2
+    c = np.arange(hp) if cols is None else np.asarray(cols, dtype=np.int64)
+    P = 2 * (ntheta - 1)
+    # circle samples at angle tau_t = t dtheta: t <= P/2 on meridian c at
+    # ring t, t > P/2 on meridian c + nphi/2 at ring P - t
+    north = a[..., :, c]                         # t = 0 .. P/2
+    south = a[..., -2:0:-1, :][..., c + hp]      # t = P/2 + 1 .. P - 1 (rings P/2 - 1 .. 1)
+    circ = np.concatenate([north, south], axis=-2)
+    X = np.fft.fft(circ, axis=-2)
+    kap = np.fft.fftfreq(P, d=1.0 / P)           # 0, 1, .., -P/2, .., -1
+    kap = np.where(np.arange(P) == P // 2, P // 2, kap)
+    dth = math.pi / (ntheta - 1)
+    out = np.empty(a.shape[:-2] + (jmax, ntheta, 2 * len(c)))
+    for j in range(1, jmax + 1):
+        mult = (1j * kap * dth) ** j / math.factorial(j)
+        if j % 2:
+            mult[P // 2] = 0.0
+        y = np.real(np.fft.ifft(X * mult[:, None], axis=-2))
+        out[..., j - 1, :, :len(c)] = y[..., :ntheta, :]
+        # opposite meridian at ring r: circle sample (P - r) mod P, d/dtheta = -d/dtau
+        idx = (P - np.arange(ntheta)) % P
+        out[..., j - 1, :, len(c):] = (-1.0) ** j * y[..., idx, :]
+    return out
+

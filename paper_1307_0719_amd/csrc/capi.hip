@@ -115,7 +115,7 @@ void free_plan_buffers(Plan &p)
     DevBuf *bufs[] = {&p.theta, &p.trig, &p.phitab, &p.phival, &p.twid64, &p.twid32, &p.coef0, &p.coef2,
                       &p.start, &p.exps, &p.mcut, &p.tab, &p.moff, &p.kstart, &p.rhs, &p.colexp, &p.tabsum, &p.Fphi, &p.alpha, &p.F, &p.D, &p.jobsDefl, &p.jobsMain, &p.jobsInt, &p.hring,
                       &p.twP64, &p.twP32, &p.bhat64, &p.bhat32, &p.D2, &p.alpha2, &p.coefP0, &p.coefP2,
-                      &p.startP, &p.expsP, &p.mcutP, &p.dscratch};
+                      &p.startP, &p.expsP, &p.mcutP, &p.dscratch, &p.twT};
     for (DevBuf *b : bufs) free_buf(*b);
     if (p.side) (void)hipStreamSynchronize(p.side);
     for (int i = 0; i < 2; ++i) {
@@ -236,12 +236,12 @@ struct Sizes {
     size_t theta, trig, phitab, phival, twid64, twid32, coef, start, exps, mcut, Fphi, alpha, F, D, jd, jm;
     size_t tab = 0, moff = 0, kstart = 0, rhs = 0, colexp = 0, tabsum = 0, hring = 0;
     size_t twP64 = 0, twP32 = 0, bhat64 = 0, bhat32 = 0, jx = 0, D2 = 0, alpha2 = 0;
-    size_t coefP = 0, startP = 0, expsP = 0, mcutP = 0, dscratch = 0;
+    size_t coefP = 0, startP = 0, expsP = 0, mcutP = 0, dscratch = 0, twT = 0;
     size_t total() const
     {
         return theta + trig + phitab + phival + twid64 + twid32 + 2 * coef + start + exps + mcut + Fphi + alpha + F +
                D + jd + jm + tab + moff + kstart + rhs + colexp + tabsum + hring + twP64 + twP32 + bhat64 + bhat32 + jx +
-               D2 + alpha2 + 2 * coefP + startP + expsP + mcutP + dscratch;
+               D2 + alpha2 + 2 * coefP + startP + expsP + mcutP + dscratch + twT;
     }
 };
 
@@ -312,6 +312,8 @@ Sizes plan_sizes(const Plan &p)
                   : (size_t)p.nfield() * p.ndmap() * p.dstride * rbytes;
     if (defl32_sized(p))  // FP32 rows and deflection of the FP32 deflection FFTs
         s.dscratch = (size_t)2 * p.ntheta * (p.lmax_phi + 1) * 2 * sizeof(float) + 2 * p.npix() * sizeof(float);
+    if (!p.nside && theta_fft_grid(p.ntheta))  // twiddles of the theta-derivative FFTs
+        s.twT = (size_t)(p.ntheta - 1) * sizeof(double2);
     if (p.tabform() && p.batch > 1) {  // the second set of maps and deflections
         s.D2 = s.D;
         s.alpha2 = s.alpha;
@@ -602,6 +604,15 @@ int upload_tables(Plan &p)
     }
     TL_HIP(hipMemcpy(p.twid64.ptr, t64.data(), t64.size() * sizeof(double2), hipMemcpyHostToDevice), "table copy");
     TL_HIP(hipMemcpy(p.twid32.ptr, t32.data(), t32.size() * sizeof(float2), hipMemcpyHostToDevice), "table copy");
+    if (p.twT.ptr) {  // e^{-2 pi i t / P}, t < P / 2, P = 2 (ntheta - 1)
+        const int P = 2 * (p.ntheta - 1);
+        std::vector<double2> tt(P / 2);
+        for (int t = 0; t < P / 2; ++t) {
+            long double a = 2.0L * 3.141592653589793238462643383279502884L * (long double)t / (long double)P;
+            tt[t] = make_double2((double)cosl(a), -(double)sinl(a));
+        }
+        TL_HIP(hipMemcpy(p.twT.ptr, tt.data(), tt.size() * sizeof(double2), hipMemcpyHostToDevice), "table copy");
+    }
     return TL_OK;
 }
 
@@ -1358,7 +1369,8 @@ std::vector<BufItem> plan_buffer_list(Plan &p, const Sizes &sz)
             {&p.twP64, sz.twP64, "twP64"},   {&p.twP32, sz.twP32, "twP32"},   {&p.bhat64, sz.bhat64, "bhat64"},
             {&p.bhat32, sz.bhat32, "bhat32"}, {&p.D2, sz.D2, "D2"},       {&p.alpha2, sz.alpha2, "alpha2"},
             {&p.coefP0, sz.coefP, "coefP0"}, {&p.coefP2, sz.coefP, "coefP2"}, {&p.startP, sz.startP, "startP"},
-            {&p.expsP, sz.expsP, "expsP"},   {&p.mcutP, sz.mcutP, "mcutP"},   {&p.dscratch, sz.dscratch, "dscratch"}};
+            {&p.expsP, sz.expsP, "expsP"},   {&p.mcutP, sz.mcutP, "mcutP"},   {&p.dscratch, sz.dscratch, "dscratch"},
+            {&p.twT, sz.twT, "twT"}};
 }
 
 // Everything a plan computes into its buffers once they exist: angle and
@@ -1674,6 +1686,32 @@ int tl_remap(tl_plan plan, const void *D, const double *alpha_theta, const doubl
     if (rc) return rc;
     if ((rc = set_device_of(p))) return rc;
     TL_HIP(launch_remap(p, D, alpha_theta, alpha_phi, nullptr, nullptr, T_out, Q_out, U_out), "remap");
+    return TL_OK;
+}
+
+int tl_theta_derivs(tl_plan plan, const void *maps, int32_t nmaps, int32_t jmax, void *out)
+{
+    if (check_plan(plan)) return TL_ERR_INVALID;
+    Plan &p = plan->p;
+    if (!maps || !out) return fail(TL_ERR_INVALID, "NULL argument");
+    if (jmax < 1 || jmax > TL_MAX_ORDER) return fail(TL_ERR_INVALID, "jmax must be in 1..8");
+    if (nmaps < 0) return fail(TL_ERR_INVALID, "nmaps must be >= 0");
+    const size_t vec = p.fp64() ? 16 : 8;
+    if ((uintptr_t)maps % vec || (uintptr_t)out % vec)
+        return fail(TL_ERR_INVALID, "maps and out must be aligned to two values");
+    if (p.nside || !p.twT.ptr)
+        return fail(TL_ERR_UNSUPPORTED, "theta-derivative FFTs need an equal-theta plan with ntheta - 1 a power of "
+                                        "two in [2, 4096]");
+    if (p.lmax > p.ntheta - 2)
+        return fail(TL_ERR_UNSUPPORTED, "theta-derivative FFTs need lmax <= ntheta - 2");
+    // one workgroup of 512 threads per pair of circles and map; the grid's
+    // work items must stay below 2^32
+    const int64_t nwg = (int64_t)((p.nphi / 2 + 1) / 2) * nmaps;
+    if (nwg * 512 > (int64_t)UINT32_MAX) return fail(TL_ERR_INVALID, "too many maps for one launch");
+    if (nmaps == 0) return TL_OK;
+    int rc = set_device_of(p);
+    if (rc) return rc;
+    TL_HIP(launch_theta_fft(p, maps, out, nmaps, jmax), "theta fft");
     return TL_OK;
 }
 

@@ -167,6 +167,7 @@ struct Plan {
     // for the FP64 transform in LDS): FP32 rows and deflection in dscratch
     bool defl32 = false;
     DevBuf dscratch;
+    DevBuf twT;       // double2 [ntheta - 1] e^{-2 pi i t / (2 (ntheta - 1))} (theta_fft_grid)
     DevBuf hring;     // HRing [ntheta] (HEALPix plans)
     DevBuf twP64;     // double2 [8192] e^{2 pi i t / 8192} (HEALPix plans with Bluestein rings)
     DevBuf twP32;     // float2  [8192]
@@ -346,6 +347,13 @@ int mfma_m_group();     // consecutive m per m-group
 hipError_t launch_legendre_mfma_queue(int order, bool pol, bool hasb, hipStream_t st, const MfmaJob *jobs,
                                       const int4 *items, int nitems, int *head, int ngroups);
 hipError_t fill_words(void *x, size_t n, uint32_t v, hipStream_t st);
+// theta-derivatives by FFT along the great circles through both poles
+// (thetafft.hip): grids with ntheta - 1 a power of two in [2, kThetaFftMaxP / 2]
+constexpr int kThetaFftMaxP = 8192;
+bool theta_fft_grid(int ntheta);
+// out[map][j - 1] = dtheta^j / j! d^j_theta in[map], j = 1..jmax, maps in the
+// plan's real type; on the plan's stream
+hipError_t launch_theta_fft(Plan &p, const void *in, void *out, int nmaps, int jmax);
 // the deflection's ring FFTs in FP32 (Plan::defl32) from the FP64 rows at
 // band limit L into the FP64 deflection alpha
 hipError_t launch_defl_fft32(Plan &p, const void *rows64, void *alpha, int L);

@@ -412,3 +412,65 @@ def test_p11_deflection_band_limit_above_the_fields(oracle):
             cut[m * (2 * Lp + 1 - m) // 2 + l] = 0
     c = oracle.lens_map(L, 3, ntheta, nphi, sky.alm_T, sky.alm_E, None, cut)
     assert np.max(np.abs(c["_alpha_theta"] - a["_alpha_theta"])) > 1e-3 * np.max(np.abs(a["_alpha_theta"]))
+
+
+@pytest.mark.parametrize("lmax,ntheta,nphi", [(30, 33, 64), (31, 33, 66), (60, 65, 122)])
+def test_p12_fft_theta_derivatives_equal_the_recursion_for_band_limited_fields(oracle, lmax, ntheta, nphi):
+    """Step 8 (theta-derivatives by FFT along the great circles through both
+    poles, Sec. IV) against step 1's Legendre / Wigner-d recursion: for T and
+    for Q, U with E and B (components in the (e_theta, e_phi) basis), the FFT
+    derivatives of every D_{0,k} equal the recursion's D_{j,k}, j + k <= 4,
+    on every ring including both poles and on both meridians of each circle;
+    lmax = ntheta - 2 is the largest band limit the circle of
+    2 (ntheta - 1) points carries, and nphi / 2 = 33 makes one circle of
+    pairs of meridians odd."""
+    order = 4
+    sky = skygen.make_sky(lmax, 3, pol=True)
+    aB = skygen.random_alm(lmax, 1003, lmin=2) * 0.2
+    D = oracle.derivative_rings(lmax, order, ntheta, nphi, np.arange(ntheta), sky.alm_T, sky.alm_E, aB)
+    dth = math.pi / (ntheta - 1)
+    dph = 2 * math.pi / nphi
+    hp = nphi // 2
+    for f in "TQU":
+        for k in range(order):
+            base = D[f][(0, k)] * dph ** k / math.factorial(k)
+            out = oracle.theta_derivs_fft(base, order - k)
+            for j in range(1, order - k + 1):
+                want = D[f][(j, k)] * dth ** j * dph ** k / (math.factorial(j) * math.factorial(k))
+                got = out[j - 1]
+                err = max(np.max(np.abs(got[:, :hp] - want[:, :hp])), np.max(np.abs(got[:, hp:] - want[:, hp:])))
+                assert err < 1e-12 * np.max(np.abs(want)), (f, j, k, err)
+
+
+@pytest.mark.parametrize("q", [0, 1, 5, 15, 16])
+def test_p12_fft_theta_derivatives_of_single_circle_harmonics(oracle, q):
+    """Closed form: a map whose samples along every circle are cos(q tau + psi_c)
+    (tau the angle along the circle from the north pole down meridian c) has
+    scaled derivatives dtheta^j / j! q^j cos(q tau + psi_c + j pi / 2) on
+    meridian c and (-1)^j times that on meridian c + pi, where theta runs
+    against tau.  At the Nyquist degree q = P / 2 = 16 the samples are
+    cos(psi_c) cos(P/2 tau): even derivatives only, odd ones zero."""
+    ntheta, nphi = 17, 10
+    P, hp = 2 * (ntheta - 1), nphi // 2
+    th = oracle.grid_theta(ntheta)
+    psi = np.random.default_rng(q).uniform(0, 2 * np.pi, hp)
+    m = np.zeros((ntheta, nphi))
+    for c in range(hp):
+        m[:, c] = np.cos(q * th + psi[c])
+        m[:, c + hp] = np.cos(q * (2 * np.pi - th) + psi[c])
+    out = oracle.theta_derivs_fft(m, 5)
+    dth = math.pi / (ntheta - 1)
+    for j in range(1, 6):
+        want = np.zeros((ntheta, nphi))
+        for c in range(hp):
+            amp, ph = (math.cos(psi[c]), 0.0) if q == P // 2 else (1.0, psi[c])
+            if q == P // 2 and j % 2:
+                continue
+            want[:, c] = amp * q ** j * np.cos(q * th + ph + j * np.pi / 2)
+            want[:, c + hp] = (-1) ** j * amp * q ** j * np.cos(q * (2 * np.pi - th) + ph + j * np.pi / 2)
+        want *= dth ** j / math.factorial(j)
+        assert np.max(np.abs(out[j - 1] - want)) < 1e-13 * max(1.0, q ** j * dth ** j), (j, q)
+    # the column subset returns the same columns
+    sub = oracle.theta_derivs_fft(m, 2, cols=[1, 3])
+    np.testing.assert_array_equal(sub[..., [0, 1]], out[:2][..., [1, 3]])
+    np.testing.assert_array_equal(sub[..., [2, 3]], out[:2][..., [1 + hp, 3 + hp]])
