@@ -12,8 +12,10 @@
 //
 // One workgroup takes two circles (columns c, c + 1 and their opposites) as
 // the real and imaginary parts of one complex transform in LDS (FP64, P <=
-// 8192: 128 KiB), keeps the spectrum in registers and runs one inverse
-// transform per derivative order.  Workgroups are ordered so that each XCD
+// 8192: 128 KiB; radix-8 steps, a barrier per three stages; twiddles as
+// products of two 64-entry tables in LDS), keeps the
+// spectrum in registers and runs one inverse transform per derivative
+// order.  Workgroups are ordered so that each XCD
 // takes a contiguous range of columns: the strided column loads of
 // neighbouring workgroups then share the lines in that XCD's L2.
 #include "tl_internal.h"
@@ -31,26 +33,61 @@ __device__ inline double2 cmul(double2 a, double2 b)
     return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 
-// In-place radix-2 decimation-in-time transform of x[0..P) stored in
-// bit-reversed order; tw[t] = e^{-2 pi i t / P}, t < P / 2; inverse: the
-// conjugate twiddles (no 1/P).  Ends with a barrier.
-__device__ void circle_fft(double2 *x, int P, int lg, const double2 *__restrict__ tw, bool inverse)
+// r consecutive radix-2 decimation-in-time stages s .. s + r - 1 of an
+// in-place transform, in registers: with half = 2^(s-1), block b holds the
+// 2^r elements base + pos + t half (pos = b mod half), which those stages
+// combine only among themselves; stage s + q pairs t with t + 2^q (t mod
+// 2^(q+1) < 2^q) under the twiddle W_{2^(s+q)}^(pos + (t mod 2^q) half).
+// The twiddle e^{-2 pi i e / P}, e < P / 2, is th[e / 64] tl[e % 64] from
+// two tables in LDS; inverse: conjugate twiddles (no 1/P).  Ends with a
+// barrier.
+constexpr int kTwLo = 64;
+constexpr int kTwHi = kThetaFftMaxP / 2 / kTwLo;
+
+__device__ inline double2 twiddle(const double2 *th, const double2 *tl, int e)
 {
-    for (int s = 1; s <= lg; ++s) {
-        const int half = 1 << (s - 1);
-        const int step = P >> s;
-        for (int b = threadIdx.x; b < P / 2; b += kTfThreads) {
-            const int pos = b & (half - 1);
-            const int i0 = ((b >> (s - 1)) << s) + pos;
-            double2 w = tw[pos * step];
-            if (inverse) w.y = -w.y;
-            const double2 a = x[i0];
-            const double2 c = cmul(w, x[i0 + half]);
-            x[i0] = make_double2(a.x + c.x, a.y + c.y);
-            x[i0 + half] = make_double2(a.x - c.x, a.y - c.y);
+    return cmul(th[e / kTwLo], tl[e % kTwLo]);
+}
+
+template <int r>
+__device__ void fft_stages(double2 *x, int P, int s, const double2 *th, const double2 *tl, bool inverse)
+{
+    constexpr int R = 1 << r;
+    const int half = 1 << (s - 1);
+    for (int b = threadIdx.x; b < P / R; b += kTfThreads) {
+        const int pos = b & (half - 1);
+        double2 *xb = x + (b >> (s - 1)) * (R * half) + pos;
+        double2 v[R];
+#pragma unroll
+        for (int t = 0; t < R; ++t) v[t] = xb[t * half];
+#pragma unroll
+        for (int q = 0; q < r; ++q) {
+            const int hq = 1 << q;
+#pragma unroll
+            for (int t = 0; t < R; ++t) {
+                if ((t & (2 * hq - 1)) < hq) {
+                    double2 w = twiddle(th, tl, (pos + (t & (hq - 1)) * half) * (P >> (s + q)));
+                    if (inverse) w.y = -w.y;
+                    const double2 a = v[t], c = cmul(w, v[t + hq]);
+                    v[t] = make_double2(a.x + c.x, a.y + c.y);
+                    v[t + hq] = make_double2(a.x - c.x, a.y - c.y);
+                }
+            }
         }
-        __syncthreads();
+#pragma unroll
+        for (int t = 0; t < R; ++t) xb[t * half] = v[t];
     }
+    __syncthreads();
+}
+
+// In-place transform of x[0..P) stored in bit-reversed order: the lg
+// radix-2 stages three at a time (radix 8), the rest two or one at a time.
+__device__ void circle_fft(double2 *x, int P, int lg, const double2 *th, const double2 *tl, bool inverse)
+{
+    int s = 1;
+    for (; s + 2 <= lg; s += 3) fft_stages<3>(x, P, s, th, tl, inverse);
+    if (s + 1 == lg) fft_stages<2>(x, P, s, th, tl, inverse);
+    else if (s == lg) fft_stages<1>(x, P, s, th, tl, inverse);
 }
 
 template <typename T> struct Vec2;
@@ -67,6 +104,15 @@ __global__ __launch_bounds__(kTfThreads) void k_theta_fft(const T *__restrict__ 
     using V = typename Vec2<T>::type;
     extern __shared__ unsigned char smem_raw[];
     double2 *x = reinterpret_cast<double2 *>(smem_raw);
+    double2 *th = x + P;       // tw[64 a], a < P / 128 (at least one)
+    double2 *tl = th + kTwHi;  // tw[b], b < min(64, P / 2)
+    for (int i = threadIdx.x; i < kTwHi + kTwLo; i += kTfThreads) {
+        if (i < kTwHi) {
+            if (i * kTwLo < P / 2) th[i] = tw[i * kTwLo];
+        } else if (i - kTwHi < P / 2) {
+            tl[i - kTwHi] = tw[i - kTwHi];
+        }
+    }
 
     // XCD-contiguous order: XCD w % 8 takes a contiguous run of the
     // (map, circle pair) items
@@ -82,21 +128,29 @@ __global__ __launch_bounds__(kTfThreads) void k_theta_fft(const T *__restrict__ 
     const size_t plane = (size_t)nr * nphi;
     const T *src = in + (size_t)map * plane;
 
-    for (int t = threadIdx.x; t < P; t += kTfThreads) {
-        const bool north = t <= P / 2;
-        const T *q = src + (size_t)(north ? t : P - t) * nphi + (north ? c0 : c0 + hp);
-        double a, b = 0.0;
-        if (two) {
-            const V v = *reinterpret_cast<const V *>(q);
-            a = (double)v.x;
-            b = (double)v.y;
-        } else {
-            a = (double)q[0];
+    // all loads of a thread in flight before the first LDS store
+    V ld[kTfReg];
+#pragma unroll
+    for (int r = 0; r < kTfReg; ++r) {
+        const int t = threadIdx.x + r * kTfThreads;
+        if (t < P) {
+            const bool north = t <= P / 2;
+            const T *q = src + (size_t)(north ? t : P - t) * nphi + (north ? c0 : c0 + hp);
+            if (two) {
+                ld[r] = *reinterpret_cast<const V *>(q);
+            } else {
+                ld[r].x = q[0];
+                ld[r].y = (T)0;
+            }
         }
-        x[bitrev(t, lg)] = make_double2(a, b);
+    }
+#pragma unroll
+    for (int r = 0; r < kTfReg; ++r) {
+        const int t = threadIdx.x + r * kTfThreads;
+        if (t < P) x[bitrev(t, lg)] = make_double2((double)ld[r].x, (double)ld[r].y);
     }
     __syncthreads();
-    circle_fft(x, P, lg, tw, false);
+    circle_fft(x, P, lg, th, tl, false);
 
     double2 X[kTfReg];
 #pragma unroll
@@ -133,7 +187,7 @@ __global__ __launch_bounds__(kTfThreads) void k_theta_fft(const T *__restrict__ 
             }
         }
         __syncthreads();
-        circle_fft(x, P, lg, tw, true);
+        circle_fft(x, P, lg, th, tl, true);
 
         T *dst = out + ((size_t)map * jmax + (j - 1)) * plane;
         const double sg = (j & 1) ? -1.0 : 1.0;
@@ -173,7 +227,7 @@ hipError_t launch_theta_fft(Plan &p, const void *in, void *out, int nmaps, int j
     while ((1 << lg) < P) ++lg;
     const int npair = (p.nphi / 2 + 1) / 2;
     const int64_t nwg = (int64_t)npair * nmaps;
-    const size_t smem = (size_t)P * sizeof(double2);
+    const size_t smem = (size_t)(P + kTwHi + kTwLo) * sizeof(double2);
     hipError_t e;
     if (p.fp64()) {
         e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_theta_fft<double>),
