@@ -596,6 +596,42 @@ def bench_theta_fft(args, lmax=4095, ntheta=4097, nphi=8192, order=4, reps=7):
                      "hbm_gbs": round(nbytes / ms / 1e6, 1), "frac_of_8tbs": round(nbytes / ms / 1e6 / 8000.0, 4)}
         del plan, maps, outs
         torch.cuda.empty_cache()
+
+    # the FP64 form lensing T+Q/U at order 4 with the theta-derivatives from
+    # the recursion (every row j) and from the FFTs (rows j = 0 only)
+    from paper_1307_0719_amd import skygen
+
+    sky = skygen.make_sky(lmax, 41, pol=True)
+    a = (sky.alm_T, sky.alm_E, None, sky.alm_phi)
+    fp64 = {"workload": f"T+Q/U lmax {lmax} on {ntheta} x {nphi} rings, order {order}, FP64 form, tl_lens_map"}
+    maps = {}
+    for tf in (False, True):
+        plan = tl.Plan(lmax, ntheta, nphi, order, "fp64", pol=True, theta_fft=tf)
+        out = plan.lens_map(*a)
+        torch.cuda.synchronize()
+        times = []
+        for _ in range(3):
+            t0 = torch.cuda.Event(enable_timing=True)
+            t1 = torch.cuda.Event(enable_timing=True)
+            t0.record(plan.stream)
+            plan.lens_map(*a, out=out)
+            t1.record(plan.stream)
+            t1.synchronize()
+            times.append(t0.elapsed_time(t1))
+        plan.profile(True)
+        plan.lens_map(*a, out=out)
+        st = {k: round(v[0], 2) for k, v in plan.stage_times().items() if v[1]}
+        plan.profile(False)
+        key = "theta_fft" if tf else "recursion"
+        fp64[key] = {"ms_per_map": round(statistics.median(times), 2), "stages_ms": st}
+        maps[key] = [x.clone() for x in out]
+        del plan, out
+        torch.cuda.empty_cache()
+    fp64["max_rel_rms_difference"] = max(
+        float(torch.sqrt(torch.mean((x - y) ** 2)) / torch.sqrt(torch.mean(y ** 2)))
+        for x, y in zip(maps["theta_fft"], maps["recursion"]))
+    fp64["speedup"] = round(fp64["recursion"]["ms_per_map"] / fp64["theta_fft"]["ms_per_map"], 3)
+    res["fp64_lens_map"] = fp64
     return res
 
 

@@ -123,6 +123,17 @@ typedef struct {
                               (lmax_phi + 1)(lmax_phi + 2)/2 coefficients; the
                               deflection takes the direct FP64 recursion on
                               every ring (not the tables of the tabulated forms). */
+    int32_t theta_fft;     /* 1: TL_FP64 plans synthesize only the rows j = 0 in the
+                              harmonic stage (the ring FFTs give D_0k) and take the
+                              theta-derivatives D_jk, j >= 1, by FFT along the great
+                              circles through both poles (tl_theta_derivs; the FFT
+                              route of Sec. IV), for tl_lens_map, tl_lens_map_many,
+                              tl_lens_map_pos and tl_synth_derivs (tl_legendre still
+                              returns every row).  Needs the equal-theta grid with
+                              ntheta - 1 a power of two in [2, 4096] and
+                              lmax <= ntheta - 2, and TL_FP64 (TL_ERR_UNSUPPORTED
+                              otherwise); results equal the recursion's to FP64
+                              rounding.  0: every row by the recursion.            */
 } tl_options;
 
 typedef struct tl_plan_s *tl_plan;

@@ -364,6 +364,13 @@ int validate_options(int32_t lmax, tl_grid grid, const tl_options *opt)
         if ((int64_t)grid.nphi < 2 * (int64_t)opt->lmax_phi)
             return fail(TL_ERR_INVALID, "nphi must be >= 2*lmax_phi (band limit of the deflection on each ring)");
     }
+    if (opt->theta_fft != 0 && opt->theta_fft != 1) return fail(TL_ERR_INVALID, "theta_fft must be 0 or 1");
+    if (opt->theta_fft) {
+        if (opt->precision != TL_FP64) return fail(TL_ERR_UNSUPPORTED, "theta_fft is an option of the FP64 form");
+        if (!theta_fft_grid(grid.ntheta) || (int64_t)lmax > (int64_t)grid.ntheta - 2)
+            return fail(TL_ERR_UNSUPPORTED, "theta_fft needs ntheta - 1 a power of two in [2, 4096] and "
+                                            "lmax <= ntheta - 2");
+    }
     Plan tmp;
     if (!factor_radices(grid.nphi / 2, tmp))
         return fail(TL_ERR_UNSUPPORTED, "nphi/2 must be a product of 2, 3 and 5");
@@ -739,9 +746,12 @@ int run_caps(Plan &p, int n, const void *const *T, const void *const *E, const v
 // Harmonic stage of n realizations (n <= plan batch for the table forms).
 // P (optional): their lensing potentials; when fold_deflection() holds, the
 // lam / lam' sums of phi outside the caps go to fphi_slot(q).
+// j0: the direct kernels synthesize the rows j = 0 only (the FP64 form
+// with theta_fft, whose maps then take their theta-derivatives by FFT)
 int run_legendre_many(Plan &p, int n, const void *const *T, const void *const *E, const void *const *B,
-                      void *const *Fout, const void *const *P = nullptr)
+                      void *const *Fout, const void *const *P = nullptr, bool j0 = false)
 {
+    const int J = j0 ? 0 : p.order;
     const size_t rowc = (size_t)p.ntheta * (p.lmax + 1) * (p.order + 1);
     const size_t cb = p.fp64() ? 16 : 8;
     const bool hasb = p.pol && B[0] != nullptr;
@@ -776,7 +786,7 @@ int run_legendre_many(Plan &p, int n, const void *const *T, const void *const *E
             set.F[q] = Fout[i0 + q];
         }
         StageScope sc(p, ST_LEG_T);
-        TL_HIP(launch_legendre_scalar_set(p, p.order, rend, set, p.fp64()), "legendre T");
+        TL_HIP(launch_legendre_scalar_set(p, J, rend, set, p.fp64()), "legendre T");
     }
     for (int i0 = 0, mx = direct_max(p.order, true, hasb, p.fp64()); !caps1 && p.pol && i0 < n; i0 += mx) {
         DirectSet set{};
@@ -789,7 +799,7 @@ int run_legendre_many(Plan &p, int n, const void *const *T, const void *const *E
             set.G[q] = F + 2 * rowc * cb;
         }
         StageScope sc(p, ST_LEG_QU);
-        TL_HIP(launch_legendre_spin_set(p, p.order, rend, set, p.fp64()), "legendre QU");
+        TL_HIP(launch_legendre_spin_set(p, J, rend, set, p.fp64()), "legendre QU");
     }
     for (int i = 0; i < n; ++i) {
         char *F = (char *)Fout[i];
@@ -846,19 +856,44 @@ int run_legendre_many(Plan &p, int n, const void *const *T, const void *const *E
     return TL_OK;
 }
 
-int run_legendre(Plan &p, const void *T, const void *E, const void *B, void *Fout)
+// all_j = false: only what the derivative maps need (rows j = 0 with theta_fft)
+int run_legendre(Plan &p, const void *T, const void *E, const void *B, void *Fout, bool all_j = true)
 {
     const void *Ts[1] = {T}, *Es[1] = {E}, *Bs[1] = {B};
     void *Fs[1] = {Fout};
-    return run_legendre_many(p, 1, Ts, Es, Bs, Fs);
+    return run_legendre_many(p, 1, Ts, Es, Bs, Fs, nullptr, !all_j && p.theta_fft);
+}
+
+// Derivative maps from the harmonic rows: ring FFTs of every row j, or with
+// theta_fft ring FFTs of the rows j = 0 (the maps D_0k) and the maps j >= 1
+// by FFT along the great circles through both poles.
+hipError_t maps_from_rows(Plan &p, const void *F, void *Dout)
+{
+    if (!p.theta_fft) return launch_main_fft(p, F, Dout);
+    const int N = p.order, nf = p.nfield();
+    const bool own = p.own(Dout);
+    const FftJob *jobs = (const FftJob *)(own ? p.jobsInt.ptr : p.jobsMain.ptr);
+    for (int f = 0; f < nf; ++f) {
+        const hipError_t e =
+            launch_fft_jobs(p, F, Dout, jobs + (size_t)f * (N + 1) * p.ntheta, p.ntheta, p.fp64(), 1);
+        if (e != hipSuccess) return e;
+    }
+    const size_t ds = own ? p.dstride : (size_t)p.ntheta * p.nphi;
+    const size_t rb = p.fp64() ? 8 : 4;
+    for (int k = 0; k < N; ++k) {  // D_jk = dtheta^j / j! d^j_theta D_0k, j = 1..N-k
+        const ThetaFftLayout lay{(size_t)p.ndmap() * ds, (size_t)p.ndmap() * ds, ds, N + 1, 1, k};
+        const hipError_t e = launch_theta_fft(p, (const char *)Dout + (size_t)k * ds * rb, Dout, nf, N - k, lay);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 int run_derivs(Plan &p, const void *T, const void *E, const void *B, void *Dout)
 {
-    int rc = run_legendre(p, T, E, B, p.F.ptr);
+    int rc = run_legendre(p, T, E, B, p.F.ptr, false);
     if (rc) return rc;
     StageScope sc(p, ST_FFT);
-    TL_HIP(launch_main_fft(p, p.F.ptr, Dout), "ring fft");
+    TL_HIP(maps_from_rows(p, p.F.ptr, Dout), "ring fft");
     return TL_OK;
 }
 
@@ -1234,6 +1269,7 @@ void plan_fields(Plan &p, int32_t lmax, tl_grid grid, const tl_options *opt, voi
 {
     p.lmax = lmax;
     p.lmax_phi = opt->lmax_phi > 0 ? opt->lmax_phi : lmax;
+    p.theta_fft = opt->theta_fft == 1 && nside == 0;
     p.nside = nside;
     if (nside) {
         grid.ntheta = 4 * nside - 1;  // HEALPix rings; nphi = the longest ring
@@ -1533,6 +1569,8 @@ int tl_plan_create_healpix(tl_plan *out, int32_t lmax, int32_t nside, const tl_o
     tl_grid g{3, n2};
     if (opt && opt->lmax_phi != 0 && opt->lmax_phi != lmax)
         return fail(TL_ERR_UNSUPPORTED, "a separate lmax_phi is not supported on HEALPix rings");
+    if (opt && opt->theta_fft != 0)
+        return fail(TL_ERR_UNSUPPORTED, "theta_fft needs the equal-theta grid");
     int rc = validate_options(lmax, g, opt);
     if (rc) return rc;
     tl_plan_s *h = new (std::nothrow) tl_plan_s();
@@ -1711,7 +1749,9 @@ int tl_theta_derivs(tl_plan plan, const void *maps, int32_t nmaps, int32_t jmax,
     if (nmaps == 0) return TL_OK;
     int rc = set_device_of(p);
     if (rc) return rc;
-    TL_HIP(launch_theta_fft(p, maps, out, nmaps, jmax), "theta fft");
+    const size_t plane = (size_t)p.ntheta * p.nphi;
+    const ThetaFftLayout lay{plane, (size_t)jmax * plane, plane, 1, 0, -1};
+    TL_HIP(launch_theta_fft(p, maps, out, nmaps, jmax, lay), "theta fft");
     return TL_OK;
 }
 
@@ -1825,7 +1865,7 @@ int tl_lens_map_many(tl_plan plan, int32_t n, const void *const *alms, void *con
             F[q] = (char *)p.F.ptr + q * rowbytes;
         }
         const bool fold = fold_deflection(p, k, P);
-        if ((rc = run_legendre_many(p, k, T, E, B, F, P))) return rc;
+        if ((rc = run_legendre_many(p, k, T, E, B, F, P, p.theta_fft))) return rc;
         // deflection sums of the whole group (outside the caps from the
         // table pass when folded), then per realization: deflection FFT,
         // ring FFTs, remap
@@ -1838,7 +1878,7 @@ int tl_lens_map_many(tl_plan plan, int32_t n, const void *const *alms, void *con
             if ((rc = defl_fft(p, P[q], q, alpha))) return rc;
             {
                 StageScope sc(p, ST_FFT);
-                TL_HIP(launch_main_fft(p, F[q], D), "ring fft");
+                TL_HIP(maps_from_rows(p, F[q], D), "ring fft");
             }
             const double *at = (const double *)alpha;
             void *To = outs[3 * (i0 + q)], *Qo = outs[3 * (i0 + q) + 1], *Uo = outs[3 * (i0 + q) + 2];

@@ -94,12 +94,14 @@ template <typename T> struct Vec2;
 template <> struct Vec2<double> { using type = double2; };
 template <> struct Vec2<float> { using type = float2; };
 
-// out[map][j-1] = dtheta^j / j! d^j/dtheta^j in[map], j = 1..jmax.
-// Grid: (nphi / 4 rounded up) * nmaps workgroups, linear order.
+// Map i of the launch: input in + i istride, output of order j at
+// out + i ostride + slot(j) pstride, slot(j) = sa j - sb j (j - 1) / 2 + sc,
+// = dtheta^j / j! d^j/dtheta^j of the input, j = 1..jmax; every map is
+// [nr][nphi].  Grid: (nphi / 4 rounded up) * nmaps workgroups, linear order.
 template <typename T>
 __global__ __launch_bounds__(kTfThreads) void k_theta_fft(const T *__restrict__ in, T *__restrict__ out,
                                                           const double2 *__restrict__ tw, int P, int lg, int nphi,
-                                                          int npair, int nmaps, int jmax)
+                                                          int npair, int nmaps, int jmax, ThetaFftLayout lay)
 {
     using V = typename Vec2<T>::type;
     extern __shared__ unsigned char smem_raw[];
@@ -125,8 +127,7 @@ __global__ __launch_bounds__(kTfThreads) void k_theta_fft(const T *__restrict__ 
     const int hp = nphi / 2;
     const bool two = c0 + 1 < hp;
     const int nr = P / 2 + 1;
-    const size_t plane = (size_t)nr * nphi;
-    const T *src = in + (size_t)map * plane;
+    const T *src = in + (size_t)map * lay.istride;
 
     // all loads of a thread in flight before the first LDS store
     V ld[kTfReg];
@@ -189,7 +190,7 @@ __global__ __launch_bounds__(kTfThreads) void k_theta_fft(const T *__restrict__ 
         __syncthreads();
         circle_fft(x, P, lg, th, tl, true);
 
-        T *dst = out + ((size_t)map * jmax + (j - 1)) * plane;
+        T *dst = out + (size_t)map * lay.ostride + (size_t)(lay.sa * j - lay.sb * j * (j - 1) / 2 + lay.sc) * lay.pstride;
         const double sg = (j & 1) ? -1.0 : 1.0;
         for (int t = threadIdx.x; t < nr; t += kTfThreads) {
             const double2 a = x[t];
@@ -220,7 +221,7 @@ bool theta_fft_grid(int ntheta)
     return h >= 2 && h <= kThetaFftMaxP / 2 && (h & (h - 1)) == 0;
 }
 
-hipError_t launch_theta_fft(Plan &p, const void *in, void *out, int nmaps, int jmax)
+hipError_t launch_theta_fft(Plan &p, const void *in, void *out, int nmaps, int jmax, const ThetaFftLayout &lay)
 {
     const int P = 2 * (p.ntheta - 1);
     int lg = 0;
@@ -234,13 +235,13 @@ hipError_t launch_theta_fft(Plan &p, const void *in, void *out, int nmaps, int j
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
         if (e != hipSuccess) return e;
         k_theta_fft<double><<<dim3((unsigned)nwg), dim3(kTfThreads), smem, p.stream>>>(
-            (const double *)in, (double *)out, (const double2 *)p.twT.ptr, P, lg, p.nphi, npair, nmaps, jmax);
+            (const double *)in, (double *)out, (const double2 *)p.twT.ptr, P, lg, p.nphi, npair, nmaps, jmax, lay);
     } else {
         e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_theta_fft<float>),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
         if (e != hipSuccess) return e;
         k_theta_fft<float><<<dim3((unsigned)nwg), dim3(kTfThreads), smem, p.stream>>>(
-            (const float *)in, (float *)out, (const double2 *)p.twT.ptr, P, lg, p.nphi, npair, nmaps, jmax);
+            (const float *)in, (float *)out, (const double2 *)p.twT.ptr, P, lg, p.nphi, npair, nmaps, jmax, lay);
     }
     return hipGetLastError();
 }

@@ -168,6 +168,9 @@ struct Plan {
     bool defl32 = false;
     DevBuf dscratch;
     DevBuf twT;       // double2 [ntheta - 1] e^{-2 pi i t / (2 (ntheta - 1))} (theta_fft_grid)
+    // FP64 form: the harmonic stage synthesizes the rows j = 0 only and the
+    // theta-derivatives come from FFTs along the great circles (opt.theta_fft)
+    bool theta_fft = false;
     DevBuf hring;     // HRing [ntheta] (HEALPix plans)
     DevBuf twP64;     // double2 [8192] e^{2 pi i t / 8192} (HEALPix plans with Bluestein rings)
     DevBuf twP32;     // float2  [8192]
@@ -351,9 +354,18 @@ hipError_t fill_words(void *x, size_t n, uint32_t v, hipStream_t st);
 // (thetafft.hip): grids with ntheta - 1 a power of two in [2, kThetaFftMaxP / 2]
 constexpr int kThetaFftMaxP = 8192;
 bool theta_fft_grid(int ntheta);
-// out[map][j - 1] = dtheta^j / j! d^j_theta in[map], j = 1..jmax, maps in the
-// plan's real type; on the plan's stream
-hipError_t launch_theta_fft(Plan &p, const void *in, void *out, int nmaps, int jmax);
+// Where the maps of one theta-FFT launch live (elements of the plan's real
+// type): map i at in + i istride; its order-j output at out + i ostride +
+// (sa j - sb j (j - 1) / 2 + sc) pstride.  Consecutive outputs [j - 1]:
+// {plane, jmax plane, plane, 1, 0, -1}; the plan's j-major derivative maps
+// of column k at order N: {ndmap ds, ndmap ds, ds, N + 1, 1, k}.
+struct ThetaFftLayout {
+    size_t istride, ostride, pstride;
+    int sa, sb, sc;
+};
+// dtheta^j / j! d^j_theta of each input map, j = 1..jmax, maps [ntheta][nphi]
+// in the plan's real type; on the plan's stream
+hipError_t launch_theta_fft(Plan &p, const void *in, void *out, int nmaps, int jmax, const ThetaFftLayout &lay);
 // the deflection's ring FFTs in FP32 (Plan::defl32) from the FP64 rows at
 // band limit L into the FP64 deflection alpha
 hipError_t launch_defl_fft32(Plan &p, const void *rows64, void *alpha, int L);

@@ -61,7 +61,8 @@ class Grid(ctypes.Structure):
 class Options(ctypes.Structure):
     _fields_ = [("order", ctypes.c_int32), ("precision", ctypes.c_int32), ("pol", ctypes.c_int32),
                 ("rotate", ctypes.c_int32), ("naive_pos", ctypes.c_int32), ("batch", ctypes.c_int32),
-                ("workspace_cap", ctypes.c_int64), ("maps16", ctypes.c_int32), ("lmax_phi", ctypes.c_int32)]
+                ("workspace_cap", ctypes.c_int64), ("maps16", ctypes.c_int32), ("lmax_phi", ctypes.c_int32),
+                ("theta_fft", ctypes.c_int32)]
 
 
 class BatchOptions(ctypes.Structure):
@@ -151,11 +152,13 @@ class Plan:
     def __init__(self, lmax: int, ntheta: int, nphi: int, order: int, precision: str = "fp32",
                  pol: bool = True, rotate: bool = True, naive_pos: bool = False, workspace_cap: int = 0,
                  device: Optional[torch.device] = None, stream: Optional[torch.cuda.Stream] = None,
-                 batch: int = 1, nside: int = 0, maps16: bool = False, lmax_phi: int = 0):
+                 batch: int = 1, nside: int = 0, maps16: bool = False, lmax_phi: int = 0,
+                 theta_fft: bool = False):
         """ntheta x nphi equal-theta grid, or with nside > 0 HEALPix rings
         (ntheta, nphi ignored; maps are [12 nside^2] in RING order).  maps16:
         internal derivative maps of order j + k >= 3 in FP16; lmax_phi: band
-        limit of the lensing potential, 0 = lmax (see tl_options)."""
+        limit of the lensing potential, 0 = lmax; theta_fft: FP64 plans take
+        the theta-derivatives by FFT along great circles (see tl_options)."""
         self.nside = int(nside)
         if self.nside:
             ntheta, nphi = 4 * self.nside - 1, 4 * self.nside
@@ -169,7 +172,7 @@ class Plan:
         if precision not in PRECISIONS:
             raise ValueError(f"unknown precision {precision}")
         opt = Options(order, PRECISIONS[precision], int(pol), int(rotate), int(naive_pos), int(batch),
-                      int(workspace_cap), int(maps16), int(lmax_phi))
+                      int(workspace_cap), int(maps16), int(lmax_phi), int(theta_fft))
         self.batch = int(batch)
         h = ctypes.c_void_p()
         with torch.cuda.device(self.device):

@@ -33,9 +33,10 @@ def test_every_declared_symbol_is_exported(tl):
     assert tl.version() == 10000
 
 
-def _create(tl, lmax, ntheta, nphi, order=3, prec=1, pol=1, rotate=1, naive=0, batch=0, cap=0, maps16=0, lmax_phi=0):
+def _create(tl, lmax, ntheta, nphi, order=3, prec=1, pol=1, rotate=1, naive=0, batch=0, cap=0, maps16=0, lmax_phi=0,
+            theta_fft=0):
     h = ctypes.c_void_p(123)
-    o = tl.Options(order, prec, pol, rotate, naive, batch, cap, maps16, lmax_phi)
+    o = tl.Options(order, prec, pol, rotate, naive, batch, cap, maps16, lmax_phi, theta_fft)
     rc = tl.lib().tl_plan_create(ctypes.byref(h), lmax, tl.Grid(ntheta, nphi), ctypes.byref(o), None)
     return rc, h, tl.lib().tl_last_error().decode()
 
@@ -47,7 +48,11 @@ def _create(tl, lmax, ntheta, nphi, order=3, prec=1, pol=1, rotate=1, naive=0, b
     ((10, 11, 20, 3, 1, 1, 0, 0, 2), -1), ((10, 11, 20, 3, 1, 1, 0, 0, 0, -5), -1),
     ((64, 65, 128, 3, 1, 1, 1, 0, 0, 1000), -4), ((10, 11, 20, 3, 1, 1, 1, 0, 0, 0, 2), -1),
     ((10, 11, 20, 3, 1, 1, 1, 0, 0, 0, 0, 9), -1), ((10, 11, 20, 3, 1, 1, 1, 0, 0, 0, 0, 11), -1),
-    ((10, 11, 40000, 3, 1, 1, 1, 0, 0, 0, 0, 20000), -2)])
+    ((10, 11, 40000, 3, 1, 1, 1, 0, 0, 0, 0, 20000), -2),
+    # theta_fft: 0 or 1; the FP64 form only; ntheta - 1 a power of two; lmax <= ntheta - 2
+    ((10, 17, 20, 3, 0, 1, 1, 0, 0, 0, 0, 0, 2), -1), ((10, 17, 20, 3, 1, 1, 1, 0, 0, 0, 0, 0, 1), -2),
+    ((10, 11, 20, 3, 0, 1, 1, 0, 0, 0, 0, 0, 1), -2), ((16, 17, 40, 3, 0, 1, 1, 0, 0, 0, 0, 0, 1), -2),
+    ((10, 8194, 20, 3, 0, 1, 1, 0, 0, 0, 0, 0, 1), -2)])
 def test_invalid_plan_arguments(tl, args, code):
     rc, h, msg = _create(tl, *args)
     assert rc == code, msg
@@ -118,4 +123,7 @@ def test_healpix_plan_arguments(tl):
     # the potential's own band limit is an equal-theta feature
     sep = tl.Options(3, 1, 1, 1, 0, 0, 0, 0, 24)
     assert L.tl_plan_create_healpix(ctypes.byref(h), 16, 4, ctypes.byref(sep), None) == tl.TL_ERR_UNSUPPORTED
+    # so are the theta-derivative FFTs along the great circles
+    tf = tl.Options(3, 0, 1, 1, 0, 0, 0, 0, 0, 1)
+    assert L.tl_plan_create_healpix(ctypes.byref(h), 16, 4, ctypes.byref(tf), None) == tl.TL_ERR_UNSUPPORTED
     assert not h.value

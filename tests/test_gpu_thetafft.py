@@ -16,6 +16,10 @@ oracle, through the C ABI (marked gpu).
   workgroup takes one circle), several workgroups per map, and the
   4097 x 8192 grid of the lmax 4095 workload (all maps of one field,
   sampled circles and rings).
+* The FP64 form with theta_fft (rows j = 0 from the recursion, the rest by
+  FFT): derivative maps and lensed maps against the oracle at the FP64 bars
+  and against the same plan without the option, batches bit-identical to
+  single calls, and T+Q/U order 4 at lmax 4095 on 4097 x 8192 rings.
 """
 import ctypes
 import math
@@ -25,7 +29,7 @@ import pytest
 import torch
 
 from paper_1307_0719_amd import skygen
-from tests.gpu_util import need_gpu, oracle_scaled_derivs, t2np
+from tests.gpu_util import ORACLE_THREADS, max_rel, need_gpu, oracle_scaled_derivs, rel_rms, t2np
 
 pytestmark = pytest.mark.gpu
 
@@ -149,3 +153,72 @@ def test_theta_derivs_argument_errors(tl):
     assert call(hpx, x.data_ptr(), 1, 1, y.data_ptr()) == -2
     torch.cuda.synchronize()
     assert float(y.abs().max()) == 0.0                               # nothing ran
+
+
+def _sky_b(lmax, seed, ntheta, rms_pix=1.2):
+    sky = skygen.make_sky(lmax, seed, pol=True, rms_arcmin=rms_pix * (math.pi / (ntheta - 1)) / skygen.ARCMIN)
+    sky.alm_B = skygen.random_alm(lmax, seed + 1000, lmin=2) * 0.2
+    return sky
+
+
+def _check_lens(got, ref, tol_rms, tol_max):
+    mask = ref["_tie"] > 1e-9
+    assert np.mean(~mask) < 1e-3
+    for f, g in zip("TQU", got):
+        assert rel_rms(t2np(g), ref[f], mask) < tol_rms, f
+        assert max_rel(t2np(g), ref[f], mask) < tol_max, f
+
+
+@pytest.mark.parametrize("lmax,ntheta,nphi,order", [(60, 65, 150, 4), (127, 129, 256, 4), (100, 129, 256, 1),
+                                                    (100, 129, 256, 6)])
+def test_theta_fft_plan_against_the_oracle_and_the_recursion(tl, oracle, lmax, ntheta, nphi, order):
+    sky = _sky_b(lmax, 31, ntheta)
+    a = (sky.alm_T, sky.alm_E, sky.alm_B)
+    pt = tl.Plan(lmax, ntheta, nphi, order, "fp64", pol=True, theta_fft=True)
+    pr = tl.Plan(lmax, ntheta, nphi, order, "fp64", pol=True)
+    print("theta_fft plan", lmax, ntheta, nphi, order, flush=True)
+    Dt, Dr = t2np(pt.synth_derivs(*a)), t2np(pr.synth_derivs(*a))
+    ref = oracle_scaled_derivs(oracle, lmax, order, ntheta, nphi, np.arange(ntheta), *a)
+    for f in range(3):
+        for q in range(ref.shape[1]):
+            s = np.max(np.abs(ref[f, q]))
+            assert np.max(np.abs(Dt[f, q] - ref[f, q])) < 1e-11 * s, (f, q)
+            assert np.max(np.abs(Dt[f, q] - Dr[f, q])) < 1e-11 * s, (f, q)
+    mt = pt.lens_map(*a, sky.alm_phi)
+    mr = pr.lens_map(*a, sky.alm_phi)
+    for x, y in zip(mt, mr):
+        assert rel_rms(t2np(x), t2np(y)) < 1e-12 and max_rel(t2np(x), t2np(y)) < 1e-11
+    if (lmax, order) == (127, 4):
+        ref = oracle.lens_map(lmax, order, ntheta, nphi, *a, sky.alm_phi, nthreads=ORACLE_THREADS)
+        _check_lens(mt, ref, 1e-12, 1e-11)
+    # several realizations: bit-identical to single calls
+    sky2 = _sky_b(lmax, 32, ntheta)
+    many = pt.lens_map_many([(*a, sky.alm_phi), (sky2.alm_T, sky2.alm_E, sky2.alm_B, sky2.alm_phi)])
+    single2 = pt.lens_map(sky2.alm_T, sky2.alm_E, sky2.alm_B, sky2.alm_phi)
+    for x, y in zip(many[0], mt):
+        assert torch.equal(x, y)
+    for x, y in zip(many[1], single2):
+        assert torch.equal(x, y)
+
+
+def test_theta_fft_plan_at_the_lmax4095_grid(tl, oracle):
+    """T+Q/U lmax 4095 on 4097 x 8192 rings (the largest circle), order 4,
+    FP64 with theta_fft: the whole lensed maps against the plan without the
+    option, sampled rings (poles, cap edge, belt) against the oracle."""
+    lmax, ntheta, nphi, order = 4095, 4097, 8192, 4
+    sky = skygen.make_sky(lmax, 41, pol=True)
+    a = (sky.alm_T, sky.alm_E, sky.alm_B, sky.alm_phi)
+    print("theta_fft plan lmax 4095", flush=True)
+    pt = tl.Plan(lmax, ntheta, nphi, order, "fp64", pol=True, theta_fft=True)
+    mt = pt.lens_map(*a)
+    del pt
+    pr = tl.Plan(lmax, ntheta, nphi, order, "fp64", pol=True)
+    mr = pr.lens_map(*a)
+    del pr
+    for x, y in zip(mt, mr):
+        d = float(torch.sqrt(torch.mean((x - y) ** 2)) / torch.sqrt(torch.mean(y ** 2)))
+        assert d < 1e-11, d
+    # the FP64 bar of the derivative maps above lmax 2048, 1e-11 (lmax / 2048)^2
+    rings = np.array([0, 2, 197, 1500, 2048, 3899, 4096])
+    ref = oracle.lens_rings(lmax, order, ntheta, nphi, rings, *a, nthreads=ORACLE_THREADS)
+    _check_lens([t2np(g)[rings] for g in mt], ref, 4e-11, 4e-10)
