@@ -40,6 +40,14 @@ What it computes, in the order the paper gives (Sec. II, eqs. 1, 2, 4, 5):
    is that of the circle's trigonometric interpolant (DFT coefficient kappa,
    |kappa| <= P/2, times (i kappa)^j; the Nyquist term keeps even j only),
    read back on the opposite meridian with theta running against the circle.
+9. Spectra of lensed maps (the accuracy measure of Sec. III.A-B): a_lm of a
+   map on the equal-theta grid by Clenshaw-Curtis quadrature over the rings
+   and the DFT along each ring, a_lm = sum_i w_i lambda_lm(theta_i)
+   (2 pi / nphi) sum_k T(theta_i, phi_k) e^{-i m phi_k}; C_l = (|a_l0|^2 +
+   2 sum_{m>0} |a_lm|^2) / (2l + 1); means over bins of 50 multipoles; and
+   the highest accurate multipole l*: the centre of the last bin whose
+   relative error is not above 0.5 % by more than 4 standard errors of its
+   mean over the simulations.
 
 Everything is float64 (the harmonic sums long double).  Speed is not a goal.
 """
@@ -526,4 +534,84 @@ def theta_derivs_fft(maps, jmax: int, cols=None) -> np.ndarray:
         idx = (P - np.arange(ntheta)) % P
         out[..., j - 1, :, len(c):] = (-1.0) ** j * y[..., idx, :]
     return out
+
+
+# --------------------------------------------- spectra of lensed maps (step 9) -----
+
+def cc_weights(ntheta: int) -> np.ndarray:
+    """Clenshaw-Curtis weights of the equal-theta rings, x_i = cos(pi i / N),
+    N = ntheta - 1: integral_{-1}^{1} g(x) dx = sum_i w_i g(x_i) for every
+    polynomial g of degree <= N.  w_i = (c_i / N) (1 - sum_{j=1}^{N/2} b_j
+    cos(2 pi i j / N) / (4 j^2 - 1)), c_i = 1 at the poles and 2 elsewhere,
+    b_j = 1 for j = N / 2 and 2 otherwise."""
+    N = ntheta - 1
+    if N < 1:
+        raise ValueError("need ntheta >= 2")
+    i = np.arange(ntheta, dtype=np.float64)
+    br = np.ones(ntheta)
+    for j in range(1, N // 2 + 1):
+        b = 1.0 if 2 * j == N else 2.0
+        br -= b * np.cos(2.0 * np.pi * i * j / N) / (4.0 * j * j - 1.0)
+    c = np.full(ntheta, 2.0)
+    c[0] = c[-1] = 1.0
+    return c * br / N
+
+
+def analysis_T(Tmap, lmax: int) -> np.ndarray:
+    """a_lm (triangular m-major, complex128) of a real map [ntheta][nphi] on
+    the equal-theta grid: Clenshaw-Curtis quadrature over the rings and the
+    DFT along each ring (numpy's FFT as the library primitive), lambda_lm from
+    the recursion of step 1.  Exact for maps of band limit L with
+    L + lmax <= ntheta - 1 (the integrand is then a polynomial of that degree
+    in cos theta) and L + lmax < nphi."""
+    T = np.asarray(Tmap, dtype=np.float64)
+    ntheta, nphi = T.shape
+    if lmax > nphi // 2:
+        raise ValueError("need lmax <= nphi / 2")
+    w = cc_weights(ntheta)
+    X = np.fft.fft(T, axis=1)[:, :lmax + 1] * (2.0 * np.pi / nphi)   # [ring][m]
+    th = grid_theta(ntheta)
+    out = np.zeros((lmax + 1) * (lmax + 2) // 2, np.complex128)
+    for m in range(lmax + 1):
+        lam = np.stack([spin_lambda(lmax, 0, 0, m, t)[:, 0] for t in th], axis=1)   # [l][ring]
+        off = m * (2 * lmax + 1 - m) // 2
+        out[off + m: off + lmax + 1] = lam[m:] @ (w * X[:, m])
+    return out
+
+
+def cl_from_alm(alm, lmax: int) -> np.ndarray:
+    """C_l = (|a_l0|^2 + 2 sum_{m=1}^{l} |a_lm|^2) / (2 l + 1), l = 0..lmax."""
+    a = np.asarray(alm)
+    cl = np.zeros(lmax + 1)
+    for m in range(lmax + 1):
+        off = m * (2 * lmax + 1 - m) // 2
+        p = np.abs(a[off + m: off + lmax + 1]) ** 2
+        cl[m:] += p if m == 0 else 2.0 * p
+    return cl / (2.0 * np.arange(lmax + 1) + 1.0)
+
+
+def bin_cl(cl, lmin: int = 2, width: int = 50):
+    """Means of C_l over bins [lmin + b width, lmin + (b + 1) width) that fit
+    below len(cl); returns (centres, means)."""
+    cl = np.asarray(cl, dtype=np.float64)
+    nb = (len(cl) - lmin) // width
+    edges = lmin + width * np.arange(nb + 1)
+    means = np.array([cl[edges[b]:edges[b + 1]].mean() for b in range(nb)])
+    return 0.5 * (edges[:-1] + edges[1:] - 1), means
+
+
+def ell_star(centres, rel_err, limit: float = 0.005, nsigma: float = 4.0):
+    """Highest accurate multipole: rel_err [nsim][nbin] relative errors of the
+    binned spectra; a bin fails when |mean| exceeds the limit by more than
+    nsigma standard errors of the mean (std / sqrt(nsim); one simulation: no
+    error bar); l* is the centre of the last bin before the first failing
+    one (the last bin when none fails, None when the first fails)."""
+    e = np.atleast_2d(np.asarray(rel_err, dtype=np.float64))
+    mean = e.mean(axis=0)
+    sem = e.std(axis=0, ddof=1) / np.sqrt(e.shape[0]) if e.shape[0] > 1 else np.zeros(e.shape[1])
+    bad = np.abs(mean) - limit > nsigma * sem
+    if not bad.any():
+        return float(centres[-1])
+    first = int(np.argmax(bad))
+    return None if first == 0 else float(centres[first - 1])
 

@@ -474,3 +474,60 @@ def test_p12_fft_theta_derivatives_of_single_circle_harmonics(oracle, q):
     sub = oracle.theta_derivs_fft(m, 2, cols=[1, 3])
     np.testing.assert_array_equal(sub[..., [0, 1]], out[:2][..., [1, 3]])
     np.testing.assert_array_equal(sub[..., [2, 3]], out[:2][..., [1 + hp, 3 + hp]])
+
+
+@pytest.mark.parametrize("ntheta", [2, 3, 4, 9, 16, 33, 41])
+def test_p13_clenshaw_curtis_weights_integrate_polynomials(oracle, ntheta):
+    """Step 9's ring weights: the integral of x^k over [-1, 1] for every k <= N
+    (the degree the rule is exact for), symmetric weights summing to 2."""
+    N = ntheta - 1
+    w = oracle.cc_weights(ntheta)
+    x = np.cos(math.pi * np.arange(ntheta) / N)
+    np.testing.assert_allclose(w, w[::-1], rtol=0, atol=1e-15)
+    for k in range(N + 1):
+        exact = (1.0 + (-1.0) ** k) / (k + 1.0)
+        assert abs(np.dot(w, x ** k) - exact) < 1e-14, (k, np.dot(w, x ** k), exact)
+
+
+def test_p13_analysis_closed_forms_and_round_trip(oracle):
+    """Step 9's analysis: T = 1 has a_00 = sqrt(4 pi) and T = cos theta has
+    a_10 = sqrt(4 pi / 3), nothing else; a band-limited map synthesized by
+    step 1 (lmax 24, E-independent T) comes back to its a_lm when
+    L + lmax <= ntheta - 1 and misses them when the grid is too coarse."""
+    lmax, ntheta, nphi = 24, 49, 50
+    th = oracle.grid_theta(ntheta)
+    one = oracle.analysis_T(np.ones((ntheta, nphi)), lmax)
+    want = np.zeros_like(one)
+    want[0] = math.sqrt(4 * math.pi)
+    np.testing.assert_allclose(one, want, rtol=0, atol=1e-13)
+    cz = oracle.analysis_T(np.repeat(np.cos(th)[:, None], nphi, axis=1), lmax)
+    want = np.zeros_like(cz)
+    want[1] = math.sqrt(4 * math.pi / 3)
+    np.testing.assert_allclose(cz, want, rtol=0, atol=1e-13)
+    alm = skygen.random_alm(lmax, 77)
+    alm[:lmax + 1] = alm[:lmax + 1].real                      # m = 0 entries are real
+    T = oracle.unlensed_map(lmax, ntheta, nphi, alm)["T"]
+    back = oracle.analysis_T(T, lmax)
+    assert np.max(np.abs(back - alm)) < 1e-12 * np.max(np.abs(alm))
+    Tc = oracle.unlensed_map(lmax, 25, nphi, alm)["T"]       # L + lmax = 48 > 24
+    assert np.max(np.abs(oracle.analysis_T(Tc, lmax) - alm)) > 1e-3 * np.max(np.abs(alm))
+
+
+def test_p13_spectrum_binning_and_ell_star(oracle):
+    """C_l from a_lm (one entry a_32 = 1 + i: C_3 = 2 |a_32|^2 / 7), bins of
+    50 multipoles from l = 2, and the l* rule: the last bin before the first
+    whose mean relative error exceeds 0.5 % by more than 4 standard errors."""
+    lmax = 10
+    alm = np.zeros((lmax + 1) * (lmax + 2) // 2, np.complex128)
+    alm[2 * (2 * lmax + 1 - 2) // 2 + 3] = 1 + 1j
+    cl = oracle.cl_from_alm(alm, lmax)
+    np.testing.assert_allclose(cl, np.where(np.arange(lmax + 1) == 3, 4.0 / 7.0, 0.0), atol=1e-15)
+    c, m = oracle.bin_cl(np.arange(160, dtype=float))
+    np.testing.assert_array_equal(c, [26.5, 76.5, 126.5])
+    np.testing.assert_allclose(m, [26.5, 76.5, 126.5])
+    centres = np.array([26.5, 76.5, 126.5, 176.5])
+    e = np.array([[0.001, 0.004, 0.010, 0.001], [0.001, 0.006, 0.011, 0.001], [0.001, 0.005, 0.012, 0.002]])
+    assert oracle.ell_star(centres, e) == 76.5                  # bin 3 fails, bin 2 is within its error
+    assert oracle.ell_star(centres, np.full((3, 4), 0.001)) == 176.5
+    assert oracle.ell_star(centres, np.full((3, 4), 0.02)) is None
+    assert oracle.ell_star(centres, [[0.001, 0.0051, 0.0, 0.0]]) == 26.5   # one simulation: no error bar
