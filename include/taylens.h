@@ -280,6 +280,27 @@ int tl_remap(tl_plan plan, const void *D, const double *alpha_theta, const doubl
  * plan's stream. */
 int tl_theta_derivs(tl_plan plan, const void *maps, int32_t nmaps, int32_t jmax, void *out);
 
+/* Spherical-harmonic analysis of a temperature map on the plan's equal-theta
+ * grid, the transform behind the power spectra that measure the accuracy of
+ * the lensed maps (Sec. III.A-B):
+ *   a_lm = sum_i w_i lambda_lm(theta_i) (2 pi / nphi) sum_k T(theta_i, phi_k) e^{-i m phi_k},
+ * 0 <= m <= l <= the plan's lmax, w_i the Clenshaw-Curtis weights of the
+ * rings (exact for polynomials in cos theta of degree <= ntheta - 1), so the
+ * result is exact to FP64 rounding for maps of band limit L with
+ * L + lmax <= ntheta - 1 and L + lmax < nphi.
+ *   map:     float64 [ntheta][nphi] device array (any plan precision);
+ *   alm_out: complex128 device array in the triangular layout of the plan's
+ *            lmax, overwritten (the m = 0 entries carry the rounding of a
+ *            zero imaginary part; the order of the atomic sums over ring
+ *            blocks is not fixed, so repeated calls agree to rounding).
+ * The plan's harmonic-stage buffer (ntheta (lmax + 1) complex128 values)
+ * and deflection buffer serve as scratch: requires an equal-theta plan with nphi a power of two, 2 <= nphi
+ * <= 8192, whose buffer is large enough (FP64 plans; order >= 1 or
+ * polarized plans of the other forms) -- TL_ERR_UNSUPPORTED otherwise;
+ * NULL or misaligned pointers: TL_ERR_INVALID.  Queued on the plan's
+ * stream. */
+int tl_analysis_T(tl_plan plan, const double *map, void *alm_out);
+
 /* Lens n realizations (each as tl_lens_map: eqs. 1, 2, 5), plans[i] with
  * coefficient pointers alms[4i..4i+3] (T, E, B, phi) and outputs
  * outs[3i..3i+2] (T, Q, U).  Plans may differ in lmax and grid.  Queued on

@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libtaylens.so")
-SOURCES = ["capi.hip", "legendre.hip", "legendre_mfma.hip", "legendre_tab.hip", "ringfft.hip", "remap.hip", "cnn.hip", "legendre_lp.hip", "thetafft.hip"]
+SOURCES = ["capi.hip", "legendre.hip", "legendre_mfma.hip", "legendre_tab.hip", "ringfft.hip", "remap.hip", "cnn.hip", "legendre_lp.hip", "thetafft.hip", "analysis.hip"]
 ARCH = os.environ.get("TAYLENS_ARCH", "gfx950")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -1727,6 +1727,24 @@ int tl_remap(tl_plan plan, const void *D, const double *alpha_theta, const doubl
     return TL_OK;
 }
 
+int tl_analysis_T(tl_plan plan, const double *map, void *alm_out)
+{
+    if (check_plan(plan)) return TL_ERR_INVALID;
+    Plan &p = plan->p;
+    if (!map || !alm_out) return fail(TL_ERR_INVALID, "NULL argument");
+    if ((uintptr_t)map % 8 || (uintptr_t)alm_out % 16) return fail(TL_ERR_INVALID, "misaligned map or alm_out");
+    if (p.nside) return fail(TL_ERR_UNSUPPORTED, "the analysis needs the equal-theta grid");
+    if (!analysis_grid(p.nphi))
+        return fail(TL_ERR_UNSUPPORTED, "the analysis needs nphi a power of two in [2, 8192]");
+    if (p.F.bytes < analysis_scratch_bytes(p))
+        return fail(TL_ERR_UNSUPPORTED, "the plan's harmonic-stage buffer is too small for the analysis "
+                                        "(use order >= 1, a polarized plan or the FP64 form)");
+    int rc = set_device_of(p);
+    if (rc) return rc;
+    TL_HIP(launch_analysis_T(p, map, alm_out), "analysis");
+    return TL_OK;
+}
+
 int tl_theta_derivs(tl_plan plan, const void *maps, int32_t nmaps, int32_t jmax, void *out)
 {
     if (check_plan(plan)) return TL_ERR_INVALID;

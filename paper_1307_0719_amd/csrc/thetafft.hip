@@ -18,77 +18,12 @@
 // order.  Workgroups are ordered so that each XCD
 // takes a contiguous range of columns: the strided column loads of
 // neighbouring workgroups then share the lines in that XCD's L2.
-#include "tl_internal.h"
+#include "lds_fft.h"
 
 namespace tl {
 namespace {
 
-constexpr int kTfThreads = 512;
 constexpr int kTfReg = kThetaFftMaxP / kTfThreads;  // spectrum entries per thread
-
-__device__ inline int bitrev(int t, int lg) { return (int)(__brev((unsigned)t) >> (32 - lg)); }
-
-__device__ inline double2 cmul(double2 a, double2 b)
-{
-    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
-}
-
-// r consecutive radix-2 decimation-in-time stages s .. s + r - 1 of an
-// in-place transform, in registers: with half = 2^(s-1), block b holds the
-// 2^r elements base + pos + t half (pos = b mod half), which those stages
-// combine only among themselves; stage s + q pairs t with t + 2^q (t mod
-// 2^(q+1) < 2^q) under the twiddle W_{2^(s+q)}^(pos + (t mod 2^q) half).
-// The twiddle e^{-2 pi i e / P}, e < P / 2, is th[e / 64] tl[e % 64] from
-// two tables in LDS; inverse: conjugate twiddles (no 1/P).  Ends with a
-// barrier.
-constexpr int kTwLo = 64;
-constexpr int kTwHi = kThetaFftMaxP / 2 / kTwLo;
-
-__device__ inline double2 twiddle(const double2 *th, const double2 *tl, int e)
-{
-    return cmul(th[e / kTwLo], tl[e % kTwLo]);
-}
-
-template <int r>
-__device__ void fft_stages(double2 *x, int P, int s, const double2 *th, const double2 *tl, bool inverse)
-{
-    constexpr int R = 1 << r;
-    const int half = 1 << (s - 1);
-    for (int b = threadIdx.x; b < P / R; b += kTfThreads) {
-        const int pos = b & (half - 1);
-        double2 *xb = x + (b >> (s - 1)) * (R * half) + pos;
-        double2 v[R];
-#pragma unroll
-        for (int t = 0; t < R; ++t) v[t] = xb[t * half];
-#pragma unroll
-        for (int q = 0; q < r; ++q) {
-            const int hq = 1 << q;
-#pragma unroll
-            for (int t = 0; t < R; ++t) {
-                if ((t & (2 * hq - 1)) < hq) {
-                    double2 w = twiddle(th, tl, (pos + (t & (hq - 1)) * half) * (P >> (s + q)));
-                    if (inverse) w.y = -w.y;
-                    const double2 a = v[t], c = cmul(w, v[t + hq]);
-                    v[t] = make_double2(a.x + c.x, a.y + c.y);
-                    v[t + hq] = make_double2(a.x - c.x, a.y - c.y);
-                }
-            }
-        }
-#pragma unroll
-        for (int t = 0; t < R; ++t) xb[t * half] = v[t];
-    }
-    __syncthreads();
-}
-
-// In-place transform of x[0..P) stored in bit-reversed order: the lg
-// radix-2 stages three at a time (radix 8), the rest two or one at a time.
-__device__ void circle_fft(double2 *x, int P, int lg, const double2 *th, const double2 *tl, bool inverse)
-{
-    int s = 1;
-    for (; s + 2 <= lg; s += 3) fft_stages<3>(x, P, s, th, tl, inverse);
-    if (s + 1 == lg) fft_stages<2>(x, P, s, th, tl, inverse);
-    else if (s == lg) fft_stages<1>(x, P, s, th, tl, inverse);
-}
 
 template <typename T> struct Vec2;
 template <> struct Vec2<double> { using type = double2; };
@@ -108,13 +43,7 @@ __global__ __launch_bounds__(kTfThreads) void k_theta_fft(const T *__restrict__ 
     double2 *x = reinterpret_cast<double2 *>(smem_raw);
     double2 *th = x + P;       // tw[64 a], a < P / 128 (at least one)
     double2 *tl = th + kTwHi;  // tw[b], b < min(64, P / 2)
-    for (int i = threadIdx.x; i < kTwHi + kTwLo; i += kTfThreads) {
-        if (i < kTwHi) {
-            if (i * kTwLo < P / 2) th[i] = tw[i * kTwLo];
-        } else if (i - kTwHi < P / 2) {
-            tl[i - kTwHi] = tw[i - kTwHi];
-        }
-    }
+    load_twiddles(th, tl, tw, P, false);
 
     // XCD-contiguous order: XCD w % 8 takes a contiguous run of the
     // (map, circle pair) items
@@ -151,7 +80,7 @@ __global__ __launch_bounds__(kTfThreads) void k_theta_fft(const T *__restrict__ 
         if (t < P) x[bitrev(t, lg)] = make_double2((double)ld[r].x, (double)ld[r].y);
     }
     __syncthreads();
-    circle_fft(x, P, lg, th, tl, false);
+    lds_fft(x, P, lg, th, tl, false);
 
     double2 X[kTfReg];
 #pragma unroll
@@ -188,7 +117,7 @@ __global__ __launch_bounds__(kTfThreads) void k_theta_fft(const T *__restrict__ 
             }
         }
         __syncthreads();
-        circle_fft(x, P, lg, th, tl, true);
+        lds_fft(x, P, lg, th, tl, true);
 
         T *dst = out + (size_t)map * lay.ostride + (size_t)(lay.sa * j - lay.sb * j * (j - 1) / 2 + lay.sc) * lay.pstride;
         const double sg = (j & 1) ? -1.0 : 1.0;

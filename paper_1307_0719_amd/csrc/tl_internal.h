@@ -366,6 +366,12 @@ struct ThetaFftLayout {
 // dtheta^j / j! d^j_theta of each input map, j = 1..jmax, maps [ntheta][nphi]
 // in the plan's real type; on the plan's stream
 hipError_t launch_theta_fft(Plan &p, const void *in, void *out, int nmaps, int jmax, const ThetaFftLayout &lay);
+// analysis of an FP64 temperature map into a_lm (analysis.hip): rings of a
+// power of two of pixels up to kThetaFftMaxP; scratch in the plan's F buffer
+// (analysis_scratch_bytes of it) and its deflection buffer (lmax + 1 values)
+bool analysis_grid(int nphi);
+size_t analysis_scratch_bytes(const Plan &p);
+hipError_t launch_analysis_T(Plan &p, const double *map, void *alm);
 // the deflection's ring FFTs in FP32 (Plan::defl32) from the FP64 rows at
 // band limit L into the FP64 deflection alpha
 hipError_t launch_defl_fft32(Plan &p, const void *rows64, void *alpha, int L);

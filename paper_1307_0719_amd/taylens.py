@@ -30,7 +30,7 @@ PRECISIONS = {"fp64": 0, "fp32": 1, "bf16x3": 2, "fp16x2": 3, "fp16": 4, "bf16":
 # every symbol include/taylens.h declares
 EXPORTS = [
     "tl_plan_create", "tl_plan_destroy", "tl_plan_workspace_bytes", "tl_plan_query", "tl_lens_map", "tl_lens_map_pos",
-    "tl_deflection", "tl_legendre", "tl_synth_derivs", "tl_theta_derivs", "tl_remap", "tl_lens_map_batch",
+    "tl_deflection", "tl_legendre", "tl_synth_derivs", "tl_theta_derivs", "tl_analysis_T", "tl_remap", "tl_lens_map_batch",
     "tl_lens_map_simple", "tl_lens_map_many", "tl_plan_profile", "tl_plan_stage_times", "tl_last_error", "tl_version",
     "tl_cnn_create", "tl_cnn_destroy", "tl_cnn_get_params", "tl_cnn_set_params", "tl_cnn_forward", "tl_cnn_grad",
     "tl_cnn_train_step", "tl_lens_map_cnn", "tl_batch_create", "tl_batch_destroy", "tl_batch_run", "tl_batch_info",
@@ -94,6 +94,7 @@ def lib():
         L.tl_synth_derivs.argtypes = [vp] * 5
         L.tl_remap.argtypes = [vp] * 7
         L.tl_theta_derivs.argtypes = [vp, vp, ctypes.c_int32, ctypes.c_int32, vp]
+        L.tl_analysis_T.argtypes = [vp, vp, vp]
         L.tl_lens_map_batch.argtypes = [ctypes.c_int32, vp, vp, vp]
         L.tl_lens_map_simple.argtypes = [vp, vp, vp, vp, ctypes.c_int32, ctypes.c_int32, Grid, vp, vp, vp]
         L.tl_lens_map_simple_noalloc.argtypes = [vp, vp, vp, vp, ctypes.c_int32, ctypes.c_int32, Grid, vp, vp, vp]
@@ -315,6 +316,17 @@ class Plan:
         _check(lib().tl_synth_derivs(self._h, _ptr(T), _ptr(E), _ptr(B), _ptr(D)))
         self._keep = (T, E, B)
         return D
+
+    def analysis_T(self, Tmap: torch.Tensor):
+        """a_lm (complex128, triangular) of a temperature map [ntheta, nphi]
+        by Clenshaw-Curtis quadrature over the rings and ring FFTs."""
+        Tmap = Tmap.to(self.device, torch.float64).contiguous()
+        if tuple(Tmap.shape) != tuple(self.map_shape):
+            raise ValueError("map must be (ntheta, nphi)")
+        alm = torch.empty((self.lmax + 1) * (self.lmax + 2) // 2, dtype=torch.complex128, device=self.device)
+        _check(lib().tl_analysis_T(self._h, _ptr(Tmap), _ptr(alm)))
+        self._keep = (Tmap,)
+        return alm
 
     def theta_derivs(self, maps: torch.Tensor, jmax: int):
         """dtheta^j / j! d^j_theta of maps [..., ntheta, nphi] by FFT along the

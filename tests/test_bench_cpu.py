@@ -94,3 +94,21 @@ def test_sweep_fastest_settings_per_potential_band_limit(bench):
              "rel_rms_err_max": 1e-3} for lp, t in ((8, 1.0), (16, 2.0))]
     best = bench.sweep_best(rows, targets=(1e-2,))
     assert [(b["lmax_phi"], b["row"]["ms_per_map"]) for b in best] == [(8, 1.0), (16, 2.0)]
+
+
+def test_spectra_helpers_match_the_oracle(bench, oracle):
+    """The benchmark's C_l, bins and l* rule against the oracle's (step 9)."""
+    import numpy as np
+
+    rng = np.random.default_rng(8)
+    lmax = 160
+    alm = rng.standard_normal((lmax + 1) * (lmax + 2) // 2) + 1j * rng.standard_normal((lmax + 1) * (lmax + 2) // 2)
+    np.testing.assert_allclose(bench.spectra_cl(alm, lmax), oracle.cl_from_alm(alm, lmax), rtol=1e-14)
+    cl = rng.random(lmax + 1)
+    c1, m1 = bench.spectra_bins(cl)
+    c2, m2 = oracle.bin_cl(cl)
+    np.testing.assert_array_equal(c1, c2)
+    np.testing.assert_allclose(m1, m2, rtol=1e-15)
+    for _ in range(20):
+        e = rng.normal(0.004, 0.003, size=(4, len(c1))) * np.linspace(0.5, 3.0, len(c1))
+        assert bench.spectra_ell_star(c1, e) == oracle.ell_star(c1, e)
