@@ -1111,6 +1111,7 @@ def main():
         res["batch_uneven_lmax"] = bench_batch(args, order)
         res["learned_correction"] = bench_cnn(args, w)
         res["theta_fft"] = bench_theta_fft(args)
+        res["spectra"] = bench_spectra(args)
     print(json.dumps(res))
 
 
