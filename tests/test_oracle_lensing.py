@@ -531,3 +531,26 @@ def test_p13_spectrum_binning_and_ell_star(oracle):
     assert oracle.ell_star(centres, np.full((3, 4), 0.001)) == 176.5
     assert oracle.ell_star(centres, np.full((3, 4), 0.02)) is None
     assert oracle.ell_star(centres, [[0.001, 0.0051, 0.0, 0.0]]) == 26.5   # one simulation: no error bar
+
+
+def test_p13_spin2_analysis_round_trip(oracle):
+    """Step 9's E/B analysis: Q/U maps synthesized by step 1 from E and B of
+    lmax 20 (Goldberg-pinned spin-2 functions) come back to E and B on 41
+    rings of 42 pixels; an E-only sky has no B; too few rings miss them."""
+    lmax, ntheta, nphi = 20, 41, 42
+    aT = skygen.random_alm(lmax, 1)
+    aE = skygen.random_alm(lmax, 2, lmin=2)
+    aB = skygen.random_alm(lmax, 3, lmin=2)
+    for a in (aE, aB):
+        a[:lmax + 1] = a[:lmax + 1].real
+    m = oracle.unlensed_map(lmax, ntheta, nphi, aT, aE, aB)
+    E, B = oracle.analysis_EB(m["Q"], m["U"], lmax)
+    assert np.max(np.abs(E - aE)) < 1e-12 * np.max(np.abs(aE))
+    assert np.max(np.abs(B - aB)) < 1e-12 * np.max(np.abs(aB))
+    m0 = oracle.unlensed_map(lmax, ntheta, nphi, aT, aE, None)
+    E0, B0 = oracle.analysis_EB(m0["Q"], m0["U"], lmax)
+    assert np.max(np.abs(E0 - aE)) < 1e-12 * np.max(np.abs(aE))
+    assert np.max(np.abs(B0)) < 1e-12 * np.max(np.abs(aE))
+    mc = oracle.unlensed_map(lmax, 21, nphi, aT, aE, aB)
+    Ec, _ = oracle.analysis_EB(mc["Q"], mc["U"], lmax)
+    assert np.max(np.abs(Ec - aE)) > 1e-3 * np.max(np.abs(aE))
