@@ -276,8 +276,8 @@ int tl_remap(tl_plan plan, const void *D, const double *alpha_theta, const doubl
  * plan with ntheta - 1 a power of two, 2 <= ntheta - 1 <= 4096, and
  * lmax <= ntheta - 2 (TL_ERR_UNSUPPORTED otherwise); 1 <= jmax <= 8,
  * nmaps >= 0, maps and out caller-owned device buffers aligned to two
- * values and not overlapping (TL_ERR_INVALID otherwise).  Queued on the
- * plan's stream. */
+ * values (TL_ERR_INVALID otherwise) that must not overlap (not checked: the
+ * result is then undefined).  Queued on the plan's stream. */
 int tl_theta_derivs(tl_plan plan, const void *maps, int32_t nmaps, int32_t jmax, void *out);
 
 /* Spherical-harmonic analysis of a temperature map on the plan's equal-theta
