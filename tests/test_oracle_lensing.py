@@ -554,3 +554,23 @@ def test_p13_spin2_analysis_round_trip(oracle):
     mc = oracle.unlensed_map(lmax, 21, nphi, aT, aE, aB)
     Ec, _ = oracle.analysis_EB(mc["Q"], mc["U"], lmax)
     assert np.max(np.abs(Ec - aE)) > 1e-3 * np.max(np.abs(aE))
+
+
+@pytest.mark.parametrize("lmax,ntheta,nphi,pol", [(511, 513, 1024, False), (255, 257, 512, True)])
+def test_p12_fft_theta_derivatives_at_higher_l(oracle, lmax, ntheta, nphi, pol):
+    """Step 8 against step 1 at lmax 511 (T) and 255 (T, Q, U): the FFT
+    derivatives (j <= 2) of the recursion's D_{0,k} equal its D_{j,k}, on
+    every ring, to 1e-11 of the largest value."""
+    order = 2
+    aT = skygen.random_alm(lmax, 41)
+    aE = skygen.random_alm(lmax, 42, lmin=2) if pol else None
+    D = oracle.derivative_rings(lmax, order, ntheta, nphi, np.arange(ntheta), aT, aE, None)
+    dth = math.pi / (ntheta - 1)
+    for f in D:
+        for k in range(order):
+            out = oracle.theta_derivs_fft(D[f][(0, k)], order - k)
+            hp = nphi // 2
+            for j in range(1, order - k + 1):
+                want = D[f][(j, k)] * dth ** j / math.factorial(j)
+                got = np.concatenate([out[j - 1][:, :hp], out[j - 1][:, hp:]], axis=1)
+                assert np.max(np.abs(got - want)) < 1e-11 * np.max(np.abs(want)), (f, j, k)
