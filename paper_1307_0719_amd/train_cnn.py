@@ -113,36 +113,36 @@ def evaluate(params, lmax, ntheta, nphi, seeds, precision="fp32", plain_orders=(
     its tables)."""
     dev = torch.device("cuda", torch.cuda.current_device())
     skies = []
-    judge = []
+    ref6 = []
     p6 = taylens.Plan(lmax, ntheta, nphi, 6, "fp32", pol=True)
     for sd in seeds:
         s = skygen.make_sky(lmax, sd, pol=True)
         a = (_dev(s.alm_T, dev), _dev(s.alm_E, dev), None, _dev(s.alm_phi, dev))
         skies.append(a)
-        judge.append(torch.stack(p6.lens_map(*a)).reshape(3, -1).cpu())
+        ref6.append(torch.stack(p6.lens_map(*a)).reshape(3, -1).cpu())
     p6.close()
     torch.cuda.empty_cache()
 
-    def rms_against_judge(run):
+    def rms_against_ref6(run):
         acc = np.zeros(3)
-        for a, m6 in zip(skies, judge):
+        for a, m6 in zip(skies, ref6):
             m = run(a).reshape(3, -1).double()
             acc += torch.mean((m - m6.to(dev).double()) ** 2, dim=1).cpu().numpy()
         return np.sqrt(acc / len(seeds))
 
     p2 = taylens.Plan(lmax, ntheta, nphi, 2, precision, pol=True)
     net = taylens.Cnn(params)
-    out = {"order2": rms_against_judge(lambda a: torch.stack(p2.lens_map(*a))),
-           "cnn": rms_against_judge(lambda a: torch.stack(net.lens_map(p2, *a)))}
+    out = {"order2": rms_against_ref6(lambda a: torch.stack(p2.lens_map(*a))),
+           "cnn": rms_against_ref6(lambda a: torch.stack(net.lens_map(p2, *a)))}
     net.close()
     p2.close()
     torch.cuda.empty_cache()
     for N in plain_orders:
         pn = taylens.Plan(lmax, ntheta, nphi, N, precision, pol=True)
-        out[f"order{N}"] = rms_against_judge(lambda a: torch.stack(pn.lens_map(*a)))
+        out[f"order{N}"] = rms_against_ref6(lambda a: torch.stack(pn.lens_map(*a)))
         pn.close()
         torch.cuda.empty_cache()
-    signal = np.sqrt(sum(torch.mean(m6.double() ** 2, dim=1).numpy() for m6 in judge) / len(seeds))
+    signal = np.sqrt(sum(torch.mean(m6.double() ** 2, dim=1).numpy() for m6 in ref6) / len(seeds))
     res = {"rms_err_order2": out["order2"].tolist(), "rms_err_cnn": out["cnn"].tolist(),
            "rms_signal": signal.tolist(), "gain": (out["order2"] / out["cnn"]).tolist(),
            "precision": precision, "seeds": list(seeds)}
